@@ -1,0 +1,180 @@
+/*
+ * pcmcc.h -- C ABI of the MI355X (gfx950) PIC-MCC electron library.
+ *
+ * Method: the particle (PIC-MCC) model of Wang, Sun & Teunissen, "A
+ * comparison of particle and fluid models for positive streamer discharges
+ * in air" (arXiv:2110.14494), Sec. 2.1: electrons are advanced with velocity
+ * Verlet in a field interpolated from a cell-centred grid (Sec. 2.1.1
+ * eq. (1)-(2), Sec. 2.1.3), collide with a neutral background through the
+ * null-collision method with rates from tabulated cross sections (Sec. 2.1.1,
+ * Sec. 2.1.5), and are mapped back to the grid by trilinear weighting
+ * (Sec. 2.1.3).  The same mover run in a uniform field gives the flux and bulk
+ * swarm coefficients that feed the fluid model (Sec. 2.2.1).
+ *
+ * Conventions shared by every entry point:
+ *   - SI units, except energies in eV and reduced fields E/N in Td
+ *     (1 Td = 1e-21 V m^2).
+ *   - Every function returns an int status (PCMCC_OK or a negative code);
+ *     no exception crosses the ABI.  pcmcc_last_error() gives a text for the
+ *     last failing call on a context.
+ *   - "device" pointers are HIP device memory of the context's device;
+ *     "host" pointers are ordinary host memory.  The library never frees or
+ *     keeps caller memory beyond a call.
+ *   - All work is queued on the context's HIP stream.  Calls that return
+ *     statistics or host results synchronise that stream before returning.
+ *   - A context is not thread safe: calls on one context must not overlap.
+ */
+#ifndef PCMCC_H
+#define PCMCC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define PCMCC_OK 0
+#define PCMCC_EINVAL (-1)    /* invalid argument (null pointer, size, range) */
+#define PCMCC_ECAPACITY (-2) /* a step would exceed the particle capacity */
+#define PCMCC_EHIP (-3)      /* a HIP runtime call failed (text in last_error) */
+#define PCMCC_ESTATE (-4)    /* species or tables not initialised */
+#define PCMCC_ENOMEM (-5)    /* device allocation failed */
+#define PCMCC_ETABLE (-6)    /* malformed cross-section table */
+#define PCMCC_ELIMIT (-7)    /* a per-step safety limit was reached */
+
+/* Collision process kinds (Sec. 2.1.5).  Cumulative rates are formed in the
+ * order the processes are given to pcmcc_init_tables. */
+#define PCMCC_ELASTIC 0
+#define PCMCC_EXCITATION 1
+#define PCMCC_IONIZATION 2
+#define PCMCC_ATTACHMENT 3
+
+/* pcmcc_init_tables flags. */
+#define PCMCC_EFFECTIVE_TO_ELASTIC 1 /* elastic := effective momentum transfer
+                                        minus the sum of the inelastic
+                                        processes, clamped at 0 (Sec. 2.1.5) */
+#define PCMCC_RATES 2                /* sigma already holds collision
+                                        frequencies in 1/s (no N sigma v) */
+
+typedef struct pcmcc_ctx pcmcc_ctx;
+
+/* Particle arrays, structure of arrays, all device memory with room for
+ * `capacity` particles.  Positions in m, velocities in m/s, w = number of
+ * physical electrons represented (super-particle weight, Sec. 2.1.2), id = a
+ * 64-bit identity that keys the particle's random numbers.  *n_dev (device)
+ * holds the live count. */
+typedef struct pcmcc_particles {
+  float* x;
+  float* y;
+  float* z;
+  float* vx;
+  float* vy;
+  float* vz;
+  float* w;
+  uint64_t* id;
+  int64_t* n_dev;
+  int64_t capacity;
+} pcmcc_particles;
+
+/* Cell-centred uniform grid: cell (i,j,k) has centre
+ * (x0 + (i+1/2) dx, y0 + (j+1/2) dx, z0 + (k+1/2) dx); E is float4 per cell
+ * (Ex, Ey, Ez, unused) in V/m, x fastest, device memory. */
+typedef struct pcmcc_grid {
+  const float* E; /* nx*ny*nz*4 floats */
+  int nx, ny, nz;
+  double x0, y0, z0, dx;
+} pcmcc_grid;
+
+/* Counters of one call, summed over the committed steps. */
+typedef struct pcmcc_stats {
+  int64_t n;                     /* live particles after the last committed step */
+  int64_t steps_done;            /* committed steps */
+  uint64_t particle_steps;       /* sum over committed steps of the count at the step's start */
+  uint64_t trials;               /* flight segments (one random draw each) */
+  uint64_t null_collisions;      /* includes collisions rejected below threshold */
+  uint64_t real_collisions[4];   /* by kind: elastic, excitation, ionization, attachment */
+  uint64_t lost;                 /* removed for leaving the grid */
+  uint64_t out_of_table;         /* real collisions above the last table energy */
+  uint64_t errors;               /* particles dropped at the per-step segment limit */
+} pcmcc_stats;
+
+/* Version string, static storage. */
+const char* pcmcc_version(void);
+
+/* Creates a context on HIP device `device` issuing work on `hip_stream`
+ * (a hipStream_t, or NULL for the default stream).  *out receives the
+ * context.  The library owns the context, its tables and its scratch
+ * buffers (ping-pong particle buffers, newborn queues, counters). */
+int pcmcc_create(pcmcc_ctx** out, int device, void* hip_stream);
+
+/* Releases everything the context owns; ctx may be NULL. */
+int pcmcc_destroy(pcmcc_ctx* ctx);
+
+/* Text of the last error on ctx (empty string if none); valid until the next
+ * call on ctx.  ctx may be NULL (then a global text is returned). */
+const char* pcmcc_last_error(pcmcc_ctx* ctx);
+
+/* Particle species and background gas (Sec. 2.1.1: a = (q/m) E with q = -e
+ * for electrons; Sec. 2.3: gas number density N).  target_mass_kg is the
+ * neutral mass used for the elastic recoil loss 2m/M (1 - cos chi).  Calling
+ * it again invalidates the tables (pcmcc_init_tables must follow). */
+int pcmcc_init_species(pcmcc_ctx* ctx, double mass_kg, double charge_C, double gas_N_m3, double target_mass_kg);
+
+/* Cross-section tables (Sec. 2.1.5).  Energies are log-spaced:
+ * eps_i = eps_min (eps_max/eps_min)^(i/(n_e-1)), i = 0..n_e-1.
+ * kind[n_proc], threshold_eV[n_proc] and sigma_m2[n_proc][n_e] are host
+ * arrays; sigma is in m^2 (or 1/s with PCMCC_RATES).  The library forms
+ * nu_k = N sigma_k v(eps) in double precision, the cumulative sums in the
+ * given process order and the prefix maximum of the total, and keeps them on
+ * the device in single precision.  Rates are linear in ln(eps) between nodes
+ * and constant outside [eps_min, eps_max]; a collision selected below its
+ * process threshold is treated as null.  1 <= n_proc <= 8, 2 <= n_e <= 4096.
+ * Returns PCMCC_ETABLE for negative/non-finite values or bad kinds. */
+int pcmcc_init_tables(pcmcc_ctx* ctx, int n_e, double eps_min_eV, double eps_max_eV, int n_proc, const int* kind,
+                      const double* threshold_eV, const double* sigma_m2, int flags);
+
+/* Advances the particles n_steps steps of length dt in the fixed field, then
+ * adds their charge to rho by trilinear (CIC) weighting (Sec. 2.1.1-2.1.3).
+ * Per step every particle is moved from t = 0 and newborn electrons from
+ * their birth time, all to the end of the step; attached particles and
+ * particles outside the grid at the end of the step are removed.  Random
+ * numbers are Philox4x32-10 keyed by `seed` with counter (id, step0 + s,
+ * segment, purpose), so results do not depend on array order and a run of
+ * 10 steps equals 5 steps plus 5 steps with step0 = 5.
+ *   p      : device particle arrays, updated in place; the order of the
+ *            particles on return is unspecified.
+ *   field  : device field, read only.
+ *   rho    : device int64 array laid out like the field, or NULL to skip the
+ *            deposit.  It is accumulated into (the caller zeroes it): each
+ *            particle adds round(w 2^32) split over the 8 nearest cell
+ *            centres, indices clamped to the grid, exactly conserving the sum.
+ *   stats  : host, may be NULL.
+ * On PCMCC_ECAPACITY the arrays hold the state after stats->steps_done
+ * committed steps and the deposit is skipped.  Synchronises the stream. */
+int pcmcc_push_collide_deposit(pcmcc_ctx* ctx, const pcmcc_particles* p, const pcmcc_grid* field, double dt,
+                               int n_steps, uint64_t seed, uint64_t step0, int64_t* rho, pcmcc_stats* stats);
+
+/* Deposit only (Sec. 2.1.3), same fixed-point rule as above, on n_dev
+ * particles (device count) of device arrays x, y, z, w. */
+int pcmcc_deposit(pcmcc_ctx* ctx, const float* x, const float* y, const float* z, const float* w,
+                  const int64_t* n_dev, const pcmcc_grid* grid, int64_t* rho);
+
+/* Philox4x32-10 (Salmon et al., SC'11) on n device counters ctr[n][4] with
+ * key (seed low word, seed high word); out[n][4] device.  Self-test of the
+ * generator every kernel uses. */
+int pcmcc_philox4x32_10(pcmcc_ctx* ctx, int64_t n, const uint32_t* ctr, uint64_t seed, uint32_t* out);
+
+/* Table lookups as the kernels do them, for checking the device tables:
+ * cum_out[n][n_proc] = interpolated cumulative rates at eps[n]; if maj_out is
+ * not NULL, maj_out[n] = the collision-frequency majorant for a particle of
+ * speed speed[n] with t_rem[n] left in the step under acceleration bound
+ * a_max.  All arrays device. */
+int pcmcc_tables_lookup(pcmcc_ctx* ctx, int64_t n, const float* eps, float* cum_out, const float* speed,
+                        const float* t_rem, float a_max, float* maj_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PCMCC_H */
