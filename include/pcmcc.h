@@ -97,6 +97,8 @@ typedef struct pcmcc_stats {
   uint64_t lost;                 /* removed for leaving the grid */
   uint64_t out_of_table;         /* real collisions above the last table energy */
   uint64_t errors;               /* particles dropped at the per-step segment limit */
+  double step_kernel_ms;         /* device time of the step loop kernel (HIP events on the stream) */
+  double deposit_kernel_ms;      /* device time of the deposit kernel, 0 if skipped */
 } pcmcc_stats;
 
 /* Version string, static storage. */
@@ -166,12 +168,13 @@ int pcmcc_deposit(pcmcc_ctx* ctx, const float* x, const float* y, const float* z
 int pcmcc_philox4x32_10(pcmcc_ctx* ctx, int64_t n, const uint32_t* ctr, uint64_t seed, uint32_t* out);
 
 /* Table lookups as the kernels do them, for checking the device tables:
- * cum_out[n][n_proc] = interpolated cumulative rates at eps[n]; if maj_out is
- * not NULL, maj_out[n] = the collision-frequency majorant for a particle of
- * speed speed[n] with t_rem[n] left in the step under acceleration bound
- * a_max.  All arrays device. */
-int pcmcc_tables_lookup(pcmcc_ctx* ctx, int64_t n, const float* eps, float* cum_out, const float* speed,
-                        const float* t_rem, float a_max, float* maj_out);
+ * cum_out[n][n_proc] = cumulative rates at eps[n] (linear in ln eps between
+ * nodes, held constant outside the table); if maj_out is not NULL,
+ * maj_out[n] = the collision-frequency majorant for a particle whose speed
+ * stays below s_ub[n] (m/s): the prefix maximum of the total rate at the
+ * energy of s_ub (inflated by 2^-16).  All arrays device. */
+int pcmcc_tables_lookup(pcmcc_ctx* ctx, int64_t n, const float* eps, float* cum_out, const float* s_ub,
+                        float* maj_out);
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,92 @@
+"""ctypes binding of libpcmcc.so (the C ABI declared in include/pcmcc.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  PyTorch tensors provide device memory and streams.  If the built
+library is missing the import fails loudly; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpcmcc.so")
+
+PCMCC_OK, PCMCC_EINVAL, PCMCC_ECAPACITY, PCMCC_EHIP = 0, -1, -2, -3
+PCMCC_ESTATE, PCMCC_ENOMEM, PCMCC_ETABLE, PCMCC_ELIMIT = -4, -5, -6, -7
+PCMCC_ELASTIC, PCMCC_EXCITATION, PCMCC_IONIZATION, PCMCC_ATTACHMENT = 0, 1, 2, 3
+PCMCC_EFFECTIVE_TO_ELASTIC, PCMCC_RATES = 1, 2
+
+_NAMES = {0: "OK", -1: "EINVAL", -2: "ECAPACITY", -3: "EHIP", -4: "ESTATE", -5: "ENOMEM", -6: "ETABLE",
+          -7: "ELIMIT"}
+
+
+class pcmcc_particles(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("vx", C.c_void_p),
+                ("vy", C.c_void_p), ("vz", C.c_void_p), ("w", C.c_void_p), ("id", C.c_void_p),
+                ("n_dev", C.c_void_p), ("capacity", C.c_int64)]
+
+
+class pcmcc_grid(C.Structure):
+    _fields_ = [("E", C.c_void_p), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("x0", C.c_double),
+                ("y0", C.c_double), ("z0", C.c_double), ("dx", C.c_double)]
+
+
+class pcmcc_stats(C.Structure):
+    _fields_ = [("n", C.c_int64), ("steps_done", C.c_int64), ("particle_steps", C.c_uint64),
+                ("trials", C.c_uint64), ("null_collisions", C.c_uint64),
+                ("real_collisions", C.c_uint64 * 4), ("lost", C.c_uint64), ("out_of_table", C.c_uint64),
+                ("errors", C.c_uint64), ("step_kernel_ms", C.c_double), ("deposit_kernel_ms", C.c_double)]
+
+    def as_dict(self) -> dict:
+        r = list(self.real_collisions)
+        return {"n": self.n, "steps_done": self.steps_done, "particle_steps": self.particle_steps,
+                "trials": self.trials, "null": self.null_collisions, "elastic": r[0], "excitation": r[1],
+                "ionization": r[2], "attachment": r[3], "lost": self.lost,
+                "out_of_table": self.out_of_table, "errors": self.errors,
+                "step_kernel_ms": self.step_kernel_ms, "deposit_kernel_ms": self.deposit_kernel_ms}
+
+
+class PcmccError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"pcmcc error {code} ({_NAMES.get(code, '?')}): {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Loads libpcmcc.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2110_14494_amd/build.py "
+                              "(or __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, u64 = C.c_void_p, C.c_int64, C.c_uint64
+        sigs = {
+            "pcmcc_version": ([], C.c_char_p),
+            "pcmcc_last_error": ([vp], C.c_char_p),
+            "pcmcc_create": ([C.POINTER(vp), C.c_int, vp], C.c_int),
+            "pcmcc_destroy": ([vp], C.c_int),
+            "pcmcc_init_species": ([vp, C.c_double, C.c_double, C.c_double, C.c_double], C.c_int),
+            "pcmcc_init_tables": ([vp, C.c_int, C.c_double, C.c_double, C.c_int, vp, vp, vp, C.c_int], C.c_int),
+            "pcmcc_push_collide_deposit": ([vp, C.POINTER(pcmcc_particles), C.POINTER(pcmcc_grid), C.c_double,
+                                            C.c_int, u64, u64, vp, C.POINTER(pcmcc_stats)], C.c_int),
+            "pcmcc_deposit": ([vp, vp, vp, vp, vp, vp, C.POINTER(pcmcc_grid), vp], C.c_int),
+            "pcmcc_philox4x32_10": ([vp, i64, vp, u64, vp], C.c_int),
+            "pcmcc_tables_lookup": ([vp, i64, vp, vp, vp, vp], C.c_int),
+        }
+        for name, (args, res) in sigs.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def check(rc: int, ctx=None) -> int:
+    if rc != PCMCC_OK:
+        raise PcmccError(rc, lib().pcmcc_last_error(ctx).decode())
+    return rc

@@ -1,0 +1,180 @@
+// Device-side building blocks of the PIC-MCC electron update for gfx950:
+// Philox4x32-10, single-precision collision tables, the collision-frequency
+// majorant, trilinear field interpolation and the velocity-Verlet step.
+//
+// Method: arXiv:2110.14494 Sec. 2.1.1 (velocity Verlet, eq. (1)-(2), and the
+// null-collision method), Sec. 2.1.3 (trilinear interpolation on the
+// cell-centred grid), Sec. 2.1.5 (rates from cross sections).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pcmcc {
+
+constexpr int kMaxProc = 8;
+constexpr int kMaxSegments = 1 << 20;  // per particle and step; beyond it the particle is dropped
+constexpr int kMaxGenerations = 64;    // newborn generations within one step
+constexpr float kKappa = 4.0f;         // flight horizon in expected candidate collisions
+constexpr float kGuard = 1.0f + 0x1p-16f;
+
+enum Kind { ELASTIC = 0, EXCITATION = 1, IONIZATION = 2, ATTACHMENT = 3 };
+enum Tag : uint32_t { TAG_MAIN = 0, TAG_BIRTH = 1, TAG_AUX = 2 };
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  The key is the run
+// seed, so the ten round keys are wave-uniform and live in scalar registers.
+struct Key {
+  uint32_t k0, k1;
+};
+
+__device__ __forceinline__ uint4 philox(uint4 c, Key key) {
+  uint32_t k0 = key.k0, k1 = key.k1;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * c.x;
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
+    const uint32_t lo1 = 0xCD9E8D57u * c.z;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
+    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+__device__ __forceinline__ uint4 draw(Key key, uint64_t id, uint32_t step, uint32_t j, uint32_t tag) {
+  return philox(make_uint4((uint32_t)id, (uint32_t)(id >> 32), step, (j << 2) | tag), key);
+}
+
+// Uniform in (0,1) from the top 23 bits: ((r >> 9) + 1/2) 2^-23, exact in FP32.
+__device__ __forceinline__ float unif(uint32_t r) { return ((float)(r >> 9) + 0.5f) * 0x1p-23f; }
+
+// ---------------------------------------------------------------------------
+// Collision tables: cumulative rates C[k][i] in process order and the prefix
+// maximum P[i] of the total, at energies linear in ln(eps).  The table
+// position is u = log2(eps) * u_scale + u_offset.
+struct TableView {
+  const float* C;   // [nproc][n]
+  const float* P;   // [n]
+  const float* nu;  // [nproc][n]
+  int n, nproc;
+  float u_scale, u_offset;
+  float eps_top;  // last node energy
+  float thr[kMaxProc];
+  int kind[kMaxProc];
+};
+
+// Physical constants of the species and gas, single precision.
+struct SpeciesView {
+  float qm;       // q/m
+  float k_eps;    // eps[eV] = k_eps |v|^2
+  float inv_k;    // 1 / k_eps
+  float recoil;   // 2 m / M
+};
+
+__device__ __forceinline__ void locate(const TableView& T, float eps, int& i, float& f) {
+  float u = __log2f(eps) * T.u_scale + T.u_offset;  // eps = 0 gives -inf
+  u = fminf(fmaxf(u, 0.0f), (float)(T.n - 1));
+  const float fl = fminf(floorf(u), (float)(T.n - 2));
+  i = (int)fl;
+  f = u - fl;
+}
+
+__device__ __forceinline__ float lerp_at(const float* row, int i, float f) {
+  const float a = row[i], b = row[i + 1];
+  return fmaf(f, b - a, a);
+}
+
+// Majorant of the total rate for speeds below s_ub (prefix maximum
+// interpolated at the energy of s_ub, inflated as a rounding guard).
+__device__ __forceinline__ float majorant(const TableView& T, const SpeciesView& S, const float* P, float s_ub) {
+  const float s = s_ub * kGuard;
+  int i;
+  float f;
+  locate(T, S.k_eps * s * s, i, f);
+  return lerp_at(P, i, f);
+}
+
+// Largest speed reachable within h from v under acceleration a0 now, when
+// |a| <= a_abs and |a - a0| <= da along the way.
+__device__ __forceinline__ float speed_bound(float3 v, float3 a0, float speed, float a_abs, float da, float h) {
+  const float wx = fmaf(a0.x, h, v.x), wy = fmaf(a0.y, h, v.y), wz = fmaf(a0.z, h, v.z);
+  const float s_dir = fmaf(da, h, fmaxf(speed, sqrtf(wx * wx + wy * wy + wz * wz)));
+  return fminf(fmaf(a_abs, h, speed), s_dir);
+}
+
+// ---------------------------------------------------------------------------
+// Field on the cell-centred grid: float4 per cell (Ex, Ey, Ez, -), x fastest.
+struct GridView {
+  const float4* E;
+  const float2* bound;  // per cell: (max |E| over the 4x4x4 centres, field range norm)
+  int nx, ny, nz;
+  float x0, y0, z0;     // origin
+  float inv_dx, dx;
+  float x1, y1, z1;     // upper ends of the domain
+  float a_glob;         // |q/m| max |E|
+  float qm_abs;
+};
+
+// Trilinear interpolation with clamped indices (constant outside the
+// outermost centres), returned as acceleration (q/m) E.
+__device__ __forceinline__ float3 gather(const GridView& G, float qm, float x, float y, float z) {
+  float u[3] = {(x - G.x0) * G.inv_dx - 0.5f, (y - G.y0) * G.inv_dx - 0.5f, (z - G.z0) * G.inv_dx - 0.5f};
+  const int n[3] = {G.nx, G.ny, G.nz};
+  int i0[3], i1[3];
+  float f[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const float uu = fminf(fmaxf(u[d], -1.0f), (float)n[d]);
+    const float fl = floorf(uu);
+    f[d] = uu - fl;
+    const int i = (int)fl;
+    i0[d] = min(max(i, 0), n[d] - 1);
+    i1[d] = min(max(i + 1, 0), n[d] - 1);
+  }
+  const size_t sy = (size_t)G.nx, sz = (size_t)G.nx * G.ny;
+  const size_t r00 = i0[2] * sz + i0[1] * sy, r01 = i0[2] * sz + i1[1] * sy;
+  const size_t r10 = i1[2] * sz + i0[1] * sy, r11 = i1[2] * sz + i1[1] * sy;
+  const float4 e000 = G.E[r00 + i0[0]], e001 = G.E[r00 + i1[0]];
+  const float4 e010 = G.E[r01 + i0[0]], e011 = G.E[r01 + i1[0]];
+  const float4 e100 = G.E[r10 + i0[0]], e101 = G.E[r10 + i1[0]];
+  const float4 e110 = G.E[r11 + i0[0]], e111 = G.E[r11 + i1[0]];
+  const float gx = f[0], gy = f[1], gz = f[2];
+  auto lx = [&](float4 a, float4 b) {
+    return make_float3(fmaf(gx, b.x - a.x, a.x), fmaf(gx, b.y - a.y, a.y), fmaf(gx, b.z - a.z, a.z));
+  };
+  auto l3 = [](float t, float3 a, float3 b) {
+    return make_float3(fmaf(t, b.x - a.x, a.x), fmaf(t, b.y - a.y, a.y), fmaf(t, b.z - a.z, a.z));
+  };
+  const float3 e00 = lx(e000, e001), e01 = lx(e010, e011), e10 = lx(e100, e101), e11 = lx(e110, e111);
+  const float3 e0 = l3(gy, e00, e01), e1 = l3(gy, e10, e11);
+  const float3 e = l3(gz, e0, e1);
+  return make_float3(qm * e.x, qm * e.y, qm * e.z);
+}
+
+// Acceleration bounds for the rest of a step of length t_rem: local ones if
+// the particle cannot leave its cell neighbourhood (displacement below one
+// cell with a 2^-10 margin), else the global bound.
+__device__ __forceinline__ void accel_bound(const GridView& G, float x, float y, float z, float speed, float t_rem,
+                                            float& a_abs, float& da) {
+  const float D = fmaf(0.5f * G.a_glob * t_rem, t_rem, speed * t_rem);
+  if (!(D < G.dx * (1.0f - 0x1p-10f))) {
+    a_abs = G.a_glob;
+    da = 2.0f * G.a_glob;
+    return;
+  }
+  const float u[3] = {(x - G.x0) * G.inv_dx - 0.5f, (y - G.y0) * G.inv_dx - 0.5f, (z - G.z0) * G.inv_dx - 0.5f};
+  const int n[3] = {G.nx, G.ny, G.nz};
+  int b[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const float uu = fminf(fmaxf(u[d], -1.0f), (float)n[d]);
+    b[d] = min(max((int)floorf(uu), 0), n[d] - 1);
+  }
+  const float2 m = G.bound[((size_t)b[2] * G.ny + b[1]) * G.nx + b[0]];
+  a_abs = G.qm_abs * m.x;
+  da = G.qm_abs * m.y;
+}
+
+}  // namespace pcmcc

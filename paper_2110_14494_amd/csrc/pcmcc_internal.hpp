@@ -1,0 +1,97 @@
+// Internal types shared by the kernels and the host runtime of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pcmcc.h"
+#include "pcmcc_device.hpp"
+
+namespace pcmcc {
+
+struct PState {
+  float x, y, z, vx, vy, vz, w;
+  uint64_t id;
+};
+
+// Particle arrays (structure of arrays).
+struct Soa {
+  float *x, *y, *z, *vx, *vy, *vz, *w;
+  uint64_t* id;
+};
+
+// Newborn queue: particle arrays plus the birth time within the step.
+struct PendSoa {
+  float *x, *y, *z, *vx, *vy, *vz, *w, *tb;
+  uint64_t* id;
+};
+
+// Per-step event counters.
+enum CntIdx { C_TRIALS, C_NULL, C_EL, C_EXC, C_ION, C_ATT, C_LOST, C_OOT, C_ERR, NCNT };
+
+enum Overflow : unsigned { OVF_CAPACITY = 1u, OVF_LIMIT = 2u };
+
+// Device control block of a step loop.
+struct Ctl {
+  unsigned long long n_cur;   // live particles in the current buffer
+  unsigned long long holes;   // removed particles of this step (slots in the next buffer)
+  unsigned long long child;   // newborn survivors placed so far
+  unsigned long long donors;  // tail donors found (hole filling)
+  unsigned long long fill;    // holes filled from the tail
+  unsigned long long pend[kMaxGenerations + 1];  // newborns queued per generation
+  unsigned overflow;          // Overflow bits of the running step
+  int cur_sel;                // 0: the caller's arrays are current, 1: the scratch buffer
+  int stop;
+  int status;
+  long long steps_done;
+  unsigned long long particle_steps;
+  unsigned long long tot[NCNT];
+};
+
+struct PicArgs {
+  Soa buf[2];
+  PendSoa pend[2];
+  uint32_t* holes;
+  uint32_t* flags;
+  uint32_t* donor;
+  unsigned long long* partial;  // [grid][NCNT]
+  uint64_t cap, pend_cap;
+  Ctl* ctl;
+  const unsigned* emax_bits;  // max |E| over the cells, as float bits
+  TableView T;
+  SpeciesView S;
+  GridView G;
+  Key key;
+  uint32_t step0;
+  int n_steps;
+  float dt;
+};
+
+struct DepositGeom {
+  int nx, ny, nz;
+  double x0, y0, z0, inv_dx;
+};
+
+struct TableBuild {
+  int n, nproc;
+  double lnmin, dlog, ev, mass, gas_N;
+  int rates, effective;
+  int kind[kMaxProc];
+  const double* sigma;  // device [nproc][n]
+  double* total;        // device scratch [n]
+};
+
+size_t table_lds_bytes(const TableView& T);
+hipError_t launch_pic_steps(const PicArgs& args, int grid, int block, hipStream_t stream);
+hipError_t occupancy_pic_steps(int block, size_t lds, int* blocks_per_cu);
+hipError_t launch_finalize(const Soa& user, const Soa& scratch, Ctl* ctl, int64_t* n_dev, hipStream_t stream);
+hipError_t launch_deposit(const float* x, const float* y, const float* z, const float* w, const int64_t* n_dev,
+                          const DepositGeom& g, int64_t* rho, hipStream_t stream);
+hipError_t launch_field_bounds(const float4* E, int nx, int ny, int nz, float2* out, unsigned* emax_bits,
+                               hipStream_t stream);
+hipError_t launch_build_tables(const TableBuild& B, float* C, float* P, float* nu, hipStream_t stream);
+hipError_t launch_philox(const uint32_t* ctr, Key key, uint32_t* out, int64_t n, hipStream_t stream);
+hipError_t launch_lookup(const TableView& T, const SpeciesView& S, const float* eps, float* cum, const float* s_ub,
+                         float* maj, int64_t n, hipStream_t stream);
+
+}  // namespace pcmcc

@@ -1,0 +1,678 @@
+// HIP kernels of the PIC-MCC electron update (gfx950, wave64).
+//
+// Method: arXiv:2110.14494 Sec. 2.1.  Per time step every electron is
+// advanced with velocity Verlet (Sec. 2.1.1 eq. (1)-(2)) through flight
+// segments that end in real or null collisions (null-collision method,
+// Sec. 2.1.1) against tabulated rates (Sec. 2.1.5); ionization appends a
+// newborn electron that is advanced from its birth time in the same step,
+// attachment removes the electron; the charge is then mapped to the grid by
+// trilinear weighting (Sec. 2.1.3).
+//
+// Layout: particles are structure-of-arrays single precision (x, y, z, vx,
+// vy, vz, w) plus a 64-bit id; each wave owns contiguous runs of 64
+// particles, so every load and store is a coalesced 256-byte row per array.
+// A step never moves survivors: particle i of the current buffer is written
+// to slot i of the next buffer (ping-pong, so a step that would overflow the
+// capacity leaves the previous state intact); the few removed particles
+// leave holes that the step's newborns fill first, and any holes left over
+// are filled from the tail.  Only newborns and holes take atomics, one per
+// wave and event.
+#include <hip/hip_cooperative_groups.h>
+#include <hip/hip_runtime.h>
+
+#include "pcmcc_device.hpp"
+#include "pcmcc_internal.hpp"
+
+namespace cg = cooperative_groups;
+
+namespace pcmcc {
+
+// ---------------------------------------------------------------------------
+// small device helpers
+
+template <class T>
+__device__ __forceinline__ T ld_acq(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint32_t rank_in(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Reserves one slot per calling lane in a counter with a single atomic for
+// the wave: every active lane that calls it gets base + its rank.
+__device__ __forceinline__ uint64_t wave_reserve(unsigned long long* counter) {
+  const uint64_t mask = __ballot(1);
+  const int leader = __ffsll((unsigned long long)mask) - 1;
+  uint64_t base = 0;
+  if ((int)lane_id() == leader) base = atomicAdd(counter, (unsigned long long)__popcll(mask));
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)base, leader);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(base >> 32), leader);
+  return (((uint64_t)hi << 32) | lo) + rank_in(mask);
+}
+
+struct Cnt {
+  uint32_t v[NCNT];
+};
+
+__device__ __forceinline__ void load_p(const Soa& s, uint64_t i, PState& p) {
+  p.x = s.x[i];
+  p.y = s.y[i];
+  p.z = s.z[i];
+  p.vx = s.vx[i];
+  p.vy = s.vy[i];
+  p.vz = s.vz[i];
+  p.w = s.w[i];
+  p.id = s.id[i];
+}
+
+__device__ __forceinline__ void store_p(const Soa& s, uint64_t i, const PState& p) {
+  s.x[i] = p.x;
+  s.y[i] = p.y;
+  s.z[i] = p.z;
+  s.vx[i] = p.vx;
+  s.vy[i] = p.vy;
+  s.vz[i] = p.vz;
+  s.w[i] = p.w;
+  s.id[i] = p.id;
+}
+
+__device__ __forceinline__ void load_pend(const PendSoa& s, uint64_t i, PState& p, float& tb) {
+  p.x = s.x[i];
+  p.y = s.y[i];
+  p.z = s.z[i];
+  p.vx = s.vx[i];
+  p.vy = s.vy[i];
+  p.vz = s.vz[i];
+  p.w = s.w[i];
+  p.id = s.id[i];
+  tb = s.tb[i];
+}
+
+// Queue of newborns of one generation.
+struct BirthSink {
+  PendSoa q;
+  unsigned long long* count;
+  uint64_t cap;
+  unsigned* overflow;
+  __device__ __forceinline__ void push(const PState& c, float tb) const {
+    const uint64_t slot = wave_reserve(count);
+    if (slot < cap) {
+      q.x[slot] = c.x;
+      q.y[slot] = c.y;
+      q.z[slot] = c.z;
+      q.vx[slot] = c.vx;
+      q.vy[slot] = c.vy;
+      q.vz[slot] = c.vz;
+      q.w[slot] = c.w;
+      q.id[slot] = c.id;
+      q.tb[slot] = tb;
+    } else {
+      atomicOr(overflow, OVF_CAPACITY);
+    }
+  }
+};
+
+// Field of the PIC step: the grid.
+struct GridField {
+  GridView G;
+  float qm;
+  __device__ __forceinline__ float3 accel(float x, float y, float z) const { return gather(G, qm, x, y, z); }
+  __device__ __forceinline__ void bound(float x, float y, float z, float speed, float t_rem, float& a_abs,
+                                        float& da) const {
+    accel_bound(G, x, y, z, speed, t_rem, a_abs, da);
+  }
+};
+
+// Tables as the kernels read them (staged in LDS).
+struct Tab {
+  const float* C;
+  const float* P;
+  const float* thr;
+  const int* kind;
+  int n, nproc;
+  float u_scale, u_offset, eps_max;
+};
+
+__device__ __forceinline__ float majorant_t(const Tab& T, const SpeciesView& S, float s_ub) {
+  const float s = s_ub * kGuard;
+  const float eps = S.k_eps * s * s;
+  float u = __log2f(eps) * T.u_scale + T.u_offset;
+  u = fminf(fmaxf(u, 0.0f), (float)(T.n - 1));
+  const float fl = fminf(floorf(u), (float)(T.n - 2));
+  const int i = (int)fl;
+  return lerp_at(T.P, i, u - fl);
+}
+
+// Advances one electron from time t to the end of the step (length dt).
+// Returns 0 if it is alive at the end of the step, 1 if attached, 2 if it
+// hit the segment limit.  Newborns go to `sink` with their birth time.
+template <class Field>
+__device__ int advance(PState& p, float t, float dt, const Field& F, const Tab& T, const SpeciesView& S, Key key,
+                       uint32_t step, Cnt& cnt, const BirthSink& sink) {
+  float3 a = F.accel(p.x, p.y, p.z);
+  float3 v = make_float3(p.vx, p.vy, p.vz);
+  float a_abs, da;
+  F.bound(p.x, p.y, p.z, sqrtf(v.x * v.x + v.y * v.y + v.z * v.z), dt - t, a_abs, da);
+  auto verlet = [&](float h) {
+    p.x = fmaf(fmaf(0.5f * a.x, h, v.x), h, p.x);
+    p.y = fmaf(fmaf(0.5f * a.y, h, v.y), h, p.y);
+    p.z = fmaf(fmaf(0.5f * a.z, h, v.z), h, p.z);
+    const float3 an = F.accel(p.x, p.y, p.z);
+    const float hh = 0.5f * h;
+    v.x = fmaf(a.x + an.x, hh, v.x);
+    v.y = fmaf(a.y + an.y, hh, v.y);
+    v.z = fmaf(a.z + an.z, hh, v.z);
+    a = an;
+  };
+  int result = 0;
+  for (uint32_t j = 0;; ++j) {
+    if (j >= (uint32_t)kMaxSegments) {
+      cnt.v[C_ERR]++;
+      result = 2;
+      break;
+    }
+    const uint4 r = draw(key, p.id, step, j, TAG_MAIN);
+    cnt.v[C_TRIALS]++;
+    const float t_rem = dt - t;
+    const float speed = sqrtf(v.x * v.x + v.y * v.y + v.z * v.z);
+    const float nu_full = majorant_t(T, S, speed_bound(v, a, speed, a_abs, da, t_rem));
+    const bool limited = kKappa < nu_full * t_rem;
+    const float h = limited ? kKappa / nu_full : t_rem;
+    const float nu_hat = limited ? majorant_t(T, S, speed_bound(v, a, speed, a_abs, da, h)) : nu_full;
+    const float tau = nu_hat > 0.0f ? -__logf(unif(r.x)) / nu_hat : INFINITY;
+    if (tau >= h) {  // no candidate collision within the horizon
+      verlet(h);
+      if (!limited) break;
+      t += h;
+      continue;
+    }
+    verlet(tau);
+    t += tau;
+    const float v2 = v.x * v.x + v.y * v.y + v.z * v.z;
+    const float eps = S.k_eps * v2;
+    float u = __log2f(eps) * T.u_scale + T.u_offset;
+    u = fminf(fmaxf(u, 0.0f), (float)(T.n - 1));
+    const float fl = fminf(floorf(u), (float)(T.n - 2));
+    const int i = (int)fl;
+    const float f = u - fl;
+    const float y = unif(r.y) * nu_hat;
+    int k = -1;
+    for (int kk = 0; kk < T.nproc; ++kk)
+      if (y < lerp_at(T.C + kk * T.n, i, f)) {
+        k = kk;
+        break;
+      }
+    if (k < 0 || eps < T.thr[k]) {
+      cnt.v[C_NULL]++;
+      continue;
+    }
+    if (eps > T.eps_max) cnt.v[C_OOT]++;
+    const int kind = T.kind[k];
+    cnt.v[C_EL + kind]++;
+    if (kind == ATTACHMENT) {
+      result = 1;
+      break;
+    }
+    const float cth = 1.0f - 2.0f * unif(r.z);
+    float sp, cp;
+    sincospif(2.0f * unif(r.w), &sp, &cp);
+    const float sth = sqrtf(fmaxf(0.0f, 1.0f - cth * cth));
+    const float nx = sth * cp, ny = sth * sp, nz = cth;
+    float eps_new;
+    if (kind == ELASTIC) {
+      const float sc = sqrtf(v2);
+      const float cchi = sc > 0.0f ? (v.x * nx + v.y * ny + v.z * nz) / sc : 0.0f;
+      eps_new = eps * (1.0f - S.recoil * (1.0f - cchi));
+    } else if (kind == EXCITATION) {
+      eps_new = eps - T.thr[k];
+    } else {
+      eps_new = 0.5f * (eps - T.thr[k]);
+      const uint4 b = draw(key, p.id, step, j, TAG_BIRTH);
+      PState c;
+      c.x = p.x;
+      c.y = p.y;
+      c.z = p.z;
+      c.w = p.w;
+      c.id = (uint64_t)b.x | ((uint64_t)b.y << 32);
+      const float ccth = 1.0f - 2.0f * unif(b.z);
+      float csp, ccp;
+      sincospif(2.0f * unif(b.w), &csp, &ccp);
+      const float csth = sqrtf(fmaxf(0.0f, 1.0f - ccth * ccth));
+      const float cs = sqrtf(eps_new * S.inv_k);
+      c.vx = cs * csth * ccp;
+      c.vy = cs * csth * csp;
+      c.vz = cs * ccth;
+      sink.push(c, t);
+    }
+    const float sn = sqrtf(eps_new * S.inv_k);
+    v = make_float3(sn * nx, sn * ny, sn * nz);
+  }
+  p.vx = v.x;
+  p.vy = v.y;
+  p.vz = v.z;
+  return result;
+}
+
+__device__ __forceinline__ bool inside(const GridView& G, const PState& p) {
+  return p.x >= G.x0 && p.x < G.x1 && p.y >= G.y0 && p.y < G.y1 && p.z >= G.z0 && p.z < G.z1;
+}
+
+// Stages the tables in LDS; returns the view the kernels read.
+__device__ Tab stage_tables(const TableView& TV, float* smem) {
+  const int nC = TV.nproc * TV.n;
+  for (int i = threadIdx.x; i < nC; i += blockDim.x) smem[i] = TV.C[i];
+  for (int i = threadIdx.x; i < TV.n; i += blockDim.x) smem[nC + i] = TV.P[i];
+  float* thr = smem + nC + TV.n;
+  int* kind = (int*)(thr + kMaxProc);
+  if (threadIdx.x < (unsigned)kMaxProc) {
+    thr[threadIdx.x] = TV.thr[threadIdx.x];
+    kind[threadIdx.x] = TV.kind[threadIdx.x];
+  }
+  __syncthreads();
+  Tab T;
+  T.C = smem;
+  T.P = smem + nC;
+  T.thr = thr;
+  T.kind = kind;
+  T.n = TV.n;
+  T.nproc = TV.nproc;
+  T.u_scale = TV.u_scale;
+  T.u_offset = TV.u_offset;
+  T.eps_max = TV.eps_top;
+  return T;
+}
+
+// Sums per-thread counters over the block into partial[blockIdx.x][*].
+__device__ void block_counters(const Cnt& c, unsigned long long* partial) {
+  __shared__ unsigned long long red[NCNT];
+  if (threadIdx.x < NCNT) red[threadIdx.x] = 0;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NCNT; ++k) {
+    uint32_t v = c.v[k];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane_id() == 0) atomicAdd(&red[k], (unsigned long long)v);
+  }
+  __syncthreads();
+  if (threadIdx.x < NCNT) partial[(size_t)blockIdx.x * NCNT + threadIdx.x] = red[threadIdx.x];
+}
+
+// ---------------------------------------------------------------------------
+// The step loop.  One cooperative launch runs all n_steps steps; grid-wide
+// barriers separate the phases of a step, and every loop bound that decides
+// a barrier is read after a barrier, so all blocks take the same path.
+__global__ __launch_bounds__(256) void k_pic_steps(PicArgs A) {
+  extern __shared__ float smem[];
+  cg::grid_group grid = cg::this_grid();
+  const Tab T = stage_tables(A.T, smem);
+  GridView G = A.G;
+  G.a_glob = G.qm_abs * __uint_as_float(*A.emax_bits);
+  const GridField F{G, A.S.qm};
+  const unsigned lane = lane_id();
+  const uint64_t wpb = blockDim.x >> 6;
+  const uint64_t gw = (uint64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
+  const uint64_t GW = (uint64_t)gridDim.x * wpb;
+  Ctl* ctl = A.ctl;
+
+  for (int s = 0; s < A.n_steps; ++s) {
+    if (ld_acq(&ctl->stop)) break;
+    const int sel = ld_acq(&ctl->cur_sel);
+    const Soa cur = A.buf[sel], nxt = A.buf[sel ^ 1];
+    const uint64_t n_cur = ld_acq(&ctl->n_cur);
+    const uint32_t step = A.step0 + (uint32_t)s;
+    Cnt cnt;
+#pragma unroll
+    for (int k = 0; k < NCNT; ++k) cnt.v[k] = 0;
+
+    // Phase 1: every particle of the current buffer, from t = 0.
+    {
+      const BirthSink sink{A.pend[0], &ctl->pend[0], A.pend_cap, &ctl->overflow};
+      for (uint64_t base = gw * 64; base < n_cur; base += GW * 64) {
+        const uint64_t i = base + lane;
+        if (i < n_cur) {
+          PState p;
+          load_p(cur, i, p);
+          const int r = advance(p, 0.0f, A.dt, F, T, A.S, A.key, step, cnt, sink);
+          bool alive = r == 0;
+          if (alive && !inside(A.G, p)) {
+            alive = false;
+            cnt.v[C_LOST]++;
+          }
+          if (alive) {
+            store_p(nxt, i, p);
+          } else {
+            A.holes[wave_reserve(&ctl->holes)] = (uint32_t)i;
+          }
+        }
+      }
+    }
+    grid.sync();
+
+    // Phase 2: newborns, one generation at a time.  Survivors fill the holes
+    // first, then append after the current count.
+    const uint64_t h = ld_acq(&ctl->holes);
+    for (int g = 0;; ++g) {
+      const uint64_t np_raw = ld_acq(&ctl->pend[g]);
+      if (np_raw == 0) break;
+      if (g >= kMaxGenerations) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&ctl->overflow, OVF_LIMIT);
+        break;
+      }
+      const uint64_t np = np_raw < A.pend_cap ? np_raw : A.pend_cap;
+      const PendSoa src = A.pend[g & 1];
+      const BirthSink sink{A.pend[(g + 1) & 1], &ctl->pend[g + 1], A.pend_cap, &ctl->overflow};
+      for (uint64_t base = gw * 64; base < np; base += GW * 64) {
+        const uint64_t i = base + lane;
+        if (i < np) {
+          PState p;
+          float tb;
+          load_pend(src, i, p, tb);
+          const int r = advance(p, tb, A.dt, F, T, A.S, A.key, step, cnt, sink);
+          bool alive = r == 0;
+          if (alive && !inside(A.G, p)) {
+            alive = false;
+            cnt.v[C_LOST]++;
+          }
+          if (alive) {
+            const uint64_t slot = wave_reserve(&ctl->child);
+            uint64_t dst;
+            if (slot < h) {
+              dst = A.holes[slot];
+            } else {
+              dst = n_cur + (slot - h);
+            }
+            if (dst < A.cap)
+              store_p(nxt, dst, p);
+            else
+              atomicOr(&ctl->overflow, OVF_CAPACITY);
+          }
+        }
+      }
+      grid.sync();
+    }
+
+    // Phase 3: holes not filled by newborns are filled from the tail.
+    const uint64_t nc = ld_acq(&ctl->child);
+    if (nc < h) {
+      const uint64_t r = h - nc;
+      const uint64_t n_new = n_cur - r;
+      const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+      const uint64_t nthr = (uint64_t)gridDim.x * blockDim.x;
+      for (uint64_t k = tid; k < r; k += nthr) A.flags[k] = 0;
+      grid.sync();
+      for (uint64_t k = tid; k < r; k += nthr) {
+        const uint64_t d = A.holes[nc + k];
+        if (d >= n_new) A.flags[d - n_new] = 1;
+      }
+      grid.sync();
+      for (uint64_t k = tid; k < r; k += nthr)
+        if (!A.flags[k]) A.donor[atomicAdd(&ctl->donors, 1ull)] = (uint32_t)(n_new + k);
+      grid.sync();
+      const uint64_t nd = ld_acq(&ctl->donors);
+      for (uint64_t k = tid; k < r; k += nthr) {
+        const uint64_t d = A.holes[nc + k];
+        if (d < n_new) {
+          const uint64_t m = atomicAdd(&ctl->fill, 1ull);
+          const uint64_t src = m < nd ? A.donor[m] : A.cap;
+          if (src < A.cap) {
+            PState p;
+            load_p(nxt, src, p);
+            store_p(nxt, d, p);
+          } else {
+            atomicOr(&ctl->overflow, OVF_LIMIT);  // inconsistent hole count: never expected
+          }
+        }
+      }
+    }
+    block_counters(cnt, A.partial);
+    grid.sync();
+
+    // Commit (block 0): accept the step, or stop and keep the previous state.
+    if (blockIdx.x == 0) {
+      __shared__ unsigned long long sums[NCNT];
+      if (threadIdx.x < NCNT) sums[threadIdx.x] = 0;
+      __syncthreads();
+      for (int k = 0; k < NCNT; ++k) {
+        unsigned long long acc = 0;
+        for (unsigned b = threadIdx.x; b < gridDim.x; b += blockDim.x) acc += A.partial[(size_t)b * NCNT + k];
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if (lane == 0) atomicAdd(&sums[k], acc);
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        const unsigned of = ld_acq(&ctl->overflow);
+        if (of) {
+          ctl->stop = 1;
+          ctl->status = (of & OVF_LIMIT) ? PCMCC_ELIMIT : PCMCC_ECAPACITY;
+        } else {
+          ctl->particle_steps += n_cur;
+          ctl->n_cur = n_cur + nc - h;
+          ctl->cur_sel = sel ^ 1;
+          ctl->steps_done += 1;
+          for (int k = 0; k < NCNT; ++k) ctl->tot[k] += sums[k];
+        }
+        ctl->holes = 0;
+        ctl->child = 0;
+        ctl->donors = 0;
+        ctl->fill = 0;
+        ctl->overflow = 0;
+        for (int g = 0; g <= kMaxGenerations; ++g) ctl->pend[g] = 0;
+      }
+    }
+    grid.sync();
+  }
+}
+
+// Copies the final state back to the caller's arrays if it ended in the
+// scratch buffer, and publishes the count.
+__global__ void k_finalize(Soa user, Soa scratch, Ctl* ctl, int64_t* n_dev) {
+  const uint64_t n = ctl->n_cur;
+  if (ctl->cur_sel == 1) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+      PState p;
+      load_p(scratch, i, p);
+      store_p(user, i, p);
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *n_dev = (int64_t)n;
+}
+
+// ---------------------------------------------------------------------------
+// Deposit: trilinear weights in double precision without contraction, each
+// corner rounded to 2^-32 fixed point and the last corner taking the
+// remainder, so the integer sum is independent of order and exactly
+// conserves round(w 2^32) per particle.
+__global__ void k_deposit(const float* __restrict__ x, const float* __restrict__ y, const float* __restrict__ z,
+                          const float* __restrict__ w, const int64_t* n_dev, DepositGeom g,
+                          unsigned long long* rho) {
+#pragma clang fp contract(off)
+  const uint64_t n = (uint64_t)*n_dev;
+  for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (uint64_t)gridDim.x * blockDim.x) {
+    const double pos[3] = {(double)x[p], (double)y[p], (double)z[p]};
+    const double o[3] = {g.x0, g.y0, g.z0};
+    const int nn[3] = {g.nx, g.ny, g.nz};
+    const double wd = (double)w[p];
+    const long long qw = __double2ll_rn(wd * 4294967296.0);
+    int ic[3][2];
+    double W[3][2];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      double u = (pos[d] - o[d]) * g.inv_dx - 0.5;
+      u = fmin(fmax(u, -1.0), (double)nn[d]);
+      const double fl = floor(u);
+      const double f = u - fl;
+      const int i = (int)fl;
+      ic[d][0] = min(max(i, 0), nn[d] - 1);
+      ic[d][1] = min(max(i + 1, 0), nn[d] - 1);
+      W[d][0] = 1.0 - f;
+      W[d][1] = f;
+    }
+    long long given = 0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int dz = c >> 2, dy = (c >> 1) & 1, dx = c & 1;
+      long long q;
+      if (c == 7) {
+        q = qw - given;
+      } else {
+        const double frac = (W[0][dx] * W[1][dy]) * W[2][dz];
+        q = __double2ll_rn((wd * frac) * 4294967296.0);
+        given += q;
+      }
+      const size_t cell = ((size_t)ic[2][dz] * g.ny + ic[1][dy]) * g.nx + ic[0][dx];
+      atomicAdd(&rho[cell], (unsigned long long)q);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Field bounds per cell: largest |E| over the 4x4x4 centres (i-1..i+2 per
+// axis, clamped) and the norm of the per-component ranges there; plus the
+// global maximum of |E| (as ordered bits of a non-negative float).
+__global__ void k_field_bounds(const float4* __restrict__ E, int nx, int ny, int nz, float2* __restrict__ out,
+                               unsigned* __restrict__ emax_bits) {
+  const size_t ncell = (size_t)nx * ny * nz;
+  float local_max = 0.0f;
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncell; c += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(c % nx);
+    const int j = (int)((c / nx) % ny);
+    const int k = (int)(c / ((size_t)nx * ny));
+    float m = 0.0f;
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int kk = max(k - 1, 0); kk <= min(k + 2, nz - 1); ++kk)
+      for (int jj = max(j - 1, 0); jj <= min(j + 2, ny - 1); ++jj)
+        for (int ii = max(i - 1, 0); ii <= min(i + 2, nx - 1); ++ii) {
+          const float4 e = E[((size_t)kk * ny + jj) * nx + ii];
+          m = fmaxf(m, sqrtf(e.x * e.x + e.y * e.y + e.z * e.z));
+          lo[0] = fminf(lo[0], e.x);
+          hi[0] = fmaxf(hi[0], e.x);
+          lo[1] = fminf(lo[1], e.y);
+          hi[1] = fmaxf(hi[1], e.y);
+          lo[2] = fminf(lo[2], e.z);
+          hi[2] = fmaxf(hi[2], e.z);
+        }
+    const float r0 = hi[0] - lo[0], r1 = hi[1] - lo[1], r2 = hi[2] - lo[2];
+    out[c] = make_float2(m, sqrtf(r0 * r0 + r1 * r1 + r2 * r2));
+    const float4 e = E[c];
+    local_max = fmaxf(local_max, sqrtf(e.x * e.x + e.y * e.y + e.z * e.z));
+  }
+  for (int off = 32; off > 0; off >>= 1) local_max = fmaxf(local_max, __shfl_xor(local_max, off));
+  if (lane_id() == 0) atomicMax(emax_bits, __float_as_uint(local_max));
+}
+
+// ---------------------------------------------------------------------------
+// Collision tables in double precision, stored as single precision: rates
+// nu_k = N sigma_k v at each node (Sec. 2.1.5), cumulative sums in process
+// order, prefix maximum of the total.
+__global__ void k_build_tables(TableBuild B, float* __restrict__ C, float* __restrict__ P,
+                               float* __restrict__ nu_out) {
+  const int n = B.n, np = B.nproc;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double eps = exp(B.lnmin + i * B.dlog);
+    const double v = sqrt(2.0 * B.ev * eps / B.mass);
+    double inel = 0.0;
+    for (int k = 0; k < np; ++k)
+      if (B.kind[k] != ELASTIC) inel += B.sigma[(size_t)k * n + i];
+    double acc = 0.0;
+    for (int k = 0; k < np; ++k) {
+      double s = B.sigma[(size_t)k * n + i];
+      if (B.effective && B.kind[k] == ELASTIC) s = fmax(0.0, s - inel);
+      const double rate = B.rates ? s : B.gas_N * s * v;
+      acc += rate;
+      nu_out[(size_t)k * n + i] = (float)rate;
+      C[(size_t)k * n + i] = (float)acc;
+      B.total[i] = acc;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double run = 0.0;
+    for (int i = 0; i < n; ++i) {
+      run = fmax(run, B.total[i]);
+      P[i] = (float)run;
+    }
+  }
+}
+
+// Self-test entry: raw Philox4x32-10 words.
+__global__ void k_philox(const uint4* __restrict__ ctr, Key key, uint4* __restrict__ out, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = philox(ctr[i], key);
+}
+
+// Table lookups exactly as the step kernel does them (LDS-staged tables).
+__global__ void k_lookup(TableView TV, SpeciesView S, const float* __restrict__ eps, float* __restrict__ cum,
+                         const float* __restrict__ s_ub, float* __restrict__ maj, int64_t n) {
+  extern __shared__ float smem[];
+  const Tab T = stage_tables(TV, smem);
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+    const float e = eps[q];
+    float u = __log2f(e) * T.u_scale + T.u_offset;
+    u = fminf(fmaxf(u, 0.0f), (float)(T.n - 1));
+    const float fl = fminf(floorf(u), (float)(T.n - 2));
+    const int i = (int)fl;
+    const float f = u - fl;
+    for (int k = 0; k < T.nproc; ++k) cum[q * T.nproc + k] = lerp_at(T.C + k * T.n, i, f);
+    if (maj) maj[q] = majorant_t(T, S, s_ub[q]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launch wrappers
+
+size_t table_lds_bytes(const TableView& T) {
+  return ((size_t)(T.nproc + 1) * T.n + 2 * kMaxProc) * sizeof(float);
+}
+
+hipError_t launch_pic_steps(const PicArgs& args, int grid, int block, hipStream_t stream) {
+  void* kargs[] = {(void*)&args};
+  return hipLaunchCooperativeKernel((const void*)k_pic_steps, dim3(grid), dim3(block), kargs,
+                                    (unsigned)table_lds_bytes(args.T), stream);
+}
+
+hipError_t occupancy_pic_steps(int block, size_t lds, int* blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void*)k_pic_steps, block, lds);
+}
+
+hipError_t launch_finalize(const Soa& user, const Soa& scratch, Ctl* ctl, int64_t* n_dev, hipStream_t stream) {
+  hipLaunchKernelGGL(k_finalize, dim3(2048), dim3(256), 0, stream, user, scratch, ctl, n_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_deposit(const float* x, const float* y, const float* z, const float* w, const int64_t* n_dev,
+                          const DepositGeom& g, int64_t* rho, hipStream_t stream) {
+  hipLaunchKernelGGL(k_deposit, dim3(4096), dim3(256), 0, stream, x, y, z, w, n_dev, g,
+                     (unsigned long long*)rho);
+  return hipGetLastError();
+}
+
+hipError_t launch_field_bounds(const float4* E, int nx, int ny, int nz, float2* out, unsigned* emax_bits,
+                               hipStream_t stream) {
+  const size_t ncell = (size_t)nx * ny * nz;
+  const int blocks = (int)std::min<size_t>((ncell + 255) / 256, 16384);
+  hipLaunchKernelGGL(k_field_bounds, dim3(blocks), dim3(256), 0, stream, E, nx, ny, nz, out, emax_bits);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_tables(const TableBuild& B, float* C, float* P, float* nu, hipStream_t stream) {
+  hipLaunchKernelGGL(k_build_tables, dim3(1), dim3(1024), 0, stream, B, C, P, nu);
+  return hipGetLastError();
+}
+
+hipError_t launch_philox(const uint32_t* ctr, Key key, uint32_t* out, int64_t n, hipStream_t stream) {
+  const int blocks = (int)std::min<int64_t>((n + 255) / 256 + 1, 4096);
+  hipLaunchKernelGGL(k_philox, dim3(blocks), dim3(256), 0, stream, (const uint4*)ctr, key, (uint4*)out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_lookup(const TableView& T, const SpeciesView& S, const float* eps, float* cum, const float* s_ub,
+                         float* maj, int64_t n, hipStream_t stream) {
+  const int blocks = (int)std::min<int64_t>((n + 255) / 256 + 1, 4096);
+  hipLaunchKernelGGL(k_lookup, dim3(blocks), dim3(256), table_lds_bytes(T), stream, T, S, eps, cum, s_ub, maj, n);
+  return hipGetLastError();
+}
+
+}  // namespace pcmcc

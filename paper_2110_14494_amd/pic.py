@@ -1,0 +1,164 @@
+"""Python-side handles for the C ABI: a context, device particle arrays and a
+device field grid, all backed by PyTorch tensors (memory and streams only).
+
+Every function forwards to libpcmcc.so; nothing here computes.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _binding as B
+
+FIELDS = ("x", "y", "z", "vx", "vy", "vz", "w")
+
+
+def _dev(device) -> torch.device:
+    d = torch.device(device) if not isinstance(device, torch.device) else device
+    if d.type != "cuda":
+        raise ValueError("pcmcc runs on a HIP device only")
+    return d
+
+
+class Particles:
+    """Structure-of-arrays electrons on the device with room for `capacity`."""
+
+    def __init__(self, capacity: int, device="cuda:0"):
+        dev = _dev(device)
+        self.capacity = int(capacity)
+        self.t = {k: torch.zeros(self.capacity, dtype=torch.float32, device=dev) for k in FIELDS}
+        self.t["id"] = torch.zeros(self.capacity, dtype=torch.int64, device=dev)
+        self.n_dev = torch.zeros(1, dtype=torch.int64, device=dev)
+
+    @classmethod
+    def from_numpy(cls, parts: dict, capacity: int | None = None, device="cuda:0") -> "Particles":
+        n = int(np.asarray(parts["x"]).size)
+        p = cls(capacity if capacity is not None else max(n, 1), device)
+        if n > p.capacity:
+            raise ValueError("more particles than capacity")
+        for k in FIELDS:
+            p.t[k][:n] = torch.from_numpy(np.ascontiguousarray(parts[k], dtype=np.float32))
+        p.t["id"][:n] = torch.from_numpy(np.ascontiguousarray(parts["id"], dtype=np.uint64).view(np.int64))
+        p.n_dev.fill_(n)
+        return p
+
+    @property
+    def n(self) -> int:
+        return int(self.n_dev.item())
+
+    def to_numpy(self) -> dict:
+        n = self.n
+        out = {k: self.t[k][:n].cpu().numpy() for k in FIELDS}
+        out["id"] = self.t["id"][:n].cpu().numpy().view(np.uint64)
+        return out
+
+    def struct(self) -> B.pcmcc_particles:
+        t = self.t
+        return B.pcmcc_particles(*(t[k].data_ptr() for k in FIELDS), t["id"].data_ptr(), self.n_dev.data_ptr(),
+                                 self.capacity)
+
+
+class DeviceGrid:
+    """Cell-centred field grid on the device (float4 per cell, x fastest)."""
+
+    def __init__(self, grid: dict, device="cuda:0"):
+        E = np.asarray(grid["E"], dtype=np.float32)
+        if E.ndim != 4 or E.shape[3] not in (3, 4):
+            raise ValueError("E must be [nz][ny][nx][3|4]")
+        if E.shape[3] == 3:
+            E = np.concatenate([E, np.zeros(E.shape[:3] + (1,), np.float32)], axis=3)
+        self.E = torch.from_numpy(np.ascontiguousarray(E)).to(_dev(device))
+        self.nz, self.ny, self.nx = E.shape[:3]
+        self.x0, self.y0, self.z0, self.dx = (float(grid[k]) for k in ("x0", "y0", "z0", "dx"))
+
+    def struct(self) -> B.pcmcc_grid:
+        return B.pcmcc_grid(self.E.data_ptr(), self.nx, self.ny, self.nz, self.x0, self.y0, self.z0, self.dx)
+
+    def zeros_rho(self) -> torch.Tensor:
+        return torch.zeros((self.nz, self.ny, self.nx), dtype=torch.int64, device=self.E.device)
+
+
+class Context:
+    """One library context on a device, issuing work on a torch stream."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
+        torch.cuda.set_device(device)
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        h = C.c_void_p()
+        B.check(B.lib().pcmcc_create(C.byref(h), device, C.c_void_p(self.stream.cuda_stream)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            B.lib().pcmcc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def last_error(self) -> str:
+        return B.lib().pcmcc_last_error(self.h).decode()
+
+    def init_species(self, species: dict):
+        B.check(B.lib().pcmcc_init_species(self.h, float(species["mass"]), float(species["charge"]),
+                                           float(species["gas_N"]), float(species["target_mass"])), self.h)
+
+    def init_tables(self, tables: dict) -> int:
+        kind = np.ascontiguousarray(tables["kind"], dtype=np.int32)
+        thr = np.ascontiguousarray(tables["threshold"], dtype=np.float64)
+        sig = np.ascontiguousarray(tables["sigma"], dtype=np.float64)
+        return B.lib().pcmcc_init_tables(self.h, int(sig.shape[1]), float(tables["eps_min"]),
+                                         float(tables["eps_max"]), int(sig.shape[0]),
+                                         kind.ctypes.data_as(C.c_void_p), thr.ctypes.data_as(C.c_void_p),
+                                         sig.ctypes.data_as(C.c_void_p), int(tables.get("flags", 0)))
+
+    def setup(self, species: dict, tables: dict):
+        self.init_species(species)
+        B.check(self.init_tables(tables), self.h)
+
+    def push_collide_deposit(self, parts: Particles, grid: DeviceGrid, dt: float, n_steps: int, seed: int,
+                             step0: int = 0, rho: torch.Tensor | None = None, check: bool = True):
+        st = B.pcmcc_stats()
+        ps, gs = parts.struct(), grid.struct()
+        rc = B.lib().pcmcc_push_collide_deposit(self.h, C.byref(ps), C.byref(gs), float(dt), int(n_steps),
+                                                int(seed), int(step0),
+                                                C.c_void_p(rho.data_ptr() if rho is not None else 0),
+                                                C.byref(st))
+        if check:
+            B.check(rc, self.h)
+        return rc, st.as_dict()
+
+    def deposit(self, parts: Particles, grid: DeviceGrid, rho: torch.Tensor):
+        t = parts.t
+        gs = grid.struct()
+        B.check(B.lib().pcmcc_deposit(self.h, t["x"].data_ptr(), t["y"].data_ptr(), t["z"].data_ptr(),
+                                      t["w"].data_ptr(), parts.n_dev.data_ptr(), C.byref(gs), rho.data_ptr()),
+                self.h)
+
+    def philox4x32_10(self, ctr: torch.Tensor, seed: int) -> torch.Tensor:
+        assert ctr.dtype == torch.int32 and ctr.is_contiguous() and ctr.shape[-1] == 4
+        out = torch.empty_like(ctr)
+        B.check(B.lib().pcmcc_philox4x32_10(self.h, ctr.shape[0], ctr.data_ptr(), int(seed), out.data_ptr()),
+                self.h)
+        return out
+
+    def tables_lookup(self, eps: torch.Tensor, n_proc: int, s_ub: torch.Tensor | None = None):
+        n = eps.numel()
+        cum = torch.empty((n, n_proc), dtype=torch.float32, device=eps.device)
+        maj = torch.empty(n, dtype=torch.float32, device=eps.device) if s_ub is not None else None
+        B.check(B.lib().pcmcc_tables_lookup(self.h, n, eps.data_ptr(), cum.data_ptr(),
+                                            s_ub.data_ptr() if s_ub is not None else None,
+                                            maj.data_ptr() if maj is not None else None), self.h)
+        return cum, maj
