@@ -240,6 +240,17 @@ struct Particle {
   double x[3], v[3], w;
   uint64_t id;
 };
+
+// The particle record holds single-precision position, velocity and weight
+// (the particle arrays are single precision); within a step everything is
+// computed in double precision and the record is rounded at the end of each
+// step and when a newborn is queued.
+void round_record(Particle& p) {
+  for (int c = 0; c < 3; ++c) {
+    p.x[c] = (double)(float)p.x[c];
+    p.v[c] = (double)(float)p.v[c];
+  }
+}
 struct Pending {
   Particle p;
   double tb;
@@ -442,7 +453,8 @@ int advance(const Tables& T, const Species& S, const Accel& accel, Particle& p, 
       c.p.v[0] = cs * csth * std::cos(cphi);
       c.p.v[1] = cs * csth * std::sin(cphi);
       c.p.v[2] = cs * ccth;
-      c.tb = t;
+      round_record(c.p);
+      c.tb = (double)(float)t;
       births.push_back(c);
     }
     const double s_new = std::sqrt(eps_new / S.k_eps);
@@ -480,10 +492,12 @@ void run_step(const Tables& T, const Species& S, const Accel& accel, const std::
         Particle p = work[i].p;
         const int r = advance(T, S, accel, p, work[i].tb, dt, key0, key1, step, my_births, my_cnt);
         if (r == 0) {
-          if (keep(p))
+          if (keep(p)) {
+            round_record(p);
             my_out.push_back(p);
-          else
+          } else {
             my_cnt.lost++;
+          }
         }
       }
 #pragma omp critical
@@ -606,8 +620,9 @@ int orc_pic_run(const orc_problem* pb, const orc_grid* g, double* x, double* y, 
     p.v[0] = vx[i];
     p.v[1] = vy[i];
     p.v[2] = vz[i];
-    p.w = w[i];
+    p.w = (double)(float)w[i];
     p.id = id[i];
+    round_record(p);
   }
   Counters total;
   int64_t steps_done = 0, particle_steps = 0;
