@@ -176,6 +176,8 @@ SpeciesView species_view(const pcmcc_ctx* c) {
   S.k_eps = (float)(0.5 * c->mass / kEV);
   S.inv_k = (float)(2.0 * kEV / c->mass);
   S.recoil = (float)(2.0 * c->mass / c->target_mass);
+  S.k_eps_d = 0.5 * c->mass / kEV;
+  S.inv_k_d = 2.0 * kEV / c->mass;
   return S;
 }
 
@@ -401,14 +403,17 @@ int pcmcc_push_collide_deposit(pcmcc_ctx* c, const pcmcc_particles* p, const pcm
   G.nx = field->nx;
   G.ny = field->ny;
   G.nz = field->nz;
-  G.x0 = (float)field->x0;
-  G.y0 = (float)field->y0;
-  G.z0 = (float)field->z0;
+  G.o[0] = field->x0;
+  G.o[1] = field->y0;
+  G.o[2] = field->z0;
   G.dx = (float)field->dx;
-  G.inv_dx = (float)(1.0 / field->dx);
-  G.x1 = (float)(field->x0 + field->nx * field->dx);
-  G.y1 = (float)(field->y0 + field->ny * field->dx);
-  G.z1 = (float)(field->z0 + field->nz * field->dx);
+  G.inv_dx = 1.0 / field->dx;
+  G.lo[0] = field->x0;
+  G.lo[1] = field->y0;
+  G.lo[2] = field->z0;
+  G.hi[0] = field->x0 + field->nx * field->dx;
+  G.hi[1] = field->y0 + field->ny * field->dx;
+  G.hi[2] = field->z0 + field->nz * field->dx;
   G.qm_abs = std::fabs(A.S.qm);
   A.key = Key{(uint32_t)seed, (uint32_t)(seed >> 32)};
   A.step0 = (uint32_t)step0;

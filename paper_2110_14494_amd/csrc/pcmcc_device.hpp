@@ -67,10 +67,12 @@ struct TableView {
 
 // Physical constants of the species and gas, single precision.
 struct SpeciesView {
-  float qm;       // q/m
-  float k_eps;    // eps[eV] = k_eps |v|^2
-  float inv_k;    // 1 / k_eps
-  float recoil;   // 2 m / M
+  float qm;        // q/m
+  float k_eps;     // eps[eV] = k_eps |v|^2
+  float inv_k;     // 1 / k_eps
+  float recoil;    // 2 m / M
+  double k_eps_d;  // the same two in double precision
+  double inv_k_d;
 };
 
 __device__ __forceinline__ void locate(const TableView& T, float eps, int& i, float& f) {
@@ -110,26 +112,35 @@ struct GridView {
   const float4* E;
   const float2* bound;  // per cell: (max |E| over the 4x4x4 centres, field range norm)
   int nx, ny, nz;
-  float x0, y0, z0;     // origin
-  float inv_dx, dx;
-  float x1, y1, z1;     // upper ends of the domain
+  double o[3];          // origin
+  double inv_dx;
+  float dx;
+  double lo[3], hi[3];  // domain
   float a_glob;         // |q/m| max |E|
   float qm_abs;
 };
 
+// Cell-centre coordinate u = (x - x0)/dx - 1/2 of one axis, clamped to
+// [-1, n], split into the lower centre index and the fraction.
+__device__ __forceinline__ void cell_coord(double x, double o, double inv_dx, int n, int& i, float& f) {
+  double u = (x - o) * inv_dx - 0.5;
+  u = fmin(fmax(u, -1.0), (double)n);
+  const double fl = floor(u);
+  i = (int)fl;
+  f = (float)(u - fl);
+}
+
 // Trilinear interpolation with clamped indices (constant outside the
 // outermost centres), returned as acceleration (q/m) E.
-__device__ __forceinline__ float3 gather(const GridView& G, float qm, float x, float y, float z) {
-  float u[3] = {(x - G.x0) * G.inv_dx - 0.5f, (y - G.y0) * G.inv_dx - 0.5f, (z - G.z0) * G.inv_dx - 0.5f};
+__device__ __forceinline__ float3 gather(const GridView& G, float qm, double x, double y, double z) {
   const int n[3] = {G.nx, G.ny, G.nz};
+  const double pos[3] = {x, y, z};
   int i0[3], i1[3];
   float f[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    const float uu = fminf(fmaxf(u[d], -1.0f), (float)n[d]);
-    const float fl = floorf(uu);
-    f[d] = uu - fl;
-    const int i = (int)fl;
+    int i;
+    cell_coord(pos[d], G.o[d], G.inv_dx, n[d], i, f[d]);
     i0[d] = min(max(i, 0), n[d] - 1);
     i1[d] = min(max(i + 1, 0), n[d] - 1);
   }
@@ -156,21 +167,23 @@ __device__ __forceinline__ float3 gather(const GridView& G, float qm, float x, f
 // Acceleration bounds for the rest of a step of length t_rem: local ones if
 // the particle cannot leave its cell neighbourhood (displacement below one
 // cell with a 2^-10 margin), else the global bound.
-__device__ __forceinline__ void accel_bound(const GridView& G, float x, float y, float z, float speed, float t_rem,
-                                            float& a_abs, float& da) {
+__device__ __forceinline__ void accel_bound(const GridView& G, double x, double y, double z, float speed,
+                                            float t_rem, float& a_abs, float& da) {
   const float D = fmaf(0.5f * G.a_glob * t_rem, t_rem, speed * t_rem);
   if (!(D < G.dx * (1.0f - 0x1p-10f))) {
     a_abs = G.a_glob;
     da = 2.0f * G.a_glob;
     return;
   }
-  const float u[3] = {(x - G.x0) * G.inv_dx - 0.5f, (y - G.y0) * G.inv_dx - 0.5f, (z - G.z0) * G.inv_dx - 0.5f};
   const int n[3] = {G.nx, G.ny, G.nz};
+  const double pos[3] = {x, y, z};
   int b[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    const float uu = fminf(fmaxf(u[d], -1.0f), (float)n[d]);
-    b[d] = min(max((int)floorf(uu), 0), n[d] - 1);
+    int i;
+    float f;
+    cell_coord(pos[d], G.o[d], G.inv_dx, n[d], i, f);
+    b[d] = min(max(i, 0), n[d] - 1);
   }
   const float2 m = G.bound[((size_t)b[2] * G.ny + b[1]) * G.nx + b[0]];
   a_abs = G.qm_abs * m.x;

@@ -12,6 +12,7 @@ namespace pcmcc {
 struct PState {
   float x, y, z, vx, vy, vz, w;
   uint64_t id;
+  double xd, yd, zd;  // end position before rounding (domain test)
 };
 
 // Particle arrays (structure of arrays).

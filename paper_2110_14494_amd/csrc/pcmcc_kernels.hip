@@ -119,8 +119,8 @@ struct BirthSink {
 struct GridField {
   GridView G;
   float qm;
-  __device__ __forceinline__ float3 accel(float x, float y, float z) const { return gather(G, qm, x, y, z); }
-  __device__ __forceinline__ void bound(float x, float y, float z, float speed, float t_rem, float& a_abs,
+  __device__ __forceinline__ float3 accel(double x, double y, double z) const { return gather(G, qm, x, y, z); }
+  __device__ __forceinline__ void bound(double x, double y, double z, float speed, float t_rem, float& a_abs,
                                         float& da) const {
     accel_bound(G, x, y, z, speed, t_rem, a_abs, da);
   }
@@ -149,22 +149,29 @@ __device__ __forceinline__ float majorant_t(const Tab& T, const SpeciesView& S, 
 // Advances one electron from time t to the end of the step (length dt).
 // Returns 0 if it is alive at the end of the step, 1 if attached, 2 if it
 // hit the segment limit.  Newborns go to `sink` with their birth time.
+//
+// Position, velocity, time and energy are carried in double precision within
+// the step (stored single precision between steps): on CDNA4 unpacked FP32
+// and FP64 fused multiply-adds issue at the same rate, and double keeps the
+// energy bookkeeping of tens of collisions per step free of drift.  Field,
+// tables, majorant and random numbers stay single precision.
 template <class Field>
-__device__ int advance(PState& p, float t, float dt, const Field& F, const Tab& T, const SpeciesView& S, Key key,
+__device__ int advance(PState& p, double t, double dt, const Field& F, const Tab& T, const SpeciesView& S, Key key,
                        uint32_t step, Cnt& cnt, const BirthSink& sink) {
-  float3 a = F.accel(p.x, p.y, p.z);
-  float3 v = make_float3(p.vx, p.vy, p.vz);
+  double x = p.x, y = p.y, z = p.z;
+  double vx = p.vx, vy = p.vy, vz = p.vz;
+  float3 a = F.accel(x, y, z);
   float a_abs, da;
-  F.bound(p.x, p.y, p.z, sqrtf(v.x * v.x + v.y * v.y + v.z * v.z), dt - t, a_abs, da);
-  auto verlet = [&](float h) {
-    p.x = fmaf(fmaf(0.5f * a.x, h, v.x), h, p.x);
-    p.y = fmaf(fmaf(0.5f * a.y, h, v.y), h, p.y);
-    p.z = fmaf(fmaf(0.5f * a.z, h, v.z), h, p.z);
-    const float3 an = F.accel(p.x, p.y, p.z);
-    const float hh = 0.5f * h;
-    v.x = fmaf(a.x + an.x, hh, v.x);
-    v.y = fmaf(a.y + an.y, hh, v.y);
-    v.z = fmaf(a.z + an.z, hh, v.z);
+  F.bound(x, y, z, sqrtf((float)(vx * vx + vy * vy + vz * vz)), (float)(dt - t), a_abs, da);
+  auto verlet = [&](double h) {
+    x += h * fma(0.5 * a.x, h, vx);
+    y += h * fma(0.5 * a.y, h, vy);
+    z += h * fma(0.5 * a.z, h, vz);
+    const float3 an = F.accel(x, y, z);
+    const double hh = 0.5 * h;
+    vx = fma((double)a.x + (double)an.x, hh, vx);
+    vy = fma((double)a.y + (double)an.y, hh, vy);
+    vz = fma((double)a.z + (double)an.z, hh, vz);
     a = an;
   };
   int result = 0;
@@ -176,13 +183,14 @@ __device__ int advance(PState& p, float t, float dt, const Field& F, const Tab& 
     }
     const uint4 r = draw(key, p.id, step, j, TAG_MAIN);
     cnt.v[C_TRIALS]++;
-    const float t_rem = dt - t;
-    const float speed = sqrtf(v.x * v.x + v.y * v.y + v.z * v.z);
-    const float nu_full = majorant_t(T, S, speed_bound(v, a, speed, a_abs, da, t_rem));
-    const bool limited = kKappa < nu_full * t_rem;
-    const float h = limited ? kKappa / nu_full : t_rem;
-    const float nu_hat = limited ? majorant_t(T, S, speed_bound(v, a, speed, a_abs, da, h)) : nu_full;
-    const float tau = nu_hat > 0.0f ? -__logf(unif(r.x)) / nu_hat : INFINITY;
+    const double t_rem = dt - t;
+    const float3 vf = make_float3((float)vx, (float)vy, (float)vz);
+    const float speed = sqrtf(vf.x * vf.x + vf.y * vf.y + vf.z * vf.z);
+    const float nu_full = majorant_t(T, S, speed_bound(vf, a, speed, a_abs, da, (float)t_rem));
+    const bool limited = kKappa < nu_full * (float)t_rem;
+    const double h = limited ? (double)(kKappa / nu_full) : t_rem;
+    const float nu_hat = limited ? majorant_t(T, S, speed_bound(vf, a, speed, a_abs, da, (float)h)) : nu_full;
+    const double tau = nu_hat > 0.0f ? (double)(-__logf(unif(r.x)) / nu_hat) : (double)INFINITY;
     if (tau >= h) {  // no candidate collision within the horizon
       verlet(h);
       if (!limited) break;
@@ -191,73 +199,91 @@ __device__ int advance(PState& p, float t, float dt, const Field& F, const Tab& 
     }
     verlet(tau);
     t += tau;
-    const float v2 = v.x * v.x + v.y * v.y + v.z * v.z;
-    const float eps = S.k_eps * v2;
-    float u = __log2f(eps) * T.u_scale + T.u_offset;
+    const double v2 = vx * vx + vy * vy + vz * vz;
+    const double eps = (double)S.k_eps_d * v2;
+    float u = __log2f((float)eps) * T.u_scale + T.u_offset;
     u = fminf(fmaxf(u, 0.0f), (float)(T.n - 1));
     const float fl = fminf(floorf(u), (float)(T.n - 2));
     const int i = (int)fl;
     const float f = u - fl;
-    const float y = unif(r.y) * nu_hat;
+    const float yv = unif(r.y) * nu_hat;
     int k = -1;
     for (int kk = 0; kk < T.nproc; ++kk)
-      if (y < lerp_at(T.C + kk * T.n, i, f)) {
+      if (yv < lerp_at(T.C + kk * T.n, i, f)) {
         k = kk;
         break;
       }
-    if (k < 0 || eps < T.thr[k]) {
+    if (k < 0 || eps < (double)T.thr[k]) {
       cnt.v[C_NULL]++;
       continue;
     }
-    if (eps > T.eps_max) cnt.v[C_OOT]++;
+    if (eps > (double)T.eps_max) cnt.v[C_OOT]++;
     const int kind = T.kind[k];
-    cnt.v[C_EL + kind]++;
+    // (register array: no dynamic index, which would move it to scratch)
+    cnt.v[C_EL] += kind == ELASTIC;
+    cnt.v[C_EXC] += kind == EXCITATION;
+    cnt.v[C_ION] += kind == IONIZATION;
+    cnt.v[C_ATT] += kind == ATTACHMENT;
     if (kind == ATTACHMENT) {
       result = 1;
       break;
     }
-    const float cth = 1.0f - 2.0f * unif(r.z);
+    // cos(theta) = 1 - 2U; sin(theta) = 2 sqrt(U (1 - U)) avoids the
+    // cancellation of 1 - cos^2 near the poles (U and 1 - U are exact).
+    const float uz = unif(r.z);
+    const float cth = 1.0f - 2.0f * uz;
     float sp, cp;
     sincospif(2.0f * unif(r.w), &sp, &cp);
-    const float sth = sqrtf(fmaxf(0.0f, 1.0f - cth * cth));
-    const float nx = sth * cp, ny = sth * sp, nz = cth;
-    float eps_new;
+    const float sth = 2.0f * sqrtf(uz * (1.0f - uz));
+    const double nx = (double)(sth * cp), ny = (double)(sth * sp), nz = (double)cth;
+    double eps_new;
     if (kind == ELASTIC) {
-      const float sc = sqrtf(v2);
-      const float cchi = sc > 0.0f ? (v.x * nx + v.y * ny + v.z * nz) / sc : 0.0f;
-      eps_new = eps * (1.0f - S.recoil * (1.0f - cchi));
+      const double sc = sqrt(v2);
+      const double cchi = sc > 0.0 ? (vx * nx + vy * ny + vz * nz) / sc : 0.0;
+      eps_new = eps * (1.0 - (double)S.recoil * (1.0 - cchi));
     } else if (kind == EXCITATION) {
-      eps_new = eps - T.thr[k];
+      eps_new = eps - (double)T.thr[k];
     } else {
-      eps_new = 0.5f * (eps - T.thr[k]);
+      eps_new = 0.5 * (eps - (double)T.thr[k]);
       const uint4 b = draw(key, p.id, step, j, TAG_BIRTH);
       PState c;
-      c.x = p.x;
-      c.y = p.y;
-      c.z = p.z;
+      c.x = (float)x;
+      c.y = (float)y;
+      c.z = (float)z;
       c.w = p.w;
       c.id = (uint64_t)b.x | ((uint64_t)b.y << 32);
-      const float ccth = 1.0f - 2.0f * unif(b.z);
+      const float bz = unif(b.z);
+      const float ccth = 1.0f - 2.0f * bz;
       float csp, ccp;
       sincospif(2.0f * unif(b.w), &csp, &ccp);
-      const float csth = sqrtf(fmaxf(0.0f, 1.0f - ccth * ccth));
-      const float cs = sqrtf(eps_new * S.inv_k);
-      c.vx = cs * csth * ccp;
-      c.vy = cs * csth * csp;
-      c.vz = cs * ccth;
-      sink.push(c, t);
+      const float csth = 2.0f * sqrtf(bz * (1.0f - bz));
+      const double cs = sqrt(eps_new * S.inv_k_d);
+      c.vx = (float)(cs * (double)(csth * ccp));
+      c.vy = (float)(cs * (double)(csth * csp));
+      c.vz = (float)(cs * (double)ccth);
+      sink.push(c, (float)t);
     }
-    const float sn = sqrtf(eps_new * S.inv_k);
-    v = make_float3(sn * nx, sn * ny, sn * nz);
+    const double sn = sqrt(eps_new * S.inv_k_d);
+    vx = sn * nx;
+    vy = sn * ny;
+    vz = sn * nz;
   }
-  p.vx = v.x;
-  p.vy = v.y;
-  p.vz = v.z;
+  p.x = (float)x;
+  p.y = (float)y;
+  p.z = (float)z;
+  p.vx = (float)vx;
+  p.vy = (float)vy;
+  p.vz = (float)vz;
+  p.xd = x;
+  p.yd = y;
+  p.zd = z;
   return result;
 }
 
+// Inside the grid, judged on the double-precision end position.
 __device__ __forceinline__ bool inside(const GridView& G, const PState& p) {
-  return p.x >= G.x0 && p.x < G.x1 && p.y >= G.y0 && p.y < G.y1 && p.z >= G.z0 && p.z < G.z1;
+  return p.xd >= G.lo[0] && p.xd < G.hi[0] && p.yd >= G.lo[1] && p.yd < G.hi[1] && p.zd >= G.lo[2] &&
+         p.zd < G.hi[2];
 }
 
 // Stages the tables in LDS; returns the view the kernels read.
