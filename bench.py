@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--workload", choices=["streamer", "stress", "plain"], default="streamer")
     ap.add_argument("--n", type=int, default=None, help="override the start count")
     ap.add_argument("--cap-factor", type=int, default=32)
+    ap.add_argument("--max-steps", type=int, default=None, help="cap the committed steps (profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2 ** 17)
     ap.add_argument("--cpu-steps", type=int, default=10)
@@ -110,7 +111,7 @@ def main():
     # Warmup: how many steps fit the capacity.
     reset()
     rc, st = ctx.push_collide_deposit(work, grid, cfg["dt"], cfg["n_steps"], cfg["seed"], check=False)
-    n_fit = st["steps_done"]
+    n_fit = st["steps_done"] if a.max_steps is None else min(st["steps_done"], a.max_steps)
     print(f"[bench] probe rc={rc} steps_done={n_fit} n={st['n']}", file=sys.stderr, flush=True)
     for _ in range(a.warmup):
         reset()

@@ -172,7 +172,7 @@ TableView table_view(const pcmcc_ctx* c) {
 
 SpeciesView species_view(const pcmcc_ctx* c) {
   SpeciesView S{};
-  S.qm = (float)(c->charge / c->mass);
+  S.qm = c->charge / c->mass;
   S.k_eps = (float)(0.5 * c->mass / kEV);
   S.inv_k = (float)(2.0 * kEV / c->mass);
   S.recoil = (float)(2.0 * c->mass / c->target_mass);
@@ -414,7 +414,7 @@ int pcmcc_push_collide_deposit(pcmcc_ctx* c, const pcmcc_particles* p, const pcm
   G.hi[0] = field->x0 + field->nx * field->dx;
   G.hi[1] = field->y0 + field->ny * field->dx;
   G.hi[2] = field->z0 + field->nz * field->dx;
-  G.qm_abs = std::fabs(A.S.qm);
+  G.qm_abs = (float)std::fabs(A.S.qm);
   A.key = Key{(uint32_t)seed, (uint32_t)(seed >> 32)};
   A.step0 = (uint32_t)step0;
   A.n_steps = n_steps;

@@ -67,7 +67,7 @@ struct TableView {
 
 // Physical constants of the species and gas, single precision.
 struct SpeciesView {
-  float qm;        // q/m
+  double qm;       // q/m
   float k_eps;     // eps[eV] = k_eps |v|^2
   float inv_k;     // 1 / k_eps
   float recoil;    // 2 m / M
@@ -131,8 +131,9 @@ __device__ __forceinline__ void cell_coord(double x, double o, double inv_dx, in
 }
 
 // Trilinear interpolation with clamped indices (constant outside the
-// outermost centres), returned as acceleration (q/m) E.
-__device__ __forceinline__ float3 gather(const GridView& G, float qm, double x, double y, double z) {
+// outermost centres), returned as acceleration (q/m) E with q/m applied in
+// double precision.
+__device__ __forceinline__ double3 gather(const GridView& G, double qm, double x, double y, double z) {
   const int n[3] = {G.nx, G.ny, G.nz};
   const double pos[3] = {x, y, z};
   int i0[3], i1[3];
@@ -161,7 +162,7 @@ __device__ __forceinline__ float3 gather(const GridView& G, float qm, double x, 
   const float3 e00 = lx(e000, e001), e01 = lx(e010, e011), e10 = lx(e100, e101), e11 = lx(e110, e111);
   const float3 e0 = l3(gy, e00, e01), e1 = l3(gy, e10, e11);
   const float3 e = l3(gz, e0, e1);
-  return make_float3(qm * e.x, qm * e.y, qm * e.z);
+  return make_double3(qm * e.x, qm * e.y, qm * e.z);
 }
 
 // Acceleration bounds for the rest of a step of length t_rem: local ones if

@@ -118,8 +118,8 @@ struct BirthSink {
 // Field of the PIC step: the grid.
 struct GridField {
   GridView G;
-  float qm;
-  __device__ __forceinline__ float3 accel(double x, double y, double z) const { return gather(G, qm, x, y, z); }
+  double qm;
+  __device__ __forceinline__ double3 accel(double x, double y, double z) const { return gather(G, qm, x, y, z); }
   __device__ __forceinline__ void bound(double x, double y, double z, float speed, float t_rem, float& a_abs,
                                         float& da) const {
     accel_bound(G, x, y, z, speed, t_rem, a_abs, da);
@@ -146,6 +146,22 @@ __device__ __forceinline__ float majorant_t(const Tab& T, const SpeciesView& S, 
   return lerp_at(T.P, i, u - fl);
 }
 
+// Isotropic unit vector from two uniforms: cos(theta) = 1 - 2 U1 and
+// sin(theta) = 2 sqrt(U1 (1 - U1)) (no cancellation near the poles; U1 and
+// 1 - U1 are exact), azimuth 2 pi U2 from a single-precision sincospi whose
+// (cos, sin) pair is renormalised so that |n| = 1 in double precision.
+__device__ __forceinline__ void iso_dir(uint32_t r1, uint32_t r2, double& nx, double& ny, double& nz) {
+  const double u = (double)unif(r1);
+  const double cth = 1.0 - 2.0 * u;
+  const double sth = 2.0 * sqrt(u * (1.0 - u));
+  float sp, cp;
+  sincospif(2.0f * unif(r2), &sp, &cp);
+  const double inv = sth / sqrt((double)cp * cp + (double)sp * sp);
+  nx = inv * cp;
+  ny = inv * sp;
+  nz = cth;
+}
+
 // Advances one electron from time t to the end of the step (length dt).
 // Returns 0 if it is alive at the end of the step, 1 if attached, 2 if it
 // hit the segment limit.  Newborns go to `sink` with their birth time.
@@ -160,18 +176,18 @@ __device__ int advance(PState& p, double t, double dt, const Field& F, const Tab
                        uint32_t step, Cnt& cnt, const BirthSink& sink) {
   double x = p.x, y = p.y, z = p.z;
   double vx = p.vx, vy = p.vy, vz = p.vz;
-  float3 a = F.accel(x, y, z);
+  double3 a = F.accel(x, y, z);
   float a_abs, da;
   F.bound(x, y, z, sqrtf((float)(vx * vx + vy * vy + vz * vz)), (float)(dt - t), a_abs, da);
   auto verlet = [&](double h) {
     x += h * fma(0.5 * a.x, h, vx);
     y += h * fma(0.5 * a.y, h, vy);
     z += h * fma(0.5 * a.z, h, vz);
-    const float3 an = F.accel(x, y, z);
+    const double3 an = F.accel(x, y, z);
     const double hh = 0.5 * h;
-    vx = fma((double)a.x + (double)an.x, hh, vx);
-    vy = fma((double)a.y + (double)an.y, hh, vy);
-    vz = fma((double)a.z + (double)an.z, hh, vz);
+    vx = fma(a.x + an.x, hh, vx);
+    vy = fma(a.y + an.y, hh, vy);
+    vz = fma(a.z + an.z, hh, vz);
     a = an;
   };
   int result = 0;
@@ -185,11 +201,12 @@ __device__ int advance(PState& p, double t, double dt, const Field& F, const Tab
     cnt.v[C_TRIALS]++;
     const double t_rem = dt - t;
     const float3 vf = make_float3((float)vx, (float)vy, (float)vz);
+    const float3 af = make_float3((float)a.x, (float)a.y, (float)a.z);
     const float speed = sqrtf(vf.x * vf.x + vf.y * vf.y + vf.z * vf.z);
-    const float nu_full = majorant_t(T, S, speed_bound(vf, a, speed, a_abs, da, (float)t_rem));
+    const float nu_full = majorant_t(T, S, speed_bound(vf, af, speed, a_abs, da, (float)t_rem));
     const bool limited = kKappa < nu_full * (float)t_rem;
     const double h = limited ? (double)(kKappa / nu_full) : t_rem;
-    const float nu_hat = limited ? majorant_t(T, S, speed_bound(vf, a, speed, a_abs, da, (float)h)) : nu_full;
+    const float nu_hat = limited ? majorant_t(T, S, speed_bound(vf, af, speed, a_abs, da, (float)h)) : nu_full;
     const double tau = nu_hat > 0.0f ? (double)(-__logf(unif(r.x)) / nu_hat) : (double)INFINITY;
     if (tau >= h) {  // no candidate collision within the horizon
       verlet(h);
@@ -230,12 +247,8 @@ __device__ int advance(PState& p, double t, double dt, const Field& F, const Tab
     }
     // cos(theta) = 1 - 2U; sin(theta) = 2 sqrt(U (1 - U)) avoids the
     // cancellation of 1 - cos^2 near the poles (U and 1 - U are exact).
-    const float uz = unif(r.z);
-    const float cth = 1.0f - 2.0f * uz;
-    float sp, cp;
-    sincospif(2.0f * unif(r.w), &sp, &cp);
-    const float sth = 2.0f * sqrtf(uz * (1.0f - uz));
-    const double nx = (double)(sth * cp), ny = (double)(sth * sp), nz = (double)cth;
+    double nx, ny, nz;
+    iso_dir(r.z, r.w, nx, ny, nz);
     double eps_new;
     if (kind == ELASTIC) {
       const double sc = sqrt(v2);
@@ -252,15 +265,12 @@ __device__ int advance(PState& p, double t, double dt, const Field& F, const Tab
       c.z = (float)z;
       c.w = p.w;
       c.id = (uint64_t)b.x | ((uint64_t)b.y << 32);
-      const float bz = unif(b.z);
-      const float ccth = 1.0f - 2.0f * bz;
-      float csp, ccp;
-      sincospif(2.0f * unif(b.w), &csp, &ccp);
-      const float csth = 2.0f * sqrtf(bz * (1.0f - bz));
+      double cx, cy, cz;
+      iso_dir(b.z, b.w, cx, cy, cz);
       const double cs = sqrt(eps_new * S.inv_k_d);
-      c.vx = (float)(cs * (double)(csth * ccp));
-      c.vy = (float)(cs * (double)(csth * csp));
-      c.vz = (float)(cs * (double)ccth);
+      c.vx = (float)(cs * cx);
+      c.vy = (float)(cs * cy);
+      c.vz = (float)(cs * cz);
       sink.push(c, (float)t);
     }
     const double sn = sqrt(eps_new * S.inv_k_d);
