@@ -99,6 +99,8 @@ typedef struct pcmcc_stats {
   uint64_t errors;               /* particles dropped at the per-step segment limit */
   double step_kernel_ms;         /* device time of the step loop kernel (HIP events on the stream) */
   double deposit_kernel_ms;      /* device time of the deposit kernel, 0 if skipped */
+  int32_t launch_block;          /* threads per block of the step loop kernel */
+  int32_t launch_grid;           /* blocks of the step loop kernel */
 } pcmcc_stats;
 
 /* Version string, static storage. */
@@ -156,6 +158,73 @@ int pcmcc_init_tables(pcmcc_ctx* ctx, int n_e, double eps_min_eV, double eps_max
  * committed steps and the deposit is skipped.  Synchronises the stream. */
 int pcmcc_push_collide_deposit(pcmcc_ctx* ctx, const pcmcc_particles* p, const pcmcc_grid* field, double dt,
                                int n_steps, uint64_t seed, uint64_t step0, int64_t* rho, pcmcc_stats* stats);
+
+/* ---- Batched uniform-field swarms (Sec. 2.2.1) ---------------------------
+ * Swarm s starts with n0[s] electrons at rest at the origin in the field
+ * E = EN_Td[s] * 1e-21 * N along +z and is advanced n_steps steps of dt with
+ * the same mover as pcmcc_push_collide_deposit (newborns, attachment), all
+ * swarms in one persistent launch.  Random numbers: Philox4x32-10 with key
+ * (seed low word, seed high word XOR s) and counter (id, step, segment,
+ * purpose); initial ids are 0..n0[s]-1.
+ * Every sample_every steps, after the step's newborns, the moments of each
+ * swarm are summed exactly (128-bit fixed point); then, with population
+ * control on, a swarm above 2 n0 keeps each electron with probability 2^-k
+ * (the smallest k that brings the expected size to 2 n0 or below) and a
+ * swarm below n0/2 duplicates every electron, the weight scale 2^L of the
+ * swarm following.  From the samples with t >= window_start_s:
+ *   W_flux = -<v_z> (time mean),  W_bulk = -d<z>/dt,
+ *   DL_flux = <dz dv_z>,  DL_bulk = (1/2) d var(z)/dt,
+ *   DT_flux = (1/2) <dx dv_x + dy dv_y>,  DT_bulk = (1/4) d (var x + var y)/dt,
+ *   nu_ion, nu_att = time means of the rate functions over the population,
+ *   nu_eff = d ln(N 2^L)/dt (temporal growth),  mean energy,
+ *   mu = W_flux/E,  alpha = nu_ion/W_flux,  eta = nu_att/W_flux,
+ *   W_bulk/W_flux; slopes are least-squares fits against time; errors are
+ *   batch means over n_batches contiguous sub-windows.  Drift is positive
+ *   along -E (electrons). */
+#define PCMCC_SWARM_NQ 14
+#define PCMCC_Q_W_FLUX 0
+#define PCMCC_Q_W_BULK 1
+#define PCMCC_Q_DL_FLUX 2
+#define PCMCC_Q_DL_BULK 3
+#define PCMCC_Q_DT_FLUX 4
+#define PCMCC_Q_DT_BULK 5
+#define PCMCC_Q_NU_ION 6
+#define PCMCC_Q_NU_ATT 7
+#define PCMCC_Q_NU_EFF 8
+#define PCMCC_Q_MEAN_EPS 9
+#define PCMCC_Q_MU 10
+#define PCMCC_Q_ALPHA 11
+#define PCMCC_Q_ETA 12
+#define PCMCC_Q_BULK_FLUX_RATIO 13
+#define PCMCC_SWARM_NMOM 14 /* moments per sample: count, Sx, Sy, Sz, S(x^2+y^2), Sz^2, Svx, Svy,
+                               Svz, S(x vx + y vy), S(z vz), S eps, S nu_ion(eps), S nu_att(eps) */
+
+typedef struct pcmcc_swarm_opts {
+  int sample_every;        /* steps between samples, >= 1 */
+  double window_start_s;   /* estimators use samples at t >= this */
+  int n_batches;           /* sub-windows of the batch-means error, >= 2 */
+  int cap_factor;          /* slots per swarm = cap_factor * n0, >= 4 */
+  int population_control;  /* 1 on, 0 off */
+  int block;               /* threads per block: 64, 128, 256, 512; 0 = tuned or default */
+  int blocks_per_cu;       /* persistent blocks per compute unit; 0 = tuned or default */
+  int autotune;            /* 1: time the candidate shapes on this input and keep the fastest */
+  const char* tune_cache;  /* JSON file the tuned shapes are read from and written to, or NULL */
+} pcmcc_swarm_opts;
+
+typedef struct pcmcc_swarm_result {
+  double value[PCMCC_SWARM_NQ];
+  double error[PCMCC_SWARM_NQ];
+} pcmcc_swarm_result;
+
+/* EN_Td[n_swarms], n0[n_swarms] host; out[n_swarms] host.  Optional host
+ * outputs (NULL to skip): moments_out[n_swarms][J][14] double sums and
+ * counters_out[n_swarms][J][4] (live count, L, cumulative ionizations,
+ * cumulative attachments), J = n_steps / sample_every.  1 <= n_swarms <= 4096,
+ * n0[s] >= 1.  PCMCC_ECAPACITY if a swarm outgrows its slots within a step.
+ * Synchronises the stream. */
+int pcmcc_swarm_batch(pcmcc_ctx* ctx, int n_swarms, const double* EN_Td, const int32_t* n0, double dt, int n_steps,
+                      uint64_t seed, const pcmcc_swarm_opts* opts, pcmcc_swarm_result* out, double* moments_out,
+                      int64_t* counters_out, pcmcc_stats* stats);
 
 /* Deposit only (Sec. 2.1.3), same fixed-point rule as above, on n_dev
  * particles (device count) of device arrays x, y, z, w. */

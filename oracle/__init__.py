@@ -73,7 +73,7 @@ def lib():
             L.orc_deposit.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_int, C.c_int, C.c_int,
                                       C.c_double, C.c_double, C.c_double, C.c_double, vp]
             L.orc_swarm_run.argtypes = [C.POINTER(Problem), C.c_int, vp, vp, C.c_double, C.c_int,
-                                        C.c_uint64, C.c_int, C.c_int64, vp, vp, vp, C.c_int]
+                                        C.c_uint64, C.c_int, C.c_int64, C.c_int, vp, vp, vp, C.c_int]
             _lib = L
     return _lib
 
@@ -203,7 +203,7 @@ def deposit(x, y, z, w, grid: dict) -> np.ndarray:
 
 
 def swarm_run(species: dict, tables: dict, EN_Td, n0, dt: float, n_steps: int, seed: int,
-              sample_every: int, cap_factor: int = 8, n_threads: int = 0):
+              sample_every: int, cap_factor: int = 8, n_threads: int = 0, population_control: bool = True):
     """Uniform-field swarms; returns (rc, moments[S,J,14], counters[S,J,4], stats)."""
     pb, keep = make_problem(species, tables)
     EN = np.ascontiguousarray(EN_Td, dtype=np.float64)
@@ -214,7 +214,7 @@ def swarm_run(species: dict, tables: dict, EN_Td, n0, dt: float, n_steps: int, s
     cnt = np.zeros((S, J, 4), dtype=np.int64)
     stats = np.zeros(12, dtype=np.int64)
     rc = lib().orc_swarm_run(C.byref(pb), S, _ptr(EN), _ptr(n0), float(dt), int(n_steps), int(seed),
-                             int(sample_every), int(cap_factor), _ptr(mom), _ptr(cnt), _ptr(stats),
-                             int(n_threads))
+                             int(sample_every), int(cap_factor), 1 if population_control else 0, _ptr(mom),
+                             _ptr(cnt), _ptr(stats), int(n_threads))
     del keep
     return rc, mom, cnt, dict(zip(STATS_FIELDS, (int(s) for s in stats)))

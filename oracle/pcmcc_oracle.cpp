@@ -715,11 +715,11 @@ int orc_deposit(const float* x, const float* y, const float* z, const float* w, 
 //                       S(x vx + y vy), S(z vz), S eps, S nu_ion(eps), S nu_att(eps)
 //   counters[s][j][4] = live count, log2 weight scale L, cumulative
 //                       ionizations, cumulative attachments.
-// Population control after each step: above 2 n0 every particle is kept with
+// Population control after each step (if pop_control): above 2 n0 every particle is kept with
 // probability 2^-k (the smallest k that brings the expected count to 2 n0 or
 // below) and L += k; below n0/2 every particle is duplicated and L -= 1.
 int orc_swarm_run(const orc_problem* pb, int n_swarms, const double* EN_Td, const int32_t* n0, double dt,
-                  int n_steps, uint64_t seed, int sample_every, int64_t cap_factor, double* moments,
+                  int n_steps, uint64_t seed, int sample_every, int64_t cap_factor, int pop_control, double* moments,
                   int64_t* counters, int64_t* stats, int n_threads) {
   Species S;
   Tables T;
@@ -799,7 +799,9 @@ int orc_swarm_run(const orc_problem* pb, int n_swarms, const double* EN_Td, cons
       // Population control.
       const int64_t N = (int64_t)cur.size();
       const int64_t n0s = n0[sw];
-      if (N > 2 * n0s) {
+      if (!pop_control) {
+        // off: the population is left as it is
+      } else if (N > 2 * n0s) {
         int k = 1;
         while (std::ldexp((double)N, -k) > 2.0 * (double)n0s) ++k;
         const double p_keep = std::ldexp(1.0, -k);

@@ -36,7 +36,8 @@ class pcmcc_stats(C.Structure):
     _fields_ = [("n", C.c_int64), ("steps_done", C.c_int64), ("particle_steps", C.c_uint64),
                 ("trials", C.c_uint64), ("null_collisions", C.c_uint64),
                 ("real_collisions", C.c_uint64 * 4), ("lost", C.c_uint64), ("out_of_table", C.c_uint64),
-                ("errors", C.c_uint64), ("step_kernel_ms", C.c_double), ("deposit_kernel_ms", C.c_double)]
+                ("errors", C.c_uint64), ("step_kernel_ms", C.c_double), ("deposit_kernel_ms", C.c_double),
+                ("launch_block", C.c_int32), ("launch_grid", C.c_int32)]
 
     def as_dict(self) -> dict:
         r = list(self.real_collisions)
@@ -44,7 +45,24 @@ class pcmcc_stats(C.Structure):
                 "trials": self.trials, "null": self.null_collisions, "elastic": r[0], "excitation": r[1],
                 "ionization": r[2], "attachment": r[3], "lost": self.lost,
                 "out_of_table": self.out_of_table, "errors": self.errors,
-                "step_kernel_ms": self.step_kernel_ms, "deposit_kernel_ms": self.deposit_kernel_ms}
+                "step_kernel_ms": self.step_kernel_ms, "deposit_kernel_ms": self.deposit_kernel_ms,
+                "launch_block": self.launch_block, "launch_grid": self.launch_grid}
+
+
+SWARM_QUANTITIES = ("W_flux", "W_bulk", "DL_flux", "DL_bulk", "DT_flux", "DT_bulk", "nu_ion", "nu_att",
+                    "nu_eff", "mean_eps", "mu", "alpha", "eta", "bulk_flux_ratio")
+SWARM_NQ = len(SWARM_QUANTITIES)
+SWARM_NMOM = 14
+
+
+class pcmcc_swarm_opts(C.Structure):
+    _fields_ = [("sample_every", C.c_int), ("window_start_s", C.c_double), ("n_batches", C.c_int),
+                ("cap_factor", C.c_int), ("population_control", C.c_int), ("block", C.c_int),
+                ("blocks_per_cu", C.c_int), ("autotune", C.c_int), ("tune_cache", C.c_char_p)]
+
+
+class pcmcc_swarm_result(C.Structure):
+    _fields_ = [("value", C.c_double * SWARM_NQ), ("error", C.c_double * SWARM_NQ)]
 
 
 class PcmccError(RuntimeError):
@@ -77,6 +95,8 @@ def lib() -> C.CDLL:
             "pcmcc_deposit": ([vp, vp, vp, vp, vp, vp, C.POINTER(pcmcc_grid), vp], C.c_int),
             "pcmcc_philox4x32_10": ([vp, i64, vp, u64, vp], C.c_int),
             "pcmcc_tables_lookup": ([vp, i64, vp, vp, vp, vp], C.c_int),
+            "pcmcc_swarm_batch": ([vp, C.c_int, vp, vp, C.c_double, C.c_int, u64, C.POINTER(pcmcc_swarm_opts),
+                                   vp, vp, vp, C.POINTER(pcmcc_stats)], C.c_int),
         }
         for name, (args, res) in sigs.items():
             f = getattr(L, name)

@@ -11,7 +11,11 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "pcmcc.h"
@@ -63,6 +67,25 @@ struct pcmcc_ctx {
   unsigned* emax_bits = nullptr;
   int64_t* host_n = nullptr;  // pinned
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // swarm batch scratch
+  struct Swarm {
+    uint64_t slots = 0, pend_cap = 0;
+    int S = 0, J = 0, grid = 0;
+    Soa buf[2]{};
+    PendSoa pend[2]{};
+    uint64_t *base = nullptr, *cap_s = nullptr;
+    int32_t* n0 = nullptr;
+    double *az = nullptr, *EN = nullptr;
+    unsigned long long *n_cur = nullptr, *n_nxt = nullptr, *cum_ion = nullptr, *cum_att = nullptr;
+    int* pc_k = nullptr;
+    long long* L = nullptr;
+    unsigned long long* mom = nullptr;
+    long long* cnt = nullptr;
+    unsigned long long *partial = nullptr, *partial_ps = nullptr;
+    SwarmCtl* ctl = nullptr;
+    double *values = nullptr, *errors = nullptr, *work = nullptr;
+  } sw;
+  std::map<std::string, std::pair<int, int>> tuned;  // shape key -> (block, blocks per CU)
 };
 
 namespace {
@@ -143,6 +166,126 @@ int ensure_scratch(pcmcc_ctx* c, uint64_t cap) {
   c->cap = cap;
   c->pend_cap = pc;
   return PCMCC_OK;
+}
+
+void free_soa(Soa& b) {
+  float** fs[] = {&b.x, &b.y, &b.z, &b.vx, &b.vy, &b.vz, &b.w};
+  for (float** f : fs) {
+    dfree(*f);
+    *f = nullptr;
+  }
+  dfree(b.id);
+  b.id = nullptr;
+}
+
+void free_pend(PendSoa& q) {
+  float** qs[] = {&q.x, &q.y, &q.z, &q.vx, &q.vy, &q.vz, &q.w, &q.tb};
+  for (float** f : qs) {
+    dfree(*f);
+    *f = nullptr;
+  }
+  dfree(q.id);
+  dfree(q.sw);
+  q.id = nullptr;
+  q.sw = nullptr;
+}
+
+void free_swarm(pcmcc_ctx* c) {
+  auto& w = c->sw;
+  for (auto& b : w.buf) free_soa(b);
+  for (auto& q : w.pend) free_pend(q);
+  void* ps[] = {w.base, w.cap_s, w.n0, w.az, w.EN, w.n_cur, w.n_nxt, w.cum_ion, w.cum_att, w.pc_k, w.L,
+                w.mom, w.cnt, w.partial, w.partial_ps, w.ctl, w.values, w.errors, w.work};
+  for (void* q : ps) dfree(q);
+  w = pcmcc_ctx::Swarm{};
+}
+
+int alloc_soa(pcmcc_ctx* c, Soa& b, uint64_t n) {
+  float** fs[] = {&b.x, &b.y, &b.z, &b.vx, &b.vy, &b.vz, &b.w};
+  for (float** f : fs) HIP_TRY(c, dalloc(f, n));
+  HIP_TRY(c, dalloc(&b.id, n));
+  return PCMCC_OK;
+}
+
+int alloc_pend(pcmcc_ctx* c, PendSoa& q, uint64_t n, bool with_sw) {
+  float** qs[] = {&q.x, &q.y, &q.z, &q.vx, &q.vy, &q.vz, &q.w, &q.tb};
+  for (float** f : qs) HIP_TRY(c, dalloc(f, n));
+  HIP_TRY(c, dalloc(&q.id, n));
+  if (with_sw) HIP_TRY(c, dalloc(&q.sw, n));
+  return PCMCC_OK;
+}
+
+// Swarm scratch for S swarms, `slots` particle slots, J samples, `grid` blocks.
+int ensure_swarm(pcmcc_ctx* c, int S, uint64_t slots, int J, int grid) {
+  auto& w = c->sw;
+  if (w.S >= S && w.slots >= slots && w.J >= J && w.grid >= grid && w.ctl) return PCMCC_OK;
+  free_swarm(c);
+  int rc;
+  for (auto& b : w.buf)
+    if ((rc = alloc_soa(c, b, slots))) return rc;
+  const uint64_t pc = std::max<uint64_t>(slots / 4, 1 << 16);
+  for (auto& q : w.pend)
+    if ((rc = alloc_pend(c, q, pc, true))) return rc;
+  HIP_TRY(c, dalloc(&w.base, S));
+  HIP_TRY(c, dalloc(&w.cap_s, S));
+  HIP_TRY(c, dalloc(&w.n0, S));
+  HIP_TRY(c, dalloc(&w.az, S));
+  HIP_TRY(c, dalloc(&w.EN, S));
+  HIP_TRY(c, dalloc(&w.n_cur, S));
+  HIP_TRY(c, dalloc(&w.n_nxt, S));
+  HIP_TRY(c, dalloc(&w.cum_ion, S));
+  HIP_TRY(c, dalloc(&w.cum_att, S));
+  HIP_TRY(c, dalloc(&w.pc_k, S));
+  HIP_TRY(c, dalloc(&w.L, S));
+  HIP_TRY(c, dalloc(&w.mom, (size_t)S * J * kNMom * 2));
+  HIP_TRY(c, dalloc(&w.cnt, (size_t)S * J * 4));
+  HIP_TRY(c, dalloc(&w.partial, (size_t)grid * NCNT));
+  HIP_TRY(c, dalloc(&w.partial_ps, (size_t)grid));
+  HIP_TRY(c, dalloc(&w.ctl, 1));
+  HIP_TRY(c, dalloc(&w.values, (size_t)S * kNQ));
+  HIP_TRY(c, dalloc(&w.errors, (size_t)S * kNQ));
+  HIP_TRY(c, dalloc(&w.work, (size_t)S * 11 * J));
+  w.S = S;
+  w.slots = slots;
+  w.J = J;
+  w.grid = grid;
+  w.pend_cap = pc;
+  return PCMCC_OK;
+}
+
+// Tuning cache: a flat JSON object {"key": [block, blocks_per_cu], ...}.
+void load_tune_cache(pcmcc_ctx* c, const char* path) {
+  if (!path) return;
+  std::ifstream f(path);
+  if (!f) return;
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string t = ss.str();
+  size_t p = 0;
+  while ((p = t.find('"', p)) != std::string::npos) {
+    const size_t q = t.find('"', p + 1);
+    if (q == std::string::npos) break;
+    const std::string key = t.substr(p + 1, q - p - 1);
+    int b = 0, k = 0;
+    const size_t lb = t.find('[', q);
+    if (lb == std::string::npos) break;
+    if (std::sscanf(t.c_str() + lb, "[%d , %d]", &b, &k) == 2 && b > 0 && k > 0) c->tuned[key] = {b, k};
+    p = t.find(']', lb);
+    if (p == std::string::npos) break;
+  }
+}
+
+void save_tune_cache(pcmcc_ctx* c, const char* path) {
+  if (!path) return;
+  std::ofstream f(path);
+  if (!f) return;
+  f << "{\n";
+  size_t i = 0;
+  for (const auto& kv : c->tuned) {
+    f << "  \"" << kv.first << "\": [" << kv.second.first << ", " << kv.second.second << "]";
+    f << (++i < c->tuned.size() ? ",\n" : "\n");
+  }
+  f << "}\n";
 }
 
 bool valid_grid(const pcmcc_grid* g) {
@@ -252,6 +395,7 @@ int pcmcc_destroy(pcmcc_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
   free_scratch(c);
+  free_swarm(c);
   dfree(c->dC);
   dfree(c->dP);
   dfree(c->dNu);
@@ -441,6 +585,8 @@ int pcmcc_push_collide_deposit(pcmcc_ctx* c, const pcmcc_particles* p, const pcm
     float ms = 0;
     HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
     stats->step_kernel_ms = ms;
+    stats->launch_block = block;
+    stats->launch_grid = grid;
     stats->n = (int64_t)h.n_cur;
     stats->steps_done = h.steps_done;
     stats->particle_steps = h.particle_steps;
@@ -457,6 +603,201 @@ int pcmcc_push_collide_deposit(pcmcc_ctx* c, const pcmcc_particles* p, const pcm
   if (rc == PCMCC_ELIMIT) return fail(c, rc, "newborn generation limit reached after %lld steps", (long long)h.steps_done);
   return rc;
 }
+
+namespace {
+
+// One run of the swarm step loop with a given launch shape (inputs already
+// on the device); the kernel time in ms goes to *ms.
+int swarm_run(pcmcc_ctx* c, SwarmArgs& A, int S, const std::vector<uint64_t>& n0h, int block, int grid,
+              float* ms) {
+  auto& w = c->sw;
+  HIP_TRY(c, hipMemsetAsync(w.n_nxt, 0, sizeof(unsigned long long) * S, c->stream));
+  HIP_TRY(c, hipMemsetAsync(w.cum_ion, 0, sizeof(unsigned long long) * S, c->stream));
+  HIP_TRY(c, hipMemsetAsync(w.cum_att, 0, sizeof(unsigned long long) * S, c->stream));
+  HIP_TRY(c, hipMemsetAsync(w.pc_k, 0, sizeof(int) * S, c->stream));
+  HIP_TRY(c, hipMemsetAsync(w.L, 0, sizeof(long long) * S, c->stream));
+  HIP_TRY(c, hipMemsetAsync(w.mom, 0, sizeof(unsigned long long) * S * A.n_samples * kNMom * 2, c->stream));
+  HIP_TRY(c, hipMemsetAsync(w.cnt, 0, sizeof(long long) * S * A.n_samples * 4, c->stream));
+  HIP_TRY(c, hipMemsetAsync(w.ctl, 0, sizeof(SwarmCtl), c->stream));
+  HIP_TRY(c, hipMemcpyAsync(w.n_cur, n0h.data(), sizeof(uint64_t) * S, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, launch_swarm_init(w.buf[0], w.base, w.n0, S, c->stream));
+  HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
+  HIP_TRY(c, launch_swarm_steps(A, grid, block, c->stream));
+  HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
+  HIP_TRY(c, hipEventSynchronize(c->ev[1]));
+  HIP_TRY(c, hipEventElapsedTime(ms, c->ev[0], c->ev[1]));
+  return PCMCC_OK;
+}
+
+}  // namespace
+
+int pcmcc_swarm_batch(pcmcc_ctx* c, int n_swarms, const double* EN_Td, const int32_t* n0, double dt, int n_steps,
+                      uint64_t seed, const pcmcc_swarm_opts* opts, pcmcc_swarm_result* out, double* moments_out,
+                      int64_t* counters_out, pcmcc_stats* stats) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  if (!EN_Td || !n0 || !opts || !out) return fail(c, PCMCC_EINVAL, "null argument");
+  const int S = n_swarms;
+  if (S < 1 || S > 4096) return fail(c, PCMCC_EINVAL, "n_swarms must be in [1, 4096]");
+  if (!(dt > 0) || !std::isfinite(dt) || n_steps < 1) return fail(c, PCMCC_EINVAL, "invalid dt or n_steps");
+  if (opts->sample_every < 1 || opts->n_batches < 2 || opts->cap_factor < 4 || !std::isfinite(opts->window_start_s))
+    return fail(c, PCMCC_EINVAL, "invalid swarm options");
+  const int J = n_steps / opts->sample_every;
+  if (J < 2 * opts->n_batches) return fail(c, PCMCC_EINVAL, "fewer samples than 2 * n_batches");
+  std::vector<uint64_t> base(S), caps(S), n0h(S);
+  std::vector<double> az(S);
+  uint64_t slots = 0;
+  for (int s = 0; s < S; ++s) {
+    if (n0[s] < 1) return fail(c, PCMCC_EINVAL, "n0[%d] < 1", s);
+    if (!(EN_Td[s] >= 0) || !std::isfinite(EN_Td[s])) return fail(c, PCMCC_EINVAL, "bad EN_Td[%d]", s);
+    base[s] = slots;
+    caps[s] = (uint64_t)opts->cap_factor * (uint64_t)n0[s];
+    n0h[s] = (uint64_t)n0[s];
+    slots += caps[s];
+    az[s] = (c->charge / c->mass) * EN_Td[s] * 1e-21 * c->gas_N;
+  }
+  if (slots > 0xFFFFFFFFull) return fail(c, PCMCC_EINVAL, "total swarm slots exceed 2^32");
+  HIP_TRY(c, hipSetDevice(c->device));
+  const TableView T = table_view(c);
+  // Launch shape: explicit, tuned (cached), or the default block of 256.
+  const int blocks[4] = {64, 128, 256, 512};
+  char keybuf[160];
+  std::snprintf(keybuf, sizeof(keybuf), "gfx950:k_swarm_steps:S%d:N%llu:cap%d:se%d:ne%d:np%d", S,
+                (unsigned long long)(slots / opts->cap_factor), opts->cap_factor, opts->sample_every, c->n_e,
+                c->n_proc);
+  const std::string key(keybuf);
+  load_tune_cache(c, opts->tune_cache);
+  int block = opts->block, bpc = opts->blocks_per_cu;
+  auto occ = [&](int b) {
+    int k = 0;
+    if (occupancy_swarm_steps(b, swarm_lds_bytes(T, S, b), &k) != hipSuccess) return 0;
+    return k;
+  };
+  if (block == 0 && !opts->autotune && c->tuned.count(key)) {
+    block = c->tuned[key].first;
+    bpc = c->tuned[key].second;
+  }
+  if (block == 0) block = 256;
+  if (block != 64 && block != 128 && block != 256 && block != 512)
+    return fail(c, PCMCC_EINVAL, "block must be 64, 128, 256 or 512");
+  const int max_grid = 32 * c->num_cu;
+  rc = ensure_swarm(c, S, slots, J, max_grid);
+  if (rc) return rc;
+  auto& w = c->sw;
+  HIP_TRY(c, hipMemcpyAsync(w.base, base.data(), sizeof(uint64_t) * S, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(w.cap_s, caps.data(), sizeof(uint64_t) * S, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(w.n0, n0, sizeof(int32_t) * S, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(w.az, az.data(), sizeof(double) * S, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(w.EN, EN_Td, sizeof(double) * S, hipMemcpyHostToDevice, c->stream));
+  SwarmArgs A{};
+  A.buf[0] = w.buf[0];
+  A.buf[1] = w.buf[1];
+  A.pend[0] = w.pend[0];
+  A.pend[1] = w.pend[1];
+  A.pend_cap = w.pend_cap;
+  A.n_swarms = S;
+  A.base = w.base;
+  A.cap_s = w.cap_s;
+  A.n0 = w.n0;
+  A.az = w.az;
+  A.ctl = w.ctl;
+  A.n_cur = w.n_cur;
+  A.n_nxt = w.n_nxt;
+  A.pc_k = w.pc_k;
+  A.L = w.L;
+  A.cum_ion = w.cum_ion;
+  A.cum_att = w.cum_att;
+  A.mom = w.mom;
+  A.cnt_out = w.cnt;
+  A.partial = w.partial;
+  A.partial_ps = w.partial_ps;
+  A.T = T;
+  A.S = species_view(c);
+  A.key = Key{(uint32_t)seed, (uint32_t)(seed >> 32)};
+  A.dt = (float)dt;
+  A.sample_every = opts->sample_every;
+  A.n_samples = J;
+  A.pop_control = opts->population_control ? 1 : 0;
+  float ms = 0;
+  if (opts->autotune) {
+    // Time each candidate shape on the first min(n_steps, 200) steps.
+    SwarmArgs probe = A;
+    probe.n_steps = std::min(n_steps, 200);
+    float best = 1e30f;
+    int best_b = 256, best_k = 1;
+    for (int b : blocks) {
+      const int kmax = std::min(occ(b), 32);
+      for (int k = 1; k <= kmax; k *= 2) {
+        float t = 0;
+        rc = swarm_run(c, probe, S, n0h, b, k * c->num_cu, &t);
+        if (rc) return rc;
+        if (t < best) {
+          best = t;
+          best_b = b;
+          best_k = k;
+        }
+      }
+    }
+    block = best_b;
+    bpc = best_k;
+    c->tuned[key] = {block, bpc};
+    save_tune_cache(c, opts->tune_cache);
+  }
+  const int kmax = std::min(occ(block), 32);
+  if (kmax < 1) return fail(c, PCMCC_EHIP, "swarm kernel does not fit on a compute unit");
+  if (bpc <= 0 || bpc > kmax) bpc = kmax;
+  const int grid = bpc * c->num_cu;
+  A.n_steps = n_steps;
+  rc = swarm_run(c, A, S, n0h, block, grid, &ms);
+  if (rc) return rc;
+  SwarmCtl hc;
+  HIP_TRY(c, hipMemcpy(&hc, w.ctl, sizeof(SwarmCtl), hipMemcpyDeviceToHost));
+  if (hc.status == PCMCC_OK) {
+    HIP_TRY(c, launch_swarm_estimate(w.mom, w.cnt, S, J, opts->sample_every * dt, opts->window_start_s,
+                                     opts->n_batches, w.EN, c->gas_N, w.values, w.errors, w.work, c->stream));
+    std::vector<double> vals((size_t)S * kNQ), errs((size_t)S * kNQ);
+    HIP_TRY(c, hipMemcpyAsync(vals.data(), w.values, sizeof(double) * S * kNQ, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(errs.data(), w.errors, sizeof(double) * S * kNQ, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (int s = 0; s < S; ++s)
+      for (int k = 0; k < kNQ; ++k) {
+        out[s].value[k] = vals[(size_t)s * kNQ + k];
+        out[s].error[k] = errs[(size_t)s * kNQ + k];
+      }
+  }
+  if (moments_out || counters_out) {
+    std::vector<unsigned long long> m((size_t)S * J * kNMom * 2);
+    std::vector<long long> cn((size_t)S * J * 4);
+    HIP_TRY(c, hipMemcpy(m.data(), w.mom, sizeof(unsigned long long) * m.size(), hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(cn.data(), w.cnt, sizeof(long long) * cn.size(), hipMemcpyDeviceToHost));
+    if (moments_out)
+      for (size_t i = 0; i < (size_t)S * J * kNMom; ++i) {
+        const double v = (double)(long long)m[2 * i + 1] * 18446744073709551616.0 + (double)m[2 * i];
+        moments_out[i] = std::ldexp(v, -kMomExpHost[i % kNMom]);
+      }
+    if (counters_out)
+      for (size_t i = 0; i < cn.size(); ++i) counters_out[i] = (int64_t)cn[i];
+  }
+  if (stats) {
+    stats->steps_done = hc.steps_done;
+    stats->particle_steps = hc.particle_steps;
+    stats->trials = hc.tot[C_TRIALS];
+    stats->null_collisions = hc.tot[C_NULL];
+    for (int k = 0; k < 4; ++k) stats->real_collisions[k] = hc.tot[C_EL + k];
+    stats->out_of_table = hc.tot[C_OOT];
+    stats->errors = hc.tot[C_ERR];
+    stats->step_kernel_ms = ms;
+    stats->launch_block = block;
+    stats->launch_grid = grid;
+  }
+  if (hc.status == PCMCC_ECAPACITY)
+    return fail(c, hc.status, "a swarm outgrew its %d x n0 slots after %lld steps", opts->cap_factor,
+                (long long)hc.steps_done);
+  if (hc.status != PCMCC_OK) return fail(c, hc.status, "swarm step loop stopped (status %d)", hc.status);
+  return PCMCC_OK;
+}
+
 
 int pcmcc_deposit(pcmcc_ctx* c, const float* x, const float* y, const float* z, const float* w,
                   const int64_t* n_dev, const pcmcc_grid* grid, int64_t* rho) {

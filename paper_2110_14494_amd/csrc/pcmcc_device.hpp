@@ -65,6 +65,11 @@ struct TableView {
   int kind[kMaxProc];
 };
 
+// Floats of LDS the staged tables take: C and P, thresholds and kinds.
+__host__ __device__ inline size_t table_lds_floats(const TableView& T) {
+  return (size_t)(T.nproc + 1) * T.n + 2 * kMaxProc;
+}
+
 // Physical constants of the species and gas, single precision.
 struct SpeciesView {
   double qm;       // q/m

@@ -25,6 +25,7 @@ struct Soa {
 struct PendSoa {
   float *x, *y, *z, *vx, *vy, *vz, *w, *tb;
   uint64_t* id;
+  uint32_t* sw;  // swarm index (swarm queues only, else null)
 };
 
 // Per-step event counters.
@@ -82,7 +83,66 @@ struct TableBuild {
   double* total;        // device scratch [n]
 };
 
+// Swarm moments per sample and the coefficients derived from them.
+constexpr int kNMom = 14;
+// Fixed-point exponents of the moment sums: each particle adds
+// round(value * 2^e) with |value * 2^e| < 2^54, summed in 128 bits.
+constexpr int kMomExpHost[kNMom] = {0, 53, 53, 53, 53, 53, 25, 25, 25, 24, 24, 36, 0, 0};
+enum Quantity {
+  Q_W_FLUX, Q_W_BULK, Q_DL_FLUX, Q_DL_BULK, Q_DT_FLUX, Q_DT_BULK, Q_NU_ION,
+  Q_NU_ATT, Q_NU_EFF, Q_MEAN_EPS, Q_MU, Q_ALPHA, Q_ETA, Q_RATIO, kNQ
+};
+
+// Device control block of the swarm step loop.
+struct SwarmCtl {
+  unsigned long long pend[kMaxGenerations + 1];
+  unsigned overflow;
+  int cur_sel;
+  int stop;
+  int status;
+  long long steps_done;
+  unsigned long long particle_steps;
+  unsigned long long tot[NCNT];
+};
+
+struct SwarmArgs {
+  Soa buf[2];
+  PendSoa pend[2];
+  uint64_t pend_cap;
+  int n_swarms;
+  const uint64_t* base;         // [S] first slot of swarm s
+  const uint64_t* cap_s;        // [S] slots of swarm s
+  const int32_t* n0;            // [S]
+  const double* az;             // [S] acceleration along z
+  SwarmCtl* ctl;
+  unsigned long long* n_cur;    // [S]
+  unsigned long long* n_nxt;    // [S]
+  int* pc_k;                    // [S] population control for the next load
+  long long* L;                 // [S] log2 of the weight scale
+  unsigned long long* cum_ion;  // [S]
+  unsigned long long* cum_att;  // [S]
+  unsigned long long* mom;      // [S][J][kNMom][2] 128-bit sums (lo, hi)
+  long long* cnt_out;           // [S][J][4]: count, L, ionizations, attachments
+  unsigned long long* partial;  // [grid][NCNT]
+  unsigned long long* partial_ps;  // [grid]
+  TableView T;
+  SpeciesView S;
+  Key key;
+  int n_steps;
+  float dt;
+  int sample_every;
+  int n_samples;
+  int pop_control;
+};
+
 size_t table_lds_bytes(const TableView& T);
+size_t swarm_lds_bytes(const TableView& T, int S, int block);
+hipError_t occupancy_swarm_steps(int block, size_t lds, int* blocks_per_cu);
+hipError_t launch_swarm_steps(const SwarmArgs& args, int grid, int block, hipStream_t stream);
+hipError_t launch_swarm_init(const Soa& buf, const uint64_t* base, const int32_t* n0, int S, hipStream_t stream);
+hipError_t launch_swarm_estimate(const unsigned long long* mom, const long long* cnt, int S, int J, double dt_sample,
+                                 double t_window, int n_batches, const double* EN, double gas_N, double* values,
+                                 double* errors, double* work, hipStream_t stream);
 hipError_t launch_pic_steps(const PicArgs& args, int grid, int block, hipStream_t stream);
 hipError_t occupancy_pic_steps(int block, size_t lds, int* blocks_per_cu);
 hipError_t launch_finalize(const Soa& user, const Soa& scratch, Ctl* ctl, int64_t* n_dev, hipStream_t stream);

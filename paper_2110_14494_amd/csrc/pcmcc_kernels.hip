@@ -22,319 +22,11 @@
 
 #include "pcmcc_device.hpp"
 #include "pcmcc_internal.hpp"
+#include "pcmcc_mover.hpp"
 
 namespace cg = cooperative_groups;
 
 namespace pcmcc {
-
-// ---------------------------------------------------------------------------
-// small device helpers
-
-template <class T>
-__device__ __forceinline__ T ld_acq(const T* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
-
-__device__ __forceinline__ uint32_t rank_in(uint64_t mask) {
-  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
-
-// Reserves one slot per calling lane in a counter with a single atomic for
-// the wave: every active lane that calls it gets base + its rank.
-__device__ __forceinline__ uint64_t wave_reserve(unsigned long long* counter) {
-  const uint64_t mask = __ballot(1);
-  const int leader = __ffsll((unsigned long long)mask) - 1;
-  uint64_t base = 0;
-  if ((int)lane_id() == leader) base = atomicAdd(counter, (unsigned long long)__popcll(mask));
-  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)base, leader);
-  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(base >> 32), leader);
-  return (((uint64_t)hi << 32) | lo) + rank_in(mask);
-}
-
-struct Cnt {
-  uint32_t v[NCNT];
-};
-
-__device__ __forceinline__ void load_p(const Soa& s, uint64_t i, PState& p) {
-  p.x = s.x[i];
-  p.y = s.y[i];
-  p.z = s.z[i];
-  p.vx = s.vx[i];
-  p.vy = s.vy[i];
-  p.vz = s.vz[i];
-  p.w = s.w[i];
-  p.id = s.id[i];
-}
-
-__device__ __forceinline__ void store_p(const Soa& s, uint64_t i, const PState& p) {
-  s.x[i] = p.x;
-  s.y[i] = p.y;
-  s.z[i] = p.z;
-  s.vx[i] = p.vx;
-  s.vy[i] = p.vy;
-  s.vz[i] = p.vz;
-  s.w[i] = p.w;
-  s.id[i] = p.id;
-}
-
-__device__ __forceinline__ void load_pend(const PendSoa& s, uint64_t i, PState& p, float& tb) {
-  p.x = s.x[i];
-  p.y = s.y[i];
-  p.z = s.z[i];
-  p.vx = s.vx[i];
-  p.vy = s.vy[i];
-  p.vz = s.vz[i];
-  p.w = s.w[i];
-  p.id = s.id[i];
-  tb = s.tb[i];
-}
-
-// Queue of newborns of one generation.
-struct BirthSink {
-  PendSoa q;
-  unsigned long long* count;
-  uint64_t cap;
-  unsigned* overflow;
-  __device__ __forceinline__ void push(const PState& c, float tb) const {
-    const uint64_t slot = wave_reserve(count);
-    if (slot < cap) {
-      q.x[slot] = c.x;
-      q.y[slot] = c.y;
-      q.z[slot] = c.z;
-      q.vx[slot] = c.vx;
-      q.vy[slot] = c.vy;
-      q.vz[slot] = c.vz;
-      q.w[slot] = c.w;
-      q.id[slot] = c.id;
-      q.tb[slot] = tb;
-    } else {
-      atomicOr(overflow, OVF_CAPACITY);
-    }
-  }
-};
-
-// Field of the PIC step: the grid.
-struct GridField {
-  GridView G;
-  double qm;
-  __device__ __forceinline__ double3 accel(double x, double y, double z) const { return gather(G, qm, x, y, z); }
-  __device__ __forceinline__ void bound(double x, double y, double z, float speed, float t_rem, float& a_abs,
-                                        float& da) const {
-    accel_bound(G, x, y, z, speed, t_rem, a_abs, da);
-  }
-};
-
-// Tables as the kernels read them (staged in LDS).
-struct Tab {
-  const float* C;
-  const float* P;
-  const float* thr;
-  const int* kind;
-  int n, nproc;
-  float u_scale, u_offset, eps_max;
-};
-
-__device__ __forceinline__ float majorant_t(const Tab& T, const SpeciesView& S, float s_ub) {
-  const float s = s_ub * kGuard;
-  const float eps = S.k_eps * s * s;
-  float u = __log2f(eps) * T.u_scale + T.u_offset;
-  u = fminf(fmaxf(u, 0.0f), (float)(T.n - 1));
-  const float fl = fminf(floorf(u), (float)(T.n - 2));
-  const int i = (int)fl;
-  return lerp_at(T.P, i, u - fl);
-}
-
-// Isotropic unit vector from two uniforms: cos(theta) = 1 - 2 U1 and
-// sin(theta) = 2 sqrt(U1 (1 - U1)) (no cancellation near the poles; U1 and
-// 1 - U1 are exact), azimuth 2 pi U2 from a single-precision sincospi whose
-// (cos, sin) pair is renormalised so that |n| = 1 in double precision.
-__device__ __forceinline__ void iso_dir(uint32_t r1, uint32_t r2, double& nx, double& ny, double& nz) {
-  const double u = (double)unif(r1);
-  const double cth = 1.0 - 2.0 * u;
-  const double sth = 2.0 * sqrt(u * (1.0 - u));
-  float sp, cp;
-  sincospif(2.0f * unif(r2), &sp, &cp);
-  const double inv = sth / sqrt((double)cp * cp + (double)sp * sp);
-  nx = inv * cp;
-  ny = inv * sp;
-  nz = cth;
-}
-
-// Advances one electron from time t to the end of the step (length dt).
-// Returns 0 if it is alive at the end of the step, 1 if attached, 2 if it
-// hit the segment limit.  Newborns go to `sink` with their birth time.
-//
-// Position, velocity, time and energy are carried in double precision within
-// the step (stored single precision between steps): on CDNA4 unpacked FP32
-// and FP64 fused multiply-adds issue at the same rate, and double keeps the
-// energy bookkeeping of tens of collisions per step free of drift.  Field,
-// tables, majorant and random numbers stay single precision.
-template <class Field>
-__device__ int advance(PState& p, double t, double dt, const Field& F, const Tab& T, const SpeciesView& S, Key key,
-                       uint32_t step, Cnt& cnt, const BirthSink& sink) {
-  double x = p.x, y = p.y, z = p.z;
-  double vx = p.vx, vy = p.vy, vz = p.vz;
-  double3 a = F.accel(x, y, z);
-  float a_abs, da;
-  F.bound(x, y, z, sqrtf((float)(vx * vx + vy * vy + vz * vz)), (float)(dt - t), a_abs, da);
-  auto verlet = [&](double h) {
-    x += h * fma(0.5 * a.x, h, vx);
-    y += h * fma(0.5 * a.y, h, vy);
-    z += h * fma(0.5 * a.z, h, vz);
-    const double3 an = F.accel(x, y, z);
-    const double hh = 0.5 * h;
-    vx = fma(a.x + an.x, hh, vx);
-    vy = fma(a.y + an.y, hh, vy);
-    vz = fma(a.z + an.z, hh, vz);
-    a = an;
-  };
-  int result = 0;
-  for (uint32_t j = 0;; ++j) {
-    if (j >= (uint32_t)kMaxSegments) {
-      cnt.v[C_ERR]++;
-      result = 2;
-      break;
-    }
-    const uint4 r = draw(key, p.id, step, j, TAG_MAIN);
-    cnt.v[C_TRIALS]++;
-    const double t_rem = dt - t;
-    const float3 vf = make_float3((float)vx, (float)vy, (float)vz);
-    const float3 af = make_float3((float)a.x, (float)a.y, (float)a.z);
-    const float speed = sqrtf(vf.x * vf.x + vf.y * vf.y + vf.z * vf.z);
-    const float nu_full = majorant_t(T, S, speed_bound(vf, af, speed, a_abs, da, (float)t_rem));
-    const bool limited = kKappa < nu_full * (float)t_rem;
-    const double h = limited ? (double)(kKappa / nu_full) : t_rem;
-    const float nu_hat = limited ? majorant_t(T, S, speed_bound(vf, af, speed, a_abs, da, (float)h)) : nu_full;
-    const double tau = nu_hat > 0.0f ? (double)(-__logf(unif(r.x)) / nu_hat) : (double)INFINITY;
-    if (tau >= h) {  // no candidate collision within the horizon
-      verlet(h);
-      if (!limited) break;
-      t += h;
-      continue;
-    }
-    verlet(tau);
-    t += tau;
-    const double v2 = vx * vx + vy * vy + vz * vz;
-    const double eps = (double)S.k_eps_d * v2;
-    float u = __log2f((float)eps) * T.u_scale + T.u_offset;
-    u = fminf(fmaxf(u, 0.0f), (float)(T.n - 1));
-    const float fl = fminf(floorf(u), (float)(T.n - 2));
-    const int i = (int)fl;
-    const float f = u - fl;
-    const float yv = unif(r.y) * nu_hat;
-    int k = -1;
-    for (int kk = 0; kk < T.nproc; ++kk)
-      if (yv < lerp_at(T.C + kk * T.n, i, f)) {
-        k = kk;
-        break;
-      }
-    if (k < 0 || eps < (double)T.thr[k]) {
-      cnt.v[C_NULL]++;
-      continue;
-    }
-    if (eps > (double)T.eps_max) cnt.v[C_OOT]++;
-    const int kind = T.kind[k];
-    // (register array: no dynamic index, which would move it to scratch)
-    cnt.v[C_EL] += kind == ELASTIC;
-    cnt.v[C_EXC] += kind == EXCITATION;
-    cnt.v[C_ION] += kind == IONIZATION;
-    cnt.v[C_ATT] += kind == ATTACHMENT;
-    if (kind == ATTACHMENT) {
-      result = 1;
-      break;
-    }
-    // cos(theta) = 1 - 2U; sin(theta) = 2 sqrt(U (1 - U)) avoids the
-    // cancellation of 1 - cos^2 near the poles (U and 1 - U are exact).
-    double nx, ny, nz;
-    iso_dir(r.z, r.w, nx, ny, nz);
-    double eps_new;
-    if (kind == ELASTIC) {
-      const double sc = sqrt(v2);
-      const double cchi = sc > 0.0 ? (vx * nx + vy * ny + vz * nz) / sc : 0.0;
-      eps_new = eps * (1.0 - (double)S.recoil * (1.0 - cchi));
-    } else if (kind == EXCITATION) {
-      eps_new = eps - (double)T.thr[k];
-    } else {
-      eps_new = 0.5 * (eps - (double)T.thr[k]);
-      const uint4 b = draw(key, p.id, step, j, TAG_BIRTH);
-      PState c;
-      c.x = (float)x;
-      c.y = (float)y;
-      c.z = (float)z;
-      c.w = p.w;
-      c.id = (uint64_t)b.x | ((uint64_t)b.y << 32);
-      double cx, cy, cz;
-      iso_dir(b.z, b.w, cx, cy, cz);
-      const double cs = sqrt(eps_new * S.inv_k_d);
-      c.vx = (float)(cs * cx);
-      c.vy = (float)(cs * cy);
-      c.vz = (float)(cs * cz);
-      sink.push(c, (float)t);
-    }
-    const double sn = sqrt(eps_new * S.inv_k_d);
-    vx = sn * nx;
-    vy = sn * ny;
-    vz = sn * nz;
-  }
-  p.x = (float)x;
-  p.y = (float)y;
-  p.z = (float)z;
-  p.vx = (float)vx;
-  p.vy = (float)vy;
-  p.vz = (float)vz;
-  p.xd = x;
-  p.yd = y;
-  p.zd = z;
-  return result;
-}
-
-// Inside the grid, judged on the double-precision end position.
-__device__ __forceinline__ bool inside(const GridView& G, const PState& p) {
-  return p.xd >= G.lo[0] && p.xd < G.hi[0] && p.yd >= G.lo[1] && p.yd < G.hi[1] && p.zd >= G.lo[2] &&
-         p.zd < G.hi[2];
-}
-
-// Stages the tables in LDS; returns the view the kernels read.
-__device__ Tab stage_tables(const TableView& TV, float* smem) {
-  const int nC = TV.nproc * TV.n;
-  for (int i = threadIdx.x; i < nC; i += blockDim.x) smem[i] = TV.C[i];
-  for (int i = threadIdx.x; i < TV.n; i += blockDim.x) smem[nC + i] = TV.P[i];
-  float* thr = smem + nC + TV.n;
-  int* kind = (int*)(thr + kMaxProc);
-  if (threadIdx.x < (unsigned)kMaxProc) {
-    thr[threadIdx.x] = TV.thr[threadIdx.x];
-    kind[threadIdx.x] = TV.kind[threadIdx.x];
-  }
-  __syncthreads();
-  Tab T;
-  T.C = smem;
-  T.P = smem + nC;
-  T.thr = thr;
-  T.kind = kind;
-  T.n = TV.n;
-  T.nproc = TV.nproc;
-  T.u_scale = TV.u_scale;
-  T.u_offset = TV.u_offset;
-  T.eps_max = TV.eps_top;
-  return T;
-}
-
-// Sums per-thread counters over the block into partial[blockIdx.x][*].
-__device__ void block_counters(const Cnt& c, unsigned long long* partial) {
-  __shared__ unsigned long long red[NCNT];
-  if (threadIdx.x < NCNT) red[threadIdx.x] = 0;
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < NCNT; ++k) {
-    uint32_t v = c.v[k];
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    if (lane_id() == 0) atomicAdd(&red[k], (unsigned long long)v);
-  }
-  __syncthreads();
-  if (threadIdx.x < NCNT) partial[(size_t)blockIdx.x * NCNT + threadIdx.x] = red[threadIdx.x];
-}
 
 // ---------------------------------------------------------------------------
 // The step loop.  One cooperative launch runs all n_steps steps; grid-wide
@@ -365,7 +57,7 @@ __global__ __launch_bounds__(256) void k_pic_steps(PicArgs A) {
 
     // Phase 1: every particle of the current buffer, from t = 0.
     {
-      const BirthSink sink{A.pend[0], &ctl->pend[0], A.pend_cap, &ctl->overflow};
+      const BirthSink sink{A.pend[0], &ctl->pend[0], A.pend_cap, &ctl->overflow, 0u};
       for (uint64_t base = gw * 64; base < n_cur; base += GW * 64) {
         const uint64_t i = base + lane;
         if (i < n_cur) {
@@ -399,7 +91,7 @@ __global__ __launch_bounds__(256) void k_pic_steps(PicArgs A) {
       }
       const uint64_t np = np_raw < A.pend_cap ? np_raw : A.pend_cap;
       const PendSoa src = A.pend[g & 1];
-      const BirthSink sink{A.pend[(g + 1) & 1], &ctl->pend[g + 1], A.pend_cap, &ctl->overflow};
+      const BirthSink sink{A.pend[(g + 1) & 1], &ctl->pend[g + 1], A.pend_cap, &ctl->overflow, 0u};
       for (uint64_t base = gw * 64; base < np; base += GW * 64) {
         const uint64_t i = base + lane;
         if (i < np) {
@@ -659,9 +351,7 @@ __global__ void k_lookup(TableView TV, SpeciesView S, const float* __restrict__ 
 // ---------------------------------------------------------------------------
 // launch wrappers
 
-size_t table_lds_bytes(const TableView& T) {
-  return ((size_t)(T.nproc + 1) * T.n + 2 * kMaxProc) * sizeof(float);
-}
+size_t table_lds_bytes(const TableView& T) { return table_lds_floats(T) * sizeof(float); }
 
 hipError_t launch_pic_steps(const PicArgs& args, int grid, int block, hipStream_t stream) {
   void* kargs[] = {(void*)&args};

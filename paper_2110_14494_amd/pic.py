@@ -162,3 +162,33 @@ class Context:
                                             s_ub.data_ptr() if s_ub is not None else None,
                                             maj.data_ptr() if maj is not None else None), self.h)
         return cum, maj
+
+
+def swarm_batch(ctx: Context, EN_Td, n0, dt: float, n_steps: int, seed: int, sample_every: int = 10,
+                window_start_s: float = 0.0, n_batches: int = 10, cap_factor: int = 8,
+                population_control: bool = True, block: int = 0, blocks_per_cu: int = 0, autotune: bool = False,
+                tune_cache: str | None = None, raw: bool = False, check: bool = True):
+    """Batched uniform-field swarms (forwards to pcmcc_swarm_batch).
+
+    Returns (rc, values[S, 14], errors[S, 14], stats[, moments[S, J, 14], counters[S, J, 4]])."""
+    EN = np.ascontiguousarray(EN_Td, dtype=np.float64)
+    n0 = np.ascontiguousarray(n0, dtype=np.int32)
+    S = EN.size
+    J = n_steps // sample_every
+    opts = B.pcmcc_swarm_opts(int(sample_every), float(window_start_s), int(n_batches), int(cap_factor),
+                              1 if population_control else 0, int(block), int(blocks_per_cu), 1 if autotune else 0,
+                              tune_cache.encode() if tune_cache else None)
+    res = (B.pcmcc_swarm_result * S)()
+    st = B.pcmcc_stats()
+    mom = np.zeros((S, J, B.SWARM_NMOM)) if raw else None
+    cnt = np.zeros((S, J, 4), dtype=np.int64) if raw else None
+    rc = B.lib().pcmcc_swarm_batch(ctx.h, S, EN.ctypes.data_as(C.c_void_p), n0.ctypes.data_as(C.c_void_p),
+                                   float(dt), int(n_steps), int(seed), C.byref(opts), res,
+                                   mom.ctypes.data_as(C.c_void_p) if raw else None,
+                                   cnt.ctypes.data_as(C.c_void_p) if raw else None, C.byref(st))
+    if check:
+        B.check(rc, ctx.h)
+    vals = np.array([list(r.value) for r in res])
+    errs = np.array([list(r.error) for r in res])
+    out = (rc, vals, errs, st.as_dict())
+    return out + ((mom, cnt) if raw else ())

@@ -1,0 +1,111 @@
+"""GPU batched swarms against the CPU swarm oracle.
+
+Same inputs and the same Philox draws on both sides; the GPU sums moments
+exactly in 128-bit fixed point.  Checks: early samples agree closely (the
+lineages are identical until a rare floating-point decision flip); the
+coefficients agree within 3 combined standard errors; moments are
+bit-identical across runs, launch shapes, and between a batch and the same
+swarm run alone.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import estimators as E
+from paper_2110_14494_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+EN = np.array([20.0, 80.0, 200.0, 400.0, 700.0, 1000.0])
+N0 = np.array([700, 1500, 1000, 2100, 900, 1200], dtype=np.int32)
+KW = dict(dt=1e-12, n_steps=300, seed=11, sample_every=10)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2110_14494_amd import pic
+    c = pic.Context(0)
+    c.setup(W.electron_species(), W.air_like_tables())
+    yield c
+    c.close()
+
+
+def gpu_run(ctx, EN_, N0_, **extra):
+    from paper_2110_14494_amd import pic
+    kw = dict(KW)
+    kw.update(extra)
+    print(f"[gpu] swarm_batch S={len(EN_)} steps={kw['n_steps']}", flush=True)
+    return pic.swarm_batch(ctx, EN_, N0_, kw["dt"], kw["n_steps"], kw["seed"], sample_every=kw["sample_every"],
+                           window_start_s=100e-12, n_batches=10, raw=True,
+                           **{k: v for k, v in extra.items() if k not in KW})
+
+
+def test_swarm_parity_with_oracle(ctx):
+    rc, vals, errs, st, mom, cnt = gpu_run(ctx, EN, N0)
+    assert rc == 0
+    sp, tab = W.electron_species(), W.air_like_tables()
+    orc, om, oc, ost = oracle.swarm_run(sp, tab, EN, N0, KW["dt"], KW["n_steps"], KW["seed"], KW["sample_every"])
+    assert orc == 0
+    # first sample: identical lineages up to rare flips
+    me, qe = W.ELECTRON_MASS, W.ELEMENTARY_CHARGE
+    for s in range(len(EN)):
+        assert abs(int(cnt[s, 0, 0]) - int(oc[s, 0, 0])) <= 2
+        n, ng = om[s, 0, 0], mom[s, 0, 0]
+        eps = om[s, 0, 11] / n
+        scales = {3: math.sqrt(om[s, 0, 5] / n), 8: math.sqrt(2 * eps * qe / me), 11: eps}
+        for m, scale in scales.items():
+            g, o = mom[s, 0, m] / ng, om[s, 0, m] / n
+            assert abs(g - o) <= 5e-3 * scale, (s, m, g, o)
+    ovals, oerrs = E.estimate(om, oc, KW["sample_every"] * KW["dt"], 100e-12, 10, EN * 1e-21 * sp["gas_N"])
+    for s in range(len(EN)):
+        for q in ("W_flux", "W_bulk", "DL_flux", "DT_flux", "mean_eps", "nu_ion", "nu_eff"):
+            k = E.QUANTITIES.index(q)
+            if not np.isfinite(ovals[s, k]):
+                continue
+            tol = 3 * math.hypot(errs[s, k], oerrs[s, k]) + 1e-9 * abs(ovals[s, k])
+            assert abs(vals[s, k] - ovals[s, k]) <= tol, (EN[s], q, vals[s, k], ovals[s, k], tol)
+    # the GPU estimator kernel against the oracle estimators on the GPU's own moments
+    gv, ge = E.estimate(mom, cnt, KW["sample_every"] * KW["dt"], 100e-12, 10, EN * 1e-21 * sp["gas_N"])
+    fin = np.isfinite(gv)
+    np.testing.assert_allclose(vals[fin], gv[fin], rtol=1e-9, atol=1e-30)
+    np.testing.assert_allclose(errs[fin], ge[fin], rtol=1e-6, atol=1e-20)
+
+
+def test_swarm_moments_exact_across_runs_and_shapes(ctx):
+    a = gpu_run(ctx, EN, N0, block=256)
+    b = gpu_run(ctx, EN, N0, block=64, blocks_per_cu=1)
+    c = gpu_run(ctx, EN, N0, block=512)
+    assert np.array_equal(a[4], b[4]) and np.array_equal(a[4], c[4])
+    assert np.array_equal(a[5], b[5]) and np.array_equal(a[5], c[5])
+
+
+def test_single_swarm_call_reproduces_batch_member(ctx):
+    from paper_2110_14494_amd import pic
+    full = gpu_run(ctx, EN, N0)
+    s = 3
+    seed_s = KW["seed"] ^ (s << 32)  # swarm s of a batch uses key (seed_lo, seed_hi ^ s)
+    one = pic.swarm_batch(ctx, EN[s:s + 1], N0[s:s + 1], KW["dt"], KW["n_steps"], seed_s,
+                          sample_every=KW["sample_every"], window_start_s=100e-12, n_batches=10, raw=True)
+    assert np.array_equal(one[4][0], full[4][s]) and np.array_equal(one[5][0], full[5][s])
+
+
+def test_autotune_cache_round_trip(ctx, tmp_path):
+    path = str(tmp_path / "tune.json")
+    a = gpu_run(ctx, EN, N0, autotune=True, tune_cache=path)
+    assert os.path.exists(path) and "k_swarm_steps" in open(path).read()
+    b = gpu_run(ctx, EN, N0, tune_cache=path)
+    assert (b[3]["launch_block"], b[3]["launch_grid"]) == (a[3]["launch_block"], a[3]["launch_grid"])
+    assert np.array_equal(a[4], b[4])
+
+
+def test_swarm_capacity_error(ctx):
+    from paper_2110_14494_amd import pic
+    rc, *_ = pic.swarm_batch(ctx, [900.0], [500], 1e-12, 400, 1, sample_every=10, window_start_s=0.0,
+                             n_batches=10, cap_factor=4, population_control=False, check=False)
+    assert rc == -2
