@@ -226,6 +226,81 @@ int pcmcc_swarm_batch(pcmcc_ctx* ctx, int n_swarms, const double* EN_Td, const i
                       uint64_t seed, const pcmcc_swarm_opts* opts, pcmcc_swarm_result* out, double* moments_out,
                       int64_t* counters_out, pcmcc_stats* stats);
 
+/* ---- Coefficient surrogate ---------------------------------------------
+ * A perceptron 1 -> 64 -> 64 -> 6 with tanh hidden layers maps the
+ * standardised input x = (ln(E/N) - mu_x) / sd_x to six standardised log
+ * swarm coefficients (ln mobility N, ln D_L N, ln alpha/N, ln eta/N, ln mean
+ * energy, ln W_bulk/W_flux), i.e. the transport data of the fluid model
+ * (Sec. 2.2), learned from pcmcc_swarm_batch output.  Parameters are one
+ * float vector of PCMCC_MLP_PARAMS values: W1[64,1], b1[64], W2[64,64],
+ * b2[64], W3[6,64], b3[6] (row-major).  Loss: masked mean squared error
+ * sum(mask (y - t)^2) / sum(mask). */
+#define PCMCC_MLP_PARAMS 4678
+#define PCMCC_MLP_OUT 6
+
+/* Loss and gradient for the parameters at params (single precision, fixed
+ * summation order).  params[4678], x[n], t[n][6], mask[n][6], grad_out[4678]
+ * and loss_out are host memory.  n >= 1, sum(mask) > 0. */
+int pcmcc_mlp_grad(pcmcc_ctx* ctx, const float* params, int64_t n, const float* x, const float* t,
+                   const float* mask, float* grad_out, double* loss_out);
+
+typedef struct pcmcc_mlp_train_opts {
+  int epochs;           /* full-batch Adam steps */
+  double lr0, lr_min;   /* cosine schedule: lr_min + (lr0 - lr_min)(1 + cos(pi e / epochs)) / 2 */
+  double beta1, beta2, eps;
+} pcmcc_mlp_train_opts;
+
+/* Trains from params_in with full-batch Adam in one persistent launch; the
+ * result is bit-reproducible.  params_out[4678] host; loss_hist[epochs]
+ * (host, nullable) gets the loss before each update; stats (nullable) gets
+ * the kernel time. */
+int pcmcc_mlp_train(pcmcc_ctx* ctx, const float* params_in, int64_t n, const float* x, const float* t,
+                    const float* mask, const pcmcc_mlp_train_opts* opts, float* params_out, float* loss_hist,
+                    pcmcc_stats* stats);
+
+typedef struct pcmcc_mlp_infer_opts {
+  double mu_x, sd_x;                       /* input standardisation */
+  double mu_y[PCMCC_MLP_OUT], sd_y[PCMCC_MLP_OUT]; /* output un-standardisation */
+  int n_cells;                             /* fallback cells uniform in ln(E/N) over [cell_lo, cell_hi); 0 = none */
+  double cell_lo, cell_hi;
+  const uint8_t* fallback;                 /* host [n_cells]: 1 = use the table in this cell */
+  int n_nodes;                             /* table nodes uniform in ln(E/N) from table_lo to table_hi */
+  double table_lo, table_hi;
+  const float* table;                      /* host [n_nodes][6] ln coefficients (linear interpolation) */
+} pcmcc_mlp_infer_opts;
+
+/* Evaluates the surrogate at n reduced fields EN_dev (device, Td) with
+ * bfloat16 weights and activations and single-precision accumulation (MFMA);
+ * out_dev (device) receives [6][n] ln coefficients (output-major).  Points in
+ * a fallback cell take the linear interpolation of the table instead. */
+int pcmcc_mlp_infer(pcmcc_ctx* ctx, const float* params, const pcmcc_mlp_infer_opts* opts, int64_t n,
+                    const float* EN_dev, float* out_dev, pcmcc_stats* stats);
+
+/* Training data from swarm results: x = ln(E/N / 1 Td); targets = ln(mu N),
+ * ln(DL_flux N), ln(alpha / N), ln(eta / N), ln(mean energy / 1 eV),
+ * ln(W_bulk / W_flux) (SI units).  An entry is masked when its value is not
+ * positive and finite or its relative batch-means error exceeds max_rel_err
+ * (unresolved, e.g. rare ionization or attachment events).  With
+ * compute_norm = 1 the standardisation (mean, std over unmasked entries) is
+ * computed into norm (mu_x, sd_x, mu_y, sd_y); otherwise norm is used as
+ * given.  x_out[n], t_out[n][6], mask_out[n][6] are the standardised data;
+ * ln_out[n][6] (nullable) the unstandardised ln values with masked entries
+ * set to ln_floor.  Host memory; no device work. */
+int pcmcc_mlp_dataset(int n, const double* EN_Td, const pcmcc_swarm_result* res, double gas_N, double max_rel_err,
+                      int compute_norm, pcmcc_mlp_infer_opts* norm, float* x_out, float* t_out, float* mask_out,
+                      float* ln_out, double ln_floor);
+
+/* Held-out check of a trained surrogate: evaluates it (the bfloat16 device
+ * path) at n_held reduced fields and marks cell c of n_cells cells uniform in
+ * ln(E/N) over [cell_lo, cell_hi) for fallback if, for any held-out point in
+ * it, an output is masked or |ln y_mlp - ln y_swarm| > tol_ln.  ln_held and
+ * mask_held [n_held][6] are unstandardised ln targets and their mask (host);
+ * fallback_out[n_cells] host; err_out[n_held][6] (nullable) receives the
+ * absolute ln errors (NaN where masked). */
+int pcmcc_mlp_fallback(pcmcc_ctx* ctx, const float* params, const pcmcc_mlp_infer_opts* norm, int n_held,
+                       const double* EN_held, const float* ln_held, const float* mask_held, double tol_ln,
+                       int n_cells, double cell_lo, double cell_hi, uint8_t* fallback_out, float* err_out);
+
 /* Deposit only (Sec. 2.1.3), same fixed-point rule as above, on n_dev
  * particles (device count) of device arrays x, y, z, w. */
 int pcmcc_deposit(pcmcc_ctx* ctx, const float* x, const float* y, const float* z, const float* w,

@@ -65,6 +65,22 @@ class pcmcc_swarm_result(C.Structure):
     _fields_ = [("value", C.c_double * SWARM_NQ), ("error", C.c_double * SWARM_NQ)]
 
 
+MLP_PARAMS = 4678
+MLP_OUT = 6
+
+
+class pcmcc_mlp_train_opts(C.Structure):
+    _fields_ = [("epochs", C.c_int), ("lr0", C.c_double), ("lr_min", C.c_double), ("beta1", C.c_double),
+                ("beta2", C.c_double), ("eps", C.c_double)]
+
+
+class pcmcc_mlp_infer_opts(C.Structure):
+    _fields_ = [("mu_x", C.c_double), ("sd_x", C.c_double), ("mu_y", C.c_double * MLP_OUT),
+                ("sd_y", C.c_double * MLP_OUT), ("n_cells", C.c_int), ("cell_lo", C.c_double),
+                ("cell_hi", C.c_double), ("fallback", C.c_void_p), ("n_nodes", C.c_int),
+                ("table_lo", C.c_double), ("table_hi", C.c_double), ("table", C.c_void_p)]
+
+
 class PcmccError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"pcmcc error {code} ({_NAMES.get(code, '?')}): {msg}")
@@ -95,6 +111,15 @@ def lib() -> C.CDLL:
             "pcmcc_deposit": ([vp, vp, vp, vp, vp, vp, C.POINTER(pcmcc_grid), vp], C.c_int),
             "pcmcc_philox4x32_10": ([vp, i64, vp, u64, vp], C.c_int),
             "pcmcc_tables_lookup": ([vp, i64, vp, vp, vp, vp], C.c_int),
+            "pcmcc_mlp_grad": ([vp, vp, i64, vp, vp, vp, vp, C.POINTER(C.c_double)], C.c_int),
+            "pcmcc_mlp_train": ([vp, vp, i64, vp, vp, vp, C.POINTER(pcmcc_mlp_train_opts), vp, vp,
+                                 C.POINTER(pcmcc_stats)], C.c_int),
+            "pcmcc_mlp_infer": ([vp, vp, C.POINTER(pcmcc_mlp_infer_opts), i64, vp, vp, C.POINTER(pcmcc_stats)],
+                                C.c_int),
+            "pcmcc_mlp_dataset": ([C.c_int, vp, vp, C.c_double, C.c_double, C.c_int,
+                                   C.POINTER(pcmcc_mlp_infer_opts), vp, vp, vp, vp, C.c_double], C.c_int),
+            "pcmcc_mlp_fallback": ([vp, vp, C.POINTER(pcmcc_mlp_infer_opts), C.c_int, vp, vp, vp, C.c_double,
+                                    C.c_int, C.c_double, C.c_double, vp, vp], C.c_int),
             "pcmcc_swarm_batch": ([vp, C.c_int, vp, vp, C.c_double, C.c_int, u64, C.POINTER(pcmcc_swarm_opts),
                                    vp, vp, vp, C.POINTER(pcmcc_stats)], C.c_int),
         }

@@ -135,6 +135,49 @@ struct SwarmArgs {
   int pop_control;
 };
 
+// Coefficient surrogate (1 -> 64 -> 64 -> 6 perceptron).
+constexpr int kMlpParams = 4678;
+
+struct MlpArgs {
+  float* params;        // [kMlpParams], updated in place by training
+  const float* x;       // [n] standardised inputs
+  const float* t;       // [n][6] standardised targets
+  const float* mask;    // [n][6] 1 = use the entry
+  int64_t n;
+  float inv_cnt;        // 1 / number of used entries
+  float* partial;       // [grid][kMlpParams]
+  float* ploss;         // [grid]
+  float* m;             // Adam first moments
+  float* v;             // Adam second moments
+  float* loss_hist;     // [epochs] or null
+  int epochs;
+  double lr0, lr_min;
+  float beta1, beta2, eps;
+};
+
+struct InferArgs {
+  const float* params;  // [kMlpParams] (device)
+  const float* EN;      // [n] reduced fields in Td
+  float* out;           // [6][n] ln coefficients
+  int64_t n;
+  float mu_x, inv_sd_x;
+  float mu_y[6], sd_y[6];
+  int n_cells;          // fallback cells in ln(E/N), 0 = none
+  float cell_lo, inv_cell_w;
+  const uint8_t* fb_mask;
+  int n_nodes;          // fallback table nodes, uniform in ln(E/N)
+  float tab_lo, inv_tab_w;
+  const float* table;   // [n_nodes][6] ln coefficients
+};
+
+size_t mlp_lds_bytes();
+hipError_t launch_mlp_grad(const MlpArgs& a, int grid, hipStream_t stream);
+hipError_t launch_mlp_reduce(const float* partial, const float* ploss, int nb, float* grad, float* loss,
+                             hipStream_t stream);
+hipError_t occupancy_mlp_train(int* blocks_per_cu);
+hipError_t launch_mlp_train(const MlpArgs& a, int grid, hipStream_t stream);
+hipError_t launch_mlp_infer(const InferArgs& a, int grid, hipStream_t stream);
+
 size_t table_lds_bytes(const TableView& T);
 size_t swarm_lds_bytes(const TableView& T, int S, int block);
 hipError_t occupancy_swarm_steps(int block, size_t lds, int* blocks_per_cu);
