@@ -1,22 +1,28 @@
-"""Benchmark of the PIC-MCC electron update on one MI355X.
+"""Benchmark of the PIC-MCC electron hot path on one MI355X.
 
-One bench step = one pass of the hot path over the streamer-scale workload:
-2^24 electrons (weights log-uniform 1-64) in a 256^3 tip field over a 10 mm
-cube, advanced with push + null-collision MCC + newborn append + compaction
-for as many 2 ps steps as the particle capacity (32 x the start count)
-holds, then CIC-deposited in int64 fixed point.  The workload grows
-explosively (ionization in the tip field), so the number of committed steps
-is found once during warmup and every timed call runs exactly that many.
+Headline (one bench step = one pass of the hot path over the streamer-scale
+workload): 2^24 electrons (weights log-uniform in 1-64) in a 256^3 tip field
+over a 10 mm cube (1.5e6 V/m background plus a 1.5e7 V/m Gaussian tip,
+sigma 200 um, at z = 8 mm), advanced by push + null-collision MCC + newborn
+append + compaction for as many 2 ps steps as a capacity of 32 x the start
+count holds, then deposited (int64 fixed-point CIC).  Ionization in the tip
+field grows the population explosively, so the number of committed steps is
+found once during warmup and every timed call runs exactly that many.
 Inputs are resident in HBM before the timed region; each step restores the
-starting particles with one device copy (included in the timing).
+starting particles with one device copy (inside the timed region).
+value = particle-steps / second of the whole timed region.
 
-Prints one JSON line (metric, value = particle-steps/s, roofline of the
-step kernel from HIP events, CPU oracle baseline on a bounded sample).
+Also reported: the roofline of the step kernel (HIP events), the CPU oracle
+on a bounded sample, and the coefficient path: batched swarms against the
+plain per-E/N swarm, surrogate training, held-out fallback and BF16
+inference on 1e8 reduced fields.  Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
+import math
 import os
 import platform
 import sys
@@ -28,8 +34,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_PSTEP = 72.0  # 36 B read + 36 B written per particle and step
-BYTES_PER_BIRTH = 116.0  # queued (40 B), read back (40 B), written to the buffer (36 B)
+# Vector peak of MI355X: 256 CUs x 64 lanes x 2.4 GHz, an FMA counted as 2
+# operations (78.6 TFLOP/s; unpacked FP32 and FP64 issue at this rate).
+VALU_PEAK_OPS = 78.6e12
+# Algorithmic work: operations per flight segment and per
+# particle-step, and bytes per particle-step and per newborn.
+OPS_PER_TRIAL = 330.0
+OPS_PER_ITEM = 60.0
+BYTES_PER_PSTEP = 72.0  # 36 B read + 36 B written
+BYTES_PER_BIRTH = 116.0  # queued (40 B), read back (40 B), written (36 B)
+KERNEL_SOURCES = ("paper_2110_14494_amd/csrc/pcmcc_kernels.hip", "paper_2110_14494_amd/csrc/pcmcc_mover.hpp",
+                  "paper_2110_14494_amd/csrc/pcmcc_device.hpp")
 
 
 def parse():
@@ -42,9 +57,19 @@ def parse():
     ap.add_argument("--cap-factor", type=int, default=32)
     ap.add_argument("--max-steps", type=int, default=None, help="cap the committed steps (profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=2 ** 17)
+    ap.add_argument("--cpu-sample", type=int, default=2 ** 18)
     ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--no-coef", action="store_true", help="skip the swarm / surrogate leg")
+    ap.add_argument("--coef-scale", type=float, default=1.0, help="scale of the swarm sizes")
+    ap.add_argument("--epochs", type=int, default=20000)
+    ap.add_argument("--infer-n", type=int, default=100_000_000)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first copy MIB mebibytes device to device (a known-size kernel for HBM counters)")
     return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def cpu_model() -> str:
@@ -55,6 +80,26 @@ def cpu_model() -> str:
     except OSError:
         pass
     return platform.processor() or "unknown"
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, p), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per particle-step of the step kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", "k_pic_steps_traffic.json")
+    try:
+        d = json.load(open(p))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha") != source_hash():
+        return None
+    return d
 
 
 def make_cfg(a):
@@ -78,24 +123,16 @@ def cpu_baseline(cfg, sample: int, steps: int) -> dict:
     return {"value": st["particle_steps"] / el, "unit": "particle-steps/s", "cores": os.cpu_count(),
             "kind": "oracle", "cpu": cpu_model(),
             "sample": f"first {n} electrons of the workload, {st['steps_done']} steps of {cfg['dt']:.0e} s "
-                      f"(oracle, OpenMP over particles, {el:.1f} s incl. table and field-bound setup)"}
+                      f"({st['particle_steps']} particle-steps in {el:.1f} s including table and field-bound "
+                      f"setup; OpenMP over particles)"}
 
 
-def main():
-    a = parse()
-    if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {a.gpus}); the multi-GPU design is documented, "
-              "not built", file=sys.stderr)
-        sys.exit(2)
+def pic_leg(a, ctx, pic):
     import torch
-    from paper_2110_14494_amd import pic
-
-    assert torch.cuda.is_available(), "needs a HIP device"
     cfg = make_cfg(a)
     n0 = cfg["parts"]["x"].size
     cap = a.cap_factor * n0
-    print(f"[bench] workload {cfg['name']} n0={n0} cap={cap}", file=sys.stderr, flush=True)
-    ctx = pic.Context(0)
+    log(f"workload {cfg['name']} n0={n0} cap={cap}")
     ctx.setup(cfg["species"], cfg["tables"])
     pristine = pic.Particles.from_numpy(cfg["parts"], n0)
     work = pic.Particles(cap)
@@ -108,11 +145,10 @@ def main():
         work.n_dev.copy_(pristine.n_dev)
         rho.zero_()
 
-    # Warmup: how many steps fit the capacity.
     reset()
     rc, st = ctx.push_collide_deposit(work, grid, cfg["dt"], cfg["n_steps"], cfg["seed"], check=False)
     n_fit = st["steps_done"] if a.max_steps is None else min(st["steps_done"], a.max_steps)
-    print(f"[bench] probe rc={rc} steps_done={n_fit} n={st['n']}", file=sys.stderr, flush=True)
+    log(f"probe rc={rc} steps_done={st['steps_done']} using {n_fit}")
     for _ in range(a.warmup):
         reset()
         ctx.push_collide_deposit(work, grid, cfg["dt"], n_fit, cfg["seed"], rho=rho)
@@ -123,31 +159,142 @@ def main():
         reset()
         rc, st = ctx.push_collide_deposit(work, grid, cfg["dt"], n_fit, cfg["seed"], rho=rho)
         stats.append(st)
-        print(f"[bench] step {k} {st['step_kernel_ms']:.1f} ms n={st['n']}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    for k, s in enumerate(stats):
+        log(f"step {k}: kernel {s['step_kernel_ms']:.1f} ms, deposit {s['deposit_kernel_ms']:.1f} ms, n={s['n']}")
     psteps = sum(s["particle_steps"] for s in stats)
-    value = psteps / el
     st = stats[-1]
-    k_ms = np.mean([s["step_kernel_ms"] for s in stats])
-    births = st["ionization"]
-    bytes_alg = BYTES_PER_PSTEP * st["particle_steps"] + BYTES_PER_BIRTH * births
-    achieved = bytes_alg / (k_ms * 1e-3) / 1e9
+    k_ms = float(np.mean([s["step_kernel_ms"] for s in stats]))
+    items = st["particle_steps"] + st["ionization"]
+    ops = OPS_PER_TRIAL * st["trials"] + OPS_PER_ITEM * items
+    bytes_alg = BYTES_PER_PSTEP * st["particle_steps"] + BYTES_PER_BIRTH * st["ionization"]
+    achieved = ops / (k_ms * 1e-3) / 1e12
+    tr = measured_traffic()
+    traffic = None
+    if tr is not None:
+        traffic = (tr["fetch_bytes_per_pstep"] + tr["write_bytes_per_pstep"]) * st["particle_steps"]
+    roof = {"bound": "alu", "kernel": "k_pic_steps", "achieved": achieved, "peak": VALU_PEAK_OPS / 1e12,
+            "unit": "TFLOP/s", "frac": achieved * 1e12 / VALU_PEAK_OPS, "traffic": traffic,
+            "ops_per_launch": ops, "kernel_ms": k_ms,
+            "hbm_algorithmic_GBs": bytes_alg / (k_ms * 1e-3) / 1e9,
+            "hbm_frac": bytes_alg / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "hbm_measured_GBs": (traffic / (k_ms * 1e-3) / 1e9) if traffic else None,
+            "deposit_ms": float(np.mean([s["deposit_kernel_ms"] for s in stats])),
+            "deposit_GBs": (16.0 * st["n"] + 8.0 * rho.numel()) / (stats[-1]["deposit_kernel_ms"] * 1e-3) / 1e9}
+    config = {"workload": cfg["name"], "n0": int(n0), "grid": int(cfg["grid"]["E"].shape[0]), "dt_s": cfg["dt"],
+              "steps_committed": int(n_fit), "capacity": int(cap), "n_final": int(st["n"]),
+              "particle_steps_per_call": int(st["particle_steps"]),
+              "trials_per_particle_step": st["trials"] / max(st["particle_steps"], 1),
+              "launch": [st["launch_grid"], st["launch_block"]]}
+    return cfg, psteps / el, el, roof, config
+
+
+def coef_leg(a, ctx, pic):
+    """Coefficient path: 2048 E/N points (8 batches of 256 swarms, sizes as the
+    batched-swarm workload), every 8th held out; surrogate trained on the GPU;
+    held-out error decides the fallback cells; BF16 inference on 1e8 fields."""
+    import torch
+    from paper_2110_14494_amd import surrogate as S
+    from paper_2110_14494_amd import workloads as W
+    sp = W.electron_species()
+    ctx.setup(sp, W.air_like_tables())
+    base = W.swarm_batch_config()
+    n_all, n_batch = 2048, 8
+    EN_all = 10.0 * 100.0 ** (np.arange(n_all) / (n_all - 1))
+    vals = np.zeros((n_all, 14))
+    errs = np.zeros((n_all, 14))
+    t_swarm = 0.0
+    for b in range(n_batch):
+        idx = np.arange(b, n_all, n_batch)
+        cfg = W.swarm_batch_config(seed=1 + b, scale=a.coef_scale)
+        t0 = time.perf_counter()
+        rc, v, e, st = pic.swarm_batch(ctx, EN_all[idx], cfg["n0"], base["dt"], base["n_steps"], 17 + b,
+                                       sample_every=base["sample_every"], window_start_s=base["window_start"],
+                                       n_batches=10)
+        t_swarm += time.perf_counter() - t0
+        vals[idx], errs[idx] = v, e
+        log(f"swarm batch {b}: {st['step_kernel_ms']:.0f} ms, {st['particle_steps']:.3g} particle-steps")
+    batched_pps = n_all / t_swarm
+    # the plain method: one swarm per launch (a few E/N values, extrapolated)
+    cfg = W.swarm_batch_config(seed=1, scale=a.coef_scale)
+    probe = [0, 85, 170, 255]
+    t0 = time.perf_counter()
+    for k in probe:
+        pic.swarm_batch(ctx, [cfg["EN_Td"][k]], cfg["n0"][k:k + 1], base["dt"], base["n_steps"], 99 + k,
+                        sample_every=base["sample_every"], window_start_s=base["window_start"], n_batches=10)
+    plain_pps = len(probe) / (time.perf_counter() - t0)
+    held = np.arange(4, n_all, n_batch)  # batch 4 = every 8th point
+    train = np.setdiff1d(np.arange(n_all), held)
+    x, t, m, ln_tr, norm = S.dataset(EN_all[train], vals[train], errs[train], sp["gas_N"], 0.1)
+    _, _, m_h, ln_h, _ = S.dataset(EN_all[held], vals[held], errs[held], sp["gas_N"], 0.1, norm=norm)
+    _, _, _, ln_all, _ = S.dataset(EN_all, vals, errs, sp["gas_N"], 0.1, norm=norm)
+    th0 = W.mlp_init(4)
+    params, hist, tst = S.train(ctx, th0, x, t, m, a.epochs, 3e-3, 1e-5)
+    log(f"surrogate trained: {a.epochs} epochs in {tst['step_kernel_ms']:.0f} ms, loss {hist[0]:.3g} -> {hist[-1]:.3g}")
+    lo, hi = math.log(10.0), math.log(1000.0)
+    tol = math.log(1.01)
+    fb, err = S.fallback(ctx, params, norm, EN_all[held], ln_h, m_h, tol, 256, lo, hi)
+    norm_fb = norm.with_fallback(fb, lo, hi, ln_all, lo, hi)
+    EN_q = torch.from_numpy(W.log_uniform_EN(a.infer_n, seed=5)).cuda()
+    out = torch.empty((6, a.infer_n), dtype=torch.float32, device="cuda")
+    S.infer(ctx, params, norm_fb, EN_q, out)  # warmup
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, ist = S.infer(ctx, params, norm_fb, EN_q, out)
+    torch.cuda.synchronize()
+    infer_s = (time.perf_counter() - t0) / reps
+    e_ok = np.where(np.isfinite(err), err, np.nan)
+    names = ("ln_muN", "ln_DLN", "ln_alpha_N", "ln_eta_N", "ln_mean_eps", "ln_bulk_flux")
+    return {
+        "swarm_points": n_all, "swarm_steps": base["n_steps"], "swarm_scale": a.coef_scale,
+        "batched_swarm_EN_points_per_s": batched_pps, "plain_swarm_EN_points_per_s": plain_pps,
+        "batched_over_plain": batched_pps / plain_pps,
+        "train_epochs": a.epochs, "train_s": tst["step_kernel_ms"] / 1e3, "train_loss": [float(hist[0]), float(hist[-1])],
+        "heldout_abs_ln_err_median": {k: float(np.nanmedian(e_ok[:, i])) for i, k in enumerate(names)},
+        "heldout_abs_ln_err_max": {k: float(np.nanmax(e_ok[:, i])) if np.any(np.isfinite(e_ok[:, i])) else None
+                                   for i, k in enumerate(names)},
+        "tolerance_ln": tol, "cells": 256, "cells_fallback": int(fb.sum()),
+        "infer_points": a.infer_n, "infer_s": infer_s, "infer_kernel_ms": ist["step_kernel_ms"],
+        "surrogate_EN_points_per_s": a.infer_n / infer_s,
+        "surrogate_over_plain_swarm": (a.infer_n / infer_s) / plain_pps,
+        "infer_GBs": 28.0 * a.infer_n / (ist["step_kernel_ms"] * 1e-3) / 1e9,
+    }
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {a.gpus}); more GPUs are a documented design, not "
+              "built", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2110_14494_amd import pic
+
+    assert torch.cuda.is_available(), "needs a HIP device"
+    ctx = pic.Context(0)
+    if a.calibrate_copy:
+        src = torch.ones(a.calibrate_copy * 2 ** 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {a.calibrate_copy} MiB done")
+        del src, dst
+    cfg, value, el, roof, config = pic_leg(a, ctx, pic)
     out = {
         "metric": "electron particle-steps/s (push+MCC+CIC)",
         "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": el / a.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
-        "config": {"workload": cfg["name"], "n0": int(n0), "grid": int(cfg["grid"]["E"].shape[0]),
-                   "dt_s": cfg["dt"], "steps_committed": int(n_fit), "capacity": int(cap),
-                   "n_final": int(st["n"]), "particle_steps_per_call": int(st["particle_steps"]),
-                   "trials_per_particle_step": st["trials"] / max(st["particle_steps"], 1)},
-        "roofline": {"bound": "hbm", "kernel": "k_pic_steps", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel_ms": k_ms, "deposit_ms": float(np.mean([s["deposit_kernel_ms"] for s in stats]))},
+        "dtype": "f32", "data": "synthetic", "config": config, "roofline": roof,
     }
     if not a.no_cpu_baseline:
+        log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(cfg, a.cpu_sample, a.cpu_steps)
+    if not a.no_coef:
+        log("coefficient path")
+        out["coefficients"] = coef_leg(a, ctx, pic)
     ctx.close()
     print(json.dumps(out))
 

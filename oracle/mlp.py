@@ -74,19 +74,6 @@ def loss_only(theta, x, t, mask):
     return np.sum(r * r) / m.sum()
 
 
-def glorot_init(seed: int) -> np.ndarray:
-    """Glorot-uniform weights, zero biases (the initial parameters are an input)."""
-    rng = np.random.default_rng(seed)
-    p = {}
-    for name, shp in SHAPES:
-        if name.startswith("W"):
-            lim = np.sqrt(6.0 / (shp[0] + shp[1]))
-            p[name] = rng.uniform(-lim, lim, size=shp)
-        else:
-            p[name] = np.zeros(shp)
-    return pack(p).astype(np.float32).astype(np.float64)
-
-
 def cosine_lr(epoch: int, epochs: int, lr0: float, lr_min: float) -> float:
     return lr_min + 0.5 * (lr0 - lr_min) * (1.0 + np.cos(np.pi * epoch / epochs))
 

@@ -160,3 +160,18 @@ def swarm_batch_config(n_swarms: int = 256, en_lo: float = 10.0, en_hi: float = 
 def log_uniform_EN(n: int, seed: int, lo: float = 10.0, hi: float = 1000.0) -> np.ndarray:
     rng = np.random.default_rng(seed)
     return (lo * (hi / lo) ** rng.random(n)).astype(np.float32)
+
+
+def mlp_init(seed: int = 4) -> np.ndarray:
+    """Initial surrogate parameters (Glorot-uniform weights, zero biases) in
+    the packed order W1[64,1], b1[64], W2[64,64], b2[64], W3[6,64], b3[6],
+    rounded to single precision; returned as float64."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for shape in ((64, 1), (64,), (64, 64), (64,), (6, 64), (6,)):
+        if len(shape) == 2:
+            lim = np.sqrt(6.0 / (shape[0] + shape[1]))
+            parts.append(rng.uniform(-lim, lim, size=shape).ravel())
+        else:
+            parts.append(np.zeros(shape))
+    return np.concatenate(parts).astype(np.float32).astype(np.float64)

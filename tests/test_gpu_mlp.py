@@ -11,6 +11,7 @@ import pytest
 import torch
 
 from oracle import mlp as M
+from paper_2110_14494_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
@@ -44,7 +45,7 @@ def test_gradient_parity(ctx, n):
     x, t, mask = _data(n, n)
     if mask.sum() == 0:
         mask[0, 0] = 1
-    th = M.glorot_init(4) + np.random.default_rng(1).normal(0, 0.1, M.N_PARAMS)
+    th = W.mlp_init(4) + np.random.default_rng(1).normal(0, 0.1, M.N_PARAMS)
     th = th.astype(np.float32).astype(np.float64)
     xf, tf = x.astype(np.float32).astype(np.float64), t.astype(np.float32).astype(np.float64)
     L_ref, g_ref = M.loss_and_grad(th, xf, tf, mask)
@@ -60,7 +61,7 @@ def test_training_reproducible_and_follows_reference(ctx):
     from paper_2110_14494_amd import surrogate as S
     x, t, mask = _data(1792, 3)
     xf, tf = x.astype(np.float32).astype(np.float64), t.astype(np.float32).astype(np.float64)
-    th0 = M.glorot_init(4)
+    th0 = W.mlp_init(4)
     epochs = 400
     p1, h1, st = S.train(ctx, th0, xf, tf, mask, epochs)
     p2, h2, _ = S.train(ctx, th0, xf, tf, mask, epochs)
@@ -79,7 +80,7 @@ def test_bf16_inference_matches_reference(ctx, n):
     from paper_2110_14494_amd import surrogate as S
     from paper_2110_14494_amd import _binding as B
     rng = np.random.default_rng(n)
-    th = (M.glorot_init(9) + rng.normal(0, 0.2, M.N_PARAMS)).astype(np.float32).astype(np.float64)
+    th = (W.mlp_init(9) + rng.normal(0, 0.2, M.N_PARAMS)).astype(np.float32).astype(np.float64)
     EN = (10 * 100 ** rng.random(n)).astype(np.float32)
     o = B.pcmcc_mlp_infer_opts()
     o.mu_x, o.sd_x = math.log(100.0), 1.3
@@ -104,7 +105,7 @@ def test_fallback_cells_use_table(ctx):
     from paper_2110_14494_amd import surrogate as S
     from paper_2110_14494_amd import _binding as B
     rng = np.random.default_rng(2)
-    th = M.glorot_init(2).astype(np.float32).astype(np.float64)
+    th = W.mlp_init(2).astype(np.float32).astype(np.float64)
     n = 100_000
     EN = (10 * 100 ** rng.random(n)).astype(np.float32)
     o = B.pcmcc_mlp_infer_opts()

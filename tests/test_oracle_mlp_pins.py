@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 from oracle import mlp as M
+from paper_2110_14494_amd import workloads as W
 
 
 def _data(n, seed):
@@ -20,13 +21,13 @@ def _data(n, seed):
 
 def test_parameter_count():
     assert M.N_PARAMS == 4678
-    th = M.glorot_init(4)
+    th = W.mlp_init(4)
     assert th.size == 4678 and np.allclose(M.pack(M.unpack(th)), th)
 
 
 def test_gradient_matches_central_differences():
     x, t, mask = _data(50, 1)
-    th = M.glorot_init(3) + np.random.default_rng(2).normal(0, 0.05, M.N_PARAMS)
+    th = W.mlp_init(3) + np.random.default_rng(2).normal(0, 0.05, M.N_PARAMS)
     L, g = M.loss_and_grad(th, x, t, mask)
     h = 1e-6
     idx = np.random.default_rng(5).choice(M.N_PARAMS, 300, replace=False)
@@ -40,7 +41,7 @@ def test_gradient_matches_central_differences():
 def test_gradient_matches_torch_autograd():
     torch = pytest.importorskip("torch")
     x, t, mask = _data(77, 2)
-    th = M.glorot_init(6)
+    th = W.mlp_init(6)
     L, g = M.loss_and_grad(th, x, t, mask)
     tt = torch.tensor(th, dtype=torch.float64, requires_grad=True)
     p, o = {}, 0
@@ -70,7 +71,7 @@ def test_bf16_rounding_known_values():
 
 def test_adam_training_fits_smooth_targets():
     x, t, mask = _data(256, 7)
-    th0 = M.glorot_init(4)
+    th0 = W.mlp_init(4)
     th, losses = M.train(th0, x, t, mask, epochs=1500, lr0=3e-3, lr_min=1e-5)
     assert losses[-1] < 1e-2 * losses[0]
     # the cosine schedule ends at lr_min
