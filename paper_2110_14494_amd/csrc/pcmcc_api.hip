@@ -64,6 +64,8 @@ struct pcmcc_ctx {
   Ctl* host_ctl = nullptr;  // pinned
   float2* fbound = nullptr;
   size_t fbound_cells = 0;
+  float4* fpack = nullptr;  // corner-packed field records
+  size_t fpack_recs = 0;
   unsigned* emax_bits = nullptr;
   int64_t* host_n = nullptr;  // pinned
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -331,17 +333,33 @@ int check_ready(pcmcc_ctx* c) {
   return PCMCC_OK;
 }
 
-// Field bounds of the majorant (per cell and global) for `g`.
-int field_bounds(pcmcc_ctx* c, const pcmcc_grid* g) {
+// Field bounds of the majorant (per cell and global) and the corner-packed
+// field for `g`.
+int prepare_field(pcmcc_ctx* c, const pcmcc_grid* g) {
   const size_t ncell = (size_t)g->nx * g->ny * g->nz;
+  const size_t nrec = ((size_t)g->nx + 2) * ((size_t)g->ny + 2) * ((size_t)g->nz + 2);
+  if (nrec >= ((size_t)1 << 31)) return fail(c, PCMCC_EINVAL, "grid too large: (nx+2)(ny+2)(nz+2) must be below 2^31");
   if (c->fbound_cells < ncell) {
     dfree(c->fbound);
     c->fbound = nullptr;
+    c->fbound_cells = 0;
     HIP_TRY(c, dalloc(&c->fbound, ncell));
     c->fbound_cells = ncell;
   }
+  if (c->fpack_recs < nrec) {
+    dfree(c->fpack);
+    c->fpack = nullptr;
+    c->fpack_recs = 0;
+    if (dalloc(&c->fpack, nrec * (kRecFloats / 4)) != hipSuccess) {
+      (void)hipGetLastError();
+      c->fpack = nullptr;
+      return fail(c, PCMCC_ENOMEM, "cannot allocate the packed field (%zu bytes)", nrec * kRecFloats * sizeof(float));
+    }
+    c->fpack_recs = nrec;
+  }
   HIP_TRY(c, hipMemsetAsync(c->emax_bits, 0, sizeof(unsigned), c->stream));
   HIP_TRY(c, launch_field_bounds((const float4*)g->E, g->nx, g->ny, g->nz, c->fbound, c->emax_bits, c->stream));
+  HIP_TRY(c, launch_pack_field((const float4*)g->E, c->fbound, g->nx, g->ny, g->nz, c->fpack, c->stream));
   return PCMCC_OK;
 }
 
@@ -402,6 +420,7 @@ int pcmcc_destroy(pcmcc_ctx* c) {
   dfree(c->partial);
   dfree(c->ctl);
   dfree(c->fbound);
+  dfree(c->fpack);
   dfree(c->emax_bits);
   if (c->host_ctl) (void)hipHostFree(c->host_ctl);
   if (c->host_n) (void)hipHostFree(c->host_n);
@@ -506,12 +525,12 @@ int pcmcc_push_collide_deposit(pcmcc_ctx* c, const pcmcc_particles* p, const pcm
   if (n0 < 0 || n0 > p->capacity) return fail(c, PCMCC_EINVAL, "particle count %lld outside [0, capacity]", (long long)n0);
   rc = ensure_scratch(c, (uint64_t)p->capacity);
   if (rc) return rc;
-  rc = field_bounds(c, field);
+  rc = prepare_field(c, field);
   if (rc) return rc;
 
   const int block = 256;
   const TableView T = table_view(c);
-  const size_t lds = table_lds_bytes(T);
+  const size_t lds = pic_lds_bytes(T, block);
   int per_cu = 0;
   HIP_TRY(c, occupancy_pic_steps(block, lds, &per_cu));
   if (per_cu < 1) return fail(c, PCMCC_EHIP, "step kernel does not fit on a compute unit");
@@ -542,11 +561,12 @@ int pcmcc_push_collide_deposit(pcmcc_ctx* c, const pcmcc_particles* p, const pcm
   A.T = T;
   A.S = species_view(c);
   GridView& G = A.G;
-  G.E = (const float4*)field->E;
-  G.bound = c->fbound;
+  G.P = c->fpack;
   G.nx = field->nx;
   G.ny = field->ny;
   G.nz = field->nz;
+  G.px = field->nx + 2;
+  G.py = field->ny + 2;
   G.o[0] = field->x0;
   G.o[1] = field->y0;
   G.o[2] = field->z0;

@@ -112,12 +112,22 @@ __device__ __forceinline__ float speed_bound(float3 v, float3 a0, float speed, f
 }
 
 // ---------------------------------------------------------------------------
-// Field on the cell-centred grid: float4 per cell (Ex, Ey, Ez, -), x fastest.
+// Field on the cell-centred grid, corner-packed.  The trilinear interpolation
+// at a point reads the fields at the 8 cell centres around it: lower centre
+// index (i, j, k) = floor((x - x0)/dx - 1/2) per axis, in [-1, n] after
+// clamping the coordinate to [-1, n], and the upper one i + 1, both clamped
+// to the grid.  The packed field holds, for every lower index (n + 2 per
+// axis), one 128-byte record: floats 3c .. 3c+2 = E at corner
+// c = 4 dz + 2 dy + dx, floats 24 and 25 = the local bound of the cell
+// clamp(i, j, k) (max |E| and field-range norm over its 4x4x4 centres).  A
+// gather therefore reads a single cache line.
+constexpr int kRecFloats = 32;
+
 struct GridView {
-  const float4* E;
-  const float2* bound;  // per cell: (max |E| over the 4x4x4 centres, field range norm)
+  const float4* P;  // packed records, kRecFloats / 4 float4 each
   int nx, ny, nz;
-  double o[3];          // origin
+  int px, py;       // records per row and per plane stride: nx + 2, ny + 2
+  double o[3];      // origin
   double inv_dx;
   float dx;
   double lo[3], hi[3];  // domain
@@ -135,36 +145,35 @@ __device__ __forceinline__ void cell_coord(double x, double o, double inv_dx, in
   f = (float)(u - fl);
 }
 
+// Record of lower centre index (i, j, k), each in [-1, n].
+__device__ __forceinline__ const float4* grid_record(const GridView& G, int i, int j, int k) {
+  const uint32_t r = ((uint32_t)(k + 1) * (uint32_t)G.py + (uint32_t)(j + 1)) * (uint32_t)G.px + (uint32_t)(i + 1);
+  return G.P + (size_t)r * (kRecFloats / 4);
+}
+
 // Trilinear interpolation with clamped indices (constant outside the
 // outermost centres), returned as acceleration (q/m) E with q/m applied in
 // double precision.
 __device__ __forceinline__ double3 gather(const GridView& G, double qm, double x, double y, double z) {
-  const int n[3] = {G.nx, G.ny, G.nz};
-  const double pos[3] = {x, y, z};
-  int i0[3], i1[3];
-  float f[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    int i;
-    cell_coord(pos[d], G.o[d], G.inv_dx, n[d], i, f[d]);
-    i0[d] = min(max(i, 0), n[d] - 1);
-    i1[d] = min(max(i + 1, 0), n[d] - 1);
-  }
-  const size_t sy = (size_t)G.nx, sz = (size_t)G.nx * G.ny;
-  const size_t r00 = i0[2] * sz + i0[1] * sy, r01 = i0[2] * sz + i1[1] * sy;
-  const size_t r10 = i1[2] * sz + i0[1] * sy, r11 = i1[2] * sz + i1[1] * sy;
-  const float4 e000 = G.E[r00 + i0[0]], e001 = G.E[r00 + i1[0]];
-  const float4 e010 = G.E[r01 + i0[0]], e011 = G.E[r01 + i1[0]];
-  const float4 e100 = G.E[r10 + i0[0]], e101 = G.E[r10 + i1[0]];
-  const float4 e110 = G.E[r11 + i0[0]], e111 = G.E[r11 + i1[0]];
-  const float gx = f[0], gy = f[1], gz = f[2];
-  auto lx = [&](float4 a, float4 b) {
-    return make_float3(fmaf(gx, b.x - a.x, a.x), fmaf(gx, b.y - a.y, a.y), fmaf(gx, b.z - a.z, a.z));
+  int i, j, k;
+  float gx, gy, gz;
+  cell_coord(x, G.o[0], G.inv_dx, G.nx, i, gx);
+  cell_coord(y, G.o[1], G.inv_dx, G.ny, j, gy);
+  cell_coord(z, G.o[2], G.inv_dx, G.nz, k, gz);
+  const float4* rec = grid_record(G, i, j, k);
+  const float4 q0 = rec[0], q1 = rec[1], q2 = rec[2], q3 = rec[3], q4 = rec[4], q5 = rec[5];
+  // corners (dz, dy, dx): 000 = q0.xyz, 001 = q0.w q1.xy, 010 = q1.zw q2.x,
+  // 011 = q2.yzw, 100 = q3.xyz, 101 = q3.w q4.xy, 110 = q4.zw q5.x, 111 = q5.yzw
+  auto lx = [&](float ax, float ay, float az, float bx, float by, float bz) {
+    return make_float3(fmaf(gx, bx - ax, ax), fmaf(gx, by - ay, ay), fmaf(gx, bz - az, az));
   };
   auto l3 = [](float t, float3 a, float3 b) {
     return make_float3(fmaf(t, b.x - a.x, a.x), fmaf(t, b.y - a.y, a.y), fmaf(t, b.z - a.z, a.z));
   };
-  const float3 e00 = lx(e000, e001), e01 = lx(e010, e011), e10 = lx(e100, e101), e11 = lx(e110, e111);
+  const float3 e00 = lx(q0.x, q0.y, q0.z, q0.w, q1.x, q1.y);
+  const float3 e01 = lx(q1.z, q1.w, q2.x, q2.y, q2.z, q2.w);
+  const float3 e10 = lx(q3.x, q3.y, q3.z, q3.w, q4.x, q4.y);
+  const float3 e11 = lx(q4.z, q4.w, q5.x, q5.y, q5.z, q5.w);
   const float3 e0 = l3(gy, e00, e01), e1 = l3(gy, e10, e11);
   const float3 e = l3(gz, e0, e1);
   return make_double3(qm * e.x, qm * e.y, qm * e.z);
@@ -181,17 +190,12 @@ __device__ __forceinline__ void accel_bound(const GridView& G, double x, double 
     da = 2.0f * G.a_glob;
     return;
   }
-  const int n[3] = {G.nx, G.ny, G.nz};
-  const double pos[3] = {x, y, z};
-  int b[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    int i;
-    float f;
-    cell_coord(pos[d], G.o[d], G.inv_dx, n[d], i, f);
-    b[d] = min(max(i, 0), n[d] - 1);
-  }
-  const float2 m = G.bound[((size_t)b[2] * G.ny + b[1]) * G.nx + b[0]];
+  int i, j, k;
+  float f;
+  cell_coord(x, G.o[0], G.inv_dx, G.nx, i, f);
+  cell_coord(y, G.o[1], G.inv_dx, G.ny, j, f);
+  cell_coord(z, G.o[2], G.inv_dx, G.nz, k, f);
+  const float4 m = grid_record(G, i, j, k)[6];
   a_abs = G.qm_abs * m.x;
   da = G.qm_abs * m.y;
 }

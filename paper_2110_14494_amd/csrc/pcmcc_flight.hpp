@@ -1,0 +1,357 @@
+// Segment-pipelined electron mover of the PIC step.
+//
+// Method: arXiv:2110.14494 Sec. 2.1.1 (velocity Verlet, eq. (1)-(2), and the
+// null-collision method) and Sec. 2.1.5 (tabulated rates).  The arithmetic of
+// each particle is the one of `advance` in pcmcc_mover.hpp, operation for
+// operation, and it draws the same random numbers; only the schedule
+// differs.
+//
+// Schedule: a lane holds one electron.  Every iteration of a wave's loop does
+// exactly one field gather per lane (at the end point of the lane's pending
+// flight segment, or at the start point of a freshly loaded electron), then
+// completes that segment (second half of the Verlet update, then the
+// collision if the segment ended in one), plans the next segment (majorant,
+// free-flight time) and moves the position to its end.  An electron that
+// reaches the end of the step, is attached or hits the segment limit leaves
+// its lane, and idle lanes take new electrons from a grid-wide work counter.
+// Lanes therefore stay busy regardless of how many segments each electron
+// needs within the step, and the gather, the only global-memory read of a
+// segment, is one instruction stream for the whole wave.
+#pragma once
+
+#include "pcmcc_mover.hpp"
+
+namespace pcmcc {
+
+enum FlightMode : int { FM_IDLE = 0, FM_NEW = 1, FM_FLY = 2 };
+enum Segment : int { SEG_END = 0, SEG_HORIZON = 1, SEG_COLLIDE = 2 };
+enum FlightEvent : int { EV_GO = 0, EV_DONE = 1, EV_ATTACHED = 2, EV_LIMIT = 3 };
+
+constexpr uint32_t kChunk = 256;  // electrons taken from the work counter at a time
+constexpr int kRefillMin = 8;     // idle lanes that trigger a refill
+
+// Per-wave staging lists in LDS.  Newborns, holes and placed newborns are
+// collected per wave and written out kFlushAt or more at a time, each batch
+// with one global atomic: events are frequent (about one newborn per
+// hundred flight segments in a streamer head), and a device-wide atomic per
+// event and wave saturates the memory-side atomic unit.  An event that finds
+// its list full (more than kStage - kFlushAt events of one wave in one
+// iteration) takes the direct path with its own atomic.
+constexpr uint32_t kStage = 64;
+constexpr uint32_t kFlushAt = 32;
+
+struct WaveStage {
+  float b[8][kStage];  // newborns: x, y, z, vx, vy, vz, w, birth time
+  uint64_t bid[kStage];
+  float s[7][kStage];  // phase 2: placed newborns x .. w (phase 1: s[0] holds hole slots)
+  uint64_t sid[kStage];
+};
+
+// Offset (in floats) of the staging lists after the staged tables in the
+// step kernel's LDS, 16-byte aligned.
+__host__ __device__ inline size_t pic_stage_offset_floats(const TableView& T) {
+  return (table_lds_floats(T) + 3) & ~(size_t)3;
+}
+
+// Newborn queue of a phase seen through the wave's staging list.
+struct StagedBirths {
+  WaveStage* L;
+  BirthSink q;  // global queue: flushes and direct pushes
+  uint32_t n;   // staged entries (wave-uniform)
+
+  // Called by the lanes that create a newborn; returns true if it was staged.
+  __device__ __forceinline__ bool push(const PState& c, float tb) const {
+    const uint32_t s = n + rank_in(__ballot(1));
+    if (s < kStage) {
+      L->b[0][s] = c.x;
+      L->b[1][s] = c.y;
+      L->b[2][s] = c.z;
+      L->b[3][s] = c.vx;
+      L->b[4][s] = c.vy;
+      L->b[5][s] = c.vz;
+      L->b[6][s] = c.w;
+      L->b[7][s] = tb;
+      L->bid[s] = c.id;
+      return true;
+    }
+    q.push(c, tb);
+    return false;
+  }
+
+  // Whole wave: writes the staged entries to the queue.
+  __device__ __forceinline__ void flush() {
+    if (n == 0) return;
+    unsigned long long base = 0;
+    if (lane_id() == 0) base = atomicAdd(q.count, (unsigned long long)n);
+    const uint64_t b = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(base >> 32)) << 32) |
+                       __builtin_amdgcn_readfirstlane((uint32_t)base);
+    const uint32_t l = lane_id();
+    if (l < n) {
+      const uint64_t slot = b + l;
+      if (slot < q.cap) {
+        q.q.x[slot] = L->b[0][l];
+        q.q.y[slot] = L->b[1][l];
+        q.q.z[slot] = L->b[2][l];
+        q.q.vx[slot] = L->b[3][l];
+        q.q.vy[slot] = L->b[4][l];
+        q.q.vz[slot] = L->b[5][l];
+        q.q.w[slot] = L->b[6][l];
+        q.q.tb[slot] = L->b[7][l];
+        q.q.id[slot] = L->bid[l];
+      } else {
+        atomicOr(q.overflow, OVF_CAPACITY);
+      }
+    }
+    n = 0;
+  }
+};
+
+struct Flight {
+  double x, y, z, vx, vy, vz, ax, ay, az;
+  double t;  // time within the step
+  double h;  // length of the pending segment
+  float a_abs, da, w, nu_hat;
+  uint64_t id;
+  uint32_t j;           // number of the next segment (random-number counter)
+  uint32_t src;         // slot the electron came from
+  uint32_t r1, r2, r3;  // uniforms of the pending collision
+  int mode, seg;
+};
+
+__device__ __forceinline__ PState flight_record(const Flight& f) {
+  PState p;
+  p.x = (float)f.x;
+  p.y = (float)f.y;
+  p.z = (float)f.z;
+  p.vx = (float)f.vx;
+  p.vy = (float)f.vy;
+  p.vz = (float)f.vz;
+  p.w = f.w;
+  p.id = f.id;
+  p.xd = f.x;
+  p.yd = f.y;
+  p.zd = f.z;
+  return p;
+}
+
+__device__ __forceinline__ void flight_start(Flight& f, const PState& p, double t0, uint32_t src) {
+  f.x = p.x;
+  f.y = p.y;
+  f.z = p.z;
+  f.vx = p.vx;
+  f.vy = p.vy;
+  f.vz = p.vz;
+  f.w = p.w;
+  f.id = p.id;
+  f.t = t0;
+  f.src = src;
+  f.j = 0;
+  f.mode = FM_NEW;
+}
+
+// Draws the next segment from the current state (acceleration valid at the
+// current position): majorant, horizon, free-flight time; then moves the
+// position to the segment's end (first half of the Verlet update).
+__device__ __forceinline__ int flight_plan(Flight& f, double dt, const Tab& T, const SpeciesView& S, Key key,
+                                           uint32_t step, Cnt& cnt) {
+  if (f.j >= (uint32_t)kMaxSegments) {
+    cnt.v[C_ERR]++;
+    return EV_LIMIT;
+  }
+  const uint4 r = draw(key, f.id, step, f.j, TAG_MAIN);
+  f.j++;
+  cnt.v[C_TRIALS]++;
+  const double t_rem = dt - f.t;
+  const float3 vf = make_float3((float)f.vx, (float)f.vy, (float)f.vz);
+  const float3 af = make_float3((float)f.ax, (float)f.ay, (float)f.az);
+  const float speed = sqrtf(vf.x * vf.x + vf.y * vf.y + vf.z * vf.z);
+  const float nu_full = majorant_t(T, S, speed_bound(vf, af, speed, f.a_abs, f.da, (float)t_rem));
+  const bool limited = kKappa < nu_full * (float)t_rem;
+  // Both majorants are evaluated and one is selected, which keeps the lanes
+  // of a wave on one path (nu_full = 0 gives an unused, finite lookup).
+  const float h_lim = kKappa / nu_full;
+  const float nu_lim = majorant_t(T, S, speed_bound(vf, af, speed, f.a_abs, f.da, h_lim));
+  const double h = limited ? (double)h_lim : t_rem;
+  const float nu_hat = limited ? nu_lim : nu_full;
+  const double tau = nu_hat > 0.0f ? (double)(-__logf(unif(r.x)) / nu_hat) : (double)INFINITY;
+  double hs;
+  if (tau >= h) {
+    hs = h;
+    f.seg = limited ? SEG_HORIZON : SEG_END;
+  } else {
+    hs = tau;
+    f.seg = SEG_COLLIDE;
+  }
+  f.r1 = r.y;
+  f.r2 = r.z;
+  f.r3 = r.w;
+  f.nu_hat = nu_hat;
+  f.h = hs;
+  f.x += hs * fma(0.5 * f.ax, hs, f.vx);
+  f.y += hs * fma(0.5 * f.ay, hs, f.vy);
+  f.z += hs * fma(0.5 * f.az, hs, f.vz);
+  if (f.seg != SEG_END) f.t += hs;
+  return EV_GO;
+}
+
+// Completes the pending segment with the acceleration `an` gathered at its
+// end point, then applies its collision, if any.
+__device__ __forceinline__ int flight_complete(Flight& f, const double3 an, const Tab& T, const SpeciesView& S,
+                                               Key key, uint32_t step, Cnt& cnt, const StagedBirths& births,
+                                               bool& staged) {
+  const double hh = 0.5 * f.h;
+  f.vx = fma(f.ax + an.x, hh, f.vx);
+  f.vy = fma(f.ay + an.y, hh, f.vy);
+  f.vz = fma(f.az + an.z, hh, f.vz);
+  f.ax = an.x;
+  f.ay = an.y;
+  f.az = an.z;
+  if (f.seg == SEG_END) return EV_DONE;
+  if (f.seg == SEG_HORIZON) return EV_GO;
+
+  // Candidate collision: real process k, or null.
+  const double v2 = f.vx * f.vx + f.vy * f.vy + f.vz * f.vz;
+  const double eps = (double)S.k_eps_d * v2;
+  float u = __log2f((float)eps) * T.u_scale + T.u_offset;
+  u = fminf(fmaxf(u, 0.0f), (float)(T.n - 1));
+  const float fl = fminf(floorf(u), (float)(T.n - 2));
+  const int i = (int)fl;
+  const float fr = u - fl;
+  const float yv = unif(f.r1) * f.nu_hat;
+  // All cumulative rates are read at once (independent LDS loads), then the
+  // first process whose cumulative rate exceeds yv is taken.
+  float cum[kMaxProc];
+#pragma unroll
+  for (int kk = 0; kk < kMaxProc; ++kk) cum[kk] = kk < T.nproc ? lerp_at(T.C + kk * T.n, i, fr) : INFINITY;
+  int k = -1;
+#pragma unroll
+  for (int kk = kMaxProc - 1; kk >= 0; --kk)
+    if (kk < T.nproc && yv < cum[kk]) k = kk;
+  if (k < 0 || eps < (double)T.thr[k]) {
+    cnt.v[C_NULL]++;
+    return EV_GO;
+  }
+  if (eps > (double)T.eps_max) cnt.v[C_OOT]++;
+  const int kind = T.kind[k];
+  cnt.v[C_EL] += kind == ELASTIC;
+  cnt.v[C_EXC] += kind == EXCITATION;
+  cnt.v[C_ION] += kind == IONIZATION;
+  cnt.v[C_ATT] += kind == ATTACHMENT;
+  if (kind == ATTACHMENT) return EV_ATTACHED;
+
+  double nx, ny, nz;
+  iso_dir(f.r2, f.r3, nx, ny, nz);
+  const double thr = (double)T.thr[k];
+  double eps_new;
+  if (kind == ELASTIC) {
+    const double sc = sqrt(v2);
+    const double cchi = sc > 0.0 ? (f.vx * nx + f.vy * ny + f.vz * nz) / sc : 0.0;
+    eps_new = eps * (1.0 - (double)S.recoil * (1.0 - cchi));
+  } else if (kind == EXCITATION) {
+    eps_new = eps - thr;
+  } else {
+    eps_new = 0.5 * (eps - thr);
+    const uint4 b = draw(key, f.id, step, f.j - 1, TAG_BIRTH);
+    PState c;
+    c.x = (float)f.x;
+    c.y = (float)f.y;
+    c.z = (float)f.z;
+    c.w = f.w;
+    c.id = (uint64_t)b.x | ((uint64_t)b.y << 32);
+    double cx, cy, cz;
+    iso_dir(b.z, b.w, cx, cy, cz);
+    const double cs = sqrt(eps_new * S.inv_k_d);
+    c.vx = (float)(cs * cx);
+    c.vy = (float)(cs * cy);
+    c.vz = (float)(cs * cz);
+    staged = births.push(c, (float)f.t);
+  }
+  const double sn = sqrt(eps_new * S.inv_k_d);
+  f.vx = sn * nx;
+  f.vy = sn * ny;
+  f.vz = sn * nz;
+  return EV_GO;
+}
+
+// Runs every electron of a source (n of them) through the rest of the step.
+// Source: load(i, Flight&) starts electron i.  Finish: done(Flight&, event,
+// Cnt&, WaveStage*, staged count, bool& staged) takes an electron that left
+// its lane, flush(WaveStage*, count) writes out the wave's staged results.
+// Must be called by whole waves with wave-uniform arguments; `take` is the
+// grid-wide work counter (zero before the first wave starts).  Every staged
+// entry is written out before the function returns.
+template <class Field, class Source, class Finish>
+__device__ __forceinline__ void fly_all(uint64_t n, unsigned long long* take, double dt, const Field& F, const Tab& T,
+                                        const SpeciesView& S, Key key, uint32_t step, Cnt& cnt,
+                                        const BirthSink& sink, WaveStage* L, const Source& source,
+                                        const Finish& finish) {
+  Flight f;
+  f.mode = FM_IDLE;
+  StagedBirths births{L, sink, 0u};
+  uint32_t n_done = 0;  // entries of the finish list
+  uint64_t pool_next = 0, pool_end = 0;
+  bool dry = n == 0;
+  const uint32_t lane = lane_id();
+  for (;;) {
+    const uint64_t idle = __ballot(f.mode == FM_IDLE);
+    const uint32_t n_idle = (uint32_t)__popcll(idle);
+    if (!dry && (n_idle >= (uint32_t)kRefillMin || n_idle == 64u)) {
+      const uint32_t rank = rank_in(idle);
+      uint32_t served = 0;
+      while (served < n_idle) {
+        if (pool_next == pool_end) {
+          unsigned long long base = 0;
+          if (lane == 0) base = atomicAdd(take, (unsigned long long)kChunk);
+          const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
+          const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
+          const uint64_t b = ((uint64_t)hi << 32) | lo;
+          if (b >= n) {
+            dry = true;
+            break;
+          }
+          pool_next = b;
+          pool_end = b + kChunk < n ? b + kChunk : n;
+        }
+        const uint32_t avail = (uint32_t)(pool_end - pool_next);
+        const uint32_t got = avail < n_idle - served ? avail : n_idle - served;
+        if (f.mode == FM_IDLE && rank >= served && rank < served + got) source.load(pool_next + (rank - served), f);
+        pool_next += got;
+        served += got;
+      }
+    }
+    if (__ballot(f.mode != FM_IDLE) == 0) break;
+    bool born = false, placed = false;
+    if (f.mode != FM_IDLE) {
+      const double3 an = F.accel(f.x, f.y, f.z);
+      int ev;
+      if (f.mode == FM_NEW) {
+        f.ax = an.x;
+        f.ay = an.y;
+        f.az = an.z;
+        F.bound(f.x, f.y, f.z, sqrtf((float)(f.vx * f.vx + f.vy * f.vy + f.vz * f.vz)), (float)(dt - f.t), f.a_abs,
+                f.da);
+        f.mode = FM_FLY;
+        ev = EV_GO;
+      } else {
+        ev = flight_complete(f, an, T, S, key, step, cnt, births, born);
+      }
+      if (ev == EV_GO) ev = flight_plan(f, dt, T, S, key, step, cnt);
+      if (ev != EV_GO) {
+        finish.done(f, ev, cnt, L, n_done, placed);
+        f.mode = FM_IDLE;
+      }
+    }
+    // Whole wave again: count what was staged, write out full lists.
+    births.n += (uint32_t)__popcll(__ballot(born));
+    n_done += (uint32_t)__popcll(__ballot(placed));
+    if (births.n >= kFlushAt) births.flush();
+    if (n_done >= kFlushAt) {
+      finish.flush(L, n_done);
+      n_done = 0;
+    }
+  }
+  births.flush();
+  if (n_done > 0) finish.flush(L, n_done);
+}
+
+}  // namespace pcmcc

@@ -41,6 +41,7 @@ struct Ctl {
   unsigned long long donors;  // tail donors found (hole filling)
   unsigned long long fill;    // holes filled from the tail
   unsigned long long pend[kMaxGenerations + 1];  // newborns queued per generation
+  unsigned long long take[kMaxGenerations + 1];  // work counters: current buffer, then each generation
   unsigned overflow;          // Overflow bits of the running step
   int cur_sel;                // 0: the caller's arrays are current, 1: the scratch buffer
   int stop;
@@ -179,6 +180,7 @@ hipError_t launch_mlp_train(const MlpArgs& a, int grid, hipStream_t stream);
 hipError_t launch_mlp_infer(const InferArgs& a, int grid, hipStream_t stream);
 
 size_t table_lds_bytes(const TableView& T);
+size_t pic_lds_bytes(const TableView& T, int block);  // step kernel: tables and per-wave staging lists
 size_t swarm_lds_bytes(const TableView& T, int S, int block);
 hipError_t occupancy_swarm_steps(int block, size_t lds, int* blocks_per_cu);
 hipError_t launch_swarm_steps(const SwarmArgs& args, int grid, int block, hipStream_t stream);
@@ -193,6 +195,8 @@ hipError_t launch_deposit(const float* x, const float* y, const float* z, const 
                           const DepositGeom& g, int64_t* rho, hipStream_t stream);
 hipError_t launch_field_bounds(const float4* E, int nx, int ny, int nz, float2* out, unsigned* emax_bits,
                                hipStream_t stream);
+hipError_t launch_pack_field(const float4* E, const float2* bound, int nx, int ny, int nz, float4* P,
+                             hipStream_t stream);
 hipError_t launch_build_tables(const TableBuild& B, float* C, float* P, float* nu, hipStream_t stream);
 hipError_t launch_philox(const uint32_t* ctr, Key key, uint32_t* out, int64_t n, hipStream_t stream);
 hipError_t launch_lookup(const TableView& T, const SpeciesView& S, const float* eps, float* cum, const float* s_ub,

@@ -9,9 +9,9 @@
 // trilinear weighting (Sec. 2.1.3).
 //
 // Layout: particles are structure-of-arrays single precision (x, y, z, vx,
-// vy, vz, w) plus a 64-bit id; each wave owns contiguous runs of 64
-// particles, so every load and store is a coalesced 256-byte row per array.
-// A step never moves survivors: particle i of the current buffer is written
+// vy, vz, w) plus a 64-bit id.  Waves take electrons in chunks of 256
+// consecutive slots from a grid-wide counter and keep every lane busy with
+// the segment-pipelined mover (pcmcc_flight.hpp).  A step never moves survivors: particle i of the current buffer is written
 // to slot i of the next buffer (ping-pong, so a step that would overflow the
 // capacity leaves the previous state intact); the few removed particles
 // leave holes that the step's newborns fill first, and any holes left over
@@ -22,11 +22,135 @@
 
 #include "pcmcc_device.hpp"
 #include "pcmcc_internal.hpp"
+#include "pcmcc_flight.hpp"
 #include "pcmcc_mover.hpp"
 
 namespace cg = cooperative_groups;
 
 namespace pcmcc {
+
+// ---------------------------------------------------------------------------
+// Electron sources and destinations of the two phases of a step.
+
+// Phase 1 source: the current buffer, every electron from t = 0.
+struct SoaSource {
+  Soa s;
+  __device__ __forceinline__ void load(uint64_t i, Flight& f) const {
+    PState p;
+    load_p(s, i, p);
+    flight_start(f, p, 0.0, (uint32_t)i);
+  }
+};
+
+// Phase 2 source: a newborn queue, each electron from its birth time.
+struct PendSource {
+  PendSoa s;
+  __device__ __forceinline__ void load(uint64_t i, Flight& f) const {
+    PState p;
+    float tb;
+    load_pend(s, i, p, tb);
+    flight_start(f, p, (double)tb, (uint32_t)i);
+  }
+};
+
+// Phase 1 destination: a survivor keeps its slot in the next buffer; a
+// removed electron leaves a hole there (hole slots are staged per wave).
+struct KeepInPlace {
+  const GridView* G;
+  Soa nxt;
+  uint32_t* holes;
+  unsigned long long* n_holes;
+  __device__ __forceinline__ void done(const Flight& f, int ev, Cnt& cnt, WaveStage* L, uint32_t n_staged,
+                                       bool& staged) const {
+    const PState p = flight_record(f);
+    bool alive = ev == EV_DONE;
+    if (alive && !inside(*G, p)) {
+      alive = false;
+      cnt.v[C_LOST]++;
+    }
+    if (alive) {
+      store_p(nxt, f.src, p);
+    } else {
+      const uint32_t s = n_staged + rank_in(__ballot(1));
+      if (s < kStage) {
+        reinterpret_cast<uint32_t*>(L->s[0])[s] = f.src;
+        staged = true;
+      } else {
+        holes[wave_reserve(n_holes)] = f.src;
+      }
+    }
+  }
+  __device__ __forceinline__ void flush(WaveStage* L, uint32_t n) const {
+    unsigned long long base = 0;
+    if (lane_id() == 0) base = atomicAdd(n_holes, (unsigned long long)n);
+    const uint64_t b = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(base >> 32)) << 32) |
+                       __builtin_amdgcn_readfirstlane((uint32_t)base);
+    const uint32_t l = lane_id();
+    if (l < n) holes[b + l] = reinterpret_cast<const uint32_t*>(L->s[0])[l];
+  }
+};
+
+// Phase 2 destination: a surviving newborn fills the next hole, or appends
+// after the current count once the holes are used up (placements are staged
+// per wave).
+struct PlaceNewborn {
+  const GridView* G;
+  Soa nxt;
+  const uint32_t* holes;
+  uint64_t n_holes, n_cur, cap;
+  unsigned long long* child;
+  unsigned* overflow;
+  __device__ __forceinline__ void place(uint64_t slot, const PState& p) const {
+    const uint64_t dst = slot < n_holes ? (uint64_t)holes[slot] : n_cur + (slot - n_holes);
+    if (dst < cap)
+      store_p(nxt, dst, p);
+    else
+      atomicOr(overflow, OVF_CAPACITY);
+  }
+  __device__ __forceinline__ void done(const Flight& f, int ev, Cnt& cnt, WaveStage* L, uint32_t n_staged,
+                                       bool& staged) const {
+    const PState p = flight_record(f);
+    bool alive = ev == EV_DONE;
+    if (alive && !inside(*G, p)) {
+      alive = false;
+      cnt.v[C_LOST]++;
+    }
+    if (!alive) return;
+    const uint32_t s = n_staged + rank_in(__ballot(1));
+    if (s < kStage) {
+      L->s[0][s] = p.x;
+      L->s[1][s] = p.y;
+      L->s[2][s] = p.z;
+      L->s[3][s] = p.vx;
+      L->s[4][s] = p.vy;
+      L->s[5][s] = p.vz;
+      L->s[6][s] = p.w;
+      L->sid[s] = p.id;
+      staged = true;
+    } else {
+      place(wave_reserve(child), p);
+    }
+  }
+  __device__ __forceinline__ void flush(WaveStage* L, uint32_t n) const {
+    unsigned long long base = 0;
+    if (lane_id() == 0) base = atomicAdd(child, (unsigned long long)n);
+    const uint64_t b = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(base >> 32)) << 32) |
+                       __builtin_amdgcn_readfirstlane((uint32_t)base);
+    const uint32_t l = lane_id();
+    if (l < n) {
+      PState p;
+      p.x = L->s[0][l];
+      p.y = L->s[1][l];
+      p.z = L->s[2][l];
+      p.vx = L->s[3][l];
+      p.vy = L->s[4][l];
+      p.vz = L->s[5][l];
+      p.w = L->s[6][l];
+      p.id = L->sid[l];
+      place(b + l, p);
+    }
+  }
+};
 
 // ---------------------------------------------------------------------------
 // The step loop.  One cooperative launch runs all n_steps steps; grid-wide
@@ -36,13 +160,11 @@ __global__ __launch_bounds__(256) void k_pic_steps(PicArgs A) {
   extern __shared__ float smem[];
   cg::grid_group grid = cg::this_grid();
   const Tab T = stage_tables(A.T, smem);
+  WaveStage* L = reinterpret_cast<WaveStage*>(smem + pic_stage_offset_floats(A.T)) + (threadIdx.x >> 6);
   GridView G = A.G;
   G.a_glob = G.qm_abs * __uint_as_float(*A.emax_bits);
   const GridField F{G, A.S.qm};
   const unsigned lane = lane_id();
-  const uint64_t wpb = blockDim.x >> 6;
-  const uint64_t gw = (uint64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
-  const uint64_t GW = (uint64_t)gridDim.x * wpb;
   Ctl* ctl = A.ctl;
 
   for (int s = 0; s < A.n_steps; ++s) {
@@ -58,24 +180,9 @@ __global__ __launch_bounds__(256) void k_pic_steps(PicArgs A) {
     // Phase 1: every particle of the current buffer, from t = 0.
     {
       const BirthSink sink{A.pend[0], &ctl->pend[0], A.pend_cap, &ctl->overflow, 0u};
-      for (uint64_t base = gw * 64; base < n_cur; base += GW * 64) {
-        const uint64_t i = base + lane;
-        if (i < n_cur) {
-          PState p;
-          load_p(cur, i, p);
-          const int r = advance(p, 0.0f, A.dt, F, T, A.S, A.key, step, cnt, sink);
-          bool alive = r == 0;
-          if (alive && !inside(A.G, p)) {
-            alive = false;
-            cnt.v[C_LOST]++;
-          }
-          if (alive) {
-            store_p(nxt, i, p);
-          } else {
-            A.holes[wave_reserve(&ctl->holes)] = (uint32_t)i;
-          }
-        }
-      }
+      const SoaSource src{cur};
+      const KeepInPlace fin{&A.G, nxt, A.holes, &ctl->holes};
+      fly_all(n_cur, &ctl->take[0], A.dt, F, T, A.S, A.key, step, cnt, sink, L, src, fin);
     }
     grid.sync();
 
@@ -90,35 +197,10 @@ __global__ __launch_bounds__(256) void k_pic_steps(PicArgs A) {
         break;
       }
       const uint64_t np = np_raw < A.pend_cap ? np_raw : A.pend_cap;
-      const PendSoa src = A.pend[g & 1];
       const BirthSink sink{A.pend[(g + 1) & 1], &ctl->pend[g + 1], A.pend_cap, &ctl->overflow, 0u};
-      for (uint64_t base = gw * 64; base < np; base += GW * 64) {
-        const uint64_t i = base + lane;
-        if (i < np) {
-          PState p;
-          float tb;
-          load_pend(src, i, p, tb);
-          const int r = advance(p, tb, A.dt, F, T, A.S, A.key, step, cnt, sink);
-          bool alive = r == 0;
-          if (alive && !inside(A.G, p)) {
-            alive = false;
-            cnt.v[C_LOST]++;
-          }
-          if (alive) {
-            const uint64_t slot = wave_reserve(&ctl->child);
-            uint64_t dst;
-            if (slot < h) {
-              dst = A.holes[slot];
-            } else {
-              dst = n_cur + (slot - h);
-            }
-            if (dst < A.cap)
-              store_p(nxt, dst, p);
-            else
-              atomicOr(&ctl->overflow, OVF_CAPACITY);
-          }
-        }
-      }
+      const PendSource src{A.pend[g & 1]};
+      const PlaceNewborn fin{&A.G, nxt, A.holes, h, n_cur, A.cap, &ctl->child, &ctl->overflow};
+      fly_all(np, &ctl->take[g + 1], A.dt, F, T, A.S, A.key, step, cnt, sink, L, src, fin);
       grid.sync();
     }
 
@@ -187,7 +269,10 @@ __global__ __launch_bounds__(256) void k_pic_steps(PicArgs A) {
         ctl->donors = 0;
         ctl->fill = 0;
         ctl->overflow = 0;
-        for (int g = 0; g <= kMaxGenerations; ++g) ctl->pend[g] = 0;
+        for (int g = 0; g <= kMaxGenerations; ++g) {
+          ctl->pend[g] = 0;
+          ctl->take[g] = 0;
+        }
       }
     }
     grid.sync();
@@ -291,6 +376,38 @@ __global__ void k_field_bounds(const float4* __restrict__ E, int nx, int ny, int
   if (lane_id() == 0) atomicMax(emax_bits, __float_as_uint(local_max));
 }
 
+// Corner-packed field (layout in pcmcc_device.hpp): one thread per record,
+// the record of lower centre index (i, j, k) in [-1, n]^3 holding the fields
+// of the 8 centres around it (indices clamped to the grid) and the bound of
+// the cell clamp(i, j, k).
+__global__ void k_pack_field(const float4* __restrict__ E, const float2* __restrict__ bound, int nx, int ny, int nz,
+                             float4* __restrict__ P) {
+  const uint64_t px = (uint64_t)nx + 2, py = (uint64_t)ny + 2;
+  const uint64_t nrec = px * py * ((uint64_t)nz + 2);
+  for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nrec; r += (uint64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(r % px) - 1, j = (int)((r / px) % py) - 1, k = (int)(r / (px * py)) - 1;
+    const int ci[2] = {min(max(i, 0), nx - 1), min(max(i + 1, 0), nx - 1)};
+    const int cj[2] = {min(max(j, 0), ny - 1), min(max(j + 1, 0), ny - 1)};
+    const int ck[2] = {min(max(k, 0), nz - 1), min(max(k + 1, 0), nz - 1)};
+    float v[kRecFloats];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const float4 e = E[((size_t)ck[c >> 2] * ny + cj[(c >> 1) & 1]) * nx + ci[c & 1]];
+      v[3 * c] = e.x;
+      v[3 * c + 1] = e.y;
+      v[3 * c + 2] = e.z;
+    }
+    const float2 b = bound[((size_t)ck[0] * ny + cj[0]) * nx + ci[0]];
+    v[24] = b.x;
+    v[25] = b.y;
+#pragma unroll
+    for (int q = 26; q < kRecFloats; ++q) v[q] = 0.0f;
+    float4* out = P + r * (kRecFloats / 4);
+#pragma unroll
+    for (int q = 0; q < kRecFloats / 4; ++q) out[q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Collision tables in double precision, stored as single precision: rates
 // nu_k = N sigma_k v at each node (Sec. 2.1.5), cumulative sums in process
@@ -353,10 +470,14 @@ __global__ void k_lookup(TableView TV, SpeciesView S, const float* __restrict__ 
 
 size_t table_lds_bytes(const TableView& T) { return table_lds_floats(T) * sizeof(float); }
 
+size_t pic_lds_bytes(const TableView& T, int block) {
+  return pic_stage_offset_floats(T) * sizeof(float) + (size_t)(block / 64) * sizeof(WaveStage);
+}
+
 hipError_t launch_pic_steps(const PicArgs& args, int grid, int block, hipStream_t stream) {
   void* kargs[] = {(void*)&args};
   return hipLaunchCooperativeKernel((const void*)k_pic_steps, dim3(grid), dim3(block), kargs,
-                                    (unsigned)table_lds_bytes(args.T), stream);
+                                    (unsigned)pic_lds_bytes(args.T, block), stream);
 }
 
 hipError_t occupancy_pic_steps(int block, size_t lds, int* blocks_per_cu) {
@@ -380,6 +501,14 @@ hipError_t launch_field_bounds(const float4* E, int nx, int ny, int nz, float2* 
   const size_t ncell = (size_t)nx * ny * nz;
   const int blocks = (int)std::min<size_t>((ncell + 255) / 256, 16384);
   hipLaunchKernelGGL(k_field_bounds, dim3(blocks), dim3(256), 0, stream, E, nx, ny, nz, out, emax_bits);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_field(const float4* E, const float2* bound, int nx, int ny, int nz, float4* P,
+                             hipStream_t stream) {
+  const uint64_t nrec = ((uint64_t)nx + 2) * ((uint64_t)ny + 2) * ((uint64_t)nz + 2);
+  const uint64_t blocks = std::min<uint64_t>((nrec + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_pack_field, dim3((unsigned)blocks), dim3(256), 0, stream, E, bound, nx, ny, nz, P);
   return hipGetLastError();
 }
 
