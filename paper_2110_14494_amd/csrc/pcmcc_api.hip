@@ -66,6 +66,8 @@ struct pcmcc_ctx {
   size_t fbound_cells = 0;
   float4* fpack = nullptr;  // corner-packed field records
   size_t fpack_recs = 0;
+  DepositWork dep{};        // binned deposit buffers
+  uint64_t dep_tiles = 0, dep_dump = 0, dep_sorted = 0;
   unsigned* emax_bits = nullptr;
   int64_t* host_n = nullptr;  // pinned
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -363,6 +365,47 @@ int prepare_field(pcmcc_ctx* c, const pcmcc_grid* g) {
   return PCMCC_OK;
 }
 
+// Charge deposit of n particles (n_dev holds the same count on the device):
+// direct kernel for small n, binned schedule from kDepositBinnedMin on.
+int run_deposit(pcmcc_ctx* c, const float* x, const float* y, const float* z, const float* w, const int64_t* n_dev,
+                uint64_t n, const pcmcc_grid* grid, int64_t* rho) {
+  const DepositGeom g{grid->nx, grid->ny, grid->nz, grid->x0, grid->y0, grid->z0, 1.0 / grid->dx};
+  const DepositNeeds d = deposit_needs(g, n);
+  if (!d.binned) {
+    HIP_TRY(c, launch_deposit(x, y, z, w, n_dev, g, rho, c->stream));
+    return PCMCC_OK;
+  }
+  if (n >= 0xFFFFFFFFull) return fail(c, PCMCC_EINVAL, "deposit of 2^32 or more particles");
+  auto grow = [&](auto** ptr, uint64_t& have, uint64_t need) -> int {
+    if (have >= need) return PCMCC_OK;
+    dfree(*ptr);
+    *ptr = nullptr;
+    have = 0;
+    if (dalloc(ptr, need) != hipSuccess) {
+      (void)hipGetLastError();
+      *ptr = nullptr;
+      return fail(c, PCMCC_ENOMEM, "cannot allocate deposit buffers");
+    }
+    have = need;
+    return PCMCC_OK;
+  };
+  // tile_count and tile_start share one capacity (n_tiles + 1 entries each)
+  int rc = PCMCC_OK;
+  if (c->dep_tiles < d.n_tiles + 1) {
+    uint64_t have = 0;
+    rc = grow(&c->dep.tile_count, have, d.n_tiles + 1);
+    have = 0;
+    if (!rc) rc = grow(&c->dep.tile_start, have, d.n_tiles + 1);
+    c->dep_tiles = rc ? 0 : d.n_tiles + 1;
+    if (rc) return rc;
+  }
+  rc = grow(&c->dep.dump, c->dep_dump, d.dump_entries);
+  if (!rc) rc = grow(&c->dep.sorted, c->dep_sorted, d.sorted);
+  if (rc) return rc;
+  HIP_TRY(c, launch_deposit_binned(x, y, z, w, n, g, rho, c->dep, c->stream));
+  return PCMCC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -421,6 +464,10 @@ int pcmcc_destroy(pcmcc_ctx* c) {
   dfree(c->ctl);
   dfree(c->fbound);
   dfree(c->fpack);
+  dfree(c->dep.tile_count);
+  dfree(c->dep.tile_start);
+  dfree(c->dep.dump);
+  dfree(c->dep.sorted);
   dfree(c->emax_bits);
   if (c->host_ctl) (void)hipHostFree(c->host_ctl);
   if (c->host_n) (void)hipHostFree(c->host_n);
@@ -592,9 +639,9 @@ int pcmcc_push_collide_deposit(pcmcc_ctx* c, const pcmcc_particles* p, const pcm
   const Ctl& h = *c->host_ctl;
   rc = h.status;
   if (rc == PCMCC_OK && rho) {
-    DepositGeom g{field->nx, field->ny, field->nz, field->x0, field->y0, field->z0, 1.0 / field->dx};
     HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
-    HIP_TRY(c, launch_deposit(p->x, p->y, p->z, p->w, p->n_dev, g, rho, c->stream));
+    const int drc = run_deposit(c, p->x, p->y, p->z, p->w, p->n_dev, h.n_cur, field, rho);
+    if (drc) return drc;
     HIP_TRY(c, hipEventRecord(c->ev[3], c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     float ms = 0;
@@ -1141,8 +1188,12 @@ int pcmcc_deposit(pcmcc_ctx* c, const float* x, const float* y, const float* z, 
   if (!grid || grid->nx < 1 || grid->ny < 1 || grid->nz < 1 || !(grid->dx > 0))
     return fail(c, PCMCC_EINVAL, "invalid grid");
   HIP_TRY(c, hipSetDevice(c->device));
-  DepositGeom g{grid->nx, grid->ny, grid->nz, grid->x0, grid->y0, grid->z0, 1.0 / grid->dx};
-  HIP_TRY(c, launch_deposit(x, y, z, w, n_dev, g, rho, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->host_n, n_dev, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const int64_t n = *c->host_n;
+  if (n < 0) return fail(c, PCMCC_EINVAL, "negative particle count");
+  const int rc = run_deposit(c, x, y, z, w, n_dev, (uint64_t)n, grid, rho);
+  if (rc) return rc;
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return PCMCC_OK;
 }

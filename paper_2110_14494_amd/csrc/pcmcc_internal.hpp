@@ -75,6 +75,20 @@ struct DepositGeom {
   double x0, y0, z0, inv_dx;
 };
 
+// Binned deposit: used from this many particles on (below, the direct
+// kernel), and the device buffers it needs.
+constexpr uint64_t kDepositBinnedMin = 1u << 18;
+struct DepositNeeds {
+  bool binned;
+  uint64_t n_tiles, dump_entries, sorted;
+};
+struct DepositWork {
+  uint32_t* tile_count;  // [n_tiles]
+  uint32_t* tile_start;  // [n_tiles + 1]
+  uint2* dump;           // [dump_entries]
+  float4* sorted;        // [n]
+};
+
 struct TableBuild {
   int n, nproc;
   double lnmin, dlog, ev, mass, gas_N;
@@ -191,6 +205,9 @@ hipError_t launch_swarm_estimate(const unsigned long long* mom, const long long*
 hipError_t launch_pic_steps(const PicArgs& args, int grid, int block, hipStream_t stream);
 hipError_t occupancy_pic_steps(int block, size_t lds, int* blocks_per_cu);
 hipError_t launch_finalize(const Soa& user, const Soa& scratch, Ctl* ctl, int64_t* n_dev, hipStream_t stream);
+DepositNeeds deposit_needs(const DepositGeom& g, uint64_t n);
+hipError_t launch_deposit_binned(const float* x, const float* y, const float* z, const float* w, uint64_t n,
+                                 const DepositGeom& g, int64_t* rho, const DepositWork& W, hipStream_t stream);
 hipError_t launch_deposit(const float* x, const float* y, const float* z, const float* w, const int64_t* n_dev,
                           const DepositGeom& g, int64_t* rho, hipStream_t stream);
 hipError_t launch_field_bounds(const float4* E, int nx, int ny, int nz, float2* out, unsigned* emax_bits,

@@ -294,54 +294,6 @@ __global__ void k_finalize(Soa user, Soa scratch, Ctl* ctl, int64_t* n_dev) {
 }
 
 // ---------------------------------------------------------------------------
-// Deposit: trilinear weights in double precision without contraction, each
-// corner rounded to 2^-32 fixed point and the last corner taking the
-// remainder, so the integer sum is independent of order and exactly
-// conserves round(w 2^32) per particle.
-__global__ void k_deposit(const float* __restrict__ x, const float* __restrict__ y, const float* __restrict__ z,
-                          const float* __restrict__ w, const int64_t* n_dev, DepositGeom g,
-                          unsigned long long* rho) {
-#pragma clang fp contract(off)
-  const uint64_t n = (uint64_t)*n_dev;
-  for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (uint64_t)gridDim.x * blockDim.x) {
-    const double pos[3] = {(double)x[p], (double)y[p], (double)z[p]};
-    const double o[3] = {g.x0, g.y0, g.z0};
-    const int nn[3] = {g.nx, g.ny, g.nz};
-    const double wd = (double)w[p];
-    const long long qw = __double2ll_rn(wd * 4294967296.0);
-    int ic[3][2];
-    double W[3][2];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      double u = (pos[d] - o[d]) * g.inv_dx - 0.5;
-      u = fmin(fmax(u, -1.0), (double)nn[d]);
-      const double fl = floor(u);
-      const double f = u - fl;
-      const int i = (int)fl;
-      ic[d][0] = min(max(i, 0), nn[d] - 1);
-      ic[d][1] = min(max(i + 1, 0), nn[d] - 1);
-      W[d][0] = 1.0 - f;
-      W[d][1] = f;
-    }
-    long long given = 0;
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const int dz = c >> 2, dy = (c >> 1) & 1, dx = c & 1;
-      long long q;
-      if (c == 7) {
-        q = qw - given;
-      } else {
-        const double frac = (W[0][dx] * W[1][dy]) * W[2][dz];
-        q = __double2ll_rn((wd * frac) * 4294967296.0);
-        given += q;
-      }
-      const size_t cell = ((size_t)ic[2][dz] * g.ny + ic[1][dy]) * g.nx + ic[0][dx];
-      atomicAdd(&rho[cell], (unsigned long long)q);
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Field bounds per cell: largest |E| over the 4x4x4 centres (i-1..i+2 per
 // axis, clamped) and the norm of the per-component ranges there; plus the
 // global maximum of |E| (as ordered bits of a non-negative float).
@@ -486,13 +438,6 @@ hipError_t occupancy_pic_steps(int block, size_t lds, int* blocks_per_cu) {
 
 hipError_t launch_finalize(const Soa& user, const Soa& scratch, Ctl* ctl, int64_t* n_dev, hipStream_t stream) {
   hipLaunchKernelGGL(k_finalize, dim3(2048), dim3(256), 0, stream, user, scratch, ctl, n_dev);
-  return hipGetLastError();
-}
-
-hipError_t launch_deposit(const float* x, const float* y, const float* z, const float* w, const int64_t* n_dev,
-                          const DepositGeom& g, int64_t* rho, hipStream_t stream) {
-  hipLaunchKernelGGL(k_deposit, dim3(4096), dim3(256), 0, stream, x, y, z, w, n_dev, g,
-                     (unsigned long long*)rho);
   return hipGetLastError();
 }
 
