@@ -12,23 +12,26 @@
 // completes that segment (second half of the Verlet update, then the
 // collision if the segment ended in one), plans the next segment (majorant,
 // free-flight time) and moves the position to its end.  An electron that
-// reaches the end of the step, is attached or hits the segment limit leaves
-// its lane, and idle lanes take new electrons from a grid-wide work counter.
-// Lanes therefore stay busy regardless of how many segments each electron
-// needs within the step, and the gather, the only global-memory read of a
-// segment, is one instruction stream for the whole wave.
+// reaches the end of the step, is attached or hits the segment limit parks
+// in its lane; once kRefillMin lanes are free, the parked electrons are
+// written out and the free lanes take new electrons from a grid-wide work
+// counter, all in one batch.  Lanes therefore stay busy regardless of how
+// many segments each electron needs within the step, the gather (the only
+// global-memory read of a segment) is one instruction stream for the whole
+// wave, and the rare per-electron work (start, finish, building a newborn)
+// runs in batches instead of with one or two lanes active.
 #pragma once
 
 #include "pcmcc_mover.hpp"
 
 namespace pcmcc {
 
-enum FlightMode : int { FM_IDLE = 0, FM_NEW = 1, FM_FLY = 2 };
+enum FlightMode : int { FM_IDLE = 0, FM_NEW = 1, FM_FLY = 2, FM_DONE = 3 };
 enum Segment : int { SEG_END = 0, SEG_HORIZON = 1, SEG_COLLIDE = 2 };
 enum FlightEvent : int { EV_GO = 0, EV_DONE = 1, EV_ATTACHED = 2, EV_LIMIT = 3 };
 
 constexpr uint32_t kChunk = 256;  // electrons taken from the work counter at a time
-constexpr int kRefillMin = 8;     // idle lanes that trigger a refill
+constexpr int kRefillMin = 8;     // free lanes that trigger a finish-and-refill batch
 
 // Per-wave staging lists in LDS.  Newborns, holes and placed newborns are
 // collected per wave and written out kFlushAt or more at a time, each batch
@@ -41,8 +44,12 @@ constexpr uint32_t kStage = 64;
 constexpr uint32_t kFlushAt = 32;
 
 struct WaveStage {
-  float b[8][kStage];  // newborns: x, y, z, vx, vy, vz, w, birth time
-  uint64_t bid[kStage];
+  // newborns as their parent left them: x, y, z, w, birth time; parent id,
+  // segment number and the newborn's energy (the rest is drawn at flush)
+  float b[5][kStage];
+  uint32_t bj[kStage];
+  uint64_t bpid[kStage];
+  double beps[kStage];
   float s[7][kStage];  // phase 2: placed newborns x .. w (phase 1: s[0] holds hole slots)
   uint64_t sid[kStage];
 };
@@ -53,32 +60,56 @@ __host__ __device__ inline size_t pic_stage_offset_floats(const TableView& T) {
   return (table_lds_floats(T) + 3) & ~(size_t)3;
 }
 
+// Id and velocity of the newborn of an ionization: the birth draw of the
+// parent's segment gives the id (first two words) and an isotropic
+// direction, the speed follows from the newborn's energy.
+__device__ __forceinline__ void make_child(Key key, uint32_t step, const SpeciesView& S, uint64_t pid, uint32_t j,
+                                           double eps_new, PState& c) {
+  const uint4 b = draw(key, pid, step, j, TAG_BIRTH);
+  c.id = (uint64_t)b.x | ((uint64_t)b.y << 32);
+  double cx, cy, cz;
+  iso_dir(b.z, b.w, cx, cy, cz);
+  const double cs = sqrt(eps_new * S.inv_k_d);
+  c.vx = (float)(cs * cx);
+  c.vy = (float)(cs * cy);
+  c.vz = (float)(cs * cz);
+}
+
 // Newborn queue of a phase seen through the wave's staging list.
 struct StagedBirths {
   WaveStage* L;
   BirthSink q;  // global queue: flushes and direct pushes
-  uint32_t n;   // staged entries (wave-uniform)
+  Key key;
+  uint32_t step;
+  SpeciesView S;
+  uint32_t n;  // staged entries (wave-uniform)
 
   // Called by the lanes that create a newborn; returns true if it was staged.
-  __device__ __forceinline__ bool push(const PState& c, float tb) const {
+  __device__ __forceinline__ bool push(float x, float y, float z, float w, float tb, uint64_t pid, uint32_t j,
+                                       double eps_new) const {
     const uint32_t s = n + rank_in(__ballot(1));
     if (s < kStage) {
-      L->b[0][s] = c.x;
-      L->b[1][s] = c.y;
-      L->b[2][s] = c.z;
-      L->b[3][s] = c.vx;
-      L->b[4][s] = c.vy;
-      L->b[5][s] = c.vz;
-      L->b[6][s] = c.w;
-      L->b[7][s] = tb;
-      L->bid[s] = c.id;
+      L->b[0][s] = x;
+      L->b[1][s] = y;
+      L->b[2][s] = z;
+      L->b[3][s] = w;
+      L->b[4][s] = tb;
+      L->bj[s] = j;
+      L->bpid[s] = pid;
+      L->beps[s] = eps_new;
       return true;
     }
+    PState c;
+    c.x = x;
+    c.y = y;
+    c.z = z;
+    c.w = w;
+    make_child(key, step, S, pid, j, eps_new, c);
     q.push(c, tb);
     return false;
   }
 
-  // Whole wave: writes the staged entries to the queue.
+  // Whole wave: builds the staged newborns and writes them to the queue.
   __device__ __forceinline__ void flush() {
     if (n == 0) return;
     unsigned long long base = 0;
@@ -89,15 +120,17 @@ struct StagedBirths {
     if (l < n) {
       const uint64_t slot = b + l;
       if (slot < q.cap) {
+        PState c;
+        make_child(key, step, S, L->bpid[l], L->bj[l], L->beps[l], c);
         q.q.x[slot] = L->b[0][l];
         q.q.y[slot] = L->b[1][l];
         q.q.z[slot] = L->b[2][l];
-        q.q.vx[slot] = L->b[3][l];
-        q.q.vy[slot] = L->b[4][l];
-        q.q.vz[slot] = L->b[5][l];
-        q.q.w[slot] = L->b[6][l];
-        q.q.tb[slot] = L->b[7][l];
-        q.q.id[slot] = L->bid[l];
+        q.q.vx[slot] = c.vx;
+        q.q.vy[slot] = c.vy;
+        q.q.vz[slot] = c.vz;
+        q.q.w[slot] = L->b[3][l];
+        q.q.tb[slot] = L->b[4][l];
+        q.q.id[slot] = c.id;
       } else {
         atomicOr(q.overflow, OVF_CAPACITY);
       }
@@ -115,7 +148,8 @@ struct Flight {
   uint32_t j;           // number of the next segment (random-number counter)
   uint32_t src;         // slot the electron came from
   uint32_t r1, r2, r3;  // uniforms of the pending collision
-  int mode, seg;
+  int mode;
+  int seg;  // kind of the pending segment; for a parked electron, its event
 };
 
 __device__ __forceinline__ PState flight_record(const Flight& f) {
@@ -197,8 +231,7 @@ __device__ __forceinline__ int flight_plan(Flight& f, double dt, const Tab& T, c
 // Completes the pending segment with the acceleration `an` gathered at its
 // end point, then applies its collision, if any.
 __device__ __forceinline__ int flight_complete(Flight& f, const double3 an, const Tab& T, const SpeciesView& S,
-                                               Key key, uint32_t step, Cnt& cnt, const StagedBirths& births,
-                                               bool& staged) {
+                                               Cnt& cnt, const StagedBirths& births, bool& staged) {
   const double hh = 0.5 * f.h;
   f.vx = fma(f.ax + an.x, hh, f.vx);
   f.vy = fma(f.ay + an.y, hh, f.vy);
@@ -251,20 +284,7 @@ __device__ __forceinline__ int flight_complete(Flight& f, const double3 an, cons
     eps_new = eps - thr;
   } else {
     eps_new = 0.5 * (eps - thr);
-    const uint4 b = draw(key, f.id, step, f.j - 1, TAG_BIRTH);
-    PState c;
-    c.x = (float)f.x;
-    c.y = (float)f.y;
-    c.z = (float)f.z;
-    c.w = f.w;
-    c.id = (uint64_t)b.x | ((uint64_t)b.y << 32);
-    double cx, cy, cz;
-    iso_dir(b.z, b.w, cx, cy, cz);
-    const double cs = sqrt(eps_new * S.inv_k_d);
-    c.vx = (float)(cs * cx);
-    c.vy = (float)(cs * cy);
-    c.vz = (float)(cs * cz);
-    staged = births.push(c, (float)f.t);
+    staged = births.push((float)f.x, (float)f.y, (float)f.z, f.w, (float)f.t, f.id, f.j - 1, eps_new);
   }
   const double sn = sqrt(eps_new * S.inv_k_d);
   f.vx = sn * nx;
@@ -276,7 +296,7 @@ __device__ __forceinline__ int flight_complete(Flight& f, const double3 an, cons
 // Runs every electron of a source (n of them) through the rest of the step.
 // Source: load(i, Flight&) starts electron i.  Finish: done(Flight&, event,
 // Cnt&, WaveStage*, staged count, bool& staged) takes an electron that left
-// its lane, flush(WaveStage*, count) writes out the wave's staged results.
+// the step, flush(WaveStage*, count) writes out the wave's staged results.
 // Must be called by whole waves with wave-uniform arguments; `take` is the
 // grid-wide work counter (zero before the first wave starts).  Every staged
 // entry is written out before the function returns.
@@ -287,68 +307,87 @@ __device__ __forceinline__ void fly_all(uint64_t n, unsigned long long* take, do
                                         const Finish& finish) {
   Flight f;
   f.mode = FM_IDLE;
-  StagedBirths births{L, sink, 0u};
+  StagedBirths births{L, sink, key, step, S, 0u};
   uint32_t n_done = 0;  // entries of the finish list
   uint64_t pool_next = 0, pool_end = 0;
   bool dry = n == 0;
   const uint32_t lane = lane_id();
   for (;;) {
-    const uint64_t idle = __ballot(f.mode == FM_IDLE);
-    const uint32_t n_idle = (uint32_t)__popcll(idle);
-    if (!dry && (n_idle >= (uint32_t)kRefillMin || n_idle == 64u)) {
-      const uint32_t rank = rank_in(idle);
-      uint32_t served = 0;
-      while (served < n_idle) {
-        if (pool_next == pool_end) {
-          unsigned long long base = 0;
-          if (lane == 0) base = atomicAdd(take, (unsigned long long)kChunk);
-          const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
-          const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
-          const uint64_t b = ((uint64_t)hi << 32) | lo;
-          if (b >= n) {
-            dry = true;
-            break;
-          }
-          pool_next = b;
-          pool_end = b + kChunk < n ? b + kChunk : n;
+    const uint64_t busy = __ballot(f.mode == FM_FLY);
+    if (64u - (uint32_t)__popcll(busy) >= (uint32_t)kRefillMin || busy == 0) {
+      // Finish the parked electrons (room for all of them in the list).
+      const uint32_t n_fin = (uint32_t)__popcll(__ballot(f.mode == FM_DONE));
+      if (n_fin > 0) {
+        if (n_done + n_fin > kStage) {
+          finish.flush(L, n_done);
+          n_done = 0;
         }
-        const uint32_t avail = (uint32_t)(pool_end - pool_next);
-        const uint32_t got = avail < n_idle - served ? avail : n_idle - served;
-        if (f.mode == FM_IDLE && rank >= served && rank < served + got) source.load(pool_next + (rank - served), f);
-        pool_next += got;
-        served += got;
+        bool placed = false;
+        if (f.mode == FM_DONE) {
+          finish.done(f, f.seg, cnt, L, n_done, placed);
+          f.mode = FM_IDLE;
+        }
+        n_done += (uint32_t)__popcll(__ballot(placed));
+        if (n_done >= kFlushAt) {
+          finish.flush(L, n_done);
+          n_done = 0;
+        }
+      }
+      // Start new electrons in the free lanes.
+      if (!dry) {
+        const uint64_t idle = __ballot(f.mode == FM_IDLE);
+        const uint32_t n_idle = (uint32_t)__popcll(idle);
+        const uint32_t rank = rank_in(idle);
+        uint32_t served = 0;
+        while (served < n_idle) {
+          if (pool_next == pool_end) {
+            unsigned long long base = 0;
+            if (lane == 0) base = atomicAdd(take, (unsigned long long)kChunk);
+            const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
+            const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
+            const uint64_t b = ((uint64_t)hi << 32) | lo;
+            if (b >= n) {
+              dry = true;
+              break;
+            }
+            pool_next = b;
+            pool_end = b + kChunk < n ? b + kChunk : n;
+          }
+          const uint32_t avail = (uint32_t)(pool_end - pool_next);
+          const uint32_t got = avail < n_idle - served ? avail : n_idle - served;
+          if (f.mode == FM_IDLE && rank >= served && rank < served + got)
+            source.load(pool_next + (rank - served), f);
+          pool_next += got;
+          served += got;
+        }
+        if (f.mode == FM_NEW)
+          F.bound(f.x, f.y, f.z, sqrtf((float)(f.vx * f.vx + f.vy * f.vy + f.vz * f.vz)), (float)(dt - f.t),
+                  f.a_abs, f.da);
       }
     }
     if (__ballot(f.mode != FM_IDLE) == 0) break;
-    bool born = false, placed = false;
-    if (f.mode != FM_IDLE) {
+    bool born = false;
+    if (f.mode == FM_FLY || f.mode == FM_NEW) {
       const double3 an = F.accel(f.x, f.y, f.z);
       int ev;
       if (f.mode == FM_NEW) {
         f.ax = an.x;
         f.ay = an.y;
         f.az = an.z;
-        F.bound(f.x, f.y, f.z, sqrtf((float)(f.vx * f.vx + f.vy * f.vy + f.vz * f.vz)), (float)(dt - f.t), f.a_abs,
-                f.da);
         f.mode = FM_FLY;
         ev = EV_GO;
       } else {
-        ev = flight_complete(f, an, T, S, key, step, cnt, births, born);
+        ev = flight_complete(f, an, T, S, cnt, births, born);
       }
       if (ev == EV_GO) ev = flight_plan(f, dt, T, S, key, step, cnt);
       if (ev != EV_GO) {
-        finish.done(f, ev, cnt, L, n_done, placed);
-        f.mode = FM_IDLE;
+        f.mode = FM_DONE;
+        f.seg = ev;
       }
     }
-    // Whole wave again: count what was staged, write out full lists.
+    // Whole wave again: count the staged newborns, write out a full list.
     births.n += (uint32_t)__popcll(__ballot(born));
-    n_done += (uint32_t)__popcll(__ballot(placed));
     if (births.n >= kFlushAt) births.flush();
-    if (n_done >= kFlushAt) {
-      finish.flush(L, n_done);
-      n_done = 0;
-    }
   }
   births.flush();
   if (n_done > 0) finish.flush(L, n_done);
