@@ -65,9 +65,14 @@ struct TableView {
   int kind[kMaxProc];
 };
 
-// Floats of LDS the staged tables take: C and P, thresholds and kinds.
+// Processes per node of the staged cumulative table (padded with zero
+// entries, which no draw selects): 4 or 8.
+__host__ __device__ inline int table_row(int nproc) { return nproc <= 4 ? 4 : 8; }
+
+// Floats of LDS the staged tables take: C (node-major rows) and P,
+// thresholds and kinds.
 __host__ __device__ inline size_t table_lds_floats(const TableView& T) {
-  return (size_t)(T.nproc + 1) * T.n + 2 * kMaxProc;
+  return (size_t)(table_row(T.nproc) + 1) * T.n + 2 * kMaxProc;
 }
 
 // Physical constants of the species and gas, single precision.
@@ -107,7 +112,7 @@ __device__ __forceinline__ float majorant(const TableView& T, const SpeciesView&
 // |a| <= a_abs and |a - a0| <= da along the way.
 __device__ __forceinline__ float speed_bound(float3 v, float3 a0, float speed, float a_abs, float da, float h) {
   const float wx = fmaf(a0.x, h, v.x), wy = fmaf(a0.y, h, v.y), wz = fmaf(a0.z, h, v.z);
-  const float s_dir = fmaf(da, h, fmaxf(speed, sqrtf(wx * wx + wy * wy + wz * wz)));
+  const float s_dir = fmaf(da, h, fmaxf(speed, __builtin_amdgcn_sqrtf(wx * wx + wy * wy + wz * wz)));
   return fminf(fmaf(a_abs, h, speed), s_dir);
 }
 

@@ -198,16 +198,19 @@ __device__ __forceinline__ int flight_plan(Flight& f, double dt, const Tab& T, c
   const double t_rem = dt - f.t;
   const float3 vf = make_float3((float)f.vx, (float)f.vy, (float)f.vz);
   const float3 af = make_float3((float)f.ax, (float)f.ay, (float)f.az);
-  const float speed = sqrtf(vf.x * vf.x + vf.y * vf.y + vf.z * vf.z);
+  // Single-precision square roots and reciprocals to about one ulp: the
+  // majorant's 2^-16 guard covers them, and the free-flight time only needs
+  // single precision.
+  const float speed = __builtin_amdgcn_sqrtf(vf.x * vf.x + vf.y * vf.y + vf.z * vf.z);
   const float nu_full = majorant_t(T, S, speed_bound(vf, af, speed, f.a_abs, f.da, (float)t_rem));
   const bool limited = kKappa < nu_full * (float)t_rem;
   // Both majorants are evaluated and one is selected, which keeps the lanes
   // of a wave on one path (nu_full = 0 gives an unused, finite lookup).
-  const float h_lim = kKappa / nu_full;
+  const float h_lim = kKappa * __builtin_amdgcn_rcpf(nu_full);
   const float nu_lim = majorant_t(T, S, speed_bound(vf, af, speed, f.a_abs, f.da, h_lim));
   const double h = limited ? (double)h_lim : t_rem;
   const float nu_hat = limited ? nu_lim : nu_full;
-  const double tau = nu_hat > 0.0f ? (double)(-__logf(unif(r.x)) / nu_hat) : (double)INFINITY;
+  const double tau = nu_hat > 0.0f ? (double)(-__logf(unif(r.x)) * __builtin_amdgcn_rcpf(nu_hat)) : (double)INFINITY;
   double hs;
   if (tau >= h) {
     hs = h;
@@ -251,15 +254,9 @@ __device__ __forceinline__ int flight_complete(Flight& f, const double3 an, cons
   const int i = (int)fl;
   const float fr = u - fl;
   const float yv = unif(f.r1) * f.nu_hat;
-  // All cumulative rates are read at once (independent LDS loads), then the
-  // first process whose cumulative rate exceeds yv is taken.
   float cum[kMaxProc];
-#pragma unroll
-  for (int kk = 0; kk < kMaxProc; ++kk) cum[kk] = kk < T.nproc ? lerp_at(T.C + kk * T.n, i, fr) : INFINITY;
-  int k = -1;
-#pragma unroll
-  for (int kk = kMaxProc - 1; kk >= 0; --kk)
-    if (kk < T.nproc && yv < cum[kk]) k = kk;
+  cum_rates(T, i, fr, cum);
+  const int k = pick_process(cum, yv);
   if (k < 0 || eps < (double)T.thr[k]) {
     cnt.v[C_NULL]++;
     return EV_GO;

@@ -412,7 +412,9 @@ __global__ void k_lookup(TableView TV, SpeciesView S, const float* __restrict__ 
     const float fl = fminf(floorf(u), (float)(T.n - 2));
     const int i = (int)fl;
     const float f = u - fl;
-    for (int k = 0; k < T.nproc; ++k) cum[q * T.nproc + k] = lerp_at(T.C + k * T.n, i, f);
+    float c[kMaxProc];
+    cum_rates(T, i, f, c);
+    for (int k = 0; k < T.nproc; ++k) cum[q * T.nproc + k] = c[k];
     if (maj) maj[q] = majorant_t(T, S, s_ub[q]);
   }
 }

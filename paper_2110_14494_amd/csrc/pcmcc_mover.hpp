@@ -114,15 +114,46 @@ struct GridField {
   }
 };
 
-// Tables as the kernels read them (staged in LDS).
+// Tables as the kernels read them (staged in LDS).  C is node-major: row i
+// holds the cumulative rates of all processes at node i, padded with zeros
+// to `row` entries, so one node is one or two 16-byte reads.
 struct Tab {
   const float* C;
   const float* P;
   const float* thr;
   const int* kind;
-  int n, nproc;
+  int n, nproc, row;
   float u_scale, u_offset, eps_max;
 };
+
+// Cumulative rates at table position (i, f), linear between nodes i and
+// i + 1 (entries at and beyond nproc are zero).
+__device__ __forceinline__ void cum_rates(const Tab& T, int i, float f, float c[kMaxProc]) {
+  const float4* a = reinterpret_cast<const float4*>(T.C + (size_t)i * T.row);
+  const float4* b = reinterpret_cast<const float4*>(T.C + (size_t)(i + 1) * T.row);
+  auto put = [&](int o, float4 lo, float4 hi) {
+    c[o] = fmaf(f, hi.x - lo.x, lo.x);
+    c[o + 1] = fmaf(f, hi.y - lo.y, lo.y);
+    c[o + 2] = fmaf(f, hi.z - lo.z, lo.z);
+    c[o + 3] = fmaf(f, hi.w - lo.w, lo.w);
+  };
+  put(0, a[0], b[0]);
+  if (T.row == 8) {
+    put(4, a[1], b[1]);
+  } else {
+#pragma unroll
+    for (int k = 4; k < kMaxProc; ++k) c[k] = 0.0f;
+  }
+}
+
+// First process whose cumulative rate exceeds y, or -1 (a null collision).
+__device__ __forceinline__ int pick_process(const float c[kMaxProc], float y) {
+  int k = -1;
+#pragma unroll
+  for (int kk = kMaxProc - 1; kk >= 0; --kk)
+    if (y < c[kk]) k = kk;
+  return k;
+}
 
 __device__ __forceinline__ float majorant_t(const Tab& T, const SpeciesView& S, float s_ub) {
   const float s = s_ub * kGuard;
@@ -212,12 +243,9 @@ __device__ int advance(PState& p, double t, double dt, const Field& F, const Tab
     const int i = (int)fl;
     const float f = u - fl;
     const float yv = unif(r.y) * nu_hat;
-    int k = -1;
-    for (int kk = 0; kk < T.nproc; ++kk)
-      if (yv < lerp_at(T.C + kk * T.n, i, f)) {
-        k = kk;
-        break;
-      }
+    float cum[kMaxProc];
+    cum_rates(T, i, f, cum);
+    const int k = pick_process(cum, yv);
     if (k < 0 || eps < (double)T.thr[k]) {
       cnt.v[C_NULL]++;
       continue;
@@ -286,8 +314,12 @@ __device__ __forceinline__ bool inside(const GridView& G, const PState& p) {
 
 // Stages the tables in LDS; returns the view the kernels read.
 __device__ inline Tab stage_tables(const TableView& TV, float* smem) {
-  const int nC = TV.nproc * TV.n;
-  for (int i = threadIdx.x; i < nC; i += blockDim.x) smem[i] = TV.C[i];
+  const int row = table_row(TV.nproc);
+  const int nC = row * TV.n;
+  for (int e = threadIdx.x; e < nC; e += blockDim.x) {
+    const int i = e / row, k = e % row;
+    smem[e] = k < TV.nproc ? TV.C[(size_t)k * TV.n + i] : 0.0f;
+  }
   for (int i = threadIdx.x; i < TV.n; i += blockDim.x) smem[nC + i] = TV.P[i];
   float* thr = smem + nC + TV.n;
   int* kind = (int*)(thr + kMaxProc);
@@ -303,6 +335,7 @@ __device__ inline Tab stage_tables(const TableView& TV, float* smem) {
   T.kind = kind;
   T.n = TV.n;
   T.nproc = TV.nproc;
+  T.row = row;
   T.u_scale = TV.u_scale;
   T.u_offset = TV.u_offset;
   T.eps_max = TV.eps_top;
