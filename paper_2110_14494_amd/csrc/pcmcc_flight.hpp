@@ -69,7 +69,7 @@ __device__ __forceinline__ void make_child(Key key, uint32_t step, const Species
   c.id = (uint64_t)b.x | ((uint64_t)b.y << 32);
   double cx, cy, cz;
   iso_dir(b.z, b.w, cx, cy, cz);
-  const double cs = sqrt(eps_new * S.inv_k_d);
+  const double cs = sqrt_nr(eps_new * S.inv_k_d);
   c.vx = (float)(cs * cx);
   c.vy = (float)(cs * cy);
   c.vz = (float)(cs * cz);
@@ -274,8 +274,7 @@ __device__ __forceinline__ int flight_complete(Flight& f, const double3 an, cons
   const double thr = (double)T.thr[k];
   double eps_new;
   if (kind == ELASTIC) {
-    const double sc = sqrt(v2);
-    const double cchi = sc > 0.0 ? (f.vx * nx + f.vy * ny + f.vz * nz) / sc : 0.0;
+    const double cchi = v2 > 0.0 ? (f.vx * nx + f.vy * ny + f.vz * nz) * rsqrt_nr(v2) : 0.0;
     eps_new = eps * (1.0 - (double)S.recoil * (1.0 - cchi));
   } else if (kind == EXCITATION) {
     eps_new = eps - thr;
@@ -283,7 +282,7 @@ __device__ __forceinline__ int flight_complete(Flight& f, const double3 an, cons
     eps_new = 0.5 * (eps - thr);
     staged = births.push((float)f.x, (float)f.y, (float)f.z, f.w, (float)f.t, f.id, f.j - 1, eps_new);
   }
-  const double sn = sqrt(eps_new * S.inv_k_d);
+  const double sn = sqrt_nr(eps_new * S.inv_k_d);
   f.vx = sn * nx;
   f.vy = sn * ny;
   f.vz = sn * nz;

@@ -165,17 +165,35 @@ __device__ __forceinline__ float majorant_t(const Tab& T, const SpeciesView& S, 
   return lerp_at(T.P, i, u - fl);
 }
 
+// Square root of x >= 0 (0 for x <= 0) from the hardware reciprocal square
+// root refined by two Newton steps (relative error near double rounding).
+__device__ __forceinline__ double sqrt_nr(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  r = r * fma(-0.5 * x * r, r, 1.5);
+  r = r * fma(-0.5 * x * r, r, 1.5);
+  return x > 0.0 ? x * r : 0.0;
+}
+
+// 1/sqrt(x) for x > 0, as above.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  r = r * fma(-0.5 * x * r, r, 1.5);
+  return r * fma(-0.5 * x * r, r, 1.5);
+}
+
 // Isotropic unit vector from two uniforms: cos(theta) = 1 - 2 U1 and
 // sin(theta) = 2 sqrt(U1 (1 - U1)) (no cancellation near the poles; U1 and
-// 1 - U1 are exact), azimuth 2 pi U2 from a single-precision sincospi whose
-// (cos, sin) pair is renormalised so that |n| = 1 in double precision.
+// 1 - U1 are exact), azimuth 2 pi U2 from a single-precision sincospi.  The
+// (cos, sin) pair has s2 = cos^2 + sin^2 within a few single-precision ulp
+// of 1, so 1/sqrt(s2) = 3/2 - s2/2 to about 1e-13: |n| = 1 to that accuracy.
 __device__ __forceinline__ void iso_dir(uint32_t r1, uint32_t r2, double& nx, double& ny, double& nz) {
   const double u = (double)unif(r1);
   const double cth = 1.0 - 2.0 * u;
   const double sth = 2.0 * sqrt(u * (1.0 - u));
   float sp, cp;
   sincospif(2.0f * unif(r2), &sp, &cp);
-  const double inv = sth / sqrt((double)cp * cp + (double)sp * sp);
+  const double s2 = (double)cp * cp + (double)sp * sp;
+  const double inv = sth * fma(-0.5, s2, 1.5);
   nx = inv * cp;
   ny = inv * sp;
   nz = cth;
