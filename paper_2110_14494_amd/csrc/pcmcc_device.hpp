@@ -158,13 +158,16 @@ __device__ __forceinline__ const float4* grid_record(const GridView& G, int i, i
 // Trilinear interpolation with clamped indices (constant outside the
 // outermost centres), returned as acceleration (q/m) E with q/m applied in
 // double precision.
-__device__ __forceinline__ double3 gather(const GridView& G, double qm, double x, double y, double z) {
+// `rec_out` receives the record read (its bound words serve accel_bound_at).
+__device__ __forceinline__ double3 gather(const GridView& G, double qm, double x, double y, double z,
+                                          const float4** rec_out = nullptr) {
   int i, j, k;
   float gx, gy, gz;
   cell_coord(x, G.o[0], G.inv_dx, G.nx, i, gx);
   cell_coord(y, G.o[1], G.inv_dx, G.ny, j, gy);
   cell_coord(z, G.o[2], G.inv_dx, G.nz, k, gz);
   const float4* rec = grid_record(G, i, j, k);
+  if (rec_out) *rec_out = rec;
   const float4 q0 = rec[0], q1 = rec[1], q2 = rec[2], q3 = rec[3], q4 = rec[4], q5 = rec[5];
   // corners (dz, dy, dx): 000 = q0.xyz, 001 = q0.w q1.xy, 010 = q1.zw q2.x,
   // 011 = q2.yzw, 100 = q3.xyz, 101 = q3.w q4.xy, 110 = q4.zw q5.x, 111 = q5.yzw
@@ -181,6 +184,20 @@ __device__ __forceinline__ double3 gather(const GridView& G, double qm, double x
   const float3 e0 = l3(gy, e00, e01), e1 = l3(gy, e10, e11);
   const float3 e = l3(gz, e0, e1);
   return make_double3(qm * e.x, qm * e.y, qm * e.z);
+}
+
+// As accel_bound, with the record of the particle's position already known.
+__device__ __forceinline__ void accel_bound_at(const GridView& G, const float4* rec, float speed, float t_rem,
+                                               float& a_abs, float& da) {
+  const float D = fmaf(0.5f * G.a_glob * t_rem, t_rem, speed * t_rem);
+  if (!(D < G.dx * (1.0f - 0x1p-10f))) {
+    a_abs = G.a_glob;
+    da = 2.0f * G.a_glob;
+    return;
+  }
+  const float4 m = rec[6];
+  a_abs = G.qm_abs * m.x;
+  da = G.qm_abs * m.y;
 }
 
 // Acceleration bounds for the rest of a step of length t_rem: local ones if

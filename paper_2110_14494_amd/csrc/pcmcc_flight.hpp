@@ -31,7 +31,7 @@ enum Segment : int { SEG_END = 0, SEG_HORIZON = 1, SEG_COLLIDE = 2 };
 enum FlightEvent : int { EV_GO = 0, EV_DONE = 1, EV_ATTACHED = 2, EV_LIMIT = 3 };
 
 constexpr uint32_t kChunk = 256;  // electrons taken from the work counter at a time
-constexpr int kRefillMin = 8;     // free lanes that trigger a finish-and-refill batch
+constexpr int kRefillMin = 24;    // free lanes that trigger a finish-and-refill batch (tuned)
 
 // Per-wave staging lists in LDS.  Newborns, holes and placed newborns are
 // collected per wave and written out kFlushAt or more at a time, each batch
@@ -356,20 +356,22 @@ __device__ __forceinline__ void fly_all(uint64_t n, unsigned long long* take, do
           pool_next += got;
           served += got;
         }
-        if (f.mode == FM_NEW)
-          F.bound(f.x, f.y, f.z, sqrtf((float)(f.vx * f.vx + f.vy * f.vy + f.vz * f.vz)), (float)(dt - f.t),
-                  f.a_abs, f.da);
       }
     }
     if (__ballot(f.mode != FM_IDLE) == 0) break;
     bool born = false;
     if (f.mode == FM_FLY || f.mode == FM_NEW) {
-      const double3 an = F.accel(f.x, f.y, f.z);
+      typename Field::Where where;
+      const double3 an = F.accel(f.x, f.y, f.z, where);
       int ev;
       if (f.mode == FM_NEW) {
+        // start of the electron's flight: acceleration and field bound for
+        // the rest of the step (the bound from the record just gathered)
         f.ax = an.x;
         f.ay = an.y;
         f.az = an.z;
+        F.bound_at(where, sqrtf((float)(f.vx * f.vx + f.vy * f.vy + f.vz * f.vz)), (float)(dt - f.t), f.a_abs,
+                   f.da);
         f.mode = FM_FLY;
         ev = EV_GO;
       } else {

@@ -112,6 +112,14 @@ struct GridField {
                                         float& da) const {
     accel_bound(G, x, y, z, speed, t_rem, a_abs, da);
   }
+  // Gather that also returns its record, and the bound from that record.
+  using Where = const float4*;
+  __device__ __forceinline__ double3 accel(double x, double y, double z, Where& w) const {
+    return gather(G, qm, x, y, z, &w);
+  }
+  __device__ __forceinline__ void bound_at(Where w, float speed, float t_rem, float& a_abs, float& da) const {
+    accel_bound_at(G, w, speed, t_rem, a_abs, da);
+  }
 };
 
 // Tables as the kernels read them (staged in LDS).  C is node-major: row i
