@@ -44,15 +44,55 @@ constexpr uint32_t kStage = 64;
 constexpr uint32_t kFlushAt = 32;
 
 struct WaveStage {
-  // newborns as their parent left them: x, y, z, w, birth time; parent id,
-  // segment number and the newborn's energy (the rest is drawn at flush)
+  // newborns as their parent left them: x, y, z, w, birth time; segment
+  // number, group, parent id and the newborn's energy (the rest is drawn at
+  // flush)
   float b[5][kStage];
   uint32_t bj[kStage];
+  uint32_t btag[kStage];
   uint64_t bpid[kStage];
   double beps[kStage];
-  float s[7][kStage];  // phase 2: placed newborns x .. w (phase 1: s[0] holds hole slots)
+  // finished electrons: x .. w, group, id (phase 1 of the PIC step: s[0]
+  // holds hole slots)
+  float s[7][kStage];
+  uint32_t stag[kStage];
   uint64_t sid[kStage];
 };
+
+// Whole wave: for the lanes with `active` set, reserves one slot each in the
+// counter ctr[tag] of the lane's group, with one atomic per distinct group
+// present; returns the lane's slot (undefined for inactive lanes).
+__device__ __forceinline__ uint64_t group_reserve(unsigned long long* ctr, uint32_t tag, bool active) {
+  uint64_t pending = __ballot(active);
+  uint64_t slot = 0;
+  const uint32_t lane = lane_id();
+  while (pending) {
+    const int leader = __ffsll((unsigned long long)pending) - 1;
+    const uint32_t t = __builtin_amdgcn_readlane(tag, leader);
+    const uint64_t m = __ballot(active && tag == t) & pending;
+    unsigned long long base = 0;
+    if ((int)lane == leader) base = atomicAdd(&ctr[t], (unsigned long long)__popcll(m));
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)base, leader);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(base >> 32), leader);
+    if ((m >> lane) & 1) slot = (((uint64_t)hi << 32) | lo) + rank_in(m);
+    pending &= ~m;
+  }
+  return slot;
+}
+
+// Whole wave: adds, per distinct group among the lanes with `active` set, the
+// number of such lanes to ctr[tag] (one atomic per group).
+__device__ __forceinline__ void group_count(unsigned long long* ctr, uint32_t tag, bool active) {
+  uint64_t pending = __ballot(active);
+  const uint32_t lane = lane_id();
+  while (pending) {
+    const int leader = __ffsll((unsigned long long)pending) - 1;
+    const uint32_t t = __builtin_amdgcn_readlane(tag, leader);
+    const uint64_t m = __ballot(active && tag == t) & pending;
+    if ((int)lane == leader) atomicAdd(&ctr[t], (unsigned long long)__popcll(m));
+    pending &= ~m;
+  }
+}
 
 // Offset (in floats) of the staging lists after the staged tables in the
 // step kernel's LDS, 16-byte aligned.
@@ -75,18 +115,23 @@ __device__ __forceinline__ void make_child(Key key, uint32_t step, const Species
   c.vz = (float)(cs * cz);
 }
 
-// Newborn queue of a phase seen through the wave's staging list.
+// Newborn queue of a phase seen through the wave's staging list.  Field
+// supplies the random-number key of an electron's group; the queue records
+// the group of each newborn when it has a group array, and cum_ion (if not
+// null) counts ionizations per group.
+template <class Field>
 struct StagedBirths {
   WaveStage* L;
   BirthSink q;  // global queue: flushes and direct pushes
-  Key key;
+  const Field& F;
   uint32_t step;
   SpeciesView S;
+  unsigned long long* cum_ion;
   uint32_t n;  // staged entries (wave-uniform)
 
   // Called by the lanes that create a newborn; returns true if it was staged.
-  __device__ __forceinline__ bool push(float x, float y, float z, float w, float tb, uint64_t pid, uint32_t j,
-                                       double eps_new) const {
+  __device__ __forceinline__ bool push(float x, float y, float z, float w, float tb, uint32_t tag, uint64_t pid,
+                                       uint32_t j, double eps_new) const {
     const uint32_t s = n + rank_in(__ballot(1));
     if (s < kStage) {
       L->b[0][s] = x;
@@ -95,6 +140,7 @@ struct StagedBirths {
       L->b[3][s] = w;
       L->b[4][s] = tb;
       L->bj[s] = j;
+      L->btag[s] = tag;
       L->bpid[s] = pid;
       L->beps[s] = eps_new;
       return true;
@@ -104,8 +150,11 @@ struct StagedBirths {
     c.y = y;
     c.z = z;
     c.w = w;
-    make_child(key, step, S, pid, j, eps_new, c);
-    q.push(c, tb);
+    make_child(F.key(tag), step, S, pid, j, eps_new, c);
+    BirthSink qt = q;
+    qt.tag = tag;
+    qt.push(c, tb);
+    if (cum_ion) atomicAdd(&cum_ion[tag], 1ull);
     return false;
   }
 
@@ -117,11 +166,14 @@ struct StagedBirths {
     const uint64_t b = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(base >> 32)) << 32) |
                        __builtin_amdgcn_readfirstlane((uint32_t)base);
     const uint32_t l = lane_id();
-    if (l < n) {
+    const bool mine = l < n;
+    const uint32_t tag = mine ? L->btag[l] : 0u;
+    if (mine) {
       const uint64_t slot = b + l;
       if (slot < q.cap) {
         PState c;
-        make_child(key, step, S, L->bpid[l], L->bj[l], L->beps[l], c);
+        make_child(F.key(tag), step, S, L->bpid[l], L->bj[l], L->beps[l], c);
+        if (q.q.sw) q.q.sw[slot] = tag;
         q.q.x[slot] = L->b[0][l];
         q.q.y[slot] = L->b[1][l];
         q.q.z[slot] = L->b[2][l];
@@ -135,6 +187,7 @@ struct StagedBirths {
         atomicOr(q.overflow, OVF_CAPACITY);
       }
     }
+    if (cum_ion) group_count(cum_ion, tag, mine);
     n = 0;
   }
 };
@@ -148,6 +201,7 @@ struct Flight {
   uint32_t j;           // number of the next segment (random-number counter)
   uint32_t src;         // slot the electron came from
   uint32_t r1, r2, r3;  // uniforms of the pending collision
+  uint32_t tag;         // group of the electron (swarm index; 0 in the PIC step)
   int mode;
   int seg;  // kind of the pending segment; for a parked electron, its event
 };
@@ -168,7 +222,8 @@ __device__ __forceinline__ PState flight_record(const Flight& f) {
   return p;
 }
 
-__device__ __forceinline__ void flight_start(Flight& f, const PState& p, double t0, uint32_t src) {
+__device__ __forceinline__ void flight_start(Flight& f, const PState& p, double t0, uint32_t src,
+                                             uint32_t tag = 0) {
   f.x = p.x;
   f.y = p.y;
   f.z = p.z;
@@ -179,6 +234,7 @@ __device__ __forceinline__ void flight_start(Flight& f, const PState& p, double 
   f.id = p.id;
   f.t = t0;
   f.src = src;
+  f.tag = tag;
   f.j = 0;
   f.mode = FM_NEW;
 }
@@ -233,8 +289,9 @@ __device__ __forceinline__ int flight_plan(Flight& f, double dt, const Tab& T, c
 
 // Completes the pending segment with the acceleration `an` gathered at its
 // end point, then applies its collision, if any.
+template <class Field>
 __device__ __forceinline__ int flight_complete(Flight& f, const double3 an, const Tab& T, const SpeciesView& S,
-                                               Cnt& cnt, const StagedBirths& births, bool& staged) {
+                                               Cnt& cnt, const StagedBirths<Field>& births, bool& staged) {
   const double hh = 0.5 * f.h;
   f.vx = fma(f.ax + an.x, hh, f.vx);
   f.vy = fma(f.ay + an.y, hh, f.vy);
@@ -280,7 +337,7 @@ __device__ __forceinline__ int flight_complete(Flight& f, const double3 an, cons
     eps_new = eps - thr;
   } else {
     eps_new = 0.5 * (eps - thr);
-    staged = births.push((float)f.x, (float)f.y, (float)f.z, f.w, (float)f.t, f.id, f.j - 1, eps_new);
+    staged = births.push((float)f.x, (float)f.y, (float)f.z, f.w, (float)f.t, f.tag, f.id, f.j - 1, eps_new);
   }
   const double sn = sqrt_nr(eps_new * S.inv_k_d);
   f.vx = sn * nx;
@@ -290,20 +347,25 @@ __device__ __forceinline__ int flight_complete(Flight& f, const double3 an, cons
 }
 
 // Runs every electron of a source (n of them) through the rest of the step.
-// Source: load(i, Flight&) starts electron i.  Finish: done(Flight&, event,
-// Cnt&, WaveStage*, staged count, bool& staged) takes an electron that left
-// the step, flush(WaveStage*, count) writes out the wave's staged results.
-// Must be called by whole waves with wave-uniform arguments; `take` is the
-// grid-wide work counter (zero before the first wave starts).  Every staged
-// entry is written out before the function returns.
+// Field: key(tag) gives the random-number key of a group, accel(x, y, z,
+// tag, where) the acceleration (and where the field was read), bound_at(where,
+// tag, speed, t_rem, a_abs, da) the field bounds for the rest of the step.
+// Source: load(i, Flight&) starts electron i (or leaves the lane idle).
+// Finish: done_all(Flight&, parked, Cnt&, WaveStage*, staged count, bool&
+// staged) takes the electrons that left the step (called by the whole wave;
+// `parked` marks the lanes holding one, f.seg is its event), flush(WaveStage*,
+// count) writes out the wave's staged results.  Must be called by whole waves with wave-uniform
+// arguments; `take` is the grid-wide work counter (zero before the first
+// wave starts).  cum_ion (nullable) counts ionizations per group.  Every
+// staged entry is written out before the function returns.
 template <class Field, class Source, class Finish>
 __device__ __forceinline__ void fly_all(uint64_t n, unsigned long long* take, double dt, const Field& F, const Tab& T,
-                                        const SpeciesView& S, Key key, uint32_t step, Cnt& cnt,
-                                        const BirthSink& sink, WaveStage* L, const Source& source,
+                                        const SpeciesView& S, uint32_t step, Cnt& cnt, const BirthSink& sink,
+                                        unsigned long long* cum_ion, WaveStage* L, const Source& source,
                                         const Finish& finish) {
   Flight f;
   f.mode = FM_IDLE;
-  StagedBirths births{L, sink, key, step, S, 0u};
+  StagedBirths<Field> births{L, sink, F, step, S, cum_ion, 0u};
   uint32_t n_done = 0;  // entries of the finish list
   uint64_t pool_next = 0, pool_end = 0;
   bool dry = n == 0;
@@ -319,10 +381,8 @@ __device__ __forceinline__ void fly_all(uint64_t n, unsigned long long* take, do
           n_done = 0;
         }
         bool placed = false;
-        if (f.mode == FM_DONE) {
-          finish.done(f, f.seg, cnt, L, n_done, placed);
-          f.mode = FM_IDLE;
-        }
+        finish.done_all(f, f.mode == FM_DONE, cnt, L, n_done, placed);
+        if (f.mode == FM_DONE) f.mode = FM_IDLE;
         n_done += (uint32_t)__popcll(__ballot(placed));
         if (n_done >= kFlushAt) {
           finish.flush(L, n_done);
@@ -362,7 +422,7 @@ __device__ __forceinline__ void fly_all(uint64_t n, unsigned long long* take, do
     bool born = false;
     if (f.mode == FM_FLY || f.mode == FM_NEW) {
       typename Field::Where where;
-      const double3 an = F.accel(f.x, f.y, f.z, where);
+      const double3 an = F.accel(f.x, f.y, f.z, f.tag, where);
       int ev;
       if (f.mode == FM_NEW) {
         // start of the electron's flight: acceleration and field bound for
@@ -370,14 +430,14 @@ __device__ __forceinline__ void fly_all(uint64_t n, unsigned long long* take, do
         f.ax = an.x;
         f.ay = an.y;
         f.az = an.z;
-        F.bound_at(where, sqrtf((float)(f.vx * f.vx + f.vy * f.vy + f.vz * f.vz)), (float)(dt - f.t), f.a_abs,
-                   f.da);
+        F.bound_at(where, f.tag, sqrtf((float)(f.vx * f.vx + f.vy * f.vy + f.vz * f.vz)), (float)(dt - f.t),
+                   f.a_abs, f.da);
         f.mode = FM_FLY;
         ev = EV_GO;
       } else {
         ev = flight_complete(f, an, T, S, cnt, births, born);
       }
-      if (ev == EV_GO) ev = flight_plan(f, dt, T, S, key, step, cnt);
+      if (ev == EV_GO) ev = flight_plan(f, dt, T, S, F.key(f.tag), step, cnt);
       if (ev != EV_GO) {
         f.mode = FM_DONE;
         f.seg = ev;

@@ -111,6 +111,7 @@ enum Quantity {
 // Device control block of the swarm step loop.
 struct SwarmCtl {
   unsigned long long pend[kMaxGenerations + 1];
+  unsigned long long take[kMaxGenerations + 1];  // work counters: current buffers, then each generation
   unsigned overflow;
   int cur_sel;
   int stop;

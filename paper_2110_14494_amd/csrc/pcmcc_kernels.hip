@@ -60,10 +60,11 @@ struct KeepInPlace {
   Soa nxt;
   uint32_t* holes;
   unsigned long long* n_holes;
-  __device__ __forceinline__ void done(const Flight& f, int ev, Cnt& cnt, WaveStage* L, uint32_t n_staged,
-                                       bool& staged) const {
+  __device__ __forceinline__ void done_all(const Flight& f, bool parked, Cnt& cnt, WaveStage* L,
+                                           uint32_t n_staged, bool& staged) const {
+    if (!parked) return;
     const PState p = flight_record(f);
-    bool alive = ev == EV_DONE;
+    bool alive = f.seg == EV_DONE;
     if (alive && !inside(*G, p)) {
       alive = false;
       cnt.v[C_LOST]++;
@@ -107,10 +108,11 @@ struct PlaceNewborn {
     else
       atomicOr(overflow, OVF_CAPACITY);
   }
-  __device__ __forceinline__ void done(const Flight& f, int ev, Cnt& cnt, WaveStage* L, uint32_t n_staged,
-                                       bool& staged) const {
+  __device__ __forceinline__ void done_all(const Flight& f, bool parked, Cnt& cnt, WaveStage* L,
+                                           uint32_t n_staged, bool& staged) const {
+    if (!parked) return;
     const PState p = flight_record(f);
-    bool alive = ev == EV_DONE;
+    bool alive = f.seg == EV_DONE;
     if (alive && !inside(*G, p)) {
       alive = false;
       cnt.v[C_LOST]++;
@@ -163,7 +165,7 @@ __global__ __launch_bounds__(256) void k_pic_steps(PicArgs A) {
   WaveStage* L = reinterpret_cast<WaveStage*>(smem + pic_stage_offset_floats(A.T)) + (threadIdx.x >> 6);
   GridView G = A.G;
   G.a_glob = G.qm_abs * __uint_as_float(*A.emax_bits);
-  const GridField F{G, A.S.qm};
+  const GridField F{G, A.S.qm, A.key};
   const unsigned lane = lane_id();
   Ctl* ctl = A.ctl;
 
@@ -182,7 +184,7 @@ __global__ __launch_bounds__(256) void k_pic_steps(PicArgs A) {
       const BirthSink sink{A.pend[0], &ctl->pend[0], A.pend_cap, &ctl->overflow, 0u};
       const SoaSource src{cur};
       const KeepInPlace fin{&A.G, nxt, A.holes, &ctl->holes};
-      fly_all(n_cur, &ctl->take[0], A.dt, F, T, A.S, A.key, step, cnt, sink, L, src, fin);
+      fly_all(n_cur, &ctl->take[0], A.dt, F, T, A.S, step, cnt, sink, nullptr, L, src, fin);
     }
     grid.sync();
 
@@ -200,7 +202,7 @@ __global__ __launch_bounds__(256) void k_pic_steps(PicArgs A) {
       const BirthSink sink{A.pend[(g + 1) & 1], &ctl->pend[g + 1], A.pend_cap, &ctl->overflow, 0u};
       const PendSource src{A.pend[g & 1]};
       const PlaceNewborn fin{&A.G, nxt, A.holes, h, n_cur, A.cap, &ctl->child, &ctl->overflow};
-      fly_all(np, &ctl->take[g + 1], A.dt, F, T, A.S, A.key, step, cnt, sink, L, src, fin);
+      fly_all(np, &ctl->take[g + 1], A.dt, F, T, A.S, step, cnt, sink, nullptr, L, src, fin);
       grid.sync();
     }
 

@@ -112,12 +112,17 @@ struct GridField {
                                         float& da) const {
     accel_bound(G, x, y, z, speed, t_rem, a_abs, da);
   }
-  // Gather that also returns its record, and the bound from that record.
+  // Interface of the segment-pipelined mover (one group: the tag is 0): the
+  // run's key, a gather that also returns its record, and the bound from
+  // that record.
+  Key k;
   using Where = const float4*;
-  __device__ __forceinline__ double3 accel(double x, double y, double z, Where& w) const {
+  __device__ __forceinline__ Key key(uint32_t) const { return k; }
+  __device__ __forceinline__ double3 accel(double x, double y, double z, uint32_t, Where& w) const {
     return gather(G, qm, x, y, z, &w);
   }
-  __device__ __forceinline__ void bound_at(Where w, float speed, float t_rem, float& a_abs, float& da) const {
+  __device__ __forceinline__ void bound_at(Where w, uint32_t, float speed, float t_rem, float& a_abs,
+                                           float& da) const {
     accel_bound_at(G, w, speed, t_rem, a_abs, da);
   }
 };

@@ -5,17 +5,20 @@
 // temporal-growth model.
 //
 // Layout: swarm s owns a contiguous region of cap_s slots in each of two
-// particle buffers; a step loads region s of the current buffer in 64-wide
-// tiles (one wave, one swarm) and appends survivors to region s of the next
-// buffer with one atomic per wave.  Newborns of all swarms share one queue
-// that carries the swarm index.  Population control runs at the start of the
-// next step's load (keep with probability 2^-k, or duplicate).  Moments are
-// summed exactly in 128-bit fixed point, so they do not depend on the order
-// in which particles land in the buffers.
+// particle buffers.  A step runs the segment-pipelined mover (pcmcc_flight.hpp)
+// over all swarms' electrons at once, the swarm index being the electron's
+// group (its field, its random-number key, its destination region); survivors
+// are appended to region s of the next buffer, one atomic per swarm and
+// batch.  Newborns of all swarms share one queue that carries the swarm
+// index.  Population control runs when an electron is loaded in the next
+// step (keep with probability 2^-k, or duplicate).  Moments are summed
+// exactly in 128-bit fixed point, so they do not depend on the order in
+// which particles land in the buffers.
 #include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
 #include "pcmcc_device.hpp"
+#include "pcmcc_flight.hpp"
 #include "pcmcc_internal.hpp"
 #include "pcmcc_mover.hpp"
 
@@ -35,6 +38,134 @@ struct UniformField {
 };
 
 __device__ __forceinline__ Key swarm_key(Key k, int s) { return Key{k.k0, k.k1 ^ (uint32_t)s}; }
+
+// Group policy of the mover for swarms: the group is the swarm index.
+struct SwarmField {
+  const double* az;    // LDS [S]: acceleration along z
+  const float* a_abs;  // LDS [S]: |az| in single precision
+  Key base;
+  using Where = int;
+  __device__ __forceinline__ Key key(uint32_t s) const { return swarm_key(base, (int)s); }
+  __device__ __forceinline__ double3 accel(double, double, double, uint32_t s, Where&) const {
+    return make_double3(0.0, 0.0, az[s]);
+  }
+  __device__ __forceinline__ void bound_at(Where, uint32_t s, float, float, float& a, float& da) const {
+    a = a_abs[s];
+    da = 0.0f;
+  }
+};
+
+// Swarm of global electron index g: the last s with prefix[s] <= g.
+__device__ __forceinline__ int swarm_of(const uint32_t* prefix, int S, uint32_t g);
+
+// Phase 1 source: the electrons of all swarms (prefix of counts in LDS),
+// with the population control decided at the previous commit applied as
+// they are loaded: keep with probability 2^-k, or duplicate (the duplicate
+// joins the newborn queue and starts from t = 0).
+struct SwarmLoad {
+  Soa cur;
+  const uint64_t* base;
+  const uint32_t* prefix;
+  const int* pck;
+  int n_swarms;
+  Key key;
+  uint32_t step;
+  BirthSink dup;  // duplicates: the generation-0 newborn queue
+  uint32_t* psteps;
+  __device__ __forceinline__ void load(uint64_t g, Flight& f) const {
+    const int s = swarm_of(prefix, n_swarms, (uint32_t)g);
+    const uint64_t i = g - prefix[s];
+    PState p;
+    load_p(cur, base[s] + i, p);
+    const int k = pck[s];
+    bool keep = true;
+    if (k != 0) {
+      const uint4 r = draw(swarm_key(key, s), p.id, step - 1, 0, TAG_AUX);
+      if (k > 0) {
+        keep = unif(r.x) < ldexpf(1.0f, -k);
+      } else {
+        PState d = p;
+        d.id = (uint64_t)r.y | ((uint64_t)r.z << 32);
+        BirthSink q = dup;
+        q.tag = (uint32_t)s;
+        q.push(d, 0.0f);
+        (*psteps)++;
+      }
+    }
+    if (!keep) return;
+    (*psteps)++;
+    flight_start(f, p, 0.0, 0u, (uint32_t)s);
+  }
+};
+
+// Phase 2 source: the newborn queue (with swarm indices and birth times).
+struct SwarmPend {
+  PendSoa q;
+  __device__ __forceinline__ void load(uint64_t i, Flight& f) const {
+    PState p;
+    float tb;
+    load_pend(q, i, p, tb);
+    flight_start(f, p, (double)tb, 0u, q.sw[i]);
+  }
+};
+
+// Destination: survivors are appended to their swarm's region of the next
+// buffer (staged per wave, one atomic per swarm and batch); attachments are
+// counted per swarm.
+struct SwarmPlace {
+  Soa nxt;
+  const uint64_t* base;
+  const uint64_t* cap_s;
+  unsigned long long* n_nxt;
+  unsigned long long* cum_att;
+  unsigned* overflow;
+  __device__ __forceinline__ void done_all(const Flight& f, bool parked, Cnt&, WaveStage* L, uint32_t n_staged,
+                                           bool& staged) const {
+    group_count(cum_att, f.tag, parked && f.seg == EV_ATTACHED);
+    if (!parked || f.seg != EV_DONE) return;
+    const PState p = flight_record(f);
+    const uint32_t s = n_staged + rank_in(__ballot(1));
+    if (s < kStage) {
+      L->s[0][s] = p.x;
+      L->s[1][s] = p.y;
+      L->s[2][s] = p.z;
+      L->s[3][s] = p.vx;
+      L->s[4][s] = p.vy;
+      L->s[5][s] = p.vz;
+      L->s[6][s] = p.w;
+      L->stag[s] = f.tag;
+      L->sid[s] = p.id;
+      staged = true;
+    } else {
+      const uint64_t slot = atomicAdd(&n_nxt[f.tag], 1ull);
+      if (slot < cap_s[f.tag])
+        store_p(nxt, base[f.tag] + slot, p);
+      else
+        atomicOr(overflow, OVF_CAPACITY);
+    }
+  }
+  __device__ __forceinline__ void flush(WaveStage* L, uint32_t n) const {
+    const uint32_t l = lane_id();
+    const bool mine = l < n;
+    const uint32_t s = mine ? L->stag[l] : 0u;
+    const uint64_t slot = group_reserve(n_nxt, s, mine);
+    if (!mine) return;
+    if (slot < cap_s[s]) {
+      PState p;
+      p.x = L->s[0][l];
+      p.y = L->s[1][l];
+      p.z = L->s[2][l];
+      p.vx = L->s[3][l];
+      p.vy = L->s[4][l];
+      p.vz = L->s[5][l];
+      p.w = L->s[6][l];
+      p.id = L->sid[l];
+      store_p(nxt, base[s] + slot, p);
+    } else {
+      atomicOr(overflow, OVF_CAPACITY);
+    }
+  }
+};
 
 // 128-bit two's-complement accumulator word pair (lo, hi), exact and order
 // independent: the carry out of the low word is added to the high word.
@@ -81,6 +212,18 @@ __device__ void tile_prefix(const unsigned long long* n, int S, int tile, uint32
   __syncthreads();
 }
 
+__device__ __forceinline__ int swarm_of(const uint32_t* prefix, int S, uint32_t g) {
+  int lo = 0, hi = S;  // prefix[lo] <= g < prefix[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (prefix[mid] <= g)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
 // Swarm owning tile tt: the last s with prefix[s] <= tt.
 __device__ __forceinline__ int find_swarm(const uint32_t* prefix, int S, uint32_t tt) {
   int lo = 0, hi = S;  // prefix[lo] <= tt < prefix[hi]
@@ -106,20 +249,27 @@ __global__ __launch_bounds__(BS) void k_swarm_steps(SwarmArgs A) {
   cg::grid_group grid = cg::this_grid();
   const Tab T = stage_tables(A.T, smem);
   const int S = A.n_swarms;
-  // LDS after the tables: tile prefix [S+1], scan scratch [BS], per-swarm
-  // acceleration [S] and population-control exponent [S].
-  uint32_t* prefix = (uint32_t*)(smem + table_lds_floats(A.T));
+  // LDS after the tables: per-wave staging lists, per-swarm acceleration [S]
+  // (double), prefix [S+1], scan scratch [BS], |acceleration| [S] and
+  // population-control exponent [S].
+  WaveStage* L = reinterpret_cast<WaveStage*>(smem + pic_stage_offset_floats(A.T)) + (threadIdx.x >> 6);
+  double* az_d = reinterpret_cast<double*>(reinterpret_cast<WaveStage*>(smem + pic_stage_offset_floats(A.T)) +
+                                           BS / 64);
+  uint32_t* prefix = (uint32_t*)(az_d + S);
   uint32_t* tmp = prefix + (S + 1);
   float* az_l = (float*)(tmp + BS);
   int* pck = (int*)(az_l + S);
   __shared__ long long red[kNMom][BS / 64];
   __shared__ unsigned long long acc_lo[kNMom];
   __shared__ long long acc_hi[kNMom];
-  for (int s = threadIdx.x; s < S; s += BS) az_l[s] = (float)A.az[s];
+  for (int s = threadIdx.x; s < S; s += BS) {
+    az_d[s] = A.az[s];
+    az_l[s] = fabsf((float)A.az[s]);
+  }
+  __syncthreads();
+  const SwarmField F{az_d, az_l, A.key};
   const unsigned lane = lane_id();
   const uint32_t wpb = BS / 64;
-  const uint32_t gw = blockIdx.x * wpb + (threadIdx.x >> 6);
-  const uint32_t GW = gridDim.x * wpb;
   SwarmCtl* ctl = A.ctl;
 
   for (int st = 0; st < A.n_steps; ++st) {
@@ -128,52 +278,20 @@ __global__ __launch_bounds__(BS) void k_swarm_steps(SwarmArgs A) {
     const Soa cur = A.buf[sel], nxt = A.buf[sel ^ 1];
     const uint32_t step = (uint32_t)st;
     for (int s = threadIdx.x; s < S; s += BS) pck[s] = ld_acq(&A.pc_k[s]);
-    tile_prefix(A.n_cur, S, 64, prefix, tmp);
+    tile_prefix(A.n_cur, S, 1, prefix, tmp);
     Cnt cnt;
 #pragma unroll
     for (int k = 0; k < NCNT; ++k) cnt.v[k] = 0;
     uint32_t psteps = 0;
+    const SwarmPlace fin{nxt, A.base, A.cap_s, A.n_nxt, A.cum_att, &ctl->overflow};
 
-    // Phase 1: each swarm's particles, after population control, from t = 0.
-    const uint32_t n_tiles = prefix[S];
-    for (uint32_t tt = gw; tt < n_tiles; tt += GW) {
-      const int s = find_swarm(prefix, S, tt);
-      const uint64_t n_s = ld_acq(&A.n_cur[s]);
-      const uint64_t i = (uint64_t)(tt - prefix[s]) * 64 + lane;
-      if (i >= n_s) continue;
-      const Key key = swarm_key(A.key, s);
-      const UniformField F{(double)A.az[s], fabsf(az_l[s])};
-      PState p;
-      load_p(cur, A.base[s] + i, p);
-      const int k = pck[s];
-      bool keep = true;
-      if (k != 0) {
-        const uint4 r = draw(key, p.id, step - 1, 0, TAG_AUX);
-        if (k > 0) {
-          keep = unif(r.x) < ldexpf(1.0f, -k);
-        } else {
-          PState d = p;
-          d.id = (uint64_t)r.y | ((uint64_t)r.z << 32);
-          const BirthSink dsink{A.pend[0], &ctl->pend[0], A.pend_cap, &ctl->overflow, (uint32_t)s};
-          dsink.push(d, 0.0f);  // advanced from t = 0 with the newborns
-          psteps++;
-        }
-      }
-      if (!keep) continue;
-      psteps++;
-      const BirthSink sink{A.pend[0], &ctl->pend[0], A.pend_cap, &ctl->overflow, (uint32_t)s};
-      const uint32_t ion0 = cnt.v[C_ION], att0 = cnt.v[C_ATT];
-      const int r = advance(p, 0.0, (double)A.dt, F, T, A.S, key, step, cnt, sink);
-      const uint32_t dion = cnt.v[C_ION] - ion0, datt = cnt.v[C_ATT] - att0;
-      if (dion) atomicAdd(&A.cum_ion[s], (unsigned long long)dion);
-      if (datt) atomicAdd(&A.cum_att[s], (unsigned long long)datt);
-      if (r == 0) {
-        const uint64_t slot = wave_reserve(&A.n_nxt[s]);
-        if (slot < A.cap_s[s])
-          store_p(nxt, A.base[s] + slot, p);
-        else
-          atomicOr(&ctl->overflow, OVF_CAPACITY);
-      }
+    // Phase 1: each swarm's electrons, after population control, from t = 0.
+    {
+      const BirthSink sink{A.pend[0], &ctl->pend[0], A.pend_cap, &ctl->overflow, 0u};
+      const SwarmLoad src{cur,  A.base, prefix, pck, S, A.key, step,
+                          BirthSink{A.pend[0], &ctl->pend[0], A.pend_cap, &ctl->overflow, 0u}, &psteps};
+      fly_all((uint64_t)prefix[S], &ctl->take[0], (double)A.dt, F, T, A.S, step, cnt, sink, A.cum_ion, L, src,
+              fin);
     }
     grid.sync();
 
@@ -186,30 +304,9 @@ __global__ __launch_bounds__(BS) void k_swarm_steps(SwarmArgs A) {
         break;
       }
       const uint64_t np = np_raw < A.pend_cap ? np_raw : A.pend_cap;
-      const PendSoa src = A.pend[g & 1];
-      for (uint64_t base = (uint64_t)gw * 64; base < np; base += (uint64_t)GW * 64) {
-        const uint64_t i = base + lane;
-        if (i >= np) continue;
-        PState p;
-        float tb;
-        load_pend(src, i, p, tb);
-        const int s = (int)src.sw[i];
-        const Key key = swarm_key(A.key, s);
-        const UniformField F{(double)A.az[s], fabsf(az_l[s])};
-        const BirthSink sink{A.pend[(g + 1) & 1], &ctl->pend[g + 1], A.pend_cap, &ctl->overflow, (uint32_t)s};
-        const uint32_t ion0 = cnt.v[C_ION], att0 = cnt.v[C_ATT];
-        const int r = advance(p, (double)tb, (double)A.dt, F, T, A.S, key, step, cnt, sink);
-        const uint32_t dion = cnt.v[C_ION] - ion0, datt = cnt.v[C_ATT] - att0;
-        if (dion) atomicAdd(&A.cum_ion[s], (unsigned long long)dion);
-        if (datt) atomicAdd(&A.cum_att[s], (unsigned long long)datt);
-        if (r == 0) {
-          const uint64_t slot = atomicAdd(&A.n_nxt[s], 1ull);
-          if (slot < A.cap_s[s])
-            store_p(nxt, A.base[s] + slot, p);
-          else
-            atomicOr(&ctl->overflow, OVF_CAPACITY);
-        }
-      }
+      const BirthSink sink{A.pend[(g + 1) & 1], &ctl->pend[g + 1], A.pend_cap, &ctl->overflow, 0u};
+      const SwarmPend src{A.pend[g & 1]};
+      fly_all(np, &ctl->take[g + 1], (double)A.dt, F, T, A.S, step, cnt, sink, A.cum_ion, L, src, fin);
       grid.sync();
     }
 
@@ -358,7 +455,10 @@ __global__ __launch_bounds__(BS) void k_swarm_steps(SwarmArgs A) {
           for (int k = 0; k < NCNT; ++k) ctl->tot[k] += sums[k];
         }
         ctl->overflow = 0;
-        for (int g = 0; g <= kMaxGenerations; ++g) ctl->pend[g] = 0;
+        for (int g = 0; g <= kMaxGenerations; ++g) {
+          ctl->pend[g] = 0;
+          ctl->take[g] = 0;
+        }
       }
     }
     grid.sync();
@@ -491,7 +591,8 @@ __global__ void k_swarm_estimate(const unsigned long long* mom, const long long*
 
 // ---------------------------------------------------------------------------
 size_t swarm_lds_bytes(const TableView& T, int S, int block) {
-  return table_lds_bytes(T) + (size_t)(S + 1) * 4 + (size_t)block * 4 + (size_t)S * 4 + (size_t)S * 4;
+  return pic_stage_offset_floats(T) * sizeof(float) + (size_t)(block / 64) * sizeof(WaveStage) + (size_t)S * 8 +
+         (size_t)(S + 1) * 4 + (size_t)block * 4 + (size_t)S * 4 + (size_t)S * 4;
 }
 
 static const void* swarm_kernel(int block) {
