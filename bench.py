@@ -57,7 +57,7 @@ def parse():
     ap.add_argument("--cap-factor", type=int, default=32)
     ap.add_argument("--max-steps", type=int, default=None, help="cap the committed steps (profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=2 ** 18)
+    ap.add_argument("--cpu-sample", type=int, default=2 ** 23)
     ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--no-coef", action="store_true", help="skip the swarm / surrogate leg")
     ap.add_argument("--coef-scale", type=float, default=1.0, help="scale of the swarm sizes")
@@ -118,9 +118,13 @@ def cpu_baseline(cfg, sample: int, steps: int) -> dict:
     sub = {k: v[:n] for k, v in p.items()}
     t0 = time.perf_counter()
     rc, out, st = oracle.pic_run(cfg["species"], cfg["tables"], cfg["grid"], sub, cfg["dt"], steps, cfg["seed"],
-                                 capacity=64 * n)
+                                 capacity=16 * n)
     el = time.perf_counter() - t0
-    return {"value": st["particle_steps"] / el, "unit": "particle-steps/s", "cores": os.cpu_count(),
+    # OpenMP threads the oracle ran with: OMP_NUM_THREADS, else the CPUs this
+    # process may run on
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    threads = int(env) if env.isdigit() and int(env) > 0 else len(os.sched_getaffinity(0))
+    return {"value": st["particle_steps"] / el, "unit": "particle-steps/s", "cores": threads,
             "kind": "oracle", "cpu": cpu_model(),
             "sample": f"first {n} electrons of the workload, {st['steps_done']} steps of {cfg['dt']:.0e} s "
                       f"({st['particle_steps']} particle-steps in {el:.1f} s including table and field-bound "
@@ -226,15 +230,18 @@ def coef_leg(a, ctx, pic):
     plain_pps = len(probe) / (time.perf_counter() - t0)
     held = np.arange(4, n_all, n_batch)  # batch 4 = every 8th point
     train = np.setdiff1d(np.arange(n_all), held)
-    x, t, m, ln_tr, norm = S.dataset(EN_all[train], vals[train], errs[train], sp["gas_N"], 0.1)
-    _, _, m_h, ln_h, _ = S.dataset(EN_all[held], vals[held], errs[held], sp["gas_N"], 0.1, norm=norm)
-    _, _, _, ln_all, _ = S.dataset(EN_all, vals, errs, sp["gas_N"], 0.1, norm=norm)
+    x, t, m, ln_tr, _, norm = S.dataset(EN_all[train], vals[train], errs[train], sp["gas_N"], 0.1)
+    _, _, m_h, ln_h, sig_h, _ = S.dataset(EN_all[held], vals[held], errs[held], sp["gas_N"], 0.1, norm=norm)
+    _, _, _, ln_all, _, _ = S.dataset(EN_all, vals, errs, sp["gas_N"], 0.1, norm=norm)
     th0 = W.mlp_init(4)
     params, hist, tst = S.train(ctx, th0, x, t, m, a.epochs, 3e-3, 1e-5)
     log(f"surrogate trained: {a.epochs} epochs in {tst['step_kernel_ms']:.0f} ms, loss {hist[0]:.3g} -> {hist[-1]:.3g}")
     lo, hi = math.log(10.0), math.log(1000.0)
-    tol = math.log(1.01)
-    fb, err = S.fallback(ctx, params, norm, EN_all[held], ln_h, m_h, tol, 256, lo, hi)
+    # a cell falls back to the swarm table where the surrogate misses a
+    # held-out swarm value by more than 1 % plus three of that value's own
+    # Monte Carlo standard errors
+    tol, z_sig = math.log(1.01), 3.0
+    fb, err = S.fallback(ctx, params, norm, EN_all[held], ln_h, m_h, tol, 256, lo, hi, sig_held=sig_h, z_sig=z_sig)
     norm_fb = norm.with_fallback(fb, lo, hi, ln_all, lo, hi)
     EN_q = torch.from_numpy(W.log_uniform_EN(a.infer_n, seed=5)).cuda()
     out = torch.empty((6, a.infer_n), dtype=torch.float32, device="cuda")
@@ -256,7 +263,9 @@ def coef_leg(a, ctx, pic):
         "heldout_abs_ln_err_median": {k: float(np.nanmedian(e_ok[:, i])) for i, k in enumerate(names)},
         "heldout_abs_ln_err_max": {k: float(np.nanmax(e_ok[:, i])) if np.any(np.isfinite(e_ok[:, i])) else None
                                    for i, k in enumerate(names)},
-        "tolerance_ln": tol, "cells": 256, "cells_fallback": int(fb.sum()),
+        "heldout_err_over_sigma_median": {k: float(np.nanmedian(e_ok[:, i] / sig_h[:, i]))
+                                          for i, k in enumerate(names)},
+        "tolerance_ln": tol, "tolerance_sigmas": z_sig, "cells": 256, "cells_fallback": int(fb.sum()),
         "infer_points": a.infer_n, "infer_s": infer_s, "infer_kernel_ms": ist["step_kernel_ms"],
         "surrogate_EN_points_per_s": a.infer_n / infer_s,
         "surrogate_over_plain_swarm": (a.infer_n / infer_s) / plain_pps,

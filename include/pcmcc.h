@@ -285,21 +285,26 @@ int pcmcc_mlp_infer(pcmcc_ctx* ctx, const float* params, const pcmcc_mlp_infer_o
  * computed into norm (mu_x, sd_x, mu_y, sd_y); otherwise norm is used as
  * given.  x_out[n], t_out[n][6], mask_out[n][6] are the standardised data;
  * ln_out[n][6] (nullable) the unstandardised ln values with masked entries
- * set to ln_floor.  Host memory; no device work. */
+ * set to ln_floor; sig_out[n][6] (nullable) the relative batch-means error of
+ * each entry, the standard error of its ln value to first order (NaN where
+ * masked).  Host memory; no device work. */
 int pcmcc_mlp_dataset(int n, const double* EN_Td, const pcmcc_swarm_result* res, double gas_N, double max_rel_err,
                       int compute_norm, pcmcc_mlp_infer_opts* norm, float* x_out, float* t_out, float* mask_out,
-                      float* ln_out, double ln_floor);
+                      float* ln_out, float* sig_out, double ln_floor);
 
 /* Held-out check of a trained surrogate: evaluates it (the bfloat16 device
  * path) at n_held reduced fields and marks cell c of n_cells cells uniform in
  * ln(E/N) over [cell_lo, cell_hi) for fallback if, for any held-out point in
- * it, an output is masked or |ln y_mlp - ln y_swarm| > tol_ln.  ln_held and
- * mask_held [n_held][6] are unstandardised ln targets and their mask (host);
- * fallback_out[n_cells] host; err_out[n_held][6] (nullable) receives the
- * absolute ln errors (NaN where masked). */
+ * it, an output is masked or |ln y_mlp - ln y_swarm| > tol_ln + z_sig sig,
+ * sig being the held-out value's own Monte Carlo standard error in ln units
+ * (a held-out swarm value is itself noisy; sig_held NULL means 0).  ln_held,
+ * mask_held and sig_held [n_held][6] are unstandardised ln targets, their
+ * mask and errors (host); fallback_out[n_cells] host; err_out[n_held][6]
+ * (nullable) receives the absolute ln errors (NaN where masked). */
 int pcmcc_mlp_fallback(pcmcc_ctx* ctx, const float* params, const pcmcc_mlp_infer_opts* norm, int n_held,
-                       const double* EN_held, const float* ln_held, const float* mask_held, double tol_ln,
-                       int n_cells, double cell_lo, double cell_hi, uint8_t* fallback_out, float* err_out);
+                       const double* EN_held, const float* ln_held, const float* mask_held, const float* sig_held,
+                       double tol_ln, double z_sig, int n_cells, double cell_lo, double cell_hi,
+                       uint8_t* fallback_out, float* err_out);
 
 /* Deposit only (Sec. 2.1.3), same fixed-point rule as above, on n_dev
  * particles (device count) of device arrays x, y, z, w. */

@@ -117,9 +117,9 @@ def lib() -> C.CDLL:
             "pcmcc_mlp_infer": ([vp, vp, C.POINTER(pcmcc_mlp_infer_opts), i64, vp, vp, C.POINTER(pcmcc_stats)],
                                 C.c_int),
             "pcmcc_mlp_dataset": ([C.c_int, vp, vp, C.c_double, C.c_double, C.c_int,
-                                   C.POINTER(pcmcc_mlp_infer_opts), vp, vp, vp, vp, C.c_double], C.c_int),
-            "pcmcc_mlp_fallback": ([vp, vp, C.POINTER(pcmcc_mlp_infer_opts), C.c_int, vp, vp, vp, C.c_double,
-                                    C.c_int, C.c_double, C.c_double, vp, vp], C.c_int),
+                                   C.POINTER(pcmcc_mlp_infer_opts), vp, vp, vp, vp, vp, C.c_double], C.c_int),
+            "pcmcc_mlp_fallback": ([vp, vp, C.POINTER(pcmcc_mlp_infer_opts), C.c_int, vp, vp, vp, vp, C.c_double,
+                                    C.c_double, C.c_int, C.c_double, C.c_double, vp, vp], C.c_int),
             "pcmcc_swarm_batch": ([vp, C.c_int, vp, vp, C.c_double, C.c_int, u64, C.POINTER(pcmcc_swarm_opts),
                                    vp, vp, vp, C.POINTER(pcmcc_stats)], C.c_int),
         }

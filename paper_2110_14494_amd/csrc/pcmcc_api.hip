@@ -1068,10 +1068,10 @@ int pcmcc_mlp_infer(pcmcc_ctx* c, const float* params, const pcmcc_mlp_infer_opt
 
 int pcmcc_mlp_dataset(int n, const double* EN_Td, const pcmcc_swarm_result* res, double gas_N, double max_rel_err,
                       int compute_norm, pcmcc_mlp_infer_opts* norm, float* x_out, float* t_out, float* mask_out,
-                      float* ln_out, double ln_floor) {
+                      float* ln_out, float* sig_out, double ln_floor) {
   if (n < 1 || !EN_Td || !res || !norm || !x_out || !t_out || !mask_out || !(gas_N > 0) || !(max_rel_err > 0))
     return fail(nullptr, PCMCC_EINVAL, "invalid surrogate dataset arguments");
-  std::vector<double> lx(n), ly((size_t)n * PCMCC_MLP_OUT);
+  std::vector<double> lx(n), ly((size_t)n * PCMCC_MLP_OUT), sg((size_t)n * PCMCC_MLP_OUT);
   std::vector<char> ok((size_t)n * PCMCC_MLP_OUT);
   for (int i = 0; i < n; ++i) {
     if (!(EN_Td[i] > 0)) return fail(nullptr, PCMCC_EINVAL, "E/N must be positive");
@@ -1090,6 +1090,7 @@ int pcmcc_mlp_dataset(int n, const double* EN_Td, const pcmcc_swarm_result* res,
       const bool good = val[k] > 0 && std::isfinite(val[k]) && rel[k] <= max_rel_err;
       ok[(size_t)i * PCMCC_MLP_OUT + k] = good;
       ly[(size_t)i * PCMCC_MLP_OUT + k] = good ? std::log(val[k]) : ln_floor;
+      sg[(size_t)i * PCMCC_MLP_OUT + k] = good ? rel[k] : NAN;
     }
   }
   if (compute_norm) {
@@ -1128,17 +1129,19 @@ int pcmcc_mlp_dataset(int n, const double* EN_Td, const pcmcc_swarm_result* res,
       mask_out[j] = ok[j] ? 1.0f : 0.0f;
       t_out[j] = ok[j] ? (float)((ly[j] - norm->mu_y[k]) / norm->sd_y[k]) : 0.0f;
       if (ln_out) ln_out[j] = (float)ly[j];
+      if (sig_out) sig_out[j] = (float)sg[j];
     }
   }
   return PCMCC_OK;
 }
 
 int pcmcc_mlp_fallback(pcmcc_ctx* c, const float* params, const pcmcc_mlp_infer_opts* norm, int n_held,
-                       const double* EN_held, const float* ln_held, const float* mask_held, double tol_ln,
-                       int n_cells, double cell_lo, double cell_hi, uint8_t* fallback_out, float* err_out) {
+                       const double* EN_held, const float* ln_held, const float* mask_held, const float* sig_held,
+                       double tol_ln, double z_sig, int n_cells, double cell_lo, double cell_hi,
+                       uint8_t* fallback_out, float* err_out) {
   if (!c) return fail(nullptr, PCMCC_EINVAL, "null context");
-  if (!params || !norm || n_held < 1 || !EN_held || !ln_held || !mask_held || !(tol_ln > 0) || n_cells < 1 ||
-      !(cell_hi > cell_lo) || !fallback_out)
+  if (!params || !norm || n_held < 1 || !EN_held || !ln_held || !mask_held || !(tol_ln > 0) || !(z_sig >= 0) ||
+      n_cells < 1 || !(cell_hi > cell_lo) || !fallback_out)
     return fail(c, PCMCC_EINVAL, "invalid fallback arguments");
   HIP_TRY(c, hipSetDevice(c->device));
   std::vector<float> en(n_held), y((size_t)PCMCC_MLP_OUT * n_held);
@@ -1173,7 +1176,8 @@ int pcmcc_mlp_fallback(pcmcc_ctx* c, const float* params, const pcmcc_mlp_infer_
         fallback_out[cell] = 1;
       } else {
         err = std::fabs(y[(size_t)k * n_held + i] - ln_held[j]);
-        if (!(err <= tol_ln)) fallback_out[cell] = 1;
+        const double sig = sig_held ? (double)sig_held[j] : 0.0;
+        if (!(err <= tol_ln + z_sig * (std::isfinite(sig) ? sig : 0.0))) fallback_out[cell] = 1;
       }
       if (err_out) err_out[j] = err;
     }

@@ -186,7 +186,10 @@ __device__ __forceinline__ double3 gather(const GridView& G, double qm, double x
   return make_double3(qm * e.x, qm * e.y, qm * e.z);
 }
 
-// As accel_bound, with the record of the particle's position already known.
+// Acceleration bounds for the rest of a step of length t_rem, from the record
+// of the particle's position: local ones if the particle cannot leave its
+// cell neighbourhood (displacement below one cell with a 2^-10 margin), else
+// the global bound.
 __device__ __forceinline__ void accel_bound_at(const GridView& G, const float4* rec, float speed, float t_rem,
                                                float& a_abs, float& da) {
   const float D = fmaf(0.5f * G.a_glob * t_rem, t_rem, speed * t_rem);
@@ -196,27 +199,6 @@ __device__ __forceinline__ void accel_bound_at(const GridView& G, const float4* 
     return;
   }
   const float4 m = rec[6];
-  a_abs = G.qm_abs * m.x;
-  da = G.qm_abs * m.y;
-}
-
-// Acceleration bounds for the rest of a step of length t_rem: local ones if
-// the particle cannot leave its cell neighbourhood (displacement below one
-// cell with a 2^-10 margin), else the global bound.
-__device__ __forceinline__ void accel_bound(const GridView& G, double x, double y, double z, float speed,
-                                            float t_rem, float& a_abs, float& da) {
-  const float D = fmaf(0.5f * G.a_glob * t_rem, t_rem, speed * t_rem);
-  if (!(D < G.dx * (1.0f - 0x1p-10f))) {
-    a_abs = G.a_glob;
-    da = 2.0f * G.a_glob;
-    return;
-  }
-  int i, j, k;
-  float f;
-  cell_coord(x, G.o[0], G.inv_dx, G.nx, i, f);
-  cell_coord(y, G.o[1], G.inv_dx, G.ny, j, f);
-  cell_coord(z, G.o[2], G.inv_dx, G.nz, k, f);
-  const float4 m = grid_record(G, i, j, k)[6];
   a_abs = G.qm_abs * m.x;
   da = G.qm_abs * m.y;
 }

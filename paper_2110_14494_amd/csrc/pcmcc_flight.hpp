@@ -1,10 +1,17 @@
-// Segment-pipelined electron mover of the PIC step.
+// Segment-pipelined electron mover of the PIC step and the swarms.
 //
 // Method: arXiv:2110.14494 Sec. 2.1.1 (velocity Verlet, eq. (1)-(2), and the
-// null-collision method) and Sec. 2.1.5 (tabulated rates).  The arithmetic of
-// each particle is the one of `advance` in pcmcc_mover.hpp, operation for
-// operation, and it draws the same random numbers; only the schedule
-// differs.
+// null-collision method) and Sec. 2.1.5 (tabulated rates).  Per electron
+// and step: from its start time, flight segments of length min(tau, horizon,
+// rest of the step), tau = -ln(U)/nu_hat with nu_hat the majorant of the total
+// rate for the speeds reachable within the horizon; at the end of a segment
+// that did not reach the horizon, the process is chosen from the cumulative
+// rates at the electron's energy (null if none or below its threshold) and
+// applied: isotropic scattering with the elastic recoil loss, excitation
+// losing its threshold, ionization sharing the remaining energy equally with
+// a newborn, attachment removing the electron.  Random numbers are
+// Philox4x32-10 keyed by the run (and group) with counter (id, step, segment,
+// purpose), so results do not depend on the schedule.
 //
 // Schedule: a lane holds one electron.  Every iteration of a wave's loop does
 // exactly one field gather per lane (at the end point of the lane's pending

@@ -1,6 +1,6 @@
-// Device code shared by the PIC step and the swarm kernels: the electron
-// mover (flight segments, null collisions, collision outcomes), newborn
-// queues, wave-aggregated slot reservation and table staging.
+// Device code shared by the PIC step and the swarm kernels: the field policy
+// of the grid, staged rate tables, isotropic scattering, newborn queues,
+// wave-aggregated slot reservation and particle record access.
 //
 // Method: arXiv:2110.14494 Sec. 2.1.1 (velocity Verlet, eq. (1)-(2), and the
 // null-collision method) and Sec. 2.1.5 (rates from cross sections).
@@ -107,11 +107,6 @@ struct BirthSink {
 struct GridField {
   GridView G;
   double qm;
-  __device__ __forceinline__ double3 accel(double x, double y, double z) const { return gather(G, qm, x, y, z); }
-  __device__ __forceinline__ void bound(double x, double y, double z, float speed, float t_rem, float& a_abs,
-                                        float& da) const {
-    accel_bound(G, x, y, z, speed, t_rem, a_abs, da);
-  }
   // Interface of the segment-pipelined mover (one group: the tag is 0): the
   // run's key, a gather that also returns its record, and the bound from
   // that record.
@@ -210,131 +205,6 @@ __device__ __forceinline__ void iso_dir(uint32_t r1, uint32_t r2, double& nx, do
   nx = inv * cp;
   ny = inv * sp;
   nz = cth;
-}
-
-// Advances one electron from time t to the end of the step (length dt).
-// Returns 0 if it is alive at the end of the step, 1 if attached, 2 if it
-// hit the segment limit.  Newborns go to `sink` with their birth time.
-//
-// Position, velocity, time and energy are carried in double precision within
-// the step (stored single precision between steps): on CDNA4 unpacked FP32
-// and FP64 fused multiply-adds issue at the same rate, and double keeps the
-// energy bookkeeping of tens of collisions per step free of drift.  Field,
-// tables, majorant and random numbers stay single precision.
-template <class Field>
-__device__ int advance(PState& p, double t, double dt, const Field& F, const Tab& T, const SpeciesView& S, Key key,
-                       uint32_t step, Cnt& cnt, const BirthSink& sink) {
-  double x = p.x, y = p.y, z = p.z;
-  double vx = p.vx, vy = p.vy, vz = p.vz;
-  double3 a = F.accel(x, y, z);
-  float a_abs, da;
-  F.bound(x, y, z, sqrtf((float)(vx * vx + vy * vy + vz * vz)), (float)(dt - t), a_abs, da);
-  auto verlet = [&](double h) {
-    x += h * fma(0.5 * a.x, h, vx);
-    y += h * fma(0.5 * a.y, h, vy);
-    z += h * fma(0.5 * a.z, h, vz);
-    const double3 an = F.accel(x, y, z);
-    const double hh = 0.5 * h;
-    vx = fma(a.x + an.x, hh, vx);
-    vy = fma(a.y + an.y, hh, vy);
-    vz = fma(a.z + an.z, hh, vz);
-    a = an;
-  };
-  int result = 0;
-  for (uint32_t j = 0;; ++j) {
-    if (j >= (uint32_t)kMaxSegments) {
-      cnt.v[C_ERR]++;
-      result = 2;
-      break;
-    }
-    const uint4 r = draw(key, p.id, step, j, TAG_MAIN);
-    cnt.v[C_TRIALS]++;
-    const double t_rem = dt - t;
-    const float3 vf = make_float3((float)vx, (float)vy, (float)vz);
-    const float3 af = make_float3((float)a.x, (float)a.y, (float)a.z);
-    const float speed = sqrtf(vf.x * vf.x + vf.y * vf.y + vf.z * vf.z);
-    const float nu_full = majorant_t(T, S, speed_bound(vf, af, speed, a_abs, da, (float)t_rem));
-    const bool limited = kKappa < nu_full * (float)t_rem;
-    const double h = limited ? (double)(kKappa / nu_full) : t_rem;
-    const float nu_hat = limited ? majorant_t(T, S, speed_bound(vf, af, speed, a_abs, da, (float)h)) : nu_full;
-    const double tau = nu_hat > 0.0f ? (double)(-__logf(unif(r.x)) / nu_hat) : (double)INFINITY;
-    if (tau >= h) {  // no candidate collision within the horizon
-      verlet(h);
-      if (!limited) break;
-      t += h;
-      continue;
-    }
-    verlet(tau);
-    t += tau;
-    const double v2 = vx * vx + vy * vy + vz * vz;
-    const double eps = (double)S.k_eps_d * v2;
-    float u = __log2f((float)eps) * T.u_scale + T.u_offset;
-    u = fminf(fmaxf(u, 0.0f), (float)(T.n - 1));
-    const float fl = fminf(floorf(u), (float)(T.n - 2));
-    const int i = (int)fl;
-    const float f = u - fl;
-    const float yv = unif(r.y) * nu_hat;
-    float cum[kMaxProc];
-    cum_rates(T, i, f, cum);
-    const int k = pick_process(cum, yv);
-    if (k < 0 || eps < (double)T.thr[k]) {
-      cnt.v[C_NULL]++;
-      continue;
-    }
-    if (eps > (double)T.eps_max) cnt.v[C_OOT]++;
-    const int kind = T.kind[k];
-    // (register array: no dynamic index, which would move it to scratch)
-    cnt.v[C_EL] += kind == ELASTIC;
-    cnt.v[C_EXC] += kind == EXCITATION;
-    cnt.v[C_ION] += kind == IONIZATION;
-    cnt.v[C_ATT] += kind == ATTACHMENT;
-    if (kind == ATTACHMENT) {
-      result = 1;
-      break;
-    }
-    // cos(theta) = 1 - 2U; sin(theta) = 2 sqrt(U (1 - U)) avoids the
-    // cancellation of 1 - cos^2 near the poles (U and 1 - U are exact).
-    double nx, ny, nz;
-    iso_dir(r.z, r.w, nx, ny, nz);
-    double eps_new;
-    if (kind == ELASTIC) {
-      const double sc = sqrt(v2);
-      const double cchi = sc > 0.0 ? (vx * nx + vy * ny + vz * nz) / sc : 0.0;
-      eps_new = eps * (1.0 - (double)S.recoil * (1.0 - cchi));
-    } else if (kind == EXCITATION) {
-      eps_new = eps - (double)T.thr[k];
-    } else {
-      eps_new = 0.5 * (eps - (double)T.thr[k]);
-      const uint4 b = draw(key, p.id, step, j, TAG_BIRTH);
-      PState c;
-      c.x = (float)x;
-      c.y = (float)y;
-      c.z = (float)z;
-      c.w = p.w;
-      c.id = (uint64_t)b.x | ((uint64_t)b.y << 32);
-      double cx, cy, cz;
-      iso_dir(b.z, b.w, cx, cy, cz);
-      const double cs = sqrt(eps_new * S.inv_k_d);
-      c.vx = (float)(cs * cx);
-      c.vy = (float)(cs * cy);
-      c.vz = (float)(cs * cz);
-      sink.push(c, (float)t);
-    }
-    const double sn = sqrt(eps_new * S.inv_k_d);
-    vx = sn * nx;
-    vy = sn * ny;
-    vz = sn * nz;
-  }
-  p.x = (float)x;
-  p.y = (float)y;
-  p.z = (float)z;
-  p.vx = (float)vx;
-  p.vy = (float)vy;
-  p.vz = (float)vz;
-  p.xd = x;
-  p.yd = y;
-  p.zd = z;
-  return result;
 }
 
 // Inside the grid, judged on the double-precision end position.

@@ -26,17 +26,6 @@ namespace cg = cooperative_groups;
 
 namespace pcmcc {
 
-// Field of a swarm: uniform, along z.
-struct UniformField {
-  double az;
-  float a_abs;
-  __device__ __forceinline__ double3 accel(double, double, double) const { return make_double3(0.0, 0.0, az); }
-  __device__ __forceinline__ void bound(double, double, double, float, float, float& a, float& da) const {
-    a = a_abs;
-    da = 0.0f;
-  }
-};
-
 __device__ __forceinline__ Key swarm_key(Key k, int s) { return Key{k.k0, k.k1 ^ (uint32_t)s}; }
 
 // Group policy of the mover for swarms: the group is the swarm index.

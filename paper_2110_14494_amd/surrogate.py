@@ -43,7 +43,8 @@ class Norm:
 
 def dataset(EN_Td, values, errors, gas_N: float, max_rel_err: float = 0.1, norm: Norm | None = None,
             ln_floor: float = -200.0):
-    """Swarm results -> (x, t, mask, ln, norm) through pcmcc_mlp_dataset."""
+    """Swarm results -> (x, t, mask, ln, sig, norm) through pcmcc_mlp_dataset
+    (sig: the standard error of each ln value, NaN where masked)."""
     EN = np.ascontiguousarray(EN_Td, dtype=np.float64)
     n = EN.size
     res = (B.pcmcc_swarm_result * n)()
@@ -55,10 +56,11 @@ def dataset(EN_Td, values, errors, gas_N: float, max_rel_err: float = 0.1, norm:
     t = np.zeros((n, 6), np.float32)
     m = np.zeros((n, 6), np.float32)
     ln = np.zeros((n, 6), np.float32)
+    sig = np.zeros((n, 6), np.float32)
     B.check(B.lib().pcmcc_mlp_dataset(n, _vp(EN), res, float(gas_N), float(max_rel_err),
                                       0 if norm is not None else 1, C.byref(nm.opts), _vp(x), _vp(t), _vp(m),
-                                      _vp(ln), float(ln_floor)))
-    return x, t, m, ln, nm
+                                      _vp(ln), _vp(sig), float(ln_floor)))
+    return x, t, m, ln, sig, nm
 
 
 def grad(ctx, params, x, t, mask):
@@ -95,13 +97,14 @@ def infer(ctx, params, norm: Norm, EN: torch.Tensor, out: torch.Tensor | None = 
 
 
 def fallback(ctx, params, norm: Norm, EN_held, ln_held, mask_held, tol_ln: float, n_cells: int, cell_lo: float,
-             cell_hi: float):
+             cell_hi: float, sig_held=None, z_sig: float = 0.0):
     params = _f32(params)
     EN = np.ascontiguousarray(EN_held, dtype=np.float64)
     ln, m = _f32(ln_held), _f32(mask_held)
+    sig = None if sig_held is None else _f32(sig_held)
     fb = np.zeros(n_cells, np.uint8)
     err = np.zeros((EN.size, 6), np.float32)
     B.check(B.lib().pcmcc_mlp_fallback(ctx.h, _vp(params), C.byref(norm.opts), EN.size, _vp(EN), _vp(ln), _vp(m),
-                                       float(tol_ln), int(n_cells), float(cell_lo), float(cell_hi), _vp(fb),
-                                       _vp(err)), ctx.h)
+                                       None if sig is None else _vp(sig), float(tol_ln), float(z_sig), int(n_cells),
+                                       float(cell_lo), float(cell_hi), _vp(fb), _vp(err)), ctx.h)
     return fb, err

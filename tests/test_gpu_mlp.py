@@ -134,3 +134,36 @@ def test_fallback_cells_use_table(ctx):
     assert np.max(np.abs(got[sel] - interp[sel])) < 2e-4
     sel = ~use & ~edge
     assert np.array_equal(got[sel], plain[sel])
+
+
+def test_fallback_criterion_counts_monte_carlo_error(ctx):
+    # Held-out values planted around the surrogate's own outputs: per cell,
+    # inside the tolerance, inside tolerance + 3 sigma, beyond it, or masked.
+    from paper_2110_14494_amd import surrogate as S
+    from paper_2110_14494_amd import _binding as B
+    th = W.mlp_init(5).astype(np.float32).astype(np.float64)
+    o = B.pcmcc_mlp_infer_opts()
+    o.mu_x, o.sd_x = math.log(100.0), 1.3
+    o.mu_y[:], o.sd_y[:] = [0.5] * 6, [2.0] * 6
+    norm = S.Norm(o)
+    lo, hi, n_cells = math.log(10.0), math.log(1000.0), 16
+    w = (hi - lo) / n_cells
+    EN = np.exp(np.concatenate([lo + (np.arange(n_cells) + f) * w for f in (0.3, 0.7)]))
+    cell = np.concatenate([np.arange(n_cells)] * 2)
+    y, _ = S.infer(ctx, th, norm, torch.from_numpy(EN.astype(np.float32)).cuda())
+    y = y.cpu().numpy().T.astype(np.float64)
+    tol, z = 0.01, 3.0
+    sig = np.full((EN.size, 6), 0.02, np.float32)
+    cat = cell % 4
+    off = np.select([cat == 0, cat == 1, cat == 2], [0.5 * tol, tol + 0.5 * z * 0.02, tol + 1.5 * z * 0.02], 0.0)
+    sign = np.where(np.arange(EN.size) % 2 == 0, 1.0, -1.0)
+    ln = (y + (off * sign)[:, None]).astype(np.float32)
+    mask = np.ones((EN.size, 6), np.float32)
+    mask[cat == 3, 4] = 0.0
+    fb, err = S.fallback(ctx, th, norm, EN, ln, mask, tol, n_cells, lo, hi, sig_held=sig, z_sig=z)
+    assert np.array_equal(fb.astype(bool), np.isin(np.arange(n_cells) % 4, [2, 3]))
+    fb0, _ = S.fallback(ctx, th, norm, EN, ln, mask, tol, n_cells, lo, hi)
+    assert np.array_equal(fb0.astype(bool), np.isin(np.arange(n_cells) % 4, [1, 2, 3]))
+    ok = mask.astype(bool)
+    np.testing.assert_allclose(err[ok], np.broadcast_to(off[:, None], err.shape)[ok], atol=1e-5)
+    assert np.all(np.isnan(err[~ok]))

@@ -91,7 +91,7 @@ def test_library_dataset_construction():
     errs[5, 12] = 0.5 * vals[5, 12]  # eta unresolved: masked
     vals[7, 2] = np.nan
     N = 2.45e25
-    x, t, m, ln, norm = S.dataset(EN, vals, errs, N, max_rel_err=0.1)
+    x, t, m, ln, sig, norm = S.dataset(EN, vals, errs, N, max_rel_err=0.1)
     q = {k: i for i, k in enumerate(B.SWARM_QUANTITIES)}
     ref = np.stack([vals[:, q["mu"]] * N, vals[:, q["DL_flux"]] * N, vals[:, q["alpha"]] / N,
                     vals[:, q["eta"]] / N, vals[:, q["mean_eps"]], vals[:, q["bulk_flux_ratio"]]], axis=1)
@@ -108,3 +108,6 @@ def test_library_dataset_construction():
         np.testing.assert_allclose(t[ok[:, k], k], (col - o.mu_y[k]) / o.sd_y[k], rtol=1e-5, atol=1e-5)
     np.testing.assert_allclose(x, (np.log(EN) - o.mu_x) / o.sd_x, rtol=1e-6, atol=1e-6)
     assert np.all(ln[~ok] == -200.0)
+    # standard errors of the ln values: relative batch-means errors (1 %)
+    assert np.all(np.isnan(sig[~ok]))
+    np.testing.assert_allclose(sig[ok], 0.01, rtol=1e-6)
