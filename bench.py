@@ -34,17 +34,24 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Vector peak of MI355X: 256 CUs x 64 lanes x 2.4 GHz, an FMA counted as 2
-# operations (78.6 TFLOP/s; unpacked FP32 and FP64 issue at this rate).
-VALU_PEAK_OPS = 78.6e12
-# Algorithmic work: operations per flight segment and per
-# particle-step, and bytes per particle-step and per newborn.
-OPS_PER_TRIAL = 330.0
-OPS_PER_ITEM = 60.0
+# Vector issue peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane
+# issue slots per second (a wave64 instruction takes 4 cycles of a 16-lane
+# SIMD; unpacked FP32 and FP64 FMAs issue at this rate, as 78.6 TFLOP/s with
+# an FMA counted as 2 flops).
+VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
+# Algorithmic work of the step kernel in lane issue slots (an FMA is 1 slot, a
+# quarter-rate transcendental or 32x32->64 integer multiply is 4); the table
+# behind each figure is in the design notes.
+SLOTS_SEGMENT = 275.0    # every flight segment: Philox, speed bounds, majorants, tau, drift, gather, velocity
+SLOTS_CANDIDATE = 37.0   # a segment ending in a candidate collision: energy, table position, process choice
+SLOTS_REAL = 73.0        # a real collision: isotropic direction, recoil or threshold loss, new speed
+SLOTS_BIRTH = 160.0      # a newborn: its Philox draw, direction and speed
+SLOTS_PSTEP = 35.0       # a particle-step: start (conversions, field bound) and finish (domain test, stores)
 BYTES_PER_PSTEP = 72.0  # 36 B read + 36 B written
 BYTES_PER_BIRTH = 116.0  # queued (40 B), read back (40 B), written (36 B)
-KERNEL_SOURCES = ("paper_2110_14494_amd/csrc/pcmcc_kernels.hip", "paper_2110_14494_amd/csrc/pcmcc_mover.hpp",
-                  "paper_2110_14494_amd/csrc/pcmcc_device.hpp")
+KERNEL_SOURCES = ("paper_2110_14494_amd/csrc/pcmcc_kernels.hip", "paper_2110_14494_amd/csrc/pcmcc_flight.hpp",
+                  "paper_2110_14494_amd/csrc/pcmcc_mover.hpp", "paper_2110_14494_amd/csrc/pcmcc_device.hpp",
+                  "paper_2110_14494_amd/csrc/pcmcc_internal.hpp")
 
 
 def parse():
@@ -90,8 +97,9 @@ def source_hash() -> str:
 
 
 def measured_traffic():
-    """HBM bytes per particle-step of the step kernel from the committed
-    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    """HBM bytes per particle-step and VALU utilisation of the step kernel from
+    the committed rocprofv3 counter summary, if it was taken on the current
+    kernel source."""
     p = os.path.join(ROOT, "profiles", "k_pic_steps_traffic.json")
     try:
         d = json.load(open(p))
@@ -170,20 +178,27 @@ def pic_leg(a, ctx, pic):
     psteps = sum(s["particle_steps"] for s in stats)
     st = stats[-1]
     k_ms = float(np.mean([s["step_kernel_ms"] for s in stats]))
-    items = st["particle_steps"] + st["ionization"]
-    ops = OPS_PER_TRIAL * st["trials"] + OPS_PER_ITEM * items
+    real = st["elastic"] + st["excitation"] + st["ionization"] + st["attachment"]
+    ops = (SLOTS_SEGMENT * st["trials"] + SLOTS_CANDIDATE * (st["null"] + real) + SLOTS_REAL * real
+           + SLOTS_BIRTH * st["ionization"] + SLOTS_PSTEP * st["particle_steps"])
     bytes_alg = BYTES_PER_PSTEP * st["particle_steps"] + BYTES_PER_BIRTH * st["ionization"]
     achieved = ops / (k_ms * 1e-3) / 1e12
     tr = measured_traffic()
     traffic = None
     if tr is not None:
         traffic = (tr["fetch_bytes_per_pstep"] + tr["write_bytes_per_pstep"]) * st["particle_steps"]
-    roof = {"bound": "alu", "kernel": "k_pic_steps", "achieved": achieved, "peak": VALU_PEAK_OPS / 1e12,
-            "unit": "TFLOP/s", "frac": achieved * 1e12 / VALU_PEAK_OPS, "traffic": traffic,
-            "ops_per_launch": ops, "kernel_ms": k_ms,
+    roof = {"bound": "alu", "kernel": "k_pic_steps", "achieved": achieved, "peak": VALU_PEAK_SLOTS / 1e12,
+            "unit": "Tslot/s", "frac": achieved * 1e12 / VALU_PEAK_SLOTS, "traffic": traffic,
+            "slot": "one VALU lane issue slot (FMA = 1, quarter-rate op = 4)",
+            "slots_per_launch": ops, "kernel_ms": k_ms,
+            "segments_per_particle_step": st["trials"] / max(st["particle_steps"], 1),
+            "candidate_fraction": (st["null"] + real) / max(st["trials"], 1),
+            "real_fraction": real / max(st["trials"], 1),
             "hbm_algorithmic_GBs": bytes_alg / (k_ms * 1e-3) / 1e9,
             "hbm_frac": bytes_alg / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "hbm_measured_GBs": (traffic / (k_ms * 1e-3) / 1e9) if traffic else None,
+            "valu_issue_measured": tr.get("valu_issue") if tr else None,
+            "valu_active_lanes_measured": tr.get("valu_active_lanes") if tr else None,
             "deposit_ms": float(np.mean([s["deposit_kernel_ms"] for s in stats])),
             "deposit_GBs": (16.0 * st["n"] + 8.0 * rho.numel()) / (stats[-1]["deposit_kernel_ms"] * 1e-3) / 1e9}
     config = {"workload": cfg["name"], "n0": int(n0), "grid": int(cfg["grid"]["E"].shape[0]), "dt_s": cfg["dt"],
