@@ -61,7 +61,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", choices=["streamer", "stress", "plain"], default="streamer")
     ap.add_argument("--n", type=int, default=None, help="override the start count")
-    ap.add_argument("--cap-factor", type=int, default=32)
+    ap.add_argument("--cap-factor", type=int, default=None,
+                    help="capacity / start count (default 32 for streamer and plain, 8 for stress)")
+    ap.add_argument("--background", type=float, default=None, help="background field of the stress stage (V/m)")
     ap.add_argument("--max-steps", type=int, default=None, help="cap the committed steps (profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2 ** 23)
@@ -115,7 +117,7 @@ def make_cfg(a):
     if a.workload == "streamer":
         return W.streamer_config(n=a.n or 2 ** 24)
     if a.workload == "stress":
-        return W.stress_config(n=a.n or 2 ** 27)
+        return W.stress_config(background=a.background or 1.5e6, n=a.n or 2 ** 27)
     return W.plain_swarm_config(n=a.n or 10_000)
 
 
@@ -143,7 +145,7 @@ def pic_leg(a, ctx, pic):
     import torch
     cfg = make_cfg(a)
     n0 = cfg["parts"]["x"].size
-    cap = a.cap_factor * n0
+    cap = (a.cap_factor or (8 if a.workload == "stress" else 32)) * n0
     log(f"workload {cfg['name']} n0={n0} cap={cap}")
     ctx.setup(cfg["species"], cfg["tables"])
     pristine = pic.Particles.from_numpy(cfg["parts"], n0)

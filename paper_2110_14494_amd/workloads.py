@@ -142,8 +142,10 @@ def streamer_config(n: int = 2 ** 24, grid_n: int = 256, length: float = 10e-3, 
 def stress_config(background: float = 1.5e6, n: int = 2 ** 27, n_steps: int = 100) -> dict:
     """Large stress stage: 2^27 electrons on 512^3 cells of 20 um, tip field
     as the streamer stage at (0.5, 0.5, 0.8) of the cube, 100 steps of 1 ps."""
-    return streamer_config(n=n, grid_n=512, length=512 * 20e-6, background=background, dt=1e-12,
-                           n_steps=n_steps, pos_seed=2, weight_seed=3, seed=0)
+    cfg = streamer_config(n=n, grid_n=512, length=512 * 20e-6, background=background, dt=1e-12,
+                          n_steps=n_steps, pos_seed=2, weight_seed=3, seed=0)
+    cfg["name"] = f"stress-2^{int(np.log2(n))}-512c-bg{background / 1e6:g}MV/m"
+    return cfg
 
 
 def swarm_batch_config(n_swarms: int = 256, en_lo: float = 10.0, en_hi: float = 1000.0, seed: int = 1,

@@ -197,6 +197,39 @@ def test_ten_steps_streamer_field(pic):
     _assert_parity(g, o, cfg["grid"]["dx"], ost["trials"])
 
 
+def test_full_size_streamer_sampled_lineages(pic):
+    # The benchmark workload at full size (2^24 electrons, 256^3 cells) in the
+    # launch configuration the benchmark times.  An electron's lineage depends
+    # only on its own state and the field, so the oracle advances a sample of
+    # the start electrons and the GPU's full-size result is compared on the
+    # descendants of that sample (matched by id).  The deposit of the full
+    # result is checked for exact charge conservation.
+    cfg = W.streamer_config()
+    parts = cfg["parts"]
+    n = parts["x"].size
+    steps = 3
+    ctx = _ctx(pic, cfg["species"], cfg["tables"])
+    dp = pic.Particles.from_numpy(parts, 2 * n)
+    dg = pic.DeviceGrid(cfg["grid"])
+    rho = dg.zeros_rho()
+    print(f"[gpu] full-size streamer n={n} steps={steps}", flush=True)
+    rc, st = ctx.push_collide_deposit(dp, dg, cfg["dt"], steps, cfg["seed"], rho=rho)
+    assert rc == 0 and st["steps_done"] == steps
+    gpu = dp.to_numpy()
+    total = int(rho.sum().item())
+    ctx.close()
+    w2 = np.rint(np.ldexp(gpu["w"].astype(np.float64), 32)).astype(np.int64)
+    assert total == int(w2.sum())
+    sample = np.sort(np.random.default_rng(7).choice(n, 2 ** 13, replace=False))
+    sub = {k: v[sample] for k, v in parts.items()}
+    orc_rc, o, ost = oracle.pic_run(cfg["species"], cfg["tables"], cfg["grid"], sub, cfg["dt"], steps, cfg["seed"],
+                                    capacity=4 * sample.size)
+    assert orc_rc == 0 and ost["ionization"] > 0
+    sel = np.isin(gpu["id"], o["id"])
+    res = _assert_parity({k: v[sel] for k, v in gpu.items()}, o, cfg["grid"]["dx"], ost["trials"])
+    assert res["matched"] >= 0.999 * o["id"].size
+
+
 def test_attachment_dominated_hole_filling(pic):
     # Strong attachment, weak ionization: removed particles outnumber newborns,
     # so the tail fill path runs every step.
