@@ -270,6 +270,26 @@ def coef_leg(a, ctx, pic):
         _, ist = S.infer(ctx, params, norm_fb, EN_q, out)
     torch.cuda.synchronize()
     infer_s = (time.perf_counter() - t0) / reps
+    # the table path alone: every cell falls back to linear interpolation of a
+    # swarm table built from the training points only (resampled onto uniform
+    # nodes in ln(E/N)), timed like the surrogate and checked on the held-out
+    # points
+    ln_tr_m = np.where(m.astype(bool), ln_tr, np.nan)
+    nodes = np.linspace(lo, hi, 2048)
+    ln_en_tr = np.log(EN_all[train])
+    table_tr = np.stack([np.interp(nodes, ln_en_tr[np.isfinite(ln_tr_m[:, k])],
+                                   ln_tr_m[np.isfinite(ln_tr_m[:, k]), k]) for k in range(6)], axis=1)
+    norm_tab = norm.with_fallback(np.ones(256, np.uint8), lo, hi, table_tr.astype(np.float32), lo, hi)
+    S.infer(ctx, params, norm_tab, EN_q, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        S.infer(ctx, params, norm_tab, EN_q, out)
+    torch.cuda.synchronize()
+    table_s = (time.perf_counter() - t0) / reps
+    y_tab, _ = S.infer(ctx, params, norm_tab, torch.from_numpy(EN_all[held].astype(np.float32)).cuda())
+    e_tab = np.abs(y_tab.cpu().numpy().T - ln_h)
+    e_tab = np.where(m_h.astype(bool), e_tab, np.nan)
     e_ok = np.where(np.isfinite(err), err, np.nan)
     names = ("ln_muN", "ln_DLN", "ln_alpha_N", "ln_eta_N", "ln_mean_eps", "ln_bulk_flux")
     return {
@@ -283,6 +303,8 @@ def coef_leg(a, ctx, pic):
         "heldout_err_over_sigma_median": {k: float(np.nanmedian(e_ok[:, i] / sig_h[:, i]))
                                           for i, k in enumerate(names)},
         "tolerance_ln": tol, "tolerance_sigmas": z_sig, "cells": 256, "cells_fallback": int(fb.sum()),
+        "table_heldout_abs_ln_err_median": {k: float(np.nanmedian(e_tab[:, i])) for i, k in enumerate(names)},
+        "table_EN_points_per_s": a.infer_n / table_s,
         "infer_points": a.infer_n, "infer_s": infer_s, "infer_kernel_ms": ist["step_kernel_ms"],
         "surrogate_EN_points_per_s": a.infer_n / infer_s,
         "surrogate_over_plain_swarm": (a.infer_n / infer_s) / plain_pps,

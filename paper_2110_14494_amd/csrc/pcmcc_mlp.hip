@@ -287,40 +287,44 @@ __global__ __launch_bounds__(256) void k_mlp_infer(InferArgs A) {
     const float EN = valid ? A.EN[p] : 1.0f;
     const float lnEN = logf(EN);
     const float xs = (lnEN - A.mu_x) * A.inv_sd_x;
-    // layer 2: C2[m] = W2[32m.., :] h1 over 4 k-steps of 16
-    floatx16 c2[2];
-    for (int m = 0; m < 2; ++m)
-      for (int r = 0; r < 16; ++r) c2[m][r] = 0.0f;
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      bf16x8 b;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int k = 16 * s + 8 * half + q;
-        b[q] = (__bf16)tanh_fast(fmaf(L.w1[k], xs, L.b1[k]));
-      }
-      c2[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(L.A2[0][s][lane], b, c2[0], 0, 0, 0);
-      c2[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(L.A2[1][s][lane], b, c2[1], 0, 0, 0);
-    }
-    // bias + tanh; rows of C2 held by this lane: 8 i + 4 half + j (i = reg / 4, j = reg % 4)
+    const int cell = A.n_cells > 0 ? min(max((int)floorf((lnEN - A.cell_lo) * A.inv_cell_w), 0), A.n_cells - 1) : 0;
+    const bool fb = A.n_cells > 0 && A.fb_mask[cell];
     floatx16 c3;
     for (int r = 0; r < 16; ++r) c3[r] = 0.0f;
+    // The perceptron runs unless every point of the wave falls back to the
+    // table (the condition is wave-uniform, as the matrix instructions need).
+    if (__ballot(valid && !fb) != 0) {
+      // layer 2: C2[m] = W2[32m.., :] h1 over 4 k-steps of 16
+      floatx16 c2[2];
+      for (int m = 0; m < 2; ++m)
+        for (int r = 0; r < 16; ++r) c2[m][r] = 0.0f;
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int m = s >> 1;
-      bf16x8 b;
+      for (int s = 0; s < 4; ++s) {
+        bf16x8 b;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int i = 2 * (s & 1) + (q >> 2), j = q & 3;
-        const int row = 8 * i + 4 * half + j;
-        b[q] = (__bf16)tanh_fast(c2[m][4 * i + j] + L.b2[32 * m + row]);
+        for (int q = 0; q < 8; ++q) {
+          const int k = 16 * s + 8 * half + q;
+          b[q] = (__bf16)tanh_fast(fmaf(L.w1[k], xs, L.b1[k]));
+        }
+        c2[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(L.A2[0][s][lane], b, c2[0], 0, 0, 0);
+        c2[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(L.A2[1][s][lane], b, c2[1], 0, 0, 0);
       }
-      c3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(L.A3[s][lane], b, c3, 0, 0, 0);
+      // bias + tanh; rows of C2 held by this lane: 8 i + 4 half + j (i = reg / 4, j = reg % 4)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int m = s >> 1;
+        bf16x8 b;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int i = 2 * (s & 1) + (q >> 2), j = q & 3;
+          const int row = 8 * i + 4 * half + j;
+          b[q] = (__bf16)tanh_fast(c2[m][4 * i + j] + L.b2[32 * m + row]);
+        }
+        c3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(L.A3[s][lane], b, c3, 0, 0, 0);
+      }
     }
     if (!valid) continue;
     // outputs: rows 4 half + j (j < 4) of C3 are outputs 0..3 (half 0) and 4..7 (half 1)
-    const int cell = A.n_cells > 0 ? min(max((int)floorf((lnEN - A.cell_lo) * A.inv_cell_w), 0), A.n_cells - 1) : 0;
-    const bool fb = A.n_cells > 0 && A.fb_mask[cell];
     float tf = 0.0f;
     int ti = 0;
     if (fb) {
