@@ -48,7 +48,7 @@ constexpr int kRefillMin = 24;    // free lanes that trigger a finish-and-refill
 // its list full (more than kStage - kFlushAt events of one wave in one
 // iteration) takes the direct path with its own atomic.
 constexpr uint32_t kStage = 64;
-constexpr uint32_t kFlushAt = 32;
+constexpr uint32_t kFlushAt = 48;  // (tuned: 32 -> 670 ms, 48 -> 657 ms per streamer call)
 
 struct WaveStage {
   // newborns as their parent left them: x, y, z, w, birth time; segment
