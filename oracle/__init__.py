@@ -69,7 +69,10 @@ def lib():
             L.orc_build_tables.argtypes = [C.POINTER(Problem), vp, vp, vp, vp]
             L.orc_lookup.argtypes = [C.POINTER(Problem), C.c_int64, vp, vp, vp, vp]
             L.orc_pic_run.argtypes = [C.POINTER(Problem), C.POINTER(Grid)] + [vp] * 8 + [
-                vp, C.c_int64, C.c_double, C.c_int, C.c_uint64, C.c_uint64, vp, C.c_int]
+                vp, C.c_int64, C.c_double, C.c_int, C.c_uint64, C.c_uint64, vp, C.c_int, C.c_double, C.c_double,
+                vp, vp]
+            L.orc_update_weights.argtypes = [vp] * 8 + [C.c_int64, C.c_int, C.c_int, C.c_int] + [C.c_double] * 5 + [
+                C.c_uint64, C.c_uint64] + [vp] * 8 + [C.c_int64, vp, vp]
             L.orc_deposit.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_int, C.c_int, C.c_int,
                                       C.c_double, C.c_double, C.c_double, C.c_double, vp]
             L.orc_swarm_run.argtypes = [C.POINTER(Problem), C.c_int, vp, vp, C.c_double, C.c_int,
@@ -162,10 +165,14 @@ def lookup(species: dict, tables: dict, eps, s_ub=None):
 
 
 def pic_run(species: dict, tables: dict, grid: dict, parts: dict, dt: float, n_steps: int,
-            seed: int, step0: int = 0, capacity: int | None = None, n_threads: int = 0):
+            seed: int, step0: int = 0, capacity: int | None = None, n_threads: int = 0, n_ppc: float = 0.0,
+            growth: float = 1.25, n_ref: int = 0):
     """Runs the PIC-MCC update on a copy of `parts` (x, y, z, vx, vy, vz, w, id).
 
-    Returns (rc, parts_out, stats) with parts_out in double precision."""
+    With n_ppc > 0 the super-particle weights are updated whenever the count
+    exceeds floor(growth * n_ref) after a step (n_ref = 0: the start count).
+    Returns (rc, parts_out, stats) with parts_out in double precision; stats
+    also holds weight_updates, merged_pairs, splits and n_ref."""
     pb, k1 = make_problem(species, tables)
     g, k2 = make_grid(grid)
     n = int(np.asarray(parts["x"]).size)
@@ -179,15 +186,45 @@ def pic_run(species: dict, tables: dict, grid: dict, parts: dict, dt: float, n_s
     ids[:n] = np.asarray(parts["id"], dtype=np.uint64)
     n_io = C.c_int64(n)
     stats = np.zeros(12, dtype=np.int64)
+    wstats = np.zeros(3, dtype=np.int64)
+    nref = C.c_int64(int(n_ref))
     rc = lib().orc_pic_run(C.byref(pb), C.byref(g), *[_ptr(arrs[k]) for k in
                                                      ("x", "y", "z", "vx", "vy", "vz", "w")],
                            _ptr(ids), C.byref(n_io), cap, float(dt), int(n_steps), int(seed),
-                           int(step0), _ptr(stats), int(n_threads))
+                           int(step0), _ptr(stats), int(n_threads), float(n_ppc), float(growth), C.byref(nref),
+                           _ptr(wstats))
     del k1, k2
     m = n_io.value
     out = {k: v[:m].copy() for k, v in arrs.items()}
     out["id"] = ids[:m].copy()
-    return rc, out, dict(zip(STATS_FIELDS, (int(s) for s in stats)))
+    st = dict(zip(STATS_FIELDS, (int(s) for s in stats)))
+    st.update(weight_updates=int(wstats[0]), merged_pairs=int(wstats[1]), splits=int(wstats[2]), n_ref=nref.value)
+    return rc, out, st
+
+
+def update_weights(parts: dict, grid: dict, n_ppc: float, seed: int, update_index: int,
+                   capacity: int | None = None):
+    """Super-particle weight update (Sec. 2.1.2) of single-precision particle
+    arrays on the grid; returns (rc, parts_out, counts) with counts =
+    {merged_pairs, splits}."""
+    n = int(np.asarray(parts["x"]).size)
+    cap = int(capacity if capacity is not None else 2 * n + 16)
+    ins = [np.ascontiguousarray(parts[k], dtype=np.float32) for k in ("x", "y", "z", "vx", "vy", "vz", "w")]
+    ids = np.ascontiguousarray(parts["id"], dtype=np.uint64)
+    outs = [np.zeros(cap, dtype=np.float32) for _ in range(7)]
+    oid = np.zeros(cap, dtype=np.uint64)
+    E = np.asarray(grid["E"])
+    nz, ny, nx = E.shape[:3]
+    n_out = C.c_int64(0)
+    counts = np.zeros(2, dtype=np.int64)
+    rc = lib().orc_update_weights(*[_ptr(a) for a in ins], _ptr(ids), n, nx, ny, nz, float(grid["x0"]),
+                                  float(grid["y0"]), float(grid["z0"]), float(grid["dx"]), float(n_ppc), int(seed),
+                                  int(update_index), *[_ptr(a) for a in outs], _ptr(oid), cap, C.byref(n_out),
+                                  _ptr(counts))
+    m = min(n_out.value, cap)
+    out = {k: a[:m].copy() for k, a in zip(("x", "y", "z", "vx", "vy", "vz", "w"), outs)}
+    out["id"] = oid[:m].copy()
+    return rc, out, {"merged_pairs": int(counts[0]), "splits": int(counts[1])}
 
 
 def deposit(x, y, z, w, grid: dict) -> np.ndarray:

@@ -34,6 +34,9 @@
 #include <omp.h>
 #endif
 
+int orc_deposit_impl(const float* x, const float* y, const float* z, const float* w, int64_t n, int nx, int ny,
+                     int nz, double x0, double y0, double z0, double inv_dx, int64_t* rho);
+
 namespace {
 
 constexpr double kEV = 1.602176634e-19;  // J per eV (exact SI value)
@@ -41,7 +44,7 @@ constexpr double kPI = 3.14159265358979323846;
 
 enum Kind { ELASTIC = 0, EXCITATION = 1, IONIZATION = 2, ATTACHMENT = 3 };
 enum Flags { EFFECTIVE_TO_ELASTIC = 1, RATES = 2 };
-enum Tag { TAG_MAIN = 0, TAG_BIRTH = 1, TAG_AUX = 2 };
+enum Tag { TAG_MAIN = 0, TAG_BIRTH = 1, TAG_AUX = 2, TAG_WEIGHT = 3 };
 
 // Upper limit on flight segments of one particle within one step; a particle
 // reaching it is dropped and counted as an error (guards a runaway loop).
@@ -513,6 +516,117 @@ void run_step(const Tables& T, const Species& S, const Accel& accel, const std::
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Super-particle weights (Sec. 2.1.2).  The desired weight of cell c is
+// omega_c = n_e dV / N_ppc with n_e dV the number of electrons the charge
+// mapping puts on the cell (the CIC density, Sec. 2.1.3, in units of
+// electrons) and omega_min = 1.  Particles in a cell with w < (2/3) omega are
+// merged pairwise, pairs formed from particles close in energy; particles with
+// w > (3/2) omega are split into two halves.  Readings where the paper is
+// silent:
+//   * the cell of a particle is the one containing it (floor of (x - x0)/dx,
+//     clamped to the grid);
+//   * "close in energy": the merge candidates of a cell are ordered by energy
+//     (|v|^2 rounded to single precision), then by id, and consecutive ones
+//     are paired; an odd one out stays as it is;
+//   * the merged particle keeps the position, velocity and id of one of the
+//     two, the first with probability w_a / (w_a + w_b) (so position and
+//     momentum are conserved on average), drawn from the weight-update draw
+//     of the smaller id; its weight is w_a + w_b;
+//   * a split halves the weight once per update and adds a copy with the same
+//     position and velocity; the copy's id is the (second, third) words of the
+//     particle's weight-update draw;
+//   * weight-update draws: counter (id, update index, 0, purpose 3).
+struct WeightCounts {
+  int64_t merged_pairs = 0, splits = 0;
+};
+
+int cell_of(double x, double o, double inv_dx, int n) {
+  int i = (int)std::floor((x - o) * inv_dx);
+  return std::min(std::max(i, 0), n - 1);
+}
+
+void update_weights(std::vector<Particle>& ps, int nx, int ny, int nz, double x0, double y0, double z0, double inv_dx,
+                    double n_ppc, uint32_t key0, uint32_t key1, uint64_t update_index, WeightCounts& wc) {
+  const size_t n = ps.size();
+  const size_t ncell = (size_t)nx * ny * nz;
+  std::vector<float> fx(n), fy(n), fz(n), fw(n);
+  for (size_t i = 0; i < n; ++i) {
+    fx[i] = (float)ps[i].x[0];
+    fy[i] = (float)ps[i].x[1];
+    fz[i] = (float)ps[i].x[2];
+    fw[i] = (float)ps[i].w;
+  }
+  std::vector<int64_t> rho(ncell, 0);
+  orc_deposit_impl(fx.data(), fy.data(), fz.data(), fw.data(), (int64_t)n, nx, ny, nz, x0, y0, z0, inv_dx, rho.data());
+  std::vector<int64_t> cell(n);
+  std::vector<int> cls(n, 0);  // 0 keep, 1 merge candidate, 2 split
+  std::vector<size_t> cand;
+  for (size_t i = 0; i < n; ++i) {
+    const Particle& p = ps[i];
+    const size_t c = ((size_t)cell_of(p.x[2], z0, inv_dx, nz) * ny + cell_of(p.x[1], y0, inv_dx, ny)) * nx +
+                     cell_of(p.x[0], x0, inv_dx, nx);
+    cell[i] = (int64_t)c;
+    const double omega = std::max(std::ldexp((double)rho[c], -32) / n_ppc, 1.0);
+    if (p.w < (2.0 / 3.0) * omega) {
+      cls[i] = 1;
+      cand.push_back(i);
+    } else if (p.w > 1.5 * omega) {
+      cls[i] = 2;
+    }
+  }
+  auto ekey = [&](size_t i) {
+    const Particle& p = ps[i];
+    return (float)((p.v[0] * p.v[0] + p.v[1] * p.v[1]) + p.v[2] * p.v[2]);
+  };
+  std::sort(cand.begin(), cand.end(), [&](size_t a, size_t b) {
+    if (cell[a] != cell[b]) return cell[a] < cell[b];
+    const float ea = ekey(a), eb = ekey(b);
+    if (ea != eb) return ea < eb;
+    return ps[a].id < ps[b].id;
+  });
+  std::vector<char> removed(n, 0);
+  size_t k = 0;
+  while (k < cand.size()) {
+    size_t e = k;
+    while (e < cand.size() && cell[cand[e]] == cell[cand[k]]) ++e;
+    for (size_t q = k; q + 1 < e; q += 2) {
+      Particle& a = ps[cand[q]];
+      Particle& b = ps[cand[q + 1]];
+      const Draw d = draw(key0, key1, std::min(a.id, b.id), update_index, 0, TAG_WEIGHT);
+      const double pa = a.w / (a.w + b.w);
+      const double wsum = (double)(float)(a.w + b.w);
+      if (unif(d.r[0]) < pa) {
+        a.w = wsum;
+        removed[cand[q + 1]] = 1;
+      } else {
+        b.w = wsum;
+        removed[cand[q]] = 1;
+      }
+      ++wc.merged_pairs;
+    }
+    k = e;
+  }
+  std::vector<Particle> out;
+  out.reserve(n + n / 4);
+  std::vector<Particle> copies;
+  for (size_t i = 0; i < n; ++i) {
+    if (removed[i]) continue;
+    Particle p = ps[i];
+    if (cls[i] == 2) {
+      p.w = 0.5 * p.w;
+      const Draw d = draw(key0, key1, p.id, update_index, 0, TAG_WEIGHT);
+      Particle c = p;
+      c.id = (uint64_t)d.r[1] | ((uint64_t)d.r[2] << 32);
+      copies.push_back(c);
+      ++wc.splits;
+    }
+    out.push_back(p);
+  }
+  out.insert(out.end(), copies.begin(), copies.end());
+  ps.swap(out);
+}
+
 extern "C" {
 
 void orc_set_constant_majorant(int on) { g_constant_majorant = on; }
@@ -561,9 +675,15 @@ int orc_lookup(const orc_problem* pb, int64_t m, const double* eps, double* C_ou
 // in double precision; arrays have room for `capacity` particles).  Stats
 // layout: n, steps_done, particle_steps, trials, null, elastic, excitation,
 // ionization, attachment, lost, out_of_table, errors.
+// Weight control (n_ppc > 0): after a committed step s, if the particle count
+// exceeds floor(growth * n_ref), the weights are updated with update index
+// step0 + s and n_ref becomes the new count; n_ref (in/out) starts at the
+// count of the first call when 0.  wstats (nullable) receives the number of
+// updates, merged pairs and splits.
 int orc_pic_run(const orc_problem* pb, const orc_grid* g, double* x, double* y, double* z, double* vx, double* vy,
                 double* vz, double* w, uint64_t* id, int64_t* n_inout, int64_t capacity, double dt, int n_steps,
-                uint64_t seed, uint64_t step0, int64_t* stats, int n_threads) {
+                uint64_t seed, uint64_t step0, int64_t* stats, int n_threads, double n_ppc, double growth,
+                int64_t* n_ref, int64_t* wstats) {
   Species S;
   Tables T;
   int rc = build_tables(pb, S, T);
@@ -627,6 +747,9 @@ int orc_pic_run(const orc_problem* pb, const orc_grid* g, double* x, double* y, 
   Counters total;
   int64_t steps_done = 0, particle_steps = 0;
   const uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
+  WeightCounts wc;
+  int64_t updates = 0;
+  int64_t nref = n_ref && *n_ref > 0 ? *n_ref : (int64_t)cur.size();
   rc = 0;
   for (int s = 0; s < n_steps; ++s) {
     Counters cnt;
@@ -639,6 +762,21 @@ int orc_pic_run(const orc_problem* pb, const orc_grid* g, double* x, double* y, 
     cur.swap(nxt);
     total.add(cnt);
     ++steps_done;
+    if (n_ppc > 0 && (int64_t)cur.size() > (int64_t)std::floor(growth * (double)nref)) {
+      update_weights(cur, g->nx, g->ny, g->nz, g->x0, g->y0, g->z0, 1.0 / g->dx, n_ppc, key0, key1, step0 + s, wc);
+      if ((int64_t)cur.size() > capacity) {
+        rc = -2;
+        break;
+      }
+      nref = (int64_t)cur.size();
+      ++updates;
+    }
+  }
+  if (n_ref) *n_ref = nref;
+  if (wstats) {
+    wstats[0] = updates;
+    wstats[1] = wc.merged_pairs;
+    wstats[2] = wc.splits;
   }
   for (size_t i = 0; i < cur.size(); ++i) {
     const Particle& p = cur[i];
@@ -668,6 +806,13 @@ int orc_pic_run(const orc_problem* pb, const orc_grid* g, double* x, double* y, 
 // charge w * 2^32 is conserved exactly.  Indices are clamped (folded back).
 int orc_deposit(const float* x, const float* y, const float* z, const float* w, int64_t n, int nx, int ny, int nz,
                 double x0, double y0, double z0, double inv_dx, int64_t* rho) {
+  return orc_deposit_impl(x, y, z, w, n, nx, ny, nz, x0, y0, z0, inv_dx, rho);
+}
+
+}  // extern "C"
+
+int orc_deposit_impl(const float* x, const float* y, const float* z, const float* w, int64_t n, int nx, int ny,
+                     int nz, double x0, double y0, double z0, double inv_dx, int64_t* rho) {
   const int nn[3] = {nx, ny, nz};
   const double o[3] = {x0, y0, z0};
   for (int64_t p = 0; p < n; ++p) {
@@ -706,6 +851,8 @@ int orc_deposit(const float* x, const float* y, const float* z, const float* w, 
   }
   return 0;
 }
+
+extern "C" {
 
 // Uniform-field swarms (Sec. 2.2.1): swarm s starts with n0[s] electrons at
 // rest at the origin in a field E = (E/N) N along +z and is advanced n_steps
@@ -831,6 +978,50 @@ int orc_swarm_run(const orc_problem* pb, int n_swarms, const double* EN_Td, cons
     std::memcpy(stats, v, sizeof(v));
   }
   return err;
+}
+
+// Weight update of n particles (single-precision arrays) on the grid
+// (nx, ny, nz, x0, y0, z0, dx); the result (at most `capacity` particles,
+// input order with removed particles dropped, split copies appended) goes to
+// the *_out arrays.  counts (nullable) = merged pairs, splits.  Returns -2
+// when the result exceeds the capacity.
+int orc_update_weights(const float* x, const float* y, const float* z, const float* vx, const float* vy,
+                       const float* vz, const float* w, const uint64_t* id, int64_t n, int nx, int ny, int nz, double x0,
+                       double y0, double z0, double dx, double n_ppc, uint64_t seed, uint64_t update_index,
+                       float* x_out, float* y_out, float* z_out, float* vx_out, float* vy_out, float* vz_out,
+                       float* w_out, uint64_t* id_out, int64_t capacity, int64_t* n_out, int64_t* counts) {
+  if (n < 0 || nx < 1 || ny < 1 || nz < 1 || !(dx > 0) || !(n_ppc > 0)) return -1;
+  std::vector<Particle> ps((size_t)n);
+  for (int64_t i = 0; i < n; ++i) {
+    ps[i].x[0] = x[i];
+    ps[i].x[1] = y[i];
+    ps[i].x[2] = z[i];
+    ps[i].v[0] = vx[i];
+    ps[i].v[1] = vy[i];
+    ps[i].v[2] = vz[i];
+    ps[i].w = w[i];
+    ps[i].id = id[i];
+  }
+  WeightCounts wc;
+  update_weights(ps, nx, ny, nz, x0, y0, z0, 1.0 / dx, n_ppc, (uint32_t)seed, (uint32_t)(seed >> 32), update_index,
+                 wc);
+  if (counts) {
+    counts[0] = wc.merged_pairs;
+    counts[1] = wc.splits;
+  }
+  *n_out = (int64_t)ps.size();
+  if ((int64_t)ps.size() > capacity) return -2;
+  for (size_t i = 0; i < ps.size(); ++i) {
+    x_out[i] = (float)ps[i].x[0];
+    y_out[i] = (float)ps[i].x[1];
+    z_out[i] = (float)ps[i].x[2];
+    vx_out[i] = (float)ps[i].v[0];
+    vy_out[i] = (float)ps[i].v[1];
+    vz_out[i] = (float)ps[i].v[2];
+    w_out[i] = (float)ps[i].w;
+    id_out[i] = ps[i].id;
+  }
+  return 0;
 }
 
 }  // extern "C"
