@@ -101,6 +101,10 @@ typedef struct pcmcc_stats {
   double deposit_kernel_ms;      /* device time of the deposit kernel, 0 if skipped */
   int32_t launch_block;          /* threads per block of the step loop kernel */
   int32_t launch_grid;           /* blocks of the step loop kernel */
+  int64_t weight_updates;        /* super-particle weight updates within the call (weight control) */
+  int64_t merged_pairs;          /* pairs merged by those updates */
+  int64_t splits;                /* particles split by those updates */
+  double weight_ms;              /* device time of those updates */
 } pcmcc_stats;
 
 /* Version string, static storage. */
@@ -305,6 +309,35 @@ int pcmcc_mlp_fallback(pcmcc_ctx* ctx, const float* params, const pcmcc_mlp_infe
                        const double* EN_held, const float* ln_held, const float* mask_held, const float* sig_held,
                        double tol_ln, double z_sig, int n_cells, double cell_lo, double cell_hi,
                        uint8_t* fallback_out, float* err_out);
+
+/* ---- Super-particle weights (Sec. 2.1.2) --------------------------------
+ * Desired weight of a cell: omega = n_e dV / n_ppc, n_e dV being the electrons
+ * the CIC mapping puts on the cell, and at least 1.  Particles in a cell with
+ * w < (2/3) omega are merged pairwise: the candidates of a cell are ordered
+ * by |v|^2 (rounded to single precision), then by id, consecutive ones are
+ * paired and the pair becomes one particle of weight w_a + w_b with the
+ * position, velocity and id of the first with probability w_a / (w_a + w_b),
+ * else of the second (an odd one out is left as it is).  Particles with
+ * w > (3/2) omega are halved and copied (same position and velocity).
+ * Random numbers: Philox4x32-10 keyed by `seed`, counter (id, update_index,
+ * 0, purpose 3) — the smaller id of a pair decides the merge, a split copy's
+ * id is the second and third words of its particle's draw.  The result does
+ * not depend on the array order (the order on return is unspecified). */
+
+/* Enables (n_ppc > 0) or disables (n_ppc = 0) weight control in
+ * pcmcc_push_collide_deposit: after a committed step whose particle count
+ * exceeds floor(growth * n_ref), the weights are updated with update_index =
+ * the absolute index of that step, and n_ref becomes the new count; n_ref is
+ * the count at the start of the first call after this one, and is kept across
+ * calls.  growth >= 1 (the paper uses 1.25). */
+int pcmcc_set_weight_control(pcmcc_ctx* ctx, double n_ppc, double growth);
+
+/* One weight update of the device particles p (in place, *p->n_dev updated)
+ * on `grid` (only its geometry is used).  merged_pairs and splits (host,
+ * nullable) receive the counts.  PCMCC_ECAPACITY (particles unchanged) if the
+ * result exceeds p->capacity.  Synchronises the stream. */
+int pcmcc_update_weights(pcmcc_ctx* ctx, const pcmcc_particles* p, const pcmcc_grid* grid, double n_ppc,
+                         uint64_t seed, uint64_t update_index, int64_t* merged_pairs, int64_t* splits);
 
 /* Deposit only (Sec. 2.1.3), same fixed-point rule as above, on n_dev
  * particles (device count) of device arrays x, y, z, w. */

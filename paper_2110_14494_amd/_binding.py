@@ -37,7 +37,8 @@ class pcmcc_stats(C.Structure):
                 ("trials", C.c_uint64), ("null_collisions", C.c_uint64),
                 ("real_collisions", C.c_uint64 * 4), ("lost", C.c_uint64), ("out_of_table", C.c_uint64),
                 ("errors", C.c_uint64), ("step_kernel_ms", C.c_double), ("deposit_kernel_ms", C.c_double),
-                ("launch_block", C.c_int32), ("launch_grid", C.c_int32)]
+                ("launch_block", C.c_int32), ("launch_grid", C.c_int32), ("weight_updates", C.c_int64),
+                ("merged_pairs", C.c_int64), ("splits", C.c_int64), ("weight_ms", C.c_double)]
 
     def as_dict(self) -> dict:
         r = list(self.real_collisions)
@@ -46,7 +47,9 @@ class pcmcc_stats(C.Structure):
                 "ionization": r[2], "attachment": r[3], "lost": self.lost,
                 "out_of_table": self.out_of_table, "errors": self.errors,
                 "step_kernel_ms": self.step_kernel_ms, "deposit_kernel_ms": self.deposit_kernel_ms,
-                "launch_block": self.launch_block, "launch_grid": self.launch_grid}
+                "launch_block": self.launch_block, "launch_grid": self.launch_grid,
+                "weight_updates": self.weight_updates, "merged_pairs": self.merged_pairs, "splits": self.splits,
+                "weight_ms": self.weight_ms}
 
 
 SWARM_QUANTITIES = ("W_flux", "W_bulk", "DL_flux", "DL_bulk", "DT_flux", "DT_bulk", "nu_ion", "nu_att",
@@ -120,6 +123,9 @@ def lib() -> C.CDLL:
                                    C.POINTER(pcmcc_mlp_infer_opts), vp, vp, vp, vp, vp, C.c_double], C.c_int),
             "pcmcc_mlp_fallback": ([vp, vp, C.POINTER(pcmcc_mlp_infer_opts), C.c_int, vp, vp, vp, vp, C.c_double,
                                     C.c_double, C.c_int, C.c_double, C.c_double, vp, vp], C.c_int),
+            "pcmcc_set_weight_control": ([vp, C.c_double, C.c_double], C.c_int),
+            "pcmcc_update_weights": ([vp, C.POINTER(pcmcc_particles), C.POINTER(pcmcc_grid), C.c_double, u64, u64,
+                                      C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int),
             "pcmcc_swarm_batch": ([vp, C.c_int, vp, vp, C.c_double, C.c_int, u64, C.POINTER(pcmcc_swarm_opts),
                                    vp, vp, vp, C.POINTER(pcmcc_stats)], C.c_int),
         }

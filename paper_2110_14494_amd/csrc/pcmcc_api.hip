@@ -70,6 +70,14 @@ struct pcmcc_ctx {
   uint64_t dep_tiles = 0, dep_dump = 0, dep_sorted = 0;
   unsigned* emax_bits = nullptr;
   int64_t* host_n = nullptr;  // pinned
+  // super-particle weights: control settings, update buffers
+  double wc_n_ppc = 0, wc_growth = 1.25;
+  int64_t wc_n_ref = 0;
+  WeightWork wt{};
+  uint64_t wt_n = 0;
+  int64_t* wt_rho = nullptr;
+  size_t wt_cells = 0;
+  int64_t* dev_n = nullptr;  // a device count for the deposit of the update
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   // swarm batch scratch
   struct Swarm {
@@ -406,6 +414,73 @@ int run_deposit(pcmcc_ctx* c, const float* x, const float* y, const float* z, co
   return PCMCC_OK;
 }
 
+// Buffers of the weight update for n particles on `ncell` cells.
+int ensure_weights(pcmcc_ctx* c, uint64_t n, size_t ncell) {
+  if (c->wt_n < n) {
+    dfree(c->wt.cls);
+    dfree(c->wt.idx0);
+    dfree(c->wt.idx1);
+    dfree(c->wt.key0);
+    dfree(c->wt.key1);
+    dfree(c->wt.pos);
+    dfree(c->wt.cnt);
+    dfree(c->wt.temp);
+    c->wt = WeightWork{};
+    c->wt_n = 0;
+    size_t tb = 0;
+    HIP_TRY(c, weight_temp_bytes(n, &tb));
+    if (dalloc(&c->wt.cls, n) != hipSuccess || dalloc(&c->wt.idx0, n) != hipSuccess ||
+        dalloc(&c->wt.idx1, n) != hipSuccess || dalloc(&c->wt.key0, n) != hipSuccess ||
+        dalloc(&c->wt.key1, n) != hipSuccess || dalloc(&c->wt.pos, n) != hipSuccess ||
+        dalloc(&c->wt.cnt, n) != hipSuccess || dalloc(&c->wt.counters, 4) != hipSuccess ||
+        hipMalloc(&c->wt.temp, std::max<size_t>(tb, 16)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(c, PCMCC_ENOMEM, "cannot allocate weight-update buffers for %llu particles", (unsigned long long)n);
+    }
+    c->wt.temp_bytes = std::max<size_t>(tb, 16);
+    c->wt_n = n;
+  }
+  if (c->wt_cells < ncell) {
+    dfree(c->wt_rho);
+    c->wt_rho = nullptr;
+    c->wt_cells = 0;
+    if (dalloc(&c->wt_rho, ncell) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(c, PCMCC_ENOMEM, "cannot allocate the weight-update density grid");
+    }
+    c->wt_cells = ncell;
+  }
+  if (!c->dev_n) HIP_TRY(c, dalloc(&c->dev_n, 1));
+  return PCMCC_OK;
+}
+
+// Weight update of the n particles of `cur` into `out` (at most capacity):
+// density of `cur` on the grid, then the update.  *n_new = the new count
+// (nothing is written to `out` when it exceeds the capacity: ECAPACITY).
+int weight_update(pcmcc_ctx* c, const Soa& cur, const Soa& out, uint64_t n, const pcmcc_grid* g, double n_ppc,
+                  uint64_t seed, uint64_t update_index, uint64_t capacity, uint64_t* n_new, uint64_t* pairs,
+                  uint64_t* splits) {
+  *n_new = n;
+  *pairs = *splits = 0;
+  if (n == 0) return PCMCC_OK;
+  const size_t ncell = (size_t)g->nx * g->ny * g->nz;
+  int rc = ensure_weights(c, n, ncell);
+  if (rc) return rc;
+  HIP_TRY(c, hipMemsetAsync(c->wt_rho, 0, ncell * sizeof(int64_t), c->stream));
+  const int64_t nn = (int64_t)n;
+  HIP_TRY(c, hipMemcpyAsync(c->dev_n, &nn, sizeof(nn), hipMemcpyHostToDevice, c->stream));
+  rc = run_deposit(c, cur.x, cur.y, cur.z, cur.w, c->dev_n, n, g, c->wt_rho);
+  if (rc) return rc;
+  WeightGeom wg{g->nx, g->ny, g->nz, g->x0, g->y0, g->z0, 1.0 / g->dx, n_ppc, 1, capacity};
+  while (wg.cell_bits < 31 && ((uint64_t)1 << wg.cell_bits) < ncell) ++wg.cell_bits;
+  HIP_TRY(c, launch_weight_update(cur, out, n, wg, c->wt_rho, Key{(uint32_t)seed, (uint32_t)(seed >> 32)},
+                                  (uint32_t)update_index, c->wt, n_new, pairs, splits, c->stream));
+  if (*n_new > capacity)
+    return fail(c, PCMCC_ECAPACITY, "weight update needs %llu slots, capacity %llu", (unsigned long long)*n_new,
+                (unsigned long long)capacity);
+  return PCMCC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -468,6 +543,17 @@ int pcmcc_destroy(pcmcc_ctx* c) {
   dfree(c->dep.tile_start);
   dfree(c->dep.dump);
   dfree(c->dep.sorted);
+  dfree(c->wt.cls);
+  dfree(c->wt.idx0);
+  dfree(c->wt.idx1);
+  dfree(c->wt.key0);
+  dfree(c->wt.key1);
+  dfree(c->wt.pos);
+  dfree(c->wt.cnt);
+  dfree(c->wt.counters);
+  dfree(c->wt.temp);
+  dfree(c->wt_rho);
+  dfree(c->dev_n);
   dfree(c->emax_bits);
   if (c->host_ctl) (void)hipHostFree(c->host_ctl);
   if (c->host_n) (void)hipHostFree(c->host_n);
@@ -627,17 +713,64 @@ int pcmcc_push_collide_deposit(pcmcc_ctx* c, const pcmcc_particles* p, const pcm
   G.hi[2] = field->z0 + field->nz * field->dx;
   G.qm_abs = (float)std::fabs(A.S.qm);
   A.key = Key{(uint32_t)seed, (uint32_t)(seed >> 32)};
-  A.step0 = (uint32_t)step0;
-  A.n_steps = n_steps;
   A.dt = (float)dt;
-  HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
-  if (n_steps > 0) HIP_TRY(c, launch_pic_steps(A, grid, block, c->stream));
-  HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
+  // Step loop launches.  With weight control the kernel stops after the step
+  // that takes the count above floor(growth * n_ref); the weights are then
+  // updated (into the other particle buffer) and the loop resumes.
+  const bool wctl = c->wc_n_ppc > 0;
+  if (wctl && c->wc_n_ref <= 0) c->wc_n_ref = n0;
+  uint64_t w_updates = 0, w_pairs = 0, w_splits = 0;
+  double step_ms = 0, weight_ms = 0;
+  int done = 0;
+  rc = PCMCC_OK;
+  while (done < n_steps) {
+    A.step0 = (uint32_t)(step0 + (uint64_t)done);
+    A.n_steps = n_steps - done;
+    A.n_limit = wctl ? (uint64_t)std::floor(c->wc_growth * (double)c->wc_n_ref) : 0;
+    HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
+    HIP_TRY(c, launch_pic_steps(A, grid, block, c->stream));
+    HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->host_ctl, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    float ms = 0;
+    HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+    step_ms += ms;
+    Ctl& h = *c->host_ctl;
+    done = (int)h.steps_done;
+    if (h.status != kStatusWeightsDue) {
+      rc = h.status;
+      break;
+    }
+    const Soa cur = A.buf[h.cur_sel], other = A.buf[h.cur_sel ^ 1];
+    uint64_t n_new = 0, pairs = 0, splits = 0;
+    HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
+    const int urc = weight_update(c, cur, other, h.n_cur, field, c->wc_n_ppc, seed, step0 + (uint64_t)done - 1,
+                                  (uint64_t)p->capacity, &n_new, &pairs, &splits);
+    HIP_TRY(c, hipEventRecord(c->ev[3], c->stream));
+    h.status = PCMCC_OK;
+    h.stop = 0;
+    if (urc == PCMCC_OK) {
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
+      HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[2], c->ev[3]));
+      weight_ms += ms;
+      ++w_updates;
+      w_pairs += pairs;
+      w_splits += splits;
+      c->wc_n_ref = (int64_t)n_new;
+      h.cur_sel ^= 1;
+      h.n_cur = n_new;
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->ctl, c->host_ctl, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
+    if (urc != PCMCC_OK) {
+      rc = urc;
+      break;
+    }
+  }
   HIP_TRY(c, launch_finalize(A.buf[0], A.buf[1], c->ctl, p->n_dev, c->stream));
   HIP_TRY(c, hipMemcpyAsync(c->host_ctl, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   const Ctl& h = *c->host_ctl;
-  rc = h.status;
+  if (rc == PCMCC_OK) rc = h.status;
   if (rc == PCMCC_OK && rho) {
     HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
     const int drc = run_deposit(c, p->x, p->y, p->z, p->w, p->n_dev, h.n_cur, field, rho);
@@ -649,9 +782,7 @@ int pcmcc_push_collide_deposit(pcmcc_ctx* c, const pcmcc_particles* p, const pcm
     if (stats) stats->deposit_kernel_ms = ms;
   }
   if (stats) {
-    float ms = 0;
-    HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
-    stats->step_kernel_ms = ms;
+    stats->step_kernel_ms = step_ms;
     stats->launch_block = block;
     stats->launch_grid = grid;
     stats->n = (int64_t)h.n_cur;
@@ -663,12 +794,64 @@ int pcmcc_push_collide_deposit(pcmcc_ctx* c, const pcmcc_particles* p, const pcm
     stats->lost = h.tot[C_LOST];
     stats->out_of_table = h.tot[C_OOT];
     stats->errors = h.tot[C_ERR];
+    stats->weight_updates = (int64_t)w_updates;
+    stats->merged_pairs = (int64_t)w_pairs;
+    stats->splits = (int64_t)w_splits;
+    stats->weight_ms = weight_ms;
   }
   if (rc == PCMCC_ECAPACITY)
     return fail(c, rc, "particle capacity %lld exceeded after %lld committed steps", (long long)p->capacity,
                 (long long)h.steps_done);
   if (rc == PCMCC_ELIMIT) return fail(c, rc, "newborn generation limit reached after %lld steps", (long long)h.steps_done);
   return rc;
+}
+
+int pcmcc_set_weight_control(pcmcc_ctx* c, double n_ppc, double growth) {
+  if (!c) return fail(nullptr, PCMCC_EINVAL, "null context");
+  if (!(n_ppc >= 0) || !std::isfinite(n_ppc) || !(growth >= 1) || !std::isfinite(growth))
+    return fail(c, PCMCC_EINVAL, "n_ppc must be >= 0 and growth >= 1");
+  c->wc_n_ppc = n_ppc;
+  c->wc_growth = growth;
+  c->wc_n_ref = 0;
+  return PCMCC_OK;
+}
+
+int pcmcc_update_weights(pcmcc_ctx* c, const pcmcc_particles* p, const pcmcc_grid* grid, double n_ppc,
+                         uint64_t seed, uint64_t update_index, int64_t* merged_pairs, int64_t* splits) {
+  if (!c) return fail(nullptr, PCMCC_EINVAL, "null context");
+  if (!p || !p->x || !p->y || !p->z || !p->vx || !p->vy || !p->vz || !p->w || !p->id || !p->n_dev)
+    return fail(c, PCMCC_EINVAL, "null particle array");
+  if (p->capacity < 1 || (uint64_t)p->capacity > 0xFFFFFFFFull)
+    return fail(c, PCMCC_EINVAL, "capacity must be in [1, 2^32)");
+  if (!valid_grid(grid)) return fail(c, PCMCC_EINVAL, "invalid grid");
+  if (!(n_ppc > 0) || !std::isfinite(n_ppc)) return fail(c, PCMCC_EINVAL, "n_ppc must be positive");
+  if (update_index > 0xFFFFFFFFull) return fail(c, PCMCC_EINVAL, "update index exceeds 32 bits");
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, hipMemcpyAsync(c->host_n, p->n_dev, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const int64_t n = *c->host_n;
+  if (n < 0 || n > p->capacity) return fail(c, PCMCC_EINVAL, "particle count %lld outside [0, capacity]", (long long)n);
+  int rc = ensure_scratch(c, (uint64_t)p->capacity);
+  if (rc) return rc;
+  const Soa user{p->x, p->y, p->z, p->vx, p->vy, p->vz, p->w, p->id};
+  uint64_t n_new = 0, pairs = 0, spl = 0;
+  rc = weight_update(c, user, c->scratch, (uint64_t)n, grid, n_ppc, seed, update_index, (uint64_t)p->capacity,
+                     &n_new, &pairs, &spl);
+  if (rc) return rc;
+  if (n > 0) {
+    float* const dst[7] = {p->x, p->y, p->z, p->vx, p->vy, p->vz, p->w};
+    float* const src[7] = {c->scratch.x, c->scratch.y, c->scratch.z, c->scratch.vx, c->scratch.vy, c->scratch.vz,
+                           c->scratch.w};
+    for (int k = 0; k < 7; ++k)
+      HIP_TRY(c, hipMemcpyAsync(dst[k], src[k], n_new * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(p->id, c->scratch.id, n_new * sizeof(uint64_t), hipMemcpyDeviceToDevice, c->stream));
+    *c->host_n = (int64_t)n_new;
+    HIP_TRY(c, hipMemcpyAsync(p->n_dev, c->host_n, sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (merged_pairs) *merged_pairs = (int64_t)pairs;
+  if (splits) *splits = (int64_t)spl;
+  return PCMCC_OK;
 }
 
 namespace {

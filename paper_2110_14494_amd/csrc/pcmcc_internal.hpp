@@ -33,6 +33,11 @@ enum CntIdx { C_TRIALS, C_NULL, C_EL, C_EXC, C_ION, C_ATT, C_LOST, C_OOT, C_ERR,
 
 enum Overflow : unsigned { OVF_CAPACITY = 1u, OVF_LIMIT = 2u };
 
+// Internal status of the step loop: stopped after a step because the count
+// exceeds the weight-control limit (not an error; the host updates the
+// weights and resumes).
+constexpr int kStatusWeightsDue = 1;
+
 // Device control block of a step loop.
 struct Ctl {
   unsigned long long n_cur;   // live particles in the current buffer
@@ -68,6 +73,7 @@ struct PicArgs {
   uint32_t step0;
   int n_steps;
   float dt;
+  uint64_t n_limit;  // stop after a step that leaves more particles (0: no limit)
 };
 
 struct DepositGeom {
@@ -97,6 +103,28 @@ struct TableBuild {
   const double* sigma;  // device [nproc][n]
   double* total;        // device scratch [n]
 };
+
+// Super-particle weight update: geometry and parameters, and device buffers.
+struct WeightGeom {
+  int nx, ny, nz;
+  double x0, y0, z0, inv_dx;
+  double n_ppc;
+  int cell_bits;      // bits of the largest cell index
+  uint64_t capacity;  // slots of the output buffer
+};
+struct WeightWork {
+  uint8_t* cls;                 // [n] class per particle
+  uint32_t *idx0, *idx1;        // [n] candidate indices (sort ping-pong)
+  uint64_t *key0, *key1;        // [n] sort keys
+  uint32_t *pos, *cnt;          // [n] output counts and positions
+  unsigned long long* counters;  // [4] candidates, merged pairs
+  void* temp;
+  size_t temp_bytes;
+};
+hipError_t weight_temp_bytes(uint64_t n, size_t* bytes);
+hipError_t launch_weight_update(const Soa& cur, const Soa& out, uint64_t n, const WeightGeom& g, const int64_t* rho,
+                                Key key, uint32_t update_index, const WeightWork& W, uint64_t* n_out,
+                                uint64_t* pairs_out, uint64_t* splits_out, hipStream_t stream);
 
 // Swarm moments per sample and the coefficients derived from them.
 constexpr int kNMom = 14;

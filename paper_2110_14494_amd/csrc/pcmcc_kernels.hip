@@ -265,6 +265,10 @@ __global__ __launch_bounds__(256) void k_pic_steps(PicArgs A) {
           ctl->cur_sel = sel ^ 1;
           ctl->steps_done += 1;
           for (int k = 0; k < NCNT; ++k) ctl->tot[k] += sums[k];
+          if (A.n_limit && ctl->n_cur > A.n_limit) {  // weights are due: back to the host
+            ctl->stop = 1;
+            ctl->status = kStatusWeightsDue;
+          }
         }
         ctl->holes = 0;
         ctl->child = 0;

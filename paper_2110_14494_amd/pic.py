@@ -140,6 +140,19 @@ class Context:
             B.check(rc, self.h)
         return rc, st.as_dict()
 
+    def set_weight_control(self, n_ppc: float, growth: float = 1.25):
+        B.check(B.lib().pcmcc_set_weight_control(self.h, float(n_ppc), float(growth)), self.h)
+
+    def update_weights(self, parts: Particles, grid: DeviceGrid, n_ppc: float, seed: int, update_index: int,
+                       check: bool = True):
+        ps, gs = parts.struct(), grid.struct()
+        mp, sp = C.c_int64(0), C.c_int64(0)
+        rc = B.lib().pcmcc_update_weights(self.h, C.byref(ps), C.byref(gs), float(n_ppc), int(seed),
+                                          int(update_index), C.byref(mp), C.byref(sp))
+        if check:
+            B.check(rc, self.h)
+        return rc, {"merged_pairs": mp.value, "splits": sp.value}
+
     def deposit(self, parts: Particles, grid: DeviceGrid, rho: torch.Tensor):
         t = parts.t
         gs = grid.struct()
