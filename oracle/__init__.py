@@ -227,15 +227,25 @@ def update_weights(parts: dict, grid: dict, n_ppc: float, seed: int, update_inde
     return rc, out, {"merged_pairs": int(counts[0]), "splits": int(counts[1])}
 
 
-def deposit(x, y, z, w, grid: dict) -> np.ndarray:
-    """Fixed-point CIC deposit of single-precision particle arrays."""
+def deposit_rc(x, y, z, w, grid: dict):
+    """Fixed-point CIC deposit of single-precision particle arrays; returns
+    (rc, rho).  rc = -8 (rho all zero) if a weight is outside [0, 2^31) or a
+    cell's exact sum leaves the int64 range."""
     x, y, z, w = (np.ascontiguousarray(a, dtype=np.float32) for a in (x, y, z, w))
     E = np.asarray(grid["E"])
     nz, ny, nx = E.shape[:3]
     rho = np.zeros((nz, ny, nx), dtype=np.int64)
     inv_dx = 1.0 / float(grid["dx"])
-    lib().orc_deposit(_ptr(x), _ptr(y), _ptr(z), _ptr(w), x.size, nx, ny, nz, float(grid["x0"]),
-                      float(grid["y0"]), float(grid["z0"]), inv_dx, _ptr(rho))
+    rc = lib().orc_deposit(_ptr(x), _ptr(y), _ptr(z), _ptr(w), x.size, nx, ny, nz, float(grid["x0"]),
+                           float(grid["y0"]), float(grid["z0"]), inv_dx, _ptr(rho))
+    return rc, rho
+
+
+def deposit(x, y, z, w, grid: dict) -> np.ndarray:
+    """Fixed-point CIC deposit of single-precision particle arrays."""
+    rc, rho = deposit_rc(x, y, z, w, grid)
+    if rc != 0:
+        raise ValueError(f"deposit out of the fixed-point range (rc {rc})")
     return rho
 
 

@@ -36,6 +36,8 @@
 
 int orc_deposit_impl(const float* x, const float* y, const float* z, const float* w, int64_t n, int nx, int ny,
                      int nz, double x0, double y0, double z0, double inv_dx, int64_t* rho);
+// A charge outside the fixed-point range of the deposit.
+constexpr int ORC_ERANGE = -8;
 
 namespace {
 
@@ -546,8 +548,8 @@ int cell_of(double x, double o, double inv_dx, int n) {
   return std::min(std::max(i, 0), n - 1);
 }
 
-void update_weights(std::vector<Particle>& ps, int nx, int ny, int nz, double x0, double y0, double z0, double inv_dx,
-                    double n_ppc, uint32_t key0, uint32_t key1, uint64_t update_index, WeightCounts& wc) {
+int update_weights(std::vector<Particle>& ps, int nx, int ny, int nz, double x0, double y0, double z0, double inv_dx,
+                   double n_ppc, uint32_t key0, uint32_t key1, uint64_t update_index, WeightCounts& wc) {
   const size_t n = ps.size();
   const size_t ncell = (size_t)nx * ny * nz;
   std::vector<float> fx(n), fy(n), fz(n), fw(n);
@@ -558,7 +560,9 @@ void update_weights(std::vector<Particle>& ps, int nx, int ny, int nz, double x0
     fw[i] = (float)ps[i].w;
   }
   std::vector<int64_t> rho(ncell, 0);
-  orc_deposit_impl(fx.data(), fy.data(), fz.data(), fw.data(), (int64_t)n, nx, ny, nz, x0, y0, z0, inv_dx, rho.data());
+  const int drc =
+      orc_deposit_impl(fx.data(), fy.data(), fz.data(), fw.data(), (int64_t)n, nx, ny, nz, x0, y0, z0, inv_dx, rho.data());
+  if (drc) return drc;
   std::vector<int64_t> cell(n);
   std::vector<int> cls(n, 0);  // 0 keep, 1 merge candidate, 2 split
   std::vector<size_t> cand;
@@ -625,6 +629,7 @@ void update_weights(std::vector<Particle>& ps, int nx, int ny, int nz, double x0
   }
   out.insert(out.end(), copies.begin(), copies.end());
   ps.swap(out);
+  return 0;
 }
 
 extern "C" {
@@ -763,7 +768,12 @@ int orc_pic_run(const orc_problem* pb, const orc_grid* g, double* x, double* y, 
     total.add(cnt);
     ++steps_done;
     if (n_ppc > 0 && (int64_t)cur.size() > (int64_t)std::floor(growth * (double)nref)) {
-      update_weights(cur, g->nx, g->ny, g->nz, g->x0, g->y0, g->z0, 1.0 / g->dx, n_ppc, key0, key1, step0 + s, wc);
+      const int urc =
+          update_weights(cur, g->nx, g->ny, g->nz, g->x0, g->y0, g->z0, 1.0 / g->dx, n_ppc, key0, key1, step0 + s, wc);
+      if (urc) {
+        rc = urc;
+        break;
+      }
       if ((int64_t)cur.size() > capacity) {
         rc = -2;
         break;
@@ -804,6 +814,8 @@ int orc_pic_run(const orc_problem* pb, const orc_grid* g, double* x, double* y, 
 // weights (1 - f, f); corners visited in (dz, dy, dx) order, each rounded to
 // the nearest integer, the last corner taking the remainder so the particle's
 // charge w * 2^32 is conserved exactly.  Indices are clamped (folded back).
+// Returns ORC_ERANGE (rho unchanged) for a weight outside [0, 2^31) or a cell
+// whose exact sum leaves the int64 range (2^31 electrons per cell).
 int orc_deposit(const float* x, const float* y, const float* z, const float* w, int64_t n, int nx, int ny, int nz,
                 double x0, double y0, double z0, double inv_dx, int64_t* rho) {
   return orc_deposit_impl(x, y, z, w, n, nx, ny, nz, x0, y0, z0, inv_dx, rho);
@@ -815,6 +827,12 @@ int orc_deposit_impl(const float* x, const float* y, const float* z, const float
                      int nz, double x0, double y0, double z0, double inv_dx, int64_t* rho) {
   const int nn[3] = {nx, ny, nz};
   const double o[3] = {x0, y0, z0};
+  // a particle's charge round(w 2^32) must fit one corner: 0 <= w < 2^31
+  for (int64_t p = 0; p < n; ++p)
+    if (!((double)w[p] >= 0.0 && (double)w[p] < 2147483648.0)) return ORC_ERANGE;
+  // exact cell sums (128-bit), stored only if every one fits int64
+  const size_t ncell = (size_t)nx * ny * nz;
+  std::vector<__int128> acc(rho, rho + ncell);
   for (int64_t p = 0; p < n; ++p) {
     const double pos[3] = {(double)x[p], (double)y[p], (double)z[p]};
     const double wd = (double)w[p];
@@ -846,9 +864,12 @@ int orc_deposit_impl(const float* x, const float* y, const float* z, const float
             given += c;
           }
           const size_t cell = ((size_t)ic[2][dz] * ny + ic[1][dy]) * nx + ic[0][dx];
-          rho[cell] += c;
+          acc[cell] += c;
         }
   }
+  for (size_t c = 0; c < ncell; ++c)
+    if (acc[c] > (__int128)INT64_MAX || acc[c] < (__int128)INT64_MIN) return ORC_ERANGE;
+  for (size_t c = 0; c < ncell; ++c) rho[c] = (int64_t)acc[c];
   return 0;
 }
 
@@ -1003,8 +1024,9 @@ int orc_update_weights(const float* x, const float* y, const float* z, const flo
     ps[i].id = id[i];
   }
   WeightCounts wc;
-  update_weights(ps, nx, ny, nz, x0, y0, z0, 1.0 / dx, n_ppc, (uint32_t)seed, (uint32_t)(seed >> 32), update_index,
-                 wc);
+  const int urc = update_weights(ps, nx, ny, nz, x0, y0, z0, 1.0 / dx, n_ppc, (uint32_t)seed, (uint32_t)(seed >> 32),
+                                 update_index, wc);
+  if (urc) return urc;
   if (counts) {
     counts[0] = wc.merged_pairs;
     counts[1] = wc.splits;

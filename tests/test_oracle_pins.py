@@ -389,3 +389,36 @@ def test_deposit_conservation_and_special_points(oracle_lib):
                 iz = np.clip(i[2] + dz, 0, 15)
                 np.add.at(ref, (iz, iy, ix), wt * w)
     assert np.max(np.abs(rho / 2.0 ** 32 - ref)) < 1e-6
+
+
+def test_deposit_range_is_int64(oracle_lib):
+    # The fixed-point cell sums are int64: 2^63 - 1 units of 2^-32, i.e. just
+    # under 2^31 electrons per cell.  Two particles at one cell centre (all of
+    # the charge in that cell) reach exactly 2^63 with weights 2^30 + 2^30
+    # (out of range) and 2^63 - 2^38 with 2^30 + (2^30 - 64) (in range).  A
+    # single weight must lie in [0, 2^31): the largest float below is 2^31 - 128.
+    dx = 2.0 ** -15
+    grid = W.uniform_grid(4, dx, x0=0.0)
+    c = (np.array([1, 2, 3]) + 0.5) * dx
+
+    def dep(ws):
+        k = len(ws)
+        return oracle_lib.deposit_rc([c[0]] * k, [c[1]] * k, [c[2]] * k, np.array(ws, np.float32), grid)
+
+    rc, rho = dep([2.0 ** 30, 2.0 ** 30 - 64])
+    assert rc == 0 and int(rho[3, 2, 1]) == 2 ** 63 - 2 ** 38 and np.count_nonzero(rho) == 1
+    rc, rho = dep([2.0 ** 30, 2.0 ** 30])
+    assert rc == -8 and not rho.any()
+    rc, rho = dep([2.0 ** 31 - 128])
+    assert rc == 0 and int(rho[3, 2, 1]) == (2 ** 31 - 128) * 2 ** 32
+    for bad in (2.0 ** 31, -1.0, np.nan, np.inf):
+        rc, rho = dep([1.0, bad])
+        assert rc == -8 and not rho.any(), bad
+    # charge spread over 8 cells: each gets an eighth (2^59 per particle of
+    # 2^30), so 16 particles at a shared corner reach 2^63 in every cell (out
+    # of range) and 15 do not
+    k = np.array([2, 2, 2]) * dx
+    rc, rho = oracle_lib.deposit_rc([k[0]] * 15, [k[1]] * 15, [k[2]] * 15, np.full(15, 2.0 ** 30, np.float32), grid)
+    assert rc == 0 and np.count_nonzero(rho) == 8 and np.all(rho[rho != 0] == 15 * 2 ** 59)
+    rc, _ = oracle_lib.deposit_rc([k[0]] * 16, [k[1]] * 16, [k[2]] * 16, np.full(16, 2.0 ** 30, np.float32), grid)
+    assert rc == -8

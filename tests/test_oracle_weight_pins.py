@@ -110,6 +110,18 @@ def test_desired_weight_has_a_floor_of_one():
     assert sorted(out["w"].tolist()) == pytest.approx([0.7, 1.0, 1.0, 1.2], abs=1e-7)
 
 
+def test_update_out_of_fixed_point_range_is_an_error():
+    # The desired weight comes from the int64 fixed-point density: three
+    # particles of 2^30 electrons in one cell (beyond 2^31) are out of range
+    # and the update is refused; one of them alone fits (and splits).
+    c = _centre(1, 1, 1)
+    p = _parts([c] * 3, np.zeros((3, 3)), [2.0 ** 30] * 3, [1, 2, 3])
+    rc, out, _ = oracle.update_weights(p, _grid(), 75.0, seed=1, update_index=0)
+    assert rc == -8 and out["id"].size == 0
+    rc, out, cnt = oracle.update_weights({k: v[:1] for k, v in p.items()}, _grid(), 75.0, seed=1, update_index=0)
+    assert rc == 0 and cnt == {"merged_pairs": 0, "splits": 1} and np.all(out["w"] == 2.0 ** 29)
+
+
 def test_update_is_independent_of_array_order():
     # 5e4 electrons (weights 1-64) in a Gaussian cloud on 16^3 cells of 80 um:
     # dense central cells merge, heavy particles split.
