@@ -13,7 +13,9 @@ starting particles with one device copy (inside the timed region).
 value = particle-steps / second of the whole timed region.
 
 Also reported: the roofline of the step kernel (HIP events), the CPU oracle
-on a bounded sample, and the coefficient path: batched swarms against the
+on a bounded sample, the streamer stage run for all of its 200 steps under
+super-particle weight control (N_ppc = 75, update when the count has grown
+by 1.25x), and the coefficient path: batched swarms against the
 plain per-E/N swarm, surrogate training, held-out fallback and BF16
 inference on 1e8 reduced fields.  Prints one JSON line.
 """
@@ -69,6 +71,11 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=2 ** 23)
     ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--no-coef", action="store_true", help="skip the swarm / surrogate leg")
+    ap.add_argument("--no-weights", action="store_true", help="skip the weight-controlled streamer run")
+    ap.add_argument("--n-ppc", type=float, default=75.0, help="particles per cell of the weight control")
+    ap.add_argument("--growth", type=float, default=1.25, help="count growth that triggers a weight update")
+    ap.add_argument("--weights-cap-factor", type=int, default=16,
+                    help="capacity / start count of the weight-controlled run")
     ap.add_argument("--coef-scale", type=float, default=1.0, help="scale of the swarm sizes")
     ap.add_argument("--epochs", type=int, default=20000)
     ap.add_argument("--infer-n", type=int, default=100_000_000)
@@ -211,6 +218,51 @@ def pic_leg(a, ctx, pic):
     return cfg, psteps / el, el, roof, config
 
 
+def weights_leg(a, ctx, pic):
+    """The streamer stage for all of its steps under super-particle weight
+    control: whenever the count has grown by the growth factor since the last
+    update, particles are merged and split towards N_ppc per cell (Sec. 2.1.2)
+    and the step loop resumes.  One untimed run, then one timed run."""
+    import torch
+    from paper_2110_14494_amd import workloads as W
+    cfg = W.streamer_config(n=a.n or 2 ** 24)
+    n0 = cfg["parts"]["x"].size
+    cap = a.weights_cap_factor * n0
+    ctx.setup(cfg["species"], cfg["tables"])
+    pristine = pic.Particles.from_numpy(cfg["parts"], n0)
+    work = pic.Particles(cap)
+    grid = pic.DeviceGrid(cfg["grid"])
+    rho = grid.zeros_rho()
+    w0 = float(pristine.t["w"][:n0].double().sum())
+    res = []
+    for run in range(2):
+        for k, t in pristine.t.items():
+            work.t[k][:n0].copy_(t[:n0])
+        work.n_dev.copy_(pristine.n_dev)
+        rho.zero_()
+        ctx.set_weight_control(a.n_ppc, a.growth)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, st = ctx.push_collide_deposit(work, grid, cfg["dt"], cfg["n_steps"], cfg["seed"], rho=rho, check=False)
+        torch.cuda.synchronize()
+        res.append((rc, st, time.perf_counter() - t0))
+    ctx.set_weight_control(0.0)
+    rc, st, el = res[-1]
+    n_fin = int(st["n"])
+    w_fin = float(work.t["w"][:n_fin].double().sum())
+    log(f"weight control: rc={rc} steps {st['steps_done']} updates {st['weight_updates']} n {n0} -> {n_fin}, "
+        f"{el:.2f} s")
+    return {"workload": cfg["name"], "n_ppc": a.n_ppc, "growth": a.growth, "capacity": int(cap), "status": rc,
+            "steps_done": int(st["steps_done"]), "steps_asked": cfg["n_steps"],
+            "particle_steps": int(st["particle_steps"]), "s": el,
+            "particle_steps_per_s": st["particle_steps"] / el,
+            "step_kernel_ms": st["step_kernel_ms"], "weight_ms": st["weight_ms"],
+            "deposit_ms": st["deposit_kernel_ms"], "weight_updates": int(st["weight_updates"]),
+            "merged_pairs": int(st["merged_pairs"]), "splits": int(st["splits"]), "n_start": int(n0),
+            "n_final": n_fin, "electrons_start": w0, "electrons_final": w_fin,
+            "ionizations": int(st["ionization"]), "attachments": int(st["attachment"])}
+
+
 def coef_leg(a, ctx, pic):
     """Coefficient path: 2048 E/N points (8 batches of 256 swarms, sizes as the
     batched-swarm workload), every 8th held out; surrogate trained on the GPU;
@@ -340,6 +392,9 @@ def main():
     if not a.no_cpu_baseline:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(cfg, a.cpu_sample, a.cpu_steps)
+    if not a.no_weights and a.workload == "streamer":
+        log("weight-controlled streamer run")
+        out["weight_control"] = weights_leg(a, ctx, pic)
     if not a.no_coef:
         log("coefficient path")
         out["coefficients"] = coef_leg(a, ctx, pic)

@@ -42,6 +42,7 @@ extern "C" {
 #define PCMCC_ENOMEM (-5)    /* device allocation failed */
 #define PCMCC_ETABLE (-6)    /* malformed cross-section table */
 #define PCMCC_ELIMIT (-7)    /* a per-step safety limit was reached */
+#define PCMCC_ERANGE (-8)    /* a charge outside the deposit's fixed-point range */
 
 /* Collision process kinds (Sec. 2.1.5).  Cumulative rates are formed in the
  * order the processes are given to pcmcc_init_tables. */
@@ -157,6 +158,9 @@ int pcmcc_init_tables(pcmcc_ctx* ctx, int n_e, double eps_min_eV, double eps_max
  *            deposit.  It is accumulated into (the caller zeroes it): each
  *            particle adds round(w 2^32) split over the 8 nearest cell
  *            centres, indices clamped to the grid, exactly conserving the sum.
+ *            Weights must lie in [0, 2^31) and every cell sum within int64
+ *            (2^31 electrons per cell); otherwise PCMCC_ERANGE is returned
+ *            after the steps, with rho unspecified.
  *   stats  : host, may be NULL.
  * On PCMCC_ECAPACITY the arrays hold the state after stats->steps_done
  * committed steps and the deposit is skipped.  Synchronises the stream. */
@@ -329,18 +333,23 @@ int pcmcc_mlp_fallback(pcmcc_ctx* ctx, const float* params, const pcmcc_mlp_infe
  * exceeds floor(growth * n_ref), the weights are updated with update_index =
  * the absolute index of that step, and n_ref becomes the new count; n_ref is
  * the count at the start of the first call after this one, and is kept across
- * calls.  growth >= 1 (the paper uses 1.25). */
+ * calls.  growth >= 1 (the paper uses 1.25).  An update that fails
+ * (PCMCC_ECAPACITY, PCMCC_ERANGE) ends the call with that code and the
+ * particles of the last committed step. */
 int pcmcc_set_weight_control(pcmcc_ctx* ctx, double n_ppc, double growth);
 
 /* One weight update of the device particles p (in place, *p->n_dev updated)
  * on `grid` (only its geometry is used).  merged_pairs and splits (host,
  * nullable) receive the counts.  PCMCC_ECAPACITY (particles unchanged) if the
- * result exceeds p->capacity.  Synchronises the stream. */
+ * result exceeds p->capacity; PCMCC_ERANGE (particles unchanged) if the
+ * density is outside the deposit's fixed-point range.  Synchronises the
+ * stream. */
 int pcmcc_update_weights(pcmcc_ctx* ctx, const pcmcc_particles* p, const pcmcc_grid* grid, double n_ppc,
                          uint64_t seed, uint64_t update_index, int64_t* merged_pairs, int64_t* splits);
 
-/* Deposit only (Sec. 2.1.3), same fixed-point rule as above, on n_dev
- * particles (device count) of device arrays x, y, z, w. */
+/* Deposit only (Sec. 2.1.3), same fixed-point rule and range as above
+ * (PCMCC_ERANGE, rho unspecified, beyond it), on n_dev particles (device
+ * count) of device arrays x, y, z, w.  Synchronises the stream. */
 int pcmcc_deposit(pcmcc_ctx* ctx, const float* x, const float* y, const float* z, const float* w,
                   const int64_t* n_dev, const pcmcc_grid* grid, int64_t* rho);
 

@@ -13,12 +13,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpcmcc.so")
 
 PCMCC_OK, PCMCC_EINVAL, PCMCC_ECAPACITY, PCMCC_EHIP = 0, -1, -2, -3
-PCMCC_ESTATE, PCMCC_ENOMEM, PCMCC_ETABLE, PCMCC_ELIMIT = -4, -5, -6, -7
+PCMCC_ESTATE, PCMCC_ENOMEM, PCMCC_ETABLE, PCMCC_ELIMIT, PCMCC_ERANGE = -4, -5, -6, -7, -8
 PCMCC_ELASTIC, PCMCC_EXCITATION, PCMCC_IONIZATION, PCMCC_ATTACHMENT = 0, 1, 2, 3
 PCMCC_EFFECTIVE_TO_ELASTIC, PCMCC_RATES = 1, 2
 
 _NAMES = {0: "OK", -1: "EINVAL", -2: "ECAPACITY", -3: "EHIP", -4: "ESTATE", -5: "ENOMEM", -6: "ETABLE",
-          -7: "ELIMIT"}
+          -7: "ELIMIT", -8: "ERANGE"}
 
 
 class pcmcc_particles(C.Structure):

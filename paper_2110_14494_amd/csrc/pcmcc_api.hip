@@ -70,6 +70,8 @@ struct pcmcc_ctx {
   uint64_t dep_tiles = 0, dep_dump = 0, dep_sorted = 0;
   unsigned* emax_bits = nullptr;
   int64_t* host_n = nullptr;  // pinned
+  unsigned* dep_err = nullptr;    // deposit range flag (device)
+  unsigned* host_err = nullptr;   // pinned copy of it
   // super-particle weights: control settings, update buffers
   double wc_n_ppc = 0, wc_growth = 1.25;
   int64_t wc_n_ref = 0;
@@ -375,13 +377,26 @@ int prepare_field(pcmcc_ctx* c, const pcmcc_grid* g) {
 
 // Charge deposit of n particles (n_dev holds the same count on the device):
 // direct kernel for small n, binned schedule from kDepositBinnedMin on.
+// Reads the deposit's range flag back (synchronises the stream).
+int deposit_range_check(pcmcc_ctx* c) {
+  HIP_TRY(c, hipMemcpyAsync(c->host_err, c->dep_err, sizeof(unsigned), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (*c->host_err)
+    return fail(c, PCMCC_ERANGE, "charge outside the deposit's fixed-point range (a weight outside [0, 2^31) or "
+                "more than 2^31 electrons in one cell)");
+  return PCMCC_OK;
+}
+
+// Deposit of n particles into rho on the context stream; with check, waits
+// and reports a range error (else the caller calls deposit_range_check).
 int run_deposit(pcmcc_ctx* c, const float* x, const float* y, const float* z, const float* w, const int64_t* n_dev,
-                uint64_t n, const pcmcc_grid* grid, int64_t* rho) {
-  const DepositGeom g{grid->nx, grid->ny, grid->nz, grid->x0, grid->y0, grid->z0, 1.0 / grid->dx};
+                uint64_t n, const pcmcc_grid* grid, int64_t* rho, bool check = true) {
+  const DepositGeom g{grid->nx, grid->ny, grid->nz, grid->x0, grid->y0, grid->z0, 1.0 / grid->dx, c->dep_err};
   const DepositNeeds d = deposit_needs(g, n);
+  HIP_TRY(c, hipMemsetAsync(c->dep_err, 0, sizeof(unsigned), c->stream));
   if (!d.binned) {
     HIP_TRY(c, launch_deposit(x, y, z, w, n_dev, g, rho, c->stream));
-    return PCMCC_OK;
+    return check ? deposit_range_check(c) : PCMCC_OK;
   }
   if (n >= 0xFFFFFFFFull) return fail(c, PCMCC_EINVAL, "deposit of 2^32 or more particles");
   auto grow = [&](auto** ptr, uint64_t& have, uint64_t need) -> int {
@@ -411,7 +426,7 @@ int run_deposit(pcmcc_ctx* c, const float* x, const float* y, const float* z, co
   if (!rc) rc = grow(&c->dep.sorted, c->dep_sorted, d.sorted);
   if (rc) return rc;
   HIP_TRY(c, launch_deposit_binned(x, y, z, w, n, g, rho, c->dep, c->stream));
-  return PCMCC_OK;
+  return check ? deposit_range_check(c) : PCMCC_OK;
 }
 
 // Buffers of the weight update for n particles on `ncell` cells.
@@ -516,8 +531,10 @@ int pcmcc_create(pcmcc_ctx** out, int device, void* hip_stream) {
     }
   }
   if (dalloc(&c->ctl, 1) != hipSuccess || dalloc(&c->emax_bits, 1) != hipSuccess ||
+      dalloc(&c->dep_err, 1) != hipSuccess ||
       hipHostMalloc((void**)&c->host_ctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&c->host_n, sizeof(int64_t), hipHostMallocDefault) != hipSuccess) {
+      hipHostMalloc((void**)&c->host_n, sizeof(int64_t), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->host_err, sizeof(unsigned), hipHostMallocDefault) != hipSuccess) {
     pcmcc_destroy(c);
     return fail(nullptr, PCMCC_ENOMEM, "context allocation failed");
   }
@@ -555,8 +572,10 @@ int pcmcc_destroy(pcmcc_ctx* c) {
   dfree(c->wt_rho);
   dfree(c->dev_n);
   dfree(c->emax_bits);
+  dfree(c->dep_err);
   if (c->host_ctl) (void)hipHostFree(c->host_ctl);
   if (c->host_n) (void)hipHostFree(c->host_n);
+  if (c->host_err) (void)hipHostFree(c->host_err);
   for (auto& ev : c->ev)
     if (ev) (void)hipEventDestroy(ev);
   delete c;
@@ -771,15 +790,17 @@ int pcmcc_push_collide_deposit(pcmcc_ctx* c, const pcmcc_particles* p, const pcm
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   const Ctl& h = *c->host_ctl;
   if (rc == PCMCC_OK) rc = h.status;
+  int drc = PCMCC_OK;
   if (rc == PCMCC_OK && rho) {
     HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
-    const int drc = run_deposit(c, p->x, p->y, p->z, p->w, p->n_dev, h.n_cur, field, rho);
+    drc = run_deposit(c, p->x, p->y, p->z, p->w, p->n_dev, h.n_cur, field, rho, false);
     if (drc) return drc;
     HIP_TRY(c, hipEventRecord(c->ev[3], c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     float ms = 0;
     HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[2], c->ev[3]));
     if (stats) stats->deposit_kernel_ms = ms;
+    drc = deposit_range_check(c);
   }
   if (stats) {
     stats->step_kernel_ms = step_ms;
@@ -803,7 +824,7 @@ int pcmcc_push_collide_deposit(pcmcc_ctx* c, const pcmcc_particles* p, const pcm
     return fail(c, rc, "particle capacity %lld exceeded after %lld committed steps", (long long)p->capacity,
                 (long long)h.steps_done);
   if (rc == PCMCC_ELIMIT) return fail(c, rc, "newborn generation limit reached after %lld steps", (long long)h.steps_done);
-  return rc;
+  return rc != PCMCC_OK ? rc : drc;
 }
 
 int pcmcc_set_weight_control(pcmcc_ctx* c, double n_ppc, double growth) {

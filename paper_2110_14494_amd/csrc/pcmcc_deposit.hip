@@ -6,6 +6,14 @@
 // taking the remainder, so the integer sum is independent of order and
 // exactly conserves round(w 2^32) per particle.
 //
+// Range: a particle's charge must fit one corner (0 <= w < 2^31) and every
+// cell sum must stay within int64 (2^31 electrons).  Every addition, in LDS
+// and in global memory, checks its own signed overflow from the value the
+// atomic returns; as the corner charges are non-negative (the remainder
+// corner can be a few units below zero) a cell whose sum leaves the range
+// overflows in one of them.  Either case raises range_err and drops nothing
+// else: the caller reports the error and rho is then unspecified.
+//
 // Two schedules of the same sums:
 //  * direct: one thread per particle, 8 global int64 atomics;
 //  * binned (large inputs): the grid is cut into tiles of 8^3 cells, the
@@ -46,7 +54,8 @@ __device__ __forceinline__ void dep_axis(double p, double o, double inv_dx, int 
 }
 
 // Cells (lower/upper per axis) and fixed-point charges of the 8 corners in
-// (dz, dy, dx) order.
+// (dz, dy, dx) order.  A weight outside [0, 2^31) raises range_err and
+// deposits nothing.
 __device__ __forceinline__ void corner_charges(const DepositGeom& g, float x, float y, float z, float w, int ic[3][2],
                                                long long q[8]) {
 #pragma clang fp contract(off)
@@ -54,7 +63,11 @@ __device__ __forceinline__ void corner_charges(const DepositGeom& g, float x, fl
   dep_axis((double)x, g.x0, g.inv_dx, g.nx, ic[0], W[0]);
   dep_axis((double)y, g.y0, g.inv_dx, g.ny, ic[1], W[1]);
   dep_axis((double)z, g.z0, g.inv_dx, g.nz, ic[2], W[2]);
-  const double wd = (double)w;
+  double wd = (double)w;
+  if (!(wd >= 0.0 && wd < 2147483648.0)) {
+    atomicOr(g.range_err, 1u);
+    wd = 0.0;
+  }
   const long long qw = __double2ll_rn(wd * 4294967296.0);
   long long given = 0;
 #pragma unroll
@@ -71,6 +84,13 @@ __device__ __forceinline__ size_t cell_index(const DepositGeom& g, int i, int j,
   return ((size_t)k * g.ny + j) * g.nx + i;
 }
 
+// rho[i] += v (int64, global or LDS), raising *err on signed overflow.
+__device__ __forceinline__ void add_checked(unsigned long long* a, long long v, unsigned* err) {
+  const long long old = (long long)atomicAdd(a, (unsigned long long)v);
+  const long long res = (long long)((unsigned long long)old + (unsigned long long)v);
+  if (((old ^ res) & (v ^ res)) < 0) atomicOr(err, 1u);
+}
+
 __global__ void k_deposit(const float* __restrict__ x, const float* __restrict__ y, const float* __restrict__ z,
                           const float* __restrict__ w, const int64_t* n_dev, DepositGeom g,
                           unsigned long long* rho) {
@@ -81,7 +101,7 @@ __global__ void k_deposit(const float* __restrict__ x, const float* __restrict__
     corner_charges(g, x[p], y[p], z[p], w[p], ic, q);
 #pragma unroll
     for (int c = 0; c < 8; ++c)
-      atomicAdd(&rho[cell_index(g, ic[0][c & 1], ic[1][(c >> 1) & 1], ic[2][c >> 2])], (unsigned long long)q[c]);
+      add_checked(&rho[cell_index(g, ic[0][c & 1], ic[1][(c >> 1) & 1], ic[2][c >> 2])], q[c], g.range_err);
   }
 }
 
@@ -206,6 +226,44 @@ __global__ __launch_bounds__(256) void k_dep_scatter(const float* __restrict__ x
   }
 }
 
+// One tile run [cur, e) of sorted particles into the LDS buffer of the tile
+// at (oi, oj, ok).  The plain pass adds without overflow checks (it cannot
+// overflow while the run carries fewer than 2^31 electrons, which the caller
+// checks with the returned weight sum) and sends a corner outside the buffer
+// to rho directly; the checked pass repeats only the LDS part.
+template <bool kChecked>
+__device__ __forceinline__ double accum_run(const float4* __restrict__ sorted, uint64_t cur, uint64_t e,
+                                            const TileGeom& T, int oi, int oj, int ok, unsigned long long* acc,
+                                            unsigned long long* rho) {
+  double wsum = 0.0;
+  for (uint64_t p = cur + threadIdx.x; p < e; p += blockDim.x) {
+    const float4 v = sorted[p];
+    int ic[3][2];
+    long long q[8];
+    corner_charges(T.g, v.x, v.y, v.z, v.w, ic, q);
+    if (v.w >= 0.0f) wsum += (double)v.w;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int ci = ic[0][c & 1], cj = ic[1][(c >> 1) & 1], ck = ic[2][c >> 2];
+      const int li = ci - oi, lj = cj - oj, lk = ck - ok;
+      if ((unsigned)li < (unsigned)kTileBuf && (unsigned)lj < (unsigned)kTileBuf && (unsigned)lk < (unsigned)kTileBuf) {
+        unsigned long long* a = &acc[(lk * kTileBuf + lj) * kTileBuf + li];
+        if (kChecked)
+          add_checked(a, q[c], T.g.range_err);
+        else
+          atomicAdd(a, (unsigned long long)q[c]);
+      } else if (!kChecked) {  // a particle outside its tile's buffer: never expected, kept exact
+        add_checked(&rho[cell_index(T.g, ci, cj, ck)], q[c], T.g.range_err);
+      }
+    }
+  }
+  return wsum;
+}
+
+// A tile run carrying this many electrons or more is summed again with
+// overflow checks (2^31 electrons is the int64 limit of one cell).
+constexpr double kAccGuard = 1073741824.0;
+
 // Pass 3: per-tile sums.  Block b covers sorted particles
 // [b kAccRange, (b+1) kAccRange), one tile at a time.
 __global__ __launch_bounds__(256) void k_dep_accum(const float4* __restrict__ sorted, uint64_t n, TileGeom T,
@@ -213,6 +271,7 @@ __global__ __launch_bounds__(256) void k_dep_accum(const float4* __restrict__ so
   __shared__ unsigned long long acc[kTileCells];
   __shared__ uint32_t s_tile;
   __shared__ uint64_t s_end;
+  __shared__ double s_wsum;
   for (int c = threadIdx.x; c < kTileCells; c += blockDim.x) acc[c] = 0;
   uint64_t cur = (uint64_t)blockIdx.x * kAccRange;
   const uint64_t end = cur + kAccRange < n ? cur + kAccRange : n;
@@ -225,6 +284,7 @@ __global__ __launch_bounds__(256) void k_dep_accum(const float4* __restrict__ so
       uint64_t te = start[t + 1];
       te = te > cur ? te : cur + 1;
       s_end = te < end ? te : end;
+      s_wsum = 0.0;
     }
     __syncthreads();
     const uint32_t t = s_tile;
@@ -232,27 +292,21 @@ __global__ __launch_bounds__(256) void k_dep_accum(const float4* __restrict__ so
     const int oi = (int)(t % T.tx) * kTile;
     const int oj = (int)((t / T.tx) % T.ty) * kTile;
     const int ok = (int)(t / ((uint32_t)T.tx * T.ty)) * kTile;
-    for (uint64_t p = cur + threadIdx.x; p < e; p += blockDim.x) {
-      const float4 v = sorted[p];
-      int ic[3][2];
-      long long q[8];
-      corner_charges(T.g, v.x, v.y, v.z, v.w, ic, q);
-#pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        const int ci = ic[0][c & 1], cj = ic[1][(c >> 1) & 1], ck = ic[2][c >> 2];
-        const int li = ci - oi, lj = cj - oj, lk = ck - ok;
-        if ((unsigned)li < (unsigned)kTileBuf && (unsigned)lj < (unsigned)kTileBuf && (unsigned)lk < (unsigned)kTileBuf)
-          atomicAdd(&acc[(lk * kTileBuf + lj) * kTileBuf + li], (unsigned long long)q[c]);
-        else  // a particle outside its tile's buffer: never expected, kept exact
-          atomicAdd(&rho[cell_index(T.g, ci, cj, ck)], (unsigned long long)q[c]);
-      }
+    const double ws = accum_run<false>(sorted, cur, e, T, oi, oj, ok, acc, rho);
+    if (ws > 0.0) atomicAdd(&s_wsum, ws);
+    __syncthreads();
+    if (s_wsum >= kAccGuard) {  // block-uniform
+      for (int c = threadIdx.x; c < kTileCells; c += blockDim.x) acc[c] = 0;
+      __syncthreads();
+      accum_run<true>(sorted, cur, e, T, oi, oj, ok, acc, rho);
     }
     __syncthreads();
     for (int c = threadIdx.x; c < kTileCells; c += blockDim.x) {
       const unsigned long long v = acc[c];
       if (v != 0) {
         const int ci = oi + c % kTileBuf, cj = oj + (c / kTileBuf) % kTileBuf, ck = ok + c / (kTileBuf * kTileBuf);
-        if (ci < T.g.nx && cj < T.g.ny && ck < T.g.nz) atomicAdd(&rho[cell_index(T.g, ci, cj, ck)], v);
+        if (ci < T.g.nx && cj < T.g.ny && ck < T.g.nz)
+          add_checked(&rho[cell_index(T.g, ci, cj, ck)], (long long)v, T.g.range_err);
         acc[c] = 0;
       }
     }

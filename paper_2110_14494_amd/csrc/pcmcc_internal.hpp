@@ -79,6 +79,7 @@ struct PicArgs {
 struct DepositGeom {
   int nx, ny, nz;
   double x0, y0, z0, inv_dx;
+  unsigned* range_err;  // set to 1 on a weight outside [0, 2^31) or an int64 cell overflow
 };
 
 // Binned deposit: used from this many particles on (below, the direct

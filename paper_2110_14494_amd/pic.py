@@ -153,12 +153,14 @@ class Context:
             B.check(rc, self.h)
         return rc, {"merged_pairs": mp.value, "splits": sp.value}
 
-    def deposit(self, parts: Particles, grid: DeviceGrid, rho: torch.Tensor):
+    def deposit(self, parts: Particles, grid: DeviceGrid, rho: torch.Tensor, check: bool = True) -> int:
         t = parts.t
         gs = grid.struct()
-        B.check(B.lib().pcmcc_deposit(self.h, t["x"].data_ptr(), t["y"].data_ptr(), t["z"].data_ptr(),
-                                      t["w"].data_ptr(), parts.n_dev.data_ptr(), C.byref(gs), rho.data_ptr()),
-                self.h)
+        rc = B.lib().pcmcc_deposit(self.h, t["x"].data_ptr(), t["y"].data_ptr(), t["z"].data_ptr(),
+                                   t["w"].data_ptr(), parts.n_dev.data_ptr(), C.byref(gs), rho.data_ptr())
+        if check:
+            B.check(rc, self.h)
+        return rc
 
     def philox4x32_10(self, ctr: torch.Tensor, seed: int) -> torch.Tensor:
         assert ctr.dtype == torch.int32 and ctr.is_contiguous() and ctr.shape[-1] == 4

@@ -145,6 +145,80 @@ def test_deposit_bit_exact_streamer_grid(pic):
     ctx.close()
 
 
+def _deposit_rc(P, parts, grid):
+    ctx = P.Context(0)
+    dp = P.Particles.from_numpy(parts, max(parts["x"].size, 1))
+    dg = P.DeviceGrid(grid)
+    rho = dg.zeros_rho()
+    rc = ctx.deposit(dp, dg, rho, check=False)
+    out = rho.cpu().numpy()
+    ctx.close()
+    return rc, out
+
+
+def _at(pos, w):
+    n = w.size
+    return {"x": np.full(n, pos[0], np.float32), "y": np.full(n, pos[1], np.float32),
+            "z": np.full(n, pos[2], np.float32), "vx": np.zeros(n, np.float32), "vy": np.zeros(n, np.float32),
+            "vz": np.zeros(n, np.float32), "w": w.astype(np.float32), "id": np.arange(n, dtype=np.uint64)}
+
+
+@pytest.mark.parametrize("case", ["direct", "binned_global", "binned_lds", "binned_guard"])
+def test_deposit_range_error_matches_oracle(pic, case):
+    # Cell sums at and just below 2^63 units (2^31 electrons), on both
+    # schedules: few particles (direct kernel), 2^18 particles summed in LDS
+    # per block whose per-block partials overflow only in the global sum,
+    # ones whose LDS partial already overflows, and heavy tile runs that are
+    # summed again with checks but stay in range.
+    dx = 2.0 ** -15
+    grid = W.uniform_grid(16, dx, x0=0.0)
+    centre = (np.array([5, 9, 2]) + 0.5) * dx
+    if case == "binned_guard":
+        n = 2 ** 18
+        rng = np.random.default_rng(12)
+        pos = rng.uniform(8 * dx, 15.5 * dx, size=(3, n)).astype(np.float32)
+        parts = _at(centre, np.full(n, 2.0 ** 16))
+        parts["x"], parts["y"], parts["z"] = pos
+        print(f"[gpu] deposit range {case} n={n}", flush=True)
+        rc, got = _deposit_rc(pic, parts, grid)
+        orc, ref = oracle.deposit_rc(parts["x"], parts["y"], parts["z"], parts["w"], grid)
+        assert rc == orc == 0 and np.array_equal(got, ref)
+        return
+    if case == "direct":
+        sets = [np.array([2.0 ** 30, 2.0 ** 30 - 64]), np.array([2.0 ** 30, 2.0 ** 30]),
+                np.array([1.0, np.nan]), np.array([1.0, -1.0]), np.array([2.0 ** 31])]
+    elif case == "binned_global":
+        n = 2 ** 18
+        sets = [np.full(n - 1, 2.0 ** 13), np.full(n, 2.0 ** 13)]
+    else:
+        n = 2 ** 18
+        sets = [np.full(n, 2.0 ** 30)]
+    for w in sets:
+        parts = _at(centre, w)
+        print(f"[gpu] deposit range {case} n={w.size} w0={w[0]}", flush=True)
+        rc, got = _deposit_rc(pic, parts, grid)
+        orc, ref = oracle.deposit_rc(parts["x"], parts["y"], parts["z"], parts["w"], grid)
+        assert rc == orc, (rc, orc)
+        if rc == 0:
+            assert np.array_equal(got, ref)
+
+
+def test_update_weights_range_error_leaves_particles(pic):
+    dx = 1e-4
+    grid = W.uniform_grid(4, dx, (0.0, 0.0, 0.0))
+    p = _at((1.5 * dx, 1.5 * dx, 1.5 * dx), np.full(3, 2.0 ** 30))
+    ctx = pic.Context(0)
+    dp = pic.Particles.from_numpy(p, 16)
+    dg = pic.DeviceGrid(grid)
+    rc, _ = ctx.update_weights(dp, dg, 75.0, 1, 0, check=False)
+    back = dp.to_numpy()
+    ctx.close()
+    orc, _, _ = oracle.update_weights(p, grid, 75.0, seed=1, update_index=0)
+    assert rc == orc == -8
+    for k in p:
+        assert np.array_equal(back[k], p[k])
+
+
 # --- push / collide ----------------------------------------------------------------
 
 def _assert_parity(g, o, dx, trials):
