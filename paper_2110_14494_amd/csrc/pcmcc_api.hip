@@ -437,16 +437,20 @@ int ensure_weights(pcmcc_ctx* c, uint64_t n, size_t ncell) {
     dfree(c->wt.idx1);
     dfree(c->wt.key0);
     dfree(c->wt.key1);
+    dfree(c->wt.key2);
     dfree(c->wt.pos);
     dfree(c->wt.cnt);
     dfree(c->wt.temp);
     c->wt = WeightWork{};
     c->wt_n = 0;
+    // room for growth: the count rises between updates of a run
+    n = n + n / 2;
     size_t tb = 0;
     HIP_TRY(c, weight_temp_bytes(n, &tb));
     if (dalloc(&c->wt.cls, n) != hipSuccess || dalloc(&c->wt.idx0, n) != hipSuccess ||
         dalloc(&c->wt.idx1, n) != hipSuccess || dalloc(&c->wt.key0, n) != hipSuccess ||
-        dalloc(&c->wt.key1, n) != hipSuccess || dalloc(&c->wt.pos, n) != hipSuccess ||
+        dalloc(&c->wt.key1, n) != hipSuccess || dalloc(&c->wt.key2, n) != hipSuccess ||
+        dalloc(&c->wt.pos, n) != hipSuccess ||
         dalloc(&c->wt.cnt, n) != hipSuccess || dalloc(&c->wt.counters, 4) != hipSuccess ||
         hipMalloc(&c->wt.temp, std::max<size_t>(tb, 16)) != hipSuccess) {
       (void)hipGetLastError();
@@ -565,6 +569,7 @@ int pcmcc_destroy(pcmcc_ctx* c) {
   dfree(c->wt.idx1);
   dfree(c->wt.key0);
   dfree(c->wt.key1);
+  dfree(c->wt.key2);
   dfree(c->wt.pos);
   dfree(c->wt.cnt);
   dfree(c->wt.counters);

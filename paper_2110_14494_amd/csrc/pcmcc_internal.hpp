@@ -117,6 +117,7 @@ struct WeightWork {
   uint8_t* cls;                 // [n] class per particle
   uint32_t *idx0, *idx1;        // [n] candidate indices (sort ping-pong)
   uint64_t *key0, *key1;        // [n] sort keys
+  uint64_t* key2;               // [n] candidates' (cell, energy) keys by slot
   uint32_t *pos, *cnt;          // [n] output counts and positions
   unsigned long long* counters;  // [4] candidates, merged pairs
   void* temp;

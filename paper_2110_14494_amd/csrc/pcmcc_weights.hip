@@ -11,8 +11,9 @@
 // w_a + w_b.  A split halves the weight and adds a copy whose id is the
 // (second, third) words of the particle's weight-update draw.
 //
-// Schedule: classify (one thread per particle, candidates appended with one
-// atomic per wave), two stable radix sorts of the candidates (by id, then by
+// Schedule: classify (blocks of 2048 particles read in order; candidates
+// appended with one atomic per block, each with its id and its (cell,
+// energy) key), two stable radix sorts of the candidates (by id, then by
 // cell and energy; rocPRIM), run starts of the cells by a max-scan, pairing
 // (one thread per candidate position), and an exclusive scan of the output
 // counts (0 removed, 1 kept, 2 split) that places every particle and copy in
@@ -54,37 +55,94 @@ __device__ __forceinline__ uint32_t wt_energy_bits(float vx, float vy, float vz)
   return __float_as_uint((float)((a * a + b * b) + c * c));
 }
 
-__global__ void k_wt_classify(Soa cur, uint64_t n, WeightGeom g, const int64_t* __restrict__ rho,
-                              uint8_t* __restrict__ cls, uint32_t* __restrict__ cand_idx,
-                              uint64_t* __restrict__ cand_id, unsigned long long* n_cand) {
+constexpr int kWtBlock = 256;
+constexpr int kWtPer = 8;                       // particles per thread and tile
+constexpr int kWtTile = kWtBlock * kWtPer;
+
+// Classification of tile [base, base + kWtTile): particle base + j kWtBlock
+// + threadIdx.x for j < kWtPer (coalesced).  The merge candidates of a tile
+// take consecutive slots reserved with one atomic; slot k holds the
+// particle's index, id and (cell << 32 | energy bits) key.
+__global__ __launch_bounds__(kWtBlock) void k_wt_classify(Soa cur, uint64_t n, WeightGeom g,
+                                                           const int64_t* __restrict__ rho, uint8_t* __restrict__ cls,
+                                                           uint32_t* __restrict__ cand_idx,
+                                                           uint64_t* __restrict__ cand_id,
+                                                           uint64_t* __restrict__ cand_key,
+                                                           unsigned long long* n_cand) {
 #pragma clang fp contract(off)
-  for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < n; base += (uint64_t)gridDim.x * blockDim.x) {
-    const uint64_t i = base + threadIdx.x;
-    uint8_t c = WC_KEEP;
-    if (i < n) {
-      const uint64_t cell = wt_cell(g, cur.x[i], cur.y[i], cur.z[i]);
-      const double omega = fmax(ldexp((double)rho[cell], -32) / g.n_ppc, 1.0);
-      const double w = (double)cur.w[i];
-      if (w < (2.0 / 3.0) * omega)
-        c = WC_MERGE;
-      else if (w > 1.5 * omega)
-        c = WC_SPLIT;
-      cls[i] = c;
+  __shared__ uint32_t s_wave[kWtBlock / 64];
+  __shared__ unsigned long long s_base;
+  const uint32_t wave = threadIdx.x / 64;
+  for (uint64_t base = (uint64_t)blockIdx.x * kWtTile; base < n; base += (uint64_t)gridDim.x * kWtTile) {
+    uint32_t merge = 0;  // bit j: item j is a merge candidate
+    uint64_t cell[kWtPer];
+#pragma unroll
+    for (int j = 0; j < kWtPer; ++j) {
+      const uint64_t i = base + (uint64_t)j * kWtBlock + threadIdx.x;
+      cell[j] = 0;
+      if (i < n) {
+        cell[j] = wt_cell(g, cur.x[i], cur.y[i], cur.z[i]);
+        const double omega = fmax(ldexp((double)rho[cell[j]], -32) / g.n_ppc, 1.0);
+        const double w = (double)cur.w[i];
+        uint8_t c = WC_KEEP;
+        if (w < (2.0 / 3.0) * omega) {
+          c = WC_MERGE;
+          merge |= 1u << j;
+        } else if (w > 1.5 * omega) {
+          c = WC_SPLIT;
+        }
+        cls[i] = c;
+      }
     }
-    if (c == WC_MERGE) {
-      const uint64_t k = wave_reserve(n_cand);
-      cand_idx[k] = (uint32_t)i;
-      cand_id[k] = cur.id[i];
+    // block-wide exclusive prefix of the candidate counts
+    const uint32_t mine = (uint32_t)__popc(merge);
+    uint32_t incl = mine;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t o = __shfl_up(incl, d, 64);
+      if ((int)lane_id() >= d) incl += o;
     }
+    if (lane_id() == 63) s_wave[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < kWtBlock / 64; ++w) {
+      const uint32_t t = s_wave[w];
+      before += (uint32_t)w < wave ? t : 0u;
+      total += t;
+    }
+    if (threadIdx.x == 0) s_base = total ? atomicAdd(n_cand, (unsigned long long)total) : 0ull;
+    __syncthreads();
+    uint64_t k = s_base + before + (incl - mine);
+#pragma unroll
+    for (int j = 0; j < kWtPer; ++j) {
+      if (merge & (1u << j)) {
+        const uint64_t i = base + (uint64_t)j * kWtBlock + threadIdx.x;
+        cand_idx[k] = (uint32_t)i;
+        cand_id[k] = cur.id[i];
+        cand_key[k] = (cell[j] << 32) | wt_energy_bits(cur.vx[i], cur.vy[i], cur.vz[i]);
+        ++k;
+      }
+    }
+    __syncthreads();  // s_wave and s_base are reused by the next tile
   }
 }
 
-__global__ void k_wt_key2(const uint32_t* __restrict__ idx, uint64_t m, Soa cur, WeightGeom g,
+// After the sort by id (values: candidate slots), the slots' particle
+// indices and (cell, energy) keys in that order.
+__global__ void k_wt_key2(const uint32_t* __restrict__ slot, uint64_t m, const uint32_t* __restrict__ cand_idx,
+                          const uint64_t* __restrict__ cand_key, uint32_t* __restrict__ idx,
                           uint64_t* __restrict__ key2) {
   for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m; k += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t i = idx[k];
-    key2[k] = (wt_cell(g, cur.x[i], cur.y[i], cur.z[i]) << 32) | wt_energy_bits(cur.vx[i], cur.vy[i], cur.vz[i]);
+    const uint32_t sk = slot[k];
+    idx[k] = cand_idx[sk];
+    key2[k] = cand_key[sk];
   }
+}
+
+__global__ void k_wt_iota(uint32_t* __restrict__ a, uint64_t m) {
+  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m; k += (uint64_t)gridDim.x * blockDim.x)
+    a[k] = (uint32_t)k;
 }
 
 __global__ void k_wt_heads(const uint64_t* __restrict__ key2, uint64_t m, uint32_t* __restrict__ head) {
@@ -95,6 +153,7 @@ __global__ void k_wt_heads(const uint64_t* __restrict__ key2, uint64_t m, uint32
 __global__ void k_wt_pair(const uint64_t* __restrict__ key2, const uint32_t* __restrict__ idx,
                           const uint32_t* __restrict__ run_start, uint64_t m, Soa cur, uint8_t* __restrict__ cls,
                           Key key, uint32_t update_index, unsigned long long* n_pairs) {
+  unsigned long long pairs = 0;  // the wave's pairs, counted by lane 0
   for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < m; base += (uint64_t)gridDim.x * blockDim.x) {
     const uint64_t k = base + threadIdx.x;
     bool paired = false;
@@ -114,9 +173,9 @@ __global__ void k_wt_pair(const uint64_t* __restrict__ key2, const uint32_t* __r
       }
       paired = true;
     }
-    const uint64_t mask = __ballot(paired);
-    if (lane_id() == 0 && mask) atomicAdd(n_pairs, (unsigned long long)__popcll(mask));
+    pairs += (unsigned long long)__popcll(__ballot(paired));
   }
+  if (lane_id() == 0 && pairs) atomicAdd(n_pairs, pairs);
 }
 
 __global__ void k_wt_counts(const uint8_t* __restrict__ cls, uint64_t n, uint32_t* __restrict__ cnt) {
@@ -172,18 +231,22 @@ hipError_t launch_weight_update(const Soa& cur, const Soa& out, uint64_t n, cons
                                 uint64_t* pairs_out, uint64_t* splits_out, hipStream_t stream) {
   hipError_t e = hipMemsetAsync(W.counters, 0, 4 * sizeof(unsigned long long), stream);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_wt_classify, dim3(blocks_for(n)), dim3(256), 0, stream, cur, n, g, rho, W.cls, W.idx0,
-                     W.key0, W.counters);
+  const uint64_t tiles = (n + kWtTile - 1) / kWtTile;
+  hipLaunchKernelGGL(k_wt_classify, dim3((unsigned)(tiles < 8192 ? tiles : 8192)), dim3(kWtBlock), 0, stream, cur, n,
+                     g, rho, W.cls, W.idx0, W.key0, W.key2, W.counters);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   unsigned long long m = 0;
   if ((e = hipMemcpyAsync(&m, W.counters, sizeof(m), hipMemcpyDeviceToHost, stream)) != hipSuccess) return e;
   if ((e = hipStreamSynchronize(stream)) != hipSuccess) return e;
   size_t tb = W.temp_bytes;
   if (m > 1) {
-    // candidates by id, then (stable) by cell and energy
-    e = rocprim::radix_sort_pairs(W.temp, tb, W.key0, W.key1, W.idx0, W.idx1, (size_t)m, 0, 64, stream);
+    // candidates by id (values: slots), then (stable) by cell and energy
+    hipLaunchKernelGGL(k_wt_iota, dim3(blocks_for(m)), dim3(256), 0, stream, W.pos, (uint64_t)m);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    e = rocprim::radix_sort_pairs(W.temp, tb, W.key0, W.key1, W.pos, W.cnt, (size_t)m, 0, 64, stream);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_wt_key2, dim3(blocks_for(m)), dim3(256), 0, stream, W.idx1, (uint64_t)m, cur, g, W.key0);
+    hipLaunchKernelGGL(k_wt_key2, dim3(blocks_for(m)), dim3(256), 0, stream, W.cnt, (uint64_t)m, W.idx0, W.key2,
+                       W.idx1, W.key0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     tb = W.temp_bytes;
     e = rocprim::radix_sort_pairs(W.temp, tb, W.key0, W.key1, W.idx1, W.idx0, (size_t)m, 0, 32 + g.cell_bits,
