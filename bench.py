@@ -13,9 +13,11 @@ starting particles with one device copy (inside the timed region).
 value = particle-steps / second of the whole timed region.
 
 Also reported: the roofline of the step kernel (HIP events), the CPU oracle
-on a bounded sample, the streamer stage run for all of its 200 steps under
-super-particle weight control (N_ppc = 75, update when the count has grown
-by 1.25x), and the coefficient path: batched swarms against the
+on a bounded sample, the streamer stage under super-particle weight control
+(N_ppc = 75, update when the count has grown by 1.25x) run until its 200
+steps, the capacity or the deposit's fixed-point range ends it (the fixed
+tip field grows the electron number without bound), and the coefficient
+path: batched swarms against the
 plain per-E/N swarm, surrogate training, held-out fallback and BF16
 inference on 1e8 reduced fields.  Prints one JSON line.
 """
@@ -219,10 +221,11 @@ def pic_leg(a, ctx, pic):
 
 
 def weights_leg(a, ctx, pic):
-    """The streamer stage for all of its steps under super-particle weight
-    control: whenever the count has grown by the growth factor since the last
-    update, particles are merged and split towards N_ppc per cell (Sec. 2.1.2)
-    and the step loop resumes.  One untimed run, then one timed run."""
+    """The streamer stage under super-particle weight control: whenever the
+    count has grown by the growth factor since the last update, particles are
+    merged and split towards N_ppc per cell (Sec. 2.1.2) and the step loop
+    resumes, until the stage's steps, the capacity or the fixed-point range of
+    the density ends the call.  One untimed run, then one timed run."""
     import torch
     from paper_2110_14494_amd import workloads as W
     cfg = W.streamer_config(n=a.n or 2 ** 24)
