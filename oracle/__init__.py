@@ -3,8 +3,9 @@
 TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the benchmark's
 CPU-baseline leg may import this package.  It shares no code with the HIP
 library: the particle update, the tables and the deposit are written in plain
-double-precision C++ (``pcmcc_oracle.cpp``), the swarm estimators and the MLP
-in NumPy (``estimators.py``, ``mlp.py``).
+double-precision C++ (``pcmcc_oracle.cpp``), the swarm estimators, the MLP and
+the electrostatics and time step of the self-consistent step in NumPy/SciPy
+(``estimators.py``, ``mlp.py``, ``field.py``).
 
 This module only loads the compiled oracle (building it with g++ if needed)
 and converts NumPy arrays to and from its C entry points.
@@ -70,7 +71,7 @@ def lib():
             L.orc_lookup.argtypes = [C.POINTER(Problem), C.c_int64, vp, vp, vp, vp]
             L.orc_pic_run.argtypes = [C.POINTER(Problem), C.POINTER(Grid)] + [vp] * 8 + [
                 vp, C.c_int64, C.c_double, C.c_int, C.c_uint64, C.c_uint64, vp, C.c_int, C.c_double, C.c_double,
-                vp, vp]
+                vp, vp, vp, vp, C.c_int64, vp]
             L.orc_update_weights.argtypes = [vp] * 8 + [C.c_int64, C.c_int, C.c_int, C.c_int] + [C.c_double] * 5 + [
                 C.c_uint64, C.c_uint64] + [vp] * 8 + [C.c_int64, vp, vp]
             L.orc_deposit.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_int, C.c_int, C.c_int,
@@ -166,13 +167,15 @@ def lookup(species: dict, tables: dict, eps, s_ub=None):
 
 def pic_run(species: dict, tables: dict, grid: dict, parts: dict, dt: float, n_steps: int,
             seed: int, step0: int = 0, capacity: int | None = None, n_threads: int = 0, n_ppc: float = 0.0,
-            growth: float = 1.25, n_ref: int = 0):
+            growth: float = 1.25, n_ref: int = 0, events: bool = False):
     """Runs the PIC-MCC update on a copy of `parts` (x, y, z, vx, vy, vz, w, id).
 
     With n_ppc > 0 the super-particle weights are updated whenever the count
     exceeds floor(growth * n_ref) after a step (n_ref = 0: the start count).
     Returns (rc, parts_out, stats) with parts_out in double precision; stats
-    also holds weight_updates, merged_pairs, splits and n_ref."""
+    also holds weight_updates, merged_pairs, splits and n_ref, and with
+    events=True the committed steps' ionization and attachment events as
+    float32 arrays [k, 4] (x, y, z, w) under ion_events and att_events."""
     pb, k1 = make_problem(species, tables)
     g, k2 = make_grid(grid)
     n = int(np.asarray(parts["x"]).size)
@@ -188,17 +191,25 @@ def pic_run(species: dict, tables: dict, grid: dict, parts: dict, dt: float, n_s
     stats = np.zeros(12, dtype=np.int64)
     wstats = np.zeros(3, dtype=np.int64)
     nref = C.c_int64(int(n_ref))
+    ev_cap = 2 * cap if events else 0
+    ion = np.zeros((ev_cap, 4), dtype=np.float32)
+    att = np.zeros((ev_cap, 4), dtype=np.float32)
+    ev_n = np.zeros(2, dtype=np.int64)
     rc = lib().orc_pic_run(C.byref(pb), C.byref(g), *[_ptr(arrs[k]) for k in
                                                      ("x", "y", "z", "vx", "vy", "vz", "w")],
                            _ptr(ids), C.byref(n_io), cap, float(dt), int(n_steps), int(seed),
                            int(step0), _ptr(stats), int(n_threads), float(n_ppc), float(growth), C.byref(nref),
-                           _ptr(wstats))
+                           _ptr(wstats), _ptr(ion) if events else None, _ptr(att) if events else None, ev_cap,
+                           _ptr(ev_n) if events else None)
     del k1, k2
     m = n_io.value
     out = {k: v[:m].copy() for k, v in arrs.items()}
     out["id"] = ids[:m].copy()
     st = dict(zip(STATS_FIELDS, (int(s) for s in stats)))
     st.update(weight_updates=int(wstats[0]), merged_pairs=int(wstats[1]), splits=int(wstats[2]), n_ref=nref.value)
+    if events:
+        st["ion_events"] = ion[:min(int(ev_n[0]), ev_cap)].copy()
+        st["att_events"] = att[:min(int(ev_n[1]), ev_cap)].copy()
     return rc, out, st
 
 

@@ -475,13 +475,22 @@ void set_threads(int n_threads) {
 #endif
 }
 
+// A charge-creating event: where an ionization left its positive ion (the
+// newborn's recorded position) or an attachment its negative ion (the
+// electron's position at attachment, rounded to single precision), with the
+// electron's weight.
+struct Event {
+  float x, y, z, w;
+};
+
 // One step of a particle population: every particle from t = 0, then the
 // newborns from their birth times, generation after generation until none
-// are left.  Survivors (alive and accepted by `keep`) are returned in `out`.
+// are left.  Survivors (alive and accepted by `keep`) are returned in `out`;
+// ionization and attachment events are appended to ion_ev / att_ev if given.
 template <class Accel, class Keep>
 void run_step(const Tables& T, const Species& S, const Accel& accel, const std::vector<Particle>& in,
               double dt, uint32_t key0, uint32_t key1, uint64_t step, const Keep& keep, std::vector<Particle>& out,
-              Counters& cnt) {
+              Counters& cnt, std::vector<Event>* ion_ev = nullptr, std::vector<Event>* att_ev = nullptr) {
   out.clear();
   std::vector<Pending> work(in.size());
   for (size_t i = 0; i < in.size(); ++i) work[i] = Pending{in[i], 0.0};
@@ -491,6 +500,7 @@ void run_step(const Tables& T, const Species& S, const Accel& accel, const std::
     {
       std::vector<Particle> my_out;
       std::vector<Pending> my_births;
+      std::vector<Event> my_att;
       Counters my_cnt;
 #pragma omp for schedule(static)
       for (int64_t i = 0; i < (int64_t)work.size(); ++i) {
@@ -503,12 +513,18 @@ void run_step(const Tables& T, const Species& S, const Accel& accel, const std::
           } else {
             my_cnt.lost++;
           }
+        } else if (r == 1 && att_ev) {
+          my_att.push_back(Event{(float)p.x[0], (float)p.x[1], (float)p.x[2], (float)p.w});
         }
       }
 #pragma omp critical
       {
         out.insert(out.end(), my_out.begin(), my_out.end());
         next_gen.insert(next_gen.end(), my_births.begin(), my_births.end());
+        if (ion_ev)
+          for (const Pending& b : my_births)
+            ion_ev->push_back(Event{(float)b.p.x[0], (float)b.p.x[1], (float)b.p.x[2], (float)b.p.w});
+        if (att_ev) att_ev->insert(att_ev->end(), my_att.begin(), my_att.end());
         cnt.add(my_cnt);
       }
     }
@@ -688,7 +704,7 @@ int orc_lookup(const orc_problem* pb, int64_t m, const double* eps, double* C_ou
 int orc_pic_run(const orc_problem* pb, const orc_grid* g, double* x, double* y, double* z, double* vx, double* vy,
                 double* vz, double* w, uint64_t* id, int64_t* n_inout, int64_t capacity, double dt, int n_steps,
                 uint64_t seed, uint64_t step0, int64_t* stats, int n_threads, double n_ppc, double growth,
-                int64_t* n_ref, int64_t* wstats) {
+                int64_t* n_ref, int64_t* wstats, float* ion_ev, float* att_ev, int64_t ev_cap, int64_t* ev_counts) {
   Species S;
   Tables T;
   int rc = build_tables(pb, S, T);
@@ -756,13 +772,20 @@ int orc_pic_run(const orc_problem* pb, const orc_grid* g, double* x, double* y, 
   int64_t updates = 0;
   int64_t nref = n_ref && *n_ref > 0 ? *n_ref : (int64_t)cur.size();
   rc = 0;
+  const bool events = ion_ev && att_ev && ev_counts;
+  std::vector<Event> ions, atts, step_ions, step_atts;
   for (int s = 0; s < n_steps; ++s) {
     Counters cnt;
-    run_step(T, S, accel, cur, dt, key0, key1, step0 + s, inside, nxt, cnt);
+    step_ions.clear();
+    step_atts.clear();
+    run_step(T, S, accel, cur, dt, key0, key1, step0 + s, inside, nxt, cnt, events ? &step_ions : nullptr,
+             events ? &step_atts : nullptr);
     if ((int64_t)nxt.size() > capacity) {
       rc = -2;
       break;
     }
+    ions.insert(ions.end(), step_ions.begin(), step_ions.end());
+    atts.insert(atts.end(), step_atts.begin(), step_atts.end());
     particle_steps += (int64_t)cur.size();
     cur.swap(nxt);
     total.add(cnt);
@@ -783,6 +806,16 @@ int orc_pic_run(const orc_problem* pb, const orc_grid* g, double* x, double* y, 
     }
   }
   if (n_ref) *n_ref = nref;
+  if (events) {
+    ev_counts[0] = (int64_t)ions.size();
+    ev_counts[1] = (int64_t)atts.size();
+    if ((int64_t)ions.size() > ev_cap || (int64_t)atts.size() > ev_cap) {
+      if (rc == 0) rc = -2;
+    } else {
+      std::memcpy(ion_ev, ions.data(), ions.size() * sizeof(Event));
+      std::memcpy(att_ev, atts.data(), atts.size() * sizeof(Event));
+    }
+  }
   if (wstats) {
     wstats[0] = updates;
     wstats[1] = wc.merged_pairs;
