@@ -106,6 +106,8 @@ typedef struct pcmcc_stats {
   int64_t merged_pairs;          /* pairs merged by those updates */
   int64_t splits;                /* particles split by those updates */
   double weight_ms;              /* device time of those updates */
+  double field_ms;               /* self-consistent steps: device time of densities, potential and field */
+  int64_t mg_cycles;             /* self-consistent steps: multigrid V-cycles */
 } pcmcc_stats;
 
 /* Version string, static storage. */
@@ -346,6 +348,73 @@ int pcmcc_set_weight_control(pcmcc_ctx* ctx, double n_ppc, double growth);
  * stream. */
 int pcmcc_update_weights(pcmcc_ctx* ctx, const pcmcc_particles* p, const pcmcc_grid* grid, double n_ppc,
                          uint64_t seed, uint64_t update_index, int64_t* merged_pairs, int64_t* splits);
+
+/* ---- Self-consistent step (Sec. 2.5, Sec. 2.3, Sec. 2.1.4) ----------------
+ * Space charge rho = e (n_+ - n_e - n_-), each density a fixed-point CIC grid
+ * as above (int64, 2^-32 electrons per unit, laid out like the field).  The
+ * potential of the space charge solves lap phi = -rho / eps0 (Sec. 2.5, the
+ * sign read as a typo) on the cell centres with phi = 0 on the two z faces and
+ * zero normal derivative on the x and y faces (Sec. 2.3): the 7-point stencil
+ * with ghost cells (Dirichlet ghost = -phi of the boundary cell, Neumann ghost
+ * = phi).  The caller's grid field is the applied field (it stands in for the
+ * electrode and the applied voltage); the electrons see E = E_applied -
+ * grad phi, central differences with the same ghosts.  Ions do not move. */
+
+/* Geometric multigrid V(2,2) cycles (double precision) on phi (device, double
+ * [nz][ny][nx], the start value and the result) until max |residual| <= tol *
+ * max |rhs| or max_cycles; the grid is halved while every dimension is even
+ * and above 2, and the coarsest grid must hold at most 2048 cells (else
+ * PCMCC_EINVAL).  n_pos, n_e, n_neg: device int64 densities.  cycles_out and
+ * rel_residual_out (host, nullable) receive the cycles run and the final
+ * relative residual.  Synchronises the stream. */
+int pcmcc_solve_potential(pcmcc_ctx* ctx, const pcmcc_grid* grid, const int64_t* n_pos, const int64_t* n_e,
+                          const int64_t* n_neg, double* phi, double tol, int max_cycles, int* cycles_out,
+                          double* rel_residual_out);
+
+/* E_out (device float4 per cell, 4th component 0) = applied->E - grad phi. */
+int pcmcc_field_from_potential(pcmcc_ctx* ctx, const pcmcc_grid* applied, const double* phi, float* E_out);
+
+/* Speed at the 90 % quantile (Sec. 2.1.4): with keys |v|^2 = (vx^2 + vy^2) +
+ * vz^2 in double from the single-precision components, rounded to single
+ * precision, the key of rank ceil(9 n / 10) in ascending order (exact radix
+ * selection); *v90_out = its square root (0 for no particles).  Device arrays,
+ * *n_dev device count. */
+int pcmcc_speed_quantile(pcmcc_ctx* ctx, const float* vx, const float* vy, const float* vz, const int64_t* n_dev,
+                         double* v90_out);
+
+typedef struct pcmcc_sc_opts {
+  int adaptive;          /* 0: every step takes *dt_inout; 1: the Sec. 2.1.4 rule below */
+  double dt_max;         /* upper bound of the adaptive step (s) */
+  double cfl;            /* dt <= cfl dx / v90 (the paper: 0.5) */
+  double growth_max;     /* the electron number may grow by this factor per step (the paper: 1.2) */
+  int mu_n;              /* electron mobility table: mu N (1/(V m s)) at mu_n log-spaced E/N nodes */
+  double mu_EN_lo, mu_EN_hi; /* (Td) first and last node; mu_n = 1: a constant */
+  const double* mu_N;    /* host [mu_n] */
+  double mg_tol;         /* multigrid relative residual */
+  int mg_max_cycles;
+} pcmcc_sc_opts;
+
+/* n_steps self-consistent steps.  Before each step the field is computed from
+ * the present densities (electrons deposited from p, ions from n_pos and
+ * n_neg); the electrons then take one step of pcmcc_push_collide_deposit in
+ * that field (weight control applies as set); every ionization adds the
+ * newborn's charge to n_pos at its position and every attachment the
+ * electron's charge to n_neg (device int64 grids, caller-owned, accumulated:
+ * initialise n_pos with the electron density for a neutral seed, Sec. 2.3).
+ * With opts->adaptive the next step is dt = min(dt_max, cfl dx / v90,
+ * eps0 / (e n_e,max mu_e), dt ln(growth_max) / ln(N_new / N_old)) with v90 as
+ * pcmcc_speed_quantile, n_e,max the largest electron density (first cell in
+ * x-fastest order), mu_e from the table at that cell's |E|/N (linear in
+ * ln E/N, clamped), N the sum of the weights (the last term only when N
+ * grew).  *dt_inout: host, the first step in, the next step out; dt_hist
+ * (host [n_steps], nullable) receives the steps taken.  phi (device double)
+ * is the multigrid start value and holds the last potential; E_out (device
+ * float4, nullable) the field of the final state.  On an error the particles
+ * and ion grids hold the state after stats->steps_done steps.  Synchronises
+ * the stream. */
+int pcmcc_streamer_steps(pcmcc_ctx* ctx, const pcmcc_particles* p, const pcmcc_grid* applied, int64_t* n_pos,
+                         int64_t* n_neg, double* phi, float* E_out, const pcmcc_sc_opts* opts, int n_steps,
+                         uint64_t seed, uint64_t step0, double* dt_inout, double* dt_hist, pcmcc_stats* stats);
 
 /* Deposit only (Sec. 2.1.3), same fixed-point rule and range as above
  * (PCMCC_ERANGE, rho unspecified, beyond it), on n_dev particles (device

@@ -80,6 +80,22 @@ struct pcmcc_ctx {
   int64_t* wt_rho = nullptr;
   size_t wt_cells = 0;
   int64_t* dev_n = nullptr;  // a device count for the deposit of the update
+  // self-consistent field: multigrid levels (u[0] is the caller's potential),
+  // the field the electrons see, the electron density, event lists, and the
+  // small reduction results
+  MgWork mg{};
+  double* mg_store = nullptr;
+  size_t mg_store_n = 0;
+  MgDims mg_dims0{0, 0, 0};
+  float4* sc_E = nullptr;
+  int64_t* sc_ne = nullptr;
+  size_t sc_cells = 0;
+  float* ev_store = nullptr;  // 8 lists of ev_cap floats
+  uint64_t ev_cap = 0;
+  unsigned long long* sc_red = nullptr;  // [0] max |f| bits [1] max |r| bits [2] ne max [3] first cell [4] sum w [5..6] events
+  unsigned long long* sc_host = nullptr;  // pinned copy
+  SelState* sel = nullptr;
+  unsigned* sel_hist = nullptr;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   // swarm batch scratch
   struct Swarm {
@@ -576,6 +592,14 @@ int pcmcc_destroy(pcmcc_ctx* c) {
   dfree(c->wt.temp);
   dfree(c->wt_rho);
   dfree(c->dev_n);
+  dfree(c->mg_store);
+  dfree(c->sc_E);
+  dfree(c->sc_ne);
+  dfree(c->ev_store);
+  dfree(c->sc_red);
+  dfree(c->sel);
+  dfree(c->sel_hist);
+  if (c->sc_host) (void)hipHostFree(c->sc_host);
   dfree(c->emax_bits);
   dfree(c->dep_err);
   if (c->host_ctl) (void)hipHostFree(c->host_ctl);
@@ -663,8 +687,10 @@ int pcmcc_init_tables(pcmcc_ctx* c, int n_e, double eps_min_eV, double eps_max_e
   return PCMCC_OK;
 }
 
-int pcmcc_push_collide_deposit(pcmcc_ctx* c, const pcmcc_particles* p, const pcmcc_grid* field, double dt,
-                               int n_steps, uint64_t seed, uint64_t step0, int64_t* rho, pcmcc_stats* stats) {
+// The step loop; with ev, the ionization and attachment events of the
+// committed steps are appended to its lists.
+static int push_impl(pcmcc_ctx* c, const pcmcc_particles* p, const pcmcc_grid* field, double dt, int n_steps,
+                     uint64_t seed, uint64_t step0, int64_t* rho, pcmcc_stats* stats, const EventSink* ev) {
   int rc = check_ready(c);
   if (rc) return rc;
   if (stats) std::memset(stats, 0, sizeof(*stats));
@@ -738,6 +764,7 @@ int pcmcc_push_collide_deposit(pcmcc_ctx* c, const pcmcc_particles* p, const pcm
   G.qm_abs = (float)std::fabs(A.S.qm);
   A.key = Key{(uint32_t)seed, (uint32_t)(seed >> 32)};
   A.dt = (float)dt;
+  if (ev) A.ev = *ev;
   // Step loop launches.  With weight control the kernel stops after the step
   // that takes the count above floor(growth * n_ref); the weights are then
   // updated (into the other particle buffer) and the loop resumes.
@@ -830,6 +857,11 @@ int pcmcc_push_collide_deposit(pcmcc_ctx* c, const pcmcc_particles* p, const pcm
                 (long long)h.steps_done);
   if (rc == PCMCC_ELIMIT) return fail(c, rc, "newborn generation limit reached after %lld steps", (long long)h.steps_done);
   return rc != PCMCC_OK ? rc : drc;
+}
+
+int pcmcc_push_collide_deposit(pcmcc_ctx* c, const pcmcc_particles* p, const pcmcc_grid* field, double dt,
+                               int n_steps, uint64_t seed, uint64_t step0, int64_t* rho, pcmcc_stats* stats) {
+  return push_impl(c, p, field, dt, n_steps, seed, step0, rho, stats, nullptr);
 }
 
 int pcmcc_set_weight_control(pcmcc_ctx* c, double n_ppc, double growth) {
@@ -1432,6 +1464,350 @@ int pcmcc_tables_lookup(pcmcc_ctx* c, int64_t n, const float* eps, float* cum_ou
   HIP_TRY(c, launch_lookup(table_view(c), species_view(c), eps, cum_out, s_ub, maj_out, n, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return PCMCC_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Self-consistent step (Sec. 2.5, Sec. 2.3, Sec. 2.1.4).
+
+namespace {
+
+constexpr double kEps0 = 8.8541878128e-12;
+constexpr double kQe = 1.602176634e-19;
+
+// The small reduction buffers.
+int ensure_red(pcmcc_ctx* c) {
+  if (!c->sc_red) {
+    HIP_TRY(c, dalloc(&c->sc_red, 8));
+    HIP_TRY(c, dalloc(&c->sel, 1));
+    HIP_TRY(c, dalloc(&c->sel_hist, 1u << 12));
+    HIP_TRY(c, hipHostMalloc((void**)&c->sc_host, 8 * sizeof(unsigned long long), hipHostMallocDefault));
+  }
+  return PCMCC_OK;
+}
+
+// Multigrid levels, field and density grids for g.
+int ensure_sc(pcmcc_ctx* c, const pcmcc_grid* g) {
+  const size_t ncell = (size_t)g->nx * g->ny * g->nz;
+  int r = ensure_red(c);
+  if (r) return r;
+  if (c->mg_dims0.nx != g->nx || c->mg_dims0.ny != g->ny || c->mg_dims0.nz != g->nz) {
+    MgDims d[kMgMaxLevels];
+    const int L = mg_levels(g->nx, g->ny, g->nz, d);
+    const MgDims dl = d[L - 1];
+    if ((size_t)dl.nx * dl.ny * dl.nz > (size_t)kMgCoarseMax)
+      return fail(c, PCMCC_EINVAL, "grid %dx%dx%d coarsens only to %dx%dx%d (> %d cells): use dimensions with more "
+                  "factors of two", g->nx, g->ny, g->nz, dl.nx, dl.ny, dl.nz, kMgCoarseMax);
+    size_t need = ncell;  // f of level 0
+    for (int l = 1; l < L; ++l) need += 2 * (size_t)d[l].nx * d[l].ny * d[l].nz;
+    if (c->mg_store_n < need) {
+      dfree(c->mg_store);
+      c->mg_store = nullptr;
+      c->mg_store_n = 0;
+      HIP_TRY(c, dalloc(&c->mg_store, need));
+      c->mg_store_n = need;
+    }
+    c->mg = MgWork{};
+    c->mg.levels = L;
+    double* q = c->mg_store;
+    c->mg.f[0] = q;
+    q += ncell;
+    for (int l = 0; l < L; ++l) c->mg.dims[l] = d[l];
+    for (int l = 1; l < L; ++l) {
+      const size_t n = (size_t)d[l].nx * d[l].ny * d[l].nz;
+      c->mg.u[l] = q;
+      c->mg.f[l] = q + n;
+      q += 2 * n;
+    }
+    c->mg_dims0 = MgDims{g->nx, g->ny, g->nz};
+  }
+  c->mg.dx = g->dx;
+  if (c->sc_cells < ncell) {
+    dfree(c->sc_E);
+    dfree(c->sc_ne);
+    c->sc_E = nullptr;
+    c->sc_ne = nullptr;
+    c->sc_cells = 0;
+    HIP_TRY(c, dalloc(&c->sc_E, ncell));
+    HIP_TRY(c, dalloc(&c->sc_ne, ncell));
+    c->sc_cells = ncell;
+  }
+  return PCMCC_OK;
+}
+
+int read_red(pcmcc_ctx* c, int first, int count) {
+  HIP_TRY(c, hipMemcpyAsync(c->sc_host + first, c->sc_red + first, count * sizeof(unsigned long long),
+                            hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return PCMCC_OK;
+}
+
+// phi (device, level-0 u) for the densities; cycles and relative residual out.
+int solve_potential(pcmcc_ctx* c, const pcmcc_grid* g, const int64_t* np, const int64_t* ne, const int64_t* nn,
+                    double* phi, double tol, int max_cycles, int* cycles, double* rel) {
+  const size_t ncell = (size_t)g->nx * g->ny * g->nz;
+  c->mg.u[0] = phi;
+  HIP_TRY(c, hipMemsetAsync(c->sc_red, 0, 2 * sizeof(unsigned long long), c->stream));
+  const double scale = -(kQe * 0x1p-32 / (g->dx * g->dx * g->dx)) / kEps0;
+  HIP_TRY(c, launch_sc_rhs(np, ne, nn, ncell, scale, c->mg.f[0], c->sc_red, c->stream));
+  int rc = read_red(c, 0, 1);
+  if (rc) return rc;
+  double fmax;
+  std::memcpy(&fmax, &c->sc_host[0], sizeof(double));
+  *cycles = 0;
+  *rel = 0;
+  if (fmax == 0) {  // no space charge: phi = 0
+    HIP_TRY(c, hipMemsetAsync(phi, 0, ncell * sizeof(double), c->stream));
+    return PCMCC_OK;
+  }
+  for (int it = 0; it < max_cycles; ++it) {
+    HIP_TRY(c, mg_vcycle(c->mg, 0, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->sc_red + 1, 0, sizeof(unsigned long long), c->stream));
+    HIP_TRY(c, launch_residual_max(c->mg, c->sc_red + 1, c->stream));
+    rc = read_red(c, 1, 1);
+    if (rc) return rc;
+    double rmax;
+    std::memcpy(&rmax, &c->sc_host[1], sizeof(double));
+    *cycles = it + 1;
+    *rel = rmax / fmax;
+    if (*rel <= tol) break;
+  }
+  return PCMCC_OK;
+}
+
+double mobility(const pcmcc_sc_opts* o, double EN_Td, double gas_N) {
+  if (o->mu_n == 1) return o->mu_N[0] / gas_N;
+  const double lo = std::log(o->mu_EN_lo), hi = std::log(o->mu_EN_hi);
+  double u = (std::log(std::max(EN_Td, 1e-300)) - lo) / (hi - lo) * (o->mu_n - 1);
+  u = std::min(std::max(u, 0.0), o->mu_n - 1.0);
+  const int i = std::min((int)std::floor(u), o->mu_n - 2);
+  const double f = u - i;
+  return ((1.0 - f) * o->mu_N[i] + f * o->mu_N[i + 1]) / gas_N;
+}
+
+}  // namespace
+
+int pcmcc_solve_potential(pcmcc_ctx* c, const pcmcc_grid* grid, const int64_t* n_pos, const int64_t* n_e,
+                          const int64_t* n_neg, double* phi, double tol, int max_cycles, int* cycles_out,
+                          double* rel_residual_out) {
+  if (!c) return fail(nullptr, PCMCC_EINVAL, "null context");
+  if (!valid_grid(grid) || !n_pos || !n_e || !n_neg || !phi) return fail(c, PCMCC_EINVAL, "invalid arguments");
+  if (!(tol > 0) || max_cycles < 1) return fail(c, PCMCC_EINVAL, "tol must be > 0 and max_cycles >= 1");
+  HIP_TRY(c, hipSetDevice(c->device));
+  int rc = ensure_sc(c, grid);
+  if (rc) return rc;
+  int cyc = 0;
+  double rel = 0;
+  rc = solve_potential(c, grid, n_pos, n_e, n_neg, phi, tol, max_cycles, &cyc, &rel);
+  if (rc) return rc;
+  if (cycles_out) *cycles_out = cyc;
+  if (rel_residual_out) *rel_residual_out = rel;
+  return PCMCC_OK;
+}
+
+int pcmcc_field_from_potential(pcmcc_ctx* c, const pcmcc_grid* applied, const double* phi, float* E_out) {
+  if (!c) return fail(nullptr, PCMCC_EINVAL, "null context");
+  if (!valid_grid(applied) || !phi || !E_out) return fail(c, PCMCC_EINVAL, "invalid arguments");
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, launch_sc_field((const float4*)applied->E, phi, applied->nx, applied->ny, applied->nz, applied->dx,
+                             (float4*)E_out, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return PCMCC_OK;
+}
+
+int pcmcc_speed_quantile(pcmcc_ctx* c, const float* vx, const float* vy, const float* vz, const int64_t* n_dev,
+                         double* v90_out) {
+  if (!c) return fail(nullptr, PCMCC_EINVAL, "null context");
+  if (!vx || !vy || !vz || !n_dev || !v90_out) return fail(c, PCMCC_EINVAL, "null argument");
+  HIP_TRY(c, hipSetDevice(c->device));
+  int rc = ensure_red(c);
+  if (rc) return rc;
+  HIP_TRY(c, hipMemcpyAsync(c->host_n, n_dev, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const int64_t n = *c->host_n;
+  if (n < 0) return fail(c, PCMCC_EINVAL, "negative count");
+  *v90_out = 0;
+  if (n == 0) return PCMCC_OK;
+  HIP_TRY(c, launch_speed_select(vx, vy, vz, n_dev, (uint64_t)n, c->sel, c->sel_hist, c->stream));
+  SelState st;
+  HIP_TRY(c, hipMemcpyAsync(&st, c->sel, sizeof(st), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  float key;
+  std::memcpy(&key, &st.prefix, sizeof(key));
+  *v90_out = std::sqrt((double)key);
+  return PCMCC_OK;
+}
+
+int pcmcc_streamer_steps(pcmcc_ctx* c, const pcmcc_particles* p, const pcmcc_grid* applied, int64_t* n_pos,
+                         int64_t* n_neg, double* phi, float* E_out, const pcmcc_sc_opts* o, int n_steps, uint64_t seed,
+                         uint64_t step0, double* dt_inout, double* dt_hist, pcmcc_stats* stats) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  if (!p || !p->x || !p->n_dev || !valid_grid(applied) || !n_pos || !n_neg || !phi || !o || !dt_inout)
+    return fail(c, PCMCC_EINVAL, "null argument");
+  if (!(*dt_inout > 0) || !std::isfinite(*dt_inout) || n_steps < 0) return fail(c, PCMCC_EINVAL, "invalid dt or steps");
+  if (o->adaptive && (!(o->dt_max > 0) || !(o->cfl > 0) || !(o->growth_max > 1) || o->mu_n < 1 || !o->mu_N ||
+                      (o->mu_n > 1 && !(o->mu_EN_hi > o->mu_EN_lo && o->mu_EN_lo > 0))))
+    return fail(c, PCMCC_EINVAL, "invalid time-step options");
+  if (!(o->mg_tol > 0) || o->mg_max_cycles < 1) return fail(c, PCMCC_EINVAL, "invalid multigrid options");
+  HIP_TRY(c, hipSetDevice(c->device));
+  rc = ensure_sc(c, applied);
+  if (rc) return rc;
+  const size_t ncell = (size_t)applied->nx * applied->ny * applied->nz;
+  // event lists: up to `capacity` ionizations and attachments per step
+  const uint64_t cap = (uint64_t)p->capacity;
+  if (c->ev_cap < cap) {
+    dfree(c->ev_store);
+    c->ev_store = nullptr;
+    c->ev_cap = 0;
+    HIP_TRY(c, dalloc(&c->ev_store, 8 * (size_t)cap));
+    c->ev_cap = cap;
+  }
+  EventSink ev;
+  float* e = c->ev_store;
+  const size_t ec = (size_t)c->ev_cap;
+  ev.ix = e; ev.iy = e + ec; ev.iz = e + 2 * ec; ev.iw = e + 3 * ec;
+  ev.ax = e + 4 * ec; ev.ay = e + 5 * ec; ev.az = e + 6 * ec; ev.aw = e + 7 * ec;
+  ev.n = c->sc_red + 5;
+  ev.cap = c->ev_cap;
+  ev.overflow = &c->ctl->overflow;
+  pcmcc_grid cur = *applied;
+  cur.E = (const float*)c->sc_E;
+  const double gas_N = c->gas_N;
+  double field_ms = 0, dep_ms = 0;
+  int64_t mg_cycles = 0;
+  // densities, potential and field of the present state
+  auto refresh = [&]() -> int {
+    HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->sc_ne, 0, ncell * sizeof(int64_t), c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->host_n, p->n_dev, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    int r = run_deposit(c, p->x, p->y, p->z, p->w, p->n_dev, (uint64_t)*c->host_n, applied, c->sc_ne);
+    if (r) return r;
+    int cyc = 0;
+    double rel = 0;
+    r = solve_potential(c, applied, n_pos, c->sc_ne, n_neg, phi, o->mg_tol, o->mg_max_cycles, &cyc, &rel);
+    if (r) return r;
+    mg_cycles += cyc;
+    HIP_TRY(c, launch_sc_field((const float4*)applied->E, phi, applied->nx, applied->ny, applied->nz, applied->dx,
+                               c->sc_E, c->stream));
+    HIP_TRY(c, hipEventRecord(c->ev[3], c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    float ms = 0;
+    HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[2], c->ev[3]));
+    field_ms += ms;
+    return PCMCC_OK;
+  };
+  auto weight_total = [&](double* out) -> int {
+    HIP_TRY(c, hipMemsetAsync(c->sc_red + 4, 0, sizeof(unsigned long long), c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->host_n, p->n_dev, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, launch_weight_sum(p->w, p->n_dev, (uint64_t)*c->host_n, (double*)(c->sc_red + 4), c->stream));
+    int r = read_red(c, 4, 1);
+    if (r) return r;
+    std::memcpy(out, &c->sc_host[4], sizeof(double));
+    return PCMCC_OK;
+  };
+  rc = refresh();
+  if (rc) return rc;
+  double n_old = 0;
+  if (o->adaptive) {
+    rc = weight_total(&n_old);
+    if (rc) return rc;
+  }
+  double dt = *dt_inout;
+  pcmcc_stats tot{};
+  int s = 0;
+  for (; s < n_steps; ++s) {
+    HIP_TRY(c, hipMemsetAsync(ev.n, 0, 2 * sizeof(unsigned long long), c->stream));
+    pcmcc_stats st{};
+    rc = push_impl(c, p, &cur, dt, 1, seed, step0 + (uint64_t)s, nullptr, &st, &ev);
+    if (rc) break;
+    tot.n = st.n;
+    tot.steps_done += st.steps_done;
+    tot.particle_steps += st.particle_steps;
+    tot.trials += st.trials;
+    tot.null_collisions += st.null_collisions;
+    for (int k = 0; k < 4; ++k) tot.real_collisions[k] += st.real_collisions[k];
+    tot.lost += st.lost;
+    tot.out_of_table += st.out_of_table;
+    tot.errors += st.errors;
+    tot.step_kernel_ms += st.step_kernel_ms;
+    tot.launch_block = st.launch_block;
+    tot.launch_grid = st.launch_grid;
+    tot.weight_updates += st.weight_updates;
+    tot.merged_pairs += st.merged_pairs;
+    tot.splits += st.splits;
+    tot.weight_ms += st.weight_ms;
+    // ions of the step's events
+    rc = read_red(c, 5, 2);
+    if (rc) break;
+    const uint64_t n_ion = c->sc_host[5], n_att = c->sc_host[6];
+    HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
+    if (n_ion) {
+      rc = run_deposit(c, ev.ix, ev.iy, ev.iz, ev.iw, (const int64_t*)ev.n, n_ion, applied, n_pos);
+      if (rc) break;
+    }
+    if (n_att) {
+      rc = run_deposit(c, ev.ax, ev.ay, ev.az, ev.aw, (const int64_t*)(ev.n + 1), n_att, applied, n_neg);
+      if (rc) break;
+    }
+    HIP_TRY(c, hipEventRecord(c->ev[3], c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    float ms = 0;
+    HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[2], c->ev[3]));
+    dep_ms += ms;
+    rc = refresh();
+    if (rc) break;
+    if (dt_hist) dt_hist[s] = dt;
+    if (o->adaptive) {
+      double v90 = 0;
+      rc = pcmcc_speed_quantile(c, p->vx, p->vy, p->vz, p->n_dev, &v90);
+      if (rc) break;
+      // the densest cell and the field there
+      c->sc_host[2] = 0x8000000000000000ull;
+      c->sc_host[3] = ~0ull;
+      HIP_TRY(c, hipMemcpyAsync(c->sc_red + 2, c->sc_host + 2, 2 * sizeof(unsigned long long), hipMemcpyHostToDevice,
+                                c->stream));
+      HIP_TRY(c, launch_densest(c->sc_ne, ncell, (long long*)(c->sc_red + 2), c->sc_red + 3, c->stream));
+      rc = read_red(c, 2, 2);
+      if (rc) break;
+      const long long ne_units = (long long)c->sc_host[2];
+      const uint64_t cell = c->sc_host[3];
+      double ne_max = 0, e_at = 0;
+      if (ne_units > 0 && cell < ncell) {
+        float4 Ec;
+        HIP_TRY(c, hipMemcpyAsync(&Ec, c->sc_E + cell, sizeof(Ec), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        ne_max = (double)ne_units * 0x1p-32 / (applied->dx * applied->dx * applied->dx);
+        const double ex = Ec.x, ey = Ec.y, ez = Ec.z;
+        e_at = std::sqrt(ex * ex + ey * ey + ez * ez);
+      }
+      const double mu_e = ne_max > 0 ? mobility(o, e_at / gas_N * 1e21, gas_N) : 0.0;
+      double n_new = 0;
+      rc = weight_total(&n_new);
+      if (rc) break;
+      double nd = o->dt_max;
+      if (v90 > 0) nd = std::min(nd, o->cfl * applied->dx / v90);
+      if (ne_max > 0 && mu_e > 0) nd = std::min(nd, kEps0 / (kQe * ne_max * mu_e));
+      if (n_old > 0 && n_new > n_old) nd = std::min(nd, dt * std::log(o->growth_max) / std::log(n_new / n_old));
+      dt = nd;
+      n_old = n_new;
+    }
+  }
+  *dt_inout = dt;
+  if (E_out) {
+    HIP_TRY(c, hipMemcpyAsync(E_out, c->sc_E, ncell * sizeof(float4), hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
+  if (stats) {
+    *stats = tot;
+    stats->deposit_kernel_ms = dep_ms;
+    stats->field_ms = field_ms;
+    stats->mg_cycles = mg_cycles;
+  }
+  return rc;
 }
 
 }  // extern "C"

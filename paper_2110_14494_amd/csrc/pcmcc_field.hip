@@ -1,0 +1,396 @@
+// Self-consistent field of the particle step (arXiv:2110.14494: Sec. 2.5
+// Poisson's equation and E = -grad phi, Sec. 2.3 boundary conditions,
+// Sec. 2.1.4 time step).
+//
+// * Space charge rho = e (n_+ - n_e - n_-) from the three int64 fixed-point
+//   density grids (2^-32 electrons per unit), lap phi = -rho / eps0.
+// * phi = 0 on the two z faces (Dirichlet), zero normal derivative on the x
+//   and y faces (homogeneous Neumann): 7-point stencil on cell centres with
+//   ghost cells (Dirichlet ghost = -phi of the boundary cell, Neumann ghost =
+//   phi).  The caller's field is the applied field; the field the electrons
+//   see is E_applied - grad phi (central differences, same ghosts).
+// * Geometric multigrid in double precision: V(2,2) cycles, red-black
+//   Gauss-Seidel smoothing, restriction by the mean of the 8 children,
+//   trilinear prolongation with the error's ghost rules, the coarsest grid
+//   (every dimension halved while all are even and above 2) solved by one
+//   block in LDS.  All passes are HBM-streaming stencils.
+// * Time-step ingredients: the 90 % speed quantile by a three-pass radix
+//   selection on |v|^2 keys (exact), the densest cell (largest fixed-point
+//   density, first in x-fastest order), and the sum of the weights.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+
+#include "pcmcc_internal.hpp"
+
+namespace pcmcc {
+
+namespace {
+
+__device__ __forceinline__ size_t idx3(int i, int j, int k, int nx, int ny) {
+  return ((size_t)k * ny + j) * nx + i;
+}
+
+// Non-negative doubles compare like their bit patterns.
+__device__ __forceinline__ void atomic_max_pos(unsigned long long* a, double v) {
+  atomicMax(a, (unsigned long long)__double_as_longlong(v));
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+  for (int d = 32; d > 0; d >>= 1) v = fmax(v, __shfl_xor(v, d, 64));
+  return v;
+}
+
+// Sum of the neighbours present and the diagonal of the stencil at (i,j,k):
+// a missing x/y neighbour is a Neumann ghost (diagonal 6 -> one less), a
+// missing z neighbour a Dirichlet ghost (one more).
+__device__ __forceinline__ double nb_sum(const double* u, int i, int j, int k, int nx, int ny, int nz, double& diag) {
+  const size_t c = idx3(i, j, k, nx, ny);
+  const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
+  double s = 0.0;
+  double d = 6.0;
+  if (i > 0) s += u[c - 1]; else d -= 1.0;
+  if (i < nx - 1) s += u[c + 1]; else d -= 1.0;
+  if (j > 0) s += u[c - sy]; else d -= 1.0;
+  if (j < ny - 1) s += u[c + sy]; else d -= 1.0;
+  if (k > 0) s += u[c - sz]; else d += 1.0;
+  if (k < nz - 1) s += u[c + sz]; else d += 1.0;
+  diag = d;
+  return s;
+}
+
+}  // namespace
+
+// Right-hand side of the finest level and its largest magnitude.
+__global__ void k_sc_rhs(const int64_t* __restrict__ np, const int64_t* __restrict__ ne,
+                         const int64_t* __restrict__ nn, size_t n, double scale, double* __restrict__ f,
+                         unsigned long long* fmax_bits) {
+#pragma clang fp contract(off)
+  double m = 0.0;
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (size_t)gridDim.x * blockDim.x) {
+    const double v = (((double)np[c] - (double)ne[c]) - (double)nn[c]) * scale;
+    f[c] = v;
+    m = fmax(m, fabs(v));
+  }
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0 && m > 0.0) atomic_max_pos(fmax_bits, m);
+}
+
+// One red-black Gauss-Seidel half sweep: cells with (i + j + k) % 2 == color.
+__global__ void k_mg_smooth(double* __restrict__ u, const double* __restrict__ f, int nx, int ny, int nz, double h2,
+                            int color) {
+#pragma clang fp contract(off)
+  const int hx = (nx + 1) / 2;
+  const size_t total = (size_t)hx * ny * nz;
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+    const int k = (int)(t / ((size_t)hx * ny));
+    const int j = (int)((t / hx) % ny);
+    const int i = 2 * (int)(t % hx) + ((j + k + color) & 1);
+    if (i >= nx) continue;
+    double d;
+    const double s = nb_sum(u, i, j, k, nx, ny, nz, d);
+    const size_t c = idx3(i, j, k, nx, ny);
+    u[c] = (s - h2 * f[c]) / d;
+  }
+}
+
+// Residual r = f - L u of the 8 children of every coarse cell, averaged into
+// the coarse right-hand side.
+__global__ void k_mg_restrict(const double* __restrict__ u, const double* __restrict__ f, int nx, int ny, int nz,
+                              double inv_h2, double* __restrict__ fc) {
+#pragma clang fp contract(off)
+  const int cx = nx / 2, cy = ny / 2, cz = nz / 2;
+  const size_t total = (size_t)cx * cy * cz;
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+    const int I = (int)(t % cx), J = (int)((t / cx) % cy), K = (int)(t / ((size_t)cx * cy));
+    double acc = 0.0;
+    for (int q = 0; q < 8; ++q) {
+      const int i = 2 * I + (q & 1), j = 2 * J + ((q >> 1) & 1), k = 2 * K + (q >> 2);
+      double d;
+      const double s = nb_sum(u, i, j, k, nx, ny, nz, d);
+      const size_t c = idx3(i, j, k, nx, ny);
+      acc += f[c] - (s - d * u[c]) * inv_h2;
+    }
+    fc[t] = 0.125 * acc;
+  }
+}
+
+// Coarse value with the error's ghost rule outside the grid.
+__device__ __forceinline__ double coarse_at(const double* U, int I, int J, int K, int cx, int cy, int cz) {
+  double sgn = 1.0;
+  I = min(max(I, 0), cx - 1);
+  J = min(max(J, 0), cy - 1);
+  if (K < 0) {
+    K = 0;
+    sgn = -1.0;
+  } else if (K >= cz) {
+    K = cz - 1;
+    sgn = -1.0;
+  }
+  return sgn * U[idx3(I, J, K, cx, cy)];
+}
+
+// u_fine += trilinear interpolation of the coarse correction.
+__global__ void k_mg_prolong(double* __restrict__ u, const double* __restrict__ U, int nx, int ny, int nz) {
+#pragma clang fp contract(off)
+  const int cx = nx / 2, cy = ny / 2, cz = nz / 2;
+  const size_t total = (size_t)nx * ny * nz;
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < total; c += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / ((size_t)nx * ny));
+    const int I = i >> 1, J = j >> 1, K = k >> 1;
+    const int I2 = I + ((i & 1) ? 1 : -1), J2 = J + ((j & 1) ? 1 : -1), K2 = K + ((k & 1) ? 1 : -1);
+    const double v = 27.0 * coarse_at(U, I, J, K, cx, cy, cz) +
+                     9.0 * (coarse_at(U, I2, J, K, cx, cy, cz) + coarse_at(U, I, J2, K, cx, cy, cz) +
+                            coarse_at(U, I, J, K2, cx, cy, cz)) +
+                     3.0 * (coarse_at(U, I2, J2, K, cx, cy, cz) + coarse_at(U, I2, J, K2, cx, cy, cz) +
+                            coarse_at(U, I, J2, K2, cx, cy, cz)) +
+                     coarse_at(U, I2, J2, K2, cx, cy, cz);
+    u[c] += v * (1.0 / 64.0);
+  }
+}
+
+// Coarsest level: one block, LDS, red-black sweeps (the level is at most
+// kMgCoarseMax cells).
+__global__ __launch_bounds__(256) void k_mg_coarse(double* __restrict__ u, const double* __restrict__ f, int nx,
+                                                    int ny, int nz, double h2, int iters) {
+#pragma clang fp contract(off)
+  __shared__ double s_u[kMgCoarseMax];
+  __shared__ double s_f[kMgCoarseMax];
+  const int n = nx * ny * nz;
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    s_u[c] = u[c];
+    s_f[c] = f[c];
+  }
+  __syncthreads();
+  for (int it = 0; it < iters; ++it) {
+    for (int color = 0; color < 2; ++color) {
+      for (int c = threadIdx.x; c < n; c += blockDim.x) {
+        const int i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
+        if (((i + j + k) & 1) != color) continue;
+        double d;
+        const double s = nb_sum(s_u, i, j, k, nx, ny, nz, d);
+        s_u[c] = (s - h2 * s_f[c]) / d;
+      }
+      __syncthreads();
+    }
+  }
+  for (int c = threadIdx.x; c < n; c += blockDim.x) u[c] = s_u[c];
+}
+
+// Largest |f - L u| on a level.
+__global__ void k_mg_residual_max(const double* __restrict__ u, const double* __restrict__ f, int nx, int ny, int nz,
+                                  double inv_h2, unsigned long long* rmax) {
+#pragma clang fp contract(off)
+  const size_t total = (size_t)nx * ny * nz;
+  double m = 0.0;
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < total; c += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / ((size_t)nx * ny));
+    double d;
+    const double s = nb_sum(u, i, j, k, nx, ny, nz, d);
+    m = fmax(m, fabs(f[c] - (s - d * u[c]) * inv_h2));
+  }
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0 && m > 0.0) atomic_max_pos(rmax, m);
+}
+
+// E = E_applied - grad phi at the centres (central differences with ghosts).
+__global__ void k_sc_field(const float4* __restrict__ Ea, const double* __restrict__ phi, int nx, int ny, int nz,
+                           double two_dx, float4* __restrict__ E) {
+#pragma clang fp contract(off)
+  const size_t total = (size_t)nx * ny * nz;
+  const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < total; c += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / sz);
+    const double p = phi[c];
+    const double xm = i > 0 ? phi[c - 1] : p, xp = i < nx - 1 ? phi[c + 1] : p;
+    const double ym = j > 0 ? phi[c - sy] : p, yp = j < ny - 1 ? phi[c + sy] : p;
+    const double zm = k > 0 ? phi[c - sz] : -p, zp = k < nz - 1 ? phi[c + sz] : -p;
+    const float4 a = Ea[c];
+    E[c] = make_float4((float)((double)a.x - (xp - xm) / two_dx), (float)((double)a.y - (yp - ym) / two_dx),
+                       (float)((double)a.z - (zp - zm) / two_dx), 0.0f);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Time-step ingredients.
+
+__device__ __forceinline__ uint32_t speed_key(float vx, float vy, float vz) {
+#pragma clang fp contract(off)
+  const double a = (double)vx, b = (double)vy, c = (double)vz;
+  return __float_as_uint((float)((a * a + b * b) + c * c));
+}
+
+// Radix-selection pass: histogram of the key bits [shift, shift + bits) of
+// the particles whose higher bits equal the state's prefix.
+__global__ __launch_bounds__(256) void k_sel_hist(const float* __restrict__ vx, const float* __restrict__ vy,
+                                                  const float* __restrict__ vz, const int64_t* n_dev,
+                                                  const SelState* st, int shift, int bits,
+                                                  unsigned* __restrict__ hist) {
+  __shared__ unsigned h[1 << 12];
+  const int nb = 1 << bits;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) h[b] = 0;
+  __syncthreads();
+  const uint64_t n = (uint64_t)*n_dev;
+  const int hi = shift + bits;
+  const uint32_t want = st->prefix;
+  for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t key = speed_key(vx[p], vy[p], vz[p]);
+    if (hi >= 32 || (key >> hi) == (want >> hi)) atomicAdd(&h[(key >> shift) & (uint32_t)(nb - 1)], 1u);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < nb; b += blockDim.x)
+    if (h[b]) atomicAdd(&hist[b], h[b]);
+}
+
+// Picks the bin holding the wanted rank; the first pass sets the rank
+// ceil(9 n / 10) from the count.
+__global__ void k_sel_pick(const int64_t* n_dev, unsigned* __restrict__ hist, SelState* st, int shift, int bits,
+                           int first) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (first) {
+    const uint64_t n = (uint64_t)*n_dev;
+    st->rank = n ? (9 * n + 9) / 10 : 0;
+    st->prefix = 0;
+  }
+  if (st->rank == 0) return;
+  uint64_t acc = 0;
+  const int nb = 1 << bits;
+  for (int b = 0; b < nb; ++b) {
+    const uint64_t h = hist[b];
+    if (acc + h >= st->rank) {
+      st->prefix |= (uint32_t)b << shift;
+      st->rank -= acc;
+      break;
+    }
+    acc += h;
+  }
+  for (int b = 0; b < nb; ++b) hist[b] = 0;  // ready for the next pass
+}
+
+// Largest fixed-point electron density, then the first cell holding it.
+__global__ void k_ne_max(const int64_t* __restrict__ ne, size_t n, long long* out) {
+  long long m = LLONG_MIN;
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (size_t)gridDim.x * blockDim.x)
+    m = max(m, (long long)ne[c]);
+  for (int d = 32; d > 0; d >>= 1) m = max(m, (long long)__shfl_xor(m, d, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, m);
+}
+
+__global__ void k_ne_first(const int64_t* __restrict__ ne, size_t n, const long long* mx,
+                           unsigned long long* first) {
+  const long long m = *mx;
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (size_t)gridDim.x * blockDim.x)
+    if ((long long)ne[c] == m) atomicMin(first, (unsigned long long)c);
+}
+
+__global__ void k_weight_sum(const float* __restrict__ w, const int64_t* n_dev, double* out) {
+  const uint64_t n = (uint64_t)*n_dev;
+  double s = 0.0;
+  for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (uint64_t)gridDim.x * blockDim.x)
+    s += (double)w[p];
+  for (int d = 32; d > 0; d >>= 1) s += __shfl_xor(s, d, 64);
+  if ((threadIdx.x & 63) == 0 && s != 0.0) atomicAdd(out, s);
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers.
+
+static unsigned grid_for(size_t n, unsigned cap = 16384) {
+  const size_t b = (n + 255) / 256;
+  return (unsigned)(b < cap ? (b > 0 ? b : 1) : cap);
+}
+
+int mg_levels(int nx, int ny, int nz, MgDims* dims) {
+  int L = 0;
+  dims[L++] = MgDims{nx, ny, nz};
+  while (L < kMgMaxLevels && nx % 2 == 0 && ny % 2 == 0 && nz % 2 == 0 && nx > 2 && ny > 2 && nz > 2) {
+    nx /= 2;
+    ny /= 2;
+    nz /= 2;
+    dims[L++] = MgDims{nx, ny, nz};
+  }
+  return L;
+}
+
+hipError_t launch_sc_rhs(const int64_t* np, const int64_t* ne, const int64_t* nn, size_t n, double scale, double* f,
+                         unsigned long long* fmax, hipStream_t s) {
+  hipLaunchKernelGGL(k_sc_rhs, dim3(grid_for(n)), dim3(256), 0, s, np, ne, nn, n, scale, f, fmax);
+  return hipGetLastError();
+}
+
+// One V(2,2) cycle from level l down.  u[l], f[l]: the level's arrays.
+hipError_t mg_vcycle(const MgWork& W, int l, hipStream_t s) {
+  const MgDims d = W.dims[l];
+  const size_t n = (size_t)d.nx * d.ny * d.nz;
+  const double h = W.dx * (double)(1 << l);
+  const double h2 = h * h;
+  if (l == W.levels - 1) {
+    const int m = d.nx > d.ny ? (d.nx > d.nz ? d.nx : d.nz) : (d.ny > d.nz ? d.ny : d.nz);
+    int iters = 8 * m * m;
+    iters = iters < 64 ? 64 : (iters > 4096 ? 4096 : iters);
+    hipLaunchKernelGGL(k_mg_coarse, dim3(1), dim3(256), 0, s, W.u[l], W.f[l], d.nx, d.ny, d.nz, h2, iters);
+    return hipGetLastError();
+  }
+  const unsigned gs = grid_for((n + 1) / 2);
+  for (int it = 0; it < 2; ++it)
+    for (int color = 0; color < 2; ++color)
+      hipLaunchKernelGGL(k_mg_smooth, dim3(gs), dim3(256), 0, s, W.u[l], W.f[l], d.nx, d.ny, d.nz, h2, color);
+  const MgDims dc = W.dims[l + 1];
+  const size_t nc = (size_t)dc.nx * dc.ny * dc.nz;
+  hipLaunchKernelGGL(k_mg_restrict, dim3(grid_for(nc)), dim3(256), 0, s, W.u[l], W.f[l], d.nx, d.ny, d.nz, 1.0 / h2,
+                     W.f[l + 1]);
+  hipError_t e = hipMemsetAsync(W.u[l + 1], 0, nc * sizeof(double), s);
+  if (e != hipSuccess) return e;
+  e = mg_vcycle(W, l + 1, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mg_prolong, dim3(grid_for(n)), dim3(256), 0, s, W.u[l], W.u[l + 1], d.nx, d.ny, d.nz);
+  for (int it = 0; it < 2; ++it)
+    for (int color = 0; color < 2; ++color)
+      hipLaunchKernelGGL(k_mg_smooth, dim3(gs), dim3(256), 0, s, W.u[l], W.f[l], d.nx, d.ny, d.nz, h2, color);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual_max(const MgWork& W, unsigned long long* rmax, hipStream_t s) {
+  const MgDims d = W.dims[0];
+  const size_t n = (size_t)d.nx * d.ny * d.nz;
+  hipLaunchKernelGGL(k_mg_residual_max, dim3(grid_for(n)), dim3(256), 0, s, W.u[0], W.f[0], d.nx, d.ny, d.nz,
+                     1.0 / (W.dx * W.dx), rmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_sc_field(const float4* Ea, const double* phi, int nx, int ny, int nz, double dx, float4* E,
+                           hipStream_t s) {
+  const size_t n = (size_t)nx * ny * nz;
+  hipLaunchKernelGGL(k_sc_field, dim3(grid_for(n)), dim3(256), 0, s, Ea, phi, nx, ny, nz, 2.0 * dx, E);
+  return hipGetLastError();
+}
+
+hipError_t launch_speed_select(const float* vx, const float* vy, const float* vz, const int64_t* n_dev, uint64_t n,
+                               SelState* st, unsigned* hist, hipStream_t s) {
+  const unsigned g = grid_for(n, 1024);
+  const int shifts[3] = {20, 8, 0}, bits[3] = {12, 12, 8};
+  for (int pass = 0; pass < 3; ++pass) {
+    if (pass == 0) {  // the first pick sets the rank; the histogram needs the prefix 0
+      hipError_t e = hipMemsetAsync(st, 0, sizeof(SelState), s);
+      if (e == hipSuccess) e = hipMemsetAsync(hist, 0, (1u << 12) * sizeof(unsigned), s);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_sel_hist, dim3(g), dim3(256), 0, s, vx, vy, vz, n_dev, st, shifts[pass], bits[pass], hist);
+    hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(64), 0, s, n_dev, hist, st, shifts[pass], bits[pass],
+                       pass == 0 ? 1 : 0);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_densest(const int64_t* ne, size_t n, long long* mx, unsigned long long* first, hipStream_t s) {
+  hipLaunchKernelGGL(k_ne_max, dim3(grid_for(n)), dim3(256), 0, s, ne, n, mx);
+  hipLaunchKernelGGL(k_ne_first, dim3(grid_for(n)), dim3(256), 0, s, ne, n, mx, first);
+  return hipGetLastError();
+}
+
+hipError_t launch_weight_sum(const float* w, const int64_t* n_dev, uint64_t n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_weight_sum, dim3(grid_for(n, 2048)), dim3(256), 0, s, w, n_dev, out);
+  return hipGetLastError();
+}
+
+}  // namespace pcmcc

@@ -162,6 +162,17 @@ struct StagedBirths {
     qt.tag = tag;
     qt.push(c, tb);
     if (cum_ion) atomicAdd(&cum_ion[tag], 1ull);
+    if (q.ev.ix) {
+      const uint64_t es = wave_reserve(q.ev.n);
+      if (es < q.ev.cap) {
+        q.ev.ix[es] = x;
+        q.ev.iy[es] = y;
+        q.ev.iz[es] = z;
+        q.ev.iw[es] = w;
+      } else {
+        atomicOr(q.ev.overflow, OVF_CAPACITY);
+      }
+    }
     return false;
   }
 
@@ -195,6 +206,23 @@ struct StagedBirths {
       }
     }
     if (cum_ion) group_count(cum_ion, tag, mine);
+    if (q.ev.ix) {  // the positive ions of the flushed births
+      unsigned long long eb = 0;
+      if (lane_id() == 0) eb = atomicAdd(q.ev.n, (unsigned long long)n);
+      const uint64_t e0 = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(eb >> 32)) << 32) |
+                          __builtin_amdgcn_readfirstlane((uint32_t)eb);
+      if (mine) {
+        const uint64_t es = e0 + l;
+        if (es < q.ev.cap) {
+          q.ev.ix[es] = L->b[0][l];
+          q.ev.iy[es] = L->b[1][l];
+          q.ev.iz[es] = L->b[2][l];
+          q.ev.iw[es] = L->b[3][l];
+        } else {
+          atomicOr(q.ev.overflow, OVF_CAPACITY);
+        }
+      }
+    }
     n = 0;
   }
 };

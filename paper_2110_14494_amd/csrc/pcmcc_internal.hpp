@@ -33,6 +33,17 @@ enum CntIdx { C_TRIALS, C_NULL, C_EL, C_EXC, C_ION, C_ATT, C_LOST, C_OOT, C_ERR,
 
 enum Overflow : unsigned { OVF_CAPACITY = 1u, OVF_LIMIT = 2u };
 
+// Event lists of the self-consistent step (ix == nullptr: not recorded):
+// where each ionization left a positive ion (the newborn's position) and each
+// attachment a negative ion (the electron's position), with the weight.
+struct EventSink {
+  float *ix = nullptr, *iy = nullptr, *iz = nullptr, *iw = nullptr;
+  float *ax = nullptr, *ay = nullptr, *az = nullptr, *aw = nullptr;
+  unsigned long long* n = nullptr;  // [2]: ionizations, attachments
+  uint64_t cap = 0;                 // entries per list
+  unsigned* overflow = nullptr;
+};
+
 // Internal status of the step loop: stopped after a step because the count
 // exceeds the weight-control limit (not an error; the host updates the
 // weights and resumes).
@@ -74,6 +85,7 @@ struct PicArgs {
   int n_steps;
   float dt;
   uint64_t n_limit;  // stop after a step that leaves more particles (0: no limit)
+  EventSink ev;
 };
 
 struct DepositGeom {
@@ -123,6 +135,36 @@ struct WeightWork {
   void* temp;
   size_t temp_bytes;
 };
+// Self-consistent field: multigrid levels and the time-step selection state.
+constexpr int kMgMaxLevels = 16;
+constexpr int kMgCoarseMax = 2048;  // cells of the coarsest level (solved in LDS)
+struct MgDims {
+  int nx, ny, nz;
+};
+struct MgWork {
+  int levels;
+  MgDims dims[kMgMaxLevels];
+  double* u[kMgMaxLevels];  // u[0]: the potential
+  double* f[kMgMaxLevels];
+  double dx;                // finest spacing
+};
+struct SelState {
+  uint32_t prefix;
+  uint32_t pad;
+  uint64_t rank;  // wanted rank (1-based) within the prefix
+};
+int mg_levels(int nx, int ny, int nz, MgDims* dims);
+hipError_t launch_sc_rhs(const int64_t* np, const int64_t* ne, const int64_t* nn, size_t n, double scale, double* f,
+                         unsigned long long* fmax, hipStream_t s);
+hipError_t mg_vcycle(const MgWork& W, int l, hipStream_t s);
+hipError_t launch_residual_max(const MgWork& W, unsigned long long* rmax, hipStream_t s);
+hipError_t launch_sc_field(const float4* Ea, const double* phi, int nx, int ny, int nz, double dx, float4* E,
+                           hipStream_t s);
+hipError_t launch_speed_select(const float* vx, const float* vy, const float* vz, const int64_t* n_dev, uint64_t n,
+                               SelState* st, unsigned* hist, hipStream_t s);
+hipError_t launch_densest(const int64_t* ne, size_t n, long long* mx, unsigned long long* first, hipStream_t s);
+hipError_t launch_weight_sum(const float* w, const int64_t* n_dev, uint64_t n, double* out, hipStream_t s);
+
 hipError_t weight_temp_bytes(uint64_t n, size_t* bytes);
 hipError_t launch_weight_update(const Soa& cur, const Soa& out, uint64_t n, const WeightGeom& g, const int64_t* rho,
                                 Key key, uint32_t update_index, const WeightWork& W, uint64_t* n_out,

@@ -55,14 +55,29 @@ struct PendSource {
 
 // Phase 1 destination: a survivor keeps its slot in the next buffer; a
 // removed electron leaves a hole there (hole slots are staged per wave).
+// A negative ion where an electron was attached (self-consistent step only).
+__device__ __forceinline__ void record_attachment(const EventSink& ev, const Flight& f) {
+  const uint64_t es = wave_reserve(&ev.n[1]);
+  if (es < ev.cap) {
+    ev.ax[es] = (float)f.x;
+    ev.ay[es] = (float)f.y;
+    ev.az[es] = (float)f.z;
+    ev.aw[es] = f.w;
+  } else {
+    atomicOr(ev.overflow, OVF_CAPACITY);
+  }
+}
+
 struct KeepInPlace {
   const GridView* G;
   Soa nxt;
   uint32_t* holes;
   unsigned long long* n_holes;
+  EventSink ev;
   __device__ __forceinline__ void done_all(const Flight& f, bool parked, Cnt& cnt, WaveStage* L,
                                            uint32_t n_staged, bool& staged) const {
     if (!parked) return;
+    if (f.seg == EV_ATTACHED && ev.ax) record_attachment(ev, f);
     const PState p = flight_record(f);
     bool alive = f.seg == EV_DONE;
     if (alive && !inside(*G, p)) {
@@ -101,6 +116,7 @@ struct PlaceNewborn {
   uint64_t n_holes, n_cur, cap;
   unsigned long long* child;
   unsigned* overflow;
+  EventSink ev;
   __device__ __forceinline__ void place(uint64_t slot, const PState& p) const {
     const uint64_t dst = slot < n_holes ? (uint64_t)holes[slot] : n_cur + (slot - n_holes);
     if (dst < cap)
@@ -111,6 +127,7 @@ struct PlaceNewborn {
   __device__ __forceinline__ void done_all(const Flight& f, bool parked, Cnt& cnt, WaveStage* L,
                                            uint32_t n_staged, bool& staged) const {
     if (!parked) return;
+    if (f.seg == EV_ATTACHED && ev.ax) record_attachment(ev, f);
     const PState p = flight_record(f);
     bool alive = f.seg == EV_DONE;
     if (alive && !inside(*G, p)) {
@@ -181,9 +198,9 @@ __global__ __launch_bounds__(256) void k_pic_steps(PicArgs A) {
 
     // Phase 1: every particle of the current buffer, from t = 0.
     {
-      const BirthSink sink{A.pend[0], &ctl->pend[0], A.pend_cap, &ctl->overflow, 0u};
+      const BirthSink sink{A.pend[0], &ctl->pend[0], A.pend_cap, &ctl->overflow, 0u, A.ev};
       const SoaSource src{cur};
-      const KeepInPlace fin{&A.G, nxt, A.holes, &ctl->holes};
+      const KeepInPlace fin{&A.G, nxt, A.holes, &ctl->holes, A.ev};
       fly_all(n_cur, &ctl->take[0], A.dt, F, T, A.S, step, cnt, sink, nullptr, L, src, fin);
     }
     grid.sync();
@@ -199,9 +216,9 @@ __global__ __launch_bounds__(256) void k_pic_steps(PicArgs A) {
         break;
       }
       const uint64_t np = np_raw < A.pend_cap ? np_raw : A.pend_cap;
-      const BirthSink sink{A.pend[(g + 1) & 1], &ctl->pend[g + 1], A.pend_cap, &ctl->overflow, 0u};
+      const BirthSink sink{A.pend[(g + 1) & 1], &ctl->pend[g + 1], A.pend_cap, &ctl->overflow, 0u, A.ev};
       const PendSource src{A.pend[g & 1]};
-      const PlaceNewborn fin{&A.G, nxt, A.holes, h, n_cur, A.cap, &ctl->child, &ctl->overflow};
+      const PlaceNewborn fin{&A.G, nxt, A.holes, h, n_cur, A.cap, &ctl->child, &ctl->overflow, A.ev};
       fly_all(np, &ctl->take[g + 1], A.dt, F, T, A.S, step, cnt, sink, nullptr, L, src, fin);
       grid.sync();
     }

@@ -84,6 +84,7 @@ struct BirthSink {
   uint64_t cap;
   unsigned* overflow;
   uint32_t tag;  // swarm index of the items being advanced (swarm queues only)
+  EventSink ev{};
   __device__ __forceinline__ void push(const PState& c, float tb) const {
     const uint64_t slot = wave_reserve(count);
     if (slot < cap) {

@@ -162,6 +162,63 @@ class Context:
             B.check(rc, self.h)
         return rc
 
+    # --- self-consistent step -------------------------------------------------
+
+    def solve_potential(self, grid: DeviceGrid, n_pos: torch.Tensor, n_e: torch.Tensor, n_neg: torch.Tensor,
+                        phi: torch.Tensor, tol: float = 1e-10, max_cycles: int = 50):
+        """Multigrid solve into phi (float64 [nz][ny][nx], also the start value);
+        returns (cycles, relative residual)."""
+        for t in (n_pos, n_e, n_neg):
+            assert t.dtype == torch.int64 and t.is_contiguous() and t.numel() == grid.nx * grid.ny * grid.nz
+        assert phi.dtype == torch.float64 and phi.is_contiguous() and phi.numel() == grid.nx * grid.ny * grid.nz
+        cyc, rel = C.c_int(0), C.c_double(0)
+        gs = grid.struct()
+        B.check(B.lib().pcmcc_solve_potential(self.h, C.byref(gs), n_pos.data_ptr(), n_e.data_ptr(), n_neg.data_ptr(),
+                                              phi.data_ptr(), float(tol), int(max_cycles), C.byref(cyc),
+                                              C.byref(rel)), self.h)
+        return cyc.value, rel.value
+
+    def field_from_potential(self, grid: DeviceGrid, phi: torch.Tensor) -> torch.Tensor:
+        """E_applied - grad phi as float32 [nz][ny][nx][4]."""
+        assert phi.dtype == torch.float64 and phi.is_contiguous() and phi.numel() == grid.nx * grid.ny * grid.nz
+        out = torch.empty((grid.nz, grid.ny, grid.nx, 4), dtype=torch.float32, device=grid.E.device)
+        gs = grid.struct()
+        B.check(B.lib().pcmcc_field_from_potential(self.h, C.byref(gs), phi.data_ptr(), out.data_ptr()), self.h)
+        return out
+
+    def speed_quantile(self, parts: Particles) -> float:
+        v = C.c_double(0)
+        t = parts.t
+        B.check(B.lib().pcmcc_speed_quantile(self.h, t["vx"].data_ptr(), t["vy"].data_ptr(), t["vz"].data_ptr(),
+                                             parts.n_dev.data_ptr(), C.byref(v)), self.h)
+        return v.value
+
+    def streamer_steps(self, parts: Particles, grid: DeviceGrid, n_pos: torch.Tensor, n_neg: torch.Tensor,
+                       phi: torch.Tensor, dt: float, n_steps: int, seed: int, step0: int = 0, adaptive: bool = True,
+                       dt_max: float | None = None, mu: dict | None = None, cfl: float = 0.5,
+                       growth_max: float = 1.2, mg_tol: float = 1e-8, mg_max_cycles: int = 30,
+                       E_out: torch.Tensor | None = None, check: bool = True):
+        """Self-consistent steps (field from the densities before every step,
+        ions from the step's events, Sec. 2.1.4 time step).  Returns (rc,
+        next dt, dt per step, stats)."""
+        mu = mu or {"EN_lo": 1.0, "EN_hi": 10.0, "muN": np.array([0.0])}
+        muN = np.ascontiguousarray(mu["muN"], dtype=np.float64)
+        o = B.pcmcc_sc_opts(1 if adaptive else 0, float(dt_max if dt_max is not None else dt), float(cfl),
+                            float(growth_max), int(muN.size), float(mu.get("EN_lo", 1.0)), float(mu.get("EN_hi", 10.0)),
+                            muN.ctypes.data_as(C.c_void_p), float(mg_tol), int(mg_max_cycles))
+        d = C.c_double(dt)
+        hist = np.zeros(max(n_steps, 1), dtype=np.float64)
+        st = B.pcmcc_stats()
+        ps, gs = parts.struct(), grid.struct()
+        rc = B.lib().pcmcc_streamer_steps(self.h, C.byref(ps), C.byref(gs), n_pos.data_ptr(), n_neg.data_ptr(),
+                                          phi.data_ptr(), C.c_void_p(E_out.data_ptr() if E_out is not None else 0),
+                                          C.byref(o), int(n_steps), int(seed), int(step0), C.byref(d),
+                                          hist.ctypes.data_as(C.c_void_p), C.byref(st))
+        if check:
+            B.check(rc, self.h)
+        sd = st.as_dict()
+        return rc, d.value, hist[:sd["steps_done"]], sd
+
     def philox4x32_10(self, ctr: torch.Tensor, seed: int) -> torch.Tensor:
         assert ctr.dtype == torch.int32 and ctr.is_contiguous() and ctr.shape[-1] == 4
         out = torch.empty_like(ctr)

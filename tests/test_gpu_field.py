@@ -1,0 +1,147 @@
+"""GPU parity of the self-consistent step (arXiv:2110.14494 Sec. 2.5 Poisson's
+equation and E = -grad phi, Sec. 2.3 boundary conditions, Sec. 2.1.4 time
+step) against the oracle.
+
+Bars: the multigrid potential within 1e-9 of the oracle's exact discrete
+solution (relative to its largest value) at a residual tolerance of 1e-12;
+the field from a given potential bit for bit; the 90 % speed quantile bit for
+bit; a coupled run within the step tests' bars (state within 1e-5, flips
+below 1e-4 of the flight segments), the same time steps to 1e-6, the same
+ion charge in total to the fixed-point unit and the same charge balance.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import field as F
+from paper_2110_14494_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pic():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2110_14494_amd import pic as P
+    return P
+
+
+def _grid(nx, ny, nz, dx, Ez=0.0):
+    E = np.zeros((nz, ny, nx, 4), np.float32)
+    E[..., 2] = Ez
+    return {"E": E, "x0": 0.0, "y0": 0.0, "z0": 0.0, "dx": dx}
+
+
+def _densities(shape, seed):
+    rng = np.random.default_rng(seed)
+    base = rng.integers(0, 2 ** 40, size=shape, dtype=np.int64)
+    blob = np.zeros(shape, np.int64)
+    nz, ny, nx = shape
+    blob[nz // 3:nz // 2, ny // 4:ny // 2, nx // 3:2 * nx // 3] = 2 ** 44
+    n_pos = base + blob
+    n_e = rng.integers(0, 2 ** 40, size=shape, dtype=np.int64)
+    n_neg = rng.integers(0, 2 ** 36, size=shape, dtype=np.int64)
+    return n_pos, n_e, n_neg
+
+
+@pytest.mark.parametrize("shape,dx", [((16, 16, 16), 5e-5), ((24, 40, 32), 2e-5), ((64, 64, 64), 4e-5)])
+def test_potential_matches_exact_discrete_solution(pic, shape, dx):
+    nz, ny, nx = shape
+    grid = _grid(nx, ny, nz, dx)
+    n_pos, n_e, n_neg = _densities(shape, 7)
+    ref = F.poisson(F.charge_density(n_pos, n_e, n_neg, dx), dx)
+    ctx = pic.Context(0)
+    dg = pic.DeviceGrid(grid)
+    t = [torch.from_numpy(a).cuda() for a in (n_pos, n_e, n_neg)]
+    phi = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    print(f"[gpu] potential {shape}", flush=True)
+    cyc, rel = ctx.solve_potential(dg, *t, phi, tol=1e-12, max_cycles=60)
+    got = phi.cpu().numpy()
+    # a warm start from the solution converges at once
+    cyc2, rel2 = ctx.solve_potential(dg, *t, phi, tol=1e-12, max_cycles=60)
+    ctx.close()
+    print(f"[gpu] cycles {cyc} rel {rel:.2e}; warm {cyc2}", flush=True)
+    assert rel <= 1e-12 and cyc < 40 and cyc2 <= 2
+    assert np.max(np.abs(got - ref)) <= 1e-9 * np.max(np.abs(ref))
+
+
+def test_field_from_potential_bit_exact(pic):
+    nz, ny, nx, dx = 12, 20, 16, 3e-5
+    grid = _grid(nx, ny, nz, dx, Ez=1.5e6)
+    grid["E"][..., 0] = np.random.default_rng(1).normal(0, 1e5, (nz, ny, nx)).astype(np.float32)
+    phi = np.random.default_rng(2).normal(0, 10.0, (nz, ny, nx))
+    ref = F.field(phi, grid["E"], dx)
+    ctx = pic.Context(0)
+    dg = pic.DeviceGrid(grid)
+    E = ctx.field_from_potential(dg, torch.from_numpy(phi).cuda()).cpu().numpy()
+    ctx.close()
+    assert np.array_equal(E[..., :3], ref) and np.all(E[..., 3] == 0)
+
+
+@pytest.mark.parametrize("n", [1, 2, 10, 11, 1000, 1_048_579])
+def test_speed_quantile_exact(pic, n):
+    rng = np.random.default_rng(n + 5)
+    v = rng.normal(0, 2e5, (3, n)).astype(np.float32)
+    if n > 8:
+        v[:, : n // 4] = v[:, :1]  # a quarter of ties
+    parts = {"x": np.zeros(n, np.float32), "y": np.zeros(n, np.float32), "z": np.zeros(n, np.float32),
+             "vx": v[0], "vy": v[1], "vz": v[2], "w": np.ones(n, np.float32), "id": np.arange(n, dtype=np.uint64)}
+    ctx = pic.Context(0)
+    dp = pic.Particles.from_numpy(parts, n)
+    got = ctx.speed_quantile(dp)
+    ctx.close()
+    assert got == F.v90(*v)
+
+
+def _coupled_case(n=3000, w=1e4):
+    cfg = W.plain_swarm_config(n=n)
+    cfg["grid"] = W.uniform_grid(16, 80e-6, (0.0, 0.0, 1.0e7))
+    parts = W.uniform_box_particles(n, 0.45e-3, 0.85e-3, 3e5, seed=8)
+    parts["w"][:] = w
+    return cfg, parts
+
+
+def test_coupled_steps_match_oracle(pic):
+    from test_gpu_pic import compare
+    cfg, parts = _coupled_case()
+    grid = cfg["grid"]
+    mu = {"EN_lo": 10.0, "EN_hi": 1000.0, "muN": np.array([4e24, 2e24, 1e24, 0.8e24])}
+    steps, seed = 6, 3
+    n_pos0 = oracle.deposit(parts["x"], parts["y"], parts["z"], parts["w"], grid)  # neutral seed
+    n_pos_o, n_neg_o = n_pos0.copy(), np.zeros_like(n_pos0)
+    orc_rc, o, info = F.streamer_run(cfg["species"], cfg["tables"], grid, parts, n_pos_o, n_neg_o, 1e-12, steps,
+                                     seed, dt_max=2e-12, mu=mu)
+    assert orc_rc == 0
+    ctx = pic.Context(0)
+    ctx.setup(cfg["species"], cfg["tables"])
+    n = parts["x"].size
+    dp = pic.Particles.from_numpy(parts, 16 * n)
+    dg = pic.DeviceGrid(grid)
+    n_pos = torch.from_numpy(n_pos0.copy()).cuda()
+    n_neg = torch.zeros_like(n_pos)
+    phi = torch.zeros(n_pos.shape, dtype=torch.float64, device="cuda")
+    E = torch.empty((16, 16, 16, 4), dtype=torch.float32, device="cuda")
+    print("[gpu] coupled steps", flush=True)
+    rc, dt_next, hist, st = ctx.streamer_steps(dp, dg, n_pos, n_neg, phi, 1e-12, steps, seed, dt_max=2e-12, mu=mu,
+                                               mg_tol=1e-12, mg_max_cycles=60, E_out=E, check=False)
+    g = dp.to_numpy()
+    n_pos_g, n_neg_g, E_g = n_pos.cpu().numpy(), n_neg.cpu().numpy(), E.cpu().numpy()
+    ctx.close()
+    assert rc == 0 and st["steps_done"] == steps
+    print("[gpu] dt", hist, info["dt"], dt_next, info["next_dt"], flush=True)
+    assert np.allclose(hist, info["dt"], rtol=1e-6, atol=0) and math.isclose(dt_next, info["next_dt"], rel_tol=1e-6)
+    res = compare(g, {k: np.asarray(v) for k, v in o.items()}, grid["dx"])
+    print("[gpu] parity", res, flush=True)
+    trials = st["trials"]
+    assert res["flips"] <= max(1e-4 * trials, 2), res
+    # same ion charge created, exact charge balance on the GPU side
+    assert int(n_pos_g.sum()) == int(n_pos_o.sum()) and int(n_neg_g.sum()) == int(n_neg_o.sum())
+    n_e_g = oracle.deposit(g["x"], g["y"], g["z"], g["w"], grid)
+    assert int(n_pos_g.sum()) - int(n_e_g.sum()) - int(n_neg_g.sum()) == 0
+    # the final fields agree to the state differences
+    scale = np.max(np.abs(info["E"]))
+    assert np.max(np.abs(E_g[..., :3] - info["E"])) <= 1e-4 * scale
