@@ -16,8 +16,9 @@ Also reported: the roofline of the step kernel (HIP events), the CPU oracle
 on a bounded sample, the streamer stage under super-particle weight control
 (N_ppc = 75, update when the count has grown by 1.25x) run until its 200
 steps, the capacity or the deposit's fixed-point range ends it (the fixed
-tip field grows the electron number without bound), and the coefficient
-path: batched swarms against the
+tip field grows the electron number without bound), the same stage with its
+own space-charge field (multigrid Poisson every step, immobile ions, the
+adaptive time step), and the coefficient path: batched swarms against the
 plain per-E/N swarm, surrogate training, held-out fallback and BF16
 inference on 1e8 reduced fields.  Prints one JSON line.
 """
@@ -77,7 +78,9 @@ def parse():
     ap.add_argument("--n-ppc", type=float, default=75.0, help="particles per cell of the weight control")
     ap.add_argument("--growth", type=float, default=1.25, help="count growth that triggers a weight update")
     ap.add_argument("--weights-cap-factor", type=int, default=16,
-                    help="capacity / start count of the weight-controlled run")
+                    help="capacity / start count of the weight-controlled and self-consistent runs")
+    ap.add_argument("--no-sc", action="store_true", help="skip the self-consistent streamer run")
+    ap.add_argument("--sc-steps", type=int, default=40, help="steps of the self-consistent streamer run")
     ap.add_argument("--coef-scale", type=float, default=1.0, help="scale of the swarm sizes")
     ap.add_argument("--epochs", type=int, default=20000)
     ap.add_argument("--infer-n", type=int, default=100_000_000)
@@ -266,6 +269,62 @@ def weights_leg(a, ctx, pic):
             "ionizations": int(st["ionization"]), "attachments": int(st["attachment"])}
 
 
+def sc_leg(a, ctx, pic, mu_table):
+    """The streamer stage with its own space-charge field (Sec. 2.5, Sec. 2.3):
+    a neutral seed (positive ions = the start electrons), the tip field as the
+    applied field, multigrid Poisson and E = E_applied - grad phi before every
+    step, ions from the step's ionizations and attachments, super-particle
+    weight control, and the Sec. 2.1.4 time step (CFL on the 90 % speed
+    quantile, dielectric relaxation with the swarm mobility, 20 % growth, at
+    most 4 ps).  One untimed run of a few steps, then the timed run."""
+    import torch
+    from paper_2110_14494_amd import workloads as W
+    cfg = W.streamer_config(n=a.n or 2 ** 24)
+    n0 = cfg["parts"]["x"].size
+    cap = a.weights_cap_factor * n0
+    ctx.setup(cfg["species"], cfg["tables"])
+    pristine = pic.Particles.from_numpy(cfg["parts"], n0)
+    work = pic.Particles(cap)
+    grid = pic.DeviceGrid(cfg["grid"])
+    shape = (grid.nz, grid.ny, grid.nx)
+    n_pos = torch.zeros(shape, dtype=torch.int64, device="cuda")
+    n_neg = torch.zeros_like(n_pos)
+    phi = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    E = torch.empty(shape + (4,), dtype=torch.float32, device="cuda")
+    res = None
+    for run, steps in ((0, 3), (1, a.sc_steps)):
+        for k, t in pristine.t.items():
+            work.t[k][:n0].copy_(t[:n0])
+        work.n_dev.copy_(pristine.n_dev)
+        n_pos.zero_()
+        n_neg.zero_()
+        phi.zero_()
+        ctx.deposit(work, grid, n_pos)  # neutral seed
+        ctx.set_weight_control(a.n_ppc, a.growth)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, dt_next, hist, st = ctx.streamer_steps(work, grid, n_pos, n_neg, phi, cfg["dt"], steps, cfg["seed"],
+                                                   dt_max=4e-12, mu=mu_table, mg_tol=1e-6, mg_max_cycles=30,
+                                                   E_out=E, check=False)
+        torch.cuda.synchronize()
+        res = (rc, hist, st, time.perf_counter() - t0)
+    ctx.set_weight_control(0.0)
+    rc, hist, st, el = res
+    n_fin = int(st["n"])
+    w_fin = float(work.t["w"][:n_fin].double().sum())
+    e_mag = torch.linalg.vector_norm(E[..., :3], dim=-1)
+    log(f"self-consistent: rc={rc} steps {st['steps_done']} t={hist.sum():.3g} s n {n0} -> {n_fin}, {el:.2f} s, "
+        f"mg cycles {st['mg_cycles']}")
+    return {"workload": cfg["name"], "steps_asked": a.sc_steps, "status": rc, "steps_done": int(st["steps_done"]),
+            "t_simulated_s": float(hist.sum()), "dt_min_s": float(hist.min()) if hist.size else None,
+            "dt_max_s": float(hist.max()) if hist.size else None, "particle_steps": int(st["particle_steps"]),
+            "s": el, "particle_steps_per_s": st["particle_steps"] / el, "step_kernel_ms": st["step_kernel_ms"],
+            "weight_ms": st["weight_ms"], "ion_deposit_ms": st["deposit_kernel_ms"], "field_ms": st["field_ms"],
+            "mg_cycles": int(st["mg_cycles"]), "weight_updates": int(st["weight_updates"]), "n_start": int(n0),
+            "n_final": n_fin, "electrons_final": w_fin, "E_max_final_V_per_m": float(e_mag.max()),
+            "mobility": "swarm table (coefficient leg)" if mu_table.get("from_swarms") else "constant mu N = 3e24"}
+
+
 def coef_leg(a, ctx, pic):
     """Coefficient path: 2048 E/N points (8 batches of 256 swarms, sizes as the
     batched-swarm workload), every 8th held out; surrogate trained on the GPU;
@@ -347,6 +406,10 @@ def coef_leg(a, ctx, pic):
     e_tab = np.where(m_h.astype(bool), e_tab, np.nan)
     e_ok = np.where(np.isfinite(err), err, np.nan)
     names = ("ln_muN", "ln_DLN", "ln_alpha_N", "ln_eta_N", "ln_mean_eps", "ln_bulk_flux")
+    muN = vals[:, pic.B.SWARM_QUANTITIES.index("mu")] * sp["gas_N"]
+    ok = np.isfinite(muN) & (muN > 0)
+    a.mu_table = {"EN_lo": float(EN_all[0]), "EN_hi": float(EN_all[-1]), "from_swarms": True,
+                  "muN": np.interp(np.arange(n_all), np.flatnonzero(ok), muN[ok])}
     return {
         "swarm_points": n_all, "swarm_steps": base["n_steps"], "swarm_scale": a.coef_scale,
         "batched_swarm_EN_points_per_s": batched_pps, "plain_swarm_EN_points_per_s": plain_pps,
@@ -401,6 +464,10 @@ def main():
     if not a.no_coef:
         log("coefficient path")
         out["coefficients"] = coef_leg(a, ctx, pic)
+    if not a.no_sc and a.workload == "streamer":
+        log("self-consistent streamer run")
+        mu = getattr(a, "mu_table", None) or {"EN_lo": 1.0, "EN_hi": 10.0, "muN": np.array([3e24])}
+        out["self_consistent"] = sc_leg(a, ctx, pic, mu)
     ctx.close()
     print(json.dumps(out))
 

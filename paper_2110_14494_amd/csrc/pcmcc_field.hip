@@ -41,6 +41,20 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// Largest non-negative value of the block into *a (one atomic per block).
+__device__ __forceinline__ void block_max_to(unsigned long long* a, double v) {
+  __shared__ double s_w[16];
+  v = wave_max(v);
+  const int wid = threadIdx.x / 64, nw = (blockDim.x + 63) / 64;
+  if ((threadIdx.x & 63) == 0) s_w[wid] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int w = 0; w < nw; ++w) m = fmax(m, s_w[w]);
+    if (m > 0.0) atomic_max_pos(a, m);
+  }
+}
+
 // Sum of the neighbours present and the diagonal of the stencil at (i,j,k):
 // a missing x/y neighbour is a Neumann ghost (diagonal 6 -> one less), a
 // missing z neighbour a Dirichlet ghost (one more).
@@ -72,37 +86,33 @@ __global__ void k_sc_rhs(const int64_t* __restrict__ np, const int64_t* __restri
     f[c] = v;
     m = fmax(m, fabs(v));
   }
-  m = wave_max(m);
-  if ((threadIdx.x & 63) == 0 && m > 0.0) atomic_max_pos(fmax_bits, m);
+  block_max_to(fmax_bits, m);
 }
 
+// Launch shape of the level kernels: x threads along a row, one block row
+// per (j, k) in blockIdx.y / blockIdx.z (no index division).
+
 // One red-black Gauss-Seidel half sweep: cells with (i + j + k) % 2 == color.
-__global__ void k_mg_smooth(double* __restrict__ u, const double* __restrict__ f, int nx, int ny, int nz, double h2,
-                            int color) {
+__global__ __launch_bounds__(128) void k_mg_smooth(double* __restrict__ u, const double* __restrict__ f, int nx,
+                                                   int ny, int nz, double h2, int color) {
 #pragma clang fp contract(off)
-  const int hx = (nx + 1) / 2;
-  const size_t total = (size_t)hx * ny * nz;
-  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
-    const int k = (int)(t / ((size_t)hx * ny));
-    const int j = (int)((t / hx) % ny);
-    const int i = 2 * (int)(t % hx) + ((j + k + color) & 1);
-    if (i >= nx) continue;
-    double d;
-    const double s = nb_sum(u, i, j, k, nx, ny, nz, d);
-    const size_t c = idx3(i, j, k, nx, ny);
-    u[c] = (s - h2 * f[c]) / d;
-  }
+  const int j = blockIdx.y, k = blockIdx.z;
+  const int i = 2 * (int)(blockIdx.x * blockDim.x + threadIdx.x) + ((j + k + color) & 1);
+  if (i >= nx) return;
+  double d;
+  const double s = nb_sum(u, i, j, k, nx, ny, nz, d);
+  const size_t c = idx3(i, j, k, nx, ny);
+  u[c] = (s - h2 * f[c]) / d;
 }
 
 // Residual r = f - L u of the 8 children of every coarse cell, averaged into
 // the coarse right-hand side.
-__global__ void k_mg_restrict(const double* __restrict__ u, const double* __restrict__ f, int nx, int ny, int nz,
-                              double inv_h2, double* __restrict__ fc) {
+__global__ __launch_bounds__(128) void k_mg_restrict(const double* __restrict__ u, const double* __restrict__ f,
+                                                     int nx, int ny, int nz, double inv_h2, double* __restrict__ fc) {
 #pragma clang fp contract(off)
-  const int cx = nx / 2, cy = ny / 2, cz = nz / 2;
-  const size_t total = (size_t)cx * cy * cz;
-  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
-    const int I = (int)(t % cx), J = (int)((t / cx) % cy), K = (int)(t / ((size_t)cx * cy));
+  const int cx = nx / 2, cy = ny / 2;
+  const int I = blockIdx.x * blockDim.x + threadIdx.x, J = blockIdx.y, K = blockIdx.z;
+  if (I < cx) {
     double acc = 0.0;
     for (int q = 0; q < 8; ++q) {
       const int i = 2 * I + (q & 1), j = 2 * J + ((q >> 1) & 1), k = 2 * K + (q >> 2);
@@ -111,7 +121,7 @@ __global__ void k_mg_restrict(const double* __restrict__ u, const double* __rest
       const size_t c = idx3(i, j, k, nx, ny);
       acc += f[c] - (s - d * u[c]) * inv_h2;
     }
-    fc[t] = 0.125 * acc;
+    fc[idx3(I, J, K, cx, cy)] = 0.125 * acc;
   }
 }
 
@@ -131,12 +141,13 @@ __device__ __forceinline__ double coarse_at(const double* U, int I, int J, int K
 }
 
 // u_fine += trilinear interpolation of the coarse correction.
-__global__ void k_mg_prolong(double* __restrict__ u, const double* __restrict__ U, int nx, int ny, int nz) {
+__global__ __launch_bounds__(128) void k_mg_prolong(double* __restrict__ u, const double* __restrict__ U, int nx,
+                                                    int ny, int nz) {
 #pragma clang fp contract(off)
   const int cx = nx / 2, cy = ny / 2, cz = nz / 2;
-  const size_t total = (size_t)nx * ny * nz;
-  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < total; c += (size_t)gridDim.x * blockDim.x) {
-    const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / ((size_t)nx * ny));
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+  if (i < nx) {
+    const size_t c = idx3(i, j, k, nx, ny);
     const int I = i >> 1, J = j >> 1, K = k >> 1;
     const int I2 = I + ((i & 1) ? 1 : -1), J2 = J + ((j & 1) ? 1 : -1), K2 = K + ((k & 1) ? 1 : -1);
     const double v = 27.0 * coarse_at(U, I, J, K, cx, cy, cz) +
@@ -178,29 +189,34 @@ __global__ __launch_bounds__(256) void k_mg_coarse(double* __restrict__ u, const
 }
 
 // Largest |f - L u| on a level.
-__global__ void k_mg_residual_max(const double* __restrict__ u, const double* __restrict__ f, int nx, int ny, int nz,
-                                  double inv_h2, unsigned long long* rmax) {
+__global__ __launch_bounds__(128) void k_mg_residual_max(const double* __restrict__ u, const double* __restrict__ f,
+                                                         int nx, int ny, int nz, double inv_h2,
+                                                         unsigned long long* rmax) {
 #pragma clang fp contract(off)
-  const size_t total = (size_t)nx * ny * nz;
+  // blockIdx.z strides over the planes: a block reduces several rows
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
   double m = 0.0;
-  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < total; c += (size_t)gridDim.x * blockDim.x) {
-    const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / ((size_t)nx * ny));
-    double d;
-    const double s = nb_sum(u, i, j, k, nx, ny, nz, d);
-    m = fmax(m, fabs(f[c] - (s - d * u[c]) * inv_h2));
+  if (i < nx) {
+    for (int k = blockIdx.z; k < nz; k += gridDim.z) {
+      const size_t c = idx3(i, j, k, nx, ny);
+      double d;
+      const double s = nb_sum(u, i, j, k, nx, ny, nz, d);
+      m = fmax(m, fabs(f[c] - (s - d * u[c]) * inv_h2));
+    }
   }
-  m = wave_max(m);
-  if ((threadIdx.x & 63) == 0 && m > 0.0) atomic_max_pos(rmax, m);
+  block_max_to(rmax, m);
 }
 
+
+
 // E = E_applied - grad phi at the centres (central differences with ghosts).
-__global__ void k_sc_field(const float4* __restrict__ Ea, const double* __restrict__ phi, int nx, int ny, int nz,
-                           double two_dx, float4* __restrict__ E) {
+__global__ __launch_bounds__(128) void k_sc_field(const float4* __restrict__ Ea, const double* __restrict__ phi,
+                                                  int nx, int ny, int nz, double two_dx, float4* __restrict__ E) {
 #pragma clang fp contract(off)
-  const size_t total = (size_t)nx * ny * nz;
   const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
-  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < total; c += (size_t)gridDim.x * blockDim.x) {
-    const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / sz);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+  if (i < nx) {
+    const size_t c = idx3(i, j, k, nx, ny);
     const double p = phi[c];
     const double xm = i > 0 ? phi[c - 1] : p, xp = i < nx - 1 ? phi[c + 1] : p;
     const double ym = j > 0 ? phi[c - sy] : p, yp = j < ny - 1 ? phi[c + sy] : p;
@@ -242,38 +258,57 @@ __global__ __launch_bounds__(256) void k_sel_hist(const float* __restrict__ vx, 
     if (h[b]) atomicAdd(&hist[b], h[b]);
 }
 
-// Picks the bin holding the wanted rank; the first pass sets the rank
-// ceil(9 n / 10) from the count.
-__global__ void k_sel_pick(const int64_t* n_dev, unsigned* __restrict__ hist, SelState* st, int shift, int bits,
-                           int first) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  if (first) {
-    const uint64_t n = (uint64_t)*n_dev;
-    st->rank = n ? (9 * n + 9) / 10 : 0;
-    st->prefix = 0;
+// Picks the bin holding the wanted rank (one wave: each lane sums a
+// contiguous chunk of bins, a prefix over the lanes finds the chunk, its lane
+// the bin); the first pass sets the rank ceil(9 n / 10) from the count.  The
+// histogram is cleared for the next pass.
+__global__ __launch_bounds__(64) void k_sel_pick(const int64_t* n_dev, unsigned* __restrict__ hist, SelState* st,
+                                                 int shift, int bits, int first) {
+  const int lane = threadIdx.x;
+  const int nb = 1 << bits, per = nb / 64;
+  uint64_t rank = first ? ((uint64_t)*n_dev ? (9 * (uint64_t)*n_dev + 9) / 10 : 0) : st->rank;
+  uint64_t mine = 0;
+  for (int b = lane * per; b < (lane + 1) * per; ++b) mine += hist[b];
+  uint64_t incl = mine;
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t o = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += o;
   }
-  if (st->rank == 0) return;
-  uint64_t acc = 0;
-  const int nb = 1 << bits;
-  for (int b = 0; b < nb; ++b) {
-    const uint64_t h = hist[b];
-    if (acc + h >= st->rank) {
-      st->prefix |= (uint32_t)b << shift;
-      st->rank -= acc;
-      break;
+  const uint64_t excl = incl - mine;
+  const bool here = rank > 0 && excl < rank && rank <= incl;
+  if (here) {
+    uint64_t acc = excl;
+    for (int b = lane * per; b < (lane + 1) * per; ++b) {
+      const uint64_t h = hist[b];
+      if (acc + h >= rank) {
+        st->prefix = (first ? 0u : st->prefix) | ((uint32_t)b << shift);
+        st->rank = rank - acc;
+        break;
+      }
+      acc += h;
     }
-    acc += h;
   }
-  for (int b = 0; b < nb; ++b) hist[b] = 0;  // ready for the next pass
+  if (lane == 0 && first && rank == 0) {
+    st->prefix = 0;
+    st->rank = 0;
+  }
+  __syncthreads();
+  for (int b = lane; b < nb; b += 64) hist[b] = 0;
 }
 
 // Largest fixed-point electron density, then the first cell holding it.
 __global__ void k_ne_max(const int64_t* __restrict__ ne, size_t n, long long* out) {
+  __shared__ long long s_w[16];
   long long m = LLONG_MIN;
   for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (size_t)gridDim.x * blockDim.x)
     m = max(m, (long long)ne[c]);
   for (int d = 32; d > 0; d >>= 1) m = max(m, (long long)__shfl_xor(m, d, 64));
-  if ((threadIdx.x & 63) == 0) atomicMax(out, m);
+  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x / 64] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x + 63) / 64; ++w) m = max(m, s_w[w]);
+    atomicMax(out, max(m, s_w[0]));
+  }
 }
 
 __global__ void k_ne_first(const int64_t* __restrict__ ne, size_t n, const long long* mx,
@@ -295,6 +330,9 @@ __global__ void k_weight_sum(const float* __restrict__ w, const int64_t* n_dev, 
 // ---------------------------------------------------------------------------
 // Host launchers.
 
+// Rows of n cells: blocks of 128 threads along x, one per (j, k).
+static dim3 rows(int n_x, int ny, int nz) { return dim3((unsigned)((n_x + 127) / 128), (unsigned)ny, (unsigned)nz); }
+
 static unsigned grid_for(size_t n, unsigned cap = 16384) {
   const size_t b = (n + 255) / 256;
   return (unsigned)(b < cap ? (b > 0 ? b : 1) : cap);
@@ -314,14 +352,13 @@ int mg_levels(int nx, int ny, int nz, MgDims* dims) {
 
 hipError_t launch_sc_rhs(const int64_t* np, const int64_t* ne, const int64_t* nn, size_t n, double scale, double* f,
                          unsigned long long* fmax, hipStream_t s) {
-  hipLaunchKernelGGL(k_sc_rhs, dim3(grid_for(n)), dim3(256), 0, s, np, ne, nn, n, scale, f, fmax);
+  hipLaunchKernelGGL(k_sc_rhs, dim3(grid_for(n, 2048)), dim3(256), 0, s, np, ne, nn, n, scale, f, fmax);
   return hipGetLastError();
 }
 
 // One V(2,2) cycle from level l down.  u[l], f[l]: the level's arrays.
 hipError_t mg_vcycle(const MgWork& W, int l, hipStream_t s) {
   const MgDims d = W.dims[l];
-  const size_t n = (size_t)d.nx * d.ny * d.nz;
   const double h = W.dx * (double)(1 << l);
   const double h2 = h * h;
   if (l == W.levels - 1) {
@@ -331,37 +368,37 @@ hipError_t mg_vcycle(const MgWork& W, int l, hipStream_t s) {
     hipLaunchKernelGGL(k_mg_coarse, dim3(1), dim3(256), 0, s, W.u[l], W.f[l], d.nx, d.ny, d.nz, h2, iters);
     return hipGetLastError();
   }
-  const unsigned gs = grid_for((n + 1) / 2);
+  const dim3 gs = rows((d.nx + 1) / 2, d.ny, d.nz);
   for (int it = 0; it < 2; ++it)
     for (int color = 0; color < 2; ++color)
-      hipLaunchKernelGGL(k_mg_smooth, dim3(gs), dim3(256), 0, s, W.u[l], W.f[l], d.nx, d.ny, d.nz, h2, color);
+      hipLaunchKernelGGL(k_mg_smooth, gs, dim3(128), 0, s, W.u[l], W.f[l], d.nx, d.ny, d.nz, h2, color);
   const MgDims dc = W.dims[l + 1];
   const size_t nc = (size_t)dc.nx * dc.ny * dc.nz;
-  hipLaunchKernelGGL(k_mg_restrict, dim3(grid_for(nc)), dim3(256), 0, s, W.u[l], W.f[l], d.nx, d.ny, d.nz, 1.0 / h2,
-                     W.f[l + 1]);
+  hipLaunchKernelGGL(k_mg_restrict, rows(dc.nx, dc.ny, dc.nz), dim3(128), 0, s, W.u[l], W.f[l], d.nx, d.ny, d.nz,
+                     1.0 / h2, W.f[l + 1]);
   hipError_t e = hipMemsetAsync(W.u[l + 1], 0, nc * sizeof(double), s);
   if (e != hipSuccess) return e;
   e = mg_vcycle(W, l + 1, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_mg_prolong, dim3(grid_for(n)), dim3(256), 0, s, W.u[l], W.u[l + 1], d.nx, d.ny, d.nz);
+  hipLaunchKernelGGL(k_mg_prolong, rows(d.nx, d.ny, d.nz), dim3(128), 0, s, W.u[l], W.u[l + 1], d.nx, d.ny, d.nz);
   for (int it = 0; it < 2; ++it)
     for (int color = 0; color < 2; ++color)
-      hipLaunchKernelGGL(k_mg_smooth, dim3(gs), dim3(256), 0, s, W.u[l], W.f[l], d.nx, d.ny, d.nz, h2, color);
+      hipLaunchKernelGGL(k_mg_smooth, gs, dim3(128), 0, s, W.u[l], W.f[l], d.nx, d.ny, d.nz, h2, color);
   return hipGetLastError();
 }
 
 hipError_t launch_residual_max(const MgWork& W, unsigned long long* rmax, hipStream_t s) {
   const MgDims d = W.dims[0];
-  const size_t n = (size_t)d.nx * d.ny * d.nz;
-  hipLaunchKernelGGL(k_mg_residual_max, dim3(grid_for(n)), dim3(256), 0, s, W.u[0], W.f[0], d.nx, d.ny, d.nz,
-                     1.0 / (W.dx * W.dx), rmax);
+  dim3 g = rows(d.nx, d.ny, d.nz);
+  g.z = g.z < 16 ? g.z : 16;
+  hipLaunchKernelGGL(k_mg_residual_max, g, dim3(128), 0, s, W.u[0], W.f[0], d.nx, d.ny, d.nz, 1.0 / (W.dx * W.dx),
+                     rmax);
   return hipGetLastError();
 }
 
 hipError_t launch_sc_field(const float4* Ea, const double* phi, int nx, int ny, int nz, double dx, float4* E,
                            hipStream_t s) {
-  const size_t n = (size_t)nx * ny * nz;
-  hipLaunchKernelGGL(k_sc_field, dim3(grid_for(n)), dim3(256), 0, s, Ea, phi, nx, ny, nz, 2.0 * dx, E);
+  hipLaunchKernelGGL(k_sc_field, rows(nx, ny, nz), dim3(128), 0, s, Ea, phi, nx, ny, nz, 2.0 * dx, E);
   return hipGetLastError();
 }
 
@@ -383,7 +420,7 @@ hipError_t launch_speed_select(const float* vx, const float* vy, const float* vz
 }
 
 hipError_t launch_densest(const int64_t* ne, size_t n, long long* mx, unsigned long long* first, hipStream_t s) {
-  hipLaunchKernelGGL(k_ne_max, dim3(grid_for(n)), dim3(256), 0, s, ne, n, mx);
+  hipLaunchKernelGGL(k_ne_max, dim3(grid_for(n, 2048)), dim3(256), 0, s, ne, n, mx);
   hipLaunchKernelGGL(k_ne_first, dim3(grid_for(n)), dim3(256), 0, s, ne, n, mx, first);
   return hipGetLastError();
 }
