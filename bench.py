@@ -81,6 +81,8 @@ def parse():
                     help="capacity / start count of the weight-controlled and self-consistent runs")
     ap.add_argument("--no-sc", action="store_true", help="skip the self-consistent streamer run")
     ap.add_argument("--sc-steps", type=int, default=40, help="steps of the self-consistent streamer run")
+    ap.add_argument("--no-fluid", action="store_true", help="skip the fluid run")
+    ap.add_argument("--fluid-steps", type=int, default=100, help="Heun steps of the fluid run")
     ap.add_argument("--coef-scale", type=float, default=1.0, help="scale of the swarm sizes")
     ap.add_argument("--epochs", type=int, default=20000)
     ap.add_argument("--infer-n", type=int, default=100_000_000)
@@ -325,6 +327,57 @@ def sc_leg(a, ctx, pic, mu_table):
             "mobility": "swarm table (coefficient leg)" if mu_table.get("from_swarms") else "constant mu N = 3e24"}
 
 
+FLUID_BYTES_PER_CELL_STAGE = 92.0  # both Heun stages: densities, field, derivatives (mean of 88 and 96 B)
+
+
+def fluid_leg(a, ctx, pic, table):
+    """The fluid model (Sec. 2.2) on the streamer stage's grid: a neutral
+    Gaussian seed (peak 5.8e17 m^-3, sigma 300 um, the particle seed's
+    density) at the tip, the tip field as the applied field, transport data
+    sampled from the trained surrogate (cells that fall back use the swarm
+    table), Heun steps with the space-charge field recomputed per stage."""
+    import torch
+    from paper_2110_14494_amd import workloads as W
+    cfg = W.streamer_config(n=1)
+    sp = cfg["species"]
+    ctx.setup(sp, cfg["tables"])
+    grid = pic.DeviceGrid(cfg["grid"])
+    shape = (grid.nz, grid.ny, grid.nx)
+    dx = grid.dx
+    c = [(torch.arange(m, dtype=torch.float64, device="cuda") + 0.5) * dx for m in shape]
+    tip = (8e-3, 5e-3, 5e-3)
+    r2 = ((c[0] - tip[0]) ** 2)[:, None, None] + ((c[1] - tip[1]) ** 2)[None, :, None] + \
+        ((c[2] - tip[2]) ** 2)[None, None, :]
+    seed = 5.8e17 * torch.exp(-r2 / (2 * 300e-6 ** 2))
+    E = torch.empty(shape + (4,), dtype=torch.float32, device="cuda")
+    res = None
+    for run, steps in ((0, 2), (1, a.fluid_steps)):
+        ne, npo, nne = seed.clone(), seed.clone(), torch.zeros_like(seed)
+        phi = torch.zeros_like(seed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, hist, st = ctx.fluid_steps(grid, ne, npo, nne, phi, table, 2e-11, steps, mg_tol=1e-6, mg_max_cycles=30,
+                                       E_out=E, check=False)
+        torch.cuda.synchronize()
+        res = (rc, hist, st, time.perf_counter() - t0, ne, nne)
+    rc, hist, st, el, ne, nne = res
+    cells = float(grid.nx * grid.ny * grid.nz)
+    done = int(st["steps_done"])
+    stage_ms = st["step_kernel_ms"]
+    gbs = 2 * done * cells * FLUID_BYTES_PER_CELL_STAGE / (stage_ms * 1e-3) / 1e9 if stage_ms > 0 else None
+    log(f"fluid: rc={rc} steps {done} t={hist.sum():.3g} s in {el:.2f} s, stages {stage_ms:.1f} ms, "
+        f"field {st['field_ms']:.1f} ms, mg cycles {st['mg_cycles']}")
+    return {"grid": int(grid.nx), "cells": int(cells), "status": rc, "steps_done": done,
+            "t_simulated_s": float(hist.sum()), "dt_min_s": float(hist.min()) if done else None,
+            "dt_max_s": float(hist.max()) if done else None, "s": el, "cell_steps_per_s": cells * done / el,
+            "stage_kernel_ms": stage_ms, "field_ms": st["field_ms"], "mg_cycles": int(st["mg_cycles"]),
+            "stage_roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": gbs / HBM_PEAK_GBS if gbs else None,
+                               "bytes_per_cell_stage": FLUID_BYTES_PER_CELL_STAGE},
+            "ne_max_final": float(ne.max()), "n_neg_max_final": float(nne.max()),
+            "transport": "surrogate sampled on 2048 log-spaced E/N nodes (fallback cells: swarm table)"}
+
+
 def coef_leg(a, ctx, pic):
     """Coefficient path: 2048 E/N points (8 batches of 256 swarms, sizes as the
     batched-swarm workload), every 8th held out; surrogate trained on the GPU;
@@ -410,6 +463,13 @@ def coef_leg(a, ctx, pic):
     ok = np.isfinite(muN) & (muN > 0)
     a.mu_table = {"EN_lo": float(EN_all[0]), "EN_hi": float(EN_all[-1]), "from_swarms": True,
                   "muN": np.interp(np.arange(n_all), np.flatnonzero(ok), muN[ok])}
+    # transport data for the fluid model: the surrogate (with its fallback
+    # cells) sampled on log-spaced E/N nodes
+    nodes = torch.from_numpy(EN_all.astype(np.float32)).cuda()
+    y_nodes, _ = S.infer(ctx, params, norm_fb, nodes)
+    yn = np.exp(y_nodes.cpu().numpy().astype(np.float64))
+    a.fluid_table = {"EN_lo": float(EN_all[0]), "EN_hi": float(EN_all[-1]), "muN": yn[0], "DN": yn[1],
+                     "alphaN": yn[2], "etaN": yn[3]}
     return {
         "swarm_points": n_all, "swarm_steps": base["n_steps"], "swarm_scale": a.coef_scale,
         "batched_swarm_EN_points_per_s": batched_pps, "plain_swarm_EN_points_per_s": plain_pps,
@@ -464,6 +524,9 @@ def main():
     if not a.no_coef:
         log("coefficient path")
         out["coefficients"] = coef_leg(a, ctx, pic)
+    if not a.no_fluid and getattr(a, "fluid_table", None) is not None:
+        log("fluid run")
+        out["fluid"] = fluid_leg(a, ctx, pic, a.fluid_table)
     if not a.no_sc and a.workload == "streamer":
         log("self-consistent streamer run")
         mu = getattr(a, "mu_table", None) or {"EN_lo": 1.0, "EN_hi": 10.0, "muN": np.array([3e24])}

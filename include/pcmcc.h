@@ -416,6 +416,40 @@ int pcmcc_streamer_steps(pcmcc_ctx* ctx, const pcmcc_particles* p, const pcmcc_g
                          int64_t* n_neg, double* phi, float* E_out, const pcmcc_sc_opts* opts, int n_steps,
                          uint64_t seed, uint64_t step0, double* dt_inout, double* dt_hist, pcmcc_stats* stats);
 
+/* ---- Fluid step (Sec. 2.2) -------------------------------------------------
+ * Drift-diffusion-reaction model in the local field approximation: electrons
+ * drift with v = -mu E, flux = v n_face - D grad n, dn_e/dt = -div(flux) +
+ * (alpha - eta) mu |E| n_e; positive ions gain alpha mu |E| n_e, negative ions
+ * eta mu |E| n_e; ions do not move (photoionization is not included).  Face
+ * field = mean of the two cells' fields, mu and D from its magnitude, the
+ * advected face density the upwind value plus half the Koren-limited slope;
+ * densities have homogeneous Neumann boundaries (mirror ghosts, Sec. 2.3).
+ * Heun's method with the field (as pcmcc_solve_potential, from the densities
+ * in double precision) recomputed for the predicted state; per step
+ * dt = min(dt_max, 0.9 min(0.5 / max(6 D / dx^2 + sum |v_i| / dx),
+ * eps0 / max(e n_e mu))) (the printed CFL limit drops D from its diffusion
+ * term).  Transport data: mu N, D N, alpha / N, eta / N (SI) on tab->n
+ * log-spaced E/N nodes from EN_lo to EN_hi (Td), linear in ln E/N, held
+ * constant outside; N is the gas density of pcmcc_init_species. */
+typedef struct pcmcc_fluid_table {
+  int n;
+  double EN_lo, EN_hi;
+  const double* muN;
+  const double* DN;
+  const double* alphaN;
+  const double* etaN;
+} pcmcc_fluid_table;
+
+/* n_steps Heun steps.  n_e, n_pos, n_neg: device double [nz][ny][nx]
+ * densities (m^-3), updated in place; phi: device double, the multigrid start
+ * value and the last potential; dt_hist: host [n_steps] (nullable); E_out:
+ * device float4 field of the final state (nullable).  stats: steps_done,
+ * step_kernel_ms (the two stage kernels), field_ms (right-hand sides,
+ * multigrid, fields), mg_cycles.  Synchronises the stream. */
+int pcmcc_fluid_steps(pcmcc_ctx* ctx, const pcmcc_grid* applied, double* n_e, double* n_pos, double* n_neg,
+                      double* phi, const pcmcc_fluid_table* tab, double dt_max, double mg_tol, int mg_max_cycles,
+                      int n_steps, double* dt_hist, float* E_out, pcmcc_stats* stats);
+
 /* Deposit only (Sec. 2.1.3), same fixed-point rule and range as above
  * (PCMCC_ERANGE, rho unspecified, beyond it), on n_dev particles (device
  * count) of device arrays x, y, z, w.  Synchronises the stream. */

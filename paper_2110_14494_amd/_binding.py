@@ -65,6 +65,11 @@ class pcmcc_sc_opts(C.Structure):
                 ("mg_tol", C.c_double), ("mg_max_cycles", C.c_int)]
 
 
+class pcmcc_fluid_table(C.Structure):
+    _fields_ = [("n", C.c_int), ("EN_lo", C.c_double), ("EN_hi", C.c_double), ("muN", C.c_void_p),
+                ("DN", C.c_void_p), ("alphaN", C.c_void_p), ("etaN", C.c_void_p)]
+
+
 class pcmcc_swarm_opts(C.Structure):
     _fields_ = [("sample_every", C.c_int), ("window_start_s", C.c_double), ("n_batches", C.c_int),
                 ("cap_factor", C.c_int), ("population_control", C.c_int), ("block", C.c_int),
@@ -140,6 +145,8 @@ def lib() -> C.CDLL:
             "pcmcc_streamer_steps": ([vp, C.POINTER(pcmcc_particles), C.POINTER(pcmcc_grid), vp, vp, vp, vp,
                                       C.POINTER(pcmcc_sc_opts), C.c_int, u64, u64, C.POINTER(C.c_double), vp,
                                       C.POINTER(pcmcc_stats)], C.c_int),
+            "pcmcc_fluid_steps": ([vp, C.POINTER(pcmcc_grid), vp, vp, vp, vp, C.POINTER(pcmcc_fluid_table), C.c_double,
+                                   C.c_double, C.c_int, C.c_int, vp, vp, C.POINTER(pcmcc_stats)], C.c_int),
             "pcmcc_swarm_batch": ([vp, C.c_int, vp, vp, C.c_double, C.c_int, u64, C.POINTER(pcmcc_swarm_opts),
                                    vp, vp, vp, C.POINTER(pcmcc_stats)], C.c_int),
         }

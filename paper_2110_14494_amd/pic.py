@@ -219,6 +219,29 @@ class Context:
         sd = st.as_dict()
         return rc, d.value, hist[:sd["steps_done"]], sd
 
+    def fluid_steps(self, grid: DeviceGrid, n_e: torch.Tensor, n_pos: torch.Tensor, n_neg: torch.Tensor,
+                    phi: torch.Tensor, table: dict, dt_max: float, n_steps: int, mg_tol: float = 1e-8,
+                    mg_max_cycles: int = 30, E_out: torch.Tensor | None = None, check: bool = True):
+        """Fluid steps (Sec. 2.2) on float64 densities [nz][ny][nx] (in place);
+        table: EN_lo, EN_hi and muN, DN, alphaN, etaN arrays on log-spaced
+        E/N nodes.  Returns (rc, dt per step, stats)."""
+        for t in (n_e, n_pos, n_neg, phi):
+            assert t.dtype == torch.float64 and t.is_contiguous() and t.numel() == grid.nx * grid.ny * grid.nz
+        arrs = [np.ascontiguousarray(table[k], dtype=np.float64) for k in ("muN", "DN", "alphaN", "etaN")]
+        tb = B.pcmcc_fluid_table(int(arrs[0].size), float(table["EN_lo"]), float(table["EN_hi"]),
+                                 *[a.ctypes.data_as(C.c_void_p) for a in arrs])
+        hist = np.zeros(max(n_steps, 1), dtype=np.float64)
+        st = B.pcmcc_stats()
+        gs = grid.struct()
+        rc = B.lib().pcmcc_fluid_steps(self.h, C.byref(gs), n_e.data_ptr(), n_pos.data_ptr(), n_neg.data_ptr(),
+                                       phi.data_ptr(), C.byref(tb), float(dt_max), float(mg_tol), int(mg_max_cycles),
+                                       int(n_steps), hist.ctypes.data_as(C.c_void_p),
+                                       C.c_void_p(E_out.data_ptr() if E_out is not None else 0), C.byref(st))
+        if check:
+            B.check(rc, self.h)
+        sd = st.as_dict()
+        return rc, hist[:sd["steps_done"]], sd
+
     def philox4x32_10(self, ctr: torch.Tensor, seed: int) -> torch.Tensor:
         assert ctr.dtype == torch.int32 and ctr.is_contiguous() and ctr.shape[-1] == 4
         out = torch.empty_like(ctr)
