@@ -360,10 +360,12 @@ int pcmcc_update_weights(pcmcc_ctx* ctx, const pcmcc_particles* p, const pcmcc_g
  * electrode and the applied voltage); the electrons see E = E_applied -
  * grad phi, central differences with the same ghosts.  Ions do not move. */
 
-/* Geometric multigrid V(2,2) cycles (double precision) on phi (device, double
- * [nz][ny][nx], the start value and the result) until max |residual| <= tol *
- * max |rhs| or max_cycles; the grid is halved while every dimension is even
- * and above 2, and the coarsest grid must hold at most 2048 cells (else
+/* Geometric multigrid on phi (device, double [nz][ny][nx], the start value
+ * and the result) as defect correction: the residual in double precision,
+ * one single-precision V(2,2) cycle for the correction, repeated until
+ * max |residual| <= tol * max |rhs| or max_cycles cycles; the grid is halved
+ * while every dimension is even
+ * and above 2, and the coarsest grid must hold at most 4096 cells (else
  * PCMCC_EINVAL).  n_pos, n_e, n_neg: device int64 densities.  cycles_out and
  * rel_residual_out (host, nullable) receive the cycles run and the final
  * relative residual.  Synchronises the stream. */

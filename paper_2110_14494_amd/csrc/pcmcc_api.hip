@@ -84,8 +84,10 @@ struct pcmcc_ctx {
   // the field the electrons see, the electron density, event lists, and the
   // small reduction results
   MgWork mg{};
-  double* mg_store = nullptr;
+  float* mg_store = nullptr;  // single-precision correction levels
   size_t mg_store_n = 0;
+  double* mg_rhs = nullptr;
+  size_t mg_rhs_n = 0;
   MgDims mg_dims0{0, 0, 0};
   float4* sc_E = nullptr;
   int64_t* sc_ne = nullptr;
@@ -598,6 +600,7 @@ int pcmcc_destroy(pcmcc_ctx* c) {
   dfree(c->wt_rho);
   dfree(c->dev_n);
   dfree(c->mg_store);
+  dfree(c->mg_rhs);
   dfree(c->sc_E);
   dfree(c->sc_ne);
   dfree(c->ev_store);
@@ -1505,8 +1508,8 @@ int ensure_sc(pcmcc_ctx* c, const pcmcc_grid* g) {
     if ((size_t)dl.nx * dl.ny * dl.nz > (size_t)kMgCoarseMax)
       return fail(c, PCMCC_EINVAL, "grid %dx%dx%d coarsens only to %dx%dx%d (> %d cells): use dimensions with more "
                   "factors of two", g->nx, g->ny, g->nz, dl.nx, dl.ny, dl.nz, kMgCoarseMax);
-    size_t need = ncell;  // f of level 0
-    for (int l = 1; l < L; ++l) need += 2 * (size_t)d[l].nx * d[l].ny * d[l].nz;
+    size_t need = 0;  // u and f of every level
+    for (int l = 0; l < L; ++l) need += 2 * (size_t)d[l].nx * d[l].ny * d[l].nz;
     if (c->mg_store_n < need) {
       dfree(c->mg_store);
       c->mg_store = nullptr;
@@ -1514,13 +1517,19 @@ int ensure_sc(pcmcc_ctx* c, const pcmcc_grid* g) {
       HIP_TRY(c, dalloc(&c->mg_store, need));
       c->mg_store_n = need;
     }
+    if (c->mg_rhs_n < ncell) {
+      dfree(c->mg_rhs);
+      c->mg_rhs = nullptr;
+      c->mg_rhs_n = 0;
+      HIP_TRY(c, dalloc(&c->mg_rhs, ncell));
+      c->mg_rhs_n = ncell;
+    }
     c->mg = MgWork{};
     c->mg.levels = L;
-    double* q = c->mg_store;
-    c->mg.f[0] = q;
-    q += ncell;
-    for (int l = 0; l < L; ++l) c->mg.dims[l] = d[l];
-    for (int l = 1; l < L; ++l) {
+    c->mg.rhs = c->mg_rhs;
+    float* q = c->mg_store;
+    for (int l = 0; l < L; ++l) {
+      c->mg.dims[l] = d[l];
       const size_t n = (size_t)d[l].nx * d[l].ny * d[l].nz;
       c->mg.u[l] = q;
       c->mg.f[l] = q + n;
@@ -1558,16 +1567,18 @@ int solve_potential(pcmcc_ctx* c, const pcmcc_grid* g, const int64_t* np, const 
   const size_t ncell = (size_t)g->nx * g->ny * g->nz;
   HIP_TRY(c, hipMemsetAsync(c->sc_red, 0, 2 * sizeof(unsigned long long), c->stream));
   const double scale = -(kQe * 0x1p-32 / (g->dx * g->dx * g->dx)) / kEps0;
-  HIP_TRY(c, launch_sc_rhs(np, ne, nn, ncell, scale, c->mg.f[0], c->sc_red, c->stream));
+  HIP_TRY(c, launch_sc_rhs(np, ne, nn, ncell, scale, c->mg.rhs, c->sc_red, c->stream));
   return mg_iterate(c, g, phi, tol, max_cycles, cycles, rel);
 }
 
-// Multigrid cycles on phi for the right-hand side in mg.f[0] (its largest
-// magnitude in sc_red[0], set by the kernel that wrote it).
+// Defect correction on phi for the right-hand side in mg.rhs (its largest
+// magnitude in sc_red[0], set by the kernel that wrote it): the double
+// defect, checked against tol, then one single-precision V-cycle for the
+// correction, until the relative defect is at most tol or max_cycles cycles.
 int mg_iterate(pcmcc_ctx* c, const pcmcc_grid* g, double* phi, double tol, int max_cycles, int* cycles,
                double* rel) {
   const size_t ncell = (size_t)g->nx * g->ny * g->nz;
-  c->mg.u[0] = phi;
+  c->mg.phi = phi;
   int rc = read_red(c, 0, 1);
   if (rc) return rc;
   double fmax;
@@ -1578,17 +1589,19 @@ int mg_iterate(pcmcc_ctx* c, const pcmcc_grid* g, double* phi, double tol, int m
     HIP_TRY(c, hipMemsetAsync(phi, 0, ncell * sizeof(double), c->stream));
     return PCMCC_OK;
   }
-  for (int it = 0; it < max_cycles; ++it) {
-    HIP_TRY(c, mg_vcycle(c->mg, 0, c->stream));
+  for (int it = 0;; ++it) {
     HIP_TRY(c, hipMemsetAsync(c->sc_red + 1, 0, sizeof(unsigned long long), c->stream));
-    HIP_TRY(c, launch_residual_max(c->mg, c->sc_red + 1, c->stream));
+    HIP_TRY(c, launch_defect(c->mg, c->sc_red + 1, c->stream));
     rc = read_red(c, 1, 1);
     if (rc) return rc;
     double rmax;
     std::memcpy(&rmax, &c->sc_host[1], sizeof(double));
-    *cycles = it + 1;
+    *cycles = it;
     *rel = rmax / fmax;
-    if (*rel <= tol) break;
+    if (*rel <= tol || it >= max_cycles) break;
+    HIP_TRY(c, hipMemsetAsync(c->mg.u[0], 0, ncell * sizeof(float), c->stream));
+    HIP_TRY(c, mg_vcycle(c->mg, 0, c->stream));
+    HIP_TRY(c, launch_correct(c->mg, c->stream));
   }
   return PCMCC_OK;
 }
@@ -1895,7 +1908,7 @@ int pcmcc_fluid_steps(pcmcc_ctx* c, const pcmcc_grid* applied, double* n_e, doub
   auto field = [&](const double* ne, const double* np, const double* nn) -> int {
     HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
     HIP_TRY(c, hipMemsetAsync(c->sc_red, 0, 2 * sizeof(unsigned long long), c->stream));
-    HIP_TRY(c, launch_fluid_rhs(np, ne, nn, ncell, c->mg.f[0], c->sc_red, c->stream));
+    HIP_TRY(c, launch_fluid_rhs(np, ne, nn, ncell, c->mg.rhs, c->sc_red, c->stream));
     int cyc = 0;
     double rel = 0;
     int r = mg_iterate(c, applied, phi, mg_tol, mg_max_cycles, &cyc, &rel);

@@ -9,11 +9,15 @@
 //   ghost cells (Dirichlet ghost = -phi of the boundary cell, Neumann ghost =
 //   phi).  The caller's field is the applied field; the field the electrons
 //   see is E_applied - grad phi (central differences, same ghosts).
-// * Geometric multigrid in double precision: V(2,2) cycles, red-black
-//   Gauss-Seidel smoothing, restriction by the mean of the 8 children,
-//   trilinear prolongation with the error's ghost rules, the coarsest grid
-//   (every dimension halved while all are even and above 2) solved by one
-//   block in LDS.  All passes are HBM-streaming stencils.
+// * Geometric multigrid as defect correction: the defect of the potential is
+//   computed in double precision, the correction solved by one V(2,2) cycle in
+//   single precision (red-black Gauss-Seidel smoothing, restriction by the
+//   mean of the 8 children, trilinear prolongation with the error's ghost
+//   rules, the coarsest grid - every dimension halved while all are even and
+//   above 2 - solved by one block in LDS) and added to the potential; the
+//   iteration converges to the double-precision solution of the discrete
+//   system while the cycles move half the bytes.  All passes are
+//   HBM-streaming stencils.
 // * Time-step ingredients: the 90 % speed quantile by a three-pass radix
 //   selection on |v|^2 keys (exact), the densest cell (largest fixed-point
 //   density, first in x-fastest order), and the sum of the weights.
@@ -58,17 +62,18 @@ __device__ __forceinline__ void block_max_to(unsigned long long* a, double v) {
 // Sum of the neighbours present and the diagonal of the stencil at (i,j,k):
 // a missing x/y neighbour is a Neumann ghost (diagonal 6 -> one less), a
 // missing z neighbour a Dirichlet ghost (one more).
-__device__ __forceinline__ double nb_sum(const double* u, int i, int j, int k, int nx, int ny, int nz, double& diag) {
+template <class T>
+__device__ __forceinline__ T nb_sum(const T* u, int i, int j, int k, int nx, int ny, int nz, T& diag) {
   const size_t c = idx3(i, j, k, nx, ny);
   const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
-  double s = 0.0;
-  double d = 6.0;
-  if (i > 0) s += u[c - 1]; else d -= 1.0;
-  if (i < nx - 1) s += u[c + 1]; else d -= 1.0;
-  if (j > 0) s += u[c - sy]; else d -= 1.0;
-  if (j < ny - 1) s += u[c + sy]; else d -= 1.0;
-  if (k > 0) s += u[c - sz]; else d += 1.0;
-  if (k < nz - 1) s += u[c + sz]; else d += 1.0;
+  T s = 0;
+  T d = 6;
+  if (i > 0) s += u[c - 1]; else d -= 1;
+  if (i < nx - 1) s += u[c + 1]; else d -= 1;
+  if (j > 0) s += u[c - sy]; else d -= 1;
+  if (j < ny - 1) s += u[c + sy]; else d -= 1;
+  if (k > 0) s += u[c - sz]; else d += 1;
+  if (k < nz - 1) s += u[c + sz]; else d += 1;
   diag = d;
   return s;
 }
@@ -93,55 +98,55 @@ __global__ void k_sc_rhs(const int64_t* __restrict__ np, const int64_t* __restri
 // per (j, k) in blockIdx.y / blockIdx.z (no index division).
 
 // One red-black Gauss-Seidel half sweep: cells with (i + j + k) % 2 == color.
-__global__ __launch_bounds__(128) void k_mg_smooth(double* __restrict__ u, const double* __restrict__ f, int nx,
-                                                   int ny, int nz, double h2, int color) {
+__global__ __launch_bounds__(128) void k_mg_smooth(float* __restrict__ u, const float* __restrict__ f, int nx,
+                                                   int ny, int nz, float h2, int color) {
 #pragma clang fp contract(off)
   const int j = blockIdx.y, k = blockIdx.z;
   const int i = 2 * (int)(blockIdx.x * blockDim.x + threadIdx.x) + ((j + k + color) & 1);
   if (i >= nx) return;
-  double d;
-  const double s = nb_sum(u, i, j, k, nx, ny, nz, d);
+  float d;
+  const float s = nb_sum(u, i, j, k, nx, ny, nz, d);
   const size_t c = idx3(i, j, k, nx, ny);
   u[c] = (s - h2 * f[c]) / d;
 }
 
 // Residual r = f - L u of the 8 children of every coarse cell, averaged into
 // the coarse right-hand side.
-__global__ __launch_bounds__(128) void k_mg_restrict(const double* __restrict__ u, const double* __restrict__ f,
-                                                     int nx, int ny, int nz, double inv_h2, double* __restrict__ fc) {
+__global__ __launch_bounds__(128) void k_mg_restrict(const float* __restrict__ u, const float* __restrict__ f,
+                                                     int nx, int ny, int nz, float inv_h2, float* __restrict__ fc) {
 #pragma clang fp contract(off)
   const int cx = nx / 2, cy = ny / 2;
   const int I = blockIdx.x * blockDim.x + threadIdx.x, J = blockIdx.y, K = blockIdx.z;
   if (I < cx) {
-    double acc = 0.0;
+    float acc = 0.0f;
     for (int q = 0; q < 8; ++q) {
       const int i = 2 * I + (q & 1), j = 2 * J + ((q >> 1) & 1), k = 2 * K + (q >> 2);
-      double d;
-      const double s = nb_sum(u, i, j, k, nx, ny, nz, d);
+      float d;
+      const float s = nb_sum(u, i, j, k, nx, ny, nz, d);
       const size_t c = idx3(i, j, k, nx, ny);
       acc += f[c] - (s - d * u[c]) * inv_h2;
     }
-    fc[idx3(I, J, K, cx, cy)] = 0.125 * acc;
+    fc[idx3(I, J, K, cx, cy)] = 0.125f * acc;
   }
 }
 
 // Coarse value with the error's ghost rule outside the grid.
-__device__ __forceinline__ double coarse_at(const double* U, int I, int J, int K, int cx, int cy, int cz) {
-  double sgn = 1.0;
+__device__ __forceinline__ float coarse_at(const float* U, int I, int J, int K, int cx, int cy, int cz) {
+  float sgn = 1.0f;
   I = min(max(I, 0), cx - 1);
   J = min(max(J, 0), cy - 1);
   if (K < 0) {
     K = 0;
-    sgn = -1.0;
+    sgn = -1.0f;
   } else if (K >= cz) {
     K = cz - 1;
-    sgn = -1.0;
+    sgn = -1.0f;
   }
   return sgn * U[idx3(I, J, K, cx, cy)];
 }
 
 // u_fine += trilinear interpolation of the coarse correction.
-__global__ __launch_bounds__(128) void k_mg_prolong(double* __restrict__ u, const double* __restrict__ U, int nx,
+__global__ __launch_bounds__(128) void k_mg_prolong(float* __restrict__ u, const float* __restrict__ U, int nx,
                                                     int ny, int nz) {
 #pragma clang fp contract(off)
   const int cx = nx / 2, cy = ny / 2, cz = nz / 2;
@@ -150,23 +155,23 @@ __global__ __launch_bounds__(128) void k_mg_prolong(double* __restrict__ u, cons
     const size_t c = idx3(i, j, k, nx, ny);
     const int I = i >> 1, J = j >> 1, K = k >> 1;
     const int I2 = I + ((i & 1) ? 1 : -1), J2 = J + ((j & 1) ? 1 : -1), K2 = K + ((k & 1) ? 1 : -1);
-    const double v = 27.0 * coarse_at(U, I, J, K, cx, cy, cz) +
-                     9.0 * (coarse_at(U, I2, J, K, cx, cy, cz) + coarse_at(U, I, J2, K, cx, cy, cz) +
+    const float v = 27.0f * coarse_at(U, I, J, K, cx, cy, cz) +
+                    9.0f * (coarse_at(U, I2, J, K, cx, cy, cz) + coarse_at(U, I, J2, K, cx, cy, cz) +
                             coarse_at(U, I, J, K2, cx, cy, cz)) +
-                     3.0 * (coarse_at(U, I2, J2, K, cx, cy, cz) + coarse_at(U, I2, J, K2, cx, cy, cz) +
+                    3.0f * (coarse_at(U, I2, J2, K, cx, cy, cz) + coarse_at(U, I2, J, K2, cx, cy, cz) +
                             coarse_at(U, I, J2, K2, cx, cy, cz)) +
-                     coarse_at(U, I2, J2, K2, cx, cy, cz);
-    u[c] += v * (1.0 / 64.0);
+                    coarse_at(U, I2, J2, K2, cx, cy, cz);
+    u[c] += v * (1.0f / 64.0f);
   }
 }
 
 // Coarsest level: one block, LDS, red-black sweeps (the level is at most
 // kMgCoarseMax cells).
-__global__ __launch_bounds__(256) void k_mg_coarse(double* __restrict__ u, const double* __restrict__ f, int nx,
-                                                    int ny, int nz, double h2, int iters) {
+__global__ __launch_bounds__(256) void k_mg_coarse(float* __restrict__ u, const float* __restrict__ f, int nx,
+                                                    int ny, int nz, float h2, int iters) {
 #pragma clang fp contract(off)
-  __shared__ double s_u[kMgCoarseMax];
-  __shared__ double s_f[kMgCoarseMax];
+  __shared__ float s_u[kMgCoarseMax];
+  __shared__ float s_f[kMgCoarseMax];
   const int n = nx * ny * nz;
   for (int c = threadIdx.x; c < n; c += blockDim.x) {
     s_u[c] = u[c];
@@ -178,8 +183,8 @@ __global__ __launch_bounds__(256) void k_mg_coarse(double* __restrict__ u, const
       for (int c = threadIdx.x; c < n; c += blockDim.x) {
         const int i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
         if (((i + j + k) & 1) != color) continue;
-        double d;
-        const double s = nb_sum(s_u, i, j, k, nx, ny, nz, d);
+        float d;
+        const float s = nb_sum(s_u, i, j, k, nx, ny, nz, d);
         s_u[c] = (s - h2 * s_f[c]) / d;
       }
       __syncthreads();
@@ -188,10 +193,12 @@ __global__ __launch_bounds__(256) void k_mg_coarse(double* __restrict__ u, const
   for (int c = threadIdx.x; c < n; c += blockDim.x) u[c] = s_u[c];
 }
 
-// Largest |f - L u| on a level.
-__global__ __launch_bounds__(128) void k_mg_residual_max(const double* __restrict__ u, const double* __restrict__ f,
-                                                         int nx, int ny, int nz, double inv_h2,
-                                                         unsigned long long* rmax) {
+// Defect of the potential, r = rhs - L phi in double precision: stored in
+// single precision as the right-hand side of the correction cycle, and its
+// largest magnitude.
+__global__ __launch_bounds__(128) void k_mg_defect(const double* __restrict__ phi, const double* __restrict__ rhs,
+                                                   int nx, int ny, int nz, double inv_h2, float* __restrict__ r,
+                                                   unsigned long long* rmax) {
 #pragma clang fp contract(off)
   // blockIdx.z strides over the planes: a block reduces several rows
   const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
@@ -200,11 +207,19 @@ __global__ __launch_bounds__(128) void k_mg_residual_max(const double* __restric
     for (int k = blockIdx.z; k < nz; k += gridDim.z) {
       const size_t c = idx3(i, j, k, nx, ny);
       double d;
-      const double s = nb_sum(u, i, j, k, nx, ny, nz, d);
-      m = fmax(m, fabs(f[c] - (s - d * u[c]) * inv_h2));
+      const double s = nb_sum(phi, i, j, k, nx, ny, nz, d);
+      const double v = rhs[c] - (s - d * phi[c]) * inv_h2;
+      r[c] = (float)v;
+      m = fmax(m, fabs(v));
     }
   }
   block_max_to(rmax, m);
+}
+
+// phi += the correction.
+__global__ void k_mg_correct(double* __restrict__ phi, const float* __restrict__ e, size_t n) {
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (size_t)gridDim.x * blockDim.x)
+    phi[c] += (double)e[c];
 }
 
 
@@ -356,11 +371,12 @@ hipError_t launch_sc_rhs(const int64_t* np, const int64_t* ne, const int64_t* nn
   return hipGetLastError();
 }
 
-// One V(2,2) cycle from level l down.  u[l], f[l]: the level's arrays.
+// One V(2,2) cycle of the correction from level l down.  u[l], f[l]: the
+// level's single-precision arrays.
 hipError_t mg_vcycle(const MgWork& W, int l, hipStream_t s) {
   const MgDims d = W.dims[l];
   const double h = W.dx * (double)(1 << l);
-  const double h2 = h * h;
+  const float h2 = (float)(h * h);
   if (l == W.levels - 1) {
     const int m = d.nx > d.ny ? (d.nx > d.nz ? d.nx : d.nz) : (d.ny > d.nz ? d.ny : d.nz);
     int iters = 8 * m * m;
@@ -375,8 +391,8 @@ hipError_t mg_vcycle(const MgWork& W, int l, hipStream_t s) {
   const MgDims dc = W.dims[l + 1];
   const size_t nc = (size_t)dc.nx * dc.ny * dc.nz;
   hipLaunchKernelGGL(k_mg_restrict, rows(dc.nx, dc.ny, dc.nz), dim3(128), 0, s, W.u[l], W.f[l], d.nx, d.ny, d.nz,
-                     1.0 / h2, W.f[l + 1]);
-  hipError_t e = hipMemsetAsync(W.u[l + 1], 0, nc * sizeof(double), s);
+                     1.0f / h2, W.f[l + 1]);
+  hipError_t e = hipMemsetAsync(W.u[l + 1], 0, nc * sizeof(float), s);
   if (e != hipSuccess) return e;
   e = mg_vcycle(W, l + 1, s);
   if (e != hipSuccess) return e;
@@ -387,12 +403,18 @@ hipError_t mg_vcycle(const MgWork& W, int l, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_residual_max(const MgWork& W, unsigned long long* rmax, hipStream_t s) {
+hipError_t launch_defect(const MgWork& W, unsigned long long* rmax, hipStream_t s) {
   const MgDims d = W.dims[0];
   dim3 g = rows(d.nx, d.ny, d.nz);
   g.z = g.z < 16 ? g.z : 16;
-  hipLaunchKernelGGL(k_mg_residual_max, g, dim3(128), 0, s, W.u[0], W.f[0], d.nx, d.ny, d.nz, 1.0 / (W.dx * W.dx),
+  hipLaunchKernelGGL(k_mg_defect, g, dim3(128), 0, s, W.phi, W.rhs, d.nx, d.ny, d.nz, 1.0 / (W.dx * W.dx), W.f[0],
                      rmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_correct(const MgWork& W, hipStream_t s) {
+  const size_t n = (size_t)W.dims[0].nx * W.dims[0].ny * W.dims[0].nz;
+  hipLaunchKernelGGL(k_mg_correct, dim3(grid_for(n, 4096)), dim3(256), 0, s, W.phi, W.u[0], n);
   return hipGetLastError();
 }
 

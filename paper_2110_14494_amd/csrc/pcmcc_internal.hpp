@@ -137,16 +137,18 @@ struct WeightWork {
 };
 // Self-consistent field: multigrid levels and the time-step selection state.
 constexpr int kMgMaxLevels = 16;
-constexpr int kMgCoarseMax = 2048;  // cells of the coarsest level (solved in LDS)
+constexpr int kMgCoarseMax = 4096;  // cells of the coarsest level (solved in LDS)
 struct MgDims {
   int nx, ny, nz;
 };
 struct MgWork {
   int levels;
   MgDims dims[kMgMaxLevels];
-  double* u[kMgMaxLevels];  // u[0]: the potential
-  double* f[kMgMaxLevels];
-  double dx;                // finest spacing
+  float* u[kMgMaxLevels];  // correction cycle: u[0] the correction of the potential
+  float* f[kMgMaxLevels];  // f[0]: the defect of the potential
+  double* rhs;             // right-hand side of the potential
+  double* phi;             // the potential
+  double dx;               // finest spacing
 };
 struct SelState {
   uint32_t prefix;
@@ -157,7 +159,8 @@ int mg_levels(int nx, int ny, int nz, MgDims* dims);
 hipError_t launch_sc_rhs(const int64_t* np, const int64_t* ne, const int64_t* nn, size_t n, double scale, double* f,
                          unsigned long long* fmax, hipStream_t s);
 hipError_t mg_vcycle(const MgWork& W, int l, hipStream_t s);
-hipError_t launch_residual_max(const MgWork& W, unsigned long long* rmax, hipStream_t s);
+hipError_t launch_defect(const MgWork& W, unsigned long long* rmax, hipStream_t s);
+hipError_t launch_correct(const MgWork& W, hipStream_t s);
 hipError_t launch_sc_field(const float4* Ea, const double* phi, int nx, int ny, int nz, double dx, float4* E,
                            hipStream_t s);
 hipError_t launch_speed_select(const float* vx, const float* vy, const float* vz, const int64_t* n_dev, uint64_t n,
