@@ -147,3 +147,26 @@ def test_coupled_run_neutral_start_and_charge_conservation():
     assert int(n_pos.sum()) - int(info["n_e"].sum()) - int(n_neg.sum()) == 0
     assert np.max(np.abs(info["phi"])) > 0
     assert all(0 < d <= 2e-12 for d in info["dt"])
+
+
+def test_event_lists_balance_the_weights():
+    # Every ionization event carries its newborn's weight and every
+    # attachment event the attached electron's: over a run in which nothing
+    # leaves the box, the electrons' total weight changes by exactly the
+    # events' weights, and the event counts equal the collision counts.
+    cfg = W.plain_swarm_config(n=2000)
+    cfg["grid"] = W.uniform_grid(16, 80e-6, (0.0, 0.0, 1.2e7))
+    parts = W.uniform_box_particles(2000, 0.5e-3, 0.8e-3, 1e6, seed=5)
+    parts["w"] = np.random.default_rng(6).uniform(1, 50, 2000).astype(np.float32)
+    rc, out, st = oracle.pic_run(cfg["species"], cfg["tables"], cfg["grid"], parts, 1e-12, 4, 9, events=True,
+                                 capacity=100_000)
+    assert rc == 0 and st["lost"] == 0 and st["ionization"] > 100
+    ion, att = st["ion_events"], st["att_events"]
+    assert ion.shape[0] == st["ionization"] and att.shape[0] == st["attachment"]
+    w_in = float(np.sum(parts["w"], dtype=np.float64))
+    w_out = float(np.sum(out["w"], dtype=np.float64))
+    assert abs(w_out - (w_in + float(np.sum(ion[:, 3], dtype=np.float64)) - float(np.sum(att[:, 3], dtype=np.float64)))) \
+        <= 1e-9 * w_in
+    # the events lie inside the box
+    hi = 16 * 80e-6
+    assert np.all((ion[:, :3] >= 0) & (ion[:, :3] < hi))
