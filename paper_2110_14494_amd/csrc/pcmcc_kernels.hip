@@ -320,14 +320,14 @@ __global__ void k_finalize(Soa user, Soa scratch, Ctl* ctl, int64_t* n_dev) {
 // Field bounds per cell: largest |E| over the 4x4x4 centres (i-1..i+2 per
 // axis, clamped) and the norm of the per-component ranges there; plus the
 // global maximum of |E| (as ordered bits of a non-negative float).
-__global__ void k_field_bounds(const float4* __restrict__ E, int nx, int ny, int nz, float2* __restrict__ out,
-                               unsigned* __restrict__ emax_bits) {
-  const size_t ncell = (size_t)nx * ny * nz;
+// Threads along x, one block row per j (blockIdx.y); blockIdx.z strides over
+// the planes, so the largest |E| takes few atomics.
+__global__ __launch_bounds__(128) void k_field_bounds(const float4* __restrict__ E, int nx, int ny, int nz,
+                                                      float2* __restrict__ out, unsigned* __restrict__ emax_bits) {
   float local_max = 0.0f;
-  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncell; c += (size_t)gridDim.x * blockDim.x) {
-    const int i = (int)(c % nx);
-    const int j = (int)((c / nx) % ny);
-    const int k = (int)(c / ((size_t)nx * ny));
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+  for (int k = blockIdx.z; i < nx && k < nz; k += gridDim.z) {
+    const size_t c = ((size_t)k * ny + j) * nx + i;
     float m = 0.0f;
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int kk = max(k - 1, 0); kk <= min(k + 2, nz - 1); ++kk)
@@ -348,19 +348,21 @@ __global__ void k_field_bounds(const float4* __restrict__ E, int nx, int ny, int
     local_max = fmaxf(local_max, sqrtf(e.x * e.x + e.y * e.y + e.z * e.z));
   }
   for (int off = 32; off > 0; off >>= 1) local_max = fmaxf(local_max, __shfl_xor(local_max, off));
-  if (lane_id() == 0) atomicMax(emax_bits, __float_as_uint(local_max));
+  if (lane_id() == 0 && local_max > 0.0f) atomicMax(emax_bits, __float_as_uint(local_max));
 }
 
 // Corner-packed field (layout in pcmcc_device.hpp): one thread per record,
 // the record of lower centre index (i, j, k) in [-1, n]^3 holding the fields
 // of the 8 centres around it (indices clamped to the grid) and the bound of
 // the cell clamp(i, j, k).
-__global__ void k_pack_field(const float4* __restrict__ E, const float2* __restrict__ bound, int nx, int ny, int nz,
-                             float4* __restrict__ P) {
+// One block row of records per (j, k) in [-1, n]^2 (blockIdx.y, blockIdx.z).
+__global__ __launch_bounds__(128) void k_pack_field(const float4* __restrict__ E, const float2* __restrict__ bound,
+                                                    int nx, int ny, int nz, float4* __restrict__ P) {
   const uint64_t px = (uint64_t)nx + 2, py = (uint64_t)ny + 2;
-  const uint64_t nrec = px * py * ((uint64_t)nz + 2);
-  for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nrec; r += (uint64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(r % px) - 1, j = (int)((r / px) % py) - 1, k = (int)(r / (px * py)) - 1;
+  const int ri = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ri < nx + 2) {
+    const uint64_t r = ((uint64_t)blockIdx.z * py + blockIdx.y) * px + (uint64_t)ri;
+    const int i = ri - 1, j = (int)blockIdx.y - 1, k = (int)blockIdx.z - 1;
     const int ci[2] = {min(max(i, 0), nx - 1), min(max(i + 1, 0), nx - 1)};
     const int cj[2] = {min(max(j, 0), ny - 1), min(max(j + 1, 0), ny - 1)};
     const int ck[2] = {min(max(k, 0), nz - 1), min(max(k + 1, 0), nz - 1)};
@@ -468,17 +470,15 @@ hipError_t launch_finalize(const Soa& user, const Soa& scratch, Ctl* ctl, int64_
 
 hipError_t launch_field_bounds(const float4* E, int nx, int ny, int nz, float2* out, unsigned* emax_bits,
                                hipStream_t stream) {
-  const size_t ncell = (size_t)nx * ny * nz;
-  const int blocks = (int)std::min<size_t>((ncell + 255) / 256, 16384);
-  hipLaunchKernelGGL(k_field_bounds, dim3(blocks), dim3(256), 0, stream, E, nx, ny, nz, out, emax_bits);
+  hipLaunchKernelGGL(k_field_bounds, dim3((unsigned)((nx + 127) / 128), (unsigned)ny, (unsigned)std::min(nz, 16)),
+                     dim3(128), 0, stream, E, nx, ny, nz, out, emax_bits);
   return hipGetLastError();
 }
 
 hipError_t launch_pack_field(const float4* E, const float2* bound, int nx, int ny, int nz, float4* P,
                              hipStream_t stream) {
-  const uint64_t nrec = ((uint64_t)nx + 2) * ((uint64_t)ny + 2) * ((uint64_t)nz + 2);
-  const uint64_t blocks = std::min<uint64_t>((nrec + 255) / 256, 65536);
-  hipLaunchKernelGGL(k_pack_field, dim3((unsigned)blocks), dim3(256), 0, stream, E, bound, nx, ny, nz, P);
+  hipLaunchKernelGGL(k_pack_field, dim3((unsigned)((nx + 2 + 127) / 128), (unsigned)(ny + 2), (unsigned)(nz + 2)),
+                     dim3(128), 0, stream, E, bound, nx, ny, nz, P);
   return hipGetLastError();
 }
 
