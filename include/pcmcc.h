@@ -411,8 +411,11 @@ typedef struct pcmcc_sc_opts {
  * grew).  *dt_inout: host, the first step in, the next step out; dt_hist
  * (host [n_steps], nullable) receives the steps taken.  phi (device double)
  * is the multigrid start value and holds the last potential; E_out (device
- * float4, nullable) the field of the final state.  On an error the particles
- * and ion grids hold the state after stats->steps_done steps.  Synchronises
+ * float4, nullable) the field of the final state.  On an error from a step
+ * (PCMCC_ECAPACITY, PCMCC_ERANGE from a weight update) the particles and ion
+ * grids hold the state after stats->steps_done steps; on PCMCC_ERANGE from the
+ * deposit of a step's ions the particles hold the state after steps_done
+ * steps and the ion grids lack (part of) that last step's ions.  Synchronises
  * the stream. */
 int pcmcc_streamer_steps(pcmcc_ctx* ctx, const pcmcc_particles* p, const pcmcc_grid* applied, int64_t* n_pos,
                          int64_t* n_neg, double* phi, float* E_out, const pcmcc_sc_opts* opts, int n_steps,

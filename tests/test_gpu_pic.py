@@ -304,6 +304,40 @@ def test_full_size_streamer_sampled_lineages(pic):
     assert res["matched"] >= 0.999 * o["id"].size
 
 
+def test_stress_stage_sampled_lineages(pic):
+    # The large stress stage at full size (2^27 electrons, 512^3 cells of
+    # 20 um, 1 ps steps, background 1.75e6 V/m) in the launch configuration of
+    # the step kernel, compared as above on the descendants of a sample, with
+    # exact charge conservation of the full deposit.
+    cfg = W.stress_config(background=1.75e6)
+    parts = cfg["parts"]
+    n = parts["x"].size
+    steps = 2
+    ctx = _ctx(pic, cfg["species"], cfg["tables"])
+    dp = pic.Particles.from_numpy(parts, 2 * n)
+    dg = pic.DeviceGrid(cfg["grid"])
+    rho = dg.zeros_rho()
+    print(f"[gpu] stress stage n={n} steps={steps}", flush=True)
+    rc, st = ctx.push_collide_deposit(dp, dg, cfg["dt"], steps, cfg["seed"], rho=rho)
+    assert rc == 0 and st["steps_done"] == steps
+    gpu_id = dp.t["id"][:st["n"]].cpu().numpy()
+    # exact totals near 2^63 units: int64 sums of chunks, added as Python ints
+    chunked = lambda t: sum(int(c.sum().item()) for c in t.reshape(-1).split(1 << 22))
+    w = dp.t["w"][:st["n"]].double()
+    w2 = torch.round(torch.ldexp(w, torch.tensor(32, device=w.device))).to(torch.int64)
+    assert chunked(rho) == chunked(w2)
+    sample = np.sort(np.random.default_rng(11).choice(n, 2 ** 13, replace=False))
+    sub = {k: v[sample] for k, v in parts.items()}
+    orc_rc, o, ost = oracle.pic_run(cfg["species"], cfg["tables"], cfg["grid"], sub, cfg["dt"], steps, cfg["seed"],
+                                    capacity=4 * sample.size)
+    assert orc_rc == 0 and ost["ionization"] > 0
+    sel = torch.from_numpy(np.flatnonzero(np.isin(gpu_id, o["id"]))).cuda()
+    gpu = {k: dp.t[k][:st["n"]][sel].cpu().numpy() for k in ("x", "y", "z", "vx", "vy", "vz", "w", "id")}
+    ctx.close()
+    res = _assert_parity(gpu, o, cfg["grid"]["dx"], ost["trials"])
+    assert res["matched"] >= 0.999 * o["id"].size
+
+
 def test_attachment_dominated_hole_filling(pic):
     # Strong attachment, weak ionization: removed particles outnumber newborns,
     # so the tail fill path runs every step.
