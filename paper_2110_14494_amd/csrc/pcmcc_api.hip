@@ -736,6 +736,21 @@ static int push_impl(pcmcc_ctx* c, const pcmcc_particles* p, const pcmcc_grid* f
   }
   std::memset(c->host_ctl, 0, sizeof(Ctl));
   c->host_ctl->n_cur = (unsigned long long)n0;
+  // The steps alternate between the caller's arrays and the scratch buffer.
+  // For an odd step count, start from a copy in the scratch buffer so that
+  // the last step lands in the caller's arrays: copying the start population
+  // is cheaper than copying back the grown one (any other outcome is copied
+  // back at the end as usual).
+  if ((n_steps & 1) && n0 > 0) {
+    float* const from[7] = {p->x, p->y, p->z, p->vx, p->vy, p->vz, p->w};
+    float* const to[7] = {c->scratch.x, c->scratch.y, c->scratch.z, c->scratch.vx, c->scratch.vy, c->scratch.vz,
+                          c->scratch.w};
+    for (int k = 0; k < 7; ++k)
+      HIP_TRY(c, hipMemcpyAsync(to[k], from[k], (size_t)n0 * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->scratch.id, p->id, (size_t)n0 * sizeof(uint64_t), hipMemcpyDeviceToDevice,
+                              c->stream));
+    c->host_ctl->cur_sel = 1;
+  }
   HIP_TRY(c, hipMemcpyAsync(c->ctl, c->host_ctl, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
 
   PicArgs A{};

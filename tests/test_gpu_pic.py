@@ -320,7 +320,7 @@ def test_stress_stage_sampled_lineages(pic):
     print(f"[gpu] stress stage n={n} steps={steps}", flush=True)
     rc, st = ctx.push_collide_deposit(dp, dg, cfg["dt"], steps, cfg["seed"], rho=rho)
     assert rc == 0 and st["steps_done"] == steps
-    gpu_id = dp.t["id"][:st["n"]].cpu().numpy()
+    gpu_id = dp.t["id"][:st["n"]].cpu().numpy().view(np.uint64)  # ids are stored as int64 bit patterns
     # exact totals near 2^63 units: int64 sums of chunks, added as Python ints
     chunked = lambda t: sum(int(c.sum().item()) for c in t.reshape(-1).split(1 << 22))
     w = dp.t["w"][:st["n"]].double()
@@ -332,7 +332,8 @@ def test_stress_stage_sampled_lineages(pic):
                                     capacity=4 * sample.size)
     assert orc_rc == 0 and ost["ionization"] > 0
     sel = torch.from_numpy(np.flatnonzero(np.isin(gpu_id, o["id"]))).cuda()
-    gpu = {k: dp.t[k][:st["n"]][sel].cpu().numpy() for k in ("x", "y", "z", "vx", "vy", "vz", "w", "id")}
+    gpu = {k: dp.t[k][:st["n"]][sel].cpu().numpy() for k in ("x", "y", "z", "vx", "vy", "vz", "w")}
+    gpu["id"] = dp.t["id"][:st["n"]][sel].cpu().numpy().view(np.uint64)
     ctx.close()
     res = _assert_parity(gpu, o, cfg["grid"]["dx"], ost["trials"])
     assert res["matched"] >= 0.999 * o["id"].size
