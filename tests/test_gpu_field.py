@@ -192,3 +192,41 @@ def test_coupled_adaptive_steps_match_oracle_in_ensemble(pic):
     assert np.max(np.abs(gpu["E"] - info["E"])) <= 0.05 * scale
     n_e_g = oracle.deposit(g["x"], g["y"], g["z"], g["w"], grid)
     assert int(gpu["n_pos"].sum()) - int(n_e_g.sum()) - int(gpu["n_neg"].sum()) == 0
+
+
+def test_error_paths(pic):
+    # a grid that does not coarsen to a small enough level, missing species,
+    # invalid options: errors, not faults
+    from paper_2110_14494_amd import _binding as B
+    ctx = pic.Context(0)
+    g = _grid(65, 65, 65, 1e-5)
+    dg = pic.DeviceGrid(g)
+    z = torch.zeros((65, 65, 65), dtype=torch.int64, device="cuda")
+    phi = torch.zeros((65, 65, 65), dtype=torch.float64, device="cuda")
+    with pytest.raises(B.PcmccError) as e:
+        ctx.solve_potential(dg, z, z, z, phi)
+    assert e.value.code == B.PCMCC_EINVAL
+    dg8 = pic.DeviceGrid(_grid(8, 8, 8, 1e-5))
+    d8 = torch.zeros((8, 8, 8), dtype=torch.float64, device="cuda")
+    tab = {"EN_lo": 10.0, "EN_hi": 1000.0, "muN": np.ones(4), "DN": np.ones(4), "alphaN": np.zeros(4),
+           "etaN": np.zeros(4)}
+    rc, _, _ = ctx.fluid_steps(dg8, d8, d8.clone(), d8.clone(), d8.clone(), tab, 1e-12, 1, check=False)
+    assert rc == B.PCMCC_ESTATE  # no species yet: the gas density is unknown
+    ctx.init_species(W.electron_species())
+    bad = dict(tab, EN_hi=5.0)
+    rc, _, _ = ctx.fluid_steps(dg8, d8, d8.clone(), d8.clone(), d8.clone(), bad, 1e-12, 1, check=False)
+    assert rc == B.PCMCC_EINVAL
+    rc, _, _ = ctx.fluid_steps(dg8, d8, d8.clone(), d8.clone(), d8.clone(), tab, -1.0, 1, check=False)
+    assert rc == B.PCMCC_EINVAL
+    cfg, parts = _coupled_case(n=100)
+    ctx.setup(cfg["species"], cfg["tables"])
+    dp = pic.Particles.from_numpy(parts, 1000)
+    dg16 = pic.DeviceGrid(cfg["grid"])
+    n16 = torch.zeros((16, 16, 16), dtype=torch.int64, device="cuda")
+    p16 = torch.zeros((16, 16, 16), dtype=torch.float64, device="cuda")
+    rc, _, _, _ = ctx.streamer_steps(dp, dg16, n16, n16.clone(), p16, 1e-12, 1, 0, growth_max=0.5, check=False)
+    assert rc == B.PCMCC_EINVAL
+    rc, _, _, _ = ctx.streamer_steps(dp, dg16, n16, n16.clone(), p16, -1e-12, 1, 0, check=False)
+    assert rc == B.PCMCC_EINVAL
+    assert dp.n == 100  # nothing moved
+    ctx.close()
