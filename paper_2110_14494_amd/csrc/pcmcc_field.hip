@@ -200,11 +200,14 @@ __global__ __launch_bounds__(128) void k_mg_defect(const double* __restrict__ ph
                                                    int nx, int ny, int nz, double inv_h2, float* __restrict__ r,
                                                    unsigned long long* rmax) {
 #pragma clang fp contract(off)
-  // blockIdx.z strides over the planes: a block reduces several rows
+  // blockIdx.z takes a contiguous range of planes (the neighbour planes stay
+  // in cache from one plane to the next); a block reduces several rows
   const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+  const int per = (nz + (int)gridDim.z - 1) / (int)gridDim.z;
+  const int k0 = (int)blockIdx.z * per, k1 = min(nz, k0 + per);
   double m = 0.0;
   if (i < nx) {
-    for (int k = blockIdx.z; k < nz; k += gridDim.z) {
+    for (int k = k0; k < k1; ++k) {
       const size_t c = idx3(i, j, k, nx, ny);
       double d;
       const double s = nb_sum(phi, i, j, k, nx, ny, nz, d);
@@ -379,8 +382,8 @@ hipError_t mg_vcycle(const MgWork& W, int l, hipStream_t s) {
   const float h2 = (float)(h * h);
   if (l == W.levels - 1) {
     const int m = d.nx > d.ny ? (d.nx > d.nz ? d.nx : d.nz) : (d.ny > d.nz ? d.ny : d.nz);
-    int iters = 8 * m * m;
-    iters = iters < 64 ? 64 : (iters > 4096 ? 4096 : iters);
+    int iters = 4 * m * m;  // enough red-black sweeps for a grid of m cells a side
+    iters = iters < 16 ? 16 : (iters > 4096 ? 4096 : iters);
     hipLaunchKernelGGL(k_mg_coarse, dim3(1), dim3(256), 0, s, W.u[l], W.f[l], d.nx, d.ny, d.nz, h2, iters);
     return hipGetLastError();
   }

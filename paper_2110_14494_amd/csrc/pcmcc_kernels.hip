@@ -320,13 +320,16 @@ __global__ void k_finalize(Soa user, Soa scratch, Ctl* ctl, int64_t* n_dev) {
 // Field bounds per cell: largest |E| over the 4x4x4 centres (i-1..i+2 per
 // axis, clamped) and the norm of the per-component ranges there; plus the
 // global maximum of |E| (as ordered bits of a non-negative float).
-// Threads along x, one block row per j (blockIdx.y); blockIdx.z strides over
-// the planes, so the largest |E| takes few atomics.
+// Threads along x, one block row per j (blockIdx.y); blockIdx.z takes a
+// contiguous range of planes (the neighbour planes stay in cache), so the
+// largest |E| takes few atomics.
 __global__ __launch_bounds__(128) void k_field_bounds(const float4* __restrict__ E, int nx, int ny, int nz,
                                                       float2* __restrict__ out, unsigned* __restrict__ emax_bits) {
   float local_max = 0.0f;
   const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
-  for (int k = blockIdx.z; i < nx && k < nz; k += gridDim.z) {
+  const int per = (nz + (int)gridDim.z - 1) / (int)gridDim.z;
+  const int k0 = (int)blockIdx.z * per, k1 = min(nz, k0 + per);
+  for (int k = k0; i < nx && k < k1; ++k) {
     const size_t c = ((size_t)k * ny + j) * nx + i;
     float m = 0.0f;
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
