@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "pcmcc.h"
+#include "pcmcc_field.hpp"
 #include "pcmcc_internal.hpp"
 
 using namespace pcmcc;
@@ -88,6 +89,8 @@ struct pcmcc_ctx {
   size_t mg_store_n = 0;
   double* mg_rhs = nullptr;
   size_t mg_rhs_n = 0;
+  double* mg_part = nullptr;  // per-block maxima of the defect pass
+  size_t mg_part_n = 0;
   MgDims mg_dims0{0, 0, 0};
   float4* sc_E = nullptr;
   int64_t* sc_ne = nullptr;
@@ -601,6 +604,7 @@ int pcmcc_destroy(pcmcc_ctx* c) {
   dfree(c->dev_n);
   dfree(c->mg_store);
   dfree(c->mg_rhs);
+  dfree(c->mg_part);
   dfree(c->sc_E);
   dfree(c->sc_ne);
   dfree(c->ev_store);
@@ -1539,9 +1543,18 @@ int ensure_sc(pcmcc_ctx* c, const pcmcc_grid* g) {
       HIP_TRY(c, dalloc(&c->mg_rhs, ncell));
       c->mg_rhs_n = ncell;
     }
+    const size_t nparts = defect_blocks(g->nx, g->ny, g->nz);
+    if (c->mg_part_n < nparts) {
+      dfree(c->mg_part);
+      c->mg_part = nullptr;
+      c->mg_part_n = 0;
+      HIP_TRY(c, dalloc(&c->mg_part, nparts));
+      c->mg_part_n = nparts;
+    }
     c->mg = MgWork{};
     c->mg.levels = L;
     c->mg.rhs = c->mg_rhs;
+    c->mg.part = c->mg_part;
     float* q = c->mg_store;
     for (int l = 0; l < L; ++l) {
       c->mg.dims[l] = d[l];

@@ -13,8 +13,8 @@
 //   computed in double precision, the correction solved by one V(2,2) cycle in
 //   single precision (red-black Gauss-Seidel smoothing, restriction by the
 //   mean of the 8 children, trilinear prolongation with the error's ghost
-//   rules, the coarsest grid - every dimension halved while all are even and
-//   above 2 - solved by one block in LDS) and added to the potential; the
+//   rules, every dimension halved while all are even and above 2, the levels
+//   of at most 4096 cells run by one block in LDS) and added to the potential; the
 //   iteration converges to the double-precision solution of the discrete
 //   system while the cycles move half the bytes.  All passes are
 //   HBM-streaming stencils.
@@ -25,6 +25,7 @@
 
 #include <climits>
 
+#include "pcmcc_field.hpp"
 #include "pcmcc_internal.hpp"
 
 namespace pcmcc {
@@ -61,20 +62,25 @@ __device__ __forceinline__ void block_max_to(unsigned long long* a, double v) {
 
 // Sum of the neighbours present and the diagonal of the stencil at (i,j,k):
 // a missing x/y neighbour is a Neumann ghost (diagonal 6 -> one less), a
-// missing z neighbour a Dirichlet ghost (one more).
+// missing z neighbour a Dirichlet ghost (one more).  The six loads are issued
+// together (a missing neighbour reads the cell itself and is then replaced by
+// zero) and summed in the order -x, +x, -y, +y, -z, +z.
 template <class T>
 __device__ __forceinline__ T nb_sum(const T* u, int i, int j, int k, int nx, int ny, int nz, T& diag) {
   const size_t c = idx3(i, j, k, nx, ny);
   const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
+  const bool xm = i > 0, xp = i < nx - 1, ym = j > 0, yp = j < ny - 1, zm = k > 0, zp = k < nz - 1;
+  const T a = u[xm ? c - 1 : c], b = u[xp ? c + 1 : c];
+  const T e = u[ym ? c - sy : c], f = u[yp ? c + sy : c];
+  const T g = u[zm ? c - sz : c], h = u[zp ? c + sz : c];
   T s = 0;
-  T d = 6;
-  if (i > 0) s += u[c - 1]; else d -= 1;
-  if (i < nx - 1) s += u[c + 1]; else d -= 1;
-  if (j > 0) s += u[c - sy]; else d -= 1;
-  if (j < ny - 1) s += u[c + sy]; else d -= 1;
-  if (k > 0) s += u[c - sz]; else d += 1;
-  if (k < nz - 1) s += u[c + sz]; else d += 1;
-  diag = d;
+  s += xm ? a : T(0);
+  s += xp ? b : T(0);
+  s += ym ? e : T(0);
+  s += yp ? f : T(0);
+  s += zm ? g : T(0);
+  s += zp ? h : T(0);
+  diag = (T)(6 - (int)!xm - (int)!xp - (int)!ym - (int)!yp + (int)!zm + (int)!zp);
   return s;
 }
 
@@ -94,15 +100,15 @@ __global__ void k_sc_rhs(const int64_t* __restrict__ np, const int64_t* __restri
   block_max_to(fmax_bits, m);
 }
 
-// Launch shape of the level kernels: x threads along a row, one block row
-// per (j, k) in blockIdx.y / blockIdx.z (no index division).
+// The level kernels are row stencils (row_pos: XCD-local runs of rows).
 
 // One red-black Gauss-Seidel half sweep: cells with (i + j + k) % 2 == color.
-__global__ __launch_bounds__(128) void k_mg_smooth(float* __restrict__ u, const float* __restrict__ f, int nx,
-                                                   int ny, int nz, float h2, int color) {
+__global__ __launch_bounds__(kRowThreads) void k_mg_smooth(float* __restrict__ u, const float* __restrict__ f,
+                                                           int nx, int ny, int nz, float h2, int color) {
 #pragma clang fp contract(off)
-  const int j = blockIdx.y, k = blockIdx.z;
-  const int i = 2 * (int)(blockIdx.x * blockDim.x + threadIdx.x) + ((j + k + color) & 1);
+  const RowPos P = row_pos((nx + 1) / 2, ny);
+  const int j = P.j, k = P.k;
+  const int i = 2 * (P.x0 + (int)threadIdx.x) + ((j + k + color) & 1);
   if (i >= nx) return;
   float d;
   const float s = nb_sum(u, i, j, k, nx, ny, nz, d);
@@ -112,11 +118,13 @@ __global__ __launch_bounds__(128) void k_mg_smooth(float* __restrict__ u, const 
 
 // Residual r = f - L u of the 8 children of every coarse cell, averaged into
 // the coarse right-hand side.
-__global__ __launch_bounds__(128) void k_mg_restrict(const float* __restrict__ u, const float* __restrict__ f,
-                                                     int nx, int ny, int nz, float inv_h2, float* __restrict__ fc) {
+__global__ __launch_bounds__(kRowThreads) void k_mg_restrict(const float* __restrict__ u,
+                                                             const float* __restrict__ f, int nx, int ny, int nz,
+                                                             float inv_h2, float* __restrict__ fc) {
 #pragma clang fp contract(off)
   const int cx = nx / 2, cy = ny / 2;
-  const int I = blockIdx.x * blockDim.x + threadIdx.x, J = blockIdx.y, K = blockIdx.z;
+  const RowPos P = row_pos(cx, cy);
+  const int I = P.x0 + (int)threadIdx.x, J = P.j, K = P.k;
   if (I < cx) {
     float acc = 0.0f;
     for (int q = 0; q < 8; ++q) {
@@ -146,11 +154,12 @@ __device__ __forceinline__ float coarse_at(const float* U, int I, int J, int K, 
 }
 
 // u_fine += trilinear interpolation of the coarse correction.
-__global__ __launch_bounds__(128) void k_mg_prolong(float* __restrict__ u, const float* __restrict__ U, int nx,
-                                                    int ny, int nz) {
+__global__ __launch_bounds__(kRowThreads) void k_mg_prolong(float* __restrict__ u, const float* __restrict__ U,
+                                                            int nx, int ny, int nz) {
 #pragma clang fp contract(off)
   const int cx = nx / 2, cy = ny / 2, cz = nz / 2;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+  const RowPos P = row_pos(nx, ny);
+  const int i = P.x0 + (int)threadIdx.x, j = P.j, k = P.k;
   if (i < nx) {
     const size_t c = idx3(i, j, k, nx, ny);
     const int I = i >> 1, J = j >> 1, K = k >> 1;
@@ -165,49 +174,123 @@ __global__ __launch_bounds__(128) void k_mg_prolong(float* __restrict__ u, const
   }
 }
 
-// Coarsest level: one block, LDS, red-black sweeps (the level is at most
-// kMgCoarseMax cells).
-__global__ __launch_bounds__(256) void k_mg_coarse(float* __restrict__ u, const float* __restrict__ f, int nx,
-                                                    int ny, int nz, float h2, int iters) {
+// The levels of a V(2,2) cycle from the first one of at most kMgCoarseMax
+// cells down to the coarsest, run by one block with every level in LDS (the
+// same arithmetic as the level kernels; one launch instead of about eleven
+// per level).  The coarsest level takes `coarse_iters` red-black sweeps.
+constexpr int kMgTailCells = 4696;  // >= kMgCoarseMax * (1 + 1/8 + 1/64 + ...)
+struct MgTailArgs {
+  float* u;        // the first tail level's correction (global; starts at zero)
+  const float* f;  // its right-hand side (global)
+  int first, levels, coarse_iters;
+  MgDims d[kMgMaxLevels];
+  float h2[kMgMaxLevels];
+  float inv_h2[kMgMaxLevels];
+};
+
+__device__ void tail_smooth(float* u, const float* f, MgDims d, float h2, int color) {
 #pragma clang fp contract(off)
-  __shared__ float s_u[kMgCoarseMax];
-  __shared__ float s_f[kMgCoarseMax];
-  const int n = nx * ny * nz;
+  const int n = d.nx * d.ny * d.nz;
   for (int c = threadIdx.x; c < n; c += blockDim.x) {
-    s_u[c] = u[c];
-    s_f[c] = f[c];
+    const int i = c % d.nx, j = (c / d.nx) % d.ny, k = c / (d.nx * d.ny);
+    if (((i + j + k) & 1) != color) continue;
+    float dg;
+    const float s = nb_sum(u, i, j, k, d.nx, d.ny, d.nz, dg);
+    u[c] = (s - h2 * f[c]) / dg;
   }
   __syncthreads();
-  for (int it = 0; it < iters; ++it) {
-    for (int color = 0; color < 2; ++color) {
-      for (int c = threadIdx.x; c < n; c += blockDim.x) {
-        const int i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
-        if (((i + j + k) & 1) != color) continue;
-        float d;
-        const float s = nb_sum(s_u, i, j, k, nx, ny, nz, d);
-        s_u[c] = (s - h2 * s_f[c]) / d;
-      }
-      __syncthreads();
+}
+
+__global__ __launch_bounds__(512) void k_mg_tail(MgTailArgs A) {
+#pragma clang fp contract(off)
+  __shared__ float s_u[kMgTailCells];
+  __shared__ float s_f[kMgTailCells];
+  __shared__ int off[kMgMaxLevels];  // level offsets in s_u / s_f
+  if (threadIdx.x == 0) {
+    int o = 0;
+    for (int l = A.first; l < A.levels; ++l) {
+      off[l] = o;
+      o += A.d[l].nx * A.d[l].ny * A.d[l].nz;
     }
   }
-  for (int c = threadIdx.x; c < n; c += blockDim.x) u[c] = s_u[c];
+  const MgDims d0 = A.d[A.first];
+  const int n0 = d0.nx * d0.ny * d0.nz;
+  for (int c = threadIdx.x; c < n0; c += blockDim.x) {
+    s_u[c] = 0.0f;
+    s_f[c] = A.f[c];
+  }
+  __syncthreads();
+  for (int l = A.first; l < A.levels - 1; ++l) {  // down: pre-smoothing, restriction
+    const MgDims d = A.d[l], dc = A.d[l + 1];
+    float *u = s_u + off[l], *uc = s_u + off[l + 1], *fc = s_f + off[l + 1];
+    const float* f = s_f + off[l];
+    for (int it = 0; it < 2; ++it)
+      for (int color = 0; color < 2; ++color) tail_smooth(u, f, d, A.h2[l], color);
+    const int nc = dc.nx * dc.ny * dc.nz;
+    for (int C = threadIdx.x; C < nc; C += blockDim.x) {
+      const int I = C % dc.nx, J = (C / dc.nx) % dc.ny, K = C / (dc.nx * dc.ny);
+      float acc = 0.0f;
+      for (int q = 0; q < 8; ++q) {
+        const int i = 2 * I + (q & 1), j = 2 * J + ((q >> 1) & 1), k = 2 * K + (q >> 2);
+        float dg;
+        const float s = nb_sum(u, i, j, k, d.nx, d.ny, d.nz, dg);
+        const size_t c = idx3(i, j, k, d.nx, d.ny);
+        acc += f[c] - (s - dg * u[c]) * A.inv_h2[l];
+      }
+      fc[C] = 0.125f * acc;
+      uc[C] = 0.0f;
+    }
+    __syncthreads();
+  }
+  {
+    const int l = A.levels - 1;
+    for (int it = 0; it < A.coarse_iters; ++it)
+      for (int color = 0; color < 2; ++color) tail_smooth(s_u + off[l], s_f + off[l], A.d[l], A.h2[l], color);
+  }
+  for (int l = A.levels - 2; l >= A.first; --l) {  // up: prolongation, post-smoothing
+    const MgDims d = A.d[l], dc = A.d[l + 1];
+    float* u = s_u + off[l];
+    const float* U = s_u + off[l + 1];
+    const int n = d.nx * d.ny * d.nz;
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {
+      const int i = c % d.nx, j = (c / d.nx) % d.ny, k = c / (d.nx * d.ny);
+      const int I = i >> 1, J = j >> 1, K = k >> 1;
+      const int I2 = I + ((i & 1) ? 1 : -1), J2 = J + ((j & 1) ? 1 : -1), K2 = K + ((k & 1) ? 1 : -1);
+      const float v = 27.0f * coarse_at(U, I, J, K, dc.nx, dc.ny, dc.nz) +
+                      9.0f * (coarse_at(U, I2, J, K, dc.nx, dc.ny, dc.nz) + coarse_at(U, I, J2, K, dc.nx, dc.ny, dc.nz) +
+                              coarse_at(U, I, J, K2, dc.nx, dc.ny, dc.nz)) +
+                      3.0f * (coarse_at(U, I2, J2, K, dc.nx, dc.ny, dc.nz) +
+                              coarse_at(U, I2, J, K2, dc.nx, dc.ny, dc.nz) +
+                              coarse_at(U, I, J2, K2, dc.nx, dc.ny, dc.nz)) +
+                      coarse_at(U, I2, J2, K2, dc.nx, dc.ny, dc.nz);
+      u[c] += v * (1.0f / 64.0f);
+    }
+    __syncthreads();
+    for (int it = 0; it < 2; ++it)
+      for (int color = 0; color < 2; ++color) tail_smooth(u, s_f + off[l], d, A.h2[l], color);
+  }
+  for (int c = threadIdx.x; c < n0; c += blockDim.x) A.u[c] = s_u[c];
 }
 
 // Defect of the potential, r = rhs - L phi in double precision: stored in
-// single precision as the right-hand side of the correction cycle, and its
-// largest magnitude.
-__global__ __launch_bounds__(128) void k_mg_defect(const double* __restrict__ phi, const double* __restrict__ rhs,
-                                                   int nx, int ny, int nz, double inv_h2, float* __restrict__ r,
-                                                   unsigned long long* rmax) {
+// single precision as the right-hand side of the correction cycle; a block
+// takes kDefectRows consecutive row blocks and its largest magnitude goes to
+// part[block] (k_max_parts reduces them:
+// one same-address atomic per block would serialise in the memory-side
+// atomic unit).
+__global__ __launch_bounds__(kRowThreads) void k_mg_defect(const double* __restrict__ phi,
+                                                           const double* __restrict__ rhs, int nx, int ny, int nz,
+                                                           double inv_h2, float* __restrict__ r,
+                                                           double* __restrict__ part) {
 #pragma clang fp contract(off)
-  // blockIdx.z takes a contiguous range of planes (the neighbour planes stay
-  // in cache from one plane to the next); a block reduces several rows
-  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
-  const int per = (nz + (int)gridDim.z - 1) / (int)gridDim.z;
-  const int k0 = (int)blockIdx.z * per, k1 = min(nz, k0 + per);
+  __shared__ double s_w[kRowThreads / 64];
+  const unsigned nrb = (unsigned)((nx + kRowThreads - 1) / kRowThreads) * (unsigned)ny * (unsigned)nz;
+  const unsigned L0 = xcd_block() * kDefectRows;
   double m = 0.0;
-  if (i < nx) {
-    for (int k = k0; k < k1; ++k) {
+  for (unsigned L = L0; L < L0 + kDefectRows && L < nrb; ++L) {
+    const RowPos P = row_at(L, nx, ny);
+    const int i = P.x0 + (int)threadIdx.x, j = P.j, k = P.k;
+    if (i < nx) {
       const size_t c = idx3(i, j, k, nx, ny);
       double d;
       const double s = nb_sum(phi, i, j, k, nx, ny, nz, d);
@@ -216,7 +299,28 @@ __global__ __launch_bounds__(128) void k_mg_defect(const double* __restrict__ ph
       m = fmax(m, fabs(v));
     }
   }
-  block_max_to(rmax, m);
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x / 64] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kRowThreads / 64; ++w) m = fmax(m, s_w[w]);
+    part[blockIdx.x] = m;
+  }
+}
+
+// Largest of n non-negative partial maxima, stored as its bit pattern.
+__global__ __launch_bounds__(1024) void k_max_parts(const double* __restrict__ part, unsigned n,
+                                                    unsigned long long* out) {
+  __shared__ double s_w[16];
+  double m = 0.0;
+  for (unsigned q = threadIdx.x; q < n; q += blockDim.x) m = fmax(m, part[q]);
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x / 64] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)blockDim.x / 64; ++w) m = fmax(m, s_w[w]);
+    *out = (unsigned long long)__double_as_longlong(m);
+  }
 }
 
 // phi += the correction.
@@ -228,11 +332,12 @@ __global__ void k_mg_correct(double* __restrict__ phi, const float* __restrict__
 
 
 // E = E_applied - grad phi at the centres (central differences with ghosts).
-__global__ __launch_bounds__(128) void k_sc_field(const float4* __restrict__ Ea, const double* __restrict__ phi,
+__global__ __launch_bounds__(kRowThreads) void k_sc_field(const float4* __restrict__ Ea, const double* __restrict__ phi,
                                                   int nx, int ny, int nz, double two_dx, float4* __restrict__ E) {
 #pragma clang fp contract(off)
   const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+  const RowPos P = row_pos(nx, ny);
+  const int i = P.x0 + (int)threadIdx.x, j = P.j, k = P.k;
   if (i < nx) {
     const size_t c = idx3(i, j, k, nx, ny);
     const double p = phi[c];
@@ -348,8 +453,6 @@ __global__ void k_weight_sum(const float* __restrict__ w, const int64_t* n_dev, 
 // ---------------------------------------------------------------------------
 // Host launchers.
 
-// Rows of n cells: blocks of 128 threads along x, one per (j, k).
-static dim3 rows(int n_x, int ny, int nz) { return dim3((unsigned)((n_x + 127) / 128), (unsigned)ny, (unsigned)nz); }
 
 static unsigned grid_for(size_t n, unsigned cap = 16384) {
   const size_t b = (n + 255) / 256;
@@ -380,38 +483,55 @@ hipError_t mg_vcycle(const MgWork& W, int l, hipStream_t s) {
   const MgDims d = W.dims[l];
   const double h = W.dx * (double)(1 << l);
   const float h2 = (float)(h * h);
-  if (l == W.levels - 1) {
-    const int m = d.nx > d.ny ? (d.nx > d.nz ? d.nx : d.nz) : (d.ny > d.nz ? d.ny : d.nz);
+  if ((size_t)d.nx * d.ny * d.nz <= (size_t)kMgCoarseMax) {
+    MgTailArgs A{};
+    A.u = W.u[l];
+    A.f = W.f[l];
+    A.first = l;
+    A.levels = W.levels;
+    size_t cells = 0;
+    for (int q = l; q < W.levels; ++q) {
+      cells += (size_t)W.dims[q].nx * W.dims[q].ny * W.dims[q].nz;
+      const double hq = W.dx * (double)(1 << q);
+      A.d[q] = W.dims[q];
+      A.h2[q] = (float)(hq * hq);
+      A.inv_h2[q] = 1.0f / A.h2[q];
+    }
+    const MgDims dl = W.dims[W.levels - 1];
+    const int m = dl.nx > dl.ny ? (dl.nx > dl.nz ? dl.nx : dl.nz) : (dl.ny > dl.nz ? dl.ny : dl.nz);
     int iters = 4 * m * m;  // enough red-black sweeps for a grid of m cells a side
-    iters = iters < 16 ? 16 : (iters > 4096 ? 4096 : iters);
-    hipLaunchKernelGGL(k_mg_coarse, dim3(1), dim3(256), 0, s, W.u[l], W.f[l], d.nx, d.ny, d.nz, h2, iters);
+    A.coarse_iters = iters < 16 ? 16 : (iters > 4096 ? 4096 : iters);
+    if (cells > (size_t)kMgTailCells) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_mg_tail, dim3(1), dim3(512), 0, s, A);
     return hipGetLastError();
   }
-  const dim3 gs = rows((d.nx + 1) / 2, d.ny, d.nz);
+  const dim3 gs = row_grid((d.nx + 1) / 2, d.ny, d.nz);
   for (int it = 0; it < 2; ++it)
     for (int color = 0; color < 2; ++color)
-      hipLaunchKernelGGL(k_mg_smooth, gs, dim3(128), 0, s, W.u[l], W.f[l], d.nx, d.ny, d.nz, h2, color);
+      hipLaunchKernelGGL(k_mg_smooth, gs, dim3(kRowThreads), 0, s, W.u[l], W.f[l], d.nx, d.ny, d.nz, h2, color);
   const MgDims dc = W.dims[l + 1];
   const size_t nc = (size_t)dc.nx * dc.ny * dc.nz;
-  hipLaunchKernelGGL(k_mg_restrict, rows(dc.nx, dc.ny, dc.nz), dim3(128), 0, s, W.u[l], W.f[l], d.nx, d.ny, d.nz,
+  hipLaunchKernelGGL(k_mg_restrict, row_grid(dc.nx, dc.ny, dc.nz), dim3(kRowThreads), 0, s, W.u[l], W.f[l], d.nx, d.ny, d.nz,
                      1.0f / h2, W.f[l + 1]);
-  hipError_t e = hipMemsetAsync(W.u[l + 1], 0, nc * sizeof(float), s);
+  hipError_t e = hipSuccess;
+  if (nc > (size_t)kMgCoarseMax) e = hipMemsetAsync(W.u[l + 1], 0, nc * sizeof(float), s);  // the tail zeroes its own
   if (e != hipSuccess) return e;
   e = mg_vcycle(W, l + 1, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_mg_prolong, rows(d.nx, d.ny, d.nz), dim3(128), 0, s, W.u[l], W.u[l + 1], d.nx, d.ny, d.nz);
+  hipLaunchKernelGGL(k_mg_prolong, row_grid(d.nx, d.ny, d.nz), dim3(kRowThreads), 0, s, W.u[l], W.u[l + 1], d.nx,
+                     d.ny, d.nz);
   for (int it = 0; it < 2; ++it)
     for (int color = 0; color < 2; ++color)
-      hipLaunchKernelGGL(k_mg_smooth, gs, dim3(128), 0, s, W.u[l], W.f[l], d.nx, d.ny, d.nz, h2, color);
+      hipLaunchKernelGGL(k_mg_smooth, gs, dim3(kRowThreads), 0, s, W.u[l], W.f[l], d.nx, d.ny, d.nz, h2, color);
   return hipGetLastError();
 }
 
 hipError_t launch_defect(const MgWork& W, unsigned long long* rmax, hipStream_t s) {
   const MgDims d = W.dims[0];
-  dim3 g = rows(d.nx, d.ny, d.nz);
-  g.z = g.z < 16 ? g.z : 16;
-  hipLaunchKernelGGL(k_mg_defect, g, dim3(128), 0, s, W.phi, W.rhs, d.nx, d.ny, d.nz, 1.0 / (W.dx * W.dx), W.f[0],
-                     rmax);
+  const unsigned nb = defect_blocks(d.nx, d.ny, d.nz);
+  hipLaunchKernelGGL(k_mg_defect, dim3(nb), dim3(kRowThreads), 0, s, W.phi, W.rhs, d.nx, d.ny, d.nz,
+                     1.0 / (W.dx * W.dx), W.f[0], W.part);
+  hipLaunchKernelGGL(k_max_parts, dim3(1), dim3(1024), 0, s, W.part, nb, rmax);
   return hipGetLastError();
 }
 
@@ -423,7 +543,7 @@ hipError_t launch_correct(const MgWork& W, hipStream_t s) {
 
 hipError_t launch_sc_field(const float4* Ea, const double* phi, int nx, int ny, int nz, double dx, float4* E,
                            hipStream_t s) {
-  hipLaunchKernelGGL(k_sc_field, rows(nx, ny, nz), dim3(128), 0, s, Ea, phi, nx, ny, nz, 2.0 * dx, E);
+  hipLaunchKernelGGL(k_sc_field, row_grid(nx, ny, nz), dim3(kRowThreads), 0, s, Ea, phi, nx, ny, nz, 2.0 * dx, E);
   return hipGetLastError();
 }
 

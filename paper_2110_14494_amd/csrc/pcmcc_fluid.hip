@@ -15,9 +15,11 @@
 // * Transport data: tables of mu N, D N, alpha / N, eta / N on log-spaced E/N
 //   nodes, linear in ln(E/N), held constant outside.
 // One thread per cell computes its six face fluxes (each face twice: no
-// flux array, one pass over the densities and fields per stage).
+// flux array, one pass over the densities and fields per stage); rows are
+// handed out in XCD-local runs (row_pos).
 #include <hip/hip_runtime.h>
 
+#include "pcmcc_field.hpp"
 #include "pcmcc_internal.hpp"
 
 namespace pcmcc {
@@ -53,10 +55,11 @@ __device__ __forceinline__ double3 e3(float4 e) { return make_double3((double)e.
 
 // One Heun stage on cell (i, j, k).  Stage 1: k1 = F(n0); out = n0 + dt k1.
 // Stage 2: n0 += dt/2 (k1 + F(n_s)) in place (n_s: the predicted densities).
-__global__ __launch_bounds__(128) void k_fl_stage(FluidArgs A, int stage) {
+__global__ __launch_bounds__(kRowThreads) void k_fl_stage(FluidArgs A, int stage) {
 #pragma clang fp contract(off)
   const int nx = A.nx, ny = A.ny, nz = A.nz;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+  const RowPos P = row_pos(nx, ny);
+  const int i = P.x0 + (int)threadIdx.x, j = P.j, k = P.k;
   if (i >= nx) return;
   const double* __restrict__ n = stage == 1 ? A.ne : A.se;
   const size_t c = ((size_t)k * ny + j) * nx + i;
@@ -177,8 +180,7 @@ static unsigned fl_blocks(size_t n) {
 }
 
 hipError_t launch_fluid_stage(const FluidArgs& A, int stage, hipStream_t s) {
-  hipLaunchKernelGGL(k_fl_stage, dim3((unsigned)((A.nx + 127) / 128), (unsigned)A.ny, (unsigned)A.nz), dim3(128), 0,
-                     s, A, stage);
+  hipLaunchKernelGGL(k_fl_stage, row_grid(A.nx, A.ny, A.nz), dim3(kRowThreads), 0, s, A, stage);
   return hipGetLastError();
 }
 

@@ -135,63 +135,6 @@ struct WeightWork {
   void* temp;
   size_t temp_bytes;
 };
-// Self-consistent field: multigrid levels and the time-step selection state.
-constexpr int kMgMaxLevels = 16;
-constexpr int kMgCoarseMax = 4096;  // cells of the coarsest level (solved in LDS)
-struct MgDims {
-  int nx, ny, nz;
-};
-struct MgWork {
-  int levels;
-  MgDims dims[kMgMaxLevels];
-  float* u[kMgMaxLevels];  // correction cycle: u[0] the correction of the potential
-  float* f[kMgMaxLevels];  // f[0]: the defect of the potential
-  double* rhs;             // right-hand side of the potential
-  double* phi;             // the potential
-  double dx;               // finest spacing
-};
-struct SelState {
-  uint32_t prefix;
-  uint32_t pad;
-  uint64_t rank;  // wanted rank (1-based) within the prefix
-};
-int mg_levels(int nx, int ny, int nz, MgDims* dims);
-hipError_t launch_sc_rhs(const int64_t* np, const int64_t* ne, const int64_t* nn, size_t n, double scale, double* f,
-                         unsigned long long* fmax, hipStream_t s);
-hipError_t mg_vcycle(const MgWork& W, int l, hipStream_t s);
-hipError_t launch_defect(const MgWork& W, unsigned long long* rmax, hipStream_t s);
-hipError_t launch_correct(const MgWork& W, hipStream_t s);
-hipError_t launch_sc_field(const float4* Ea, const double* phi, int nx, int ny, int nz, double dx, float4* E,
-                           hipStream_t s);
-hipError_t launch_speed_select(const float* vx, const float* vy, const float* vz, const int64_t* n_dev, uint64_t n,
-                               SelState* st, unsigned* hist, hipStream_t s);
-hipError_t launch_densest(const int64_t* ne, size_t n, long long* mx, unsigned long long* first, hipStream_t s);
-hipError_t launch_weight_sum(const float* w, const int64_t* n_dev, uint64_t n, double* out, hipStream_t s);
-
-// Fluid step: local-field tables on the device and the stage arguments.
-constexpr double kFlQe = 1.602176634e-19;
-constexpr double kFlEps0 = 8.8541878128e-12;
-struct FluidTab {
-  int n;
-  double ln_lo, ln_span;  // ln of the first E/N node (Td), ln(last / first)
-  const double *muN, *DN, *aN, *eN;
-  double gas_N;
-};
-struct FluidArgs {
-  int nx, ny, nz;
-  double dx, dt;
-  const float4* E;
-  double *ne, *np, *nn;     // densities (m^-3), updated in place by stage 2
-  double *se, *sp, *sn;     // predicted densities
-  double *k1e, *k1p, *k1n;  // first-stage derivatives
-  FluidTab T;
-};
-hipError_t launch_fluid_stage(const FluidArgs& A, int stage, hipStream_t s);
-hipError_t launch_fluid_rhs(const double* np, const double* ne, const double* nn, size_t n, double* f,
-                            unsigned long long* fmax_bits, hipStream_t s);
-hipError_t launch_fluid_dt(const double* ne, const float4* E, size_t n, const FluidTab& T, double dx,
-                           unsigned long long* out, hipStream_t s);
-
 hipError_t weight_temp_bytes(uint64_t n, size_t* bytes);
 hipError_t launch_weight_update(const Soa& cur, const Soa& out, uint64_t n, const WeightGeom& g, const int64_t* rho,
                                 Key key, uint32_t update_index, const WeightWork& W, uint64_t* n_out,
