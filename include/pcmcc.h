@@ -108,6 +108,9 @@ typedef struct pcmcc_stats {
   double weight_ms;              /* device time of those updates */
   double field_ms;               /* self-consistent steps: device time of densities, potential and field */
   int64_t mg_cycles;             /* self-consistent steps: multigrid V-cycles */
+  int64_t photons;               /* photoionization: photons emitted */
+  int64_t photoelectrons;        /* photoionization: photons absorbed inside the grid */
+  double photo_ms;               /* photoionization: device time */
 } pcmcc_stats;
 
 /* Version string, static storage. */
@@ -384,6 +387,49 @@ int pcmcc_field_from_potential(pcmcc_ctx* ctx, const pcmcc_grid* applied, const 
 int pcmcc_speed_quantile(pcmcc_ctx* ctx, const float* vx, const float* vy, const float* vz, const int64_t* n_dev,
                          double* v90_out);
 
+/* ---- Discrete photoionization (Sec. 2.4) -----------------------------------
+ * Zheleznyak's model of photoionization in air with discrete photons.
+ * Ionizing photons are produced in proportion to the electron-impact
+ * ionizations, eta = p_q / (p + p_q) xi photons per ionization (eq. of the UV
+ * source term; the paper: p_q = 40 mbar, xi = 0.075).  They fly in isotropic
+ * directions without scattering and are absorbed at a distance r drawn from
+ * the absorption function f(r) = (exp(-k1 r) - exp(-k2 r)) / (r ln(k2 / k1)).
+ * Each absorbed photon leaves a photoelectron at rest and a positive ion at
+ * the absorption point.  The paper does not give k1 and k2 (the oxygen
+ * partial pressure times Zheleznyak's chi_min and chi_max): they are inputs.
+ *
+ * Per ionization event of weight w: lambda = eta w / w_photon photons of
+ * weight w_photon (w_photon <= 0: of the event's weight, lambda = eta), and
+ * the count is floor(lambda) + [U < lambda - floor(lambda)].  Draws are
+ * Philox4x32-10 with key (seed low word ^ 0x50484F54, seed high word ^ step
+ * low word) and counter (bit patterns of the event's x, y, z; c), output
+ * words r0..r3: c = 0 gives the count's U = (r0 + 1/2) 2^-32; c = 2j + 1
+ * photon j's direction (cos theta = 1 - 2 u(r0), azimuth 2 pi u(r1),
+ * u(r) = (r + 1/2) 2^-32) and distance (U = ((r2 >> 5) 2^26 + (r3 >> 6) +
+ * 1/2) 2^-53, r solving F(r) = U by 64 bisections on ln r over
+ * [ln(1e-6 / k2), ln(60 / k1)], F(r) = 1 - (E1(k1 r) - E1(k2 r)) / ln(k2 / k1)
+ * the distribution function of f); c = 2j + 2 its id (r0 | r1 << 32).  The
+ * absorption point x + r n is rounded to single precision; a photon absorbed
+ * outside [x0, x0 + nx dx) x [y0, ..) x [z0, ..) is lost. */
+typedef struct pcmcc_photo_opts {
+  double eta;      /* photons per ionization, p_q / (p + p_q) xi */
+  double k1, k2;   /* absorption coefficients (1/m), 0 < k1 < k2 */
+  double w_photon; /* weight of a photoelectron; <= 0: the ionizing event's weight */
+} pcmcc_photo_opts;
+
+/* Photoionization from n_ev ionization events at device float arrays ev_x,
+ * ev_y, ev_z (positions, m) and ev_w (weights).  The photoelectrons are
+ * appended to p (after its *n_dev particles, velocity 0, ids from the draws;
+ * order unspecified) and, if n_pos is not null, their charge is added to the
+ * device int64 grid n_pos as by pcmcc_deposit (PCMCC_ERANGE as there).  If
+ * the emitted photons could exceed p->capacity, PCMCC_ECAPACITY and nothing
+ * changes.  photons_out / absorbed_out (host, nullable): photons emitted and
+ * photoelectrons appended.  Synchronises the stream. */
+int pcmcc_photoionize(pcmcc_ctx* ctx, const pcmcc_grid* grid, const float* ev_x, const float* ev_y,
+                      const float* ev_z, const float* ev_w, int64_t n_ev, const pcmcc_photo_opts* opts,
+                      uint64_t seed, uint64_t step, const pcmcc_particles* p, int64_t* n_pos, int64_t* photons_out,
+                      int64_t* absorbed_out);
+
 typedef struct pcmcc_sc_opts {
   int adaptive;          /* 0: every step takes *dt_inout; 1: the Sec. 2.1.4 rule below */
   double dt_max;         /* upper bound of the adaptive step (s) */
@@ -394,6 +440,7 @@ typedef struct pcmcc_sc_opts {
   const double* mu_N;    /* host [mu_n] */
   double mg_tol;         /* multigrid relative residual */
   int mg_max_cycles;
+  const pcmcc_photo_opts* photo; /* nullable: photoionization from each step's ionizations (host struct) */
 } pcmcc_sc_opts;
 
 /* n_steps self-consistent steps.  Before each step the field is computed from
@@ -415,8 +462,12 @@ typedef struct pcmcc_sc_opts {
  * (PCMCC_ECAPACITY, PCMCC_ERANGE from a weight update) the particles and ion
  * grids hold the state after stats->steps_done steps; on PCMCC_ERANGE from the
  * deposit of a step's ions the particles hold the state after steps_done
- * steps and the ion grids lack (part of) that last step's ions.  Synchronises
- * the stream. */
+ * steps and the ion grids lack (part of) that last step's ions.  With
+ * opts->photo, after each step's ion deposit the step's ionizations emit
+ * photons as pcmcc_photoionize (seed, step index step0 + s): photoelectrons
+ * join p, their ions n_pos, before the next field; on PCMCC_ECAPACITY from it
+ * the particles and ion grids hold that step without its photoelectrons.
+ * stats: photons, photoelectrons, photo_ms.  Synchronises the stream. */
 int pcmcc_streamer_steps(pcmcc_ctx* ctx, const pcmcc_particles* p, const pcmcc_grid* applied, int64_t* n_pos,
                          int64_t* n_neg, double* phi, float* E_out, const pcmcc_sc_opts* opts, int n_steps,
                          uint64_t seed, uint64_t step0, double* dt_inout, double* dt_hist, pcmcc_stats* stats);

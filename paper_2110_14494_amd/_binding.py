@@ -39,7 +39,8 @@ class pcmcc_stats(C.Structure):
                 ("errors", C.c_uint64), ("step_kernel_ms", C.c_double), ("deposit_kernel_ms", C.c_double),
                 ("launch_block", C.c_int32), ("launch_grid", C.c_int32), ("weight_updates", C.c_int64),
                 ("merged_pairs", C.c_int64), ("splits", C.c_int64), ("weight_ms", C.c_double),
-                ("field_ms", C.c_double), ("mg_cycles", C.c_int64)]
+                ("field_ms", C.c_double), ("mg_cycles", C.c_int64), ("photons", C.c_int64),
+                ("photoelectrons", C.c_int64), ("photo_ms", C.c_double)]
 
     def as_dict(self) -> dict:
         r = list(self.real_collisions)
@@ -50,7 +51,8 @@ class pcmcc_stats(C.Structure):
                 "step_kernel_ms": self.step_kernel_ms, "deposit_kernel_ms": self.deposit_kernel_ms,
                 "launch_block": self.launch_block, "launch_grid": self.launch_grid,
                 "weight_updates": self.weight_updates, "merged_pairs": self.merged_pairs, "splits": self.splits,
-                "weight_ms": self.weight_ms, "field_ms": self.field_ms, "mg_cycles": self.mg_cycles}
+                "weight_ms": self.weight_ms, "field_ms": self.field_ms, "mg_cycles": self.mg_cycles,
+                "photons": self.photons, "photoelectrons": self.photoelectrons, "photo_ms": self.photo_ms}
 
 
 SWARM_QUANTITIES = ("W_flux", "W_bulk", "DL_flux", "DL_bulk", "DT_flux", "DT_bulk", "nu_ion", "nu_att",
@@ -59,10 +61,14 @@ SWARM_NQ = len(SWARM_QUANTITIES)
 SWARM_NMOM = 14
 
 
+class pcmcc_photo_opts(C.Structure):
+    _fields_ = [("eta", C.c_double), ("k1", C.c_double), ("k2", C.c_double), ("w_photon", C.c_double)]
+
+
 class pcmcc_sc_opts(C.Structure):
     _fields_ = [("adaptive", C.c_int), ("dt_max", C.c_double), ("cfl", C.c_double), ("growth_max", C.c_double),
                 ("mu_n", C.c_int), ("mu_EN_lo", C.c_double), ("mu_EN_hi", C.c_double), ("mu_N", C.c_void_p),
-                ("mg_tol", C.c_double), ("mg_max_cycles", C.c_int)]
+                ("mg_tol", C.c_double), ("mg_max_cycles", C.c_int), ("photo", C.POINTER(pcmcc_photo_opts))]
 
 
 class pcmcc_fluid_table(C.Structure):
@@ -145,6 +151,9 @@ def lib() -> C.CDLL:
             "pcmcc_streamer_steps": ([vp, C.POINTER(pcmcc_particles), C.POINTER(pcmcc_grid), vp, vp, vp, vp,
                                       C.POINTER(pcmcc_sc_opts), C.c_int, u64, u64, C.POINTER(C.c_double), vp,
                                       C.POINTER(pcmcc_stats)], C.c_int),
+            "pcmcc_photoionize": ([vp, C.POINTER(pcmcc_grid), vp, vp, vp, vp, i64, C.POINTER(pcmcc_photo_opts), u64,
+                                   u64, C.POINTER(pcmcc_particles), vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
+                                  C.c_int),
             "pcmcc_fluid_steps": ([vp, C.POINTER(pcmcc_grid), vp, vp, vp, vp, C.POINTER(pcmcc_fluid_table), C.c_double,
                                    C.c_double, C.c_int, C.c_int, vp, vp, C.POINTER(pcmcc_stats)], C.c_int),
             "pcmcc_swarm_batch": ([vp, C.c_int, vp, vp, C.c_double, C.c_int, u64, C.POINTER(pcmcc_swarm_opts),

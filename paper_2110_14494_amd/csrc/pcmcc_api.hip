@@ -21,6 +21,7 @@
 #include "pcmcc.h"
 #include "pcmcc_field.hpp"
 #include "pcmcc_internal.hpp"
+#include "pcmcc_photo.hpp"
 
 using namespace pcmcc;
 
@@ -97,7 +98,7 @@ struct pcmcc_ctx {
   size_t sc_cells = 0;
   float* ev_store = nullptr;  // 8 lists of ev_cap floats
   uint64_t ev_cap = 0;
-  unsigned long long* sc_red = nullptr;  // [0] max |f| bits [1] max |r| bits [2] ne max [3] first cell [4] sum w [5..6] events
+  unsigned long long* sc_red = nullptr;  // [0] max |f| bits [1] max |r| bits [2] ne max [3] first cell [4] sum w [5..6] events [7] photons
   unsigned long long* sc_host = nullptr;  // pinned copy
   SelState* sel = nullptr;
   unsigned* sel_hist = nullptr;
@@ -1644,6 +1645,88 @@ double mobility(const pcmcc_sc_opts* o, double EN_Td, double gas_N) {
   return ((1.0 - f) * o->mu_N[i] + f * o->mu_N[i + 1]) / gas_N;
 }
 
+// Photoionization from n_ev events (device arrays): counts the photons,
+// checks the capacity, appends the photoelectrons at p's count and deposits
+// their charge into n_pos (nullable).
+int photoionize(pcmcc_ctx* c, const pcmcc_grid* g, const float* ex, const float* ey, const float* ez, const float* ew,
+                uint64_t n_ev, const pcmcc_photo_opts* o, uint64_t seed, uint64_t step, const pcmcc_particles* p,
+                int64_t* n_pos, int64_t* photons, int64_t* absorbed, double* ms) {
+  *photons = 0;
+  *absorbed = 0;
+  *ms = 0;
+  if (n_ev == 0) return PCMCC_OK;
+  int rc = ensure_red(c);
+  if (rc) return rc;
+  PhotoArgs A{};
+  A.ex = ex;
+  A.ey = ey;
+  A.ez = ez;
+  A.ew = ew;
+  A.n = n_ev;
+  A.eta = o->eta;
+  A.w_ph = o->w_photon;
+  A.k1 = o->k1;
+  A.k2 = o->k2;
+  A.ln_k = std::log(o->k2 / o->k1);
+  A.s_lo = std::log(1e-6 / o->k2);
+  A.s_hi = std::log(60.0 / o->k1);
+  A.key = Key{(uint32_t)seed ^ 0x50484F54u, (uint32_t)(seed >> 32) ^ (uint32_t)step};
+  A.lo[0] = g->x0;
+  A.lo[1] = g->y0;
+  A.lo[2] = g->z0;
+  A.hi[0] = g->x0 + g->nx * g->dx;
+  A.hi[1] = g->y0 + g->ny * g->dx;
+  A.hi[2] = g->z0 + g->nz * g->dx;
+  A.x = p->x;
+  A.y = p->y;
+  A.z = p->z;
+  A.vx = p->vx;
+  A.vy = p->vy;
+  A.vz = p->vz;
+  A.w = p->w;
+  A.id = p->id;
+  A.n_dev = (unsigned long long*)p->n_dev;
+  HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->sc_red + 7, 0, sizeof(unsigned long long), c->stream));
+  HIP_TRY(c, launch_photo_count(A, c->sc_red + 7, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->sc_host + 7, c->sc_red + 7, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                            c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->host_n, p->n_dev, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const uint64_t total = c->sc_host[7];
+  const int64_t n_cur = *c->host_n;
+  if (n_cur < 0 || n_cur > p->capacity) return fail(c, PCMCC_EINVAL, "particle count outside [0, capacity]");
+  if (total > (uint64_t)(p->capacity - n_cur))
+    return fail(c, PCMCC_ECAPACITY, "photoionization: %llu photons for %lld free slots", (unsigned long long)total,
+                (long long)(p->capacity - n_cur));
+  *photons = (int64_t)total;
+  if (total == 0) return PCMCC_OK;
+  HIP_TRY(c, launch_photo_emit(A, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->host_n, p->n_dev, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const int64_t n_new = *c->host_n;
+  *absorbed = n_new - n_cur;
+  if (n_pos && *absorbed > 0) {
+    c->sc_host[7] = (unsigned long long)*absorbed;
+    HIP_TRY(c, hipMemcpyAsync(c->sc_red + 7, c->sc_host + 7, sizeof(unsigned long long), hipMemcpyHostToDevice,
+                              c->stream));
+    rc = run_deposit(c, p->x + n_cur, p->y + n_cur, p->z + n_cur, p->w + n_cur, (const int64_t*)(c->sc_red + 7),
+                     (uint64_t)*absorbed, g, n_pos);
+    if (rc) return rc;
+  }
+  HIP_TRY(c, hipEventRecord(c->ev[3], c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  float t = 0;
+  HIP_TRY(c, hipEventElapsedTime(&t, c->ev[2], c->ev[3]));
+  *ms = t;
+  return PCMCC_OK;
+}
+
+bool valid_photo(const pcmcc_photo_opts* o) {
+  return o && std::isfinite(o->eta) && o->eta >= 0 && std::isfinite(o->k1) && std::isfinite(o->k2) && o->k1 > 0 &&
+         o->k2 > o->k1 && std::isfinite(o->w_photon);
+}
+
 }  // namespace
 
 int pcmcc_solve_potential(pcmcc_ctx* c, const pcmcc_grid* grid, const int64_t* n_pos, const int64_t* n_e,
@@ -1662,6 +1745,26 @@ int pcmcc_solve_potential(pcmcc_ctx* c, const pcmcc_grid* grid, const int64_t* n
   if (cycles_out) *cycles_out = cyc;
   if (rel_residual_out) *rel_residual_out = rel;
   return PCMCC_OK;
+}
+
+int pcmcc_photoionize(pcmcc_ctx* c, const pcmcc_grid* grid, const float* ev_x, const float* ev_y, const float* ev_z,
+                      const float* ev_w, int64_t n_ev, const pcmcc_photo_opts* opts, uint64_t seed, uint64_t step,
+                      const pcmcc_particles* p, int64_t* n_pos, int64_t* photons_out, int64_t* absorbed_out) {
+  if (!c) return fail(nullptr, PCMCC_EINVAL, "null context");
+  if (!valid_grid(grid) || n_ev < 0 || (n_ev > 0 && (!ev_x || !ev_y || !ev_z || !ev_w)))
+    return fail(c, PCMCC_EINVAL, "invalid grid or events");
+  if (!valid_photo(opts)) return fail(c, PCMCC_EINVAL, "invalid photoionization options (eta >= 0, 0 < k1 < k2)");
+  if (!p || !p->x || !p->y || !p->z || !p->vx || !p->vy || !p->vz || !p->w || !p->id || !p->n_dev ||
+      p->capacity < 0)
+    return fail(c, PCMCC_EINVAL, "invalid particle set");
+  HIP_TRY(c, hipSetDevice(c->device));
+  int64_t ph = 0, ab = 0;
+  double ms = 0;
+  const int rc = photoionize(c, grid, ev_x, ev_y, ev_z, ev_w, (uint64_t)n_ev, opts, seed, step, p, n_pos, &ph, &ab,
+                             &ms);
+  if (photons_out) *photons_out = ph;
+  if (absorbed_out) *absorbed_out = ab;
+  return rc;
 }
 
 int pcmcc_field_from_potential(pcmcc_ctx* c, const pcmcc_grid* applied, const double* phi, float* E_out) {
@@ -1710,6 +1813,8 @@ int pcmcc_streamer_steps(pcmcc_ctx* c, const pcmcc_particles* p, const pcmcc_gri
                       (o->mu_n > 1 && !(o->mu_EN_hi > o->mu_EN_lo && o->mu_EN_lo > 0))))
     return fail(c, PCMCC_EINVAL, "invalid time-step options");
   if (!(o->mg_tol > 0) || o->mg_max_cycles < 1) return fail(c, PCMCC_EINVAL, "invalid multigrid options");
+  if (o->photo && !valid_photo(o->photo))
+    return fail(c, PCMCC_EINVAL, "invalid photoionization options (eta >= 0, 0 < k1 < k2)");
   HIP_TRY(c, hipSetDevice(c->device));
   rc = ensure_sc(c, applied);
   if (rc) return rc;
@@ -1817,6 +1922,16 @@ int pcmcc_streamer_steps(pcmcc_ctx* c, const pcmcc_particles* p, const pcmcc_gri
     float ms = 0;
     HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[2], c->ev[3]));
     dep_ms += ms;
+    if (o->photo && n_ion) {
+      int64_t ph = 0, ab = 0;
+      double pms = 0;
+      rc = photoionize(c, applied, ev.ix, ev.iy, ev.iz, ev.iw, n_ion, o->photo, seed, step0 + (uint64_t)s, p, n_pos,
+                       &ph, &ab, &pms);
+      tot.photons += ph;
+      tot.photoelectrons += ab;
+      tot.photo_ms += pms;
+      if (rc) break;
+    }
     rc = refresh();
     if (rc) break;
     if (dt_hist) dt_hist[s] = dt;

@@ -80,6 +80,11 @@ class DeviceGrid:
         return torch.zeros((self.nz, self.ny, self.nx), dtype=torch.int64, device=self.E.device)
 
 
+def _photo_opts(photo: dict):
+    return B.pcmcc_photo_opts(float(photo["eta"]), float(photo["k1"]), float(photo["k2"]),
+                              float(photo.get("w_photon", 0.0)))
+
+
 class Context:
     """One library context on a device, issuing work on a torch stream."""
 
@@ -197,15 +202,18 @@ class Context:
                        phi: torch.Tensor, dt: float, n_steps: int, seed: int, step0: int = 0, adaptive: bool = True,
                        dt_max: float | None = None, mu: dict | None = None, cfl: float = 0.5,
                        growth_max: float = 1.2, mg_tol: float = 1e-8, mg_max_cycles: int = 30,
-                       E_out: torch.Tensor | None = None, check: bool = True):
+                       E_out: torch.Tensor | None = None, check: bool = True, photo: dict | None = None):
         """Self-consistent steps (field from the densities before every step,
-        ions from the step's events, Sec. 2.1.4 time step).  Returns (rc,
-        next dt, dt per step, stats)."""
+        ions from the step's events, Sec. 2.1.4 time step; photo: eta, k1, k2,
+        w_photon of the photoionization after each step, Sec. 2.4).  Returns
+        (rc, next dt, dt per step, stats)."""
         mu = mu or {"EN_lo": 1.0, "EN_hi": 10.0, "muN": np.array([0.0])}
         muN = np.ascontiguousarray(mu["muN"], dtype=np.float64)
+        po = _photo_opts(photo) if photo is not None else None
         o = B.pcmcc_sc_opts(1 if adaptive else 0, float(dt_max if dt_max is not None else dt), float(cfl),
                             float(growth_max), int(muN.size), float(mu.get("EN_lo", 1.0)), float(mu.get("EN_hi", 10.0)),
-                            muN.ctypes.data_as(C.c_void_p), float(mg_tol), int(mg_max_cycles))
+                            muN.ctypes.data_as(C.c_void_p), float(mg_tol), int(mg_max_cycles),
+                            C.pointer(po) if po is not None else None)
         d = C.c_double(dt)
         hist = np.zeros(max(n_steps, 1), dtype=np.float64)
         st = B.pcmcc_stats()
@@ -218,6 +226,25 @@ class Context:
             B.check(rc, self.h)
         sd = st.as_dict()
         return rc, d.value, hist[:sd["steps_done"]], sd
+
+    def photoionize(self, grid: DeviceGrid, ev: dict, photo: dict, seed: int, step: int, parts: Particles,
+                    n_pos: torch.Tensor | None = None):
+        """Photoelectrons of the ionization events ev (float32 device tensors
+        x, y, z, w) appended to parts, their charge to n_pos (Sec. 2.4).
+        Returns (photons emitted, photoelectrons appended)."""
+        for k in ("x", "y", "z", "w"):
+            assert ev[k].dtype == torch.float32 and ev[k].is_contiguous() and ev[k].numel() == ev["x"].numel()
+        if n_pos is not None:
+            assert n_pos.dtype == torch.int64 and n_pos.is_contiguous() and n_pos.numel() == grid.nx * grid.ny * grid.nz
+        po = _photo_opts(photo)
+        ph, ab = C.c_int64(0), C.c_int64(0)
+        gs, ps = grid.struct(), parts.struct()
+        B.check(B.lib().pcmcc_photoionize(self.h, C.byref(gs), ev["x"].data_ptr(), ev["y"].data_ptr(),
+                                          ev["z"].data_ptr(), ev["w"].data_ptr(), int(ev["x"].numel()), C.byref(po),
+                                          int(seed), int(step), C.byref(ps),
+                                          C.c_void_p(n_pos.data_ptr() if n_pos is not None else 0), C.byref(ph),
+                                          C.byref(ab)), self.h)
+        return ph.value, ab.value
 
     def fluid_steps(self, grid: DeviceGrid, n_e: torch.Tensor, n_pos: torch.Tensor, n_neg: torch.Tensor,
                     phi: torch.Tensor, table: dict, dt_max: float, n_steps: int, mg_tol: float = 1e-8,
