@@ -81,6 +81,11 @@ def parse():
                     help="capacity / start count of the weight-controlled and self-consistent runs")
     ap.add_argument("--no-sc", action="store_true", help="skip the self-consistent streamer run")
     ap.add_argument("--sc-steps", type=int, default=40, help="steps of the self-consistent streamer run")
+    ap.add_argument("--no-photo", action="store_true", help="self-consistent run without photoionization")
+    ap.add_argument("--photo-xi", type=float, default=0.075, help="photoionization factor xi")
+    ap.add_argument("--photo-k1", type=float, default=5.25e3,
+                    help="absorption coefficient chi_min p_O2 (1/m; the paper gives none: air at 1 bar)")
+    ap.add_argument("--photo-k2", type=float, default=3.0e5, help="absorption coefficient chi_max p_O2 (1/m)")
     ap.add_argument("--no-fluid", action="store_true", help="skip the fluid run")
     ap.add_argument("--fluid-steps", type=int, default=100, help="Heun steps of the fluid run")
     ap.add_argument("--coef-scale", type=float, default=1.0, help="scale of the swarm sizes")
@@ -278,7 +283,10 @@ def sc_leg(a, ctx, pic, mu_table):
     step, ions from the step's ionizations and attachments, super-particle
     weight control, and the Sec. 2.1.4 time step (CFL on the 90 % speed
     quantile, dielectric relaxation with the swarm mobility, 20 % growth, at
-    most 4 ps).  One untimed run of a few steps, then the timed run."""
+    most 4 ps), and discrete photoionization from each step's ionizations
+    (Sec. 2.4: eta = p_q / (p + p_q) xi with p_q = 40 mbar at 1 bar, photons
+    of the ionizing electron's weight).  One untimed run of a few steps, then
+    the timed run."""
     import torch
     from paper_2110_14494_amd import workloads as W
     cfg = W.streamer_config(n=a.n or 2 ** 24)
@@ -293,6 +301,9 @@ def sc_leg(a, ctx, pic, mu_table):
     n_neg = torch.zeros_like(n_pos)
     phi = torch.zeros(shape, dtype=torch.float64, device="cuda")
     E = torch.empty(shape + (4,), dtype=torch.float32, device="cuda")
+    photo = None
+    if not a.no_photo:
+        photo = {"eta": 40.0 / (1000.0 + 40.0) * a.photo_xi, "k1": a.photo_k1, "k2": a.photo_k2, "w_photon": 0.0}
     res = None
     for run, steps in ((0, 3), (1, a.sc_steps)):
         for k, t in pristine.t.items():
@@ -307,7 +318,7 @@ def sc_leg(a, ctx, pic, mu_table):
         t0 = time.perf_counter()
         rc, dt_next, hist, st = ctx.streamer_steps(work, grid, n_pos, n_neg, phi, cfg["dt"], steps, cfg["seed"],
                                                    dt_max=4e-12, mu=mu_table, mg_tol=1e-6, mg_max_cycles=30,
-                                                   E_out=E, check=False)
+                                                   E_out=E, check=False, photo=photo)
         torch.cuda.synchronize()
         res = (rc, hist, st, time.perf_counter() - t0)
     ctx.set_weight_control(0.0)
@@ -316,7 +327,8 @@ def sc_leg(a, ctx, pic, mu_table):
     w_fin = float(work.t["w"][:n_fin].double().sum())
     e_mag = torch.linalg.vector_norm(E[..., :3], dim=-1)
     log(f"self-consistent: rc={rc} steps {st['steps_done']} t={hist.sum():.3g} s n {n0} -> {n_fin}, {el:.2f} s, "
-        f"mg cycles {st['mg_cycles']}")
+        f"mg cycles {st['mg_cycles']}, photons {st['photons']} ({st['photoelectrons']} absorbed) "
+        f"in {st['photo_ms']:.1f} ms")
     return {"workload": cfg["name"], "steps_asked": a.sc_steps, "status": rc, "steps_done": int(st["steps_done"]),
             "t_simulated_s": float(hist.sum()), "dt_min_s": float(hist.min()) if hist.size else None,
             "dt_max_s": float(hist.max()) if hist.size else None, "particle_steps": int(st["particle_steps"]),
@@ -324,7 +336,11 @@ def sc_leg(a, ctx, pic, mu_table):
             "weight_ms": st["weight_ms"], "ion_deposit_ms": st["deposit_kernel_ms"], "field_ms": st["field_ms"],
             "mg_cycles": int(st["mg_cycles"]), "weight_updates": int(st["weight_updates"]), "n_start": int(n0),
             "n_final": n_fin, "electrons_final": w_fin, "E_max_final_V_per_m": float(e_mag.max()),
-            "mobility": "swarm table (coefficient leg)" if mu_table.get("from_swarms") else "constant mu N = 3e24"}
+            "mobility": "swarm table (coefficient leg)" if mu_table.get("from_swarms") else "constant mu N = 3e24",
+            "ionizations": int(st["ionization"]), "photons": int(st["photons"]),
+            "photoelectrons": int(st["photoelectrons"]), "photo_ms": st["photo_ms"],
+            "photoionization": None if photo is None else dict(photo, xi=a.photo_xi, p_q_mbar=40.0, p_mbar=1000.0,
+                                                               w_photon="ionizing electron's weight")}
 
 
 FLUID_BYTES_PER_CELL_STAGE = 92.0  # both Heun stages: densities, field, derivatives (mean of 88 and 96 B)
