@@ -406,7 +406,7 @@ int pcmcc_speed_quantile(pcmcc_ctx* ctx, const float* vx, const float* vy, const
  * words r0..r3: c = 0 gives the count's U = (r0 + 1/2) 2^-32; c = 2j + 1
  * photon j's direction (cos theta = 1 - 2 u(r0), azimuth 2 pi u(r1),
  * u(r) = (r + 1/2) 2^-32) and distance (U = ((r2 >> 5) 2^26 + (r3 >> 6) +
- * 1/2) 2^-53, r solving F(r) = U by 64 bisections on ln r over
+ * 1/2) 2^-53, r solving F(r) = U to about 1e-14 in ln r within
  * [ln(1e-6 / k2), ln(60 / k1)], F(r) = 1 - (E1(k1 r) - E1(k2 r)) / ln(k2 / k1)
  * the distribution function of f); c = 2j + 2 its id (r0 | r1 << 32).  The
  * absorption point x + r n is rounded to single precision; a photon absorbed

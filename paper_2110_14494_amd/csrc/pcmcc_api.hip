@@ -92,6 +92,11 @@ struct pcmcc_ctx {
   size_t mg_rhs_n = 0;
   double* mg_part = nullptr;  // per-block maxima of the defect pass
   size_t mg_part_n = 0;
+  uint32_t* ph_cnt = nullptr;  // photoionization: photon counts per event
+  uint64_t* ph_off = nullptr;  // and their exclusive scan
+  uint64_t ph_n = 0;
+  void* ph_temp = nullptr;
+  size_t ph_temp_bytes = 0;
   MgDims mg_dims0{0, 0, 0};
   float4* sc_E = nullptr;
   int64_t* sc_ne = nullptr;
@@ -606,6 +611,9 @@ int pcmcc_destroy(pcmcc_ctx* c) {
   dfree(c->mg_store);
   dfree(c->mg_rhs);
   dfree(c->mg_part);
+  dfree(c->ph_cnt);
+  dfree(c->ph_off);
+  if (c->ph_temp) (void)hipFree(c->ph_temp);
   dfree(c->sc_E);
   dfree(c->sc_ne);
   dfree(c->ev_store);
@@ -1686,14 +1694,34 @@ int photoionize(pcmcc_ctx* c, const pcmcc_grid* g, const float* ex, const float*
   A.w = p->w;
   A.id = p->id;
   A.n_dev = (unsigned long long*)p->n_dev;
+  if (c->ph_n < n_ev) {
+    dfree(c->ph_cnt);
+    dfree(c->ph_off);
+    c->ph_cnt = nullptr;
+    c->ph_off = nullptr;
+    c->ph_n = 0;
+    HIP_TRY(c, dalloc(&c->ph_cnt, n_ev));
+    HIP_TRY(c, dalloc(&c->ph_off, n_ev));
+    c->ph_n = n_ev;
+  }
+  size_t tb = 0;
+  HIP_TRY(c, photo_scan_bytes(n_ev, &tb));
+  if (c->ph_temp_bytes < tb) {
+    if (c->ph_temp) (void)hipFree(c->ph_temp);
+    c->ph_temp = nullptr;
+    c->ph_temp_bytes = 0;
+    HIP_TRY(c, hipMalloc(&c->ph_temp, std::max<size_t>(tb, 16)));
+    c->ph_temp_bytes = std::max<size_t>(tb, 16);
+  }
   HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
-  HIP_TRY(c, hipMemsetAsync(c->sc_red + 7, 0, sizeof(unsigned long long), c->stream));
-  HIP_TRY(c, launch_photo_count(A, c->sc_red + 7, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(c->sc_host + 7, c->sc_red + 7, sizeof(unsigned long long), hipMemcpyDeviceToHost,
-                            c->stream));
+  HIP_TRY(c, launch_photo_count(A, c->ph_cnt, c->ph_temp, c->ph_temp_bytes, c->ph_off, c->stream));
+  uint64_t last[2] = {0, 0};  // offs and count of the last event
+  uint32_t last_cnt = 0;
+  HIP_TRY(c, hipMemcpyAsync(&last[0], c->ph_off + (n_ev - 1), sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(&last_cnt, c->ph_cnt + (n_ev - 1), sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipMemcpyAsync(c->host_n, p->n_dev, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  const uint64_t total = c->sc_host[7];
+  const uint64_t total = last[0] + last_cnt;
   const int64_t n_cur = *c->host_n;
   if (n_cur < 0 || n_cur > p->capacity) return fail(c, PCMCC_EINVAL, "particle count outside [0, capacity]");
   if (total > (uint64_t)(p->capacity - n_cur))
@@ -1701,6 +1729,8 @@ int photoionize(pcmcc_ctx* c, const pcmcc_grid* g, const float* ex, const float*
                 (long long)(p->capacity - n_cur));
   *photons = (int64_t)total;
   if (total == 0) return PCMCC_OK;
+  A.offs = c->ph_off;
+  A.total = total;
   HIP_TRY(c, launch_photo_emit(A, c->stream));
   HIP_TRY(c, hipMemcpyAsync(c->host_n, p->n_dev, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
