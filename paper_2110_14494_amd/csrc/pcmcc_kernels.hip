@@ -320,72 +320,149 @@ __global__ void k_finalize(Soa user, Soa scratch, Ctl* ctl, int64_t* n_dev) {
 // Field bounds per cell: largest |E| over the 4x4x4 centres (i-1..i+2 per
 // axis, clamped) and the norm of the per-component ranges there; plus the
 // global maximum of |E| (as ordered bits of a non-negative float).
-// Threads along x, one block row per j (blockIdx.y); blockIdx.z takes a
-// contiguous range of planes (the neighbour planes stay in cache), so the
-// largest |E| takes few atomics.
-__global__ __launch_bounds__(128) void k_field_bounds(const float4* __restrict__ E, int nx, int ny, int nz,
-                                                      float2* __restrict__ out, unsigned* __restrict__ emax_bits) {
-  float local_max = 0.0f;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
-  const int per = (nz + (int)gridDim.z - 1) / (int)gridDim.z;
-  const int k0 = (int)blockIdx.z * per, k1 = min(nz, k0 + per);
-  for (int k = k0; i < nx && k < k1; ++k) {
-    const size_t c = ((size_t)k * ny + j) * nx + i;
-    float m = 0.0f;
-    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int kk = max(k - 1, 0); kk <= min(k + 2, nz - 1); ++kk)
-      for (int jj = max(j - 1, 0); jj <= min(j + 2, ny - 1); ++jj)
-        for (int ii = max(i - 1, 0); ii <= min(i + 2, nx - 1); ++ii) {
-          const float4 e = E[((size_t)kk * ny + jj) * nx + ii];
-          m = fmaxf(m, sqrtf(e.x * e.x + e.y * e.y + e.z * e.z));
-          lo[0] = fminf(lo[0], e.x);
-          hi[0] = fmaxf(hi[0], e.x);
-          lo[1] = fminf(lo[1], e.y);
-          hi[1] = fmaxf(hi[1], e.y);
-          lo[2] = fminf(lo[2], e.z);
-          hi[2] = fmaxf(hi[2], e.z);
-        }
-    const float r0 = hi[0] - lo[0], r1 = hi[1] - lo[1], r2 = hi[2] - lo[2];
-    out[c] = make_float2(m, sqrtf(r0 * r0 + r1 * r1 + r2 * r2));
-    const float4 e = E[c];
-    local_max = fmaxf(local_max, sqrtf(e.x * e.x + e.y * e.y + e.z * e.z));
-  }
-  for (int off = 32; off > 0; off >>= 1) local_max = fmaxf(local_max, __shfl_xor(local_max, off));
-  if (lane_id() == 0 && local_max > 0.0f) atomicMax(emax_bits, __float_as_uint(local_max));
+// The box maximum and minimum are separable: a block owns kFbTX x kFbTY
+// output columns and marches through a range of planes; per input plane it
+// stages the tile with its halo (|E| computed once per cell, next plane's
+// loads in flight meanwhile), reduces 4-wide along x into LDS, then 4-wide
+// along y per output column, and keeps the last four planes' results in
+// registers for the z window.  The sums of squares are written as explicit
+// fused multiply-adds (z, then x over y), the rounding these bounds have
+// always had.
+constexpr int kFbTX = 64, kFbTY = 4, kFbThreads = kFbTX * kFbTY;
+constexpr int kFbIX = kFbTX + 3, kFbIY = kFbTY + 3, kFbIn = kFbIX * kFbIY;  // input tile: halo -1 .. +2
+constexpr int kFbLoads = (kFbIn + kFbThreads - 1) / kFbThreads;
+constexpr int kFbXR = kFbIY * kFbTX;  // x-reduced entries per plane
+
+struct Box7 {
+  float m, lo0, lo1, lo2, hi0, hi1, hi2;
+};
+__device__ __forceinline__ Box7 box_empty() { return Box7{0.0f, INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY}; }
+__device__ __forceinline__ void box_add(Box7& b, const Box7& o) {
+  b.m = fmaxf(b.m, o.m);
+  b.lo0 = fminf(b.lo0, o.lo0);
+  b.lo1 = fminf(b.lo1, o.lo1);
+  b.lo2 = fminf(b.lo2, o.lo2);
+  b.hi0 = fmaxf(b.hi0, o.hi0);
+  b.hi1 = fmaxf(b.hi1, o.hi1);
+  b.hi2 = fmaxf(b.hi2, o.hi2);
 }
 
-// Corner-packed field (layout in pcmcc_device.hpp): one thread per record,
-// the record of lower centre index (i, j, k) in [-1, n]^3 holding the fields
-// of the 8 centres around it (indices clamped to the grid) and the bound of
-// the cell clamp(i, j, k).
-// One block row of records per (j, k) in [-1, n]^2 (blockIdx.y, blockIdx.z).
-__global__ __launch_bounds__(128) void k_pack_field(const float4* __restrict__ E, const float2* __restrict__ bound,
-                                                    int nx, int ny, int nz, float4* __restrict__ P) {
-  const uint64_t px = (uint64_t)nx + 2, py = (uint64_t)ny + 2;
-  const int ri = blockIdx.x * blockDim.x + threadIdx.x;
-  if (ri < nx + 2) {
-    const uint64_t r = ((uint64_t)blockIdx.z * py + blockIdx.y) * px + (uint64_t)ri;
-    const int i = ri - 1, j = (int)blockIdx.y - 1, k = (int)blockIdx.z - 1;
-    const int ci[2] = {min(max(i, 0), nx - 1), min(max(i + 1, 0), nx - 1)};
-    const int cj[2] = {min(max(j, 0), ny - 1), min(max(j + 1, 0), ny - 1)};
-    const int ck[2] = {min(max(k, 0), nz - 1), min(max(k + 1, 0), nz - 1)};
-    float v[kRecFloats];
+__global__ __launch_bounds__(kFbThreads) void k_field_bounds(const float4* __restrict__ E, int nx, int ny, int nz,
+                                                             float2* __restrict__ out, unsigned* __restrict__ emax_bits) {
+  __shared__ float4 s_e[kFbIn];  // (Ex, Ey, Ez, |E|), |E| < 0 outside the grid
+  __shared__ float s_x[7][kFbXR];
+  __shared__ float s_w[kFbThreads / 64];
+  const int gx0 = (int)blockIdx.x * kFbTX - 1, gy0 = (int)blockIdx.y * kFbTY - 1;
+  const int per = (nz + (int)gridDim.z - 1) / (int)gridDim.z;
+  const int k0 = (int)blockIdx.z * per, k1 = min(nz, k0 + per);
+  const int tid = threadIdx.x, tx = tid % kFbTX, ty = tid / kFbTX;
+  float local_max = 0.0f;
+  if (k0 < k1) {  // block-uniform
+    float4 pre[kFbLoads];
+    auto load = [&](int kk) {
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const float4 e = E[((size_t)ck[c >> 2] * ny + cj[(c >> 1) & 1]) * nx + ci[c & 1]];
-      v[3 * c] = e.x;
-      v[3 * c + 1] = e.y;
-      v[3 * c + 2] = e.z;
+      for (int q = 0; q < kFbLoads; ++q) {
+        const int e = tid + q * kFbThreads;
+        const int gx = gx0 + e % kFbIX, gy = gy0 + e / kFbIX;
+        pre[q] = make_float4(0.0f, 0.0f, 0.0f, -1.0f);
+        if (e < kFbIn && kk >= 0 && kk < nz && gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+          const float4 v = E[((size_t)kk * ny + gy) * nx + gx];
+          pre[q] = make_float4(v.x, v.y, v.z, sqrtf(fmaf(v.z, v.z, fmaf(v.x, v.x, v.y * v.y))));
+        }
+      }
+    };
+    Box7 r0 = box_empty(), r1 = box_empty(), r2 = box_empty(), r3 = box_empty();  // planes kk-3 .. kk
+    load(k0 - 1);
+    for (int kk = k0 - 1; kk <= k1 + 1; ++kk) {
+      __syncthreads();  // the previous plane's readers are done
+#pragma unroll
+      for (int q = 0; q < kFbLoads; ++q)
+        if (tid + q * kFbThreads < kFbIn) s_e[tid + q * kFbThreads] = pre[q];
+      if (kk + 1 <= k1 + 1) load(kk + 1);
+      __syncthreads();
+      for (int e = tid; e < kFbXR; e += kFbThreads) {  // 4-wide x windows of the tile's 7 rows
+        const int row = e / kFbTX, col = e % kFbTX;
+        Box7 b = box_empty();
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+          const float4 v = s_e[row * kFbIX + col + d];
+          if (v.w >= 0.0f) box_add(b, Box7{v.w, v.x, v.y, v.z, v.x, v.y, v.z});
+        }
+        s_x[0][e] = b.m;
+        s_x[1][e] = b.lo0;
+        s_x[2][e] = b.lo1;
+        s_x[3][e] = b.lo2;
+        s_x[4][e] = b.hi0;
+        s_x[5][e] = b.hi1;
+        s_x[6][e] = b.hi2;
+      }
+      __syncthreads();
+      Box7 nv = box_empty();  // 4-wide y window of this thread's column
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        const int e = (ty + d) * kFbTX + tx;
+        box_add(nv, Box7{s_x[0][e], s_x[1][e], s_x[2][e], s_x[3][e], s_x[4][e], s_x[5][e], s_x[6][e]});
+      }
+      r0 = r1;
+      r1 = r2;
+      r2 = r3;
+      r3 = nv;
+      const int k = kk - 2, i = gx0 + 1 + tx, j = gy0 + 1 + ty;
+      if (k >= k0 && i < nx && j < ny) {
+        Box7 b = r0;
+        box_add(b, r1);
+        box_add(b, r2);
+        box_add(b, r3);
+        const float d0 = b.hi0 - b.lo0, d1 = b.hi1 - b.lo1, d2 = b.hi2 - b.lo2;
+        out[((size_t)k * ny + j) * nx + i] = make_float2(b.m, sqrtf(fmaf(d2, d2, fmaf(d0, d0, d1 * d1))));
+        local_max = fmaxf(local_max, b.m);  // every cell lies in its own box
+      }
     }
-    const float2 b = bound[((size_t)ck[0] * ny + cj[0]) * nx + ci[0]];
-    v[24] = b.x;
-    v[25] = b.y;
-#pragma unroll
-    for (int q = 26; q < kRecFloats; ++q) v[q] = 0.0f;
-    float4* out = P + r * (kRecFloats / 4);
-#pragma unroll
-    for (int q = 0; q < kRecFloats / 4; ++q) out[q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
   }
+  for (int off = 32; off > 0; off >>= 1) local_max = fmaxf(local_max, __shfl_xor(local_max, off));
+  if ((tid & 63) == 0) s_w[tid / 64] = local_max;
+  __syncthreads();
+  if (tid == 0) {
+    float m = 0.0f;
+    for (int w = 0; w < kFbThreads / 64; ++w) m = fmaxf(m, s_w[w]);
+    if (m > 0.0f) atomicMax(emax_bits, __float_as_uint(m));
+  }
+}
+
+// Corner-packed field (layout in pcmcc_device.hpp): the record of lower
+// centre index (i, j, k) in [-1, n]^3 holds the fields of the 8 centres
+// around it (indices clamped to the grid) and the bound of the cell
+// clamp(i, j, k).  Each lane writes one float4 of a record, so that a wave's
+// store covers eight whole consecutive records.
+__global__ __launch_bounds__(256) void k_pack_field(const float4* __restrict__ E, const float2* __restrict__ bound,
+                                                    int nx, int ny, int nz, float4* __restrict__ P) {
+  constexpr int Q = kRecFloats / 4;  // float4 per record
+  const uint64_t px = (uint64_t)nx + 2, py = (uint64_t)ny + 2;
+  const uint64_t nrec = px * py * ((uint64_t)nz + 2);
+  const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t r = g / Q;
+  const int q = (int)(g % Q);
+  if (r >= nrec) return;
+  const int i = (int)(r % px) - 1, j = (int)((r / px) % py) - 1, k = (int)(r / (px * py)) - 1;
+  const int ci[2] = {min(max(i, 0), nx - 1), min(max(i + 1, 0), nx - 1)};
+  const int cj[2] = {min(max(j, 0), ny - 1), min(max(j + 1, 0), ny - 1)};
+  const int ck[2] = {min(max(k, 0), nz - 1), min(max(k + 1, 0), nz - 1)};
+  float v[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int f = 4 * q + t;  // float index within the record
+    float x = 0.0f;
+    if (f < 24) {
+      const int c = f / 3, comp = f % 3;
+      const float4 e = E[((size_t)ck[c >> 2] * ny + cj[(c >> 1) & 1]) * nx + ci[c & 1]];
+      x = comp == 0 ? e.x : (comp == 1 ? e.y : e.z);
+    } else if (f < 26) {
+      const float2 b = bound[((size_t)ck[0] * ny + cj[0]) * nx + ci[0]];
+      x = f == 24 ? b.x : b.y;
+    }
+    v[t] = x;
+  }
+  P[r * Q + q] = make_float4(v[0], v[1], v[2], v[3]);
 }
 
 // ---------------------------------------------------------------------------
@@ -473,15 +550,20 @@ hipError_t launch_finalize(const Soa& user, const Soa& scratch, Ctl* ctl, int64_
 
 hipError_t launch_field_bounds(const float4* E, int nx, int ny, int nz, float2* out, unsigned* emax_bits,
                                hipStream_t stream) {
-  hipLaunchKernelGGL(k_field_bounds, dim3((unsigned)((nx + 127) / 128), (unsigned)ny, (unsigned)std::min(nz, 16)),
-                     dim3(128), 0, stream, E, nx, ny, nz, out, emax_bits);
+  const unsigned tx = (unsigned)((nx + kFbTX - 1) / kFbTX), ty = (unsigned)((ny + kFbTY - 1) / kFbTY);
+  unsigned chunks = (2048 + tx * ty - 1) / (tx * ty);  // plane ranges: about 2048 blocks, at least 16 planes each
+  if (chunks > (unsigned)(nz / 16)) chunks = (unsigned)(nz / 16);
+  if (chunks < 1) chunks = 1;
+  hipLaunchKernelGGL(k_field_bounds, dim3(tx, ty, chunks), dim3(kFbThreads), 0, stream, E, nx, ny, nz, out,
+                     emax_bits);
   return hipGetLastError();
 }
 
 hipError_t launch_pack_field(const float4* E, const float2* bound, int nx, int ny, int nz, float4* P,
                              hipStream_t stream) {
-  hipLaunchKernelGGL(k_pack_field, dim3((unsigned)((nx + 2 + 127) / 128), (unsigned)(ny + 2), (unsigned)(nz + 2)),
-                     dim3(128), 0, stream, E, bound, nx, ny, nz, P);
+  const uint64_t lanes = ((uint64_t)nx + 2) * ((uint64_t)ny + 2) * ((uint64_t)nz + 2) * (kRecFloats / 4);
+  hipLaunchKernelGGL(k_pack_field, dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, stream, E, bound, nx, ny, nz,
+                     P);
   return hipGetLastError();
 }
 
