@@ -429,40 +429,38 @@ __global__ __launch_bounds__(kFbThreads) void k_field_bounds(const float4* __res
   }
 }
 
-// Corner-packed field (layout in pcmcc_device.hpp): the record of lower
-// centre index (i, j, k) in [-1, n]^3 holds the fields of the 8 centres
-// around it (indices clamped to the grid) and the bound of the cell
-// clamp(i, j, k).  Each lane writes one float4 of a record, so that a wave's
-// store covers eight whole consecutive records.
-__global__ __launch_bounds__(256) void k_pack_field(const float4* __restrict__ E, const float2* __restrict__ bound,
+// Corner-packed field (layout in pcmcc_device.hpp): one thread per record,
+// the record of lower centre index (i, j, k) in [-1, n]^3 holding the fields
+// of the 8 centres around it (indices clamped to the grid) and the bound of
+// the cell clamp(i, j, k).
+// One block row of records per (j, k) in [-1, n]^2 (blockIdx.y, blockIdx.z).
+__global__ __launch_bounds__(128) void k_pack_field(const float4* __restrict__ E, const float2* __restrict__ bound,
                                                     int nx, int ny, int nz, float4* __restrict__ P) {
-  constexpr int Q = kRecFloats / 4;  // float4 per record
   const uint64_t px = (uint64_t)nx + 2, py = (uint64_t)ny + 2;
-  const uint64_t nrec = px * py * ((uint64_t)nz + 2);
-  const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t r = g / Q;
-  const int q = (int)(g % Q);
-  if (r >= nrec) return;
-  const int i = (int)(r % px) - 1, j = (int)((r / px) % py) - 1, k = (int)(r / (px * py)) - 1;
-  const int ci[2] = {min(max(i, 0), nx - 1), min(max(i + 1, 0), nx - 1)};
-  const int cj[2] = {min(max(j, 0), ny - 1), min(max(j + 1, 0), ny - 1)};
-  const int ck[2] = {min(max(k, 0), nz - 1), min(max(k + 1, 0), nz - 1)};
-  float v[4];
+  const int ri = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ri < nx + 2) {
+    const uint64_t r = ((uint64_t)blockIdx.z * py + blockIdx.y) * px + (uint64_t)ri;
+    const int i = ri - 1, j = (int)blockIdx.y - 1, k = (int)blockIdx.z - 1;
+    const int ci[2] = {min(max(i, 0), nx - 1), min(max(i + 1, 0), nx - 1)};
+    const int cj[2] = {min(max(j, 0), ny - 1), min(max(j + 1, 0), ny - 1)};
+    const int ck[2] = {min(max(k, 0), nz - 1), min(max(k + 1, 0), nz - 1)};
+    float v[kRecFloats];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int f = 4 * q + t;  // float index within the record
-    float x = 0.0f;
-    if (f < 24) {
-      const int c = f / 3, comp = f % 3;
+    for (int c = 0; c < 8; ++c) {
       const float4 e = E[((size_t)ck[c >> 2] * ny + cj[(c >> 1) & 1]) * nx + ci[c & 1]];
-      x = comp == 0 ? e.x : (comp == 1 ? e.y : e.z);
-    } else if (f < 26) {
-      const float2 b = bound[((size_t)ck[0] * ny + cj[0]) * nx + ci[0]];
-      x = f == 24 ? b.x : b.y;
+      v[3 * c] = e.x;
+      v[3 * c + 1] = e.y;
+      v[3 * c + 2] = e.z;
     }
-    v[t] = x;
+    const float2 b = bound[((size_t)ck[0] * ny + cj[0]) * nx + ci[0]];
+    v[24] = b.x;
+    v[25] = b.y;
+#pragma unroll
+    for (int q = 26; q < kRecFloats; ++q) v[q] = 0.0f;
+    float4* out = P + r * (kRecFloats / 4);
+#pragma unroll
+    for (int q = 0; q < kRecFloats / 4; ++q) out[q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
   }
-  P[r * Q + q] = make_float4(v[0], v[1], v[2], v[3]);
 }
 
 // ---------------------------------------------------------------------------
@@ -561,9 +559,8 @@ hipError_t launch_field_bounds(const float4* E, int nx, int ny, int nz, float2* 
 
 hipError_t launch_pack_field(const float4* E, const float2* bound, int nx, int ny, int nz, float4* P,
                              hipStream_t stream) {
-  const uint64_t lanes = ((uint64_t)nx + 2) * ((uint64_t)ny + 2) * ((uint64_t)nz + 2) * (kRecFloats / 4);
-  hipLaunchKernelGGL(k_pack_field, dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, stream, E, bound, nx, ny, nz,
-                     P);
+  hipLaunchKernelGGL(k_pack_field, dim3((unsigned)((nx + 2 + 127) / 128), (unsigned)(ny + 2), (unsigned)(nz + 2)),
+                     dim3(128), 0, stream, E, bound, nx, ny, nz, P);
   return hipGetLastError();
 }
 
