@@ -88,6 +88,43 @@ def test_photoionize_matches_oracle(pic, k, eta, w_photon):
     assert np.array_equal(rho, oracle.deposit(new["x"], new["y"], new["z"], new["w"], grid))
 
 
+def test_photoionize_streamer_scale(pic):
+    # The self-consistent streamer stage's scale: 1e6 ionization events around
+    # the tip (N(tip, 300 um)) on the 256^3 grid of 10 mm, the paper's yield
+    # (xi 0.075, p_q 40 mbar at 1 bar) with photons of the event's weight and
+    # the absorption constants of air: every photon compared with the oracle.
+    from paper_2110_14494_amd import workloads as W
+    cfg = W.streamer_config(n=2 ** 10)
+    grid = cfg["grid"]
+    nz, ny, nx = np.asarray(grid["E"]).shape[:3]
+    rng = np.random.default_rng(11)
+    n_ev = 1_000_000
+    tip = np.array([5e-3, 5e-3, 8e-3])
+    pos = (tip + 300e-6 * rng.standard_normal((n_ev, 3))).astype(np.float32)
+    ev = {"x": pos[:, 0].copy(), "y": pos[:, 1].copy(), "z": pos[:, 2].copy(),
+          "w": rng.uniform(200.0, 2000.0, n_ev).astype(np.float32)}
+    eta = 40.0 / 1040.0 * 0.075
+    photo = {"eta": eta, "k1": 5.25e3, "k2": 3.0e5, "w_photon": 0.0}
+    o = P.photoionize(ev["x"], ev["y"], ev["z"], ev["w"], grid, eta, 5.25e3, 3.0e5, 0.0, 77, 123, nx, ny, nz)
+    ctx = pic.Context(0)
+    dg = pic.DeviceGrid(grid)
+    parts = pic.Particles(o["photons"] + 16)
+    n_pos = dg.zeros_rho()
+    dev = {c: torch.from_numpy(ev[c]).cuda() for c in ev}
+    print(f"[gpu] photoionize streamer scale: oracle {o['photons']} photons", flush=True)
+    ph, ab = ctx.photoionize(dg, dev, photo, 77, 123, parts, n_pos)
+    g = parts.to_numpy()
+    rho = n_pos.cpu().numpy()
+    ctx.close()
+    assert ph == o["photons"] and abs(ph - eta * n_ev) < 5 * math.sqrt(eta * n_ev)
+    common, ig, io = np.intersect1d(g["id"], o["id"], return_indices=True)
+    assert ab - len(common) <= 1 and o["absorbed"] - len(common) <= 1
+    for c in ("x", "y", "z"):
+        assert np.max(_ulps(g[c][ig], o[c][io])) <= 2.0, c
+    assert np.array_equal(g["w"][ig], o["w"][io])
+    assert np.array_equal(rho, oracle.deposit(g["x"], g["y"], g["z"], g["w"], grid))
+
+
 def test_photoionize_capacity_empty_and_errors(pic):
     grid, nc = _grid(16, 4e-5)
     ev = _events(5000, 4, nc * grid["dx"])
