@@ -2024,6 +2024,7 @@ int pcmcc_fluid_steps(pcmcc_ctx* c, const pcmcc_grid* applied, double* n_e, doub
   if (!c) return fail(nullptr, PCMCC_EINVAL, "null context");
   if (stats) std::memset(stats, 0, sizeof(*stats));
   if (!c->species_ok) return fail(c, PCMCC_ESTATE, "species not initialised (the gas density is needed)");
+  if (!(c->gas_N > 0)) return fail(c, PCMCC_EINVAL, "the fluid step needs a gas density > 0");
   if (!valid_grid(applied) || !n_e || !n_pos || !n_neg || !phi || !tab) return fail(c, PCMCC_EINVAL, "null argument");
   if (tab->n < 2 || !(tab->EN_lo > 0) || !(tab->EN_hi > tab->EN_lo) || !tab->muN || !tab->DN || !tab->alphaN ||
       !tab->etaN)
@@ -2076,6 +2077,9 @@ int pcmcc_fluid_steps(pcmcc_ctx* c, const pcmcc_grid* applied, double* n_e, doub
   A.T.aN = c->fl_tab + 2 * (size_t)tab->n;
   A.T.eN = c->fl_tab + 3 * (size_t)tab->n;
   A.T.gas_N = c->gas_N;
+  A.T.pos_scale = (double)(tab->n - 1) / A.T.ln_span;
+  A.T.inv_gas_N = 1.0 / c->gas_N;
+  A.T.ln_td = std::log(1e21 / c->gas_N);
   double field_ms = 0, stage_ms = 0;
   int64_t cycles = 0;
   auto field = [&](const double* ne, const double* np, const double* nn) -> int {

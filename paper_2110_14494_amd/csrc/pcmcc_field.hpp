@@ -81,6 +81,10 @@ struct FluidTab {
   double ln_lo, ln_span;  // ln of the first E/N node (Td), ln(last / first)
   const double *muN, *DN, *aN, *eN;
   double gas_N;
+  // precomputed so that the kernels multiply instead of dividing
+  double pos_scale;  // (n - 1) / ln_span: table position per unit of ln(E/N)
+  double inv_gas_N;  // 1 / N
+  double ln_td;      // ln(1e21 / N): ln(E/N in Td) = ln|E| + ln_td
 };
 struct FluidArgs {
   int nx, ny, nz;

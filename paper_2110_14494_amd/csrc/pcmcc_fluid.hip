@@ -31,13 +31,24 @@ __device__ __forceinline__ int mirror(int i, int m) {
   return min(max(i, 0), m - 1);
 }
 
-__device__ __forceinline__ double tab_at(const FluidTab& T, const double* v, double EN) {
+// Table position of a field of squared magnitude E2: u = (ln(E/N in Td) -
+// ln_lo) (n - 1) / ln_span with ln(E/N) = ln(E2) / 2 + ln(1e21 / N), clamped.
+// (Reciprocals and logarithms of the constants are precomputed: the kernel
+// multiplies where the definition divides, a difference of an ulp or so.)
+struct TabPos {
+  int i;
+  double f;
+};
+__device__ __forceinline__ TabPos tab_pos(const FluidTab& T, double E2) {
 #pragma clang fp contract(off)
-  double u = (log(fmax(EN, 1e-300)) - T.ln_lo) / T.ln_span * (double)(T.n - 1);
+  double u = (0.5 * log(fmax(E2, 1e-300)) + T.ln_td - T.ln_lo) * T.pos_scale;
   u = fmin(fmax(u, 0.0), (double)(T.n - 1));
   const int i = min((int)floor(u), T.n - 2);
-  const double f = u - (double)i;
-  return (1.0 - f) * v[i] + f * v[i + 1];
+  return TabPos{i, u - (double)i};
+}
+__device__ __forceinline__ double tab_at(const TabPos& p, const double* v) {
+#pragma clang fp contract(off)
+  return (1.0 - p.f) * v[p.i] + p.f * v[p.i + 1];
 }
 
 // Koren-limited slope from the upwind slope a and the downwind slope b.
@@ -45,7 +56,7 @@ __device__ __forceinline__ double koren(double a, double b) {
 #pragma clang fp contract(off)
   if (!(a * b > 0.0)) return 0.0;
   const double aa = fabs(a), ab = fabs(b);
-  const double m = fmin(fmin(2.0 * ab, (aa + 2.0 * ab) / 3.0), 2.0 * aa);
+  const double m = fmin(fmin(2.0 * ab, (aa + 2.0 * ab) * (1.0 / 3.0)), 2.0 * aa);
   return a > 0.0 ? m : -m;
 }
 
@@ -82,10 +93,9 @@ __global__ __launch_bounds__(kRowThreads) void k_fl_stage(FluidArgs A, int stage
     for (int side = 0; side < 2; ++side) {  // face between cells (p-1+side) and (p+side)
       const double3 EL = side ? Ec : Em, ER = side ? Ep : Ec;
       const double3 Ef = make_double3(0.5 * (EL.x + ER.x), 0.5 * (EL.y + ER.y), 0.5 * (EL.z + ER.z));
-      const double Efm = sqrt((Ef.x * Ef.x + Ef.y * Ef.y) + Ef.z * Ef.z);
-      const double EN = Efm / A.T.gas_N * 1e21;
-      const double mu = tab_at(A.T, A.T.muN, EN) / A.T.gas_N;
-      const double D = tab_at(A.T, A.T.DN, EN) / A.T.gas_N;
+      const TabPos tp = tab_pos(A.T, (Ef.x * Ef.x + Ef.y * Ef.y) + Ef.z * Ef.z);
+      const double mu = tab_at(tp, A.T.muN) * A.T.inv_gas_N;
+      const double D = tab_at(tp, A.T.DN) * A.T.inv_gas_N;
       const double En = ax == 0 ? Ef.x : (ax == 1 ? Ef.y : Ef.z);
       const double v = -mu * En;
       const double nLL = nv[side], nL = nv[side + 1], nR = nv[side + 2], nRR = nv[side + 3];
@@ -94,11 +104,12 @@ __global__ __launch_bounds__(kRowThreads) void k_fl_stage(FluidArgs A, int stage
     }
     div += (fl[1] - fl[0]) * inv_dx;
   }
-  const double Emag = sqrt((Ec.x * Ec.x + Ec.y * Ec.y) + Ec.z * Ec.z);
-  const double EN = Emag / A.T.gas_N * 1e21;
-  const double mu = tab_at(A.T, A.T.muN, EN) / A.T.gas_N;
-  const double alpha = tab_at(A.T, A.T.aN, EN) * A.T.gas_N;
-  const double eta = tab_at(A.T, A.T.eN, EN) * A.T.gas_N;
+  const double E2 = (Ec.x * Ec.x + Ec.y * Ec.y) + Ec.z * Ec.z;
+  const double Emag = sqrt(E2);
+  const TabPos tp = tab_pos(A.T, E2);
+  const double mu = tab_at(tp, A.T.muN) * A.T.inv_gas_N;
+  const double alpha = tab_at(tp, A.T.aN) * A.T.gas_N;
+  const double eta = tab_at(tp, A.T.eN) * A.T.gas_N;
   const double rate = mu * Emag * n[c];
   const double ke = -div + (alpha - eta) * rate, kp = alpha * rate, kn = eta * rate;
   if (stage == 1) {
@@ -146,10 +157,9 @@ __global__ __launch_bounds__(256) void k_fl_dt(const double* __restrict__ ne, co
   double mc = 0.0, md = 0.0;
   for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (size_t)gridDim.x * blockDim.x) {
     const double3 e = e3(E[c]);
-    const double Emag = sqrt((e.x * e.x + e.y * e.y) + e.z * e.z);
-    const double EN = Emag / T.gas_N * 1e21;
-    const double mu = tab_at(T, T.muN, EN) / T.gas_N;
-    const double D = tab_at(T, T.DN, EN) / T.gas_N;
+    const TabPos tp = tab_pos(T, (e.x * e.x + e.y * e.y) + e.z * e.z);
+    const double mu = tab_at(tp, T.muN) * T.inv_gas_N;
+    const double D = tab_at(tp, T.DN) * T.inv_gas_N;
     const double cfl = 2.0 * 3.0 * D / (dx * dx) + (mu * ((fabs(e.x) + fabs(e.y)) + fabs(e.z))) / dx;
     const double drt = kFlQe * ne[c] * mu / kFlEps0;
     mc = fmax(mc, cfl);
