@@ -88,6 +88,32 @@ def test_photoionize_matches_oracle(pic, k, eta, w_photon):
     assert np.array_equal(rho, oracle.deposit(new["x"], new["y"], new["z"], new["w"], grid))
 
 
+def test_photoionize_many_photons_per_event(pic):
+    # lambda up to 200 photons per event (weights up to 2000, single photons):
+    # the per-event photon index j runs far beyond the first draw words
+    grid, nc = _grid(32, 2e-5)
+    ev = _events(2000, 9, nc * grid["dx"])
+    k1, k2 = 2.0e4, 1.0e6
+    o = P.photoionize(ev["x"], ev["y"], ev["z"], ev["w"], grid, 0.1, k1, k2, 1.0, 5, 2, nc, nc, nc)
+    ctx = pic.Context(0)
+    dg = pic.DeviceGrid(grid)
+    parts = pic.Particles(o["photons"] + 1)
+    n_pos = dg.zeros_rho()
+    dev = {c: torch.from_numpy(ev[c]).cuda() for c in ev}
+    print(f"[gpu] photoionize many photons: oracle {o['photons']}", flush=True)
+    ph, ab = ctx.photoionize(dg, dev, {"eta": 0.1, "k1": k1, "k2": k2, "w_photon": 1.0}, 5, 2, parts, n_pos)
+    g = parts.to_numpy()
+    rho = n_pos.cpu().numpy()
+    ctx.close()
+    assert ph == o["photons"] and ph > 150_000
+    common, ig, io = np.intersect1d(g["id"], o["id"], return_indices=True)
+    assert ab - len(common) <= max(1, 1e-4 * ab) and o["absorbed"] - len(common) <= max(1, 1e-4 * ab)
+    for c in ("x", "y", "z"):
+        assert np.max(_ulps(g[c][ig], o[c][io])) <= 2.0, c
+    assert np.all(g["w"] == 1.0)
+    assert np.array_equal(rho, oracle.deposit(g["x"], g["y"], g["z"], g["w"], grid))
+
+
 def test_photoionize_streamer_scale(pic):
     # The self-consistent streamer stage's scale: 1e6 ionization events around
     # the tip (N(tip, 300 um)) on the 256^3 grid of 10 mm, the paper's yield
