@@ -178,6 +178,15 @@ def test_photoionize_capacity_empty_and_errors(pic):
     big = pic.Particles.from_numpy(pre, 10_000)
     ph, ab = ctx.photoionize(dg, dev, photo, 1, 0, big, None)
     assert big.n == 10 + ab and 0 < ab <= ph
+    # free slots exactly equal to the photons emitted: accepted
+    exact = pic.Particles.from_numpy(pre, 10 + ph)
+    ph2, ab2 = ctx.photoionize(dg, dev, photo, 1, 0, exact, None)
+    assert (ph2, ab2) == (ph, ab) and exact.n == 10 + ab
+    # one slot fewer: refused, nothing written
+    short = pic.Particles.from_numpy(pre, 9 + ph)
+    with pytest.raises(pic.B.PcmccError) as e:
+        ctx.photoionize(dg, dev, photo, 1, 0, short, None)
+    assert e.value.code == pic.B.PCMCC_ECAPACITY and short.n == 10
     ctx.close()
 
 
