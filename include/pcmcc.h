@@ -400,7 +400,8 @@ int pcmcc_speed_quantile(pcmcc_ctx* ctx, const float* vx, const float* vy, const
  *
  * Per ionization event of weight w: lambda = eta w / w_photon photons of
  * weight w_photon (w_photon <= 0: of the event's weight, lambda = eta), and
- * the count is floor(lambda) + [U < lambda - floor(lambda)].  Draws are
+ * the count is floor(lambda) + [U < lambda - floor(lambda)] (an event with
+ * lambda >= 2^31 counts as 2^31 photons, which no capacity accepts).  Draws are
  * Philox4x32-10 with key (seed low word ^ 0x50484F54, seed high word ^ step
  * low word) and counter (bit patterns of the event's x, y, z; c), output
  * words r0..r3: c = 0 gives the count's U = (r0 + 1/2) 2^-32; c = 2j + 1

@@ -1715,13 +1715,13 @@ int photoionize(pcmcc_ctx* c, const pcmcc_grid* g, const float* ex, const float*
   }
   HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
   HIP_TRY(c, launch_photo_count(A, c->ph_cnt, c->ph_temp, c->ph_temp_bytes, c->ph_off, c->stream));
-  uint64_t last[2] = {0, 0};  // offs and count of the last event
+  uint64_t last_off = 0;  // offset and count of the last event: their sum is the total
   uint32_t last_cnt = 0;
-  HIP_TRY(c, hipMemcpyAsync(&last[0], c->ph_off + (n_ev - 1), sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(&last_off, c->ph_off + (n_ev - 1), sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipMemcpyAsync(&last_cnt, c->ph_cnt + (n_ev - 1), sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipMemcpyAsync(c->host_n, p->n_dev, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  const uint64_t total = last[0] + last_cnt;
+  const uint64_t total = last_off + last_cnt;
   const int64_t n_cur = *c->host_n;
   if (n_cur < 0 || n_cur > p->capacity) return fail(c, PCMCC_EINVAL, "particle count outside [0, capacity]");
   if (total > (uint64_t)(p->capacity - n_cur))

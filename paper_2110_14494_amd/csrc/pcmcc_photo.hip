@@ -111,6 +111,7 @@ __device__ __forceinline__ uint32_t photon_count(const PhotoArgs& A, uint64_t e,
     wph = (double)w;
   }
   if (!(lam > 0.0)) return 0u;
+  if (lam >= 2147483648.0) return 0x80000000u;  // saturated: far beyond any particle capacity
   const double fl = floor(lam);
   const uint4 r = photo_draw(A, xb, yb, zb, 0u);
   return (uint32_t)fl + (u32(r.x) < lam - fl ? 1u : 0u);
