@@ -3,10 +3,10 @@
 TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the benchmark's
 CPU-baseline leg may import this package.  It shares no code with the HIP
 library: the particle update, the tables and the deposit are written in plain
-double-precision C++ (``pcmcc_oracle.cpp``), the swarm estimators, the MLP and
-the electrostatics and time step of the self-consistent step and the fluid
-step in NumPy/SciPy (``estimators.py``, ``mlp.py``, ``field.py``,
-``fluid.py``).
+double-precision C++ (``pcmcc_oracle.cpp``), the swarm estimators, the MLP,
+the electrostatics and time step of the self-consistent step, the fluid step
+and the discrete photoionization in NumPy/SciPy (``estimators.py``,
+``mlp.py``, ``field.py``, ``fluid.py``, ``photo.py``).
 
 This module only loads the compiled oracle (building it with g++ if needed)
 and converts NumPy arrays to and from its C entry points.
