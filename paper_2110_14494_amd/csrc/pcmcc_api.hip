@@ -82,7 +82,7 @@ struct pcmcc_ctx {
   int64_t* wt_rho = nullptr;
   size_t wt_cells = 0;
   int64_t* dev_n = nullptr;  // a device count for the deposit of the update
-  // self-consistent field: multigrid levels (u[0] is the caller's potential),
+  // self-consistent field: multigrid levels (u[0] is the correction of the potential),
   // the field the electrons see, the electron density, event lists, and the
   // small reduction results
   MgWork mg{};

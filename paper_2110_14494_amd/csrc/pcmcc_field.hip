@@ -84,6 +84,42 @@ __device__ __forceinline__ T nb_sum(const T* u, int i, int j, int k, int nx, int
   return s;
 }
 
+// Storage of a level's u and f: natural (x fastest), or split by colour
+// (the finest launched level): the red cells ((i + j + k) even) fill the
+// first half and the black cells the second, each in natural order at index
+// c / 2 (c the natural index; nx even, so every pair 2m, 2m + 1 of a row
+// holds one cell of each colour).  A half sweep then streams the other
+// colour and its own right-hand side: half the bytes of the natural layout.
+template <bool kSplit>
+struct Lay {
+  size_t half;
+  __device__ __forceinline__ size_t at(size_t c, int parity) const {
+    return kSplit ? (parity ? half : 0) + (c >> 1) : c;
+  }
+};
+
+// nb_sum in layout L (the neighbours have the opposite parity).
+template <bool kSplit, class T>
+__device__ __forceinline__ T nb_sum_l(const T* u, Lay<kSplit> L, int i, int j, int k, int nx, int ny, int nz,
+                                      T& diag) {
+  const size_t c = idx3(i, j, k, nx, ny);
+  const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
+  const int q = 1 - ((i + j + k) & 1);
+  const bool xm = i > 0, xp = i < nx - 1, ym = j > 0, yp = j < ny - 1, zm = k > 0, zp = k < nz - 1;
+  const T a = u[L.at(xm ? c - 1 : c, q)], b = u[L.at(xp ? c + 1 : c, q)];
+  const T e = u[L.at(ym ? c - sy : c, q)], f = u[L.at(yp ? c + sy : c, q)];
+  const T g = u[L.at(zm ? c - sz : c, q)], h = u[L.at(zp ? c + sz : c, q)];
+  T s = 0;
+  s += xm ? a : T(0);
+  s += xp ? b : T(0);
+  s += ym ? e : T(0);
+  s += yp ? f : T(0);
+  s += zm ? g : T(0);
+  s += zp ? h : T(0);
+  diag = (T)(6 - (int)!xm - (int)!xp - (int)!ym - (int)!yp + (int)!zm + (int)!zp);
+  return s;
+}
+
 }  // namespace
 
 // Right-hand side of the finest level and its largest magnitude.
@@ -103,16 +139,18 @@ __global__ void k_sc_rhs(const int64_t* __restrict__ np, const int64_t* __restri
 // The level kernels are row stencils (row_pos: XCD-local runs of rows).
 
 // One red-black Gauss-Seidel half sweep: cells with (i + j + k) % 2 == color.
+template <bool kSplit>
 __global__ __launch_bounds__(kRowThreads) void k_mg_smooth(float* __restrict__ u, const float* __restrict__ f,
                                                            int nx, int ny, int nz, float h2, int color) {
 #pragma clang fp contract(off)
+  const Lay<kSplit> L{(size_t)nx * ny * nz / 2};
   const RowPos P = row_pos((nx + 1) / 2, ny);
   const int j = P.j, k = P.k;
   const int i = 2 * (P.x0 + (int)threadIdx.x) + ((j + k + color) & 1);
   if (i >= nx) return;
   float d;
-  const float s = nb_sum(u, i, j, k, nx, ny, nz, d);
-  const size_t c = idx3(i, j, k, nx, ny);
+  const float s = nb_sum_l(u, L, i, j, k, nx, ny, nz, d);
+  const size_t c = L.at(idx3(i, j, k, nx, ny), color);
   u[c] = (s - h2 * f[c]) / d;
 }
 
@@ -121,10 +159,12 @@ __global__ __launch_bounds__(kRowThreads) void k_mg_smooth(float* __restrict__ u
 // whose last half sweep relaxed the black cells ((i + j + k) odd): their
 // residual is zero up to rounding, so only the four red children are summed
 // (child offsets 000, 110, 101, 011).
+template <bool kSplit>
 __global__ __launch_bounds__(kRowThreads) void k_mg_restrict(const float* __restrict__ u,
                                                              const float* __restrict__ f, int nx, int ny, int nz,
                                                              float inv_h2, float* __restrict__ fc) {
 #pragma clang fp contract(off)
+  const Lay<kSplit> L{(size_t)nx * ny * nz / 2};
   const int cx = nx / 2, cy = ny / 2;
   const RowPos P = row_pos(cx, cy);
   const int I = P.x0 + (int)threadIdx.x, J = P.j, K = P.k;
@@ -135,8 +175,8 @@ __global__ __launch_bounds__(kRowThreads) void k_mg_restrict(const float* __rest
       if (((q ^ (q >> 1) ^ (q >> 2)) & 1) != 0) continue;
       const int i = 2 * I + (q & 1), j = 2 * J + ((q >> 1) & 1), k = 2 * K + (q >> 2);
       float d;
-      const float s = nb_sum(u, i, j, k, nx, ny, nz, d);
-      const size_t c = idx3(i, j, k, nx, ny);
+      const float s = nb_sum_l(u, L, i, j, k, nx, ny, nz, d);
+      const size_t c = L.at(idx3(i, j, k, nx, ny), 0);  // red
       acc += f[c] - (s - d * u[c]) * inv_h2;
     }
     fc[idx3(I, J, K, cx, cy)] = 0.125f * acc;
@@ -162,9 +202,11 @@ __device__ __forceinline__ float coarse_at(const float* U, int I, int J, int K, 
 // takes four consecutive fine cells of a row, 4t .. 4t + 3: they read the
 // coarse columns 2t - 1 .. 2t + 2 of the same four coarse rows, sixteen loads
 // instead of eight per cell.
+template <bool kSplit>
 __global__ __launch_bounds__(kRowThreads) void k_mg_prolong(float* __restrict__ u, const float* __restrict__ U,
                                                             int nx, int ny, int nz) {
 #pragma clang fp contract(off)
+  const Lay<kSplit> L{(size_t)nx * ny * nz / 2};
   const int cx = nx / 2, cy = ny / 2, cz = nz / 2;
   const RowPos P = row_pos((nx + 3) / 4, ny);
   const int t = P.x0 + (int)threadIdx.x, j = P.j, k = P.k;
@@ -187,7 +229,7 @@ __global__ __launch_bounds__(kRowThreads) void k_mg_prolong(float* __restrict__ 
     const int xi = (e >> 1) + 1, xi2 = (e & 1) ? xi + 1 : xi - 1;  // columns of I and I2
     const float v = 27.0f * a[xi][0] + 9.0f * (a[xi2][0] + a[xi][1] + a[xi][2]) +
                     3.0f * (a[xi2][1] + a[xi2][2] + a[xi][3]) + a[xi2][3];
-    u[c0 + e] += v * (1.0f / 64.0f);
+    u[L.at(c0 + e, (4 * t + e + j + k) & 1)] += v * (1.0f / 64.0f);
   }
 }
 
@@ -308,11 +350,13 @@ __global__ __launch_bounds__(512) void k_mg_tail(MgTailArgs A) {
 // part[block] (k_max_parts reduces them:
 // one same-address atomic per block would serialise in the memory-side
 // atomic unit).
+template <bool kSplit>
 __global__ __launch_bounds__(kRowThreads) void k_mg_defect(const double* __restrict__ phi,
                                                            const double* __restrict__ rhs, int nx, int ny, int nz,
                                                            double inv_h2, float* __restrict__ r,
                                                            double* __restrict__ part) {
 #pragma clang fp contract(off)
+  const Lay<kSplit> lay{(size_t)nx * ny * nz / 2};
   __shared__ double s_w[kRowThreads / 64];
   const unsigned nrb = (unsigned)((nx + kRowThreads - 1) / kRowThreads) * (unsigned)ny * (unsigned)nz;
   const unsigned L0 = xcd_block() * kDefectRows;
@@ -325,7 +369,7 @@ __global__ __launch_bounds__(kRowThreads) void k_mg_defect(const double* __restr
       double d;
       const double s = nb_sum(phi, i, j, k, nx, ny, nz, d);
       const double v = rhs[c] - (s - d * phi[c]) * inv_h2;
-      r[c] = (float)v;
+      r[lay.at(c, (i + j + k) & 1)] = (float)v;
       m = fmax(m, fabs(v));
     }
   }
@@ -353,10 +397,17 @@ __global__ __launch_bounds__(1024) void k_max_parts(const double* __restrict__ p
   }
 }
 
-// phi += the correction.
-__global__ void k_mg_correct(double* __restrict__ phi, const float* __restrict__ e, size_t n) {
-  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (size_t)gridDim.x * blockDim.x)
-    phi[c] += (double)e[c];
+// phi += the correction (a row kernel: the split layout needs the parity).
+template <bool kSplit>
+__global__ __launch_bounds__(kRowThreads) void k_mg_correct(double* __restrict__ phi, const float* __restrict__ e,
+                                                            int nx, int ny, int nz) {
+  const Lay<kSplit> L{(size_t)nx * ny * nz / 2};
+  const RowPos P = row_pos(nx, ny);
+  const int i = P.x0 + (int)threadIdx.x;
+  if (i < nx) {
+    const size_t c = idx3(i, P.j, P.k, nx, ny);
+    phi[c] += (double)e[L.at(c, (i + P.j + P.k) & 1)];
+  }
 }
 
 
@@ -507,8 +558,15 @@ hipError_t launch_sc_rhs(const int64_t* np, const int64_t* ne, const int64_t* nn
   return hipGetLastError();
 }
 
+// The finest level is stored split by colour when it is swept by launches
+// (above kMgCoarseMax cells; then every dimension is even).
+static bool split_finest(const MgWork& W) {
+  const MgDims d = W.dims[0];
+  return (size_t)d.nx * d.ny * d.nz > (size_t)kMgCoarseMax && d.nx % 2 == 0 && W.levels > 1;
+}
+
 // One V(2,2) cycle of the correction from level l down.  u[l], f[l]: the
-// level's single-precision arrays.
+// level's single-precision arrays (level 0 in the layout of split_finest).
 hipError_t mg_vcycle(const MgWork& W, int l, hipStream_t s) {
   const MgDims d = W.dims[l];
   const double h = W.dx * (double)(1 << l);
@@ -536,38 +594,60 @@ hipError_t mg_vcycle(const MgWork& W, int l, hipStream_t s) {
     return hipGetLastError();
   }
   const dim3 gs = row_grid((d.nx + 1) / 2, d.ny, d.nz);
+  const bool split = l == 0 && split_finest(W);
+  auto smooth = [&](int color) {
+    if (split)
+      hipLaunchKernelGGL(k_mg_smooth<true>, gs, dim3(kRowThreads), 0, s, W.u[l], W.f[l], d.nx, d.ny, d.nz, h2, color);
+    else
+      hipLaunchKernelGGL(k_mg_smooth<false>, gs, dim3(kRowThreads), 0, s, W.u[l], W.f[l], d.nx, d.ny, d.nz, h2, color);
+  };
   for (int it = 0; it < 2; ++it)
-    for (int color = 0; color < 2; ++color)
-      hipLaunchKernelGGL(k_mg_smooth, gs, dim3(kRowThreads), 0, s, W.u[l], W.f[l], d.nx, d.ny, d.nz, h2, color);
+    for (int color = 0; color < 2; ++color) smooth(color);
   const MgDims dc = W.dims[l + 1];
   const size_t nc = (size_t)dc.nx * dc.ny * dc.nz;
-  hipLaunchKernelGGL(k_mg_restrict, row_grid(dc.nx, dc.ny, dc.nz), dim3(kRowThreads), 0, s, W.u[l], W.f[l], d.nx, d.ny, d.nz,
-                     1.0f / h2, W.f[l + 1]);
+  if (split)
+    hipLaunchKernelGGL(k_mg_restrict<true>, row_grid(dc.nx, dc.ny, dc.nz), dim3(kRowThreads), 0, s, W.u[l], W.f[l],
+                       d.nx, d.ny, d.nz, 1.0f / h2, W.f[l + 1]);
+  else
+    hipLaunchKernelGGL(k_mg_restrict<false>, row_grid(dc.nx, dc.ny, dc.nz), dim3(kRowThreads), 0, s, W.u[l], W.f[l],
+                       d.nx, d.ny, d.nz, 1.0f / h2, W.f[l + 1]);
   hipError_t e = hipSuccess;
   if (nc > (size_t)kMgCoarseMax) e = hipMemsetAsync(W.u[l + 1], 0, nc * sizeof(float), s);  // the tail zeroes its own
   if (e != hipSuccess) return e;
   e = mg_vcycle(W, l + 1, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_mg_prolong, row_grid((d.nx + 3) / 4, d.ny, d.nz), dim3(kRowThreads), 0, s, W.u[l],
-                     W.u[l + 1], d.nx, d.ny, d.nz);
+  const dim3 gp = row_grid((d.nx + 3) / 4, d.ny, d.nz);
+  if (split)
+    hipLaunchKernelGGL(k_mg_prolong<true>, gp, dim3(kRowThreads), 0, s, W.u[l], W.u[l + 1], d.nx, d.ny, d.nz);
+  else
+    hipLaunchKernelGGL(k_mg_prolong<false>, gp, dim3(kRowThreads), 0, s, W.u[l], W.u[l + 1], d.nx, d.ny, d.nz);
   for (int it = 0; it < 2; ++it)
-    for (int color = 0; color < 2; ++color)
-      hipLaunchKernelGGL(k_mg_smooth, gs, dim3(kRowThreads), 0, s, W.u[l], W.f[l], d.nx, d.ny, d.nz, h2, color);
+    for (int color = 0; color < 2; ++color) smooth(color);
   return hipGetLastError();
 }
 
 hipError_t launch_defect(const MgWork& W, unsigned long long* rmax, hipStream_t s) {
   const MgDims d = W.dims[0];
   const unsigned nb = defect_blocks(d.nx, d.ny, d.nz);
-  hipLaunchKernelGGL(k_mg_defect, dim3(nb), dim3(kRowThreads), 0, s, W.phi, W.rhs, d.nx, d.ny, d.nz,
-                     1.0 / (W.dx * W.dx), W.f[0], W.part);
+  const double ih2 = 1.0 / (W.dx * W.dx);
+  if (split_finest(W))
+    hipLaunchKernelGGL(k_mg_defect<true>, dim3(nb), dim3(kRowThreads), 0, s, W.phi, W.rhs, d.nx, d.ny, d.nz, ih2,
+                       W.f[0], W.part);
+  else
+    hipLaunchKernelGGL(k_mg_defect<false>, dim3(nb), dim3(kRowThreads), 0, s, W.phi, W.rhs, d.nx, d.ny, d.nz, ih2,
+                       W.f[0], W.part);
   hipLaunchKernelGGL(k_max_parts, dim3(1), dim3(1024), 0, s, W.part, nb, rmax);
   return hipGetLastError();
 }
 
 hipError_t launch_correct(const MgWork& W, hipStream_t s) {
-  const size_t n = (size_t)W.dims[0].nx * W.dims[0].ny * W.dims[0].nz;
-  hipLaunchKernelGGL(k_mg_correct, dim3(grid_for(n, 4096)), dim3(256), 0, s, W.phi, W.u[0], n);
+  const MgDims d = W.dims[0];
+  if (split_finest(W))
+    hipLaunchKernelGGL(k_mg_correct<true>, row_grid(d.nx, d.ny, d.nz), dim3(kRowThreads), 0, s, W.phi, W.u[0], d.nx,
+                       d.ny, d.nz);
+  else
+    hipLaunchKernelGGL(k_mg_correct<false>, row_grid(d.nx, d.ny, d.nz), dim3(kRowThreads), 0, s, W.phi, W.u[0], d.nx,
+                       d.ny, d.nz);
   return hipGetLastError();
 }
 
