@@ -87,6 +87,7 @@ def parse():
                     help="absorption coefficient chi_min p_O2 (1/m; the paper gives none: air at 1 bar)")
     ap.add_argument("--photo-k2", type=float, default=3.0e5, help="absorption coefficient chi_max p_O2 (1/m)")
     ap.add_argument("--no-fluid", action="store_true", help="skip the fluid run")
+    ap.add_argument("--no-mg", action="store_true", help="skip the multigrid solve")
     ap.add_argument("--fluid-steps", type=int, default=100, help="Heun steps of the fluid run")
     ap.add_argument("--coef-scale", type=float, default=1.0, help="scale of the swarm sizes")
     ap.add_argument("--epochs", type=int, default=20000)
@@ -356,6 +357,43 @@ def sc_leg(a, ctx, pic, mu_table):
                                                                w_photon="ionizing electron's weight")}
 
 
+def multigrid_leg(a, ctx, pic):
+    """The potential solve of the self-consistent step (Sec. 2.5) alone on
+    the streamer grid (256^3 cells of 39 um): a seeded charge (uniform random
+    ion and electron densities of 2^40 units per cell plus a positive block at
+    the tip), solved from zero to a relative residual of 1e-6, four times;
+    reported: V-cycles per solve and milliseconds per cycle (defect and
+    correction included)."""
+    import torch
+    from paper_2110_14494_amd import workloads as W
+    cfg = W.streamer_config(n=2 ** 10)
+    grid = pic.DeviceGrid(cfg["grid"])
+    n = grid.nx
+    shape = (grid.nz, grid.ny, grid.nx)
+    rng = np.random.default_rng(3)
+    n_pos = rng.integers(0, 2 ** 40, size=shape, dtype=np.int64)
+    n_pos[n // 3:n // 2, n // 4:n // 2, n // 3:2 * n // 3] += 2 ** 44
+    n_e = rng.integers(0, 2 ** 40, size=shape, dtype=np.int64)
+    n_neg = rng.integers(0, 2 ** 36, size=shape, dtype=np.int64)
+    t = [torch.from_numpy(x).cuda() for x in (n_pos, n_e, n_neg)]
+    phi = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    res = []
+    for rep in range(5):
+        phi.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cyc, rel = ctx.solve_potential(grid, *t, phi, tol=1e-6, max_cycles=30)
+        torch.cuda.synchronize()
+        if rep > 0:  # the first solve allocates the levels
+            res.append(((time.perf_counter() - t0) * 1e3, cyc, rel))
+    ms = float(np.median([r[0] for r in res]))
+    cyc = res[-1][1]
+    log(f"multigrid: {cyc} cycles to {res[-1][2]:.2e}, {ms:.2f} ms per solve, {ms / cyc:.3f} ms per cycle")
+    return {"grid": n, "cells": n ** 3, "tol": 1e-6, "cycles_per_solve": int(cyc), "rel_residual": float(res[-1][2]),
+            "ms_per_solve": ms, "ms_per_cycle": ms / cyc, "cycle": "V(2,2), red-black Gauss-Seidel, single precision, "
+            "double-precision defect correction"}
+
+
 FLUID_BYTES_PER_CELL_STAGE = 92.0  # both Heun stages: densities, field, derivatives (mean of 88 and 96 B)
 
 
@@ -553,6 +591,9 @@ def main():
     if not a.no_coef:
         log("coefficient path")
         out["coefficients"] = coef_leg(a, ctx, pic)
+    if not a.no_mg:
+        log("multigrid solve")
+        out["multigrid"] = multigrid_leg(a, ctx, pic)
     if not a.no_fluid and getattr(a, "fluid_table", None) is not None:
         log("fluid run")
         out["fluid"] = fluid_leg(a, ctx, pic, a.fluid_table)
