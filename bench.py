@@ -438,9 +438,11 @@ def fluid_leg(a, ctx, pic, table):
             "t_simulated_s": float(hist.sum()), "dt_min_s": float(hist.min()) if done else None,
             "dt_max_s": float(hist.max()) if done else None, "s": el, "cell_steps_per_s": cells * done / el,
             "stage_kernel_ms": stage_ms, "field_ms": st["field_ms"], "mg_cycles": int(st["mg_cycles"]),
-            "stage_roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "stage_roofline": {"bound": "fp64 issue", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": gbs / HBM_PEAK_GBS if gbs else None,
-                               "bytes_per_cell_stage": FLUID_BYTES_PER_CELL_STAGE},
+                               "bytes_per_cell_stage": FLUID_BYTES_PER_CELL_STAGE,
+                               "note": "HBM fraction of the stage kernels; they are bound by FP64 instruction issue "
+                                       "(about 1500 instructions per cell: table logarithms, limiter, interpolation)"},
             "ne_max_final": float(ne.max()), "n_neg_max_final": float(nne.max()),
             "transport": "surrogate sampled on 2048 log-spaced E/N nodes (fallback cells: swarm table)"}
 
