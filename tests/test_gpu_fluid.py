@@ -67,3 +67,39 @@ def test_fluid_steps_match_oracle(pic, shape, dx, steps):
     for g, o in ((ne, ne_o), (npo, np_o), (nne, nn_o)):
         assert np.max(np.abs(g - o)) <= 1e-7 * np.max(np.abs(o)), np.max(np.abs(g - o)) / np.max(np.abs(o))
     assert np.max(np.abs(Eg[..., :3] - info["E"])) <= 1e-6 * np.max(np.abs(info["E"]))
+
+
+def test_fluid_streamer_grid_one_step(pic):
+    # The fluid leg's full size: the 256^3 streamer grid (39 um cells, tip
+    # field), the neutral Gaussian seed at the tip (peak 5.8e17 m^-3, sigma
+    # 300 um), one Heun step against the oracle, with the same bars.
+    cfg = W.streamer_config(n=2 ** 10)
+    grid = cfg["grid"]
+    E0 = np.asarray(grid["E"])
+    nz, ny, nx = E0.shape[:3]
+    dx = grid["dx"]
+    c = [(np.arange(m) + 0.5) * dx for m in (nz, ny, nx)]
+    tip = (8e-3, 5e-3, 5e-3)
+    r2 = ((c[0] - tip[0]) ** 2)[:, None, None] + ((c[1] - tip[1]) ** 2)[None, :, None] + \
+        ((c[2] - tip[2]) ** 2)[None, None, :]
+    seed = 5.8e17 * np.exp(-r2 / (2 * 300e-6 ** 2))
+    sp = W.electron_species()
+    tab = _table()
+    print(f"[gpu] fluid streamer grid {nx}^3, oracle step", flush=True)
+    ne_o, np_o, nn_o, info = FL.fluid_run(grid, seed, seed, np.zeros_like(seed), tab, sp["gas_N"], 1, 2e-11)
+    ctx = pic.Context(0)
+    ctx.init_species(sp)
+    dg = pic.DeviceGrid(grid)
+    t = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (seed, seed.copy(), np.zeros_like(seed))]
+    phi = torch.zeros(seed.shape, dtype=torch.float64, device="cuda")
+    E = torch.empty(seed.shape + (4,), dtype=torch.float32, device="cuda")
+    print("[gpu] fluid streamer grid, GPU step", flush=True)
+    rc, hist, st = ctx.fluid_steps(dg, *t, phi, tab, 2e-11, 1, mg_tol=1e-12, mg_max_cycles=80, E_out=E, check=False)
+    ne, npo, nne = (a.cpu().numpy() for a in t)
+    Eg = E.cpu().numpy()
+    ctx.close()
+    assert rc == 0 and st["steps_done"] == 1
+    assert np.allclose(hist, info["dt"], rtol=1e-9, atol=0)
+    for g, o in ((ne, ne_o), (npo, np_o), (nne, nn_o)):
+        assert np.max(np.abs(g - o)) <= 1e-7 * np.max(np.abs(o)), np.max(np.abs(g - o)) / np.max(np.abs(o))
+    assert np.max(np.abs(Eg[..., :3] - info["E"])) <= 1e-6 * np.max(np.abs(info["E"]))
