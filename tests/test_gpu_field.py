@@ -230,3 +230,50 @@ def test_error_paths(pic):
     assert rc == B.PCMCC_EINVAL
     assert dp.n == 100  # nothing moved
     ctx.close()
+
+
+def test_streamer_full_size_two_coupled_steps(pic):
+    # The self-consistent leg's full size: 2^24 electrons on the 256^3
+    # streamer grid with the neutral seed, two steps in the space-charge
+    # field against the oracle.  The first step's field is the applied one
+    # (no net charge), the second sees the charge the first separated: a weak
+    # coupling, so lineages are compared electron by electron with the step
+    # tests' bars, plus the field, the ion charge and the exact balance.
+    from test_gpu_pic import compare
+    cfg = W.streamer_config()
+    parts, grid = cfg["parts"], cfg["grid"]
+    n = parts["x"].size
+    n_pos0 = oracle.deposit(parts["x"], parts["y"], parts["z"], parts["w"], grid)
+    n_pos_o, n_neg_o = n_pos0.copy(), np.zeros_like(n_pos0)
+    print(f"[gpu] full-size coupled steps n={n}: oracle", flush=True)
+    orc_rc, o, info = F.streamer_run(cfg["species"], cfg["tables"], grid, parts, n_pos_o, n_neg_o, cfg["dt"], 2,
+                                     cfg["seed"], capacity=4 * n, adaptive=False)
+    assert orc_rc == 0
+    ctx = pic.Context(0)
+    ctx.setup(cfg["species"], cfg["tables"])
+    dp = pic.Particles.from_numpy(parts, 4 * n)
+    dg = pic.DeviceGrid(grid)
+    n_pos = torch.from_numpy(n_pos0.copy()).cuda()
+    n_neg = torch.zeros_like(n_pos)
+    phi = torch.zeros(n_pos.shape, dtype=torch.float64, device="cuda")
+    E = torch.empty(tuple(n_pos.shape) + (4,), dtype=torch.float32, device="cuda")
+    print("[gpu] full-size coupled steps: GPU", flush=True)
+    rc, _, hist, st = ctx.streamer_steps(dp, dg, n_pos, n_neg, phi, cfg["dt"], 2, cfg["seed"], adaptive=False,
+                                         mg_tol=1e-12, mg_max_cycles=80, E_out=E, check=False)
+    g = dp.to_numpy()
+    gp, gn, Eg = n_pos.cpu().numpy(), n_neg.cpu().numpy(), E.cpu().numpy()[..., :3]
+    ctx.close()
+    assert rc == 0 and st["steps_done"] == 2 and st["lost"] == 0
+    res = compare(g, {k: np.asarray(v) for k, v in o.items()}, grid["dx"])
+    print("[gpu] parity", res, flush=True)
+    assert res["flips"] <= max(1e-4 * st["trials"], 2), res
+    assert res["matched"] >= 0.999 * o["id"].size
+    tol = (res["flips"] + 2) * int(np.max(parts["w"])) * 2 ** 32
+    assert abs(int(gp.sum()) - int(n_pos_o.sum())) <= tol
+    assert abs(int(gn.sum()) - int(n_neg_o.sum())) <= tol
+    n_e = oracle.deposit(g["x"], g["y"], g["z"], g["w"], grid)
+    assert int(gp.sum()) - int(gn.sum()) == int(n_e.sum())  # neutral: ions = electrons, exactly
+    scale = np.max(np.abs(info["E"]))
+    assert np.max(np.abs(Eg - info["E"])) <= 1e-5 * scale
+    # the second step's field is not the applied one
+    assert np.max(np.abs(info["E"] - np.asarray(grid["E"])[..., :3])) > 1e-6 * scale
