@@ -92,6 +92,8 @@ struct pcmcc_ctx {
   size_t mg_rhs_n = 0;
   double* mg_part = nullptr;  // per-block maxima of the defect pass
   size_t mg_part_n = 0;
+  double* phi_prev = nullptr;  // the potential of the solve before the last (start-value extrapolation)
+  size_t phi_prev_n = 0;
   uint32_t* ph_cnt = nullptr;  // photoionization: photon counts per event
   uint64_t* ph_off = nullptr;  // and their exclusive scan
   uint64_t ph_n = 0;
@@ -611,6 +613,7 @@ int pcmcc_destroy(pcmcc_ctx* c) {
   dfree(c->mg_store);
   dfree(c->mg_rhs);
   dfree(c->mg_part);
+  dfree(c->phi_prev);
   dfree(c->ph_cnt);
   dfree(c->ph_off);
   if (c->ph_temp) (void)hipFree(c->ph_temp);
@@ -1757,6 +1760,28 @@ bool valid_photo(const pcmcc_photo_opts* o) {
          o->k2 > o->k1 && std::isfinite(o->w_photon);
 }
 
+// Start value of a sequence of solves in time: with two earlier solutions
+// (n_sol >= 2) phi becomes phi + r (phi - prev), r = dt_next / dt_last, and
+// prev the old phi; after the first solution prev is set to it.  The
+// converged potential is the same to the solve's tolerance; the extrapolated
+// start saves cycles.
+int solve_start(pcmcc_ctx* c, double* phi, size_t ncell, int n_sol, double r) {
+  if (n_sol < 1) return PCMCC_OK;
+  if (c->phi_prev_n < ncell) {
+    dfree(c->phi_prev);
+    c->phi_prev = nullptr;
+    c->phi_prev_n = 0;
+    HIP_TRY(c, dalloc(&c->phi_prev, ncell));
+    c->phi_prev_n = ncell;
+  }
+  if (n_sol == 1 || !(r > 0) || !std::isfinite(r)) {
+    HIP_TRY(c, hipMemcpyAsync(c->phi_prev, phi, ncell * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    return PCMCC_OK;
+  }
+  HIP_TRY(c, launch_extrapolate(phi, c->phi_prev, r, ncell, c->stream));
+  return PCMCC_OK;
+}
+
 }  // namespace
 
 int pcmcc_solve_potential(pcmcc_ctx* c, const pcmcc_grid* grid, const int64_t* n_pos, const int64_t* n_e,
@@ -1872,8 +1897,12 @@ int pcmcc_streamer_steps(pcmcc_ctx* c, const pcmcc_particles* p, const pcmcc_gri
   double field_ms = 0, dep_ms = 0;
   int64_t mg_cycles = 0;
   // densities, potential and field of the present state
-  auto refresh = [&]() -> int {
+  int n_sol = 0;         // solutions so far (start-value extrapolation)
+  double dt_last = 0;    // the step between the last two solutions
+  auto refresh = [&](double dt_taken) -> int {
     HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
+    int r0 = solve_start(c, phi, ncell, n_sol, dt_last > 0 ? dt_taken / dt_last : 0.0);
+    if (r0) return r0;
     HIP_TRY(c, hipMemsetAsync(c->sc_ne, 0, ncell * sizeof(int64_t), c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->host_n, p->n_dev, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -1884,6 +1913,8 @@ int pcmcc_streamer_steps(pcmcc_ctx* c, const pcmcc_particles* p, const pcmcc_gri
     r = solve_potential(c, applied, n_pos, c->sc_ne, n_neg, phi, o->mg_tol, o->mg_max_cycles, &cyc, &rel);
     if (r) return r;
     mg_cycles += cyc;
+    if (n_sol >= 1) dt_last = dt_taken;
+    ++n_sol;
     HIP_TRY(c, launch_sc_field((const float4*)applied->E, phi, applied->nx, applied->ny, applied->nz, applied->dx,
                                c->sc_E, c->stream));
     HIP_TRY(c, hipEventRecord(c->ev[3], c->stream));
@@ -1903,7 +1934,7 @@ int pcmcc_streamer_steps(pcmcc_ctx* c, const pcmcc_particles* p, const pcmcc_gri
     std::memcpy(out, &c->sc_host[4], sizeof(double));
     return PCMCC_OK;
   };
-  rc = refresh();
+  rc = refresh(0.0);
   if (rc) return rc;
   double n_old = 0;
   if (o->adaptive) {
@@ -1962,7 +1993,7 @@ int pcmcc_streamer_steps(pcmcc_ctx* c, const pcmcc_particles* p, const pcmcc_gri
       tot.photo_ms += pms;
       if (rc) break;
     }
-    rc = refresh();
+    rc = refresh(dt);
     if (rc) break;
     if (dt_hist) dt_hist[s] = dt;
     if (o->adaptive) {
@@ -2102,6 +2133,8 @@ int pcmcc_fluid_steps(pcmcc_ctx* c, const pcmcc_grid* applied, double* n_e, doub
   };
   rc = field(n_e, n_pos, n_neg);
   if (rc) return rc;
+  int n_sol = 1;       // solutions of the states at whole steps (start-value extrapolation)
+  double dt_last = 0;  // the step between the last two of them
   int s = 0;
   for (; s < n_steps; ++s) {
     HIP_TRY(c, hipMemsetAsync(c->sc_red + 2, 0, 2 * sizeof(unsigned long long), c->stream));
@@ -2121,6 +2154,8 @@ int pcmcc_fluid_steps(pcmcc_ctx* c, const pcmcc_grid* applied, double* n_e, doub
     float ms = 0;
     HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
     stage_ms += ms;
+    rc = solve_start(c, phi, ncell, n_sol, dt_last > 0 ? dt / dt_last : 0.0);  // from the last two steps' fields
+    if (rc) break;
     rc = field(A.se, A.sp, A.sn);
     if (rc) break;
     HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
@@ -2131,6 +2166,8 @@ int pcmcc_fluid_steps(pcmcc_ctx* c, const pcmcc_grid* applied, double* n_e, doub
     stage_ms += ms;
     rc = field(n_e, n_pos, n_neg);
     if (rc) break;
+    if (n_sol >= 1) dt_last = dt;
+    ++n_sol;
     if (dt_hist) dt_hist[s] = dt;
   }
   if (E_out) {

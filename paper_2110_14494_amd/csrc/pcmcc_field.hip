@@ -412,6 +412,18 @@ __global__ __launch_bounds__(kRowThreads) void k_mg_correct(double* __restrict__
 
 
 
+// Start value of the next solve from the last two solutions: phi <- phi +
+// r (phi - prev) (linear in time, r the ratio of the coming to the last time
+// step), prev <- the old phi.
+__global__ void k_extrapolate(double* __restrict__ phi, double* __restrict__ prev, double r, size_t n) {
+#pragma clang fp contract(off)
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (size_t)gridDim.x * blockDim.x) {
+    const double t = phi[c];
+    phi[c] = t + r * (t - prev[c]);
+    prev[c] = t;
+  }
+}
+
 // E = E_applied - grad phi at the centres (central differences with ghosts).
 __global__ __launch_bounds__(kRowThreads) void k_sc_field(const float4* __restrict__ Ea, const double* __restrict__ phi,
                                                   int nx, int ny, int nz, double two_dx, float4* __restrict__ E) {
@@ -648,6 +660,11 @@ hipError_t launch_correct(const MgWork& W, hipStream_t s) {
   else
     hipLaunchKernelGGL(k_mg_correct<false>, row_grid(d.nx, d.ny, d.nz), dim3(kRowThreads), 0, s, W.phi, W.u[0], d.nx,
                        d.ny, d.nz);
+  return hipGetLastError();
+}
+
+hipError_t launch_extrapolate(double* phi, double* prev, double r, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_extrapolate, dim3(grid_for(n, 4096)), dim3(256), 0, s, phi, prev, r, n);
   return hipGetLastError();
 }
 

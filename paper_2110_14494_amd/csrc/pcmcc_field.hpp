@@ -66,6 +66,7 @@ hipError_t launch_sc_rhs(const int64_t* np, const int64_t* ne, const int64_t* nn
 hipError_t mg_vcycle(const MgWork& W, int l, hipStream_t s);
 hipError_t launch_defect(const MgWork& W, unsigned long long* rmax, hipStream_t s);
 hipError_t launch_correct(const MgWork& W, hipStream_t s);
+hipError_t launch_extrapolate(double* phi, double* prev, double r, size_t n, hipStream_t s);
 hipError_t launch_sc_field(const float4* Ea, const double* phi, int nx, int ny, int nz, double dx, float4* E,
                            hipStream_t s);
 hipError_t launch_speed_select(const float* vx, const float* vy, const float* vz, const int64_t* n_dev, uint64_t n,
