@@ -113,7 +113,15 @@ struct GridField {
   // that record.
   Key k;
   using Where = const float4*;
-  __device__ __forceinline__ Key key(uint32_t) const { return k; }
+  // The key passes through an empty asm statement at every use, so that the
+  // Philox round keys are derived there with scalar adds instead of being
+  // hoisted out of the mover loop as twenty more uniform values (which spill
+  // into vector lanes and come back one v_readlane each).
+  __device__ __forceinline__ Key key(uint32_t) const {
+    uint32_t k0 = k.k0, k1 = k.k1;
+    asm volatile("" : "+s"(k0), "+s"(k1));
+    return Key{k0, k1};
+  }
   __device__ __forceinline__ double3 accel(double x, double y, double z, uint32_t, Where& w) const {
     return gather(G, qm, x, y, z, &w);
   }
