@@ -803,6 +803,7 @@ static int push_impl(pcmcc_ctx* c, const pcmcc_particles* p, const pcmcc_grid* f
   G.hi[1] = field->y0 + field->ny * field->dx;
   G.hi[2] = field->z0 + field->nz * field->dx;
   G.qm_abs = (float)std::fabs(A.S.qm);
+  G.qm = A.S.qm;
   A.key = Key{(uint32_t)seed, (uint32_t)(seed >> 32)};
   A.dt = (float)dt;
   if (ev) A.ev = *ev;

@@ -137,6 +137,7 @@ struct GridView {
   double lo[3], hi[3];  // domain
   float a_glob;         // |q/m| max |E|
   float qm_abs;
+  double qm;  // q/m of the species (the gather's factor)
 };
 
 // Cell-centre coordinate u = (x - x0)/dx - 1/2 of one axis, clamped to

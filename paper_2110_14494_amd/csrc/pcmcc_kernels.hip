@@ -182,7 +182,8 @@ __global__ __launch_bounds__(256) void k_pic_steps(PicArgs A) {
   WaveStage* L = reinterpret_cast<WaveStage*>(smem + pic_stage_offset_floats(A.T)) + (threadIdx.x >> 6);
   GridView G = A.G;
   G.a_glob = G.qm_abs * __uint_as_float(*A.emax_bits);
-  const GridField F{G, A.S.qm, A.key};
+  const auto* ka = (const __attribute__((address_space(4))) PicArgs*)__builtin_amdgcn_kernarg_segment_ptr();
+  const GridField F{G, A.S.qm, A.key, &ka->G};
   const unsigned lane = lane_id();
   Ctl* ctl = A.ctl;
 

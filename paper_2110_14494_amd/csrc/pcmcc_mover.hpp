@@ -112,6 +112,12 @@ struct GridField {
   // run's key, a gather that also returns its record, and the bound from
   // that record.
   Key k;
+  // The same view in kernel-argument memory.  The gather reads its
+  // constants from there through a pointer made opaque at each use, so they
+  // come back with a few scalar loads per segment instead of living in
+  // scalar registers for the whole mover loop (where they would spill into
+  // vector lanes and return one v_readlane each).
+  const __attribute__((address_space(4))) GridView* gk;
   using Where = const float4*;
   // The key passes through an empty asm statement at every use, so that the
   // Philox round keys are derived there with scalar adds instead of being
@@ -123,7 +129,20 @@ struct GridField {
     return Key{k0, k1};
   }
   __device__ __forceinline__ double3 accel(double x, double y, double z, uint32_t, Where& w) const {
-    return gather(G, qm, x, y, z, &w);
+    const __attribute__((address_space(4))) GridView* g = gk;
+    asm volatile("" : "+s"(g));
+    GridView v;
+    v.P = g->P;
+    v.nx = g->nx;
+    v.ny = g->ny;
+    v.nz = g->nz;
+    v.px = g->px;
+    v.py = g->py;
+    v.o[0] = g->o[0];
+    v.o[1] = g->o[1];
+    v.o[2] = g->o[2];
+    v.inv_dx = g->inv_dx;
+    return gather(v, g->qm, x, y, z, &w);
   }
   __device__ __forceinline__ void bound_at(Where w, uint32_t, float speed, float t_rem, float& a_abs,
                                            float& da) const {
