@@ -293,12 +293,13 @@ __device__ __forceinline__ int flight_plan(Flight& f, double dt, const Tab& T, c
   // majorant's 2^-16 guard covers them, and the free-flight time only needs
   // single precision.
   const float speed = __builtin_amdgcn_sqrtf(vf.x * vf.x + vf.y * vf.y + vf.z * vf.z);
-  const float nu_full = majorant_t(T, S, speed_bound(vf, af, speed, f.a_abs, f.da, (float)t_rem));
+  const TabConst tc = tab_const();
+  const float nu_full = majorant_t(T, tc, speed_bound(vf, af, speed, f.a_abs, f.da, (float)t_rem));
   const bool limited = kKappa < nu_full * (float)t_rem;
   // Both majorants are evaluated and one is selected, which keeps the lanes
   // of a wave on one path (nu_full = 0 gives an unused, finite lookup).
   const float h_lim = kKappa * __builtin_amdgcn_rcpf(nu_full);
-  const float nu_lim = majorant_t(T, S, speed_bound(vf, af, speed, f.a_abs, f.da, h_lim));
+  const float nu_lim = majorant_t(T, tc, speed_bound(vf, af, speed, f.a_abs, f.da, h_lim));
   const double h = limited ? (double)h_lim : t_rem;
   const float nu_hat = limited ? nu_lim : nu_full;
   const double tau = nu_hat > 0.0f ? (double)(-__logf(unif(r.x)) * __builtin_amdgcn_rcpf(nu_hat)) : (double)INFINITY;
@@ -338,22 +339,23 @@ __device__ __forceinline__ int flight_complete(Flight& f, const double3 an, cons
   if (f.seg == SEG_HORIZON) return EV_GO;
 
   // Candidate collision: real process k, or null.
+  const TabConst tc = tab_const();
   const double v2 = f.vx * f.vx + f.vy * f.vy + f.vz * f.vz;
-  const double eps = (double)S.k_eps_d * v2;
-  float u = __log2f((float)eps) * T.u_scale + T.u_offset;
-  u = fminf(fmaxf(u, 0.0f), (float)(T.n - 1));
-  const float fl = fminf(floorf(u), (float)(T.n - 2));
+  const double eps = tc.k_eps_d * v2;
+  float u = __log2f((float)eps) * tc.u_scale + tc.u_offset;
+  u = fminf(fmaxf(u, 0.0f), tc.u_top);
+  const float fl = fminf(floorf(u), tc.fl_top);
   const int i = (int)fl;
   const float fr = u - fl;
   const float yv = unif(f.r1) * f.nu_hat;
   float cum[kMaxProc];
-  cum_rates(T, i, fr, cum);
+  cum_rates(T, i, fr, cum, tc.row);
   const int k = pick_process(cum, yv);
   if (k < 0 || eps < (double)T.thr[k]) {
     cnt.v[C_NULL]++;
     return EV_GO;
   }
-  if (eps > (double)T.eps_max) cnt.v[C_OOT]++;
+  if (eps > tc.eps_max) cnt.v[C_OOT]++;
   const int kind = T.kind[k];
   cnt.v[C_EL] += kind == ELASTIC;
   cnt.v[C_EXC] += kind == EXCITATION;
@@ -367,14 +369,14 @@ __device__ __forceinline__ int flight_complete(Flight& f, const double3 an, cons
   double eps_new;
   if (kind == ELASTIC) {
     const double cchi = v2 > 0.0 ? (f.vx * nx + f.vy * ny + f.vz * nz) * rsqrt_nr(v2) : 0.0;
-    eps_new = eps * (1.0 - (double)S.recoil * (1.0 - cchi));
+    eps_new = eps * (1.0 - (double)tc.recoil * (1.0 - cchi));
   } else if (kind == EXCITATION) {
     eps_new = eps - thr;
   } else {
     eps_new = 0.5 * (eps - thr);
     staged = births.push((float)f.x, (float)f.y, (float)f.z, f.w, (float)f.t, f.tag, f.id, f.j - 1, eps_new);
   }
-  const double sn = sqrt_nr(eps_new * S.inv_k_d);
+  const double sn = sqrt_nr(eps_new * tc.inv_k_d);
   f.vx = sn * nx;
   f.vy = sn * ny;
   f.vz = sn * nz;

@@ -178,7 +178,7 @@ struct PlaceNewborn {
 __global__ __launch_bounds__(256) void k_pic_steps(PicArgs A) {
   extern __shared__ float smem[];
   cg::grid_group grid = cg::this_grid();
-  const Tab T = stage_tables(A.T, smem);
+  const Tab T = stage_tables(A.T, A.S, smem);
   WaveStage* L = reinterpret_cast<WaveStage*>(smem + pic_stage_offset_floats(A.T)) + (threadIdx.x >> 6);
   GridView G = A.G;
   G.a_glob = G.qm_abs * __uint_as_float(*A.emax_bits);
@@ -508,7 +508,7 @@ __global__ void k_philox(const uint4* __restrict__ ctr, Key key, uint4* __restri
 __global__ void k_lookup(TableView TV, SpeciesView S, const float* __restrict__ eps, float* __restrict__ cum,
                          const float* __restrict__ s_ub, float* __restrict__ maj, int64_t n) {
   extern __shared__ float smem[];
-  const Tab T = stage_tables(TV, smem);
+  const Tab T = stage_tables(TV, S, smem);
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
     const float e = eps[q];
     float u = __log2f(e) * T.u_scale + T.u_offset;

@@ -162,11 +162,33 @@ struct Tab {
   float u_scale, u_offset, eps_max;
 };
 
+// The scalars a flight segment needs from the tables and the species, kept
+// at a fixed LDS address and read at each use through an offset made opaque
+// there: held in scalar registers for the whole mover loop they would spill
+// into vector lanes and come back one v_readlane each, while one LDS read
+// brings four of them.
+struct TabConst {
+  float u_scale, u_offset, u_top, fl_top;  // table position; clamps n - 1 and n - 2
+  float k_eps;                             // eps[eV] = k_eps |v|^2
+  float recoil;                            // 2 m / M
+  int row;                                 // floats per node of C
+  int p_off;                               // P at C + p_off
+  double k_eps_d, inv_k_d;                 // k_eps and 1 / k_eps in double precision
+  double eps_max;                          // last node energy
+};
+static __shared__ TabConst g_tab_const;
+
+__device__ __forceinline__ TabConst tab_const() {
+  uint32_t off = 0;
+  asm volatile("" : "+v"(off));
+  return *reinterpret_cast<const TabConst*>(reinterpret_cast<const char*>(&g_tab_const) + off);
+}
+
 // Cumulative rates at table position (i, f), linear between nodes i and
 // i + 1 (entries at and beyond nproc are zero).
-__device__ __forceinline__ void cum_rates(const Tab& T, int i, float f, float c[kMaxProc]) {
-  const float4* a = reinterpret_cast<const float4*>(T.C + (size_t)i * T.row);
-  const float4* b = reinterpret_cast<const float4*>(T.C + (size_t)(i + 1) * T.row);
+__device__ __forceinline__ void cum_rates(const Tab& T, int i, float f, float c[kMaxProc], int row) {
+  const float4* a = reinterpret_cast<const float4*>(T.C + (size_t)i * row);
+  const float4* b = reinterpret_cast<const float4*>(T.C + (size_t)(i + 1) * row);
   auto put = [&](int o, float4 lo, float4 hi) {
     c[o] = fmaf(f, hi.x - lo.x, lo.x);
     c[o + 1] = fmaf(f, hi.y - lo.y, lo.y);
@@ -174,12 +196,15 @@ __device__ __forceinline__ void cum_rates(const Tab& T, int i, float f, float c[
     c[o + 3] = fmaf(f, hi.w - lo.w, lo.w);
   };
   put(0, a[0], b[0]);
-  if (T.row == 8) {
+  if (row == 8) {
     put(4, a[1], b[1]);
   } else {
 #pragma unroll
     for (int k = 4; k < kMaxProc; ++k) c[k] = 0.0f;
   }
+}
+__device__ __forceinline__ void cum_rates(const Tab& T, int i, float f, float c[kMaxProc]) {
+  cum_rates(T, i, f, c, T.row);
 }
 
 // First process whose cumulative rate exceeds y, or -1 (a null collision).
@@ -191,14 +216,17 @@ __device__ __forceinline__ int pick_process(const float c[kMaxProc], float y) {
   return k;
 }
 
-__device__ __forceinline__ float majorant_t(const Tab& T, const SpeciesView& S, float s_ub) {
+__device__ __forceinline__ float majorant_t(const Tab& T, const TabConst& c, float s_ub) {
   const float s = s_ub * kGuard;
-  const float eps = S.k_eps * s * s;
-  float u = __log2f(eps) * T.u_scale + T.u_offset;
-  u = fminf(fmaxf(u, 0.0f), (float)(T.n - 1));
-  const float fl = fminf(floorf(u), (float)(T.n - 2));
+  const float eps = c.k_eps * s * s;
+  float u = __log2f(eps) * c.u_scale + c.u_offset;
+  u = fminf(fmaxf(u, 0.0f), c.u_top);
+  const float fl = fminf(floorf(u), c.fl_top);
   const int i = (int)fl;
-  return lerp_at(T.P, i, u - fl);
+  return lerp_at(T.C + c.p_off, i, u - fl);
+}
+__device__ __forceinline__ float majorant_t(const Tab& T, const SpeciesView&, float s_ub) {
+  return majorant_t(T, tab_const(), s_ub);
 }
 
 // Square root of x >= 0 (0 for x <= 0) from the hardware reciprocal square
@@ -242,7 +270,7 @@ __device__ __forceinline__ bool inside(const GridView& G, const PState& p) {
 }
 
 // Stages the tables in LDS; returns the view the kernels read.
-__device__ inline Tab stage_tables(const TableView& TV, float* smem) {
+__device__ inline Tab stage_tables(const TableView& TV, const SpeciesView& S, float* smem) {
   const int row = table_row(TV.nproc);
   const int nC = row * TV.n;
   for (int e = threadIdx.x; e < nC; e += blockDim.x) {
@@ -255,6 +283,21 @@ __device__ inline Tab stage_tables(const TableView& TV, float* smem) {
   if (threadIdx.x < (unsigned)kMaxProc) {
     thr[threadIdx.x] = TV.thr[threadIdx.x];
     kind[threadIdx.x] = TV.kind[threadIdx.x];
+  }
+  if (threadIdx.x == 0) {
+    TabConst c;
+    c.u_scale = TV.u_scale;
+    c.u_offset = TV.u_offset;
+    c.u_top = (float)(TV.n - 1);
+    c.fl_top = (float)(TV.n - 2);
+    c.k_eps = S.k_eps;
+    c.recoil = S.recoil;
+    c.row = row;
+    c.p_off = nC;
+    c.k_eps_d = S.k_eps_d;
+    c.inv_k_d = S.inv_k_d;
+    c.eps_max = (double)TV.eps_top;
+    g_tab_const = c;
   }
   __syncthreads();
   Tab T;

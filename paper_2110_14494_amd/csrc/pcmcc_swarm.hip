@@ -236,7 +236,7 @@ template <int BS>
 __global__ __launch_bounds__(BS) void k_swarm_steps(SwarmArgs A) {
   extern __shared__ float smem[];
   cg::grid_group grid = cg::this_grid();
-  const Tab T = stage_tables(A.T, smem);
+  const Tab T = stage_tables(A.T, A.S, smem);
   const int S = A.n_swarms;
   // LDS after the tables: per-wave staging lists, per-swarm acceleration [S]
   // (double), prefix [S+1], scan scratch [BS], |acceleration| [S] and
