@@ -304,6 +304,27 @@ def test_full_size_streamer_sampled_lineages(pic):
     assert res["matched"] >= 0.999 * o["id"].size
 
 
+def test_full_size_streamer_timed_call_conserves_electrons(pic):
+    # The timed benchmark call itself (2^24 start electrons, 25 steps of 2 ps,
+    # 5.2e8 electrons at the end): every electron is accounted for (start +
+    # ionizations - attachments - lost = final count, exactly) and no id is
+    # duplicated or lost in the hole filling and newborn placement at that size.
+    cfg = W.streamer_config()
+    n0 = cfg["parts"]["x"].size
+    ctx = _ctx(pic, cfg["species"], cfg["tables"])
+    dp = pic.Particles.from_numpy(cfg["parts"], 32 * n0)
+    dg = pic.DeviceGrid(cfg["grid"])
+    print(f"[gpu] full-size streamer timed call n0={n0} steps=25", flush=True)
+    rc, st = ctx.push_collide_deposit(dp, dg, cfg["dt"], 25, cfg["seed"], check=False)
+    assert rc == 0 and st["steps_done"] == 25
+    n = st["n"]
+    assert n == n0 + st["ionization"] - st["attachment"] - st["lost"]
+    assert n > 500_000_000
+    ids = dp.t["id"][:n]
+    assert torch.unique(ids).numel() == n
+    ctx.close()
+
+
 def test_stress_stage_sampled_lineages(pic):
     # The large stress stage at full size (2^27 electrons, 512^3 cells of
     # 20 um, 1 ps steps, background 1.75e6 V/m) in the launch configuration of
