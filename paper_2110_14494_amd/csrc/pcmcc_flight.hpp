@@ -38,7 +38,7 @@ enum Segment : int { SEG_END = 0, SEG_HORIZON = 1, SEG_COLLIDE = 2 };
 enum FlightEvent : int { EV_GO = 0, EV_DONE = 1, EV_ATTACHED = 2, EV_LIMIT = 3 };
 
 constexpr uint32_t kChunk = 256;  // electrons taken from the work counter at a time
-constexpr int kRefillMin = 24;    // free lanes that trigger a finish-and-refill batch (tuned)
+constexpr int kRefillMin = 16;    // free lanes that trigger a finish-and-refill batch (tuned)
 
 // Per-wave staging lists in LDS.  Newborns, holes and placed newborns are
 // collected per wave and written out kFlushAt or more at a time, each batch
