@@ -111,6 +111,9 @@ typedef struct pcmcc_stats {
   int64_t photons;               /* photoionization: photons emitted */
   int64_t photoelectrons;        /* photoionization: photons absorbed inside the grid */
   double photo_ms;               /* photoionization: device time */
+  uint64_t majorant_violations;  /* candidate collisions whose total rate exceeded the majorant of their flight
+                                    segment (the null-collision method, Sec. 2.1.1, needs 0; a nonzero count
+                                    means the majorant rule is wrong) */
 } pcmcc_stats;
 
 /* Version string, static storage. */

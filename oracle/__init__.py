@@ -29,7 +29,8 @@ _lib = None
 ELASTIC, EXCITATION, IONIZATION, ATTACHMENT = 0, 1, 2, 3
 EFFECTIVE_TO_ELASTIC, RATES = 1, 2
 STATS_FIELDS = ("n", "steps_done", "particle_steps", "trials", "null", "elastic",
-                "excitation", "ionization", "attachment", "lost", "out_of_table", "errors")
+                "excitation", "ionization", "attachment", "lost", "out_of_table", "errors",
+                "majorant_violations", "bound_local", "bound_global")
 N_MOMENTS = 14
 
 
@@ -68,6 +69,8 @@ def lib():
             L.orc_philox4x32_10.restype = None
             L.orc_set_constant_majorant.argtypes = [C.c_int]
             L.orc_set_constant_majorant.restype = None
+            L.orc_set_majorant_fault.argtypes = [C.c_int]
+            L.orc_set_majorant_fault.restype = None
             L.orc_build_tables.argtypes = [C.POINTER(Problem), vp, vp, vp, vp]
             L.orc_lookup.argtypes = [C.POINTER(Problem), C.c_int64, vp, vp, vp, vp]
             L.orc_pic_run.argtypes = [C.POINTER(Problem), C.POINTER(Grid)] + [vp] * 8 + [
@@ -120,6 +123,13 @@ def make_grid(grid: dict):
 def set_constant_majorant(on: bool) -> None:
     """Test knob: replace the majorant rule by the constant table maximum."""
     lib().orc_set_constant_majorant(1 if on else 0)
+
+
+def set_majorant_fault(mode: int) -> None:
+    """Test knob: plant a known mistake in the majorant rule (1: drop the
+    field-range term of the speed bound, 2: nine tenths of every majorant;
+    0: the rule as stated), to show that the violation counter catches it."""
+    lib().orc_set_majorant_fault(int(mode))
 
 
 def philox4x32_10(ctr: np.ndarray, key: np.ndarray) -> np.ndarray:
@@ -189,7 +199,7 @@ def pic_run(species: dict, tables: dict, grid: dict, parts: dict, dt: float, n_s
     ids = np.zeros(cap, dtype=np.uint64)
     ids[:n] = np.asarray(parts["id"], dtype=np.uint64)
     n_io = C.c_int64(n)
-    stats = np.zeros(12, dtype=np.int64)
+    stats = np.zeros(len(STATS_FIELDS), dtype=np.int64)
     wstats = np.zeros(3, dtype=np.int64)
     nref = C.c_int64(int(n_ref))
     ev_cap = 2 * cap if events else 0
@@ -271,7 +281,7 @@ def swarm_run(species: dict, tables: dict, EN_Td, n0, dt: float, n_steps: int, s
     J = n_steps // sample_every
     mom = np.zeros((S, J, N_MOMENTS))
     cnt = np.zeros((S, J, 4), dtype=np.int64)
-    stats = np.zeros(12, dtype=np.int64)
+    stats = np.zeros(len(STATS_FIELDS), dtype=np.int64)
     rc = lib().orc_swarm_run(C.byref(pb), S, _ptr(EN), _ptr(n0), float(dt), int(n_steps), int(seed),
                              int(sample_every), int(cap_factor), 1 if population_control else 0, _ptr(mom),
                              _ptr(cnt), _ptr(stats), int(n_threads))

@@ -63,6 +63,12 @@ constexpr double KAPPA = 4.0;
 // leaves the physics unchanged.
 int g_constant_majorant = 0;
 
+// Test knob that plants a known mistake in the majorant rule, so that the
+// tests can show the violation counter detects a wrong bound: 1 drops the
+// field-range term of the speed bound (as if the field did not change along
+// the flight), 2 takes nine tenths of every majorant.  0 = the rule as stated.
+int g_majorant_fault = 0;
+
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
 // easy as 1, 2, 3", SC'11): ten rounds of two 32x32->64 multiplies with the
@@ -234,11 +240,12 @@ double row_at(const Tables& T, const std::vector<double>& tab, int row, int i, d
 double majorant(const Tables& T, const Species& S, double s_ub0) {
   const double s_ub = s_ub0 * (1.0 + 0x1p-16);
   const double eps_ub = S.k_eps * s_ub * s_ub;
-  if (eps_ub >= T.node[T.n - 1]) return T.P[T.n - 1];
+  const double scale = g_majorant_fault == 2 ? 0.9 : 1.0;
+  if (eps_ub >= T.node[T.n - 1]) return scale * T.P[T.n - 1];
   int i;
   double f;
   locate(T, eps_ub, i, f);
-  return (1.0 - f) * T.P[i] + f * T.P[i + 1];
+  return scale * ((1.0 - f) * T.P[i] + f * T.P[i + 1]);
 }
 
 struct Particle {
@@ -261,9 +268,11 @@ struct Pending {
   double tb;
 };
 
-// Bound on |a| along the rest of a step and on how much a can change there.
+// Bound on |a| along the rest of a step and on how much a can change there;
+// local = taken from the particle's cell neighbourhood (not the global one).
 struct ABound {
   double a_abs, da;
+  bool local;
 };
 
 // Largest speed reachable within time h from velocity v under acceleration
@@ -275,12 +284,19 @@ double speed_bound(const double v[3], const double a0[3], double speed, const AB
     const double q = v[c] + a0[c] * h;
     w2 += q * q;
   }
-  const double s_dir = std::max(speed, std::sqrt(w2)) + b.da * h;
+  const double s_dir = std::max(speed, std::sqrt(w2)) + (g_majorant_fault == 1 ? 0.0 : b.da) * h;
   return std::min(speed + b.a_abs * h, s_dir);
 }
 
+// Event counters.  maj_viol counts flight segments whose end point has a
+// total collision rate above the majorant the segment was drawn with (the
+// null-collision method needs nu_hat >= nu_tot(eps) everywhere along the
+// flight, Sec. 2.1.1; a count above zero means the bound is wrong);
+// bound_local / bound_global count particle-steps whose field bound came from
+// the 4x4x4 cell neighbourhood or from the global maximum.
 struct Counters {
   int64_t trials = 0, null = 0, real[4] = {0, 0, 0, 0}, lost = 0, oot = 0, errors = 0;
+  int64_t maj_viol = 0, bound_local = 0, bound_global = 0;
   void add(const Counters& o) {
     trials += o.trials;
     null += o.null;
@@ -288,6 +304,9 @@ struct Counters {
     lost += o.lost;
     oot += o.oot;
     errors += o.errors;
+    maj_viol += o.maj_viol;
+    bound_local += o.bound_local;
+    bound_global += o.bound_global;
   }
 };
 
@@ -348,13 +367,13 @@ struct UniformAccel {
     out[1] = a[1];
     out[2] = a[2];
   }
-  ABound bound(const Particle&, double) const { return ABound{a_abs, 0.0}; }
+  ABound bound(const Particle&, double) const { return ABound{a_abs, 0.0, true}; }
 };
 
 ABound GridAccel::bound(const Particle& p, double t_rem) const {
   const double speed = std::sqrt(p.v[0] * p.v[0] + p.v[1] * p.v[1] + p.v[2] * p.v[2]);
   const double D = speed * t_rem + 0.5 * a_glob * t_rem * t_rem;
-  if (!(D < g->dx * (1.0 - 0x1p-10))) return ABound{a_glob, 2.0 * a_glob};
+  if (!(D < g->dx * (1.0 - 0x1p-10))) return ABound{a_glob, 2.0 * a_glob, false};
   const int n[3] = {g->nx, g->ny, g->nz};
   const double o[3] = {g->x0, g->y0, g->z0};
   int b[3];
@@ -365,7 +384,7 @@ ABound GridAccel::bound(const Particle& p, double t_rem) const {
     b[d] = std::min(std::max((int)std::floor(u), 0), n[d] - 1);
   }
   const size_t c = ((size_t)b[2] * g->ny + b[1]) * g->nx + b[0];
-  return ABound{std::fabs(qm) * (*Amax)[c], std::fabs(qm) * (*Dvar)[c]};
+  return ABound{std::fabs(qm) * (*Amax)[c], std::fabs(qm) * (*Dvar)[c], true};
 }
 
 // Advance one particle from time t0 to the end of the step (length dt):
@@ -379,6 +398,16 @@ int advance(const Tables& T, const Species& S, const Accel& accel, Particle& p, 
   accel(p.x, a);
   double t = t0;
   const ABound bnd = accel.bound(p, dt - t0);  // fixed for this item's step
+  (bnd.local ? cnt.bound_local : cnt.bound_global)++;
+  // The majorant must bound the total rate wherever the flight reaches; it is
+  // checked at the end point of every segment.
+  auto check_majorant = [&](double nu_hat) {
+    const double e = S.k_eps * (p.v[0] * p.v[0] + p.v[1] * p.v[1] + p.v[2] * p.v[2]);
+    int ii;
+    double ff;
+    locate(T, e, ii, ff);
+    if (row_at(T, T.C, T.nproc - 1, ii, ff) > nu_hat) cnt.maj_viol++;
+  };
   // Velocity Verlet over a sub-interval h (eq. 1-2).
   auto verlet = [&](double h) {
     for (int c = 0; c < 3; ++c) p.x[c] += p.v[c] * h + 0.5 * a[c] * h * h;
@@ -405,12 +434,14 @@ int advance(const Tables& T, const Species& S, const Accel& accel, Particle& p, 
     const double tau = nu_hat > 0 ? -std::log(unif(d.r[0])) / nu_hat : std::numeric_limits<double>::infinity();
     if (tau >= h) {  // no candidate collision within the horizon
       verlet(h);
+      check_majorant(nu_hat);
       if (!limited) return 0;
       t += h;
       continue;
     }
     verlet(tau);
     t += tau;
+    check_majorant(nu_hat);
     const double v2 = p.v[0] * p.v[0] + p.v[1] * p.v[1] + p.v[2] * p.v[2];
     const double eps = S.k_eps * v2;
     int i;
@@ -651,6 +682,7 @@ int update_weights(std::vector<Particle>& ps, int nx, int ny, int nz, double x0,
 extern "C" {
 
 void orc_set_constant_majorant(int on) { g_constant_majorant = on; }
+void orc_set_majorant_fault(int mode) { g_majorant_fault = mode; }
 
 void orc_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t n) {
   for (int64_t i = 0; i < n; ++i) {
@@ -834,9 +866,10 @@ int orc_pic_run(const orc_problem* pb, const orc_grid* g, double* x, double* y, 
   }
   *n_inout = (int64_t)cur.size();
   if (stats) {
-    const int64_t v[12] = {(int64_t)cur.size(), steps_done,    particle_steps, total.trials,
+    const int64_t v[15] = {(int64_t)cur.size(), steps_done,    particle_steps, total.trials,
                            total.null,          total.real[0], total.real[1],  total.real[2],
-                           total.real[3],       total.lost,    total.oot,      total.errors};
+                           total.real[3],       total.lost,    total.oot,      total.errors,
+                           total.maj_viol,      total.bound_local, total.bound_global};
     std::memcpy(stats, v, sizeof(v));
   }
   return rc;
@@ -1027,8 +1060,9 @@ int orc_swarm_run(const orc_problem* pb, int n_swarms, const double* EN_Td, cons
     if (err) break;
   }
   if (stats) {
-    const int64_t v[12] = {0,           n_steps,       grand_psteps,  grand.trials,  grand.null, grand.real[0],
-                           grand.real[1], grand.real[2], grand.real[3], grand.lost, grand.oot,  grand.errors};
+    const int64_t v[15] = {0,           n_steps,       grand_psteps,  grand.trials,  grand.null, grand.real[0],
+                           grand.real[1], grand.real[2], grand.real[3], grand.lost, grand.oot,  grand.errors,
+                           grand.maj_viol, grand.bound_local, grand.bound_global};
     std::memcpy(stats, v, sizeof(v));
   }
   return err;

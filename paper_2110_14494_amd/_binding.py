@@ -40,7 +40,7 @@ class pcmcc_stats(C.Structure):
                 ("launch_block", C.c_int32), ("launch_grid", C.c_int32), ("weight_updates", C.c_int64),
                 ("merged_pairs", C.c_int64), ("splits", C.c_int64), ("weight_ms", C.c_double),
                 ("field_ms", C.c_double), ("mg_cycles", C.c_int64), ("photons", C.c_int64),
-                ("photoelectrons", C.c_int64), ("photo_ms", C.c_double)]
+                ("photoelectrons", C.c_int64), ("photo_ms", C.c_double), ("majorant_violations", C.c_uint64)]
 
     def as_dict(self) -> dict:
         r = list(self.real_collisions)
@@ -52,7 +52,8 @@ class pcmcc_stats(C.Structure):
                 "launch_block": self.launch_block, "launch_grid": self.launch_grid,
                 "weight_updates": self.weight_updates, "merged_pairs": self.merged_pairs, "splits": self.splits,
                 "weight_ms": self.weight_ms, "field_ms": self.field_ms, "mg_cycles": self.mg_cycles,
-                "photons": self.photons, "photoelectrons": self.photoelectrons, "photo_ms": self.photo_ms}
+                "photons": self.photons, "photoelectrons": self.photoelectrons, "photo_ms": self.photo_ms,
+                "majorant_violations": self.majorant_violations}
 
 
 SWARM_QUANTITIES = ("W_flux", "W_bulk", "DL_flux", "DL_bulk", "DT_flux", "DT_bulk", "nu_ion", "nu_att",

@@ -474,6 +474,7 @@ int ensure_weights(pcmcc_ctx* c, uint64_t n, size_t ncell) {
     dfree(c->wt.key2);
     dfree(c->wt.pos);
     dfree(c->wt.cnt);
+    dfree(c->wt.counters);
     dfree(c->wt.temp);
     c->wt = WeightWork{};
     c->wt_n = 0;
@@ -889,6 +890,7 @@ static int push_impl(pcmcc_ctx* c, const pcmcc_particles* p, const pcmcc_grid* f
     stats->lost = h.tot[C_LOST];
     stats->out_of_table = h.tot[C_OOT];
     stats->errors = h.tot[C_ERR];
+    stats->majorant_violations = h.tot[C_MAJ];
     stats->weight_updates = (int64_t)w_updates;
     stats->merged_pairs = (int64_t)w_pairs;
     stats->splits = (int64_t)w_splits;
@@ -1137,6 +1139,7 @@ int pcmcc_swarm_batch(pcmcc_ctx* c, int n_swarms, const double* EN_Td, const int
     for (int k = 0; k < 4; ++k) stats->real_collisions[k] = hc.tot[C_EL + k];
     stats->out_of_table = hc.tot[C_OOT];
     stats->errors = hc.tot[C_ERR];
+    stats->majorant_violations = hc.tot[C_MAJ];
     stats->step_kernel_ms = ms;
     stats->launch_block = block;
     stats->launch_grid = grid;
@@ -1959,6 +1962,7 @@ int pcmcc_streamer_steps(pcmcc_ctx* c, const pcmcc_particles* p, const pcmcc_gri
     tot.lost += st.lost;
     tot.out_of_table += st.out_of_table;
     tot.errors += st.errors;
+    tot.majorant_violations += st.majorant_violations;
     tot.step_kernel_ms += st.step_kernel_ms;
     tot.launch_block = st.launch_block;
     tot.launch_grid = st.launch_grid;

@@ -350,6 +350,12 @@ __device__ __forceinline__ int flight_complete(Flight& f, const double3 an, cons
   const float yv = unif(f.r1) * f.nu_hat;
   float cum[kMaxProc];
   cum_rates(T, i, fr, cum, tc.row);
+  // the total rate (the largest cumulative entry; padding entries are zero)
+  // must not exceed the majorant
+  float tot = cum[0];
+#pragma unroll
+  for (int kk = 1; kk < kMaxProc; ++kk) tot = fmaxf(tot, cum[kk]);
+  cnt.v[C_MAJ] += tot > f.nu_hat;
   const int k = pick_process(cum, yv);
   if (k < 0 || eps < (double)T.thr[k]) {
     cnt.v[C_NULL]++;
@@ -455,7 +461,10 @@ __device__ __forceinline__ void fly_all(uint64_t n, unsigned long long* take, do
         }
       }
     }
-    if (__ballot(f.mode != FM_IDLE) == 0) break;
+    // Leave only when the work counter is exhausted: a refill may leave every
+    // lane idle (a swarm's population control drops the electrons it loads),
+    // and the next iteration then refills again.
+    if (dry && __ballot(f.mode != FM_IDLE) == 0) break;
     bool born = false;
     if (f.mode == FM_FLY || f.mode == FM_NEW) {
       typename Field::Where where;

@@ -29,7 +29,10 @@ struct PendSoa {
 };
 
 // Per-step event counters.
-enum CntIdx { C_TRIALS, C_NULL, C_EL, C_EXC, C_ION, C_ATT, C_LOST, C_OOT, C_ERR, NCNT };
+// C_MAJ: candidate collisions at an energy whose total rate exceeds the
+// majorant the flight segment was drawn with (the null-collision method
+// needs nu_hat >= nu_tot; any count means the bound is wrong).
+enum CntIdx { C_TRIALS, C_NULL, C_EL, C_EXC, C_ION, C_ATT, C_LOST, C_OOT, C_ERR, C_MAJ, NCNT };
 
 enum Overflow : unsigned { OVF_CAPACITY = 1u, OVF_LIMIT = 2u };
 

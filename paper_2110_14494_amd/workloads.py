@@ -148,6 +148,32 @@ def stress_config(background: float = 1.5e6, n: int = 2 ** 27, n_steps: int = 10
     return cfg
 
 
+def tip_block_config(m: int = 64, n: int = 4096) -> dict:
+    """The streamer stage's tip field (256^3 cells over 10 mm) cut to the m^3
+    block of its cells centred on the tip, with the stage's first n electrons
+    (which start within a few sigma of the tip, inside the block)."""
+    cfg = streamer_config(n=n)
+    g = cfg["grid"]
+    dx = g["dx"]
+    ci = int(round(5e-3 / dx)) - m // 2
+    ck = int(round(8e-3 / dx)) - m // 2
+    E = np.ascontiguousarray(g["E"][ck:ck + m, ci:ci + m, ci:ci + m])
+    cfg["grid"] = {"E": E, "x0": ci * dx, "y0": ci * dx, "z0": ck * dx, "dx": dx}
+    cfg["name"] = f"tip-block-{m}c-n{n}"
+    return cfg
+
+
+def steep_field_grid(n: int = 48, dx: float = 4e-6) -> dict:
+    """A field with steep gradients on cells of 4 um: E_z rises from 1e6 to
+    6e7 V/m within a few cells around z = 0 (tanh profile of width 1.5 cells)
+    and E_x varies as 2e7 sin(2 pi y / L) V/m; the cube is centred on 0."""
+    zc = (np.arange(n) + 0.5) * dx - n * dx / 2
+    E4 = np.zeros((n, n, n, 4), np.float32)
+    E4[..., 2] = (1e6 + 5.9e7 * 0.5 * (1 + np.tanh(zc / (1.5 * dx))))[:, None, None]
+    E4[..., 0] = (2e7 * np.sin(2 * np.pi * (np.arange(n) + 0.5) / n))[None, :, None]
+    return {"E": E4, "x0": -n * dx / 2, "y0": -n * dx / 2, "z0": -n * dx / 2, "dx": dx}
+
+
 def swarm_batch_config(n_swarms: int = 256, en_lo: float = 10.0, en_hi: float = 1000.0, seed: int = 1,
                        log2_lo: float = 12.0, log2_hi: float = 17.0, scale: float = 1.0) -> dict:
     """256 swarms at E/N log-spaced over 10-1000 Td, sizes log-uniform in

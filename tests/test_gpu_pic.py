@@ -75,6 +75,9 @@ def run_both(P, cfg, n_steps, seed=None, capacity=None, step0=0):
     orc_rc, orc_out, orc_st = oracle.pic_run(cfg["species"], cfg["tables"], cfg["grid"], parts, cfg["dt"],
                                              n_steps, seed, step0=step0, capacity=cap)
     ctx.close()
+    # the null-collision majorant bounded the total rate at every candidate
+    # (device) and at every segment end (oracle)
+    assert st["majorant_violations"] == 0 and orc_st["majorant_violations"] == 0
     return (rc, gpu, st), (orc_rc, orc_out, orc_st)
 
 
@@ -289,6 +292,7 @@ def test_full_size_streamer_sampled_lineages(pic):
     print(f"[gpu] full-size streamer n={n} steps={steps}", flush=True)
     rc, st = ctx.push_collide_deposit(dp, dg, cfg["dt"], steps, cfg["seed"], rho=rho)
     assert rc == 0 and st["steps_done"] == steps
+    assert st["majorant_violations"] == 0
     gpu = dp.to_numpy()
     total = int(rho.sum().item())
     ctx.close()
@@ -317,6 +321,7 @@ def test_full_size_streamer_timed_call_conserves_electrons(pic):
     print(f"[gpu] full-size streamer timed call n0={n0} steps=25", flush=True)
     rc, st = ctx.push_collide_deposit(dp, dg, cfg["dt"], 25, cfg["seed"], check=False)
     assert rc == 0 and st["steps_done"] == 25
+    assert st["majorant_violations"] == 0 and st["trials"] > 1e10
     n = st["n"]
     assert n == n0 + st["ionization"] - st["attachment"] - st["lost"]
     assert n > 500_000_000
@@ -341,6 +346,7 @@ def test_stress_stage_sampled_lineages(pic):
     print(f"[gpu] stress stage n={n} steps={steps}", flush=True)
     rc, st = ctx.push_collide_deposit(dp, dg, cfg["dt"], steps, cfg["seed"], rho=rho)
     assert rc == 0 and st["steps_done"] == steps
+    assert st["majorant_violations"] == 0
     gpu_id = dp.t["id"][:st["n"]].cpu().numpy().view(np.uint64)  # ids are stored as int64 bit patterns
     # exact totals near 2^63 units: int64 sums of chunks, added as Python ints
     chunked = lambda t: sum(int(c.sum().item()) for c in t.reshape(-1).split(1 << 22))
@@ -469,3 +475,72 @@ def test_error_paths(pic):
     rc, _ = ctx.push_collide_deposit(dp, dg, 1e-12, 1, 0, check=False)
     assert rc == B.PCMCC_EINVAL and "capacity" in ctx.last_error()
     ctx.close()
+
+
+# --- process selection and the majorant on the device ---------------------------
+
+CHI2_999 = {2: 13.816, 3: 16.266}
+
+
+def _pearson(counts, probs):
+    counts = np.asarray(counts, float)
+    expect = counts.sum() * np.asarray(probs, float)
+    return float(((counts - expect) ** 2 / expect).sum())
+
+
+def test_process_selection_frequencies(pic):
+    # Four processes of every kind at constant frequencies, no field: each
+    # candidate picks process k with probability nu_k / nu_tot (Pearson
+    # chi-square, 3 degrees of freedom), as the oracle's pin states.
+    rates = {W.ELASTIC: 4e12, W.EXCITATION: 2e12, W.IONIZATION: 1e12, W.ATTACHMENT: 1e12}
+    n = 200_000
+    p = W.uniform_box_particles(n, -1e-4, 1e-4, 1e6, seed=31)
+    ctx = _ctx(pic, W.electron_species(target_mass=1e6), W.rate_tables(rates))
+    dp = pic.Particles.from_numpy(p, 4 * n)
+    dg = pic.DeviceGrid(W.uniform_grid(8, 1e-3, (0.0, 0.0, 0.0), x0=-4e-3))
+    rc, st = ctx.push_collide_deposit(dp, dg, 0.4e-12, 8, 12, check=False)
+    ctx.close()
+    assert rc == 0 and st["null"] == 0 and st["majorant_violations"] == 0
+    counts = [st["elastic"], st["excitation"], st["ionization"], st["attachment"]]
+    assert _pearson(counts, np.array([4.0, 2.0, 1.0, 1.0]) / 8.0) < CHI2_999[3], counts
+
+
+def test_real_null_split_at_frozen_energy(pic):
+    # nu_el = 1e12, nu_exc = 3e12 below 10 eV and 0.5e12 above (given as
+    # frequencies), energy-preserving scattering, no field: at a node above
+    # 10 eV a candidate is null / elastic / excitation with probabilities
+    # 2.5 / 1 / 0.5 out of 4 (the prefix maximum of the total is 4e12).
+    n_e = 64
+    node = W.node_energies(n_e, 1e-3, 1e4)
+    tab = {"eps_min": 1e-3, "eps_max": 1e4, "kind": [W.ELASTIC, W.EXCITATION], "threshold": [0.0, 0.0],
+           "sigma": np.stack([np.full(n_e, 1e12), np.where(node < 10.0, 3e12, 0.5e12)]), "flags": 2}
+    eps0 = node[int(np.searchsorted(node, 100.0))]
+    n = 200_000
+    p = W.uniform_box_particles(n, -1e-4, 1e-4, math.sqrt(2 * QE * eps0 / ME), seed=33)
+    ctx = _ctx(pic, W.electron_species(target_mass=1e6), tab)
+    dp = pic.Particles.from_numpy(p, 2 * n)
+    dg = pic.DeviceGrid(W.uniform_grid(8, 1e-3, (0.0, 0.0, 0.0), x0=-4e-3))
+    rc, st = ctx.push_collide_deposit(dp, dg, 0.5e-12, 6, 13, check=False)
+    g = dp.to_numpy()
+    ctx.close()
+    assert rc == 0 and st["majorant_violations"] == 0
+    cand = st["trials"] - st["particle_steps"]
+    counts = [st["null"], st["elastic"], st["excitation"]]
+    assert sum(counts) == cand
+    assert _pearson(counts, np.array([2.5, 1.0, 0.5]) / 4.0) < CHI2_999[2], counts
+    e = 0.5 * ME * (g["vx"].astype(np.float64) ** 2 + g["vy"] ** 2 + g["vz"] ** 2) / QE
+    assert np.allclose(e, eps0, rtol=1e-5)
+
+
+def test_majorant_holds_in_a_steep_field(pic):
+    # A field with steep gradients on 4 um cells (E_z from 1e6 to 6e7 V/m over
+    # a few cells, E_x varying along y), where both the local and the global
+    # field bound are taken: the device majorant bounds the total rate at
+    # every candidate, and the result matches the oracle by lineage.
+    cfg = {"name": "steep-field", "species": W.electron_species(), "tables": W.air_like_tables(),
+           "grid": W.steep_field_grid(), "parts": W.gaussian_particles(50_000, (0.0, 0.0, 0.0), 15e-6, seed=21),
+           "dt": 1e-12, "seed": 1}
+    (rc, g, st), (orc, o, ost) = run_both(pic, cfg, 4, capacity=2 ** 20)
+    assert rc == 0 and orc == 0
+    assert ost["bound_local"] > 1000 and ost["bound_global"] > 1000
+    _assert_parity(g, o, 4e-6, ost["trials"])

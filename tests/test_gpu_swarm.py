@@ -109,3 +109,31 @@ def test_swarm_capacity_error(ctx):
     rc, *_ = pic.swarm_batch(ctx, [900.0], [500], 1e-12, 400, 1, sample_every=10, window_start_s=0.0,
                              n_batches=10, cap_factor=4, population_control=False, check=False)
     assert rc == -2
+
+
+def test_population_control_with_deep_culls_keeps_every_electron(ctx):
+    # Ionization only at a constant frequency with a step of three e-foldings:
+    # each swarm grows about twentyfold per step, so population control keeps
+    # every electron with probability 2^-4 or 2^-5 and whole 64-electron
+    # refills of a wave are culled.  The live counts (and weight scales) of
+    # every sample must match the oracle, which applies the same draws; a wave
+    # that left its work early would lose the rest of its chunk.
+    from paper_2110_14494_amd import pic
+    sp, tab = W.electron_species(), W.rate_tables({W.IONIZATION: 1e12})
+    EN_ = np.array([1.0, 5.0, 20.0, 50.0, 100.0, 200.0, 400.0, 800.0])
+    N0_ = np.array([2000, 3000, 1500, 2500, 4000, 1000, 3500, 2200], dtype=np.int32)
+    c = pic.Context(0)
+    c.setup(sp, tab)
+    kw = dict(dt=3e-12, n_steps=8, seed=23, sample_every=1)
+    print(f"[gpu] swarm_batch deep culls S={len(EN_)} steps={kw['n_steps']}", flush=True)
+    rc, vals, errs, st, mom, cnt = pic.swarm_batch(c, EN_, N0_, kw["dt"], kw["n_steps"], kw["seed"],
+                                                   sample_every=1, window_start_s=0.0, n_batches=2,
+                                                   cap_factor=64, raw=True)
+    c.close()
+    assert rc == 0 and st["majorant_violations"] == 0
+    orc, om, oc, ost = oracle.swarm_run(sp, tab, EN_, N0_, kw["dt"], kw["n_steps"], kw["seed"], 1, cap_factor=64)
+    assert orc == 0
+    assert np.all(np.diff(oc[:, :, 1], axis=1) >= 4)  # each control kept 2^-4 or less
+    assert np.array_equal(cnt[:, :, 1], oc[:, :, 1])
+    # a rare single-precision decision flip may change a lineage by one or two
+    assert np.max(np.abs(cnt[:, :, 0] - oc[:, :, 0])) <= 2, (cnt[:, :, 0], oc[:, :, 0])
