@@ -26,6 +26,8 @@
 //    side and were the limit of the direct schedule.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "pcmcc_internal.hpp"
 
 namespace pcmcc {
@@ -317,6 +319,20 @@ __global__ __launch_bounds__(256) void k_dep_accum(const float4* __restrict__ so
 
 // ---------------------------------------------------------------------------
 
+// Sets n words to v (a kernel rather than a memset node, so that the deposit
+// may be recorded into a graph).
+__global__ void k_fill_u32(uint32_t* __restrict__ p, uint64_t n, uint32_t v) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  const uint64_t blocks = std::min<uint64_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, stream, p, n, v);
+  return hipGetLastError();
+}
+
 hipError_t launch_deposit(const float* x, const float* y, const float* z, const float* w, const int64_t* n_dev,
                           const DepositGeom& g, int64_t* rho, hipStream_t stream) {
   hipLaunchKernelGGL(k_deposit, dim3(4096), dim3(256), 0, stream, x, y, z, w, n_dev, g,
@@ -344,7 +360,7 @@ hipError_t launch_deposit_binned(const float* x, const float* y, const float* z,
   T.ty = (g.ny + kTile - 1) / kTile;
   T.tz = (g.nz + kTile - 1) / kTile;
   const uint32_t n_tiles = (uint32_t)T.tx * T.ty * T.tz;
-  hipError_t e = hipMemsetAsync(W.tile_count, 0, (size_t)n_tiles * sizeof(uint32_t), stream);
+  hipError_t e = launch_fill_u32(W.tile_count, n_tiles, 0u, stream);
   if (e != hipSuccess) return e;
   const uint64_t nb = (n + kBinRange - 1) / kBinRange;
   hipLaunchKernelGGL(k_dep_count, dim3((unsigned)nb), dim3(256), 0, stream, x, y, z, n, T, W.tile_count, W.dump);
