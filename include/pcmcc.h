@@ -516,6 +516,17 @@ int pcmcc_fluid_steps(pcmcc_ctx* ctx, const pcmcc_grid* applied, double* n_e, do
 int pcmcc_deposit(pcmcc_ctx* ctx, const float* x, const float* y, const float* z, const float* w,
                   const int64_t* n_dev, const pcmcc_grid* grid, int64_t* rho);
 
+/* Allocation-free variant of pcmcc_deposit, for callers that cannot
+ * allocate device memory (code being captured into a graph, tight serving
+ * loops, harnesses that forbid allocation): the same arguments, result and
+ * errors, but the call allocates nothing.  Its scratch is one file-scope
+ * device array per GPU (about 50 MiB, held until the process ends) that every
+ * call on that GPU shares, so calls that overlap on one GPU race.  Limits:
+ * at most 2^21 particles and 2^18 tiles of 8^3 cells (a 512^3 grid); beyond
+ * them PCMCC_EINVAL and rho is untouched.  Synchronises the stream. */
+int pcmcc_deposit_noalloc(pcmcc_ctx* ctx, const float* x, const float* y, const float* z, const float* w,
+                          const int64_t* n_dev, const pcmcc_grid* grid, int64_t* rho);
+
 /* Philox4x32-10 (Salmon et al., SC'11) on n device counters ctr[n][4] with
  * key (seed low word, seed high word); out[n][4] device.  Self-test of the
  * generator every kernel uses. */

@@ -131,6 +131,7 @@ def lib() -> C.CDLL:
             "pcmcc_push_collide_deposit": ([vp, C.POINTER(pcmcc_particles), C.POINTER(pcmcc_grid), C.c_double,
                                             C.c_int, u64, u64, vp, C.POINTER(pcmcc_stats)], C.c_int),
             "pcmcc_deposit": ([vp, vp, vp, vp, vp, vp, C.POINTER(pcmcc_grid), vp], C.c_int),
+            "pcmcc_deposit_noalloc": ([vp, vp, vp, vp, vp, vp, C.POINTER(pcmcc_grid), vp], C.c_int),
             "pcmcc_philox4x32_10": ([vp, i64, vp, u64, vp], C.c_int),
             "pcmcc_tables_lookup": ([vp, i64, vp, vp, vp, vp], C.c_int),
             "pcmcc_mlp_grad": ([vp, vp, i64, vp, vp, vp, vp, C.POINTER(C.c_double)], C.c_int),

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpcmcc.so")
 SOURCES = ["pcmcc_kernels.hip", "pcmcc_deposit.hip", "pcmcc_weights.hip", "pcmcc_swarm.hip", "pcmcc_mlp.hip",
-           "pcmcc_field.hip", "pcmcc_fluid.hip", "pcmcc_photo.hip", "pcmcc_runtime.hip", "pcmcc_api.hip",
+           "pcmcc_field.hip", "pcmcc_fluid.hip", "pcmcc_photo.hip", "pcmcc_runtime.hip", "pcmcc_api.hip", "pcmcc_noalloc.hip",
            "pcmcc_api_swarm.hip", "pcmcc_api_mlp.hip", "pcmcc_api_field.hip", "pcmcc_api_fluid.hip"]
 ARCH = os.environ.get("PCMCC_OFFLOAD_ARCH", "gfx950")
 

@@ -32,6 +32,7 @@ int pcmcc_create(pcmcc_ctx** out, int device, void* hip_stream) {
     return fail(nullptr, PCMCC_EHIP, "hipGetDeviceProperties: %s", hipGetErrorString(e));
   }
   c->num_cu = prop.multiProcessorCount;
+  noalloc_setup(device);
   for (auto& ev : c->ev) {
     if (hipEventCreate(&ev) != hipSuccess) {
       pcmcc_destroy(c);

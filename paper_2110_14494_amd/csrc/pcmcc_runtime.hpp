@@ -190,6 +190,9 @@ int photoionize(pcmcc_ctx* c, const pcmcc_grid* g, const float* ex, const float*
                 int64_t* n_pos, int64_t* photons, int64_t* absorbed, double* ms);
 bool valid_photo(const pcmcc_photo_opts* o);
 int solve_start(pcmcc_ctx* c, double* phi, size_t ncell, int n_sol, double r);
+// Looks up this device's allocation-free deposit scratch (once per device;
+// the device must be current).
+void noalloc_setup(int device);
 
 }  // namespace pcmcc_rt
 

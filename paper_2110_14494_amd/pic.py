@@ -158,11 +158,16 @@ class Context:
             B.check(rc, self.h)
         return rc, {"merged_pairs": mp.value, "splits": sp.value}
 
-    def deposit(self, parts: Particles, grid: DeviceGrid, rho: torch.Tensor, check: bool = True) -> int:
+    def deposit(self, parts: Particles, grid: DeviceGrid, rho: torch.Tensor, check: bool = True,
+                no_alloc: bool = False) -> int:
+        """Adds the particles' charge to rho (pcmcc_deposit, or with no_alloc
+        pcmcc_deposit_noalloc, which allocates nothing and takes at most 2^21
+        particles)."""
         t = parts.t
         gs = grid.struct()
-        rc = B.lib().pcmcc_deposit(self.h, t["x"].data_ptr(), t["y"].data_ptr(), t["z"].data_ptr(),
-                                   t["w"].data_ptr(), parts.n_dev.data_ptr(), C.byref(gs), rho.data_ptr())
+        fn = B.lib().pcmcc_deposit_noalloc if no_alloc else B.lib().pcmcc_deposit
+        rc = fn(self.h, t["x"].data_ptr(), t["y"].data_ptr(), t["z"].data_ptr(), t["w"].data_ptr(),
+                parts.n_dev.data_ptr(), C.byref(gs), rho.data_ptr())
         if check:
             B.check(rc, self.h)
         return rc
