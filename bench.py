@@ -1,26 +1,29 @@
 """Benchmark of the PIC-MCC electron hot path on one MI355X.
 
-Headline (one bench step = one pass of the hot path over the streamer-scale
-workload): 2^24 electrons (weights log-uniform in 1-64) in a 256^3 tip field
-over a 10 mm cube (1.5e6 V/m background plus a 1.5e7 V/m Gaussian tip,
-sigma 200 um, at z = 8 mm), advanced by push + null-collision MCC + newborn
-append + compaction for as many 2 ps steps as a capacity of 32 x the start
-count holds, then deposited (int64 fixed-point CIC).  Ionization in the tip
-field grows the population explosively, so the number of committed steps is
-found once during warmup and every timed call runs exactly that many.
-Inputs are resident in HBM before the timed region; each step restores the
-starting particles with one device copy (inside the timed region).
-value = particle-steps / second of the whole timed region.
+Headline (one bench step = one pass of the hot path over the large stress
+stage): 2^27 electrons (weights log-uniform in 1-64, positions Gaussian of
+sigma 300 um around the tip) on a 512^3 grid of 20 um cells carrying the tip
+field (1.5e6 V/m background plus a 1.5e7 V/m Gaussian of sigma 200 um at
+(0.5, 0.5, 0.8) of the cube), advanced by push + null-collision MCC + newborn
+append + compaction for as many 1 ps steps as a capacity of 8 x the start
+count (2^30) holds, then deposited (int64 fixed-point CIC).  Ionization grows
+the population, so the number of committed steps is found once during warmup
+and every timed call runs exactly that many.  Inputs are resident in HBM
+before the timed region; each step restores the starting particles with one
+device copy (inside the timed region).  value = particle-steps / second of
+the whole timed region.
 
 Also reported: the roofline of the step kernel (HIP events), the CPU oracle
-on a bounded sample, the streamer stage under super-particle weight control
-(N_ppc = 75, update when the count has grown by 1.25x) run until its 200
-steps, the capacity or the deposit's fixed-point range ends it (the fixed
-tip field grows the electron number without bound), the same stage with its
-own space-charge field (multigrid Poisson every step, immobile ions, the
-adaptive time step), and the coefficient path: batched swarms against the
-plain per-E/N swarm, surrogate training, held-out fallback and BF16
-inference on 1e8 reduced fields.  Prints one JSON line.
+on bounded samples (one core and all cores), the stress stage at the other
+two background fields (1.75e6, 2.0e6 V/m), the streamer-scale stage (2^24
+electrons on 256^3 cells, 2 ps steps), the plain swarm (1e4 electrons, 32^3
+cells, 1000 steps) with its oracle, the streamer stage under super-particle
+weight control, the same stage with its own space-charge field (multigrid
+Poisson every step, immobile ions, the adaptive time step, photoionization),
+the multigrid solve, the fluid model, and the coefficient path: batched
+swarms against the plain per-E/N swarm, surrogate training, held-out
+fallback, served error and BF16 inference on 1e8 reduced fields.  Prints one
+JSON line.
 """
 from __future__ import annotations
 
@@ -64,15 +67,19 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["streamer", "stress", "plain"], default="streamer")
+    ap.add_argument("--workload", choices=["streamer", "stress", "plain"], default="stress")
     ap.add_argument("--n", type=int, default=None, help="override the start count")
     ap.add_argument("--cap-factor", type=int, default=None,
                     help="capacity / start count (default 32 for streamer and plain, 8 for stress)")
     ap.add_argument("--background", type=float, default=None, help="background field of the stress stage (V/m)")
     ap.add_argument("--max-steps", type=int, default=None, help="cap the committed steps (profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=2 ** 23)
+    ap.add_argument("--cpu-sample", type=int, default=2 ** 23, help="oracle sample on all cores (electrons)")
+    ap.add_argument("--cpu-sample-1core", type=int, default=2 ** 21, help="oracle sample on one core (electrons)")
     ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--no-backgrounds", action="store_true", help="skip the stress stage at 1.75 and 2.0 MV/m")
+    ap.add_argument("--no-streamer", action="store_true", help="skip the streamer-stage leg")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain-swarm leg")
     ap.add_argument("--no-coef", action="store_true", help="skip the swarm / surrogate leg")
     ap.add_argument("--no-weights", action="store_true", help="skip the weight-controlled streamer run")
     ap.add_argument("--n-ppc", type=float, default=75.0, help="particles per cell of the weight control")
@@ -118,10 +125,10 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per particle-step and VALU utilisation of the step kernel from
-    the committed rocprofv3 counter summary, if it was taken on the current
-    kernel source."""
+def measured_traffic(workload: str):
+    """HBM bytes per particle-step and VALU utilisation of the step kernel on
+    `workload` from the committed rocprofv3 counter summary, if it was taken
+    on the current kernel source."""
     p = os.path.join(ROOT, "profiles", "k_pic_steps_traffic.json")
     try:
         d = json.load(open(p))
@@ -129,7 +136,7 @@ def measured_traffic():
         return None
     if d.get("kernel_source_sha") != source_hash():
         return None
-    return d
+    return d.get("workloads", {}).get(workload)
 
 
 def make_cfg(a):
@@ -141,32 +148,70 @@ def make_cfg(a):
     return W.plain_swarm_config(n=a.n or 10_000)
 
 
-def cpu_baseline(cfg, sample: int, steps: int) -> dict:
-    import oracle
+def oracle_sample(cfg, n: int, margin_sigmas: float = 4.5, sigma: float = 300e-6):
+    """The first n electrons of a workload and the field they need: on the
+    large grids, the cube of cells around the sample's mean position that
+    holds +-4.5 sigma of the Gaussian start positions (an electron moves at
+    most a few um in 10 steps, so the cut changes nothing for all but the
+    rare electron beyond that margin, which leaves the cube and is counted as
+    lost); small grids are used whole."""
     p = cfg["parts"]
-    n = min(sample, p["x"].size)
+    n = min(n, p["x"].size)
     sub = {k: v[:n] for k, v in p.items()}
+    g = cfg["grid"]
+    E = g["E"]
+    nz = E.shape[0]
+    dx = float(g["dx"])
+    m = int(math.ceil(2 * margin_sigmas * sigma / dx / 8.0)) * 8
+    if m >= nz:
+        return sub, g, f"whole {nz}^3 grid"
+    centre = [float(np.mean(sub[k].astype(np.float64))) for k in ("x", "y", "z")]
+    org = [float(g[k]) for k in ("x0", "y0", "z0")]
+    i0 = [min(max(int(round((c - o) / dx)) - m // 2, 0), nz - m) for c, o in zip(centre, org)]
+    blk = {"E": np.ascontiguousarray(E[i0[2]:i0[2] + m, i0[1]:i0[1] + m, i0[0]:i0[0] + m]),
+           "x0": org[0] + i0[0] * dx, "y0": org[1] + i0[1] * dx, "z0": org[2] + i0[2] * dx, "dx": dx}
+    return sub, blk, f"the {m}^3 cells around the sample ({2 * margin_sigmas:g} sigma of the start positions)"
+
+
+def cpu_run(cfg, sample: int, steps: int, threads: int) -> dict:
+    import oracle
+    sub, grid, where = oracle_sample(cfg, sample)
+    n = sub["x"].size
     t0 = time.perf_counter()
-    rc, out, st = oracle.pic_run(cfg["species"], cfg["tables"], cfg["grid"], sub, cfg["dt"], steps, cfg["seed"],
-                                 capacity=16 * n)
+    rc, out, st = oracle.pic_run(cfg["species"], cfg["tables"], grid, sub, cfg["dt"], steps, cfg["seed"],
+                                 capacity=4 * n + 4096, n_threads=threads)
     el = time.perf_counter() - t0
-    # OpenMP threads the oracle ran with: OMP_NUM_THREADS, else the CPUs this
-    # process may run on
+    return {"value": st["particle_steps"] / el, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
+            "s": el, "sample": f"first {n} electrons of {cfg['name']}, {st['steps_done']} steps of {cfg['dt']:.0e} s "
+                                f"on {where} ({st['particle_steps']} particle-steps in {el:.1f} s including the "
+                                f"table and field-bound setup; {threads} OpenMP thread(s))"}
+
+
+def host_cores() -> int:
+    """Cores this process may use: OMP_NUM_THREADS if set, else the CPUs of
+    its affinity mask."""
     env = os.environ.get("OMP_NUM_THREADS", "")
-    threads = int(env) if env.isdigit() and int(env) > 0 else len(os.sched_getaffinity(0))
-    return {"value": st["particle_steps"] / el, "unit": "particle-steps/s", "cores": threads,
-            "kind": "oracle", "cpu": cpu_model(),
-            "sample": f"first {n} electrons of the workload, {st['steps_done']} steps of {cfg['dt']:.0e} s "
-                      f"({st['particle_steps']} particle-steps in {el:.1f} s including table and field-bound "
-                      f"setup; OpenMP over particles)"}
+    return int(env) if env.isdigit() and int(env) > 0 else len(os.sched_getaffinity(0))
 
 
-def pic_leg(a, ctx, pic):
+def cpu_baseline(cfg, sample_all: int, sample_one: int, steps: int) -> dict:
+    """The oracle on all host cores (the reported figure) and on one core."""
+    cores = host_cores()
+    allc = cpu_run(cfg, sample_all, steps, cores)
+    one = cpu_run(cfg, sample_one, steps, 1)
+    allc.update(nproc=os.cpu_count(), cpu=cpu_model(), one_core=one)
+    return allc
+
+
+def pic_run_leg(pic, cfg, cap_factor: int, steps: int, warmup: int, max_steps=None, label: str = "") -> dict:
+    """Times the step loop on one workload in its own context: a probe call
+    finds how many steps fit the capacity, then `steps` timed bench steps of
+    restore + call + deposit.  Frees its device memory before returning."""
     import torch
-    cfg = make_cfg(a)
     n0 = cfg["parts"]["x"].size
-    cap = (a.cap_factor or (8 if a.workload == "stress" else 32)) * n0
-    log(f"workload {cfg['name']} n0={n0} cap={cap}")
+    cap = cap_factor * n0
+    log(f"{label}workload {cfg['name']} n0={n0} cap={cap}")
+    ctx = pic.Context(0)
     ctx.setup(cfg["species"], cfg["tables"])
     pristine = pic.Particles.from_numpy(cfg["parts"], n0)
     work = pic.Particles(cap)
@@ -181,22 +226,23 @@ def pic_leg(a, ctx, pic):
 
     reset()
     rc, st = ctx.push_collide_deposit(work, grid, cfg["dt"], cfg["n_steps"], cfg["seed"], check=False)
-    n_fit = st["steps_done"] if a.max_steps is None else min(st["steps_done"], a.max_steps)
-    log(f"probe rc={rc} steps_done={st['steps_done']} using {n_fit}")
-    for _ in range(a.warmup):
+    n_fit = st["steps_done"] if max_steps is None else min(st["steps_done"], max_steps)
+    log(f"{label}probe rc={rc} steps_done={st['steps_done']} using {n_fit}")
+    for _ in range(warmup):
         reset()
         ctx.push_collide_deposit(work, grid, cfg["dt"], n_fit, cfg["seed"], rho=rho)
     torch.cuda.synchronize()
     stats = []
     t0 = time.perf_counter()
-    for k in range(a.steps):
+    for k in range(steps):
         reset()
         rc, st = ctx.push_collide_deposit(work, grid, cfg["dt"], n_fit, cfg["seed"], rho=rho)
         stats.append(st)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     for k, s in enumerate(stats):
-        log(f"step {k}: kernel {s['step_kernel_ms']:.1f} ms, deposit {s['deposit_kernel_ms']:.1f} ms, n={s['n']}")
+        log(f"{label}step {k}: kernel {s['step_kernel_ms']:.1f} ms, deposit {s['deposit_kernel_ms']:.1f} ms, "
+            f"n={s['n']}")
     psteps = sum(s["particle_steps"] for s in stats)
     st = stats[-1]
     k_ms = float(np.mean([s["step_kernel_ms"] for s in stats]))
@@ -205,10 +251,11 @@ def pic_leg(a, ctx, pic):
            + SLOTS_BIRTH * st["ionization"] + SLOTS_PSTEP * st["particle_steps"])
     bytes_alg = BYTES_PER_PSTEP * st["particle_steps"] + BYTES_PER_BIRTH * st["ionization"]
     achieved = ops / (k_ms * 1e-3) / 1e12
-    tr = measured_traffic()
+    tr = measured_traffic(cfg["name"])
     traffic = None
     if tr is not None:
         traffic = (tr["fetch_bytes_per_pstep"] + tr["write_bytes_per_pstep"]) * st["particle_steps"]
+    n_cells = int(rho.numel())
     roof = {"bound": "alu", "kernel": "k_pic_steps", "achieved": achieved, "peak": VALU_PEAK_SLOTS / 1e12,
             "unit": "Tslot/s", "frac": achieved * 1e12 / VALU_PEAK_SLOTS, "traffic": traffic,
             "slot": "one VALU lane issue slot (FMA = 1, quarter-rate op = 4)",
@@ -216,19 +263,26 @@ def pic_leg(a, ctx, pic):
             "segments_per_particle_step": st["trials"] / max(st["particle_steps"], 1),
             "candidate_fraction": (st["null"] + real) / max(st["trials"], 1),
             "real_fraction": real / max(st["trials"], 1),
+            "hbm_algorithmic_bytes": bytes_alg,
             "hbm_algorithmic_GBs": bytes_alg / (k_ms * 1e-3) / 1e9,
             "hbm_frac": bytes_alg / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "hbm_measured_GBs": (traffic / (k_ms * 1e-3) / 1e9) if traffic else None,
             "valu_issue_measured": tr.get("valu_issue") if tr else None,
             "valu_active_lanes_measured": tr.get("valu_active_lanes") if tr else None,
+            "majorant_violations": int(st["majorant_violations"]),
             "deposit_ms": float(np.mean([s["deposit_kernel_ms"] for s in stats])),
-            "deposit_GBs": (16.0 * st["n"] + 8.0 * rho.numel()) / (stats[-1]["deposit_kernel_ms"] * 1e-3) / 1e9}
+            "deposit_GBs": (16.0 * st["n"] + 8.0 * n_cells) / (stats[-1]["deposit_kernel_ms"] * 1e-3) / 1e9}
     config = {"workload": cfg["name"], "n0": int(n0), "grid": int(cfg["grid"]["E"].shape[0]), "dt_s": cfg["dt"],
               "steps_committed": int(n_fit), "capacity": int(cap), "n_final": int(st["n"]),
               "particle_steps_per_call": int(st["particle_steps"]),
               "trials_per_particle_step": st["trials"] / max(st["particle_steps"], 1),
+              "ionizations_per_call": int(st["ionization"]),
               "launch": [st["launch_grid"], st["launch_block"]]}
-    return cfg, psteps / el, el, roof, config
+    ctx.close()
+    del pristine, work, grid, rho
+    torch.cuda.empty_cache()
+    return {"value": psteps / el, "s": el, "steps": steps, "ms_per_step": el / max(steps, 1) * 1e3,
+            "roofline": roof, "config": config}
 
 
 def weights_leg(a, ctx, pic):
@@ -242,7 +296,7 @@ def weights_leg(a, ctx, pic):
     timed run takes the steps before that, so that it completes."""
     import torch
     from paper_2110_14494_amd import workloads as W
-    cfg = W.streamer_config(n=a.n or 2 ** 24)
+    cfg = W.streamer_config(n=a.n if a.workload == "streamer" and a.n else 2 ** 24)
     n0 = cfg["parts"]["x"].size
     cap = a.weights_cap_factor * n0
     ctx.setup(cfg["species"], cfg["tables"])
@@ -303,7 +357,7 @@ def sc_leg(a, ctx, pic, mu_table):
     the timed run."""
     import torch
     from paper_2110_14494_amd import workloads as W
-    cfg = W.streamer_config(n=a.n or 2 ** 24)
+    cfg = W.streamer_config(n=a.n if a.workload == "streamer" and a.n else 2 ** 24)
     n0 = cfg["parts"]["x"].size
     cap = a.weights_cap_factor * n0
     ctx.setup(cfg["species"], cfg["tables"])
@@ -567,9 +621,9 @@ def main():
         sys.exit(2)
     import torch
     from paper_2110_14494_amd import pic
+    from paper_2110_14494_amd import workloads as W
 
     assert torch.cuda.is_available(), "needs a HIP device"
-    ctx = pic.Context(0)
     if a.calibrate_copy:
         src = torch.ones(a.calibrate_copy * 2 ** 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -577,17 +631,52 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy of {a.calibrate_copy} MiB done")
         del src, dst
-    cfg, value, el, roof, config = pic_leg(a, ctx, pic)
+    cfg = make_cfg(a)
+    cap_factor = a.cap_factor or (8 if a.workload == "stress" else 32)
+    head = pic_run_leg(pic, cfg, cap_factor, a.steps, a.warmup, a.max_steps)
     out = {
         "metric": "electron particle-steps/s (push+MCC+CIC)",
-        "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
-        "ms_per_step": el / a.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic", "config": config, "roofline": roof,
+        "value": head["value"], "unit": "particle-steps/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic", "config": head["config"], "roofline": head["roofline"],
     }
     if not a.no_cpu_baseline:
         log("cpu baseline")
-        out["cpu_baseline"] = cpu_baseline(cfg, a.cpu_sample, a.cpu_steps)
-    if not a.no_weights and a.workload == "streamer":
+        out["cpu_baseline"] = cpu_baseline(cfg, a.cpu_sample, a.cpu_sample_1core, a.cpu_steps)
+    if a.workload == "stress" and not a.no_backgrounds:
+        out["stress_backgrounds"] = {}
+        for bg in (1.75e6, 2.0e6):
+            # the same electrons in the field of another background
+            one = W.stress_config(background=bg, n=1)
+            cfg_b = dict(cfg, grid=one["grid"],
+                         name=one["name"].replace("2^0", f"2^{int(np.log2(cfg['parts']['x'].size))}"))
+            del one
+            leg = pic_run_leg(pic, cfg_b, cap_factor, 1, 0, a.max_steps, label=f"[{bg:.3g} V/m] ")
+            out["stress_backgrounds"][f"{bg:.3g}"] = {"value": leg["value"], "unit": "particle-steps/s",
+                                                      "config": leg["config"], "roofline": leg["roofline"]}
+            del cfg_b
+    del cfg
+    if a.workload != "streamer" and not a.no_streamer:
+        log("streamer stage")
+        scfg = W.streamer_config()
+        leg = pic_run_leg(pic, scfg, 32, 3, 1, label="[streamer] ")
+        out["streamer"] = {"value": leg["value"], "unit": "particle-steps/s", "ms_per_step": leg["ms_per_step"],
+                           "config": leg["config"], "roofline": leg["roofline"]}
+        del scfg
+    if a.workload != "plain" and not a.no_plain:
+        log("plain swarm")
+        pcfg = W.plain_swarm_config()
+        leg = pic_run_leg(pic, pcfg, 32, 3, 1, label="[plain] ")
+        out["plain"] = {"value": leg["value"], "unit": "particle-steps/s", "ms_per_step": leg["ms_per_step"],
+                        "config": leg["config"],
+                        "note": "1e4 electrons fill a small part of the 256 compute units: latency-bound, no "
+                                "roofline claim"}
+        if not a.no_cpu_baseline:
+            out["plain"]["cpu_baseline"] = {
+                "all_cores": cpu_run(pcfg, 10 ** 6, pcfg["n_steps"], host_cores()),
+                "one_core": cpu_run(pcfg, 10 ** 6, pcfg["n_steps"], 1)}
+    ctx = pic.Context(0)
+    if not a.no_weights:
         log("weight-controlled streamer run")
         out["weight_control"] = weights_leg(a, ctx, pic)
     if not a.no_coef:
@@ -599,7 +688,7 @@ def main():
     if not a.no_fluid and getattr(a, "fluid_table", None) is not None:
         log("fluid run")
         out["fluid"] = fluid_leg(a, ctx, pic, a.fluid_table)
-    if not a.no_sc and a.workload == "streamer":
+    if not a.no_sc:
         log("self-consistent streamer run")
         mu = getattr(a, "mu_table", None) or {"EN_lo": 1.0, "EN_hi": 10.0, "muN": np.array([3e24])}
         out["self_consistent"] = sc_leg(a, ctx, pic, mu)

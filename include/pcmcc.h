@@ -9,7 +9,7 @@
  * null-collision method with rates from tabulated cross sections (Sec. 2.1.1,
  * Sec. 2.1.5), and are mapped back to the grid by trilinear weighting
  * (Sec. 2.1.3).  The same mover run in a uniform field gives the flux and bulk
- * swarm coefficients that feed the fluid model (Sec. 2.2.1).
+ * swarm coefficients that feed the fluid model (Sec. 2.2.2).
  *
  * Conventions shared by every entry point:
  *   - SI units, except energies in eV and reduced fields E/N in Td
@@ -175,7 +175,7 @@ int pcmcc_init_tables(pcmcc_ctx* ctx, int n_e, double eps_min_eV, double eps_max
 int pcmcc_push_collide_deposit(pcmcc_ctx* ctx, const pcmcc_particles* p, const pcmcc_grid* field, double dt,
                                int n_steps, uint64_t seed, uint64_t step0, int64_t* rho, pcmcc_stats* stats);
 
-/* ---- Batched uniform-field swarms (Sec. 2.2.1) ---------------------------
+/* ---- Batched uniform-field swarms (Sec. 2.2.2) ---------------------------
  * Swarm s starts with n0[s] electrons at rest at the origin in the field
  * E = EN_Td[s] * 1e-21 * N along +z and is advanced n_steps steps of dt with
  * the same mover as pcmcc_push_collide_deposit (newborns, attachment), all

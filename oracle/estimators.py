@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).  Plain NumPy FP64.
 
-Definitions (arXiv:2110.14494, Sec. 2.2.1: flux coefficients describe the
+Definitions (arXiv:2110.14494, Sec. 2.2.2: flux coefficients describe the
 mean motion of individual electrons, bulk coefficients the motion of the
 centre of mass of the whole group, which differs when ionization or
 attachment depends on position through the energy):

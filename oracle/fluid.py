@@ -1,7 +1,7 @@
 """Drift-diffusion-reaction fluid step with the local field approximation
 (arXiv:2110.14494 Sec. 2.2: the electron density equation, Koren-limited
 advective fluxes with central diffusive fluxes, Heun's method and the fluid
-time-step limits; transport data versus E/N as in Sec. 2.2.1).
+time-step limits; transport data versus E/N as in Sec. 2.2.2).
 
 TEST INFRASTRUCTURE ONLY: imported by the tests, never by the product library.
 Plain NumPy in double precision, one step of the definitions at a time.

@@ -20,7 +20,7 @@
 //     cell-centred grid, Sec. 2.1.3; homogeneous Neumann density boundaries,
 //     Sec. 2.3;
 //   * flux and bulk swarm coefficients from uniform-field Monte Carlo,
-//     Sec. 2.2.1 (the estimators themselves live in estimators.py).
+//     Sec. 2.2.2 (the estimators themselves live in estimators.py).
 // Where the paper is silent (scattering law, energy sharing, majorant, random
 // number layout) the reading taken is stated next to the code.
 
@@ -941,7 +941,7 @@ int orc_deposit_impl(const float* x, const float* y, const float* z, const float
 
 extern "C" {
 
-// Uniform-field swarms (Sec. 2.2.1): swarm s starts with n0[s] electrons at
+// Uniform-field swarms (Sec. 2.2.2): swarm s starts with n0[s] electrons at
 // rest at the origin in a field E = (E/N) N along +z and is advanced n_steps
 // steps.  Every `sample_every` steps the moments of the population (after the
 // step's newborns, before population control) are recorded:

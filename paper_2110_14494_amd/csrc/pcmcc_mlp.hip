@@ -1,7 +1,7 @@
 // Coefficient surrogate: a 1 -> 64 -> 64 -> 6 perceptron (tanh hidden
 // layers) that maps standardised ln(E/N) to standardised log swarm
 // coefficients (the inputs of the fluid model of arXiv:2110.14494 Sec. 2.2,
-// computed by the swarms of Sec. 2.2.1).
+// computed by the swarms of Sec. 2.2.2).
 //
 //  * training (FP32): forward and backward over 64-point tiles held in LDS,
 //    gradients reduced in a fixed order (bit-reproducible), full-batch Adam

@@ -1,7 +1,7 @@
-// Batched uniform-field swarms (arXiv:2110.14494 Sec. 2.2.1): many
+// Batched uniform-field swarms (arXiv:2110.14494 Sec. 2.2.2): many
 // independent electron swarms, each in its own field E/N and with its own
 // size, advanced together by one persistent cooperative launch; their
-// moments give flux and bulk transport coefficients (Sec. 2.2.1) with a
+// moments give flux and bulk transport coefficients (Sec. 2.2.2) with a
 // temporal-growth model.
 //
 // Layout: swarm s owns a contiguous region of cap_s slots in each of two

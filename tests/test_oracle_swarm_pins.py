@@ -4,7 +4,7 @@ Closed forms: constant-frequency drift eE/(m nu); diffusion v^2/(3 nu) for a
 monoenergetic gas with constant frequency; temporal growth nu_i - nu_a.
 Special cases: flux and bulk coefficients coincide when the collision rates
 do not depend on energy.  Invariance: population control does not change the
-estimators.  Paper trend (Sec. 2.2.1, Sec. 3.2): once ionization matters the
+estimators.  Paper trend (Sec. 2.2.2, Sec. 3.2): once ionization matters the
 bulk drift exceeds the flux drift.
 """
 import math
