@@ -501,32 +501,49 @@ def fluid_leg(a, ctx, pic, table):
             "transport": "surrogate sampled on 2048 log-spaced E/N nodes (fallback cells: swarm table)"}
 
 
+HELD_LOG2_N = 17  # swarm size of the held-out and test batches (2^17 electrons each)
+
+
 def coef_leg(a, ctx, pic):
-    """Coefficient path: 2048 E/N points (8 batches of 256 swarms, sizes as the
-    batched-swarm workload), every 8th held out; surrogate trained on the GPU;
-    held-out error decides the fallback cells; BF16 inference on 1e8 fields."""
+    """Coefficient path: 2048 E/N points (8 batches of 256 swarms; sizes as
+    the batched-swarm workload, the held-out batch - every 8th point - at
+    2^17 electrons per swarm), surrogate trained on the GPU, per-output
+    fallback wherever the held-out error exceeds 1 %, and an independent test
+    batch of 256 swarms (2^17 electrons) half a grid step from the held-out
+    points, on which the error actually served after fallback is measured;
+    BF16 inference on 1e8 fields against the table path and the plain
+    per-E/N swarm."""
     import torch
     from paper_2110_14494_amd import surrogate as S
     from paper_2110_14494_amd import workloads as W
     sp = W.electron_species()
     ctx.setup(sp, W.air_like_tables())
     base = W.swarm_batch_config()
-    n_all, n_batch = 2048, 8
+    n_all, n_batch, held_b = 2048, 8, 4
     EN_all = 10.0 * 100.0 ** (np.arange(n_all) / (n_all - 1))
     vals = np.zeros((n_all, 14))
     errs = np.zeros((n_all, 14))
     t_swarm = 0.0
-    for b in range(n_batch):
-        idx = np.arange(b, n_all, n_batch)
-        cfg = W.swarm_batch_config(seed=1 + b, scale=a.coef_scale)
+    big = dict(log2_lo=HELD_LOG2_N, log2_hi=HELD_LOG2_N)
+
+    def batch(EN, b, sizes):
+        cfg = W.swarm_batch_config(seed=1 + b, scale=a.coef_scale, **sizes)
         t0 = time.perf_counter()
-        rc, v, e, st = pic.swarm_batch(ctx, EN_all[idx], cfg["n0"], base["dt"], base["n_steps"], 17 + b,
+        rc, v, e, st = pic.swarm_batch(ctx, EN, cfg["n0"], base["dt"], base["n_steps"], 17 + b,
                                        sample_every=base["sample_every"], window_start_s=base["window_start"],
                                        n_batches=10)
-        t_swarm += time.perf_counter() - t0
-        vals[idx], errs[idx] = v, e
+        el = time.perf_counter() - t0
         log(f"swarm batch {b}: {st['step_kernel_ms']:.0f} ms, {st['particle_steps']:.3g} particle-steps")
+        return v, e, el
+
+    for b in range(n_batch):
+        idx = np.arange(b, n_all, n_batch)
+        vals[idx], errs[idx], el = batch(EN_all[idx], b, big if b == held_b else {})
+        t_swarm += el
     batched_pps = n_all / t_swarm
+    # independent test points: half a grid step above each held-out point
+    EN_test = 10.0 * 100.0 ** ((np.arange(held_b, n_all, n_batch) + 0.5) / (n_all - 1))
+    v_test, e_test, _ = batch(EN_test, n_batch, big)
     # the plain method: one swarm per launch (a few E/N values, extrapolated)
     cfg = W.swarm_batch_config(seed=1, scale=a.coef_scale)
     probe = [0, 85, 170, 255]
@@ -535,21 +552,36 @@ def coef_leg(a, ctx, pic):
         pic.swarm_batch(ctx, [cfg["EN_Td"][k]], cfg["n0"][k:k + 1], base["dt"], base["n_steps"], 99 + k,
                         sample_every=base["sample_every"], window_start_s=base["window_start"], n_batches=10)
     plain_pps = len(probe) / (time.perf_counter() - t0)
-    held = np.arange(4, n_all, n_batch)  # batch 4 = every 8th point
+    held = np.arange(held_b, n_all, n_batch)
     train = np.setdiff1d(np.arange(n_all), held)
     x, t, m, ln_tr, _, norm = S.dataset(EN_all[train], vals[train], errs[train], sp["gas_N"], 0.1)
     _, _, m_h, ln_h, sig_h, _ = S.dataset(EN_all[held], vals[held], errs[held], sp["gas_N"], 0.1, norm=norm)
-    _, _, _, ln_all, _, _ = S.dataset(EN_all, vals, errs, sp["gas_N"], 0.1, norm=norm)
+    _, _, m_all, ln_all, _, _ = S.dataset(EN_all, vals, errs, sp["gas_N"], 0.1, norm=norm)
+    _, _, m_t, ln_t, sig_t, _ = S.dataset(EN_test, v_test, e_test, sp["gas_N"], 0.1, norm=norm)
     th0 = W.mlp_init(4)
     params, hist, tst = S.train(ctx, th0, x, t, m, a.epochs, 3e-3, 1e-5)
     log(f"surrogate trained: {a.epochs} epochs in {tst['step_kernel_ms']:.0f} ms, loss {hist[0]:.3g} -> {hist[-1]:.3g}")
     lo, hi = math.log(10.0), math.log(1000.0)
-    # a cell falls back to the swarm table where the surrogate misses a
-    # held-out swarm value by more than 1 % plus three of that value's own
-    # Monte Carlo standard errors
-    tol, z_sig = math.log(1.01), 3.0
+    # an output of a cell falls back to the swarm table where the surrogate
+    # misses a held-out swarm value by more than 1 % (or the value is
+    # unresolved); cells without a held-out point fall back entirely
+    tol, z_sig = math.log(1.01), 0.0
     fb, err = S.fallback(ctx, params, norm, EN_all[held], ln_h, m_h, tol, 256, lo, hi, sig_held=sig_h, z_sig=z_sig)
-    norm_fb = norm.with_fallback(fb, lo, hi, ln_all, lo, hi)
+    # the fallback table: every swarm point (training and held-out), each
+    # output interpolated over its resolved points, on 2048 uniform nodes
+    nodes = np.linspace(lo, hi, 2048)
+    ln_en = np.log(EN_all)
+
+    def table_from(ln_v, mask, where):
+        cols = []
+        for k in range(6):
+            ok = mask[:, k].astype(bool) & np.isfinite(ln_v[:, k])
+            cols.append(np.interp(nodes, ln_en[where][ok], ln_v[ok, k]) if ok.sum() > 1
+                        else np.full(nodes.size, np.nan))
+        return np.stack(cols, axis=1).astype(np.float32)
+
+    table_all = table_from(ln_all, m_all, np.arange(n_all))
+    norm_fb = norm.with_fallback(fb, lo, hi, table_all, lo, hi)
     EN_q = torch.from_numpy(W.log_uniform_EN(a.infer_n, seed=5)).cuda()
     out = torch.empty((6, a.infer_n), dtype=torch.float32, device="cuda")
     S.infer(ctx, params, norm_fb, EN_q, out)  # warmup
@@ -560,16 +592,11 @@ def coef_leg(a, ctx, pic):
         _, ist = S.infer(ctx, params, norm_fb, EN_q, out)
     torch.cuda.synchronize()
     infer_s = (time.perf_counter() - t0) / reps
-    # the table path alone: every cell falls back to linear interpolation of a
-    # swarm table built from the training points only (resampled onto uniform
-    # nodes in ln(E/N)), timed like the surrogate and checked on the held-out
-    # points
-    ln_tr_m = np.where(m.astype(bool), ln_tr, np.nan)
-    nodes = np.linspace(lo, hi, 2048)
-    ln_en_tr = np.log(EN_all[train])
-    table_tr = np.stack([np.interp(nodes, ln_en_tr[np.isfinite(ln_tr_m[:, k])],
-                                   ln_tr_m[np.isfinite(ln_tr_m[:, k]), k]) for k in range(6)], axis=1)
-    norm_tab = norm.with_fallback(np.ones(256, np.uint8), lo, hi, table_tr.astype(np.float32), lo, hi)
+    # the table path alone: every output of every cell interpolates the table
+    # built from the training points only (so that the held-out and test
+    # points judge it), timed like the surrogate
+    table_tr = table_from(ln_tr, m, train)
+    norm_tab = norm.with_fallback(np.full(256, 0x3F, np.uint8), lo, hi, table_tr, lo, hi)
     S.infer(ctx, params, norm_tab, EN_q, out)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -577,34 +604,58 @@ def coef_leg(a, ctx, pic):
         S.infer(ctx, params, norm_tab, EN_q, out)
     torch.cuda.synchronize()
     table_s = (time.perf_counter() - t0) / reps
-    y_tab, _ = S.infer(ctx, params, norm_tab, torch.from_numpy(EN_all[held].astype(np.float32)).cuda())
-    e_tab = np.abs(y_tab.cpu().numpy().T - ln_h)
-    e_tab = np.where(m_h.astype(bool), e_tab, np.nan)
-    e_ok = np.where(np.isfinite(err), err, np.nan)
     names = ("ln_muN", "ln_DLN", "ln_alpha_N", "ln_eta_N", "ln_mean_eps", "ln_bulk_flux")
+
+    def at(nrm, EN):
+        y, _ = S.infer(ctx, params, nrm, torch.from_numpy(np.asarray(EN, np.float32)).cuda())
+        return y.cpu().numpy().T.astype(np.float64)
+
+    def stats(e, sel):
+        e = np.where(sel, e, np.nan)
+        return ({k: (float(np.nanmedian(e[:, i])) if np.any(np.isfinite(e[:, i])) else None)
+                 for i, k in enumerate(names)},
+                {k: (float(np.nanmax(e[:, i])) if np.any(np.isfinite(e[:, i])) else None)
+                 for i, k in enumerate(names)})
+
+    # served error on the independent test points: the surrogate where its
+    # cell's output passed, the table elsewhere
+    ok_t = m_t.astype(bool)
+    served = np.abs(at(norm_fb, EN_test) - ln_t)
+    surr_t = np.abs(at(norm, EN_test) - ln_t)
+    tab_t = np.abs(at(norm_tab, EN_test) - ln_t)
+    cell_t = np.clip(np.floor((np.log(EN_test) - lo) / (hi - lo) * 256), 0, 255).astype(int)
+    by_surr = ((fb[cell_t][:, None] >> np.arange(6)[None, :]) & 1) == 0
+    served_med, served_max = stats(served, ok_t)
+    surr_med, surr_max = stats(served, ok_t & by_surr)
+    tab_med, _ = stats(tab_t, ok_t)
+    raw_med, _ = stats(surr_t, ok_t)
+    sig_med, _ = stats(np.abs(sig_t), ok_t)
+    e_ok = np.where(np.isfinite(err), err, np.nan)
     muN = vals[:, pic.B.SWARM_QUANTITIES.index("mu")] * sp["gas_N"]
-    ok = np.isfinite(muN) & (muN > 0)
+    okm = np.isfinite(muN) & (muN > 0)
     a.mu_table = {"EN_lo": float(EN_all[0]), "EN_hi": float(EN_all[-1]), "from_swarms": True,
-                  "muN": np.interp(np.arange(n_all), np.flatnonzero(ok), muN[ok])}
+                  "muN": np.interp(np.arange(n_all), np.flatnonzero(okm), muN[okm])}
     # transport data for the fluid model: the surrogate (with its fallback
-    # cells) sampled on log-spaced E/N nodes
-    nodes = torch.from_numpy(EN_all.astype(np.float32)).cuda()
-    y_nodes, _ = S.infer(ctx, params, norm_fb, nodes)
-    yn = np.exp(y_nodes.cpu().numpy().astype(np.float64))
+    # outputs) sampled on log-spaced E/N nodes
+    yn = np.exp(at(norm_fb, EN_all).T)
     a.fluid_table = {"EN_lo": float(EN_all[0]), "EN_hi": float(EN_all[-1]), "muN": yn[0], "DN": yn[1],
                      "alphaN": yn[2], "etaN": yn[3]}
+    fb_bits = (fb[:, None] >> np.arange(6)[None, :]) & 1
     return {
         "swarm_points": n_all, "swarm_steps": base["n_steps"], "swarm_scale": a.coef_scale,
+        "heldout_and_test_electrons_per_swarm": 2 ** HELD_LOG2_N,
         "batched_swarm_EN_points_per_s": batched_pps, "plain_swarm_EN_points_per_s": plain_pps,
         "batched_over_plain": batched_pps / plain_pps,
         "train_epochs": a.epochs, "train_s": tst["step_kernel_ms"] / 1e3, "train_loss": [float(hist[0]), float(hist[-1])],
+        "tolerance_ln": tol, "tolerance_sigmas": z_sig, "cells": 256,
+        "cells_fallback_any_output": int((fb != 0).sum()), "cells_fallback_all_outputs": int((fb == 0x3F).sum()),
+        "surrogate_served_fraction": {k: float(1.0 - fb_bits[:, i].mean()) for i, k in enumerate(names)},
         "heldout_abs_ln_err_median": {k: float(np.nanmedian(e_ok[:, i])) for i, k in enumerate(names)},
-        "heldout_abs_ln_err_max": {k: float(np.nanmax(e_ok[:, i])) if np.any(np.isfinite(e_ok[:, i])) else None
-                                   for i, k in enumerate(names)},
-        "heldout_err_over_sigma_median": {k: float(np.nanmedian(e_ok[:, i] / sig_h[:, i]))
-                                          for i, k in enumerate(names)},
-        "tolerance_ln": tol, "tolerance_sigmas": z_sig, "cells": 256, "cells_fallback": int(fb.sum()),
-        "table_heldout_abs_ln_err_median": {k: float(np.nanmedian(e_tab[:, i])) for i, k in enumerate(names)},
+        "test_swarm_rel_sigma_median": sig_med,
+        "test_served_abs_ln_err_median": served_med, "test_served_abs_ln_err_max": served_max,
+        "test_surrogate_served_abs_ln_err_median": surr_med, "test_surrogate_served_abs_ln_err_max": surr_max,
+        "test_surrogate_everywhere_abs_ln_err_median": raw_med,
+        "test_table_abs_ln_err_median": tab_med,
         "table_EN_points_per_s": a.infer_n / table_s,
         "infer_points": a.infer_n, "infer_s": infer_s, "infer_kernel_ms": ist["step_kernel_ms"],
         "surrogate_EN_points_per_s": a.infer_n / infer_s,

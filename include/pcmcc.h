@@ -279,7 +279,8 @@ typedef struct pcmcc_mlp_infer_opts {
   double mu_y[PCMCC_MLP_OUT], sd_y[PCMCC_MLP_OUT]; /* output un-standardisation */
   int n_cells;                             /* fallback cells uniform in ln(E/N) over [cell_lo, cell_hi); 0 = none */
   double cell_lo, cell_hi;
-  const uint8_t* fallback;                 /* host [n_cells]: 1 = use the table in this cell */
+  const uint8_t* fallback;                 /* host [n_cells]: bit k set = output k takes the table in this cell
+                                              (0x3F: every output) */
   int n_nodes;                             /* table nodes uniform in ln(E/N) from table_lo to table_hi */
   double table_lo, table_hi;
   const float* table;                      /* host [n_nodes][6] ln coefficients (linear interpolation) */
@@ -287,8 +288,9 @@ typedef struct pcmcc_mlp_infer_opts {
 
 /* Evaluates the surrogate at n reduced fields EN_dev (device, Td) with
  * bfloat16 weights and activations and single-precision accumulation (MFMA);
- * out_dev (device) receives [6][n] ln coefficients (output-major).  Points in
- * a fallback cell take the linear interpolation of the table instead. */
+ * out_dev (device) receives [6][n] ln coefficients (output-major).  The
+ * outputs flagged in a point's fallback cell take the linear interpolation of
+ * the table instead. */
 int pcmcc_mlp_infer(pcmcc_ctx* ctx, const float* params, const pcmcc_mlp_infer_opts* opts, int64_t n,
                     const float* EN_dev, float* out_dev, pcmcc_stats* stats);
 
@@ -309,14 +311,16 @@ int pcmcc_mlp_dataset(int n, const double* EN_Td, const pcmcc_swarm_result* res,
                       float* ln_out, float* sig_out, double ln_floor);
 
 /* Held-out check of a trained surrogate: evaluates it (the bfloat16 device
- * path) at n_held reduced fields and marks cell c of n_cells cells uniform in
- * ln(E/N) over [cell_lo, cell_hi) for fallback if, for any held-out point in
- * it, an output is masked or |ln y_mlp - ln y_swarm| > tol_ln + z_sig sig,
- * sig being the held-out value's own Monte Carlo standard error in ln units
- * (a held-out swarm value is itself noisy; sig_held NULL means 0).  ln_held,
- * mask_held and sig_held [n_held][6] are unstandardised ln targets, their
- * mask and errors (host); fallback_out[n_cells] host; err_out[n_held][6]
- * (nullable) receives the absolute ln errors (NaN where masked). */
+ * path) at n_held reduced fields; of n_cells cells uniform in ln(E/N) over
+ * [cell_lo, cell_hi), output k of cell c falls back (bit k of
+ * fallback_out[c]) if, for any held-out point in the cell, that output is
+ * masked or |ln y_mlp - ln y_swarm| > tol_ln + z_sig sig, sig being the
+ * held-out value's own Monte Carlo standard error in ln units (sig_held NULL
+ * means 0); a cell holding no held-out point falls back in every output
+ * (0x3F).  ln_held, mask_held and sig_held [n_held][6] are unstandardised ln
+ * targets, their mask and errors (host); fallback_out[n_cells] host;
+ * err_out[n_held][6] (nullable) receives the absolute ln errors (NaN where
+ * masked). */
 int pcmcc_mlp_fallback(pcmcc_ctx* ctx, const float* params, const pcmcc_mlp_infer_opts* norm, int n_held,
                        const double* EN_held, const float* ln_held, const float* mask_held, const float* sig_held,
                        double tol_ln, double z_sig, int n_cells, double cell_lo, double cell_hi,

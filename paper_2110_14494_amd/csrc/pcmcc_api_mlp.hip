@@ -303,19 +303,28 @@ int pcmcc_mlp_fallback(pcmcc_ctx* c, const float* params, const pcmcc_mlp_infer_
   dfree(den);
   dfree(dout);
   if (rc) return rc;
-  for (int k = 0; k < n_cells; ++k) fallback_out[k] = 0;
+  // A cell without a held-out point falls back in every output; otherwise
+  // output k falls back if it is unresolved or misses at any of the cell's
+  // held-out points.
+  const uint8_t all = (uint8_t)((1u << PCMCC_MLP_OUT) - 1u);
+  std::vector<char> seen(n_cells, 0);
+  for (int k = 0; k < n_cells; ++k) fallback_out[k] = all;
   const double w = (cell_hi - cell_lo) / n_cells;
   for (int i = 0; i < n_held; ++i) {
     const int cell = std::min(std::max((int)std::floor((std::log(EN_held[i]) - cell_lo) / w), 0), n_cells - 1);
+    if (!seen[cell]) {
+      seen[cell] = 1;
+      fallback_out[cell] = 0;
+    }
     for (int k = 0; k < PCMCC_MLP_OUT; ++k) {
       const size_t j = (size_t)i * PCMCC_MLP_OUT + k;
       float err = NAN;
       if (mask_held[j] == 0.0f) {
-        fallback_out[cell] = 1;
+        fallback_out[cell] |= (uint8_t)(1u << k);
       } else {
         err = std::fabs(y[(size_t)k * n_held + i] - ln_held[j]);
         const double sig = sig_held ? (double)sig_held[j] : 0.0;
-        if (!(err <= tol_ln + z_sig * (std::isfinite(sig) ? sig : 0.0))) fallback_out[cell] = 1;
+        if (!(err <= tol_ln + z_sig * (std::isfinite(sig) ? sig : 0.0))) fallback_out[cell] |= (uint8_t)(1u << k);
       }
       if (err_out) err_out[j] = err;
     }

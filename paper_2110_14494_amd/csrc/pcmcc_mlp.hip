@@ -9,8 +9,8 @@
 //  * inference (BF16 weights and activations, FP32 accumulation): the 64x64
 //    layer and the output layer run on MFMA (v_mfma_f32_32x32x16_bf16); the
 //    first layer is computed per lane straight into the MFMA operand layout;
-//    points whose E/N cell is flagged fall back to interpolation of the
-//    swarm table.
+//    the outputs flagged for a point's E/N cell fall back to interpolation
+//    of the swarm table.
 // Parameter vector (4678 floats): W1[64,1], b1[64], W2[64,64], b2[64],
 // W3[6,64], b3[6], row-major.
 #include <hip/hip_cooperative_groups.h>
@@ -23,6 +23,7 @@ namespace cg = cooperative_groups;
 namespace pcmcc {
 
 constexpr int kH = 64, kOut = 6, kTile = 64;
+constexpr unsigned kAllOut = (1u << kOut) - 1u;  // fallback mask with every output
 constexpr int OFF_W1 = 0, OFF_B1 = 64, OFF_W2 = 128, OFF_B2 = 128 + 4096, OFF_W3 = OFF_B2 + 64,
               OFF_B3 = OFF_W3 + 384;
 static_assert(OFF_B3 + 6 == kMlpParams, "parameter packing");
@@ -288,12 +289,14 @@ __global__ __launch_bounds__(256) void k_mlp_infer(InferArgs A) {
     const float lnEN = logf(EN);
     const float xs = (lnEN - A.mu_x) * A.inv_sd_x;
     const int cell = A.n_cells > 0 ? min(max((int)floorf((lnEN - A.cell_lo) * A.inv_cell_w), 0), A.n_cells - 1) : 0;
-    const bool fb = A.n_cells > 0 && A.fb_mask[cell];
+    // bit o set: output o of this cell takes the table
+    const unsigned fbm = A.n_cells > 0 ? (unsigned)A.fb_mask[cell] & kAllOut : 0u;
     floatx16 c3;
     for (int r = 0; r < 16; ++r) c3[r] = 0.0f;
-    // The perceptron runs unless every point of the wave falls back to the
-    // table (the condition is wave-uniform, as the matrix instructions need).
-    if (__ballot(valid && !fb) != 0) {
+    // The perceptron runs unless every output of every point of the wave
+    // falls back to the table (the condition is wave-uniform, as the matrix
+    // instructions need).
+    if (__ballot(valid && fbm != kAllOut) != 0) {
       // layer 2: C2[m] = W2[32m.., :] h1 over 4 k-steps of 16
       floatx16 c2[2];
       for (int m = 0; m < 2; ++m)
@@ -327,7 +330,7 @@ __global__ __launch_bounds__(256) void k_mlp_infer(InferArgs A) {
     // outputs: rows 4 half + j (j < 4) of C3 are outputs 0..3 (half 0) and 4..7 (half 1)
     float tf = 0.0f;
     int ti = 0;
-    if (fb) {
+    if (fbm) {
       const float u = fminf(fmaxf((lnEN - A.tab_lo) * A.inv_tab_w, 0.0f), (float)(A.n_nodes - 1));
       const float fl = fminf(floorf(u), (float)(A.n_nodes - 2));
       ti = (int)fl;
@@ -338,7 +341,7 @@ __global__ __launch_bounds__(256) void k_mlp_infer(InferArgs A) {
       const int o = 4 * half + j;
       if (o >= kOut) break;
       float y = (c3[j] + L.b3[o]) * L.sd_y[o] + L.mu_y[o];
-      if (fb) {
+      if ((fbm >> o) & 1u) {
         const float a = A.table[ti * kOut + o], bb = A.table[(ti + 1) * kOut + o];
         y = fmaf(tf, bb - a, a);
       }
