@@ -562,10 +562,11 @@ def coef_leg(a, ctx, pic):
     params, hist, tst = S.train(ctx, th0, x, t, m, a.epochs, 3e-3, 1e-5)
     log(f"surrogate trained: {a.epochs} epochs in {tst['step_kernel_ms']:.0f} ms, loss {hist[0]:.3g} -> {hist[-1]:.3g}")
     lo, hi = math.log(10.0), math.log(1000.0)
-    # an output of a cell falls back to the swarm table where the surrogate
-    # misses a held-out swarm value by more than 1 % (or the value is
-    # unresolved); cells without a held-out point fall back entirely
-    tol, z_sig = math.log(1.01), 0.0
+    # an output of a cell falls back to the swarm table unless the held-out
+    # swarm value shows the surrogate within 1 % with a margin of two of that
+    # value's standard errors (an unresolved value, or one noisier than 0.5 %,
+    # always falls back); cells without a held-out point fall back entirely
+    tol, z_sig = math.log(1.01), -2.0
     fb, err = S.fallback(ctx, params, norm, EN_all[held], ln_h, m_h, tol, 256, lo, hi, sig_held=sig_h, z_sig=z_sig)
     # the fallback table: every swarm point (training and held-out), each
     # output interpolated over its resolved points, on 2048 uniform nodes
@@ -626,6 +627,11 @@ def coef_leg(a, ctx, pic):
     cell_t = np.clip(np.floor((np.log(EN_test) - lo) / (hi - lo) * 256), 0, 255).astype(int)
     by_surr = ((fb[cell_t][:, None] >> np.arange(6)[None, :]) & 1) == 0
     served_med, served_max = stats(served, ok_t)
+    # entries whose served value is off by more than 1 % beyond three of the
+    # test value's own standard errors
+    miss = ok_t & (served > tol + 3.0 * np.abs(np.nan_to_num(sig_t)))
+    miss_surr = {k: int((miss & by_surr)[:, i].sum()) for i, k in enumerate(names)}
+    miss_tab = {k: int((miss & ~by_surr)[:, i].sum()) for i, k in enumerate(names)}
     surr_med, surr_max = stats(served, ok_t & by_surr)
     tab_med, _ = stats(tab_t, ok_t)
     raw_med, _ = stats(surr_t, ok_t)
@@ -656,6 +662,8 @@ def coef_leg(a, ctx, pic):
         "test_surrogate_served_abs_ln_err_median": surr_med, "test_surrogate_served_abs_ln_err_max": surr_max,
         "test_surrogate_everywhere_abs_ln_err_median": raw_med,
         "test_table_abs_ln_err_median": tab_med,
+        "test_entries_missing_1pct_plus_3sigma_surrogate": miss_surr,
+        "test_entries_missing_1pct_plus_3sigma_table": miss_tab,
         "table_EN_points_per_s": a.infer_n / table_s,
         "infer_points": a.infer_n, "infer_s": infer_s, "infer_kernel_ms": ist["step_kernel_ms"],
         "surrogate_EN_points_per_s": a.infer_n / infer_s,

@@ -316,7 +316,10 @@ int pcmcc_mlp_dataset(int n, const double* EN_Td, const pcmcc_swarm_result* res,
  * fallback_out[c]) if, for any held-out point in the cell, that output is
  * masked or |ln y_mlp - ln y_swarm| > tol_ln + z_sig sig, sig being the
  * held-out value's own Monte Carlo standard error in ln units (sig_held NULL
- * means 0); a cell holding no held-out point falls back in every output
+ * means 0).  z_sig > 0 forgives the held-out value's noise; z_sig < 0 asks the
+ * held-out evidence to show the error below tol_ln with a margin of |z_sig|
+ * standard errors (an output whose sig reaches tol_ln / |z_sig| always falls
+ * back).  A cell holding no held-out point falls back in every output
  * (0x3F).  ln_held, mask_held and sig_held [n_held][6] are unstandardised ln
  * targets, their mask and errors (host); fallback_out[n_cells] host;
  * err_out[n_held][6] (nullable) receives the absolute ln errors (NaN where

@@ -14,6 +14,7 @@ SOURCES = ["pcmcc_kernels.hip", "pcmcc_deposit.hip", "pcmcc_weights.hip", "pcmcc
            "pcmcc_field.hip", "pcmcc_fluid.hip", "pcmcc_photo.hip", "pcmcc_runtime.hip", "pcmcc_api.hip", "pcmcc_noalloc.hip",
            "pcmcc_api_swarm.hip", "pcmcc_api_mlp.hip", "pcmcc_api_field.hip", "pcmcc_api_fluid.hip"]
 ARCH = os.environ.get("PCMCC_OFFLOAD_ARCH", "gfx950")
+CONTRACT_OFF = ("pcmcc_kernels.hip", "pcmcc_swarm.hip")
 
 
 def hipcc() -> str:
@@ -30,7 +31,12 @@ def build(verbose: bool = False) -> str:
     os.makedirs(bdir, exist_ok=True)
     for src in SOURCES:
         obj = os.path.join(bdir, src.replace(".hip", ".o"))
-        cmd = [hipcc()] + flags + ["-c", os.path.join(CSRC, src), "-o", obj]
+        # the electron mover's arithmetic is exactly what its source writes
+        # (explicit fused multiply-adds only): implicit contraction may fuse
+        # a sum of products either way, so an unrelated code change could
+        # move results by an ulp
+        extra = ["-ffp-contract=off"] if src in CONTRACT_OFF else []
+        cmd = [hipcc()] + flags + extra + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)

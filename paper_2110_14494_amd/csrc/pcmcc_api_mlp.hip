@@ -278,7 +278,7 @@ int pcmcc_mlp_fallback(pcmcc_ctx* c, const float* params, const pcmcc_mlp_infer_
                        double tol_ln, double z_sig, int n_cells, double cell_lo, double cell_hi,
                        uint8_t* fallback_out, float* err_out) {
   if (!c) return fail(nullptr, PCMCC_EINVAL, "null context");
-  if (!params || !norm || n_held < 1 || !EN_held || !ln_held || !mask_held || !(tol_ln > 0) || !(z_sig >= 0) ||
+  if (!params || !norm || n_held < 1 || !EN_held || !ln_held || !mask_held || !(tol_ln > 0) || !std::isfinite(z_sig) ||
       n_cells < 1 || !(cell_hi > cell_lo) || !fallback_out)
     return fail(c, PCMCC_EINVAL, "invalid fallback arguments");
   HIP_TRY(c, hipSetDevice(c->device));

@@ -85,7 +85,7 @@ struct SpeciesView {
 };
 
 __device__ __forceinline__ void locate(const TableView& T, float eps, int& i, float& f) {
-  float u = __log2f(eps) * T.u_scale + T.u_offset;  // eps = 0 gives -inf
+  float u = fmaf(__log2f(eps), T.u_scale, T.u_offset);  // eps = 0 gives -inf
   u = fminf(fmaxf(u, 0.0f), (float)(T.n - 1));
   const float fl = fminf(floorf(u), (float)(T.n - 2));
   i = (int)fl;
@@ -111,7 +111,7 @@ __device__ __forceinline__ float majorant(const TableView& T, const SpeciesView&
 // |a| <= a_abs and |a - a0| <= da along the way.
 __device__ __forceinline__ float speed_bound(float3 v, float3 a0, float speed, float a_abs, float da, float h) {
   const float wx = fmaf(a0.x, h, v.x), wy = fmaf(a0.y, h, v.y), wz = fmaf(a0.z, h, v.z);
-  const float s_dir = fmaf(da, h, fmaxf(speed, __builtin_amdgcn_sqrtf(wx * wx + wy * wy + wz * wz)));
+  const float s_dir = fmaf(da, h, fmaxf(speed, __builtin_amdgcn_sqrtf(fmaf(wz, wz, fmaf(wy, wy, wx * wx)))));
   return fminf(fmaf(a_abs, h, speed), s_dir);
 }
 
@@ -143,7 +143,7 @@ struct GridView {
 // Cell-centre coordinate u = (x - x0)/dx - 1/2 of one axis, clamped to
 // [-1, n], split into the lower centre index and the fraction.
 __device__ __forceinline__ void cell_coord(double x, double o, double inv_dx, int n, int& i, float& f) {
-  double u = (x - o) * inv_dx - 0.5;
+  double u = fma(x - o, inv_dx, -0.5);
   u = fmin(fmax(u, -1.0), (double)n);
   const double fl = floor(u);
   i = (int)fl;

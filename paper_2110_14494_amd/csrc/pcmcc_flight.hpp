@@ -162,15 +162,16 @@ struct StagedBirths {
     qt.tag = tag;
     qt.push(c, tb);
     if (cum_ion) atomicAdd(&cum_ion[tag], 1ull);
-    if (q.ev.ix) {
-      const uint64_t es = wave_reserve(q.ev.n);
-      if (es < q.ev.cap) {
-        q.ev.ix[es] = x;
-        q.ev.iy[es] = y;
-        q.ev.iz[es] = z;
-        q.ev.iw[es] = w;
+    const EventSink ev = q.evk.get();
+    if (ev.ix) {
+      const uint64_t es = wave_reserve(ev.n);
+      if (es < ev.cap) {
+        ev.ix[es] = x;
+        ev.iy[es] = y;
+        ev.iz[es] = z;
+        ev.iw[es] = w;
       } else {
-        atomicOr(q.ev.overflow, OVF_CAPACITY);
+        atomicOr(ev.overflow, OVF_CAPACITY);
       }
     }
     return false;
@@ -191,35 +192,37 @@ struct StagedBirths {
       if (slot < q.cap) {
         PState c;
         make_child(F.key(tag), step, S, L->bpid[l], L->bj[l], L->beps[l], c);
-        if (q.q.sw) q.q.sw[slot] = tag;
-        q.q.x[slot] = L->b[0][l];
-        q.q.y[slot] = L->b[1][l];
-        q.q.z[slot] = L->b[2][l];
-        q.q.vx[slot] = c.vx;
-        q.q.vy[slot] = c.vy;
-        q.q.vz[slot] = c.vz;
-        q.q.w[slot] = L->b[3][l];
-        q.q.tb[slot] = L->b[4][l];
-        q.q.id[slot] = c.id;
+        const PendSoa Q = q.qk.get();
+        if (Q.sw) Q.sw[slot] = tag;
+        Q.x[slot] = L->b[0][l];
+        Q.y[slot] = L->b[1][l];
+        Q.z[slot] = L->b[2][l];
+        Q.vx[slot] = c.vx;
+        Q.vy[slot] = c.vy;
+        Q.vz[slot] = c.vz;
+        Q.w[slot] = L->b[3][l];
+        Q.tb[slot] = L->b[4][l];
+        Q.id[slot] = c.id;
       } else {
         atomicOr(q.overflow, OVF_CAPACITY);
       }
     }
     if (cum_ion) group_count(cum_ion, tag, mine);
-    if (q.ev.ix) {  // the positive ions of the flushed births
+    const EventSink ev = q.evk.get();
+    if (ev.ix) {  // the positive ions of the flushed births
       unsigned long long eb = 0;
-      if (lane_id() == 0) eb = atomicAdd(q.ev.n, (unsigned long long)n);
+      if (lane_id() == 0) eb = atomicAdd(ev.n, (unsigned long long)n);
       const uint64_t e0 = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(eb >> 32)) << 32) |
                           __builtin_amdgcn_readfirstlane((uint32_t)eb);
       if (mine) {
         const uint64_t es = e0 + l;
-        if (es < q.ev.cap) {
-          q.ev.ix[es] = L->b[0][l];
-          q.ev.iy[es] = L->b[1][l];
-          q.ev.iz[es] = L->b[2][l];
-          q.ev.iw[es] = L->b[3][l];
+        if (es < ev.cap) {
+          ev.ix[es] = L->b[0][l];
+          ev.iy[es] = L->b[1][l];
+          ev.iz[es] = L->b[2][l];
+          ev.iw[es] = L->b[3][l];
         } else {
-          atomicOr(q.ev.overflow, OVF_CAPACITY);
+          atomicOr(ev.overflow, OVF_CAPACITY);
         }
       }
     }
@@ -292,7 +295,7 @@ __device__ __forceinline__ int flight_plan(Flight& f, double dt, const Tab& T, c
   // Single-precision square roots and reciprocals to about one ulp: the
   // majorant's 2^-16 guard covers them, and the free-flight time only needs
   // single precision.
-  const float speed = __builtin_amdgcn_sqrtf(vf.x * vf.x + vf.y * vf.y + vf.z * vf.z);
+  const float speed = __builtin_amdgcn_sqrtf(fmaf(vf.z, vf.z, fmaf(vf.y, vf.y, vf.x * vf.x)));
   const TabConst tc = tab_const();
   const float nu_full = majorant_t(T, tc, speed_bound(vf, af, speed, f.a_abs, f.da, (float)t_rem));
   const bool limited = kKappa < nu_full * (float)t_rem;
@@ -316,9 +319,9 @@ __device__ __forceinline__ int flight_plan(Flight& f, double dt, const Tab& T, c
   f.r3 = r.w;
   f.nu_hat = nu_hat;
   f.h = hs;
-  f.x += hs * fma(0.5 * f.ax, hs, f.vx);
-  f.y += hs * fma(0.5 * f.ay, hs, f.vy);
-  f.z += hs * fma(0.5 * f.az, hs, f.vz);
+  f.x = fma(hs, fma(0.5 * f.ax, hs, f.vx), f.x);
+  f.y = fma(hs, fma(0.5 * f.ay, hs, f.vy), f.y);
+  f.z = fma(hs, fma(0.5 * f.az, hs, f.vz), f.z);
   if (f.seg != SEG_END) f.t += hs;
   return EV_GO;
 }
@@ -340,9 +343,9 @@ __device__ __forceinline__ int flight_complete(Flight& f, const double3 an, cons
 
   // Candidate collision: real process k, or null.
   const TabConst tc = tab_const();
-  const double v2 = f.vx * f.vx + f.vy * f.vy + f.vz * f.vz;
+  const double v2 = fma(f.vz, f.vz, fma(f.vy, f.vy, f.vx * f.vx));
   const double eps = tc.k_eps_d * v2;
-  float u = __log2f((float)eps) * tc.u_scale + tc.u_offset;
+  float u = fmaf(__log2f((float)eps), tc.u_scale, tc.u_offset);
   u = fminf(fmaxf(u, 0.0f), tc.u_top);
   const float fl = fminf(floorf(u), tc.fl_top);
   const int i = (int)fl;
@@ -374,8 +377,8 @@ __device__ __forceinline__ int flight_complete(Flight& f, const double3 an, cons
   const double thr = (double)T.thr[k];
   double eps_new;
   if (kind == ELASTIC) {
-    const double cchi = v2 > 0.0 ? (f.vx * nx + f.vy * ny + f.vz * nz) * rsqrt_nr(v2) : 0.0;
-    eps_new = eps * (1.0 - (double)tc.recoil * (1.0 - cchi));
+    const double cchi = v2 > 0.0 ? fma(f.vz, nz, fma(f.vy, ny, f.vx * nx)) * rsqrt_nr(v2) : 0.0;
+    eps_new = eps * fma(-(double)tc.recoil, 1.0 - cchi, 1.0);
   } else if (kind == EXCITATION) {
     eps_new = eps - thr;
   } else {
@@ -476,7 +479,7 @@ __device__ __forceinline__ void fly_all(uint64_t n, unsigned long long* take, do
         f.ax = an.x;
         f.ay = an.y;
         f.az = an.z;
-        F.bound_at(where, f.tag, sqrtf((float)(f.vx * f.vx + f.vy * f.vy + f.vz * f.vz)), (float)(dt - f.t),
+        F.bound_at(where, f.tag, sqrtf((float)fma(f.vz, f.vz, fma(f.vy, f.vy, f.vx * f.vx))), (float)(dt - f.t),
                    f.a_abs, f.da);
         f.mode = FM_FLY;
         ev = EV_GO;

@@ -194,6 +194,7 @@ struct SwarmArgs {
   int sample_every;
   int n_samples;
   int pop_control;
+  EventSink ev;  // no event lists (the newborn queues' event view)
 };
 
 // Coefficient surrogate (1 -> 64 -> 64 -> 6 perceptron).

@@ -34,21 +34,21 @@ namespace pcmcc {
 
 // Phase 1 source: the current buffer, every electron from t = 0.
 struct SoaSource {
-  Soa s;
+  KArg<Soa> sk;
   __device__ __forceinline__ void load(uint64_t i, Flight& f) const {
     PState p;
-    load_p(s, i, p);
+    load_p(sk.get(), i, p);
     flight_start(f, p, 0.0, (uint32_t)i);
   }
 };
 
 // Phase 2 source: a newborn queue, each electron from its birth time.
 struct PendSource {
-  PendSoa s;
+  KArg<PendSoa> sk;
   __device__ __forceinline__ void load(uint64_t i, Flight& f) const {
     PState p;
     float tb;
-    load_pend(s, i, p, tb);
+    load_pend(sk.get(), i, p, tb);
     flight_start(f, p, (double)tb, (uint32_t)i);
   }
 };
@@ -69,23 +69,26 @@ __device__ __forceinline__ void record_attachment(const EventSink& ev, const Fli
 }
 
 struct KeepInPlace {
-  const GridView* G;
-  Soa nxt;
+  KArg<GridView> G;
+  KArg<Soa> nxt;
   uint32_t* holes;
   unsigned long long* n_holes;
-  EventSink ev;
+  KArg<EventSink> ev;
   __device__ __forceinline__ void done_all(const Flight& f, bool parked, Cnt& cnt, WaveStage* L,
                                            uint32_t n_staged, bool& staged) const {
     if (!parked) return;
-    if (f.seg == EV_ATTACHED && ev.ax) record_attachment(ev, f);
+    if (f.seg == EV_ATTACHED) {
+      const EventSink e = ev.get();
+      if (e.ax) record_attachment(e, f);
+    }
     const PState p = flight_record(f);
     bool alive = f.seg == EV_DONE;
-    if (alive && !inside(*G, p)) {
+    if (alive && !inside(G.get(), p)) {
       alive = false;
       cnt.v[C_LOST]++;
     }
     if (alive) {
-      store_p(nxt, f.src, p);
+      store_p(nxt.get(), f.src, p);
     } else {
       const uint32_t s = n_staged + rank_in(__ballot(1));
       if (s < kStage) {
@@ -110,27 +113,30 @@ struct KeepInPlace {
 // after the current count once the holes are used up (placements are staged
 // per wave).
 struct PlaceNewborn {
-  const GridView* G;
-  Soa nxt;
+  KArg<GridView> G;
+  KArg<Soa> nxt;
   const uint32_t* holes;
   uint64_t n_holes, n_cur, cap;
   unsigned long long* child;
   unsigned* overflow;
-  EventSink ev;
+  KArg<EventSink> ev;
   __device__ __forceinline__ void place(uint64_t slot, const PState& p) const {
     const uint64_t dst = slot < n_holes ? (uint64_t)holes[slot] : n_cur + (slot - n_holes);
     if (dst < cap)
-      store_p(nxt, dst, p);
+      store_p(nxt.get(), dst, p);
     else
       atomicOr(overflow, OVF_CAPACITY);
   }
   __device__ __forceinline__ void done_all(const Flight& f, bool parked, Cnt& cnt, WaveStage* L,
                                            uint32_t n_staged, bool& staged) const {
     if (!parked) return;
-    if (f.seg == EV_ATTACHED && ev.ax) record_attachment(ev, f);
+    if (f.seg == EV_ATTACHED) {
+      const EventSink e = ev.get();
+      if (e.ax) record_attachment(e, f);
+    }
     const PState p = flight_record(f);
     bool alive = f.seg == EV_DONE;
-    if (alive && !inside(*G, p)) {
+    if (alive && !inside(G.get(), p)) {
       alive = false;
       cnt.v[C_LOST]++;
     }
@@ -189,8 +195,11 @@ __global__ __launch_bounds__(256) void k_pic_steps(PicArgs A) {
 
   for (int s = 0; s < A.n_steps; ++s) {
     if (ld_acq(&ctl->stop)) break;
-    const int sel = ld_acq(&ctl->cur_sel);
-    const Soa cur = A.buf[sel], nxt = A.buf[sel ^ 1];
+    const int sel = __builtin_amdgcn_readfirstlane(ld_acq(&ctl->cur_sel));  // grid-uniform
+    const Soa nxt = A.buf[sel ^ 1];
+    const KArg<Soa> cur_k{&ka->buf[sel]}, nxt_k{&ka->buf[sel ^ 1]};
+    const KArg<GridView> grid_k{&ka->G};
+    const KArg<EventSink> ev_k{&ka->ev};
     const uint64_t n_cur = ld_acq(&ctl->n_cur);
     const uint32_t step = A.step0 + (uint32_t)s;
     Cnt cnt;
@@ -199,9 +208,9 @@ __global__ __launch_bounds__(256) void k_pic_steps(PicArgs A) {
 
     // Phase 1: every particle of the current buffer, from t = 0.
     {
-      const BirthSink sink{A.pend[0], &ctl->pend[0], A.pend_cap, &ctl->overflow, 0u, A.ev};
-      const SoaSource src{cur};
-      const KeepInPlace fin{&A.G, nxt, A.holes, &ctl->holes, A.ev};
+      const BirthSink sink{{&ka->pend[0]}, &ctl->pend[0], A.pend_cap, &ctl->overflow, 0u, ev_k};
+      const SoaSource src{cur_k};
+      const KeepInPlace fin{grid_k, nxt_k, A.holes, &ctl->holes, ev_k};
       fly_all(n_cur, &ctl->take[0], A.dt, F, T, A.S, step, cnt, sink, nullptr, L, src, fin);
     }
     grid.sync();
@@ -217,9 +226,9 @@ __global__ __launch_bounds__(256) void k_pic_steps(PicArgs A) {
         break;
       }
       const uint64_t np = np_raw < A.pend_cap ? np_raw : A.pend_cap;
-      const BirthSink sink{A.pend[(g + 1) & 1], &ctl->pend[g + 1], A.pend_cap, &ctl->overflow, 0u, A.ev};
-      const PendSource src{A.pend[g & 1]};
-      const PlaceNewborn fin{&A.G, nxt, A.holes, h, n_cur, A.cap, &ctl->child, &ctl->overflow, A.ev};
+      const BirthSink sink{{&ka->pend[(g + 1) & 1]}, &ctl->pend[g + 1], A.pend_cap, &ctl->overflow, 0u, ev_k};
+      const PendSource src{{&ka->pend[g & 1]}};
+      const PlaceNewborn fin{grid_k, nxt_k, A.holes, h, n_cur, A.cap, &ctl->child, &ctl->overflow, ev_k};
       fly_all(np, &ctl->take[g + 1], A.dt, F, T, A.S, step, cnt, sink, nullptr, L, src, fin);
       grid.sync();
     }
@@ -511,7 +520,7 @@ __global__ void k_lookup(TableView TV, SpeciesView S, const float* __restrict__ 
   const Tab T = stage_tables(TV, S, smem);
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
     const float e = eps[q];
-    float u = __log2f(e) * T.u_scale + T.u_offset;
+    float u = fmaf(__log2f(e), T.u_scale, T.u_offset);
     u = fminf(fmaxf(u, 0.0f), (float)(T.n - 1));
     const float fl = fminf(floorf(u), (float)(T.n - 2));
     const int i = (int)fl;

@@ -77,17 +77,38 @@ __device__ __forceinline__ void load_pend(const PendSoa& s, uint64_t i, PState& 
   tb = s.tb[i];
 }
 
-// Queue of newborns of one generation.
+// A structure in the launch's kernel-argument memory, read where it is used
+// (scalar loads through a pointer made opaque there) instead of being held in
+// scalar registers for the whole mover loop: the mover's loop-invariant
+// pointer sets exceed the scalar registers of a wave, and spilled ones come
+// back one v_readlane (a vector instruction) each.
+template <class T>
+struct KArg {
+  const __attribute__((address_space(4))) T* p;
+  __device__ __forceinline__ T get() const {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const __attribute__((address_space(4))) T* q = p;
+    asm volatile("" : "+s"(q));
+    return *q;
+#else
+    return T{};  // host pass: never called
+#endif
+  }
+};
+
+// Queue of newborns of one generation (arrays and event lists in
+// kernel-argument memory).
 struct BirthSink {
-  PendSoa q;
+  KArg<PendSoa> qk;
   unsigned long long* count;
   uint64_t cap;
   unsigned* overflow;
   uint32_t tag;  // swarm index of the items being advanced (swarm queues only)
-  EventSink ev{};
+  KArg<EventSink> evk;
   __device__ __forceinline__ void push(const PState& c, float tb) const {
     const uint64_t slot = wave_reserve(count);
     if (slot < cap) {
+      const PendSoa q = qk.get();
       if (q.sw) q.sw[slot] = tag;
       q.x[slot] = c.x;
       q.y[slot] = c.y;
@@ -219,7 +240,7 @@ __device__ __forceinline__ int pick_process(const float c[kMaxProc], float y) {
 __device__ __forceinline__ float majorant_t(const Tab& T, const TabConst& c, float s_ub) {
   const float s = s_ub * kGuard;
   const float eps = c.k_eps * s * s;
-  float u = __log2f(eps) * c.u_scale + c.u_offset;
+  float u = fmaf(__log2f(eps), c.u_scale, c.u_offset);
   u = fminf(fmaxf(u, 0.0f), c.u_top);
   const float fl = fminf(floorf(u), c.fl_top);
   const int i = (int)fl;
@@ -252,11 +273,11 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
 // of 1, so 1/sqrt(s2) = 3/2 - s2/2 to about 1e-13: |n| = 1 to that accuracy.
 __device__ __forceinline__ void iso_dir(uint32_t r1, uint32_t r2, double& nx, double& ny, double& nz) {
   const double u = (double)unif(r1);
-  const double cth = 1.0 - 2.0 * u;
+  const double cth = fma(-2.0, u, 1.0);
   const double sth = 2.0 * sqrt(u * (1.0 - u));
   float sp, cp;
   sincospif(2.0f * unif(r2), &sp, &cp);
-  const double s2 = (double)cp * cp + (double)sp * sp;
+  const double s2 = fma((double)sp, (double)sp, (double)cp * cp);
   const double inv = sth * fma(-0.5, s2, 1.5);
   nx = inv * cp;
   ny = inv * sp;

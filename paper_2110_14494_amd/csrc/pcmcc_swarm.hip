@@ -52,7 +52,7 @@ __device__ __forceinline__ int swarm_of(const uint32_t* prefix, int S, uint32_t 
 // they are loaded: keep with probability 2^-k, or duplicate (the duplicate
 // joins the newborn queue and starts from t = 0).
 struct SwarmLoad {
-  Soa cur;
+  KArg<Soa> cur;
   const uint64_t* base;
   const uint32_t* prefix;
   const int* pck;
@@ -65,7 +65,7 @@ struct SwarmLoad {
     const int s = swarm_of(prefix, n_swarms, (uint32_t)g);
     const uint64_t i = g - prefix[s];
     PState p;
-    load_p(cur, base[s] + i, p);
+    load_p(cur.get(), base[s] + i, p);
     const int k = pck[s];
     bool keep = true;
     if (k != 0) {
@@ -89,10 +89,11 @@ struct SwarmLoad {
 
 // Phase 2 source: the newborn queue (with swarm indices and birth times).
 struct SwarmPend {
-  PendSoa q;
+  KArg<PendSoa> qk;
   __device__ __forceinline__ void load(uint64_t i, Flight& f) const {
     PState p;
     float tb;
+    const PendSoa q = qk.get();
     load_pend(q, i, p, tb);
     flight_start(f, p, (double)tb, 0u, q.sw[i]);
   }
@@ -102,7 +103,7 @@ struct SwarmPend {
 // buffer (staged per wave, one atomic per swarm and batch); attachments are
 // counted per swarm.
 struct SwarmPlace {
-  Soa nxt;
+  KArg<Soa> nxt;
   const uint64_t* base;
   const uint64_t* cap_s;
   unsigned long long* n_nxt;
@@ -128,7 +129,7 @@ struct SwarmPlace {
     } else {
       const uint64_t slot = atomicAdd(&n_nxt[f.tag], 1ull);
       if (slot < cap_s[f.tag])
-        store_p(nxt, base[f.tag] + slot, p);
+        store_p(nxt.get(), base[f.tag] + slot, p);
       else
         atomicOr(overflow, OVF_CAPACITY);
     }
@@ -149,7 +150,7 @@ struct SwarmPlace {
       p.vz = L->s[5][l];
       p.w = L->s[6][l];
       p.id = L->sid[l];
-      store_p(nxt, base[s] + slot, p);
+      store_p(nxt.get(), base[s] + slot, p);
     } else {
       atomicOr(overflow, OVF_CAPACITY);
     }
@@ -257,14 +258,17 @@ __global__ __launch_bounds__(BS) void k_swarm_steps(SwarmArgs A) {
   }
   __syncthreads();
   const SwarmField F{az_d, az_l, A.key};
+  const auto* ka = (const __attribute__((address_space(4))) SwarmArgs*)__builtin_amdgcn_kernarg_segment_ptr();
+  const KArg<EventSink> no_events{&ka->ev};
   const unsigned lane = lane_id();
   const uint32_t wpb = BS / 64;
   SwarmCtl* ctl = A.ctl;
 
   for (int st = 0; st < A.n_steps; ++st) {
     if (ld_acq(&ctl->stop)) break;
-    const int sel = ld_acq(&ctl->cur_sel);
-    const Soa cur = A.buf[sel], nxt = A.buf[sel ^ 1];
+    const int sel = __builtin_amdgcn_readfirstlane(ld_acq(&ctl->cur_sel));  // grid-uniform
+    const Soa nxt = A.buf[sel ^ 1];
+    const KArg<Soa> cur_k{&ka->buf[sel]}, nxt_k{&ka->buf[sel ^ 1]};
     const uint32_t step = (uint32_t)st;
     for (int s = threadIdx.x; s < S; s += BS) pck[s] = ld_acq(&A.pc_k[s]);
     tile_prefix(A.n_cur, S, 1, prefix, tmp);
@@ -272,13 +276,12 @@ __global__ __launch_bounds__(BS) void k_swarm_steps(SwarmArgs A) {
 #pragma unroll
     for (int k = 0; k < NCNT; ++k) cnt.v[k] = 0;
     uint32_t psteps = 0;
-    const SwarmPlace fin{nxt, A.base, A.cap_s, A.n_nxt, A.cum_att, &ctl->overflow};
+    const SwarmPlace fin{nxt_k, A.base, A.cap_s, A.n_nxt, A.cum_att, &ctl->overflow};
 
     // Phase 1: each swarm's electrons, after population control, from t = 0.
     {
-      const BirthSink sink{A.pend[0], &ctl->pend[0], A.pend_cap, &ctl->overflow, 0u};
-      const SwarmLoad src{cur,  A.base, prefix, pck, S, A.key, step,
-                          BirthSink{A.pend[0], &ctl->pend[0], A.pend_cap, &ctl->overflow, 0u}, &psteps};
+      const BirthSink sink{{&ka->pend[0]}, &ctl->pend[0], A.pend_cap, &ctl->overflow, 0u, no_events};
+      const SwarmLoad src{cur_k, A.base, prefix, pck, S, A.key, step, sink, &psteps};
       fly_all((uint64_t)prefix[S], &ctl->take[0], (double)A.dt, F, T, A.S, step, cnt, sink, A.cum_ion, L, src,
               fin);
     }
@@ -293,8 +296,8 @@ __global__ __launch_bounds__(BS) void k_swarm_steps(SwarmArgs A) {
         break;
       }
       const uint64_t np = np_raw < A.pend_cap ? np_raw : A.pend_cap;
-      const BirthSink sink{A.pend[(g + 1) & 1], &ctl->pend[g + 1], A.pend_cap, &ctl->overflow, 0u};
-      const SwarmPend src{A.pend[g & 1]};
+      const BirthSink sink{{&ka->pend[(g + 1) & 1]}, &ctl->pend[g + 1], A.pend_cap, &ctl->overflow, 0u, no_events};
+      const SwarmPend src{{&ka->pend[g & 1]}};
       fly_all(np, &ctl->take[g + 1], (double)A.dt, F, T, A.S, step, cnt, sink, A.cum_ion, L, src, fin);
       grid.sync();
     }
@@ -338,7 +341,7 @@ __global__ __launch_bounds__(BS) void k_swarm_steps(SwarmArgs A) {
           const double eps = A.S.k_eps_d * v2;
           double nu_ion = 0.0, nu_att = 0.0;
           {
-            float u = __log2f((float)eps) * T.u_scale + T.u_offset;
+            float u = fmaf(__log2f((float)eps), T.u_scale, T.u_offset);
             u = fminf(fmaxf(u, 0.0f), (float)(T.n - 1));
             const float fl = fminf(floorf(u), (float)(T.n - 2));
             const int ii = (int)fl;

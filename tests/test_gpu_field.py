@@ -99,6 +99,12 @@ def test_speed_quantile_exact(pic, n):
     assert got == F.v90(*v)
 
 
+def qsum(a):
+    """Exact sum of fixed-point charge counts (an int64 sum overflows at
+    thousands of electrons of weight 1e6, each 1e6 * 2^32)."""
+    return int(np.asarray(a).astype(object).sum())
+
+
 def _coupled_case(n=3000, w=1e4):
     cfg = W.plain_swarm_config(n=n)
     cfg["grid"] = W.uniform_grid(16, 80e-6, (0.0, 0.0, 1.0e7))
@@ -157,12 +163,12 @@ def test_coupled_steps_match_oracle(pic):
     assert res["flips"] <= max(1e-4 * gpu["stats"]["trials"], 2), res
     # the same ion charge created up to the flipped lineages, exact balance
     tol = (res["flips"] + 2) * int(w) * 2 ** 32
-    assert abs(int(gpu["n_pos"].sum()) - int(n_pos_o.sum())) <= tol
-    assert abs(int(gpu["n_neg"].sum()) - int(n_neg_o.sum())) <= tol
+    assert abs(qsum(gpu["n_pos"]) - qsum(n_pos_o)) <= tol
+    assert abs(qsum(gpu["n_neg"]) - qsum(n_neg_o)) <= tol
     n_e_g = oracle.deposit(g["x"], g["y"], g["z"], g["w"], grid)
     n_e_0 = oracle.deposit(*(np.asarray(_coupled_case(w=w)[1][k]) for k in ("x", "y", "z", "w")), grid)
     # ions created = electrons gained (no electron left the box)
-    assert int(gpu["n_pos"].sum()) - int(gpu["n_neg"].sum()) == int(n_e_g.sum()) - int(n_e_0.sum())
+    assert qsum(gpu["n_pos"]) - qsum(gpu["n_neg"]) == qsum(n_e_g) - qsum(n_e_0)
     scale = np.max(np.abs(info["E"]))
     assert np.max(np.abs(gpu["E"] - info["E"])) <= 1e-5 * scale
     # the space charge matters at this weight: the field is not the applied one
@@ -179,19 +185,22 @@ def test_coupled_adaptive_steps_match_oracle_in_ensemble(pic):
     w, steps = 1e6, 8
     grid, gpu, (o, n_pos_o, n_neg_o, info) = _run_pair(pic, w, 1e-10, steps, adaptive=True)
     g = gpu["parts"]
-    assert np.allclose(gpu["dt"], info["dt"], rtol=1e-4, atol=0)
-    assert math.isclose(gpu["next_dt"], info["next_dt"], rel_tol=1e-4)
+    # The growth limit divides by ln(N_new / N_old) ~ ln 1.2, so each electron
+    # that a flipped lineage adds or removes moves the next step by about
+    # 1 / (N ln 1.2) ~ 1.4e-3 at N ~ 4000: the bar allows a few such electrons.
+    assert np.allclose(gpu["dt"], info["dt"], rtol=1e-2, atol=0)
+    assert math.isclose(gpu["next_dt"], info["next_dt"], rel_tol=1e-2)
     assert min(info["dt"][1:]) < 0.05 * 1e-10  # the limits were active
     assert abs(g["x"].size / o["x"].size - 1) < 0.01
     for a, b in ((gpu["n_pos"], n_pos_o), (gpu["n_neg"], n_neg_o)):
-        assert abs(int(a.sum()) - int(b.sum())) <= 0.01 * max(int(b.sum()), int(w) * 2 ** 32)
+        assert abs(qsum(a) - qsum(b)) <= 0.01 * max(qsum(b), int(w) * 2 ** 32)
     ke = lambda d: float(np.mean(np.asarray(d["vx"], np.float64) ** 2 + np.asarray(d["vy"], np.float64) ** 2 +
                                  np.asarray(d["vz"], np.float64) ** 2))
     assert abs(ke(g) / ke(o) - 1) < 0.02
     scale = np.max(np.abs(info["E"]))
     assert np.max(np.abs(gpu["E"] - info["E"])) <= 0.05 * scale
     n_e_g = oracle.deposit(g["x"], g["y"], g["z"], g["w"], grid)
-    assert int(gpu["n_pos"].sum()) - int(n_e_g.sum()) - int(gpu["n_neg"].sum()) == 0
+    assert qsum(gpu["n_pos"]) - qsum(n_e_g) - qsum(gpu["n_neg"]) == 0
 
 
 def test_error_paths(pic):
@@ -269,10 +278,10 @@ def test_streamer_full_size_two_coupled_steps(pic):
     assert res["flips"] <= max(1e-4 * st["trials"], 2), res
     assert res["matched"] >= 0.999 * o["id"].size
     tol = (res["flips"] + 2) * int(np.max(parts["w"])) * 2 ** 32
-    assert abs(int(gp.sum()) - int(n_pos_o.sum())) <= tol
-    assert abs(int(gn.sum()) - int(n_neg_o.sum())) <= tol
+    assert abs(qsum(gp) - qsum(n_pos_o)) <= tol
+    assert abs(qsum(gn) - qsum(n_neg_o)) <= tol
     n_e = oracle.deposit(g["x"], g["y"], g["z"], g["w"], grid)
-    assert int(gp.sum()) - int(gn.sum()) == int(n_e.sum())  # neutral: ions = electrons, exactly
+    assert qsum(gp) - qsum(gn) == qsum(n_e)  # neutral: ions = electrons, exactly
     scale = np.max(np.abs(info["E"]))
     assert np.max(np.abs(Eg - info["E"])) <= 1e-5 * scale
     # the second step's field is not the applied one
