@@ -114,6 +114,8 @@ typedef struct pcmcc_stats {
   uint64_t majorant_violations;  /* candidate collisions whose total rate exceeded the majorant of their flight
                                     segment (the null-collision method, Sec. 2.1.1, needs 0; a nonzero count
                                     means the majorant rule is wrong) */
+  int32_t launch_refill;         /* refill threshold of the step loop kernel (see pcmcc_schedule) */
+  int32_t launch_chunk;          /* work-counter chunk of the step loop kernel */
 } pcmcc_stats;
 
 /* Version string, static storage. */
@@ -175,6 +177,44 @@ int pcmcc_init_tables(pcmcc_ctx* ctx, int n_e, double eps_min_eV, double eps_max
 int pcmcc_push_collide_deposit(pcmcc_ctx* ctx, const pcmcc_particles* p, const pcmcc_grid* field, double dt,
                                int n_steps, uint64_t seed, uint64_t step0, int64_t* rho, pcmcc_stats* stats);
 
+/* ---- Schedule of the step kernel ------------------------------------------
+ * How the electrons of a step are spread over the GPU; it changes the time
+ * of pcmcc_push_collide_deposit (and of the calls built on it), never its
+ * results (random numbers follow the electron ids, not the schedule).  A
+ * zero field takes the default. */
+typedef struct pcmcc_schedule {
+  int block;          /* threads per block: 64, 128, 256 or 512; 0 = the size with the most resident waves per
+                         compute unit (ties: the larger block) */
+  int blocks_per_cu;  /* persistent blocks per compute unit; 0 = as many as fit */
+  int refill_min;     /* free lanes of a wave that trigger a finish-and-refill batch: 16, 24 or 32; 0 = 24 */
+  int chunk;          /* electrons a wave takes from the work counter at a time: a power of two in [64, 4096];
+                         0 = 256 */
+} pcmcc_schedule;
+
+/* Sets the schedule of later steps on ctx (s NULL: all defaults).
+ * PCMCC_EINVAL for a value outside the ranges above. */
+int pcmcc_set_schedule(pcmcc_ctx* ctx, const pcmcc_schedule* s);
+
+/* The schedule the next step call on ctx uses for this field's tables and
+ * block limits, every field resolved (host *out). */
+int pcmcc_get_schedule(pcmcc_ctx* ctx, pcmcc_schedule* out);
+
+/* Launch-shape tuner of the step kernel: times n_steps steps (seed, step0
+ * as pcmcc_push_collide_deposit, no deposit) of the particles p in `field`
+ * under each candidate schedule -- the default, then block x blocks per
+ * compute unit, then refill threshold x chunk at the best shape so far --
+ * and sets the fastest on ctx.  p is restored to its input state (the tuner
+ * allocates one copy of it).  With tune_cache (a JSON file, or NULL) a
+ * schedule stored for the same workload key (particle count rounded to a
+ * power of two, grid size, tables) is taken without timing, and a new one
+ * is stored.  chosen (host, nullable) receives the schedule; tuned_ms and
+ * default_ms (host, nullable) the step-kernel times of the chosen and the
+ * default schedule (both 0 when taken from the cache).  Errors as
+ * pcmcc_push_collide_deposit; synchronises the stream. */
+int pcmcc_autotune_steps(pcmcc_ctx* ctx, const pcmcc_particles* p, const pcmcc_grid* field, double dt, int n_steps,
+                         uint64_t seed, uint64_t step0, const char* tune_cache, pcmcc_schedule* chosen,
+                         float* tuned_ms, float* default_ms);
+
 /* ---- Batched uniform-field swarms (Sec. 2.2.2) ---------------------------
  * Swarm s starts with n0[s] electrons at rest at the origin in the field
  * E = EN_Td[s] * 1e-21 * N along +z and is advanced n_steps steps of dt with
@@ -225,6 +265,8 @@ typedef struct pcmcc_swarm_opts {
   int blocks_per_cu;       /* persistent blocks per compute unit; 0 = tuned or default */
   int autotune;            /* 1: time the candidate shapes on this input and keep the fastest */
   const char* tune_cache;  /* JSON file the tuned shapes are read from and written to, or NULL */
+  int refill_min;          /* as pcmcc_schedule; 0 = tuned or 24 */
+  int chunk;               /* as pcmcc_schedule; 0 = tuned or 256 */
 } pcmcc_swarm_opts;
 
 typedef struct pcmcc_swarm_result {

@@ -40,7 +40,8 @@ class pcmcc_stats(C.Structure):
                 ("launch_block", C.c_int32), ("launch_grid", C.c_int32), ("weight_updates", C.c_int64),
                 ("merged_pairs", C.c_int64), ("splits", C.c_int64), ("weight_ms", C.c_double),
                 ("field_ms", C.c_double), ("mg_cycles", C.c_int64), ("photons", C.c_int64),
-                ("photoelectrons", C.c_int64), ("photo_ms", C.c_double), ("majorant_violations", C.c_uint64)]
+                ("photoelectrons", C.c_int64), ("photo_ms", C.c_double), ("majorant_violations", C.c_uint64),
+                ("launch_refill", C.c_int32), ("launch_chunk", C.c_int32)]
 
     def as_dict(self) -> dict:
         r = list(self.real_collisions)
@@ -53,7 +54,16 @@ class pcmcc_stats(C.Structure):
                 "weight_updates": self.weight_updates, "merged_pairs": self.merged_pairs, "splits": self.splits,
                 "weight_ms": self.weight_ms, "field_ms": self.field_ms, "mg_cycles": self.mg_cycles,
                 "photons": self.photons, "photoelectrons": self.photoelectrons, "photo_ms": self.photo_ms,
-                "majorant_violations": self.majorant_violations}
+                "majorant_violations": self.majorant_violations, "launch_refill": self.launch_refill,
+                "launch_chunk": self.launch_chunk}
+
+
+class pcmcc_schedule(C.Structure):
+    _fields_ = [("block", C.c_int), ("blocks_per_cu", C.c_int), ("refill_min", C.c_int), ("chunk", C.c_int)]
+
+    def as_dict(self) -> dict:
+        return {"block": self.block, "blocks_per_cu": self.blocks_per_cu, "refill_min": self.refill_min,
+                "chunk": self.chunk}
 
 
 SWARM_QUANTITIES = ("W_flux", "W_bulk", "DL_flux", "DL_bulk", "DT_flux", "DT_bulk", "nu_ion", "nu_att",
@@ -80,7 +90,8 @@ class pcmcc_fluid_table(C.Structure):
 class pcmcc_swarm_opts(C.Structure):
     _fields_ = [("sample_every", C.c_int), ("window_start_s", C.c_double), ("n_batches", C.c_int),
                 ("cap_factor", C.c_int), ("population_control", C.c_int), ("block", C.c_int),
-                ("blocks_per_cu", C.c_int), ("autotune", C.c_int), ("tune_cache", C.c_char_p)]
+                ("blocks_per_cu", C.c_int), ("autotune", C.c_int), ("tune_cache", C.c_char_p),
+                ("refill_min", C.c_int), ("chunk", C.c_int)]
 
 
 class pcmcc_swarm_result(C.Structure):
@@ -130,6 +141,11 @@ def lib() -> C.CDLL:
             "pcmcc_init_tables": ([vp, C.c_int, C.c_double, C.c_double, C.c_int, vp, vp, vp, C.c_int], C.c_int),
             "pcmcc_push_collide_deposit": ([vp, C.POINTER(pcmcc_particles), C.POINTER(pcmcc_grid), C.c_double,
                                             C.c_int, u64, u64, vp, C.POINTER(pcmcc_stats)], C.c_int),
+            "pcmcc_set_schedule": ([vp, C.POINTER(pcmcc_schedule)], C.c_int),
+            "pcmcc_get_schedule": ([vp, C.POINTER(pcmcc_schedule)], C.c_int),
+            "pcmcc_autotune_steps": ([vp, C.POINTER(pcmcc_particles), C.POINTER(pcmcc_grid), C.c_double, C.c_int,
+                                      u64, u64, C.c_char_p, C.POINTER(pcmcc_schedule), C.POINTER(C.c_float),
+                                      C.POINTER(C.c_float)], C.c_int),
             "pcmcc_deposit": ([vp, vp, vp, vp, vp, vp, C.POINTER(pcmcc_grid), vp], C.c_int),
             "pcmcc_deposit_noalloc": ([vp, vp, vp, vp, vp, vp, C.POINTER(pcmcc_grid), vp], C.c_int),
             "pcmcc_philox4x32_10": ([vp, i64, vp, u64, vp], C.c_int),

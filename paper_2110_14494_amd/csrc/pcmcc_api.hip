@@ -189,6 +189,152 @@ int pcmcc_push_collide_deposit(pcmcc_ctx* c, const pcmcc_particles* p, const pcm
   return push_impl(c, p, field, dt, n_steps, seed, step0, rho, stats, nullptr);
 }
 
+int pcmcc_set_schedule(pcmcc_ctx* c, const pcmcc_schedule* s) {
+  if (!c) return fail(nullptr, PCMCC_EINVAL, "null context");
+  const pcmcc_schedule v = s ? *s : pcmcc_schedule{};
+  const int rc = check_schedule(c, v);
+  if (rc) return rc;
+  c->sched = v;
+  return PCMCC_OK;
+}
+
+int pcmcc_get_schedule(pcmcc_ctx* c, pcmcc_schedule* out) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (!out) return fail(c, PCMCC_EINVAL, "out is null");
+  HIP_TRY(c, hipSetDevice(c->device));
+  StepLaunch L;
+  rc = resolve_launch(c, c->sched, pic_lds_bytes_s, occupancy_pic_steps, table_view(c), 0, &L);
+  if (rc) return rc;
+  *out = pcmcc_schedule{L.block, L.bpc, L.refill, L.chunk};
+  return PCMCC_OK;
+}
+
+int pcmcc_autotune_steps(pcmcc_ctx* c, const pcmcc_particles* p, const pcmcc_grid* field, double dt, int n_steps,
+                         uint64_t seed, uint64_t step0, const char* tune_cache, pcmcc_schedule* chosen,
+                         float* tuned_ms, float* default_ms) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (tuned_ms) *tuned_ms = 0;
+  if (default_ms) *default_ms = 0;
+  if (!p || !p->x || !p->y || !p->z || !p->vx || !p->vy || !p->vz || !p->w || !p->id || !p->n_dev)
+    return fail(c, PCMCC_EINVAL, "null particle array");
+  if (!valid_grid(field)) return fail(c, PCMCC_EINVAL, "invalid field grid");
+  if (n_steps < 1) return fail(c, PCMCC_EINVAL, "n_steps must be >= 1");
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, hipMemcpyAsync(c->host_n, p->n_dev, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const int64_t n0 = *c->host_n;
+  if (n0 < 0 || n0 > p->capacity) return fail(c, PCMCC_EINVAL, "particle count %lld outside [0, capacity]", (long long)n0);
+  char keybuf[200];
+  std::snprintf(keybuf, sizeof(keybuf), "gfx950:k_pic_steps:n2^%d:g%dx%dx%d:ne%d:np%d",
+                n0 > 0 ? (int)std::lround(std::log2((double)n0)) : 0, field->nx, field->ny, field->nz, c->n_e,
+                c->n_proc);
+  const std::string key(keybuf);
+  load_tune_cache(c, tune_cache);
+  if (c->tuned.count(key)) {
+    const auto& t = c->tuned[key];
+    const pcmcc_schedule s{t[0], t[1], t[2], t[3]};
+    StepLaunch L;
+    if (check_schedule(c, s) == PCMCC_OK &&
+        resolve_launch(c, s, pic_lds_bytes_s, occupancy_pic_steps, table_view(c), 0, &L) == PCMCC_OK) {
+      c->sched = s;
+      if (chosen) *chosen = pcmcc_schedule{L.block, L.bpc, L.refill, L.chunk};
+      return PCMCC_OK;
+    }
+    c->err.clear();  // a stored schedule that no longer fits: tune again
+  }
+  // One copy of the input (7 float arrays, the ids, the count), restored
+  // before every candidate and at the end; weight control is off meanwhile.
+  const size_t nn = (size_t)std::max<int64_t>(n0, 1);
+  char* bk = nullptr;
+  HIP_TRY(c, hipMalloc((void**)&bk, nn * 36 + 8));
+  float* const arr[7] = {p->x, p->y, p->z, p->vx, p->vy, p->vz, p->w};
+  auto copy_all = [&](bool save) -> hipError_t {
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < 7 && e == hipSuccess; ++k) {
+      char* b = bk + (size_t)k * nn * 4;
+      e = save ? hipMemcpyAsync(b, arr[k], (size_t)n0 * 4, hipMemcpyDeviceToDevice, c->stream)
+               : hipMemcpyAsync(arr[k], b, (size_t)n0 * 4, hipMemcpyDeviceToDevice, c->stream);
+    }
+    char* bid = bk + 28 * nn;
+    char* bn = bk + 36 * nn;
+    if (e == hipSuccess)
+      e = save ? hipMemcpyAsync(bid, p->id, (size_t)n0 * 8, hipMemcpyDeviceToDevice, c->stream)
+               : hipMemcpyAsync(p->id, bid, (size_t)n0 * 8, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess)
+      e = save ? hipMemcpyAsync(bn, p->n_dev, 8, hipMemcpyDeviceToDevice, c->stream)
+               : hipMemcpyAsync(p->n_dev, bn, 8, hipMemcpyDeviceToDevice, c->stream);
+    return e;
+  };
+  const pcmcc_schedule user = c->sched;
+  const double wc_ppc = c->wc_n_ppc;
+  const int64_t wc_ref = c->wc_n_ref;
+  c->wc_n_ppc = 0;
+  float best = 1e30f, t_default = 0;
+  pcmcc_schedule best_s{};
+  auto time_one = [&](const pcmcc_schedule& s, float* t_out) -> int {
+    StepLaunch L;
+    int r = resolve_launch(c, s, pic_lds_bytes_s, occupancy_pic_steps, table_view(c), 0, &L);
+    if (r) return r;
+    c->sched = s;
+    HIP_TRY(c, copy_all(false));
+    pcmcc_stats st;
+    r = push_impl(c, p, field, dt, n_steps, seed, step0, nullptr, &st, nullptr);
+    if (r) return r;
+    const float t = (float)st.step_kernel_ms;
+    if (t_out) *t_out = t;
+    if (t < best) {
+      best = t;
+      best_s = pcmcc_schedule{L.block, L.bpc, L.refill, L.chunk};
+    }
+    return (int)PCMCC_OK;
+  };
+  auto search = [&]() -> int {
+    HIP_TRY(c, copy_all(true));
+    int r = time_one(pcmcc_schedule{}, &t_default);
+    if (r) return r;
+    for (int b : {64, 128, 256, 512}) {
+      StepLaunch fit;
+      if (resolve_launch(c, pcmcc_schedule{b, 0, 0, 0}, pic_lds_bytes_s, occupancy_pic_steps, table_view(c), 0,
+                         &fit)) {
+        c->err.clear();
+        continue;  // does not fit at this block size
+      }
+      for (int k = 1; k <= fit.bpc; k = (k * 2 > fit.bpc && k < fit.bpc) ? fit.bpc : k * 2) {
+        r = time_one(pcmcc_schedule{b, k, 0, 0}, nullptr);
+        if (r) return r;
+      }
+    }
+    const pcmcc_schedule shape = best_s;
+    for (int rf : kRefillChoices)
+      for (int ch : {128, 256, 512, 1024}) {
+        r = time_one(pcmcc_schedule{shape.block, shape.blocks_per_cu, rf, ch}, nullptr);
+        if (r) return r;
+      }
+    return (int)PCMCC_OK;
+  };
+  rc = search();
+  const hipError_t e = copy_all(false);  // the input state again, also after an error
+  const hipError_t e2 = hipStreamSynchronize(c->stream);
+  (void)hipFree(bk);
+  c->wc_n_ppc = wc_ppc;
+  c->wc_n_ref = wc_ref;
+  if (rc) {
+    c->sched = user;
+    return rc;
+  }
+  HIP_TRY(c, e);
+  HIP_TRY(c, e2);
+  c->sched = best_s;
+  c->tuned[key] = {best_s.block, best_s.blocks_per_cu, best_s.refill_min, best_s.chunk};
+  save_tune_cache(c, tune_cache);
+  if (chosen) *chosen = best_s;
+  if (tuned_ms) *tuned_ms = best;
+  if (default_ms) *default_ms = t_default;
+  return PCMCC_OK;
+}
+
 int pcmcc_set_weight_control(pcmcc_ctx* c, double n_ppc, double growth) {
   if (!c) return fail(nullptr, PCMCC_EINVAL, "null context");
   if (!(n_ppc >= 0) || !std::isfinite(n_ppc) || !(growth >= 1) || !std::isfinite(growth))

@@ -182,6 +182,8 @@ int pcmcc_streamer_steps(pcmcc_ctx* c, const pcmcc_particles* p, const pcmcc_gri
     tot.step_kernel_ms += st.step_kernel_ms;
     tot.launch_block = st.launch_block;
     tot.launch_grid = st.launch_grid;
+    tot.launch_refill = st.launch_refill;
+    tot.launch_chunk = st.launch_chunk;
     tot.weight_updates += st.weight_updates;
     tot.merged_pairs += st.merged_pairs;
     tot.splits += st.splits;

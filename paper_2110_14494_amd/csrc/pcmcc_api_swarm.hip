@@ -6,10 +6,10 @@ extern "C" {
 
 namespace {
 
-// One run of the swarm step loop with a given launch shape (inputs already
-// on the device); the kernel time in ms goes to *ms.
-int swarm_run(pcmcc_ctx* c, SwarmArgs& A, int S, const std::vector<uint64_t>& n0h, int block, int grid,
-              float* ms) {
+// One run of the swarm step loop with a given launch schedule (inputs
+// already on the device); the kernel time in ms goes to *ms.
+int swarm_run(pcmcc_ctx* c, SwarmArgs& A, int S, const std::vector<uint64_t>& n0h, const StepLaunch& L, float* ms) {
+  A.chunk = (uint32_t)L.chunk;
   auto& w = c->sw;
   HIP_TRY(c, hipMemsetAsync(w.n_nxt, 0, sizeof(unsigned long long) * S, c->stream));
   HIP_TRY(c, hipMemsetAsync(w.cum_ion, 0, sizeof(unsigned long long) * S, c->stream));
@@ -22,7 +22,7 @@ int swarm_run(pcmcc_ctx* c, SwarmArgs& A, int S, const std::vector<uint64_t>& n0
   HIP_TRY(c, hipMemcpyAsync(w.n_cur, n0h.data(), sizeof(uint64_t) * S, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, launch_swarm_init(w.buf[0], w.base, w.n0, S, c->stream));
   HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
-  HIP_TRY(c, launch_swarm_steps(A, grid, block, c->stream));
+  HIP_TRY(c, launch_swarm_steps(A, L.grid, L.block, L.refill, c->stream));
   HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
   HIP_TRY(c, hipEventSynchronize(c->ev[1]));
   HIP_TRY(c, hipEventElapsedTime(ms, c->ev[0], c->ev[1]));
@@ -60,27 +60,30 @@ int pcmcc_swarm_batch(pcmcc_ctx* c, int n_swarms, const double* EN_Td, const int
   if (slots > 0xFFFFFFFFull) return fail(c, PCMCC_EINVAL, "total swarm slots exceed 2^32");
   HIP_TRY(c, hipSetDevice(c->device));
   const TableView T = table_view(c);
-  // Launch shape: explicit, tuned (cached), or the default block of 256.
-  const int blocks[4] = {64, 128, 256, 512};
+  // Launch schedule: explicit fields, else the tuned (cached) ones for this
+  // workload, else the defaults.
   char keybuf[160];
   std::snprintf(keybuf, sizeof(keybuf), "gfx950:k_swarm_steps:S%d:N%llu:cap%d:se%d:ne%d:np%d", S,
                 (unsigned long long)(slots / opts->cap_factor), opts->cap_factor, opts->sample_every, c->n_e,
                 c->n_proc);
   const std::string key(keybuf);
   load_tune_cache(c, opts->tune_cache);
-  int block = opts->block, bpc = opts->blocks_per_cu;
-  auto occ = [&](int b) {
-    int k = 0;
-    if (occupancy_swarm_steps(b, swarm_lds_bytes(T, S, b), &k) != hipSuccess) return 0;
-    return k;
-  };
-  if (block == 0 && !opts->autotune && c->tuned.count(key)) {
-    block = c->tuned[key].first;
-    bpc = c->tuned[key].second;
+  pcmcc_schedule want{opts->block, opts->blocks_per_cu, opts->refill_min, opts->chunk};
+  rc = check_schedule(c, want);
+  if (rc) return rc;
+  if (!opts->autotune && c->tuned.count(key)) {
+    const auto& t = c->tuned[key];
+    if (!want.block) {
+      want.block = t[0];
+      if (!want.blocks_per_cu) want.blocks_per_cu = t[1];
+    }
+    if (!want.refill_min) want.refill_min = t[2];
+    if (!want.chunk) want.chunk = t[3];
+    if (check_schedule(c, want)) want = pcmcc_schedule{opts->block, opts->blocks_per_cu, opts->refill_min, opts->chunk};
   }
-  if (block == 0) block = 256;
-  if (block != 64 && block != 128 && block != 256 && block != 512)
-    return fail(c, PCMCC_EINVAL, "block must be 64, 128, 256 or 512");
+  auto resolve = [&](const pcmcc_schedule& s, StepLaunch* L) {
+    return resolve_launch(c, s, swarm_lds_bytes_s, occupancy_swarm_steps, T, S, L);
+  };
   const int max_grid = 32 * c->num_cu;
   rc = ensure_swarm(c, S, slots, J, max_grid);
   if (rc) return rc;
@@ -121,35 +124,58 @@ int pcmcc_swarm_batch(pcmcc_ctx* c, int n_swarms, const double* EN_Td, const int
   A.pop_control = opts->population_control ? 1 : 0;
   float ms = 0;
   if (opts->autotune) {
-    // Time each candidate shape on the first min(n_steps, 200) steps.
+    // Time the candidates on the first min(n_steps, 200) steps: block x
+    // blocks per CU at the default refill and chunk, then refill x chunk at
+    // the fastest shape.
     SwarmArgs probe = A;
     probe.n_steps = std::min(n_steps, 200);
     float best = 1e30f;
-    int best_b = 256, best_k = 1;
-    for (int b : blocks) {
-      const int kmax = std::min(occ(b), 32);
-      for (int k = 1; k <= kmax; k *= 2) {
-        float t = 0;
-        rc = swarm_run(c, probe, S, n0h, b, k * c->num_cu, &t);
+    pcmcc_schedule best_s{};
+    auto time_one = [&](const pcmcc_schedule& s) {
+      StepLaunch L;
+      int r = resolve(s, &L);
+      if (r) return r;
+      float t = 0;
+      r = swarm_run(c, probe, S, n0h, L, &t);
+      if (r) return r;
+      if (t < best) {
+        best = t;
+        best_s = pcmcc_schedule{L.block, L.bpc, L.refill, L.chunk};
+      }
+      return (int)PCMCC_OK;
+    };
+    for (int b : {64, 128, 256, 512}) {
+      StepLaunch fit;
+      if (resolve(pcmcc_schedule{b, 0, 0, 0}, &fit)) {
+        c->err.clear();
+        continue;  // does not fit at this block size
+      }
+      const int kmax = std::min(fit.bpc, 32);
+      for (int k = 1; k <= kmax; k = (k * 2 > kmax && k < kmax) ? kmax : k * 2) {
+        rc = time_one(pcmcc_schedule{b, k, 0, 0});
         if (rc) return rc;
-        if (t < best) {
-          best = t;
-          best_b = b;
-          best_k = k;
-        }
       }
     }
-    block = best_b;
-    bpc = best_k;
-    c->tuned[key] = {block, bpc};
+    const pcmcc_schedule shape = best_s;
+    for (int r : kRefillChoices)
+      for (int ch : {128, 256, 512, 1024}) {
+        rc = time_one(pcmcc_schedule{shape.block, shape.blocks_per_cu, r, ch});
+        if (rc) return rc;
+      }
+    want = best_s;
+    c->tuned[key] = {want.block, want.blocks_per_cu, want.refill_min, want.chunk};
     save_tune_cache(c, opts->tune_cache);
   }
-  const int kmax = std::min(occ(block), 32);
-  if (kmax < 1) return fail(c, PCMCC_EHIP, "swarm kernel does not fit on a compute unit");
-  if (bpc <= 0 || bpc > kmax) bpc = kmax;
-  const int grid = bpc * c->num_cu;
+  StepLaunch L;
+  rc = resolve(want, &L);
+  if (rc == PCMCC_EINVAL && want.blocks_per_cu && !opts->blocks_per_cu) {  // a cached shape that no longer fits
+    want.blocks_per_cu = 0;
+    rc = resolve(want, &L);
+  }
+  if (rc) return rc;
+  const int block = L.block, grid = L.grid;
   A.n_steps = n_steps;
-  rc = swarm_run(c, A, S, n0h, block, grid, &ms);
+  rc = swarm_run(c, A, S, n0h, L, &ms);
   if (rc) return rc;
   SwarmCtl hc;
   HIP_TRY(c, hipMemcpy(&hc, w.ctl, sizeof(SwarmCtl), hipMemcpyDeviceToHost));
@@ -191,6 +217,8 @@ int pcmcc_swarm_batch(pcmcc_ctx* c, int n_swarms, const double* EN_Td, const int
     stats->step_kernel_ms = ms;
     stats->launch_block = block;
     stats->launch_grid = grid;
+    stats->launch_refill = L.refill;
+    stats->launch_chunk = L.chunk;
   }
   if (hc.status == PCMCC_ECAPACITY)
     return fail(c, hc.status, "a swarm outgrew its %d x n0 slots after %lld steps", opts->cap_factor,

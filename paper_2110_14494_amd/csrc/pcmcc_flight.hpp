@@ -20,7 +20,7 @@
 // collision if the segment ended in one), plans the next segment (majorant,
 // free-flight time) and moves the position to its end.  An electron that
 // reaches the end of the step, is attached or hits the segment limit parks
-// in its lane; once kRefillMin lanes are free, the parked electrons are
+// in its lane; once REFILL lanes are free, the parked electrons are
 // written out and the free lanes take new electrons from a grid-wide work
 // counter, all in one batch.  Lanes therefore stay busy regardless of how
 // many segments each electron needs within the step, the gather (the only
@@ -37,8 +37,12 @@ enum FlightMode : int { FM_IDLE = 0, FM_NEW = 1, FM_FLY = 2, FM_DONE = 3 };
 enum Segment : int { SEG_END = 0, SEG_HORIZON = 1, SEG_COLLIDE = 2 };
 enum FlightEvent : int { EV_GO = 0, EV_DONE = 1, EV_ATTACHED = 2, EV_LIMIT = 3 };
 
-constexpr uint32_t kChunk = 256;  // electrons taken from the work counter at a time
-constexpr int kRefillMin = 16;    // free lanes that trigger a finish-and-refill batch (tuned)
+// Schedule of the mover (kRefillChoices, kChunkMin, kChunkMax): REFILL, a
+// template parameter of fly_all, is the number of free lanes that triggers
+// a finish-and-refill batch (few: the batch runs often with few lanes;
+// many: lanes idle longer before it); the chunk is the number of electrons
+// a wave takes from the work counter at a time (small: more atomics; large:
+// a longer tail at the end of a phase).
 
 // Per-wave staging lists in LDS.  Newborns, holes and placed newborns are
 // collected per wave and written out kFlushAt or more at a time, each batch
@@ -392,7 +396,10 @@ __device__ __forceinline__ int flight_complete(Flight& f, const double3 an, cons
   return EV_GO;
 }
 
-// Runs every electron of a source (n of them) through the rest of the step.
+// Runs every electron of a source (n of them) through the rest of the step,
+// REFILL lanes at a time (see above), `chunk` (a power of two in [kChunkMin,
+// kChunkMax], read from the kernel arguments) electrons per work-counter
+// grab.
 // Field: key(tag) gives the random-number key of a group, accel(x, y, z,
 // tag, where) the acceleration (and where the field was read), bound_at(where,
 // tag, speed, t_rem, a_abs, da) the field bounds for the rest of the step.
@@ -404,11 +411,11 @@ __device__ __forceinline__ int flight_complete(Flight& f, const double3 an, cons
 // arguments; `take` is the grid-wide work counter (zero before the first
 // wave starts).  cum_ion (nullable) counts ionizations per group.  Every
 // staged entry is written out before the function returns.
-template <class Field, class Source, class Finish>
-__device__ __forceinline__ void fly_all(uint64_t n, unsigned long long* take, double dt, const Field& F, const Tab& T,
-                                        const SpeciesView& S, uint32_t step, Cnt& cnt, const BirthSink& sink,
-                                        unsigned long long* cum_ion, WaveStage* L, const Source& source,
-                                        const Finish& finish) {
+template <int REFILL, class Field, class Source, class Finish>
+__device__ __forceinline__ void fly_all(uint64_t n, unsigned long long* take, KArg<uint32_t> chunk, double dt,
+                                        const Field& F, const Tab& T, const SpeciesView& S, uint32_t step, Cnt& cnt,
+                                        const BirthSink& sink, unsigned long long* cum_ion, WaveStage* L,
+                                        const Source& source, const Finish& finish) {
   Flight f;
   f.mode = FM_IDLE;
   StagedBirths<Field> births{L, sink, F, step, S, cum_ion, 0u};
@@ -418,7 +425,7 @@ __device__ __forceinline__ void fly_all(uint64_t n, unsigned long long* take, do
   const uint32_t lane = lane_id();
   for (;;) {
     const uint64_t busy = __ballot(f.mode == FM_FLY);
-    if (64u - (uint32_t)__popcll(busy) >= (uint32_t)kRefillMin || busy == 0) {
+    if (64u - (uint32_t)__popcll(busy) >= (uint32_t)REFILL || busy == 0) {
       // Finish the parked electrons (room for all of them in the list).
       const uint32_t n_fin = (uint32_t)__popcll(__ballot(f.mode == FM_DONE));
       if (n_fin > 0) {
@@ -443,8 +450,9 @@ __device__ __forceinline__ void fly_all(uint64_t n, unsigned long long* take, do
         uint32_t served = 0;
         while (served < n_idle) {
           if (pool_next == pool_end) {
+            const uint32_t ch = chunk.get();
             unsigned long long base = 0;
-            if (lane == 0) base = atomicAdd(take, (unsigned long long)kChunk);
+            if (lane == 0) base = atomicAdd(take, (unsigned long long)ch);
             const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
             const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
             const uint64_t b = ((uint64_t)hi << 32) | lo;
@@ -453,7 +461,7 @@ __device__ __forceinline__ void fly_all(uint64_t n, unsigned long long* take, do
               break;
             }
             pool_next = b;
-            pool_end = b + kChunk < n ? b + kChunk : n;
+            pool_end = b + ch < n ? b + ch : n;
           }
           const uint32_t avail = (uint32_t)(pool_end - pool_next);
           const uint32_t got = avail < n_idle - served ? avail : n_idle - served;

@@ -70,6 +70,12 @@ struct Ctl {
   unsigned long long tot[NCNT];
 };
 
+// Schedule choices of the mover (chosen per workload by the launch-shape
+// tuner): refill thresholds the step kernels are built for, and the range
+// of the work-counter chunk.
+constexpr int kRefillChoices[3] = {16, 24, 32};
+constexpr uint32_t kChunkMin = 64, kChunkMax = 4096;
+
 struct PicArgs {
   Soa buf[2];
   PendSoa pend[2];
@@ -88,6 +94,7 @@ struct PicArgs {
   int n_steps;
   float dt;
   uint64_t n_limit;  // stop after a step that leaves more particles (0: no limit)
+  uint32_t chunk;    // electrons per work-counter grab (power of two, 64..4096)
   EventSink ev;
 };
 
@@ -194,7 +201,8 @@ struct SwarmArgs {
   int sample_every;
   int n_samples;
   int pop_control;
-  EventSink ev;  // no event lists (the newborn queues' event view)
+  uint32_t chunk;  // electrons per work-counter grab (power of two, 64..4096)
+  EventSink ev;    // no event lists (the newborn queues' event view)
 };
 
 // Coefficient surrogate (1 -> 64 -> 64 -> 6 perceptron).
@@ -243,14 +251,23 @@ hipError_t launch_mlp_infer(const InferArgs& a, int grid, hipStream_t stream);
 size_t table_lds_bytes(const TableView& T);
 size_t pic_lds_bytes(const TableView& T, int block);  // step kernel: tables and per-wave staging lists
 size_t swarm_lds_bytes(const TableView& T, int S, int block);
-hipError_t occupancy_swarm_steps(int block, size_t lds, int* blocks_per_cu);
-hipError_t launch_swarm_steps(const SwarmArgs& args, int grid, int block, hipStream_t stream);
+// Blocks of kernel k (block threads, lds dynamic LDS bytes) that are
+// resident on a compute unit together: the occupancy query, bounded by the
+// LDS of a compute unit (160 KiB) over the block's static plus dynamic LDS
+// rounded up to 1280 bytes.  The bound matters for cooperative launches,
+// whose grid-wide barriers need every block resident: the query's own
+// rounding can admit one block more than fit when a block's LDS comes
+// within a granule of a 1/k share of the compute unit.
+hipError_t coresident_blocks(const void* k, int block, size_t lds, int* blocks_per_cu);
+// refill: one of kRefillChoices (free lanes that trigger a refill batch)
+hipError_t occupancy_swarm_steps(int block, int refill, size_t lds, int* blocks_per_cu);
+hipError_t launch_swarm_steps(const SwarmArgs& args, int grid, int block, int refill, hipStream_t stream);
 hipError_t launch_swarm_init(const Soa& buf, const uint64_t* base, const int32_t* n0, int S, hipStream_t stream);
 hipError_t launch_swarm_estimate(const unsigned long long* mom, const long long* cnt, int S, int J, double dt_sample,
                                  double t_window, int n_batches, const double* EN, double gas_N, double* values,
                                  double* errors, double* work, hipStream_t stream);
-hipError_t launch_pic_steps(const PicArgs& args, int grid, int block, hipStream_t stream);
-hipError_t occupancy_pic_steps(int block, size_t lds, int* blocks_per_cu);
+hipError_t launch_pic_steps(const PicArgs& args, int grid, int block, int refill, hipStream_t stream);
+hipError_t occupancy_pic_steps(int block, int refill, size_t lds, int* blocks_per_cu);
 hipError_t launch_finalize(const Soa& user, const Soa& scratch, Ctl* ctl, int64_t* n_dev, hipStream_t stream);
 DepositNeeds deposit_needs(const DepositGeom& g, uint64_t n);
 hipError_t launch_deposit_binned(const float* x, const float* y, const float* z, const float* w, uint64_t n,

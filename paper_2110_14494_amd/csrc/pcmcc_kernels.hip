@@ -181,7 +181,11 @@ struct PlaceNewborn {
 // The step loop.  One cooperative launch runs all n_steps steps; grid-wide
 // barriers separate the phases of a step, and every loop bound that decides
 // a barrier is read after a barrier, so all blocks take the same path.
-__global__ __launch_bounds__(256) void k_pic_steps(PicArgs A) {
+// Four waves per SIMD (at most 128 registers a lane): the mover waits on
+// one gather per segment, and a fourth wave hides that latency better than
+// the registers the compiler would otherwise keep.
+template <int REFILL>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_pic_steps(PicArgs A) {
   extern __shared__ float smem[];
   cg::grid_group grid = cg::this_grid();
   const Tab T = stage_tables(A.T, A.S, smem);
@@ -200,6 +204,7 @@ __global__ __launch_bounds__(256) void k_pic_steps(PicArgs A) {
     const KArg<Soa> cur_k{&ka->buf[sel]}, nxt_k{&ka->buf[sel ^ 1]};
     const KArg<GridView> grid_k{&ka->G};
     const KArg<EventSink> ev_k{&ka->ev};
+    const KArg<uint32_t> chunk_k{&ka->chunk};
     const uint64_t n_cur = ld_acq(&ctl->n_cur);
     const uint32_t step = A.step0 + (uint32_t)s;
     Cnt cnt;
@@ -211,7 +216,7 @@ __global__ __launch_bounds__(256) void k_pic_steps(PicArgs A) {
       const BirthSink sink{{&ka->pend[0]}, &ctl->pend[0], A.pend_cap, &ctl->overflow, 0u, ev_k};
       const SoaSource src{cur_k};
       const KeepInPlace fin{grid_k, nxt_k, A.holes, &ctl->holes, ev_k};
-      fly_all(n_cur, &ctl->take[0], A.dt, F, T, A.S, step, cnt, sink, nullptr, L, src, fin);
+      fly_all<REFILL>(n_cur, &ctl->take[0], chunk_k, A.dt, F, T, A.S, step, cnt, sink, nullptr, L, src, fin);
     }
     grid.sync();
 
@@ -229,7 +234,7 @@ __global__ __launch_bounds__(256) void k_pic_steps(PicArgs A) {
       const BirthSink sink{{&ka->pend[(g + 1) & 1]}, &ctl->pend[g + 1], A.pend_cap, &ctl->overflow, 0u, ev_k};
       const PendSource src{{&ka->pend[g & 1]}};
       const PlaceNewborn fin{grid_k, nxt_k, A.holes, h, n_cur, A.cap, &ctl->child, &ctl->overflow, ev_k};
-      fly_all(np, &ctl->take[g + 1], A.dt, F, T, A.S, step, cnt, sink, nullptr, L, src, fin);
+      fly_all<REFILL>(np, &ctl->take[g + 1], chunk_k, A.dt, F, T, A.S, step, cnt, sink, nullptr, L, src, fin);
       grid.sync();
     }
 
@@ -541,14 +546,41 @@ size_t pic_lds_bytes(const TableView& T, int block) {
   return pic_stage_offset_floats(T) * sizeof(float) + (size_t)(block / 64) * sizeof(WaveStage);
 }
 
-hipError_t launch_pic_steps(const PicArgs& args, int grid, int block, hipStream_t stream) {
-  void* kargs[] = {(void*)&args};
-  return hipLaunchCooperativeKernel((const void*)k_pic_steps, dim3(grid), dim3(block), kargs,
-                                    (unsigned)pic_lds_bytes(args.T, block), stream);
+static const void* pic_steps_kernel(int refill) {
+  switch (refill) {
+    case 16: return (const void*)k_pic_steps<16>;
+    case 24: return (const void*)k_pic_steps<24>;
+    case 32: return (const void*)k_pic_steps<32>;
+    default: return nullptr;
+  }
 }
 
-hipError_t occupancy_pic_steps(int block, size_t lds, int* blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void*)k_pic_steps, block, lds);
+hipError_t launch_pic_steps(const PicArgs& args, int grid, int block, int refill, hipStream_t stream) {
+  const void* k = pic_steps_kernel(refill);
+  if (!k) return hipErrorInvalidValue;
+  void* kargs[] = {(void*)&args};
+  return hipLaunchCooperativeKernel(k, dim3(grid), dim3(block), kargs, (unsigned)pic_lds_bytes(args.T, block),
+                                    stream);
+}
+
+hipError_t coresident_blocks(const void* k, int block, size_t lds, int* blocks_per_cu) {
+  constexpr size_t kLdsPerCu = 160 * 1024, kLdsGranule = 1280;
+  int occ = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, block, lds);
+  if (e != hipSuccess) return e;
+  hipFuncAttributes a;
+  e = hipFuncGetAttributes(&a, k);
+  if (e != hipSuccess) return e;
+  const size_t per = (a.sharedSizeBytes + lds + kLdsGranule - 1) / kLdsGranule * kLdsGranule;
+  const int by_lds = per ? (int)(kLdsPerCu / per) : occ;
+  *blocks_per_cu = occ < by_lds ? occ : by_lds;
+  return hipSuccess;
+}
+
+hipError_t occupancy_pic_steps(int block, int refill, size_t lds, int* blocks_per_cu) {
+  const void* k = pic_steps_kernel(refill);
+  if (!k) return hipErrorInvalidValue;
+  return coresident_blocks(k, block, lds, blocks_per_cu);
 }
 
 hipError_t launch_finalize(const Soa& user, const Soa& scratch, Ctl* ctl, int64_t* n_dev, hipStream_t stream) {

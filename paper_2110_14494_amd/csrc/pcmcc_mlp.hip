@@ -366,7 +366,7 @@ hipError_t launch_mlp_reduce(const float* partial, const float* ploss, int nb, f
 }
 
 hipError_t occupancy_mlp_train(int* blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void*)k_mlp_train, 256, sizeof(MlpLds));
+  return coresident_blocks((const void*)k_mlp_train, 256, sizeof(MlpLds), blocks_per_cu);
 }
 
 hipError_t launch_mlp_train(const MlpArgs& a, int grid, hipStream_t stream) {

@@ -157,7 +157,44 @@ int ensure_swarm(pcmcc_ctx* c, int S, uint64_t slots, int J, int grid) {
   return PCMCC_OK;
 }
 
-// Tuning cache: a flat JSON object {"key": [block, blocks_per_cu], ...}.
+int check_schedule(pcmcc_ctx* c, const pcmcc_schedule& s) {
+  if (s.block != 0 && s.block != 64 && s.block != 128 && s.block != 256 && s.block != 512)
+    return fail(c, PCMCC_EINVAL, "block must be 0, 64, 128, 256 or 512");
+  if (s.blocks_per_cu < 0 || s.blocks_per_cu > 32) return fail(c, PCMCC_EINVAL, "blocks_per_cu must be in [0, 32]");
+  if (s.refill_min != 0 && s.refill_min != 16 && s.refill_min != 24 && s.refill_min != 32)
+    return fail(c, PCMCC_EINVAL, "refill_min must be 0, 16, 24 or 32");
+  if (s.chunk != 0 && (s.chunk < (int)kChunkMin || s.chunk > (int)kChunkMax || (s.chunk & (s.chunk - 1))))
+    return fail(c, PCMCC_EINVAL, "chunk must be 0 or a power of two in [64, 4096]");
+  return PCMCC_OK;
+}
+
+int resolve_launch(pcmcc_ctx* c, const pcmcc_schedule& s, size_t (*lds)(const TableView&, int, int),
+                   hipError_t (*occ)(int, int, size_t, int*), const TableView& T, int S, StepLaunch* out) {
+  const int rc = check_schedule(c, s);
+  if (rc) return rc;
+  const int refill = s.refill_min ? s.refill_min : 24;
+  const int chunk = s.chunk ? s.chunk : 256;
+  int block = 0, per_cu = 0;
+  for (int b : {512, 256, 128, 64}) {
+    if (s.block && b != s.block) continue;
+    int k = 0;
+    HIP_TRY(c, occ(b, refill, lds(T, S, b), &k));
+    if (k >= 1 && k * b > per_cu * block) {  // most resident waves; ties keep the larger block
+      block = b;
+      per_cu = k;
+    }
+  }
+  if (!block) return fail(c, PCMCC_EHIP, "the step kernel does not fit on a compute unit (block %d)", s.block);
+  if (s.blocks_per_cu > per_cu)
+    return fail(c, PCMCC_EINVAL, "blocks_per_cu %d exceeds the %d blocks of %d that fit", s.blocks_per_cu, per_cu,
+                block);
+  const int bpc = s.blocks_per_cu ? s.blocks_per_cu : per_cu;
+  *out = StepLaunch{block, bpc, refill, chunk, bpc * c->num_cu};
+  return PCMCC_OK;
+}
+
+// Tuning cache: a flat JSON object {"key": [block, blocks_per_cu, refill,
+// chunk], ...} (entries of two numbers leave refill and chunk at 0).
 void load_tune_cache(pcmcc_ctx* c, const char* path) {
   if (!path) return;
   std::ifstream f(path);
@@ -170,10 +207,11 @@ void load_tune_cache(pcmcc_ctx* c, const char* path) {
     const size_t q = t.find('"', p + 1);
     if (q == std::string::npos) break;
     const std::string key = t.substr(p + 1, q - p - 1);
-    int b = 0, k = 0;
+    int b = 0, k = 0, r = 0, ch = 0;
     const size_t lb = t.find('[', q);
     if (lb == std::string::npos) break;
-    if (std::sscanf(t.c_str() + lb, "[%d , %d]", &b, &k) == 2 && b > 0 && k > 0) c->tuned[key] = {b, k};
+    const int got = std::sscanf(t.c_str() + lb, "[%d , %d , %d , %d]", &b, &k, &r, &ch);
+    if (got >= 2 && b > 0 && k > 0) c->tuned[key] = {b, k, got == 4 ? r : 0, got == 4 ? ch : 0};
     p = t.find(']', lb);
     if (p == std::string::npos) break;
   }
@@ -186,7 +224,8 @@ void save_tune_cache(pcmcc_ctx* c, const char* path) {
   f << "{\n";
   size_t i = 0;
   for (const auto& kv : c->tuned) {
-    f << "  \"" << kv.first << "\": [" << kv.second.first << ", " << kv.second.second << "]";
+    const auto& v = kv.second;
+    f << "  \"" << kv.first << "\": [" << v[0] << ", " << v[1] << ", " << v[2] << ", " << v[3] << "]";
     f << (++i < c->tuned.size() ? ",\n" : "\n");
   }
   f << "}\n";
@@ -415,13 +454,11 @@ int push_impl(pcmcc_ctx* c, const pcmcc_particles* p, const pcmcc_grid* field, d
   rc = prepare_field(c, field);
   if (rc) return rc;
 
-  const int block = 256;
   const TableView T = table_view(c);
-  const size_t lds = pic_lds_bytes(T, block);
-  int per_cu = 0;
-  HIP_TRY(c, occupancy_pic_steps(block, lds, &per_cu));
-  if (per_cu < 1) return fail(c, PCMCC_EHIP, "step kernel does not fit on a compute unit");
-  const int grid = per_cu * c->num_cu;
+  StepLaunch sl;
+  rc = resolve_launch(c, c->sched, pic_lds_bytes_s, occupancy_pic_steps, T, 0, &sl);
+  if (rc) return rc;
+  const int block = sl.block, grid = sl.grid;
   if (c->partial_blocks < grid) {
     dfree(c->partial);
     c->partial = nullptr;
@@ -484,6 +521,7 @@ int push_impl(pcmcc_ctx* c, const pcmcc_particles* p, const pcmcc_grid* field, d
   G.qm = A.S.qm;
   A.key = Key{(uint32_t)seed, (uint32_t)(seed >> 32)};
   A.dt = (float)dt;
+  A.chunk = (uint32_t)sl.chunk;
   if (ev) A.ev = *ev;
   // Step loop launches.  With weight control the kernel stops after the step
   // that takes the count above floor(growth * n_ref); the weights are then
@@ -499,7 +537,7 @@ int push_impl(pcmcc_ctx* c, const pcmcc_particles* p, const pcmcc_grid* field, d
     A.n_steps = n_steps - done;
     A.n_limit = wctl ? (uint64_t)std::floor(c->wc_growth * (double)c->wc_n_ref) : 0;
     HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
-    HIP_TRY(c, launch_pic_steps(A, grid, block, c->stream));
+    HIP_TRY(c, launch_pic_steps(A, grid, block, sl.refill, c->stream));
     HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->host_ctl, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -558,6 +596,8 @@ int push_impl(pcmcc_ctx* c, const pcmcc_particles* p, const pcmcc_grid* field, d
     stats->step_kernel_ms = step_ms;
     stats->launch_block = block;
     stats->launch_grid = grid;
+    stats->launch_refill = sl.refill;
+    stats->launch_chunk = sl.chunk;
     stats->n = (int64_t)h.n_cur;
     stats->steps_done = h.steps_done;
     stats->particle_steps = h.particle_steps;

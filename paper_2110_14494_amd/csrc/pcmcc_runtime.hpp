@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -118,7 +119,10 @@ struct pcmcc_ctx {
     SwarmCtl* ctl = nullptr;
     double *values = nullptr, *errors = nullptr, *work = nullptr;
   } sw;
-  std::map<std::string, std::pair<int, int>> tuned;  // shape key -> (block, blocks per CU)
+  // launch schedules: the step kernel's (zero fields: defaults), and the
+  // tuned ones by workload key: (block, blocks per CU, refill, chunk)
+  pcmcc_schedule sched{};
+  std::map<std::string, std::array<int, 4>> tuned;
 };
 
 namespace pcmcc_rt {
@@ -156,6 +160,17 @@ void free_swarm(pcmcc_ctx* c);
 int alloc_soa(pcmcc_ctx* c, Soa& b, uint64_t n);
 int alloc_pend(pcmcc_ctx* c, PendSoa& q, uint64_t n, bool with_sw);
 int ensure_swarm(pcmcc_ctx* c, int S, uint64_t slots, int J, int grid);
+// A schedule resolved against the kernel's resources: every field set.
+struct StepLaunch {
+  int block, bpc, refill, chunk, grid;
+};
+int check_schedule(pcmcc_ctx* c, const pcmcc_schedule& s);
+inline size_t pic_lds_bytes_s(const TableView& T, int, int block) { return pic_lds_bytes(T, block); }
+inline size_t swarm_lds_bytes_s(const TableView& T, int S, int block) { return swarm_lds_bytes(T, S, block); }
+// lds(block): dynamic LDS bytes of the kernel at that block size; occ(block,
+// refill, lds, &per_cu) its occupancy query.
+int resolve_launch(pcmcc_ctx* c, const pcmcc_schedule& s, size_t (*lds)(const TableView&, int, int),
+                   hipError_t (*occ)(int, int, size_t, int*), const TableView& T, int S, StepLaunch* out);
 void load_tune_cache(pcmcc_ctx* c, const char* path);
 void save_tune_cache(pcmcc_ctx* c, const char* path);
 bool valid_grid(const pcmcc_grid* g);

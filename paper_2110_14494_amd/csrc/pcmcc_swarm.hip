@@ -233,8 +233,8 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
 }
 
 // ---------------------------------------------------------------------------
-template <int BS>
-__global__ __launch_bounds__(BS) void k_swarm_steps(SwarmArgs A) {
+template <int BS, int REFILL>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_swarm_steps(SwarmArgs A) {
   extern __shared__ float smem[];
   cg::grid_group grid = cg::this_grid();
   const Tab T = stage_tables(A.T, A.S, smem);
@@ -260,6 +260,7 @@ __global__ __launch_bounds__(BS) void k_swarm_steps(SwarmArgs A) {
   const SwarmField F{az_d, az_l, A.key};
   const auto* ka = (const __attribute__((address_space(4))) SwarmArgs*)__builtin_amdgcn_kernarg_segment_ptr();
   const KArg<EventSink> no_events{&ka->ev};
+  const KArg<uint32_t> chunk_k{&ka->chunk};
   const unsigned lane = lane_id();
   const uint32_t wpb = BS / 64;
   SwarmCtl* ctl = A.ctl;
@@ -282,8 +283,8 @@ __global__ __launch_bounds__(BS) void k_swarm_steps(SwarmArgs A) {
     {
       const BirthSink sink{{&ka->pend[0]}, &ctl->pend[0], A.pend_cap, &ctl->overflow, 0u, no_events};
       const SwarmLoad src{cur_k, A.base, prefix, pck, S, A.key, step, sink, &psteps};
-      fly_all((uint64_t)prefix[S], &ctl->take[0], (double)A.dt, F, T, A.S, step, cnt, sink, A.cum_ion, L, src,
-              fin);
+      fly_all<REFILL>((uint64_t)prefix[S], &ctl->take[0], chunk_k, (double)A.dt, F, T, A.S, step, cnt, sink,
+                      A.cum_ion, L, src, fin);
     }
     grid.sync();
 
@@ -298,7 +299,8 @@ __global__ __launch_bounds__(BS) void k_swarm_steps(SwarmArgs A) {
       const uint64_t np = np_raw < A.pend_cap ? np_raw : A.pend_cap;
       const BirthSink sink{{&ka->pend[(g + 1) & 1]}, &ctl->pend[g + 1], A.pend_cap, &ctl->overflow, 0u, no_events};
       const SwarmPend src{{&ka->pend[g & 1]}};
-      fly_all(np, &ctl->take[g + 1], (double)A.dt, F, T, A.S, step, cnt, sink, A.cum_ion, L, src, fin);
+      fly_all<REFILL>(np, &ctl->take[g + 1], chunk_k, (double)A.dt, F, T, A.S, step, cnt, sink, A.cum_ion, L, src,
+                      fin);
       grid.sync();
     }
 
@@ -587,29 +589,34 @@ size_t swarm_lds_bytes(const TableView& T, int S, int block) {
          (size_t)(S + 1) * 4 + (size_t)block * 4 + (size_t)S * 4 + (size_t)S * 4;
 }
 
-static const void* swarm_kernel(int block) {
-  switch (block) {
-    case 64:
-      return (const void*)k_swarm_steps<64>;
-    case 128:
-      return (const void*)k_swarm_steps<128>;
-    case 256:
-      return (const void*)k_swarm_steps<256>;
-    case 512:
-      return (const void*)k_swarm_steps<512>;
-    default:
-      return nullptr;
+template <int BS>
+static const void* swarm_kernel_r(int refill) {
+  switch (refill) {
+    case 16: return (const void*)k_swarm_steps<BS, 16>;
+    case 24: return (const void*)k_swarm_steps<BS, 24>;
+    case 32: return (const void*)k_swarm_steps<BS, 32>;
+    default: return nullptr;
   }
 }
 
-hipError_t occupancy_swarm_steps(int block, size_t lds, int* blocks_per_cu) {
-  const void* k = swarm_kernel(block);
-  if (!k) return hipErrorInvalidValue;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, block, lds);
+static const void* swarm_kernel(int block, int refill) {
+  switch (block) {
+    case 64: return swarm_kernel_r<64>(refill);
+    case 128: return swarm_kernel_r<128>(refill);
+    case 256: return swarm_kernel_r<256>(refill);
+    case 512: return swarm_kernel_r<512>(refill);
+    default: return nullptr;
+  }
 }
 
-hipError_t launch_swarm_steps(const SwarmArgs& args, int grid, int block, hipStream_t stream) {
-  const void* k = swarm_kernel(block);
+hipError_t occupancy_swarm_steps(int block, int refill, size_t lds, int* blocks_per_cu) {
+  const void* k = swarm_kernel(block, refill);
+  if (!k) return hipErrorInvalidValue;
+  return coresident_blocks(k, block, lds, blocks_per_cu);
+}
+
+hipError_t launch_swarm_steps(const SwarmArgs& args, int grid, int block, int refill, hipStream_t stream) {
+  const void* k = swarm_kernel(block, refill);
   if (!k) return hipErrorInvalidValue;
   void* kargs[] = {(void*)&args};
   return hipLaunchCooperativeKernel(k, dim3(grid), dim3(block), kargs,

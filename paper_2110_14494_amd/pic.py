@@ -145,6 +145,31 @@ class Context:
             B.check(rc, self.h)
         return rc, st.as_dict()
 
+    def set_schedule(self, block: int = 0, blocks_per_cu: int = 0, refill_min: int = 0, chunk: int = 0):
+        """Schedule of later step calls (pcmcc_set_schedule); zeros take the defaults."""
+        s = B.pcmcc_schedule(int(block), int(blocks_per_cu), int(refill_min), int(chunk))
+        B.check(B.lib().pcmcc_set_schedule(self.h, C.byref(s)), self.h)
+
+    def get_schedule(self) -> dict:
+        """The resolved schedule of the next step call (pcmcc_get_schedule)."""
+        s = B.pcmcc_schedule()
+        B.check(B.lib().pcmcc_get_schedule(self.h, C.byref(s)), self.h)
+        return s.as_dict()
+
+    def autotune_steps(self, parts: Particles, grid: DeviceGrid, dt: float, n_steps: int, seed: int, step0: int = 0,
+                       tune_cache: str | None = None, check: bool = True):
+        """Launch-shape tuner of the step kernel (pcmcc_autotune_steps): returns
+        (rc, chosen schedule, tuned ms, default ms); parts is left unchanged."""
+        ps, gs = parts.struct(), grid.struct()
+        s = B.pcmcc_schedule()
+        t_ms, d_ms = C.c_float(0), C.c_float(0)
+        rc = B.lib().pcmcc_autotune_steps(self.h, C.byref(ps), C.byref(gs), float(dt), int(n_steps), int(seed),
+                                          int(step0), tune_cache.encode() if tune_cache else None, C.byref(s),
+                                          C.byref(t_ms), C.byref(d_ms))
+        if check:
+            B.check(rc, self.h)
+        return rc, s.as_dict(), t_ms.value, d_ms.value
+
     def set_weight_control(self, n_ppc: float, growth: float = 1.25):
         B.check(B.lib().pcmcc_set_weight_control(self.h, float(n_ppc), float(growth)), self.h)
 
@@ -294,7 +319,8 @@ class Context:
 def swarm_batch(ctx: Context, EN_Td, n0, dt: float, n_steps: int, seed: int, sample_every: int = 10,
                 window_start_s: float = 0.0, n_batches: int = 10, cap_factor: int = 8,
                 population_control: bool = True, block: int = 0, blocks_per_cu: int = 0, autotune: bool = False,
-                tune_cache: str | None = None, raw: bool = False, check: bool = True):
+                tune_cache: str | None = None, raw: bool = False, check: bool = True, refill_min: int = 0,
+                chunk: int = 0):
     """Batched uniform-field swarms (forwards to pcmcc_swarm_batch).
 
     Returns (rc, values[S, 14], errors[S, 14], stats[, moments[S, J, 14], counters[S, J, 4]])."""
@@ -304,7 +330,7 @@ def swarm_batch(ctx: Context, EN_Td, n0, dt: float, n_steps: int, seed: int, sam
     J = n_steps // sample_every
     opts = B.pcmcc_swarm_opts(int(sample_every), float(window_start_s), int(n_batches), int(cap_factor),
                               1 if population_control else 0, int(block), int(blocks_per_cu), 1 if autotune else 0,
-                              tune_cache.encode() if tune_cache else None)
+                              tune_cache.encode() if tune_cache else None, int(refill_min), int(chunk))
     res = (B.pcmcc_swarm_result * S)()
     st = B.pcmcc_stats()
     mom = np.zeros((S, J, B.SWARM_NMOM)) if raw else None

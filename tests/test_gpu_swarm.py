@@ -100,7 +100,8 @@ def test_autotune_cache_round_trip(ctx, tmp_path):
     a = gpu_run(ctx, EN, N0, autotune=True, tune_cache=path)
     assert os.path.exists(path) and "k_swarm_steps" in open(path).read()
     b = gpu_run(ctx, EN, N0, tune_cache=path)
-    assert (b[3]["launch_block"], b[3]["launch_grid"]) == (a[3]["launch_block"], a[3]["launch_grid"])
+    keys = ("launch_block", "launch_grid", "launch_refill", "launch_chunk")
+    assert [b[3][k] for k in keys] == [a[3][k] for k in keys]
     assert np.array_equal(a[4], b[4])
 
 
