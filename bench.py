@@ -34,6 +34,7 @@ import math
 import os
 import platform
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -526,24 +527,48 @@ def coef_leg(a, ctx, pic):
     t_swarm = 0.0
     big = dict(log2_lo=HELD_LOG2_N, log2_hi=HELD_LOG2_N)
 
-    def batch(EN, b, sizes):
+    def batch(EN, b, sizes, **kw):
         cfg = W.swarm_batch_config(seed=1 + b, scale=a.coef_scale, **sizes)
         t0 = time.perf_counter()
         rc, v, e, st = pic.swarm_batch(ctx, EN, cfg["n0"], base["dt"], base["n_steps"], 17 + b,
                                        sample_every=base["sample_every"], window_start_s=base["window_start"],
-                                       n_batches=10)
+                                       n_batches=10, **kw)
         el = time.perf_counter() - t0
-        log(f"swarm batch {b}: {st['step_kernel_ms']:.0f} ms, {st['particle_steps']:.3g} particle-steps")
-        return v, e, el
+        log(f"swarm batch {b}: {st['step_kernel_ms']:.0f} ms, {st['particle_steps']:.3g} particle-steps, "
+            f"block {st['launch_block']} grid {st['launch_grid']} refill {st['launch_refill']} "
+            f"chunk {st['launch_chunk']}")
+        return v, e, el, st
+
+    # Launch schedule of the batched swarms from the project's tuner: batch 0
+    # at the library's default schedule, then tuned on batch 0 (each
+    # candidate runs its first 200 steps; the context keeps the result), then
+    # the tuned schedule for every batch.
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    tune_path = os.path.join(tempfile.mkdtemp(prefix="pcmcc_tune_"), "swarm_schedule.json")
+    idx0 = np.arange(0, n_all, n_batch)
+    _, _, _, st_def = batch(EN_all[idx0], 0, {})
+    t0 = time.perf_counter()
+    _, _, _, st_tuned = batch(EN_all[idx0], 0, {}, autotune=True, tune_cache=tune_path)
+    tune_s = time.perf_counter() - t0
+    sched = {"block": st_tuned["launch_block"], "blocks_per_cu": st_tuned["launch_grid"] // n_cu,
+             "refill_min": st_tuned["launch_refill"], "chunk": st_tuned["launch_chunk"]}
+    schedule = {"tuned": sched, "tuned_kernel_ms": st_tuned["step_kernel_ms"],
+                "default": {"block": st_def["launch_block"], "blocks_per_cu": st_def["launch_grid"] // n_cu,
+                            "refill_min": st_def["launch_refill"], "chunk": st_def["launch_chunk"]},
+                "default_kernel_ms": st_def["step_kernel_ms"],
+                "tuned_over_default": st_def["step_kernel_ms"] / st_tuned["step_kernel_ms"],
+                "tuning_call_s": tune_s, "tuned_on": "batch 0 (256 swarms, sizes 2^12-2^17, 2000 steps)"}
+    log(f"swarm schedule: tuned {sched} {st_tuned['step_kernel_ms']:.0f} ms, default "
+        f"{schedule['default']} {st_def['step_kernel_ms']:.0f} ms")
 
     for b in range(n_batch):
         idx = np.arange(b, n_all, n_batch)
-        vals[idx], errs[idx], el = batch(EN_all[idx], b, big if b == held_b else {})
+        vals[idx], errs[idx], el, _ = batch(EN_all[idx], b, big if b == held_b else {}, **sched)
         t_swarm += el
     batched_pps = n_all / t_swarm
     # independent test points: half a grid step above each held-out point
     EN_test = 10.0 * 100.0 ** ((np.arange(held_b, n_all, n_batch) + 0.5) / (n_all - 1))
-    v_test, e_test, _ = batch(EN_test, n_batch, big)
+    v_test, e_test, _, _ = batch(EN_test, n_batch, big, **sched)
     # the plain method: one swarm per launch (a few E/N values, extrapolated)
     cfg = W.swarm_batch_config(seed=1, scale=a.coef_scale)
     probe = [0, 85, 170, 255]
@@ -649,6 +674,7 @@ def coef_leg(a, ctx, pic):
     fb_bits = (fb[:, None] >> np.arange(6)[None, :]) & 1
     return {
         "swarm_points": n_all, "swarm_steps": base["n_steps"], "swarm_scale": a.coef_scale,
+        "swarm_launch_schedule": schedule,
         "heldout_and_test_electrons_per_swarm": 2 ** HELD_LOG2_N,
         "batched_swarm_EN_points_per_s": batched_pps, "plain_swarm_EN_points_per_s": plain_pps,
         "batched_over_plain": batched_pps / plain_pps,

@@ -228,6 +228,39 @@ __global__ __launch_bounds__(256) void k_dep_scatter(const float* __restrict__ x
   }
 }
 
+// Particle sort by tile (the step loop's start order): the count and scan
+// passes above, then every array of a particle moved to its tile's range.
+// Within a tile the order follows the atomics and is not fixed.
+__global__ __launch_bounds__(256) void k_sort_scatter(Soa src, uint64_t n, TileGeom T,
+                                                       const uint32_t* __restrict__ start,
+                                                       const uint2* __restrict__ dump, Soa dst) {
+  __shared__ uint32_t keys[kBinHash];
+  __shared__ uint32_t next[kBinHash];
+  const uint2* d = dump + (size_t)blockIdx.x * kBinHash;
+  for (int e = threadIdx.x; e < kBinHash; e += blockDim.x) {
+    const uint2 v = d[e];
+    keys[e] = v.x;
+    next[e] = v.x == kEmpty ? 0u : start[v.x] + v.y;
+  }
+  __syncthreads();
+  const uint64_t p0 = (uint64_t)blockIdx.x * kBinRange;
+  const uint64_t p1 = p0 + kBinRange < n ? p0 + kBinRange : n;
+  for (uint64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+    const float px = src.x[p], py = src.y[p], pz = src.z[p];
+    const int e = hash_find(keys, tile_of(T, px, py, pz));
+    if (e < 0) continue;  // never: both passes compute the same tile
+    const uint32_t q = atomicAdd(&next[e], 1u);
+    dst.x[q] = px;
+    dst.y[q] = py;
+    dst.z[q] = pz;
+    dst.vx[q] = src.vx[p];
+    dst.vy[q] = src.vy[p];
+    dst.vz[q] = src.vz[p];
+    dst.w[q] = src.w[p];
+    dst.id[q] = src.id[p];
+  }
+}
+
 // One tile run [cur, e) of sorted particles into the LDS buffer of the tile
 // at (oi, oj, ok).  The plain pass adds without overflow checks (it cannot
 // overflow while the run carries fewer than 2^31 electrons, which the caller
@@ -349,6 +382,25 @@ DepositNeeds deposit_needs(const DepositGeom& g, uint64_t n) {
   d.dump_entries = ((n + kBinRange - 1) / kBinRange) * kBinHash;
   d.sorted = n;
   return d;
+}
+
+hipError_t launch_sort_tiles(const Soa& src, uint64_t n, const DepositGeom& g, const DepositWork& W, const Soa& dst,
+                             hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  TileGeom T;
+  T.g = g;
+  T.tx = (g.nx + kTile - 1) / kTile;
+  T.ty = (g.ny + kTile - 1) / kTile;
+  T.tz = (g.nz + kTile - 1) / kTile;
+  const uint32_t n_tiles = (uint32_t)T.tx * T.ty * T.tz;
+  hipError_t e = launch_fill_u32(W.tile_count, n_tiles, 0u, stream);
+  if (e != hipSuccess) return e;
+  const uint64_t nb = (n + kBinRange - 1) / kBinRange;
+  hipLaunchKernelGGL(k_dep_count, dim3((unsigned)nb), dim3(256), 0, stream, src.x, src.y, src.z, n, T, W.tile_count,
+                     W.dump);
+  hipLaunchKernelGGL(k_dep_scan, dim3(1), dim3(1024), 0, stream, W.tile_count, n_tiles, W.tile_start);
+  hipLaunchKernelGGL(k_sort_scatter, dim3((unsigned)nb), dim3(256), 0, stream, src, n, T, W.tile_start, W.dump, dst);
+  return hipGetLastError();
 }
 
 hipError_t launch_deposit_binned(const float* x, const float* y, const float* z, const float* w, uint64_t n,

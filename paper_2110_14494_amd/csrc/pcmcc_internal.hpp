@@ -275,6 +275,10 @@ hipError_t launch_deposit_binned(const float* x, const float* y, const float* z,
 hipError_t launch_deposit(const float* x, const float* y, const float* z, const float* w, const int64_t* n_dev,
                           const DepositGeom& g, int64_t* rho, hipStream_t stream);
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t stream);
+// Sorts n particles of src into dst by deposit tile (8^3 cells, clamped to
+// the grid); needs W's tile counts, starts and dump as the binned deposit.
+hipError_t launch_sort_tiles(const Soa& src, uint64_t n, const DepositGeom& g, const DepositWork& W, const Soa& dst,
+                             hipStream_t stream);
 hipError_t launch_field_bounds(const float4* E, int nx, int ny, int nz, float2* out, unsigned* emax_bits,
                                hipStream_t stream);
 hipError_t launch_pack_field(const float4* E, const float2* bound, int nx, int ny, int nz, float4* P,

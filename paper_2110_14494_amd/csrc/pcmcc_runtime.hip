@@ -318,16 +318,12 @@ int deposit_range_check(pcmcc_ctx* c) {
 
 // Deposit of n particles into rho on the context stream; with check, waits
 // and reports a range error (else the caller calls deposit_range_check).
-int run_deposit(pcmcc_ctx* c, const float* x, const float* y, const float* z, const float* w, const int64_t* n_dev,
-                uint64_t n, const pcmcc_grid* grid, int64_t* rho, bool check) {
-  const DepositGeom g{grid->nx, grid->ny, grid->nz, grid->x0, grid->y0, grid->z0, 1.0 / grid->dx, c->dep_err};
-  const DepositNeeds d = deposit_needs(g, n);
-  HIP_TRY(c, hipMemsetAsync(c->dep_err, 0, sizeof(unsigned), c->stream));
-  if (!d.binned) {
-    HIP_TRY(c, launch_deposit(x, y, z, w, n_dev, g, rho, c->stream));
-    return check ? deposit_range_check(c) : PCMCC_OK;
-  }
-  if (n >= 0xFFFFFFFFull) return fail(c, PCMCC_EINVAL, "deposit of 2^32 or more particles");
+// From this many particles on, a step call starts from the population
+// sorted by tile.
+constexpr uint64_t kSortStartMin = 1u << 20;
+
+// Binned-deposit buffers for d (the sorted copy only with `sorted`).
+static int ensure_dep_work(pcmcc_ctx* c, const DepositNeeds& d, bool sorted) {
   auto grow = [&](auto** ptr, uint64_t& have, uint64_t need) -> int {
     if (have >= need) return PCMCC_OK;
     dfree(*ptr);
@@ -352,7 +348,21 @@ int run_deposit(pcmcc_ctx* c, const float* x, const float* y, const float* z, co
     if (rc) return rc;
   }
   rc = grow(&c->dep.dump, c->dep_dump, d.dump_entries);
-  if (!rc) rc = grow(&c->dep.sorted, c->dep_sorted, d.sorted);
+  if (!rc && sorted) rc = grow(&c->dep.sorted, c->dep_sorted, d.sorted);
+  return rc;
+}
+
+int run_deposit(pcmcc_ctx* c, const float* x, const float* y, const float* z, const float* w, const int64_t* n_dev,
+                uint64_t n, const pcmcc_grid* grid, int64_t* rho, bool check) {
+  const DepositGeom g{grid->nx, grid->ny, grid->nz, grid->x0, grid->y0, grid->z0, 1.0 / grid->dx, c->dep_err};
+  const DepositNeeds d = deposit_needs(g, n);
+  HIP_TRY(c, hipMemsetAsync(c->dep_err, 0, sizeof(unsigned), c->stream));
+  if (!d.binned) {
+    HIP_TRY(c, launch_deposit(x, y, z, w, n_dev, g, rho, c->stream));
+    return check ? deposit_range_check(c) : PCMCC_OK;
+  }
+  if (n >= 0xFFFFFFFFull) return fail(c, PCMCC_EINVAL, "deposit of 2^32 or more particles");
+  const int rc = ensure_dep_work(c, d, true);
   if (rc) return rc;
   HIP_TRY(c, launch_deposit_binned(x, y, z, w, n, g, rho, c->dep, c->stream));
   return check ? deposit_range_check(c) : PCMCC_OK;
@@ -468,18 +478,37 @@ int push_impl(pcmcc_ctx* c, const pcmcc_particles* p, const pcmcc_grid* field, d
   std::memset(c->host_ctl, 0, sizeof(Ctl));
   c->host_ctl->n_cur = (unsigned long long)n0;
   // The steps alternate between the caller's arrays and the scratch buffer.
-  // For an odd step count, start from a copy in the scratch buffer so that
-  // the last step lands in the caller's arrays: copying the start population
-  // is cheaper than copying back the grown one (any other outcome is copied
-  // back at the end as usual).
-  if ((n_steps & 1) && n0 > 0) {
-    float* const from[7] = {p->x, p->y, p->z, p->vx, p->vy, p->vz, p->w};
-    float* const to[7] = {c->scratch.x, c->scratch.y, c->scratch.z, c->scratch.vx, c->scratch.vy, c->scratch.vz,
-                          c->scratch.w};
-    for (int k = 0; k < 7; ++k)
-      HIP_TRY(c, hipMemcpyAsync(to[k], from[k], (size_t)n0 * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(c->scratch.id, p->id, (size_t)n0 * sizeof(uint64_t), hipMemcpyDeviceToDevice,
-                              c->stream));
+  // A large population starts sorted by 8^3-cell tile, so that the electrons
+  // a wave takes from the work counter gather from a few field records that
+  // stay in cache (the sort goes into the scratch buffer and, for an even
+  // step count, is copied back).  For an odd step count the steps start from
+  // the scratch buffer so that the last step lands in the caller's arrays:
+  // copying the start population is cheaper than copying back the grown one
+  // (any other outcome is copied back at the end as usual).
+  const Soa user{p->x, p->y, p->z, p->vx, p->vy, p->vz, p->w, p->id};
+  const bool sort_start = n0 >= (int64_t)kSortStartMin && n_steps > 0;
+  auto copy_soa = [&](const Soa& from, const Soa& to) -> hipError_t {
+    float* const f[7] = {from.x, from.y, from.z, from.vx, from.vy, from.vz, from.w};
+    float* const t[7] = {to.x, to.y, to.z, to.vx, to.vy, to.vz, to.w};
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < 7 && e == hipSuccess; ++k)
+      e = hipMemcpyAsync(t[k], f[k], (size_t)n0 * sizeof(float), hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(to.id, from.id, (size_t)n0 * sizeof(uint64_t), hipMemcpyDeviceToDevice, c->stream);
+    return e;
+  };
+  if (sort_start) {
+    const DepositGeom g{field->nx, field->ny, field->nz, field->x0, field->y0, field->z0, 1.0 / field->dx,
+                        c->dep_err};
+    rc = ensure_dep_work(c, deposit_needs(g, (uint64_t)n0), false);
+    if (rc) return rc;
+    HIP_TRY(c, launch_sort_tiles(user, (uint64_t)n0, g, c->dep, c->scratch, c->stream));
+    if (n_steps & 1)
+      c->host_ctl->cur_sel = 1;
+    else
+      HIP_TRY(c, copy_soa(c->scratch, user));
+  } else if ((n_steps & 1) && n0 > 0) {
+    HIP_TRY(c, copy_soa(user, c->scratch));
     c->host_ctl->cur_sel = 1;
   }
   HIP_TRY(c, hipMemcpyAsync(c->ctl, c->host_ctl, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
