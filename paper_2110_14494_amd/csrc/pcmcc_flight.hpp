@@ -404,10 +404,13 @@ __device__ __forceinline__ int flight_complete(Flight& f, const double3 an, cons
 // tag, where) the acceleration (and where the field was read), bound_at(where,
 // tag, speed, t_rem, a_abs, da) the field bounds for the rest of the step.
 // Source: load(i, Flight&) starts electron i (or leaves the lane idle).
-// Finish: done_all(Flight&, parked, Cnt&, WaveStage*, staged count, bool&
-// staged) takes the electrons that left the step (called by the whole wave;
-// `parked` marks the lanes holding one, f.seg is its event), flush(WaveStage*,
-// count) writes out the wave's staged results.  Must be called by whole waves with wave-uniform
+// Finish: done_all(Flight&, parked, Cnt&, WaveStage*, staged count) takes the
+// electrons that left the step (called by the whole wave; `parked` marks the
+// lanes holding one, f.seg is its event) and returns the new staged count
+// (it may flush on its own), flush(WaveStage*, count) writes out the wave's
+// staged results; can_open() tells whether the wave may take another chunk
+// of work, open_chunk(first, size) registers a chunk it took and returns its
+// tag, which tag(Flight&, tag) gives each electron loaded from it.  Must be called by whole waves with wave-uniform
 // arguments; `take` is the grid-wide work counter (zero before the first
 // wave starts).  cum_ion (nullable) counts ionizations per group.  Every
 // staged entry is written out before the function returns.
@@ -421,6 +424,7 @@ __device__ __forceinline__ void fly_all(uint64_t n, unsigned long long* take, KA
   StagedBirths<Field> births{L, sink, F, step, S, cum_ion, 0u};
   uint32_t n_done = 0;  // entries of the finish list
   uint64_t pool_next = 0, pool_end = 0;
+  uint32_t chunk_tag = 0;  // finisher's tag of the current chunk
   bool dry = n == 0;
   const uint32_t lane = lane_id();
   for (;;) {
@@ -433,10 +437,8 @@ __device__ __forceinline__ void fly_all(uint64_t n, unsigned long long* take, KA
           finish.flush(L, n_done);
           n_done = 0;
         }
-        bool placed = false;
-        finish.done_all(f, f.mode == FM_DONE, cnt, L, n_done, placed);
+        n_done = finish.done_all(f, f.mode == FM_DONE, cnt, L, n_done);
         if (f.mode == FM_DONE) f.mode = FM_IDLE;
-        n_done += (uint32_t)__popcll(__ballot(placed));
         if (n_done >= kFlushAt) {
           finish.flush(L, n_done);
           n_done = 0;
@@ -450,6 +452,7 @@ __device__ __forceinline__ void fly_all(uint64_t n, unsigned long long* take, KA
         uint32_t served = 0;
         while (served < n_idle) {
           if (pool_next == pool_end) {
+            if (!finish.can_open()) break;  // the lanes stay idle until a chunk of this wave completes
             const uint32_t ch = chunk.get();
             unsigned long long base = 0;
             if (lane == 0) base = atomicAdd(take, (unsigned long long)ch);
@@ -462,11 +465,14 @@ __device__ __forceinline__ void fly_all(uint64_t n, unsigned long long* take, KA
             }
             pool_next = b;
             pool_end = b + ch < n ? b + ch : n;
+            chunk_tag = finish.open_chunk(b, (uint32_t)(pool_end - b));
           }
           const uint32_t avail = (uint32_t)(pool_end - pool_next);
           const uint32_t got = avail < n_idle - served ? avail : n_idle - served;
-          if (f.mode == FM_IDLE && rank >= served && rank < served + got)
+          if (f.mode == FM_IDLE && rank >= served && rank < served + got) {
             source.load(pool_next + (rank - served), f);
+            finish.tag(f, chunk_tag);
+          }
           pool_next += got;
           served += got;
         }

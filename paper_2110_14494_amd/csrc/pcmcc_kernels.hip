@@ -11,12 +11,13 @@
 // Layout: particles are structure-of-arrays single precision (x, y, z, vx,
 // vy, vz, w) plus a 64-bit id.  Waves take electrons in chunks of 256
 // consecutive slots from a grid-wide counter and keep every lane busy with
-// the segment-pipelined mover (pcmcc_flight.hpp).  A step never moves survivors: particle i of the current buffer is written
-// to slot i of the next buffer (ping-pong, so a step that would overflow the
-// capacity leaves the previous state intact); the few removed particles
-// leave holes that the step's newborns fill first, and any holes left over
-// are filled from the tail.  Only newborns and holes take atomics, one per
-// wave and event.
+// the segment-pipelined mover (pcmcc_flight.hpp).  The survivors of a chunk
+// stay within that chunk's slot range of the next buffer (ping-pong, so a
+// step that would overflow the capacity leaves the previous state intact),
+// written to its front in the order they finish; the rest of the range is
+// holes that the step's newborns fill first, and any holes left over are
+// filled from the tail.  Only newborns and holes take global atomics, one
+// per wave and batch.
 #include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
@@ -68,36 +69,106 @@ __device__ __forceinline__ void record_attachment(const EventSink& ev, const Fli
   }
 }
 
+// Phase 1 destination: the survivors of a chunk of slots the wave took are
+// written to the front of that chunk's range in the next buffer, in the
+// order they finish; once every electron of the chunk has finished, the rest
+// of its range is a run of holes (staged per wave).  The chunks a wave has
+// open are kept in its ring in LDS; an electron's tag is its chunk's ring
+// entry.  Writing each chunk's survivors consecutively keeps a few partly
+// written lines per chunk open in the cache instead of one per survivor.
+struct ChunkRing {
+  static constexpr uint32_t kR = 64;  // more than the 64 lanes can keep open, plus the chunk being loaded
+  uint64_t base[kR];
+  uint32_t size[kR], cursor[kR], remaining[kR];
+  uint32_t head;
+  uint32_t pad;
+  __device__ __forceinline__ void reset() {
+    remaining[lane_id()] = 0u;
+    if (lane_id() == 0) head = 0u;
+  }
+};
+
 struct KeepInPlace {
   KArg<GridView> G;
   KArg<Soa> nxt;
   uint32_t* holes;
   unsigned long long* n_holes;
   KArg<EventSink> ev;
-  __device__ __forceinline__ void done_all(const Flight& f, bool parked, Cnt& cnt, WaveStage* L,
-                                           uint32_t n_staged, bool& staged) const {
-    if (!parked) return;
-    if (f.seg == EV_ATTACHED) {
-      const EventSink e = ev.get();
-      if (e.ax) record_attachment(e, f);
+  ChunkRing* R;  // the wave's ring (LDS)
+  __device__ __forceinline__ bool can_open() const {
+    const uint32_t h = __builtin_amdgcn_readfirstlane(R->head);
+    return __builtin_amdgcn_readfirstlane(R->remaining[h]) == 0u;
+  }
+  __device__ __forceinline__ uint32_t open_chunk(uint64_t first, uint32_t size) const {
+    const uint32_t h = __builtin_amdgcn_readfirstlane(R->head);
+    if (lane_id() == 0) {
+      R->base[h] = first;
+      R->size[h] = size;
+      R->cursor[h] = 0u;
+      R->remaining[h] = size;
+      R->head = (h + 1u) % ChunkRing::kR;
     }
-    const PState p = flight_record(f);
-    bool alive = f.seg == EV_DONE;
-    if (alive && !inside(G.get(), p)) {
-      alive = false;
-      cnt.v[C_LOST]++;
+    return h;
+  }
+  __device__ __forceinline__ void tag(Flight& f, uint32_t t) const { f.src = t; }
+  // Stages the hole slots [first, first + k) of the next buffer.
+  __device__ __forceinline__ uint32_t push_holes(WaveStage* L, uint32_t n_staged, uint32_t first, uint32_t k) const {
+    uint32_t off = 0;
+    while (off < k) {
+      if (n_staged == kStage) {
+        flush(L, n_staged);
+        n_staged = 0;
+      }
+      const uint32_t take = k - off < kStage - n_staged ? k - off : kStage - n_staged;
+      if (lane_id() < take) reinterpret_cast<uint32_t*>(L->s[0])[n_staged + lane_id()] = first + off + lane_id();
+      n_staged += take;
+      off += take;
     }
-    if (alive) {
-      store_p(nxt.get(), f.src, p);
-    } else {
-      const uint32_t s = n_staged + rank_in(__ballot(1));
-      if (s < kStage) {
-        reinterpret_cast<uint32_t*>(L->s[0])[s] = f.src;
-        staged = true;
-      } else {
-        holes[wave_reserve(n_holes)] = f.src;
+    return n_staged;
+  }
+  __device__ __forceinline__ uint32_t done_all(const Flight& f, bool parked, Cnt& cnt, WaveStage* L,
+                                               uint32_t n_staged) const {
+    PState p;
+    bool alive = false;
+    if (parked) {
+      if (f.seg == EV_ATTACHED) {
+        const EventSink e = ev.get();
+        if (e.ax) record_attachment(e, f);
+      }
+      p = flight_record(f);
+      alive = f.seg == EV_DONE;
+      if (alive && !inside(G.get(), p)) {
+        alive = false;
+        cnt.v[C_LOST]++;
       }
     }
+    // One round per chunk among the finishing electrons: the survivors take
+    // the chunk's next slots, and a chunk whose electrons have all finished
+    // hands the rest of its range to the hole list.
+    const uint32_t lane = lane_id();
+    uint64_t pending = __ballot(parked);
+    uint32_t slot = 0;
+    while (pending) {
+      const int leader = __ffsll((unsigned long long)pending) - 1;
+      const uint32_t r = __builtin_amdgcn_readlane(f.src, leader);
+      const uint64_t m_all = __ballot(parked && f.src == r);
+      const uint64_t m_alive = __ballot(parked && alive && f.src == r);
+      const uint32_t base = __builtin_amdgcn_readfirstlane((uint32_t)R->base[r]);
+      const uint32_t cur = __builtin_amdgcn_readfirstlane(R->cursor[r]);
+      const uint32_t rem = __builtin_amdgcn_readfirstlane(R->remaining[r]);
+      const uint32_t size = __builtin_amdgcn_readfirstlane(R->size[r]);
+      if ((m_alive >> lane) & 1) slot = base + cur + rank_in(m_alive);
+      const uint32_t cur2 = cur + (uint32_t)__popcll(m_alive);
+      const uint32_t rem2 = rem - (uint32_t)__popcll(m_all);
+      if (lane == 0) {
+        R->cursor[r] = cur2;
+        R->remaining[r] = rem2;
+      }
+      if (rem2 == 0u && cur2 < size) n_staged = push_holes(L, n_staged, base + cur2, size - cur2);
+      pending &= ~m_all;
+    }
+    if (alive) store_p(nxt.get(), slot, p);
+    return n_staged;
   }
   __device__ __forceinline__ void flush(WaveStage* L, uint32_t n) const {
     unsigned long long base = 0;
@@ -127,34 +198,41 @@ struct PlaceNewborn {
     else
       atomicOr(overflow, OVF_CAPACITY);
   }
-  __device__ __forceinline__ void done_all(const Flight& f, bool parked, Cnt& cnt, WaveStage* L,
-                                           uint32_t n_staged, bool& staged) const {
-    if (!parked) return;
-    if (f.seg == EV_ATTACHED) {
-      const EventSink e = ev.get();
-      if (e.ax) record_attachment(e, f);
+  __device__ __forceinline__ bool can_open() const { return true; }
+  __device__ __forceinline__ uint32_t open_chunk(uint64_t, uint32_t) const { return 0u; }
+  __device__ __forceinline__ void tag(Flight&, uint32_t) const {}
+  __device__ __forceinline__ uint32_t done_all(const Flight& f, bool parked, Cnt& cnt, WaveStage* L,
+                                               uint32_t n_staged) const {
+    bool staged = false;
+    if (parked) {
+      if (f.seg == EV_ATTACHED) {
+        const EventSink e = ev.get();
+        if (e.ax) record_attachment(e, f);
+      }
+      const PState p = flight_record(f);
+      bool alive = f.seg == EV_DONE;
+      if (alive && !inside(G.get(), p)) {
+        alive = false;
+        cnt.v[C_LOST]++;
+      }
+      if (alive) {
+        const uint32_t s = n_staged + rank_in(__ballot(1));
+        if (s < kStage) {
+          L->s[0][s] = p.x;
+          L->s[1][s] = p.y;
+          L->s[2][s] = p.z;
+          L->s[3][s] = p.vx;
+          L->s[4][s] = p.vy;
+          L->s[5][s] = p.vz;
+          L->s[6][s] = p.w;
+          L->sid[s] = p.id;
+          staged = true;
+        } else {
+          place(wave_reserve(child), p);
+        }
+      }
     }
-    const PState p = flight_record(f);
-    bool alive = f.seg == EV_DONE;
-    if (alive && !inside(G.get(), p)) {
-      alive = false;
-      cnt.v[C_LOST]++;
-    }
-    if (!alive) return;
-    const uint32_t s = n_staged + rank_in(__ballot(1));
-    if (s < kStage) {
-      L->s[0][s] = p.x;
-      L->s[1][s] = p.y;
-      L->s[2][s] = p.z;
-      L->s[3][s] = p.vx;
-      L->s[4][s] = p.vy;
-      L->s[5][s] = p.vz;
-      L->s[6][s] = p.w;
-      L->sid[s] = p.id;
-      staged = true;
-    } else {
-      place(wave_reserve(child), p);
-    }
+    return n_staged + (uint32_t)__popcll(__ballot(staged));
   }
   __device__ __forceinline__ void flush(WaveStage* L, uint32_t n) const {
     unsigned long long base = 0;
@@ -190,6 +268,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
   cg::grid_group grid = cg::this_grid();
   const Tab T = stage_tables(A.T, A.S, smem);
   WaveStage* L = reinterpret_cast<WaveStage*>(smem + pic_stage_offset_floats(A.T)) + (threadIdx.x >> 6);
+  ChunkRing* ring = reinterpret_cast<ChunkRing*>(reinterpret_cast<WaveStage*>(smem + pic_stage_offset_floats(A.T)) +
+                                                 (blockDim.x >> 6)) +
+                    (threadIdx.x >> 6);
   GridView G = A.G;
   G.a_glob = G.qm_abs * __uint_as_float(*A.emax_bits);
   const auto* ka = (const __attribute__((address_space(4))) PicArgs*)__builtin_amdgcn_kernarg_segment_ptr();
@@ -215,7 +296,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     {
       const BirthSink sink{{&ka->pend[0]}, &ctl->pend[0], A.pend_cap, &ctl->overflow, 0u, ev_k};
       const SoaSource src{cur_k};
-      const KeepInPlace fin{grid_k, nxt_k, A.holes, &ctl->holes, ev_k};
+      const KeepInPlace fin{grid_k, nxt_k, A.holes, &ctl->holes, ev_k, ring};
+      ring->reset();
       fly_all<REFILL>(n_cur, &ctl->take[0], chunk_k, A.dt, F, T, A.S, step, cnt, sink, nullptr, L, src, fin);
     }
     grid.sync();
@@ -543,7 +625,7 @@ __global__ void k_lookup(TableView TV, SpeciesView S, const float* __restrict__ 
 size_t table_lds_bytes(const TableView& T) { return table_lds_floats(T) * sizeof(float); }
 
 size_t pic_lds_bytes(const TableView& T, int block) {
-  return pic_stage_offset_floats(T) * sizeof(float) + (size_t)(block / 64) * sizeof(WaveStage);
+  return pic_stage_offset_floats(T) * sizeof(float) + (size_t)(block / 64) * (sizeof(WaveStage) + sizeof(ChunkRing));
 }
 
 static const void* pic_steps_kernel(int refill) {

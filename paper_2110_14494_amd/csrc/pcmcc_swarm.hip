@@ -109,30 +109,36 @@ struct SwarmPlace {
   unsigned long long* n_nxt;
   unsigned long long* cum_att;
   unsigned* overflow;
-  __device__ __forceinline__ void done_all(const Flight& f, bool parked, Cnt&, WaveStage* L, uint32_t n_staged,
-                                           bool& staged) const {
+  __device__ __forceinline__ bool can_open() const { return true; }
+  __device__ __forceinline__ uint32_t open_chunk(uint64_t, uint32_t) const { return 0u; }
+  __device__ __forceinline__ void tag(Flight&, uint32_t) const {}
+  __device__ __forceinline__ uint32_t done_all(const Flight& f, bool parked, Cnt&, WaveStage* L,
+                                               uint32_t n_staged) const {
     group_count(cum_att, f.tag, parked && f.seg == EV_ATTACHED);
-    if (!parked || f.seg != EV_DONE) return;
-    const PState p = flight_record(f);
-    const uint32_t s = n_staged + rank_in(__ballot(1));
-    if (s < kStage) {
-      L->s[0][s] = p.x;
-      L->s[1][s] = p.y;
-      L->s[2][s] = p.z;
-      L->s[3][s] = p.vx;
-      L->s[4][s] = p.vy;
-      L->s[5][s] = p.vz;
-      L->s[6][s] = p.w;
-      L->stag[s] = f.tag;
-      L->sid[s] = p.id;
-      staged = true;
-    } else {
-      const uint64_t slot = atomicAdd(&n_nxt[f.tag], 1ull);
-      if (slot < cap_s[f.tag])
-        store_p(nxt.get(), base[f.tag] + slot, p);
-      else
-        atomicOr(overflow, OVF_CAPACITY);
+    bool staged = false;
+    if (parked && f.seg == EV_DONE) {
+      const PState p = flight_record(f);
+      const uint32_t s = n_staged + rank_in(__ballot(1));
+      if (s < kStage) {
+        L->s[0][s] = p.x;
+        L->s[1][s] = p.y;
+        L->s[2][s] = p.z;
+        L->s[3][s] = p.vx;
+        L->s[4][s] = p.vy;
+        L->s[5][s] = p.vz;
+        L->s[6][s] = p.w;
+        L->stag[s] = f.tag;
+        L->sid[s] = p.id;
+        staged = true;
+      } else {
+        const uint64_t slot = atomicAdd(&n_nxt[f.tag], 1ull);
+        if (slot < cap_s[f.tag])
+          store_p(nxt.get(), base[f.tag] + slot, p);
+        else
+          atomicOr(overflow, OVF_CAPACITY);
+      }
     }
+    return n_staged + (uint32_t)__popcll(__ballot(staged));
   }
   __device__ __forceinline__ void flush(WaveStage* L, uint32_t n) const {
     const uint32_t l = lane_id();
