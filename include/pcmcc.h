@@ -184,11 +184,13 @@ int pcmcc_push_collide_deposit(pcmcc_ctx* ctx, const pcmcc_particles* p, const p
  * zero field takes the default. */
 typedef struct pcmcc_schedule {
   int block;          /* threads per block: 64, 128, 256 or 512; 0 = the size with the most resident waves per
-                         compute unit (ties: the larger block) */
-  int blocks_per_cu;  /* persistent blocks per compute unit; 0 = as many as fit */
+                         compute unit (ties: the larger block), or 64 for a call that starts with fewer than
+                         2^17 particles */
+  int blocks_per_cu;  /* persistent blocks per compute unit; 0 = as many as fit (1 with the 64-thread default of a
+                         small call) */
   int refill_min;     /* free lanes of a wave that trigger a finish-and-refill batch: 16, 24 or 32; 0 = 24 */
   int chunk;          /* electrons a wave takes from the work counter at a time: a power of two in [64, 4096];
-                         0 = 256 */
+                         0 = 256 (64 for a call that starts with fewer than 2^17 particles) */
 } pcmcc_schedule;
 
 /* Sets the schedule of later steps on ctx (s NULL: all defaults).
@@ -196,7 +198,8 @@ typedef struct pcmcc_schedule {
 int pcmcc_set_schedule(pcmcc_ctx* ctx, const pcmcc_schedule* s);
 
 /* The schedule the next step call on ctx uses for this field's tables and
- * block limits, every field resolved (host *out). */
+ * block limits, every field resolved, for a call that starts with 2^17
+ * particles or more (host *out). */
 int pcmcc_get_schedule(pcmcc_ctx* ctx, pcmcc_schedule* out);
 
 /* Launch-shape tuner of the step kernel: times n_steps steps (seed, step0

@@ -231,13 +231,14 @@ int pcmcc_autotune_steps(pcmcc_ctx* c, const pcmcc_particles* p, const pcmcc_gri
                 n0 > 0 ? (int)std::lround(std::log2((double)n0)) : 0, field->nx, field->ny, field->nz, c->n_e,
                 c->n_proc);
   const std::string key(keybuf);
+  const uint64_t nh = (uint64_t)std::max<int64_t>(n0, 1);  // the population the schedules are resolved for
   load_tune_cache(c, tune_cache);
   if (c->tuned.count(key)) {
     const auto& t = c->tuned[key];
     const pcmcc_schedule s{t[0], t[1], t[2], t[3]};
     StepLaunch L;
     if (check_schedule(c, s) == PCMCC_OK &&
-        resolve_launch(c, s, pic_lds_bytes_s, occupancy_pic_steps, table_view(c), 0, &L) == PCMCC_OK) {
+        resolve_launch(c, s, pic_lds_bytes_s, occupancy_pic_steps, table_view(c), 0, &L, nh) == PCMCC_OK) {
       c->sched = s;
       if (chosen) *chosen = pcmcc_schedule{L.block, L.bpc, L.refill, L.chunk};
       return PCMCC_OK;
@@ -275,7 +276,7 @@ int pcmcc_autotune_steps(pcmcc_ctx* c, const pcmcc_particles* p, const pcmcc_gri
   pcmcc_schedule best_s{};
   auto time_one = [&](const pcmcc_schedule& s, float* t_out) -> int {
     StepLaunch L;
-    int r = resolve_launch(c, s, pic_lds_bytes_s, occupancy_pic_steps, table_view(c), 0, &L);
+    int r = resolve_launch(c, s, pic_lds_bytes_s, occupancy_pic_steps, table_view(c), 0, &L, nh);
     if (r) return r;
     c->sched = s;
     HIP_TRY(c, copy_all(false));

@@ -169,14 +169,16 @@ int check_schedule(pcmcc_ctx* c, const pcmcc_schedule& s) {
 }
 
 int resolve_launch(pcmcc_ctx* c, const pcmcc_schedule& s, size_t (*lds)(const TableView&, int, int),
-                   hipError_t (*occ)(int, int, size_t, int*), const TableView& T, int S, StepLaunch* out) {
+                   hipError_t (*occ)(int, int, size_t, int*), const TableView& T, int S, StepLaunch* out,
+                   uint64_t n_hint) {
   const int rc = check_schedule(c, s);
   if (rc) return rc;
+  const bool small = n_hint > 0 && n_hint < kSmallPopulation && !s.block;
   const int refill = s.refill_min ? s.refill_min : 24;
-  const int chunk = s.chunk ? s.chunk : 256;
+  const int chunk = s.chunk ? s.chunk : (small ? 64 : 256);
   int block = 0, per_cu = 0;
   for (int b : {512, 256, 128, 64}) {
-    if (s.block && b != s.block) continue;
+    if ((s.block && b != s.block) || (small && b != 64)) continue;
     int k = 0;
     HIP_TRY(c, occ(b, refill, lds(T, S, b), &k));
     if (k >= 1 && k * b > per_cu * block) {  // most resident waves; ties keep the larger block
@@ -188,7 +190,7 @@ int resolve_launch(pcmcc_ctx* c, const pcmcc_schedule& s, size_t (*lds)(const Ta
   if (s.blocks_per_cu > per_cu)
     return fail(c, PCMCC_EINVAL, "blocks_per_cu %d exceeds the %d blocks of %d that fit", s.blocks_per_cu, per_cu,
                 block);
-  const int bpc = s.blocks_per_cu ? s.blocks_per_cu : per_cu;
+  const int bpc = s.blocks_per_cu ? s.blocks_per_cu : (small ? 1 : per_cu);
   *out = StepLaunch{block, bpc, refill, chunk, bpc * c->num_cu};
   return PCMCC_OK;
 }
@@ -466,7 +468,7 @@ int push_impl(pcmcc_ctx* c, const pcmcc_particles* p, const pcmcc_grid* field, d
 
   const TableView T = table_view(c);
   StepLaunch sl;
-  rc = resolve_launch(c, c->sched, pic_lds_bytes_s, occupancy_pic_steps, T, 0, &sl);
+  rc = resolve_launch(c, c->sched, pic_lds_bytes_s, occupancy_pic_steps, T, 0, &sl, (uint64_t)std::max<int64_t>(n0, 1));
   if (rc) return rc;
   const int block = sl.block, grid = sl.grid;
   if (c->partial_blocks < grid) {

@@ -169,8 +169,14 @@ inline size_t pic_lds_bytes_s(const TableView& T, int, int block) { return pic_l
 inline size_t swarm_lds_bytes_s(const TableView& T, int S, int block) { return swarm_lds_bytes(T, S, block); }
 // lds(block): dynamic LDS bytes of the kernel at that block size; occ(block,
 // refill, lds, &per_cu) its occupancy query.
+// n_hint (0: none) is the start population of a step call: below
+// kSmallPopulation electrons the unset fields default to one 64-thread block
+// per CU and chunks of 64, since grid barriers over fewer, smaller blocks
+// cost less and a small population fills few waves anyway.
+constexpr uint64_t kSmallPopulation = 1u << 17;
 int resolve_launch(pcmcc_ctx* c, const pcmcc_schedule& s, size_t (*lds)(const TableView&, int, int),
-                   hipError_t (*occ)(int, int, size_t, int*), const TableView& T, int S, StepLaunch* out);
+                   hipError_t (*occ)(int, int, size_t, int*), const TableView& T, int S, StepLaunch* out,
+                   uint64_t n_hint = 0);
 void load_tune_cache(pcmcc_ctx* c, const char* path);
 void save_tune_cache(pcmcc_ctx* c, const char* path);
 bool valid_grid(const pcmcc_grid* g);
