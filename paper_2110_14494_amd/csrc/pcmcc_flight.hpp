@@ -332,7 +332,7 @@ __device__ __forceinline__ int flight_plan(Flight& f, double dt, const Tab& T, c
 
 // Completes the pending segment with the acceleration `an` gathered at its
 // end point, then applies its collision, if any.
-template <class Field>
+template <int ROW, class Field>
 __device__ __forceinline__ int flight_complete(Flight& f, const double3 an, const Tab& T, const SpeciesView& S,
                                                Cnt& cnt, const StagedBirths<Field>& births, bool& staged) {
   const double hh = 0.5 * f.h;
@@ -355,15 +355,15 @@ __device__ __forceinline__ int flight_complete(Flight& f, const double3 an, cons
   const int i = (int)fl;
   const float fr = u - fl;
   const float yv = unif(f.r1) * f.nu_hat;
-  float cum[kMaxProc];
-  cum_rates(T, i, fr, cum, tc.row);
+  float cum[ROW];
+  cum_rates_row<ROW>(T, i, fr, cum);
   // the total rate (the largest cumulative entry; padding entries are zero)
   // must not exceed the majorant
   float tot = cum[0];
 #pragma unroll
-  for (int kk = 1; kk < kMaxProc; ++kk) tot = fmaxf(tot, cum[kk]);
+  for (int kk = 1; kk < ROW; ++kk) tot = fmaxf(tot, cum[kk]);
   cnt.v[C_MAJ] += tot > f.nu_hat;
-  const int k = pick_process(cum, yv);
+  const int k = pick_process_row<ROW>(cum, yv);
   if (k < 0 || eps < (double)T.thr[k]) {
     cnt.v[C_NULL]++;
     return EV_GO;
@@ -396,7 +396,8 @@ __device__ __forceinline__ int flight_complete(Flight& f, const double3 an, cons
   return EV_GO;
 }
 
-// Runs every electron of a source (n of them) through the rest of the step,
+// Runs every electron of a source (n of them) through the rest of the step
+// (tables of ROW floats per node, table_row(nproc)),
 // REFILL lanes at a time (see above), `chunk` (a power of two in [kChunkMin,
 // kChunkMax], read from the kernel arguments) electrons per work-counter
 // grab.
@@ -414,7 +415,7 @@ __device__ __forceinline__ int flight_complete(Flight& f, const double3 an, cons
 // arguments; `take` is the grid-wide work counter (zero before the first
 // wave starts).  cum_ion (nullable) counts ionizations per group.  Every
 // staged entry is written out before the function returns.
-template <int REFILL, class Field, class Source, class Finish>
+template <int REFILL, int ROW, class Field, class Source, class Finish>
 __device__ __forceinline__ void fly_all(uint64_t n, unsigned long long* take, KArg<uint32_t> chunk, double dt,
                                         const Field& F, const Tab& T, const SpeciesView& S, uint32_t step, Cnt& cnt,
                                         const BirthSink& sink, unsigned long long* cum_ion, WaveStage* L,
@@ -498,7 +499,7 @@ __device__ __forceinline__ void fly_all(uint64_t n, unsigned long long* take, KA
         f.mode = FM_FLY;
         ev = EV_GO;
       } else {
-        ev = flight_complete(f, an, T, S, cnt, births, born);
+        ev = flight_complete<ROW>(f, an, T, S, cnt, births, born);
       }
       if (ev == EV_GO) ev = flight_plan(f, dt, T, S, F.key(f.tag), step, cnt);
       if (ev != EV_GO) {

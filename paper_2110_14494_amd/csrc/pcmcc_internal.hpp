@@ -260,14 +260,15 @@ size_t swarm_lds_bytes(const TableView& T, int S, int block);
 // within a granule of a 1/k share of the compute unit.
 hipError_t coresident_blocks(const void* k, int block, size_t lds, int* blocks_per_cu);
 // refill: one of kRefillChoices (free lanes that trigger a refill batch)
-hipError_t occupancy_swarm_steps(int block, int refill, size_t lds, int* blocks_per_cu);
+// row: floats per table node (table_row(nproc)), which selects the kernel build
+hipError_t occupancy_swarm_steps(int block, int refill, int row, size_t lds, int* blocks_per_cu);
 hipError_t launch_swarm_steps(const SwarmArgs& args, int grid, int block, int refill, hipStream_t stream);
 hipError_t launch_swarm_init(const Soa& buf, const uint64_t* base, const int32_t* n0, int S, hipStream_t stream);
 hipError_t launch_swarm_estimate(const unsigned long long* mom, const long long* cnt, int S, int J, double dt_sample,
                                  double t_window, int n_batches, const double* EN, double gas_N, double* values,
                                  double* errors, double* work, hipStream_t stream);
 hipError_t launch_pic_steps(const PicArgs& args, int grid, int block, int refill, hipStream_t stream);
-hipError_t occupancy_pic_steps(int block, int refill, size_t lds, int* blocks_per_cu);
+hipError_t occupancy_pic_steps(int block, int refill, int row, size_t lds, int* blocks_per_cu);
 hipError_t launch_finalize(const Soa& user, const Soa& scratch, Ctl* ctl, int64_t* n_dev, hipStream_t stream);
 DepositNeeds deposit_needs(const DepositGeom& g, uint64_t n);
 hipError_t launch_deposit_binned(const float* x, const float* y, const float* z, const float* w, uint64_t n,

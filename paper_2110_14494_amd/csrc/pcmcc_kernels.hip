@@ -262,7 +262,7 @@ struct PlaceNewborn {
 // Four waves per SIMD (at most 128 registers a lane): the mover waits on
 // one gather per segment, and a fourth wave hides that latency better than
 // the registers the compiler would otherwise keep.
-template <int REFILL>
+template <int REFILL, int ROW>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_pic_steps(PicArgs A) {
   extern __shared__ float smem[];
   cg::grid_group grid = cg::this_grid();
@@ -298,7 +298,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
       const SoaSource src{cur_k};
       const KeepInPlace fin{grid_k, nxt_k, A.holes, &ctl->holes, ev_k, ring};
       ring->reset();
-      fly_all<REFILL>(n_cur, &ctl->take[0], chunk_k, A.dt, F, T, A.S, step, cnt, sink, nullptr, L, src, fin);
+      fly_all<REFILL, ROW>(n_cur, &ctl->take[0], chunk_k, A.dt, F, T, A.S, step, cnt, sink, nullptr, L, src, fin);
     }
     grid.sync();
 
@@ -316,7 +316,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
       const BirthSink sink{{&ka->pend[(g + 1) & 1]}, &ctl->pend[g + 1], A.pend_cap, &ctl->overflow, 0u, ev_k};
       const PendSource src{{&ka->pend[g & 1]}};
       const PlaceNewborn fin{grid_k, nxt_k, A.holes, h, n_cur, A.cap, &ctl->child, &ctl->overflow, ev_k};
-      fly_all<REFILL>(np, &ctl->take[g + 1], chunk_k, A.dt, F, T, A.S, step, cnt, sink, nullptr, L, src, fin);
+      fly_all<REFILL, ROW>(np, &ctl->take[g + 1], chunk_k, A.dt, F, T, A.S, step, cnt, sink, nullptr, L, src, fin);
       grid.sync();
     }
 
@@ -628,17 +628,22 @@ size_t pic_lds_bytes(const TableView& T, int block) {
   return pic_stage_offset_floats(T) * sizeof(float) + (size_t)(block / 64) * (sizeof(WaveStage) + sizeof(ChunkRing));
 }
 
-static const void* pic_steps_kernel(int refill) {
+template <int ROW>
+static const void* pic_steps_kernel_row(int refill) {
   switch (refill) {
-    case 16: return (const void*)k_pic_steps<16>;
-    case 24: return (const void*)k_pic_steps<24>;
-    case 32: return (const void*)k_pic_steps<32>;
+    case 16: return (const void*)k_pic_steps<16, ROW>;
+    case 24: return (const void*)k_pic_steps<24, ROW>;
+    case 32: return (const void*)k_pic_steps<32, ROW>;
     default: return nullptr;
   }
 }
 
+static const void* pic_steps_kernel(int refill, int row) {
+  return row == 4 ? pic_steps_kernel_row<4>(refill) : row == 8 ? pic_steps_kernel_row<8>(refill) : nullptr;
+}
+
 hipError_t launch_pic_steps(const PicArgs& args, int grid, int block, int refill, hipStream_t stream) {
-  const void* k = pic_steps_kernel(refill);
+  const void* k = pic_steps_kernel(refill, table_row(args.T.nproc));
   if (!k) return hipErrorInvalidValue;
   void* kargs[] = {(void*)&args};
   return hipLaunchCooperativeKernel(k, dim3(grid), dim3(block), kargs, (unsigned)pic_lds_bytes(args.T, block),
@@ -659,8 +664,8 @@ hipError_t coresident_blocks(const void* k, int block, size_t lds, int* blocks_p
   return hipSuccess;
 }
 
-hipError_t occupancy_pic_steps(int block, int refill, size_t lds, int* blocks_per_cu) {
-  const void* k = pic_steps_kernel(refill);
+hipError_t occupancy_pic_steps(int block, int refill, int row, size_t lds, int* blocks_per_cu) {
+  const void* k = pic_steps_kernel(refill, row);
   if (!k) return hipErrorInvalidValue;
   return coresident_blocks(k, block, lds, blocks_per_cu);
 }

@@ -228,6 +228,33 @@ __device__ __forceinline__ void cum_rates(const Tab& T, int i, float f, float c[
   cum_rates(T, i, f, c, T.row);
 }
 
+// The cumulative rates of a table of ROW (4 or 8) floats per node, the
+// row fixed at compile time.
+template <int ROW>
+__device__ __forceinline__ void cum_rates_row(const Tab& T, int i, float f, float c[ROW]) {
+  const float4* a = reinterpret_cast<const float4*>(T.C + (size_t)i * ROW);
+  const float4* b = reinterpret_cast<const float4*>(T.C + (size_t)(i + 1) * ROW);
+#pragma unroll
+  for (int h = 0; h < ROW / 4; ++h) {
+    const float4 lo = a[h], hi = b[h];
+    c[4 * h] = fmaf(f, hi.x - lo.x, lo.x);
+    c[4 * h + 1] = fmaf(f, hi.y - lo.y, lo.y);
+    c[4 * h + 2] = fmaf(f, hi.z - lo.z, lo.z);
+    c[4 * h + 3] = fmaf(f, hi.w - lo.w, lo.w);
+  }
+}
+
+// First process whose cumulative rate exceeds y, or -1 (a null collision),
+// over a row of ROW entries (entries past the last process are zero).
+template <int ROW>
+__device__ __forceinline__ int pick_process_row(const float c[ROW], float y) {
+  int k = -1;
+#pragma unroll
+  for (int kk = ROW - 1; kk >= 0; --kk)
+    if (y < c[kk]) k = kk;
+  return k;
+}
+
 // First process whose cumulative rate exceeds y, or -1 (a null collision).
 __device__ __forceinline__ int pick_process(const float c[kMaxProc], float y) {
   int k = -1;

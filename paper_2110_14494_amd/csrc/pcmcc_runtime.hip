@@ -169,7 +169,7 @@ int check_schedule(pcmcc_ctx* c, const pcmcc_schedule& s) {
 }
 
 int resolve_launch(pcmcc_ctx* c, const pcmcc_schedule& s, size_t (*lds)(const TableView&, int, int),
-                   hipError_t (*occ)(int, int, size_t, int*), const TableView& T, int S, StepLaunch* out,
+                   hipError_t (*occ)(int, int, int, size_t, int*), const TableView& T, int S, StepLaunch* out,
                    uint64_t n_hint) {
   const int rc = check_schedule(c, s);
   if (rc) return rc;
@@ -180,7 +180,7 @@ int resolve_launch(pcmcc_ctx* c, const pcmcc_schedule& s, size_t (*lds)(const Ta
   for (int b : {512, 256, 128, 64}) {
     if ((s.block && b != s.block) || (small && b != 64)) continue;
     int k = 0;
-    HIP_TRY(c, occ(b, refill, lds(T, S, b), &k));
+    HIP_TRY(c, occ(b, refill, table_row(T.nproc), lds(T, S, b), &k));
     if (k >= 1 && k * b > per_cu * block) {  // most resident waves; ties keep the larger block
       block = b;
       per_cu = k;

@@ -175,7 +175,7 @@ inline size_t swarm_lds_bytes_s(const TableView& T, int S, int block) { return s
 // cost less and a small population fills few waves anyway.
 constexpr uint64_t kSmallPopulation = 1u << 17;
 int resolve_launch(pcmcc_ctx* c, const pcmcc_schedule& s, size_t (*lds)(const TableView&, int, int),
-                   hipError_t (*occ)(int, int, size_t, int*), const TableView& T, int S, StepLaunch* out,
+                   hipError_t (*occ)(int, int, int, size_t, int*), const TableView& T, int S, StepLaunch* out,
                    uint64_t n_hint = 0);
 void load_tune_cache(pcmcc_ctx* c, const char* path);
 void save_tune_cache(pcmcc_ctx* c, const char* path);

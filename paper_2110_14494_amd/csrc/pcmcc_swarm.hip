@@ -239,7 +239,7 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
 }
 
 // ---------------------------------------------------------------------------
-template <int BS, int REFILL>
+template <int BS, int REFILL, int ROW>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_swarm_steps(SwarmArgs A) {
   extern __shared__ float smem[];
   cg::grid_group grid = cg::this_grid();
@@ -289,7 +289,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_
     {
       const BirthSink sink{{&ka->pend[0]}, &ctl->pend[0], A.pend_cap, &ctl->overflow, 0u, no_events};
       const SwarmLoad src{cur_k, A.base, prefix, pck, S, A.key, step, sink, &psteps};
-      fly_all<REFILL>((uint64_t)prefix[S], &ctl->take[0], chunk_k, (double)A.dt, F, T, A.S, step, cnt, sink,
+      fly_all<REFILL, ROW>((uint64_t)prefix[S], &ctl->take[0], chunk_k, (double)A.dt, F, T, A.S, step, cnt, sink,
                       A.cum_ion, L, src, fin);
     }
     grid.sync();
@@ -305,7 +305,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_
       const uint64_t np = np_raw < A.pend_cap ? np_raw : A.pend_cap;
       const BirthSink sink{{&ka->pend[(g + 1) & 1]}, &ctl->pend[g + 1], A.pend_cap, &ctl->overflow, 0u, no_events};
       const SwarmPend src{{&ka->pend[g & 1]}};
-      fly_all<REFILL>(np, &ctl->take[g + 1], chunk_k, (double)A.dt, F, T, A.S, step, cnt, sink, A.cum_ion, L, src,
+      fly_all<REFILL, ROW>(np, &ctl->take[g + 1], chunk_k, (double)A.dt, F, T, A.S, step, cnt, sink, A.cum_ion, L, src,
                       fin);
       grid.sync();
     }
@@ -595,34 +595,39 @@ size_t swarm_lds_bytes(const TableView& T, int S, int block) {
          (size_t)(S + 1) * 4 + (size_t)block * 4 + (size_t)S * 4 + (size_t)S * 4;
 }
 
-template <int BS>
+template <int BS, int ROW>
 static const void* swarm_kernel_r(int refill) {
   switch (refill) {
-    case 16: return (const void*)k_swarm_steps<BS, 16>;
-    case 24: return (const void*)k_swarm_steps<BS, 24>;
-    case 32: return (const void*)k_swarm_steps<BS, 32>;
+    case 16: return (const void*)k_swarm_steps<BS, 16, ROW>;
+    case 24: return (const void*)k_swarm_steps<BS, 24, ROW>;
+    case 32: return (const void*)k_swarm_steps<BS, 32, ROW>;
     default: return nullptr;
   }
 }
 
-static const void* swarm_kernel(int block, int refill) {
+template <int ROW>
+static const void* swarm_kernel_b(int block, int refill) {
   switch (block) {
-    case 64: return swarm_kernel_r<64>(refill);
-    case 128: return swarm_kernel_r<128>(refill);
-    case 256: return swarm_kernel_r<256>(refill);
-    case 512: return swarm_kernel_r<512>(refill);
+    case 64: return swarm_kernel_r<64, ROW>(refill);
+    case 128: return swarm_kernel_r<128, ROW>(refill);
+    case 256: return swarm_kernel_r<256, ROW>(refill);
+    case 512: return swarm_kernel_r<512, ROW>(refill);
     default: return nullptr;
   }
 }
 
-hipError_t occupancy_swarm_steps(int block, int refill, size_t lds, int* blocks_per_cu) {
-  const void* k = swarm_kernel(block, refill);
+static const void* swarm_kernel(int block, int refill, int row) {
+  return row == 4 ? swarm_kernel_b<4>(block, refill) : row == 8 ? swarm_kernel_b<8>(block, refill) : nullptr;
+}
+
+hipError_t occupancy_swarm_steps(int block, int refill, int row, size_t lds, int* blocks_per_cu) {
+  const void* k = swarm_kernel(block, refill, row);
   if (!k) return hipErrorInvalidValue;
   return coresident_blocks(k, block, lds, blocks_per_cu);
 }
 
 hipError_t launch_swarm_steps(const SwarmArgs& args, int grid, int block, int refill, hipStream_t stream) {
-  const void* k = swarm_kernel(block, refill);
+  const void* k = swarm_kernel(block, refill, table_row(args.T.nproc));
   if (!k) return hipErrorInvalidValue;
   void* kargs[] = {(void*)&args};
   return hipLaunchCooperativeKernel(k, dim3(grid), dim3(block), kargs,
