@@ -57,10 +57,11 @@ SLOTS_REAL = 73.0        # a real collision: isotropic direction, recoil or thre
 SLOTS_BIRTH = 160.0      # a newborn: its Philox draw, direction and speed
 SLOTS_PSTEP = 35.0       # a particle-step: start (conversions, field bound) and finish (domain test, stores)
 BYTES_PER_PSTEP = 72.0  # 36 B read + 36 B written
-BYTES_PER_BIRTH = 116.0  # queued (40 B), read back (40 B), written (36 B)
+BYTES_PER_BIRTH = 36.0  # the newborn written
+BYTES_QUEUE_PER_BIRTH = 80.0  # the newborn queue's own round trip (40 B written, 40 B read back), reported apart
 KERNEL_SOURCES = ("paper_2110_14494_amd/csrc/pcmcc_kernels.hip", "paper_2110_14494_amd/csrc/pcmcc_flight.hpp",
                   "paper_2110_14494_amd/csrc/pcmcc_mover.hpp", "paper_2110_14494_amd/csrc/pcmcc_device.hpp",
-                  "paper_2110_14494_amd/csrc/pcmcc_internal.hpp")
+                  "paper_2110_14494_amd/csrc/pcmcc_internal.hpp", "paper_2110_14494_amd/csrc/pcmcc_runtime.hip")
 
 
 def parse():
@@ -100,6 +101,8 @@ def parse():
     ap.add_argument("--coef-scale", type=float, default=1.0, help="scale of the swarm sizes")
     ap.add_argument("--epochs", type=int, default=20000)
     ap.add_argument("--infer-n", type=int, default=100_000_000)
+    ap.add_argument("--mlp-infer-only", action="store_true",
+                    help="only time the surrogate's inference kernel (initial weights; no and full fallback)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy MIB mebibytes device to device (a known-size kernel for HBM counters)")
     return ap.parse_args()
@@ -265,6 +268,7 @@ def pic_run_leg(pic, cfg, cap_factor: int, steps: int, warmup: int, max_steps=No
             "candidate_fraction": (st["null"] + real) / max(st["trials"], 1),
             "real_fraction": real / max(st["trials"], 1),
             "hbm_algorithmic_bytes": bytes_alg,
+            "hbm_queue_bytes": BYTES_QUEUE_PER_BIRTH * st["ionization"],
             "hbm_algorithmic_GBs": bytes_alg / (k_ms * 1e-3) / 1e9,
             "hbm_frac": bytes_alg / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "hbm_measured_GBs": (traffic / (k_ms * 1e-3) / 1e9) if traffic else None,
@@ -698,6 +702,35 @@ def coef_leg(a, ctx, pic):
     }
 
 
+def mlp_infer_leg(a, ctx, pic) -> dict:
+    """The surrogate's BF16 inference kernel alone on a.infer_n fields drawn
+    log-uniform over 10-1000 Td: the perceptron at its initial weights, every
+    output from the network, then every output from the fallback table (the
+    waves that skip the perceptron); three calls each, kernel times from HIP
+    events."""
+    import torch
+    from paper_2110_14494_amd import _binding as B
+    from paper_2110_14494_amd import surrogate as S
+    from paper_2110_14494_amd import workloads as W
+    ctx.setup(W.electron_species(), W.air_like_tables())
+    th = W.mlp_init(9).astype(np.float32)
+    EN = torch.from_numpy(W.log_uniform_EN(a.infer_n, seed=5)).cuda()
+    o = B.pcmcc_mlp_infer_opts()
+    o.mu_x, o.sd_x = math.log(100.0), 1.33
+    o.mu_y[:], o.sd_y[:] = [0.0] * 6, [1.0] * 6
+    net = S.Norm(o)
+    lo, hi = math.log(10.0), math.log(1000.0)
+    tab = net.with_fallback(np.full(256, 0x3F, np.uint8), lo, hi, np.zeros((2048, 6), np.float32), lo, hi)
+    out = torch.empty((6, a.infer_n), dtype=torch.float32, device="cuda")
+    res = {}
+    for name, nrm in (("network", net), ("all_fallback", tab)):
+        ms = [S.infer(ctx, th, nrm, EN, out)[1]["step_kernel_ms"] for _ in range(3)]
+        res[name] = {"kernel_ms": ms, "points_per_s": a.infer_n / (min(ms) * 1e-3)}
+        log(f"mlp inference ({name}): {min(ms):.3f} ms per {a.infer_n} fields")
+    res["points"] = a.infer_n
+    return res
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -709,6 +742,11 @@ def main():
     from paper_2110_14494_amd import workloads as W
 
     assert torch.cuda.is_available(), "needs a HIP device"
+    if a.mlp_infer_only:
+        ctx = pic.Context(0)
+        print(json.dumps({"mlp_infer": mlp_infer_leg(a, ctx, pic)}))
+        ctx.close()
+        return
     if a.calibrate_copy:
         src = torch.ones(a.calibrate_copy * 2 ** 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
