@@ -585,18 +585,20 @@ def coef_leg(a, ctx, pic):
     train = np.setdiff1d(np.arange(n_all), held)
     x, t, m, ln_tr, _, norm = S.dataset(EN_all[train], vals[train], errs[train], sp["gas_N"], 0.1)
     _, _, m_h, ln_h, sig_h, _ = S.dataset(EN_all[held], vals[held], errs[held], sp["gas_N"], 0.1, norm=norm)
-    _, _, m_all, ln_all, _, _ = S.dataset(EN_all, vals, errs, sp["gas_N"], 0.1, norm=norm)
+    _, _, m_all, ln_all, sig_all, _ = S.dataset(EN_all, vals, errs, sp["gas_N"], 0.1, norm=norm)
     _, _, m_t, ln_t, sig_t, _ = S.dataset(EN_test, v_test, e_test, sp["gas_N"], 0.1, norm=norm)
     th0 = W.mlp_init(4)
     params, hist, tst = S.train(ctx, th0, x, t, m, a.epochs, 3e-3, 1e-5)
     log(f"surrogate trained: {a.epochs} epochs in {tst['step_kernel_ms']:.0f} ms, loss {hist[0]:.3g} -> {hist[-1]:.3g}")
     lo, hi = math.log(10.0), math.log(1000.0)
-    # an output of a cell falls back to the swarm table unless the held-out
-    # swarm value shows the surrogate within 1 % with a margin of two of that
-    # value's standard errors (an unresolved value, or one noisier than 0.5 %,
-    # always falls back); cells without a held-out point fall back entirely
+    # an output of a cell falls back to the swarm table unless every swarm
+    # value in the cell (its held-out point and its seven training points)
+    # shows the surrogate within 1 % with a margin of two of that value's
+    # standard errors (an unresolved value, or one noisier than 0.5 %, always
+    # falls back); the held-out errors are reported on their own below
     tol, z_sig = math.log(1.01), -2.0
-    fb, err = S.fallback(ctx, params, norm, EN_all[held], ln_h, m_h, tol, 256, lo, hi, sig_held=sig_h, z_sig=z_sig)
+    fb, _ = S.fallback(ctx, params, norm, EN_all, ln_all, m_all, tol, 256, lo, hi, sig_held=sig_all, z_sig=z_sig)
+    _, err = S.fallback(ctx, params, norm, EN_all[held], ln_h, m_h, tol, 256, lo, hi, sig_held=sig_h, z_sig=z_sig)
     # the fallback table: every swarm point (training and held-out), each
     # output interpolated over its resolved points, on 2048 uniform nodes
     nodes = np.linspace(lo, hi, 2048)
