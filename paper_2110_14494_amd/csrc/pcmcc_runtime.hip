@@ -320,9 +320,10 @@ int deposit_range_check(pcmcc_ctx* c) {
 
 // Deposit of n particles into rho on the context stream; with check, waits
 // and reports a range error (else the caller calls deposit_range_check).
-// From this many particles on, a step call starts from the population
-// sorted by tile.
+// A step call of this many particles and steps or more starts from the
+// population sorted by tile (a shorter call does not earn the sort back).
 constexpr uint64_t kSortStartMin = 1u << 20;
+constexpr int kSortStartSteps = 8;
 
 // Binned-deposit buffers for d (the sorted copy only with `sorted`).
 static int ensure_dep_work(pcmcc_ctx* c, const DepositNeeds& d, bool sorted) {
@@ -480,7 +481,7 @@ int push_impl(pcmcc_ctx* c, const pcmcc_particles* p, const pcmcc_grid* field, d
   std::memset(c->host_ctl, 0, sizeof(Ctl));
   c->host_ctl->n_cur = (unsigned long long)n0;
   // The steps alternate between the caller's arrays and the scratch buffer.
-  // A large population starts sorted by 8^3-cell tile, so that the electrons
+  // A large population over several steps starts sorted by 8^3-cell tile, so that the electrons
   // a wave takes from the work counter gather from a few field records that
   // stay in cache (the sort goes into the scratch buffer and, for an even
   // step count, is copied back).  For an odd step count the steps start from
@@ -488,7 +489,7 @@ int push_impl(pcmcc_ctx* c, const pcmcc_particles* p, const pcmcc_grid* field, d
   // copying the start population is cheaper than copying back the grown one
   // (any other outcome is copied back at the end as usual).
   const Soa user{p->x, p->y, p->z, p->vx, p->vy, p->vz, p->w, p->id};
-  const bool sort_start = n0 >= (int64_t)kSortStartMin && n_steps > 0;
+  const bool sort_start = n0 >= (int64_t)kSortStartMin && n_steps >= kSortStartSteps;
   auto copy_soa = [&](const Soa& from, const Soa& to) -> hipError_t {
     float* const f[7] = {from.x, from.y, from.z, from.vx, from.vy, from.vz, from.w};
     float* const t[7] = {to.x, to.y, to.z, to.vx, to.vy, to.vz, to.w};

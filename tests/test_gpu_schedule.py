@@ -144,14 +144,15 @@ def test_autotune_leaves_input_and_caches(pic, tmp_path):
 
 
 def test_start_order_does_not_matter(pic):
-    # 2^20 electrons: the call sorts them by tile before the first step; the
-    # same electrons in another order give the same electrons by id, the
-    # same densities and counters (odd and even step counts: the sort lands
-    # in the scratch buffer or is copied back)
+    # 2^20 electrons over 8 or 9 steps: the call sorts them by tile before
+    # the first step; the same electrons in another order give the same
+    # electrons by id, the same densities and counters (odd and even step
+    # counts: the sort lands in the scratch buffer or is copied back; and a
+    # 3-step call, which keeps the given order)
     cfg = W.tip_block_config(m=64, n=2 ** 20)
     perm = np.random.default_rng(3).permutation(cfg["parts"]["x"].size)
     shuffled = dict(cfg, parts={k: v[perm] for k, v in cfg["parts"].items()})
-    for steps in (3, 4):
+    for steps in (8, 9, 3):
         a, ra, sa = _run(pic, cfg, None, steps=steps)
         b, rb, sb = _run(pic, shuffled, None, steps=steps)
         assert len(np.unique(a["id"])) == a["id"].size
