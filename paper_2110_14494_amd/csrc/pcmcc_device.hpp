@@ -32,10 +32,13 @@ __device__ __forceinline__ uint4 philox(uint4 c, Key key) {
   uint32_t k0 = key.k0, k1 = key.k1;
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    // one 32x32 -> 64-bit product per multiplier (v_mad_u64_u32)
+    // one 32x32 -> 64-bit product per multiplier (v_mad_u64_u32); each
+    // three-way xor is one v_bitop3_b32 (truth table 0x96), which the
+    // compiler does not form from two xors by itself
     const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
-    c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
+    c = make_uint4(__builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c.y, k0, 0x96), (uint32_t)p1,
+                   __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c.w, k1, 0x96), (uint32_t)p0);
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }

@@ -295,15 +295,17 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
 
 // Isotropic unit vector from two uniforms: cos(theta) = 1 - 2 U1 and
 // sin(theta) = 2 sqrt(U1 (1 - U1)) (no cancellation near the poles; U1 and
-// 1 - U1 are exact), azimuth 2 pi U2 from a single-precision sincospi.  The
-// (cos, sin) pair has s2 = cos^2 + sin^2 within a few single-precision ulp
-// of 1, so 1/sqrt(s2) = 3/2 - s2/2 to about 1e-13: |n| = 1 to that accuracy.
+// 1 - U1 are exact), azimuth 2 pi U2.  The azimuth's sine and cosine are the
+// hardware ones, which take the angle in turns (v_sin_f32, v_cos_f32: within
+// 1.3e-7 of sin(2 pi U2), cos(2 pi U2) over all 2^23 uniforms), so s2 =
+// cos^2 + sin^2 is within 3e-7 of 1 and 1/sqrt(s2) = 3/2 - s2/2 to about
+// 4e-14: |n| = 1 to that accuracy.
 __device__ __forceinline__ void iso_dir(uint32_t r1, uint32_t r2, double& nx, double& ny, double& nz) {
   const double u = (double)unif(r1);
   const double cth = fma(-2.0, u, 1.0);
-  const double sth = 2.0 * sqrt(u * (1.0 - u));
-  float sp, cp;
-  sincospif(2.0f * unif(r2), &sp, &cp);
+  const double sth = 2.0 * sqrt_nr(u * (1.0 - u));  // u (1 - u) > 2^-25: never zero or subnormal
+  const float t = unif(r2);
+  const float sp = __builtin_amdgcn_sinf(t), cp = __builtin_amdgcn_cosf(t);
   const double s2 = fma((double)sp, (double)sp, (double)cp * cp);
   const double inv = sth * fma(-0.5, s2, 1.5);
   nx = inv * cp;
