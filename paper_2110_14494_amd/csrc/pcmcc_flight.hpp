@@ -353,8 +353,8 @@ __device__ __forceinline__ int flight_complete(Flight& f, const double3 an, cons
   const double v2 = fma(f.vz, f.vz, fma(f.vy, f.vy, f.vx * f.vx));
   const double eps = tc.k_eps_d * v2;
   float u = fmaf(__log2f((float)eps), tc.u_scale, tc.u_offset);
-  u = fminf(fmaxf(u, 0.0f), tc.u_top);
-  const float fl = fminf(floorf(u), tc.fl_top);
+  u = clamp_med3(u, 0.0f, tc.u_top);
+  const float fl = clamp_med3(floorf(u), 0.0f, tc.fl_top);
   const int i = (int)fl;
   const float fr = u - fl;
   const float yv = unif(f.r1) * f.nu_hat;
@@ -497,8 +497,8 @@ __device__ __forceinline__ void fly_all(uint64_t n, unsigned long long* take, KA
         f.ax = an.x;
         f.ay = an.y;
         f.az = an.z;
-        F.bound_at(where, f.tag, sqrtf((float)fma(f.vz, f.vz, fma(f.vy, f.vy, f.vx * f.vx))), (float)(dt - f.t),
-                   f.a_abs, f.da);
+        F.bound_at(where, f.tag, __builtin_amdgcn_sqrtf((float)fma(f.vz, f.vz, fma(f.vy, f.vy, f.vx * f.vx))),
+                   (float)(dt - f.t), f.a_abs, f.da);
         f.mode = FM_FLY;
         ev = EV_GO;
       } else {

@@ -264,12 +264,18 @@ __device__ __forceinline__ int pick_process(const float c[kMaxProc], float y) {
   return k;
 }
 
+// x clamped to [lo, hi] (lo <= hi, x not NaN) in one v_med3_f32; fminf and
+// fmaxf would first quiet every operand read from memory.
+__device__ __forceinline__ float clamp_med3(float x, float lo, float hi) {
+  return __builtin_amdgcn_fmed3f(x, lo, hi);
+}
+
 __device__ __forceinline__ float majorant_t(const Tab& T, const TabConst& c, float s_ub) {
   const float s = s_ub * kGuard;
   const float eps = c.k_eps * s * s;
   float u = fmaf(__log2f(eps), c.u_scale, c.u_offset);
-  u = fminf(fmaxf(u, 0.0f), c.u_top);
-  const float fl = fminf(floorf(u), c.fl_top);
+  u = clamp_med3(u, 0.0f, c.u_top);
+  const float fl = clamp_med3(floorf(u), 0.0f, c.fl_top);
   const int i = (int)fl;
   return lerp_at(T.C + c.p_off, i, u - fl);
 }
