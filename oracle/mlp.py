@@ -105,11 +105,13 @@ def bf16_round(a):
 
 
 def forward_bf16(theta, x):
-    """The inference as the device computes it: weights and hidden activations
-    rounded to bfloat16, products accumulated exactly (here in float64)."""
+    """The inference as the device computes it: weights rounded to bfloat16; a
+    hidden activation tanh(z) carried as s = (1 + tanh z) / 2 (the logistic
+    function of 2 z) and rounded to bfloat16 in that form, so the next layer
+    sees 2 s - 1; products accumulated exactly (here in float64)."""
     p = unpack(theta)
     W1, b1, W2, b2, W3, b3 = (p[k] for k in ("W1", "b1", "W2", "b2", "W3", "b3"))
     x = np.asarray(x, dtype=np.float64).reshape(-1, 1)
-    h1 = bf16_round(np.tanh(x @ W1.T + b1))
-    h2 = bf16_round(np.tanh(h1 @ bf16_round(W2).T + b2))
+    h1 = 2.0 * bf16_round(0.5 * (1.0 + np.tanh(x @ W1.T + b1))) - 1.0
+    h2 = 2.0 * bf16_round(0.5 * (1.0 + np.tanh(h1 @ bf16_round(W2).T + b2))) - 1.0
     return h2 @ bf16_round(W3).T + b3

@@ -9,6 +9,8 @@
 //  * inference (BF16 weights and activations, FP32 accumulation): the 64x64
 //    layer and the output layer run on MFMA (v_mfma_f32_32x32x16_bf16); the
 //    first layer is computed per lane straight into the MFMA operand layout;
+//    a hidden activation is carried as s = (1 + tanh z) / 2, the logistic
+//    function of 2 z, which the next layer absorbs into its bias;
 //    the outputs flagged for a point's E/N cell fall back to interpolation
 //    of the swarm table.
 // Parameter vector (4678 floats): W1[64,1], b1[64], W2[64,64], b2[64],
@@ -231,18 +233,28 @@ __global__ __launch_bounds__(256) void k_mlp_train(MlpArgs A) {
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float floatx16;
 
-__device__ __forceinline__ float tanh_fast(float x) {
-  // 1 - 2 / (1 + e^{2x}); saturates correctly at both ends
-  const float e = __builtin_amdgcn_exp2f(2.8853900817779268f * x);
-  return 1.0f - 2.0f * __builtin_amdgcn_rcpf(1.0f + e);
+// Logistic function of t, with t given as -t log2(e) (the factor lives in the
+// weights and biases that produce it): 1 / (1 + 2^-t log2 e), one exponential
+// and one reciprocal; 0 and 1 at the ends.
+__device__ __forceinline__ float logistic_l2(float neg_t_log2e) {
+  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(neg_t_log2e));
 }
+
+// The hidden layers use tanh(z) = 2 s - 1 with s = logistic(2 z): the next
+// layer takes s as its input, with its weights doubled (exact in bfloat16, so
+// the matrix operands are the weights themselves and the doubling is applied
+// to the product) and its bias reduced by the row sum of its bfloat16 weights.
+// Each activation is then one multiply-add, one exponential, one add and one
+// reciprocal; s, not tanh(z), is what is rounded to bfloat16.
+constexpr float kM2L2E = -2.0f * 1.4426950408889634f;  // -2 log2(e)
 
 // Operand fragments in LDS: for MFMA k-step s and lane l, 8 bf16 values.
 struct InferLds {
   bf16x8 A2[2][4][64];  // W2: M-block m (output features 32m..), k-step s (inputs 16s + 8 (l/32) + q)
   bf16x8 A3[4][64];     // W3 padded to 32 rows; k-step s, q -> feature 32 (s/2) + 8 (2 (s%2) + q/4) + 4 (l/32) + q%4
-  float w1[64], b1[64], b2[64], b3[8];
-  float mu_y[8], sd_y[8];
+  float a1[64], c1[64];  // layer 1: -2 log2(e) (W1, b1)
+  float c2[64];          // layer 2: -2 log2(e) (b2 - row sums of bf16 W2)
+  float y_scale[8], y_off[8];  // output: 2 sd_y, (b3 - row sums of bf16 W3) sd_y + mu_y
 };
 
 __global__ __launch_bounds__(256) void k_mlp_infer(InferArgs A) {
@@ -269,23 +281,34 @@ __global__ __launch_bounds__(256) void k_mlp_infer(InferArgs A) {
     L.A3[s][l] = v;
   }
   if (tid < 64) {
-    L.w1[tid] = P[OFF_W1 + tid];
-    L.b1[tid] = P[OFF_B1 + tid];
-    L.b2[tid] = P[OFF_B2 + tid];
+    L.a1[tid] = kM2L2E * P[OFF_W1 + tid];
+    L.c1[tid] = kM2L2E * P[OFF_B1 + tid];
+    // the row sum of the bfloat16 weights in a fixed order (exact in double)
+    double rs = 0.0;
+    for (int k = 0; k < kH; ++k) rs += (double)(float)(__bf16)P[OFF_W2 + tid * kH + k];
+    L.c2[tid] = kM2L2E * (float)((double)P[OFF_B2 + tid] - rs);
   }
   if (tid < 8) {
-    L.b3[tid] = tid < kOut ? P[OFF_B3 + tid] : 0.0f;
-    L.mu_y[tid] = tid < kOut ? A.mu_y[tid] : 0.0f;
-    L.sd_y[tid] = tid < kOut ? A.sd_y[tid] : 0.0f;
+    double rs = 0.0;
+    if (tid < kOut)
+      for (int j = 0; j < kH; ++j) rs += (double)(float)(__bf16)P[OFF_W3 + tid * kH + j];
+    L.y_scale[tid] = tid < kOut ? 2.0f * A.sd_y[tid] : 0.0f;
+    L.y_off[tid] = tid < kOut ? (float)(((double)P[OFF_B3 + tid] - rs) * A.sd_y[tid] + A.mu_y[tid]) : 0.0f;
   }
   __syncthreads();
   const int lane = tid & 63, half = lane >> 5, col = lane & 31;
   const int64_t wave = (int64_t)blockIdx.x * 4 + (tid >> 6);
   const int64_t nwave = (int64_t)gridDim.x * 4;
-  for (int64_t p0 = wave * 32; p0 < A.n; p0 += nwave * 32) {
+  const int64_t stride = nwave * 32;
+  // the field of the lane's point in the wave's next tile, read one
+  // iteration ahead so that its latency overlaps the current tile's work
+  // (an index clamped into the array, so that the load needs no branch)
+  float en_next = A.EN[min(wave * 32 + col, A.n - 1)];
+  for (int64_t p0 = wave * 32; p0 < A.n; p0 += stride) {
     const int64_t p = p0 + col;
     const bool valid = p < A.n;
-    const float EN = valid ? A.EN[p] : 1.0f;
+    const float EN = valid ? en_next : 1.0f;
+    en_next = A.EN[min(p + stride, A.n - 1)];
     const float lnEN = logf(EN);
     const float xs = (lnEN - A.mu_x) * A.inv_sd_x;
     const int cell = A.n_cells > 0 ? min(max((int)floorf((lnEN - A.cell_lo) * A.inv_cell_w), 0), A.n_cells - 1) : 0;
@@ -297,7 +320,7 @@ __global__ __launch_bounds__(256) void k_mlp_infer(InferArgs A) {
     // falls back to the table (the condition is wave-uniform, as the matrix
     // instructions need).
     if (__ballot(valid && fbm != kAllOut) != 0) {
-      // layer 2: C2[m] = W2[32m.., :] h1 over 4 k-steps of 16
+      // layer 2: C2[m] = W2[32m.., :] s1 over 4 k-steps of 16
       floatx16 c2[2];
       for (int m = 0; m < 2; ++m)
         for (int r = 0; r < 16; ++r) c2[m][r] = 0.0f;
@@ -307,12 +330,13 @@ __global__ __launch_bounds__(256) void k_mlp_infer(InferArgs A) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
           const int k = 16 * s + 8 * half + q;
-          b[q] = (__bf16)tanh_fast(fmaf(L.w1[k], xs, L.b1[k]));
+          b[q] = (__bf16)logistic_l2(fmaf(L.a1[k], xs, L.c1[k]));
         }
         c2[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(L.A2[0][s][lane], b, c2[0], 0, 0, 0);
         c2[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(L.A2[1][s][lane], b, c2[1], 0, 0, 0);
       }
-      // bias + tanh; rows of C2 held by this lane: 8 i + 4 half + j (i = reg / 4, j = reg % 4)
+      // activation of layer 2 (z = 2 C2 + b2 - row sum); rows of C2 held by
+      // this lane: 8 i + 4 half + j (i = reg / 4, j = reg % 4)
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int m = s >> 1;
@@ -321,7 +345,7 @@ __global__ __launch_bounds__(256) void k_mlp_infer(InferArgs A) {
         for (int q = 0; q < 8; ++q) {
           const int i = 2 * (s & 1) + (q >> 2), j = q & 3;
           const int row = 8 * i + 4 * half + j;
-          b[q] = (__bf16)tanh_fast(c2[m][4 * i + j] + L.b2[32 * m + row]);
+          b[q] = (__bf16)logistic_l2(fmaf(c2[m][4 * i + j], 2.0f * kM2L2E, L.c2[32 * m + row]));
         }
         c3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(L.A3[s][lane], b, c3, 0, 0, 0);
       }
@@ -340,7 +364,7 @@ __global__ __launch_bounds__(256) void k_mlp_infer(InferArgs A) {
     for (int j = 0; j < 4; ++j) {
       const int o = 4 * half + j;
       if (o >= kOut) break;
-      float y = (c3[j] + L.b3[o]) * L.sd_y[o] + L.mu_y[o];
+      float y = fmaf(c3[j], L.y_scale[o], L.y_off[o]);
       if ((fbm >> o) & 1u) {
         const float a = A.table[ti * kOut + o], bb = A.table[(ti + 1) * kOut + o];
         y = fmaf(tf, bb - a, a);
