@@ -15,6 +15,10 @@ SOURCES = ["pcmcc_kernels.hip", "pcmcc_deposit.hip", "pcmcc_weights.hip", "pcmcc
            "pcmcc_api_swarm.hip", "pcmcc_api_mlp.hip", "pcmcc_api_field.hip", "pcmcc_api_fluid.hip"]
 ARCH = os.environ.get("PCMCC_OFFLOAD_ARCH", "gfx950")
 CONTRACT_OFF = ("pcmcc_kernels.hip", "pcmcc_swarm.hip")
+# matrix-instruction accumulators in ordinary vector registers: the
+# surrogate's inference then needs no accumulator-register reads and fits
+# five waves per SIMD (86 registers instead of 116)
+MFMA_VGPR = ("pcmcc_mlp.hip",)
 
 
 def hipcc() -> str:
@@ -36,6 +40,8 @@ def build(verbose: bool = False) -> str:
         # a sum of products either way, so an unrelated code change could
         # move results by an ulp
         extra = ["-ffp-contract=off"] if src in CONTRACT_OFF else []
+        if src in MFMA_VGPR:
+            extra += ["-mllvm", "-amdgpu-mfma-vgpr-form"]
         cmd = [hipcc()] + flags + extra + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)

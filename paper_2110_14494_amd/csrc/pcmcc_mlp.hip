@@ -248,6 +248,8 @@ __device__ __forceinline__ float logistic_l2(float neg_t_log2e) {
 // reciprocal; s, not tanh(z), is what is rounded to bfloat16.
 constexpr float kM2L2E = -2.0f * 1.4426950408889634f;  // -2 log2(e)
 
+constexpr int kMaskLds = 4096;
+
 // Operand fragments in LDS: for MFMA k-step s and lane l, 8 bf16 values.
 struct InferLds {
   bf16x8 A2[2][4][64];  // W2: M-block m (output features 32m..), k-step s (inputs 16s + 8 (l/32) + q)
@@ -255,6 +257,7 @@ struct InferLds {
   float a1[64], c1[64];  // layer 1: -2 log2(e) (W1, b1)
   float c2[64];          // layer 2: -2 log2(e) (b2 - row sums of bf16 W2)
   float y_scale[8], y_off[8];  // output: 2 sd_y, (b3 - row sums of bf16 W3) sd_y + mu_y
+  uint8_t mask[kMaskLds];      // the fallback mask per cell, when it has at most kMaskLds cells
 };
 
 __global__ __launch_bounds__(256) void k_mlp_infer(InferArgs A) {
@@ -295,6 +298,9 @@ __global__ __launch_bounds__(256) void k_mlp_infer(InferArgs A) {
     L.y_scale[tid] = tid < kOut ? 2.0f * A.sd_y[tid] : 0.0f;
     L.y_off[tid] = tid < kOut ? (float)(((double)P[OFF_B3 + tid] - rs) * A.sd_y[tid] + A.mu_y[tid]) : 0.0f;
   }
+  const bool mask_lds = A.n_cells <= kMaskLds;
+  if (mask_lds)
+    for (int i = tid; i < A.n_cells; i += 256) L.mask[i] = A.fb_mask[i];
   __syncthreads();
   const int lane = tid & 63, half = lane >> 5, col = lane & 31;
   const int64_t wave = (int64_t)blockIdx.x * 4 + (tid >> 6);
@@ -313,7 +319,8 @@ __global__ __launch_bounds__(256) void k_mlp_infer(InferArgs A) {
     const float xs = (lnEN - A.mu_x) * A.inv_sd_x;
     const int cell = A.n_cells > 0 ? min(max((int)floorf((lnEN - A.cell_lo) * A.inv_cell_w), 0), A.n_cells - 1) : 0;
     // bit o set: output o of this cell takes the table
-    const unsigned fbm = A.n_cells > 0 ? (unsigned)A.fb_mask[cell] & kAllOut : 0u;
+    const unsigned fbm =
+        A.n_cells > 0 ? (unsigned)(mask_lds ? L.mask[cell] : A.fb_mask[cell]) & kAllOut : 0u;
     floatx16 c3;
     for (int r = 0; r < 16; ++r) c3[r] = 0.0f;
     // The perceptron runs unless every output of every point of the wave
