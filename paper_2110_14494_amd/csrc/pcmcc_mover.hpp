@@ -284,18 +284,19 @@ __device__ __forceinline__ float majorant_t(const Tab& T, const SpeciesView&, fl
 }
 
 // Square root of x >= 0 (0 for x <= 0) from the hardware reciprocal square
-// root refined by two Newton steps (relative error near double rounding).
+// root refined by one Newton step: the hardware value is within 5.2e-8
+// relative and the step squares that, to within 4.3e-15 (measured over 2^22
+// values log-uniform in [2^-60, 2^60]); the mover takes new speeds, cos(chi)
+// and polar sines from it, and its results leave a step in single precision.
 __device__ __forceinline__ double sqrt_nr(double x) {
   double r = __builtin_amdgcn_rsq(x);
-  r = r * fma(-0.5 * x * r, r, 1.5);
   r = r * fma(-0.5 * x * r, r, 1.5);
   return x > 0.0 ? x * r : 0.0;
 }
 
 // 1/sqrt(x) for x > 0, as above.
 __device__ __forceinline__ double rsqrt_nr(double x) {
-  double r = __builtin_amdgcn_rsq(x);
-  r = r * fma(-0.5 * x * r, r, 1.5);
+  const double r = __builtin_amdgcn_rsq(x);
   return r * fma(-0.5 * x * r, r, 1.5);
 }
 
