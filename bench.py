@@ -53,8 +53,8 @@ VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 # behind each figure is in the design notes.
 SLOTS_SEGMENT = 275.0    # every flight segment: Philox, speed bounds, majorants, tau, drift, gather, velocity
 SLOTS_CANDIDATE = 37.0   # a segment ending in a candidate collision: energy, table position, process choice
-SLOTS_REAL = 73.0        # a real collision: isotropic direction, recoil or threshold loss, new speed
-SLOTS_BIRTH = 160.0      # a newborn: its Philox draw, direction and speed
+SLOTS_REAL = 63.0        # a real collision: isotropic direction, recoil or threshold loss, new speed
+SLOTS_BIRTH = 150.0      # a newborn: its Philox draw, direction and speed
 SLOTS_PSTEP = 35.0       # a particle-step: start (conversions, field bound) and finish (domain test, stores)
 BYTES_PER_PSTEP = 72.0  # 36 B read + 36 B written
 BYTES_PER_BIRTH = 36.0  # the newborn written
