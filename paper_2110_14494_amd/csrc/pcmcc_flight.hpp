@@ -345,8 +345,13 @@ __device__ __forceinline__ int flight_complete(Flight& f, const double3 an, cons
   f.ax = an.x;
   f.ay = an.y;
   f.az = an.z;
-  if (f.seg == SEG_END) return EV_DONE;
-  if (f.seg == SEG_HORIZON) return EV_GO;
+  // The outcome is formed with selects over the whole wave: the candidate
+  // lookup, the direction and the new energy are evaluated on every lane (a
+  // wave almost always holds lanes of each kind, so masking would save no
+  // issue slots) and applied where they hold; only the staged newborn is a
+  // branch.  A lane takes exactly the values the branchy form would give it.
+  const bool cand = f.seg == SEG_COLLIDE;
+  int ev = f.seg == SEG_END ? EV_DONE : EV_GO;
 
   // Candidate collision: real process k, or null.
   const TabConst tc = tab_const();
@@ -365,38 +370,34 @@ __device__ __forceinline__ int flight_complete(Flight& f, const double3 an, cons
   float tot = cum[0];
 #pragma unroll
   for (int kk = 1; kk < ROW; ++kk) tot = fmaxf(tot, cum[kk]);
-  cnt.v[C_MAJ] += tot > f.nu_hat;
+  cnt.v[C_MAJ] += cand && tot > f.nu_hat;
   const int k = pick_process_row<ROW>(cum, yv);
-  if (k < 0 || eps < (double)T.thr[k]) {
-    cnt.v[C_NULL]++;
-    return EV_GO;
-  }
-  if (eps > tc.eps_max) cnt.v[C_OOT]++;
-  const int kind = T.kind[k];
-  cnt.v[C_EL] += kind == ELASTIC;
-  cnt.v[C_EXC] += kind == EXCITATION;
-  cnt.v[C_ION] += kind == IONIZATION;
-  cnt.v[C_ATT] += kind == ATTACHMENT;
-  if (kind == ATTACHMENT) return EV_ATTACHED;
+  const int ks = k < 0 ? 0 : k;
+  const double thr = (double)T.thr[ks];
+  const bool real = cand && k >= 0 && !(eps < thr);
+  cnt.v[C_NULL] += cand && !real;
+  cnt.v[C_OOT] += real && eps > tc.eps_max;
+  const int kind = T.kind[ks];
+  cnt.v[C_EL] += real && kind == ELASTIC;
+  cnt.v[C_EXC] += real && kind == EXCITATION;
+  cnt.v[C_ION] += real && kind == IONIZATION;
+  cnt.v[C_ATT] += real && kind == ATTACHMENT;
+  if (real && kind == ATTACHMENT) ev = EV_ATTACHED;
+  const bool scatter = real && kind != ATTACHMENT;
 
   double nx, ny, nz;
   iso_dir(f.r2, f.r3, nx, ny, nz);
-  const double thr = (double)T.thr[k];
-  double eps_new;
-  if (kind == ELASTIC) {
-    const double cchi = v2 > 0.0 ? fma(f.vz, nz, fma(f.vy, ny, f.vx * nx)) * rsqrt_nr(v2) : 0.0;
-    eps_new = eps * fma(-(double)tc.recoil, 1.0 - cchi, 1.0);
-  } else if (kind == EXCITATION) {
-    eps_new = eps - thr;
-  } else {
-    eps_new = 0.5 * (eps - thr);
-    staged = births.push((float)f.x, (float)f.y, (float)f.z, f.w, (float)f.t, f.tag, f.id, f.j - 1, eps_new);
-  }
+  const double cchi = v2 > 0.0 ? fma(f.vz, nz, fma(f.vy, ny, f.vx * nx)) * rsqrt_nr(v2) : 0.0;
+  const double eps_el = eps * fma(-(double)tc.recoil, 1.0 - cchi, 1.0);
+  const double eps_ion = 0.5 * (eps - thr);
+  const double eps_new = kind == ELASTIC ? eps_el : (kind == EXCITATION ? eps - thr : eps_ion);
+  if (scatter && kind == IONIZATION)
+    staged = births.push((float)f.x, (float)f.y, (float)f.z, f.w, (float)f.t, f.tag, f.id, f.j - 1, eps_ion);
   const double sn = sqrt_nr(eps_new * tc.inv_k_d);
-  f.vx = sn * nx;
-  f.vy = sn * ny;
-  f.vz = sn * nz;
-  return EV_GO;
+  f.vx = scatter ? sn * nx : f.vx;
+  f.vy = scatter ? sn * ny : f.vy;
+  f.vz = scatter ? sn * nz : f.vz;
+  return ev;
 }
 
 // Runs every electron of a source (n of them) through the rest of the step
