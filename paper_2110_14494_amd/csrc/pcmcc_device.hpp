@@ -49,6 +49,58 @@ __device__ __forceinline__ uint4 draw(Key key, uint64_t id, uint32_t step, uint3
   return philox(make_uint4((uint32_t)id, (uint32_t)(id >> 32), step, (j << 2) | tag), key);
 }
 
+// An electron's draws within a step share the counter's first three words
+// (id, step), so three of the twenty products of each draw are the same for
+// all of them: the first round's product of the id's low word, the second
+// round's product of its first word and the third round's product of its
+// third word (the first round's product of the step is wave-uniform).  They
+// are formed once when the electron starts its step; draw_pre then gives
+// exactly philox(id, step, w) from them.
+struct PhiloxPre {
+  uint32_t a;  // high word of the first round's product of the id's low word
+  uint32_t b;  // low word of the second round's first product
+  uint32_t c, d;  // high and low words of the third round's second product
+};
+
+__device__ __forceinline__ PhiloxPre philox_pre(Key key, uint64_t id, uint32_t step) {
+  const uint64_t p0 = (uint64_t)0xD2511F53u * (uint32_t)id;
+  const uint64_t p1 = (uint64_t)0xCD9E8D57u * step;
+  const uint32_t x = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), (uint32_t)(id >> 32), key.k0, 0x96);
+  const uint64_t q0 = (uint64_t)0xD2511F53u * x;  // round 2, first product
+  const uint32_t z = __builtin_amdgcn_bitop3_b32((uint32_t)(q0 >> 32), (uint32_t)p0, key.k1 + 0xBB67AE85u, 0x96);
+  const uint64_t r1 = (uint64_t)0xCD9E8D57u * z;  // round 3, second product
+  return PhiloxPre{(uint32_t)(p0 >> 32), (uint32_t)q0, (uint32_t)(r1 >> 32), (uint32_t)r1};
+}
+
+// philox((id, id >> 32, step, w), key) for the electron whose PhiloxPre is pre.
+__device__ __forceinline__ uint4 draw_pre(Key key, const PhiloxPre& pre, uint32_t step, uint32_t w) {
+  uint32_t k0 = key.k0, k1 = key.k1;
+  const uint32_t y1 = (uint32_t)((uint64_t)0xCD9E8D57u * step);  // round 1's second word (uniform)
+  const uint32_t z1 = __builtin_amdgcn_bitop3_b32(pre.a, w, k1, 0x96);
+  k0 += 0x9E3779B9u;
+  k1 += 0xBB67AE85u;
+  const uint64_t p1 = (uint64_t)0xCD9E8D57u * z1;  // round 2, second product
+  const uint32_t x2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), y1, k0, 0x96);
+  const uint32_t y2 = (uint32_t)p1;
+  k0 += 0x9E3779B9u;
+  k1 += 0xBB67AE85u;
+  const uint64_t p0 = (uint64_t)0xD2511F53u * x2;  // round 3, first product
+  uint4 c = make_uint4(__builtin_amdgcn_bitop3_b32(pre.c, y2, k0, 0x96), pre.d,
+                       __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), pre.b, k1, 0x96), (uint32_t)p0);
+  k0 += 0x9E3779B9u;
+  k1 += 0xBB67AE85u;
+#pragma unroll
+  for (int r = 3; r < 10; ++r) {
+    const uint64_t q0 = (uint64_t)0xD2511F53u * c.x;
+    const uint64_t q1 = (uint64_t)0xCD9E8D57u * c.z;
+    c = make_uint4(__builtin_amdgcn_bitop3_b32((uint32_t)(q1 >> 32), c.y, k0, 0x96), (uint32_t)q1,
+                   __builtin_amdgcn_bitop3_b32((uint32_t)(q0 >> 32), c.w, k1, 0x96), (uint32_t)q0);
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
 // Uniform in (0,1) from the top 23 bits: ((r >> 9) + 1/2) 2^-23, exact in FP32.
 __device__ __forceinline__ float unif(uint32_t r) { return ((float)(r >> 9) + 0.5f) * 0x1p-23f; }
 

@@ -244,6 +244,7 @@ struct Flight {
   uint32_t src;         // slot the electron came from
   uint32_t r1, r2, r3;  // uniforms of the pending collision
   uint32_t tag;         // group of the electron (swarm index; 0 in the PIC step)
+  PhiloxPre pre;        // the products its draws of this step share
   int mode;
   int seg;  // kind of the pending segment; for a parked electron, its event
 };
@@ -290,7 +291,7 @@ __device__ __forceinline__ int flight_plan(Flight& f, double dt, const Tab& T, c
     cnt.v[C_ERR]++;
     return EV_LIMIT;
   }
-  const uint4 r = draw(key, f.id, step, f.j, TAG_MAIN);
+  const uint4 r = draw_pre(key, f.pre, step, (f.j << 2) | TAG_MAIN);
   f.j++;
   cnt.v[C_TRIALS]++;
   const double t_rem = dt - f.t;
@@ -477,6 +478,7 @@ __device__ __forceinline__ void fly_all(uint64_t n, unsigned long long* take, KA
           if (f.mode == FM_IDLE && rank >= served && rank < served + got) {
             source.load(pool_next + (rank - served), f);
             finish.tag(f, chunk_tag);
+            if (f.mode == FM_NEW) f.pre = philox_pre(F.key(f.tag), f.id, step);
           }
           pool_next += got;
           served += got;
