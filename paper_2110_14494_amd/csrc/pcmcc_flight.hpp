@@ -29,6 +29,7 @@
 // runs in batches instead of with one or two lanes active.
 #pragma once
 
+#include "pcmcc_internal.hpp"
 #include "pcmcc_mover.hpp"
 
 namespace pcmcc {
@@ -405,7 +406,7 @@ __device__ __forceinline__ int flight_complete(Flight& f, const double3 an, cons
 // (tables of ROW floats per node, table_row(nproc)),
 // REFILL lanes at a time (see above), `chunk` (a power of two in [kChunkMin,
 // kChunkMax], read from the kernel arguments) electrons per work-counter
-// grab.
+// grab, or with GUIDED a shrinking share of the rest down to kChunkMin.
 // Field: key(tag) gives the random-number key of a group, accel(x, y, z,
 // tag, where) the acceleration (and where the field was read), bound_at(where,
 // tag, speed, t_rem, a_abs, da) the field bounds for the rest of the step.
@@ -420,7 +421,7 @@ __device__ __forceinline__ int flight_complete(Flight& f, const double3 an, cons
 // arguments; `take` is the grid-wide work counter (zero before the first
 // wave starts).  cum_ion (nullable) counts ionizations per group.  Every
 // staged entry is written out before the function returns.
-template <int REFILL, int ROW, class Field, class Source, class Finish>
+template <int REFILL, int ROW, bool GUIDED, class Field, class Source, class Finish>
 __device__ __forceinline__ void fly_all(uint64_t n, unsigned long long* take, KArg<uint32_t> chunk, double dt,
                                         const Field& F, const Tab& T, const SpeciesView& S, uint32_t step, Cnt& cnt,
                                         const BirthSink& sink, unsigned long long* cum_ion, WaveStage* L,
@@ -430,6 +431,7 @@ __device__ __forceinline__ void fly_all(uint64_t n, unsigned long long* take, KA
   StagedBirths<Field> births{L, sink, F, step, S, cum_ion, 0u};
   uint32_t n_done = 0;  // entries of the finish list
   uint64_t pool_next = 0, pool_end = 0;
+  uint64_t seen = 0;  // the work counter after this wave's previous grab
   uint32_t chunk_tag = 0;  // finisher's tag of the current chunk
   bool dry = n == 0;
   const uint32_t lane = lane_id();
@@ -459,12 +461,24 @@ __device__ __forceinline__ void fly_all(uint64_t n, unsigned long long* take, KA
         while (served < n_idle) {
           if (pool_next == pool_end) {
             if (!finish.can_open()) break;  // the lanes stay idle until a chunk of this wave completes
-            const uint32_t ch = chunk.get();
+            // GUIDED: a share of what was left at this wave's previous grab,
+            // (n - seen) / (2 waves), between kChunkMin and the schedule's
+            // chunk, so that a phase ends on small chunks instead of leaving
+            // one wave a whole large chunk behind the others (the PIC step:
+            // 1 % on its large phases; the swarms' short steps lose more to
+            // the extra grabs than they gain).
+            uint32_t ch = chunk.get();
+            if (GUIDED && seen > 0) {
+              const uint64_t waves = (uint64_t)gridDim.x * blockDim.x / 64u;
+              const uint64_t share = seen < n ? (n - seen) / (2u * waves) : 0u;
+              ch = share < (uint64_t)kChunkMin ? (uint32_t)kChunkMin : (share < ch ? (uint32_t)share : ch);
+            }
             unsigned long long base = 0;
             if (lane == 0) base = atomicAdd(take, (unsigned long long)ch);
             const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
             const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
             const uint64_t b = ((uint64_t)hi << 32) | lo;
+            seen = b + ch;
             if (b >= n) {
               dry = true;
               break;

@@ -298,7 +298,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
       const SoaSource src{cur_k};
       const KeepInPlace fin{grid_k, nxt_k, A.holes, &ctl->holes, ev_k, ring};
       ring->reset();
-      fly_all<REFILL, ROW>(n_cur, &ctl->take[0], chunk_k, A.dt, F, T, A.S, step, cnt, sink, nullptr, L, src, fin);
+      fly_all<REFILL, ROW, true>(n_cur, &ctl->take[0], chunk_k, A.dt, F, T, A.S, step, cnt, sink, nullptr, L, src, fin);
     }
     grid.sync();
 
@@ -316,7 +316,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
       const BirthSink sink{{&ka->pend[(g + 1) & 1]}, &ctl->pend[g + 1], A.pend_cap, &ctl->overflow, 0u, ev_k};
       const PendSource src{{&ka->pend[g & 1]}};
       const PlaceNewborn fin{grid_k, nxt_k, A.holes, h, n_cur, A.cap, &ctl->child, &ctl->overflow, ev_k};
-      fly_all<REFILL, ROW>(np, &ctl->take[g + 1], chunk_k, A.dt, F, T, A.S, step, cnt, sink, nullptr, L, src, fin);
+      fly_all<REFILL, ROW, true>(np, &ctl->take[g + 1], chunk_k, A.dt, F, T, A.S, step, cnt, sink, nullptr, L, src, fin);
       grid.sync();
     }
 

@@ -289,7 +289,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_
     {
       const BirthSink sink{{&ka->pend[0]}, &ctl->pend[0], A.pend_cap, &ctl->overflow, 0u, no_events};
       const SwarmLoad src{cur_k, A.base, prefix, pck, S, A.key, step, sink, &psteps};
-      fly_all<REFILL, ROW>((uint64_t)prefix[S], &ctl->take[0], chunk_k, (double)A.dt, F, T, A.S, step, cnt, sink,
+      fly_all<REFILL, ROW, false>((uint64_t)prefix[S], &ctl->take[0], chunk_k, (double)A.dt, F, T, A.S, step, cnt, sink,
                       A.cum_ion, L, src, fin);
     }
     grid.sync();
@@ -305,7 +305,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_
       const uint64_t np = np_raw < A.pend_cap ? np_raw : A.pend_cap;
       const BirthSink sink{{&ka->pend[(g + 1) & 1]}, &ctl->pend[g + 1], A.pend_cap, &ctl->overflow, 0u, no_events};
       const SwarmPend src{{&ka->pend[g & 1]}};
-      fly_all<REFILL, ROW>(np, &ctl->take[g + 1], chunk_k, (double)A.dt, F, T, A.S, step, cnt, sink, A.cum_ion, L, src,
+      fly_all<REFILL, ROW, false>(np, &ctl->take[g + 1], chunk_k, (double)A.dt, F, T, A.S, step, cnt, sink, A.cum_ion, L, src,
                       fin);
       grid.sync();
     }
