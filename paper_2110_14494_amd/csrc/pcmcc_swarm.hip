@@ -246,12 +246,15 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_
   const Tab T = stage_tables(A.T, A.S, smem);
   const int S = A.n_swarms;
   // LDS after the tables: per-wave staging lists, per-swarm acceleration [S]
-  // (double), prefix [S+1], scan scratch [BS], |acceleration| [S] and
-  // population-control exponent [S].
+  // (double), region base and capacity [S] (the refills and the finishers
+  // read them from here, not from global memory), prefix [S+1], scan scratch
+  // [BS], |acceleration| [S] and population-control exponent [S].
   WaveStage* L = reinterpret_cast<WaveStage*>(smem + pic_stage_offset_floats(A.T)) + (threadIdx.x >> 6);
   double* az_d = reinterpret_cast<double*>(reinterpret_cast<WaveStage*>(smem + pic_stage_offset_floats(A.T)) +
                                            BS / 64);
-  uint32_t* prefix = (uint32_t*)(az_d + S);
+  uint64_t* base_l = reinterpret_cast<uint64_t*>(az_d + S);
+  uint64_t* cap_l = base_l + S;
+  uint32_t* prefix = (uint32_t*)(cap_l + S);
   uint32_t* tmp = prefix + (S + 1);
   float* az_l = (float*)(tmp + BS);
   int* pck = (int*)(az_l + S);
@@ -261,6 +264,8 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_
   for (int s = threadIdx.x; s < S; s += BS) {
     az_d[s] = A.az[s];
     az_l[s] = fabsf((float)A.az[s]);
+    base_l[s] = A.base[s];
+    cap_l[s] = A.cap_s[s];
   }
   __syncthreads();
   const SwarmField F{az_d, az_l, A.key};
@@ -283,12 +288,12 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_
 #pragma unroll
     for (int k = 0; k < NCNT; ++k) cnt.v[k] = 0;
     uint32_t psteps = 0;
-    const SwarmPlace fin{nxt_k, A.base, A.cap_s, A.n_nxt, A.cum_att, &ctl->overflow};
+    const SwarmPlace fin{nxt_k, base_l, cap_l, A.n_nxt, A.cum_att, &ctl->overflow};
 
     // Phase 1: each swarm's electrons, after population control, from t = 0.
     {
       const BirthSink sink{{&ka->pend[0]}, &ctl->pend[0], A.pend_cap, &ctl->overflow, 0u, no_events};
-      const SwarmLoad src{cur_k, A.base, prefix, pck, S, A.key, step, sink, &psteps};
+      const SwarmLoad src{cur_k, base_l, prefix, pck, S, A.key, step, sink, &psteps};
       fly_all<REFILL, ROW, false>((uint64_t)prefix[S], &ctl->take[0], chunk_k, (double)A.dt, F, T, A.S, step, cnt, sink,
                       A.cum_ion, L, src, fin);
     }
@@ -342,7 +347,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_
 #pragma unroll
         for (int m = 0; m < kNMom; ++m) c[m] = 0;
         if (i < n_s) {
-          const uint64_t q = A.base[s] + i;
+          const uint64_t q = base_l[s] + i;
           const double x = nxt.x[q], y = nxt.y[q], z = nxt.z[q];
           const double vx = nxt.vx[q], vy = nxt.vy[q], vz = nxt.vz[q];
           const double v2 = vx * vx + vy * vy + vz * vz;
@@ -592,7 +597,7 @@ __global__ void k_swarm_estimate(const unsigned long long* mom, const long long*
 // ---------------------------------------------------------------------------
 size_t swarm_lds_bytes(const TableView& T, int S, int block) {
   return pic_stage_offset_floats(T) * sizeof(float) + (size_t)(block / 64) * sizeof(WaveStage) + (size_t)S * 8 +
-         (size_t)(S + 1) * 4 + (size_t)block * 4 + (size_t)S * 4 + (size_t)S * 4;
+         (size_t)S * 16 + (size_t)(S + 1) * 4 + (size_t)block * 4 + (size_t)S * 4 + (size_t)S * 4;
 }
 
 template <int BS, int ROW>
