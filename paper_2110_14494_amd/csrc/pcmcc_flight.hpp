@@ -73,23 +73,32 @@ struct WaveStage {
 
 // Whole wave: for the lanes with `active` set, reserves one slot each in the
 // counter ctr[tag] of the lane's group, with one atomic per distinct group
-// present; returns the lane's slot (undefined for inactive lanes).
+// present; returns the lane's slot (undefined for inactive lanes).  The
+// groups are found first (ballots only); then every group's leader (its
+// lowest lane) issues its atomic in the same instruction, so the wave waits
+// for one round trip however many groups it holds, and each lane takes its
+// leader's base by a lane shuffle.
 __device__ __forceinline__ uint64_t group_reserve(unsigned long long* ctr, uint32_t tag, bool active) {
   uint64_t pending = __ballot(active);
-  uint64_t slot = 0;
   const uint32_t lane = lane_id();
+  int leader_of = 0;
+  uint32_t rank = 0, count = 0;
   while (pending) {
     const int leader = __ffsll((unsigned long long)pending) - 1;
     const uint32_t t = __builtin_amdgcn_readlane(tag, leader);
     const uint64_t m = __ballot(active && tag == t) & pending;
-    unsigned long long base = 0;
-    if ((int)lane == leader) base = atomicAdd(&ctr[t], (unsigned long long)__popcll(m));
-    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)base, leader);
-    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(base >> 32), leader);
-    if ((m >> lane) & 1) slot = (((uint64_t)hi << 32) | lo) + rank_in(m);
+    if ((m >> lane) & 1) {
+      leader_of = leader;
+      rank = rank_in(m);
+    }
+    if ((int)lane == leader) count = (uint32_t)__popcll(m);
     pending &= ~m;
   }
-  return slot;
+  unsigned long long base = 0;
+  if (active && rank == 0) base = atomicAdd(&ctr[tag], (unsigned long long)count);
+  const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)base, leader_of);
+  const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(base >> 32), leader_of);
+  return (((uint64_t)hi << 32) | lo) + rank;
 }
 
 // Whole wave: adds, per distinct group among the lanes with `active` set, the
