@@ -419,7 +419,9 @@ __device__ __forceinline__ int flight_complete(Flight& f, const double3 an, cons
 // Field: key(tag) gives the random-number key of a group, accel(x, y, z,
 // tag, where) the acceleration (and where the field was read), bound_at(where,
 // tag, speed, t_rem, a_abs, da) the field bounds for the rest of the step.
-// Source: load(i, Flight&) starts electron i (or leaves the lane idle).
+// Source: load(i, Flight&, hint) starts electron i (or leaves the lane
+// idle); hint(first) is computed once per chunk taken (wave-uniform) and
+// passed to the loads of its electrons.
 // Finish: done_all(Flight&, parked, Cnt&, WaveStage*, staged count) takes the
 // electrons that left the step (called by the whole wave; `parked` marks the
 // lanes holding one, f.seg is its event) and returns the new staged count
@@ -442,6 +444,7 @@ __device__ __forceinline__ void fly_all(uint64_t n, unsigned long long* take, KA
   uint64_t pool_next = 0, pool_end = 0;
   uint64_t seen = 0;  // the work counter after this wave's previous grab
   uint32_t chunk_tag = 0;  // finisher's tag of the current chunk
+  uint32_t src_hint = 0;   // source's hint for the current chunk
   bool dry = n == 0;
   const uint32_t lane = lane_id();
   for (;;) {
@@ -495,11 +498,12 @@ __device__ __forceinline__ void fly_all(uint64_t n, unsigned long long* take, KA
             pool_next = b;
             pool_end = b + ch < n ? b + ch : n;
             chunk_tag = finish.open_chunk(b, (uint32_t)(pool_end - b));
+            src_hint = source.hint(b);
           }
           const uint32_t avail = (uint32_t)(pool_end - pool_next);
           const uint32_t got = avail < n_idle - served ? avail : n_idle - served;
           if (f.mode == FM_IDLE && rank >= served && rank < served + got) {
-            source.load(pool_next + (rank - served), f);
+            source.load(pool_next + (rank - served), f, src_hint);
             finish.tag(f, chunk_tag);
             if (f.mode == FM_NEW) f.pre = philox_pre(F.key(f.tag), f.id, step);
           }

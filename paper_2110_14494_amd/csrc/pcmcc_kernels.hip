@@ -36,7 +36,8 @@ namespace pcmcc {
 // Phase 1 source: the current buffer, every electron from t = 0.
 struct SoaSource {
   KArg<Soa> sk;
-  __device__ __forceinline__ void load(uint64_t i, Flight& f) const {
+  __device__ __forceinline__ uint32_t hint(uint64_t) const { return 0u; }
+  __device__ __forceinline__ void load(uint64_t i, Flight& f, uint32_t) const {
     PState p;
     load_p(sk.get(), i, p);
     flight_start(f, p, 0.0, (uint32_t)i);
@@ -46,7 +47,8 @@ struct SoaSource {
 // Phase 2 source: a newborn queue, each electron from its birth time.
 struct PendSource {
   KArg<PendSoa> sk;
-  __device__ __forceinline__ void load(uint64_t i, Flight& f) const {
+  __device__ __forceinline__ uint32_t hint(uint64_t) const { return 0u; }
+  __device__ __forceinline__ void load(uint64_t i, Flight& f, uint32_t) const {
     PState p;
     float tb;
     load_pend(sk.get(), i, p, tb);

@@ -61,8 +61,15 @@ struct SwarmLoad {
   uint32_t step;
   BirthSink dup;  // duplicates: the generation-0 newborn queue
   uint32_t* psteps;
-  __device__ __forceinline__ void load(uint64_t g, Flight& f) const {
-    const int s = swarm_of(prefix, n_swarms, (uint32_t)g);
+  // The swarm of a chunk's first electron, found once when the wave takes the
+  // chunk; an electron of the chunk walks forward from it (a chunk is at most
+  // kChunkMax electrons, so it seldom crosses a swarm boundary).
+  __device__ __forceinline__ uint32_t hint(uint64_t first) const {
+    return (uint32_t)swarm_of(prefix, n_swarms, (uint32_t)first);
+  }
+  __device__ __forceinline__ void load(uint64_t g, Flight& f, uint32_t s0) const {
+    int s = (int)s0;
+    while (prefix[s + 1] <= (uint32_t)g) ++s;
     const uint64_t i = g - prefix[s];
     PState p;
     load_p(cur.get(), base[s] + i, p);
@@ -90,7 +97,8 @@ struct SwarmLoad {
 // Phase 2 source: the newborn queue (with swarm indices and birth times).
 struct SwarmPend {
   KArg<PendSoa> qk;
-  __device__ __forceinline__ void load(uint64_t i, Flight& f) const {
+  __device__ __forceinline__ uint32_t hint(uint64_t) const { return 0u; }
+  __device__ __forceinline__ void load(uint64_t i, Flight& f, uint32_t) const {
     PState p;
     float tb;
     const PendSoa q = qk.get();
