@@ -363,6 +363,9 @@ __device__ __forceinline__ int flight_complete(Flight& f, const double3 an, cons
   // branch.  A lane takes exactly the values the branchy form would give it.
   const bool cand = f.seg == SEG_COLLIDE;
   int ev = f.seg == SEG_END ? EV_DONE : EV_GO;
+  // a wave without a candidate (sparse waves: small populations, the ends
+  // of phases) skips the collision work
+  if (__ballot(cand) == 0) return ev;
 
   // Candidate collision: real process k, or null.
   const TabConst tc = tab_const();
