@@ -75,3 +75,41 @@ def test_adam_training_fits_smooth_targets():
     assert losses[-1] < 1e-2 * losses[0]
     # the cosine schedule ends at lr_min
     assert abs(M.cosine_lr(1500, 1500, 3e-3, 1e-5) - 1e-5) < 1e-18
+
+
+def test_bf16_emulation_without_rounding_is_the_network(monkeypatch):
+    # The emulation carries each hidden activation as s = (1 + tanh z) / 2 and
+    # feeds 2 s - 1 on; with the rounding switched off that is the network
+    # itself (the same output to rounding).
+    rng = np.random.default_rng(11)
+    th = W.mlp_init(7) + rng.normal(0, 0.3, M.N_PARAMS)
+    x = rng.uniform(-3, 3, 400)
+    monkeypatch.setattr(M, "bf16_round", lambda a: np.asarray(a, dtype=np.float64))
+    y_em = M.forward_bf16(th, x)
+    y_ref, _ = M.forward(th, x)
+    np.testing.assert_allclose(y_em, y_ref, rtol=0, atol=1e-12)
+
+
+def test_bf16_emulation_within_its_rounding_bound():
+    # Rounding to bfloat16 moves a value by at most 2^-8 of itself; the bound
+    # follows that through the two hidden layers (tanh and the logistic
+    # function change by no more than their argument) and the output layer.
+    rng = np.random.default_rng(12)
+    th = W.mlp_init(8) + rng.normal(0, 0.3, M.N_PARAMS)
+    x = rng.uniform(-3, 3, 2000)
+    y_em = M.forward_bf16(th, x)
+    y_ref, _ = M.forward(th, x)
+    p = M.unpack(th)
+    u = 2.0 ** -8
+    h1 = np.tanh(x.reshape(-1, 1) @ p["W1"].T + p["b1"])
+    h2 = np.tanh(h1 @ p["W2"].T + p["b2"])
+    d_h1 = 2 * u  # h = 2 s - 1 with s in (0, 1)
+    aW2 = np.abs(p["W2"])
+    d_z2 = (aW2.sum(axis=1) * (1 + u) * d_h1)[None, :] + u * (np.abs(h1) @ aW2.T)
+    d_h2 = d_z2 + 2 * u
+    aW3 = np.abs(p["W3"])
+    bound = (1 + u) * (d_h2 @ aW3.T) + u * (np.abs(h2) @ aW3.T)
+    err = np.abs(y_em - y_ref)
+    assert np.all(err <= bound + 1e-12)
+    # and the rounding does show (the emulation is not the exact network)
+    assert err.max() > 1e-4
