@@ -190,7 +190,7 @@ typedef struct pcmcc_schedule {
                          small call) */
   int refill_min;     /* free lanes of a wave that trigger a finish-and-refill batch: 16, 24 or 32; 0 = 24 */
   int chunk;          /* electrons a wave takes from the work counter at a time: a power of two in [64, 4096];
-                         0 = 256 (64 for a call that starts with fewer than 2^17 particles) */
+                         0 = 512 (64 for a call that starts with fewer than 2^17 particles) */
 } pcmcc_schedule;
 
 /* Sets the schedule of later steps on ctx (s NULL: all defaults).
@@ -269,7 +269,7 @@ typedef struct pcmcc_swarm_opts {
   int autotune;            /* 1: time the candidate shapes on this input and keep the fastest */
   const char* tune_cache;  /* JSON file the tuned shapes are read from and written to, or NULL */
   int refill_min;          /* as pcmcc_schedule; 0 = tuned or 24 */
-  int chunk;               /* as pcmcc_schedule; 0 = tuned or 256 */
+  int chunk;               /* as pcmcc_schedule; 0 = tuned or 512 */
 } pcmcc_swarm_opts;
 
 typedef struct pcmcc_swarm_result {

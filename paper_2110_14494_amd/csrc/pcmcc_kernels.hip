@@ -9,8 +9,9 @@
 // trilinear weighting (Sec. 2.1.3).
 //
 // Layout: particles are structure-of-arrays single precision (x, y, z, vx,
-// vy, vz, w) plus a 64-bit id.  Waves take electrons in chunks of 256
-// consecutive slots from a grid-wide counter and keep every lane busy with
+// vy, vz, w) plus a 64-bit id.  Waves take electrons in chunks (512
+// consecutive slots by default, shrinking towards the end of a phase) from a
+// grid-wide counter and keep every lane busy with
 // the segment-pipelined mover (pcmcc_flight.hpp).  The survivors of a chunk
 // stay within that chunk's slot range of the next buffer (ping-pong, so a
 // step that would overflow the capacity leaves the previous state intact),

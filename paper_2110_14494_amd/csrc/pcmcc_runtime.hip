@@ -175,7 +175,7 @@ int resolve_launch(pcmcc_ctx* c, const pcmcc_schedule& s, size_t (*lds)(const Ta
   if (rc) return rc;
   const bool small = n_hint > 0 && n_hint < kSmallPopulation && !s.block;
   const int refill = s.refill_min ? s.refill_min : 24;
-  const int chunk = s.chunk ? s.chunk : (small ? 64 : 256);
+  const int chunk = s.chunk ? s.chunk : (small ? 64 : 512);
   int block = 0, per_cu = 0;
   for (int b : {512, 256, 128, 64}) {
     if ((s.block && b != s.block) || (small && b != 64)) continue;

@@ -75,7 +75,7 @@ def test_default_schedule_and_invalid_values(pic):
     d = ctx.get_schedule()
     # the most resident waves per compute unit, then the defaults
     assert d["block"] in (64, 128, 256, 512) and d["blocks_per_cu"] >= 1
-    assert d["refill_min"] == 24 and d["chunk"] == 256
+    assert d["refill_min"] == 24 and d["chunk"] == 512
     for bad in ({"block": 96}, {"refill_min": 20}, {"chunk": 100}, {"chunk": 8192}, {"blocks_per_cu": -1}):
         with pytest.raises(B.PcmccError) as e:
             ctx.set_schedule(**bad)
