@@ -177,7 +177,10 @@ __device__ __forceinline__ float speed_bound(float3 v, float3 a0, float speed, f
 // clamping the coordinate to [-1, n], and the upper one i + 1, both clamped
 // to the grid.  The packed field holds, for every lower index (n + 2 per
 // axis), one 128-byte record: floats 3c .. 3c+2 = E at corner
-// c = 4 dz + 2 dy + dx, floats 24 and 25 = the local bound of the cell
+// c = 4 dz + 2 dy + dx for dx = 0, and the single-precision difference
+// E(c) - E(c - 1) along x for dx = 1 (so that each x interpolation is one
+// multiply-add; the gather's result is the same as from the plain corner
+// values), floats 24 and 25 = the local bound of the cell
 // clamp(i, j, k) (max |E| and field-range norm over its 4x4x4 centres).  A
 // gather therefore reads a single cache line.
 constexpr int kRecFloats = 32;
@@ -226,9 +229,10 @@ __device__ __forceinline__ double3 gather(const GridView& G, double qm, double x
   if (rec_out) *rec_out = rec;
   const float4 q0 = rec[0], q1 = rec[1], q2 = rec[2], q3 = rec[3], q4 = rec[4], q5 = rec[5];
   // corners (dz, dy, dx): 000 = q0.xyz, 001 = q0.w q1.xy, 010 = q1.zw q2.x,
-  // 011 = q2.yzw, 100 = q3.xyz, 101 = q3.w q4.xy, 110 = q4.zw q5.x, 111 = q5.yzw
-  auto lx = [&](float ax, float ay, float az, float bx, float by, float bz) {
-    return make_float3(fmaf(gx, bx - ax, ax), fmaf(gx, by - ay, ay), fmaf(gx, bz - az, az));
+  // 011 = q2.yzw, 100 = q3.xyz, 101 = q3.w q4.xy, 110 = q4.zw q5.x, 111 = q5.yzw;
+  // the dx = 1 corners hold the x-differences
+  auto lx = [&](float ax, float ay, float az, float dx_, float dy_, float dz_) {
+    return make_float3(fmaf(gx, dx_, ax), fmaf(gx, dy_, ay), fmaf(gx, dz_, az));
   };
   auto l3 = [](float t, float3 a, float3 b) {
     return make_float3(fmaf(t, b.x - a.x, a.x), fmaf(t, b.y - a.y, a.y), fmaf(t, b.z - a.z, a.z));

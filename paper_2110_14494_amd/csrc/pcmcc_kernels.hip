@@ -552,6 +552,12 @@ __global__ __launch_bounds__(128) void k_pack_field(const float4* __restrict__ E
       v[3 * c + 1] = e.y;
       v[3 * c + 2] = e.z;
     }
+    // the dx = 1 corners as differences along x (rounded as the gather
+    // would round them)
+#pragma unroll
+    for (int c = 1; c < 8; c += 2)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) v[3 * c + q] = v[3 * c + q] - v[3 * (c - 1) + q];
     const float2 b = bound[((size_t)ck[0] * ny + cj[0]) * nx + ci[0]];
     v[24] = b.x;
     v[25] = b.y;
