@@ -190,6 +190,7 @@ struct GridView {
   int nx, ny, nz;
   int px, py;       // records per row and per plane stride: nx + 2, ny + 2
   double o[3];      // origin
+  double nd[3];     // nx, ny, nz as doubles (the coordinate clamp)
   double inv_dx;
   float dx;
   double lo[3], hi[3];  // domain
@@ -200,9 +201,9 @@ struct GridView {
 
 // Cell-centre coordinate u = (x - x0)/dx - 1/2 of one axis, clamped to
 // [-1, n], split into the lower centre index and the fraction.
-__device__ __forceinline__ void cell_coord(double x, double o, double inv_dx, int n, int& i, float& f) {
+__device__ __forceinline__ void cell_coord(double x, double o, double inv_dx, double n, int& i, float& f) {
   double u = fma(x - o, inv_dx, -0.5);
-  u = fmin(fmax(u, -1.0), (double)n);
+  u = fmin(fmax(u, -1.0), n);
   const double fl = floor(u);
   i = (int)fl;
   f = (float)(u - fl);
@@ -222,9 +223,9 @@ __device__ __forceinline__ double3 gather(const GridView& G, double qm, double x
                                           const float4** rec_out = nullptr) {
   int i, j, k;
   float gx, gy, gz;
-  cell_coord(x, G.o[0], G.inv_dx, G.nx, i, gx);
-  cell_coord(y, G.o[1], G.inv_dx, G.ny, j, gy);
-  cell_coord(z, G.o[2], G.inv_dx, G.nz, k, gz);
+  cell_coord(x, G.o[0], G.inv_dx, G.nd[0], i, gx);
+  cell_coord(y, G.o[1], G.inv_dx, G.nd[1], j, gy);
+  cell_coord(z, G.o[2], G.inv_dx, G.nd[2], k, gz);
   const float4* rec = grid_record(G, i, j, k);
   if (rec_out) *rec_out = rec;
   const float4 q0 = rec[0], q1 = rec[1], q2 = rec[2], q3 = rec[3], q4 = rec[4], q5 = rec[5];

@@ -162,6 +162,9 @@ struct GridField {
     v.o[0] = g->o[0];
     v.o[1] = g->o[1];
     v.o[2] = g->o[2];
+    v.nd[0] = g->nd[0];
+    v.nd[1] = g->nd[1];
+    v.nd[2] = g->nd[2];
     v.inv_dx = g->inv_dx;
     return gather(v, g->qm, x, y, z, &w);
   }
@@ -310,11 +313,12 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
 __device__ __forceinline__ void iso_dir(uint32_t r1, uint32_t r2, double& nx, double& ny, double& nz) {
   const double u = (double)unif(r1);
   const double cth = fma(-2.0, u, 1.0);
-  const double sth = 2.0 * sqrt_nr(u * (1.0 - u));  // u (1 - u) > 2^-25: never zero or subnormal
+  const double sth_half = sqrt_nr(u * (1.0 - u));  // u (1 - u) > 2^-25: never zero or subnormal
   const float t = unif(r2);
   const float sp = __builtin_amdgcn_sinf(t), cp = __builtin_amdgcn_cosf(t);
   const double s2 = fma((double)sp, (double)sp, (double)cp * cp);
-  const double inv = sth * fma(-0.5, s2, 1.5);
+  // sin(theta) (3/2 - s2/2) = sth_half (3 - s2), the factor 2 moved exactly
+  const double inv = sth_half * fma(-1.0, s2, 3.0);
   nx = inv * cp;
   ny = inv * sp;
   nz = cth;

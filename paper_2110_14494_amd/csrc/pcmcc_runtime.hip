@@ -541,6 +541,9 @@ int push_impl(pcmcc_ctx* c, const pcmcc_particles* p, const pcmcc_grid* field, d
   G.o[0] = field->x0;
   G.o[1] = field->y0;
   G.o[2] = field->z0;
+  G.nd[0] = (double)field->nx;
+  G.nd[1] = (double)field->ny;
+  G.nd[2] = (double)field->nz;
   G.dx = (float)field->dx;
   G.inv_dx = 1.0 / field->dx;
   G.lo[0] = field->x0;
