@@ -314,10 +314,14 @@ __device__ __forceinline__ int flight_plan(Flight& f, double dt, const Tab& T, c
   const TabConst tc = tab_const();
   const float nu_full = majorant_t(T, tc, speed_bound(vf, af, speed, f.a_abs, f.da, (float)t_rem));
   const bool limited = kKappa < nu_full * (float)t_rem;
-  // Both majorants are evaluated and one is selected, which keeps the lanes
-  // of a wave on one path (nu_full = 0 gives an unused, finite lookup).
-  const float h_lim = kKappa * __builtin_amdgcn_rcpf(nu_full);
-  const float nu_lim = majorant_t(T, tc, speed_bound(vf, af, speed, f.a_abs, f.da, h_lim));
+  // Where any lane of the wave is limited, both majorants are evaluated and
+  // one is selected, which keeps the lanes on one path (nu_full = 0 gives an
+  // unused, finite lookup); a wave without a limited lane skips the second.
+  float h_lim = 0.0f, nu_lim = 0.0f;
+  if (__ballot(limited) != 0) {
+    h_lim = kKappa * __builtin_amdgcn_rcpf(nu_full);
+    nu_lim = majorant_t(T, tc, speed_bound(vf, af, speed, f.a_abs, f.da, h_lim));
+  }
   const double h = limited ? (double)h_lim : t_rem;
   const float nu_hat = limited ? nu_lim : nu_full;
   // ln U from the hardware base-2 logarithm (U in [2^-24, 1) is never
