@@ -101,8 +101,10 @@ __device__ __forceinline__ uint4 draw_pre(Key key, const PhiloxPre& pre, uint32_
   return c;
 }
 
-// Uniform in (0,1) from the top 23 bits: ((r >> 9) + 1/2) 2^-23, exact in FP32.
-__device__ __forceinline__ float unif(uint32_t r) { return ((float)(r >> 9) + 0.5f) * 0x1p-23f; }
+// Uniform in (0,1) from the top 23 bits: ((r >> 9) + 1/2) 2^-23, exact in FP32
+// (one multiply-add: k 2^-23 + 2^-24 = (2k + 1) 2^-24 has at most 24
+// significant bits, so the fused result is the exact value).
+__device__ __forceinline__ float unif(uint32_t r) { return fmaf((float)(r >> 9), 0x1p-23f, 0x1p-24f); }
 
 // ---------------------------------------------------------------------------
 // Collision tables: cumulative rates C[k][i] in process order and the prefix
