@@ -260,7 +260,101 @@ struct InferLds {
   uint8_t mask[kMaskLds];      // the fallback mask per cell, when it has at most kMaskLds cells
 };
 
-__global__ __launch_bounds__(256) void k_mlp_infer(InferArgs A) {
+// The tiles of one wave, 32 points each: lanes l and l + 32 both work on
+// point l of a tile (the two halves of the MFMA operands), and each writes its
+// half of the outputs.  MASK_LDS: the fallback mask sits in LDS (otherwise it
+// is read from global memory); the two cases are separate instantiations so
+// that each read is a plain LDS or global load, never a generic one, whose wait
+// would also wait for the field read ahead for the next tile.  The table rows
+// of the outputs that fall back are read before the next tile's field and
+// before the network, so that their latency overlaps the network and waiting
+// for them does not wait for that prefetch.
+template <bool MASK_LDS>
+__device__ __forceinline__ void infer_tiles(const InferArgs& A, const InferLds& L, int lane, int64_t wave,
+                                            int64_t nwave) {
+  const int half = lane >> 5, col = lane & 31;
+  const int64_t stride = nwave * 32;
+  // the field of the lane's point in the wave's next tile, read one
+  // iteration ahead (an index clamped into the array, so that the load needs
+  // no branch)
+  float en_next = A.EN[min(wave * 32 + col, A.n - 1)];
+  for (int64_t p0 = wave * 32; p0 < A.n; p0 += stride) {
+    const int64_t p = p0 + col;
+    const bool valid = p < A.n;
+    const float EN = valid ? en_next : 1.0f;
+    const float lnEN = logf(EN);
+    const float xs = (lnEN - A.mu_x) * A.inv_sd_x;
+    // bit o set: output o of this point's cell takes the table
+    unsigned fbm = 0u;
+    float tf = 0.0f, ta[4] = {0.0f, 0.0f, 0.0f, 0.0f}, tb[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (A.n_cells > 0) {
+      const int cell = min(max((int)floorf((lnEN - A.cell_lo) * A.inv_cell_w), 0), A.n_cells - 1);
+      fbm = (unsigned)(MASK_LDS ? L.mask[cell] : A.fb_mask[cell]) & kAllOut;
+      if (fbm) {
+        const float u = fminf(fmaxf((lnEN - A.tab_lo) * A.inv_tab_w, 0.0f), (float)(A.n_nodes - 1));
+        const float fl = fminf(floorf(u), (float)(A.n_nodes - 2));
+        tf = u - fl;
+        // this lane's outputs 4 half + j of the nodes on either side
+        const float* row = A.table + (size_t)(int)fl * kOut + 4 * half;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (4 * half + j < kOut) {
+            ta[j] = row[j];
+            tb[j] = row[kOut + j];
+          }
+      }
+    }
+    en_next = A.EN[min(p + stride, A.n - 1)];
+    floatx16 c3;
+    for (int r = 0; r < 16; ++r) c3[r] = 0.0f;
+    // The perceptron runs unless every output of every point of the wave
+    // falls back to the table (the condition is wave-uniform, as the matrix
+    // instructions need).
+    if (__ballot(valid && fbm != kAllOut) != 0) {
+      // layer 2: C2[m] = W2[32m.., :] s1 over 4 k-steps of 16
+      floatx16 c2[2];
+      for (int m = 0; m < 2; ++m)
+        for (int r = 0; r < 16; ++r) c2[m][r] = 0.0f;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        bf16x8 b;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int k = 16 * s + 8 * half + q;
+          b[q] = (__bf16)logistic_l2(fmaf(L.a1[k], xs, L.c1[k]));
+        }
+        c2[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(L.A2[0][s][lane], b, c2[0], 0, 0, 0);
+        c2[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(L.A2[1][s][lane], b, c2[1], 0, 0, 0);
+      }
+      // activation of layer 2 (z = 2 C2 + b2 - row sum); rows of C2 held by
+      // this lane: 8 i + 4 half + j (i = reg / 4, j = reg % 4)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int m = s >> 1;
+        bf16x8 b;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int i = 2 * (s & 1) + (q >> 2), j = q & 3;
+          const int row = 8 * i + 4 * half + j;
+          b[q] = (__bf16)logistic_l2(fmaf(c2[m][4 * i + j], 2.0f * kM2L2E, L.c2[32 * m + row]));
+        }
+        c3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(L.A3[s][lane], b, c3, 0, 0, 0);
+      }
+    }
+    if (!valid) continue;
+    // outputs: rows 4 half + j (j < 4) of C3 are outputs 0..3 (half 0) and 4..7 (half 1)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int o = 4 * half + j;
+      if (o >= kOut) break;
+      float y = fmaf(c3[j], L.y_scale[o], L.y_off[o]);
+      if ((fbm >> o) & 1u) y = fmaf(tf, tb[j] - ta[j], ta[j]);
+      A.out[(size_t)o * A.n + p] = y;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_mlp_infer(InferArgs A) {
   __shared__ InferLds L;
   const int tid = threadIdx.x;
   const float* P = A.params;
@@ -302,83 +396,12 @@ __global__ __launch_bounds__(256) void k_mlp_infer(InferArgs A) {
   if (mask_lds)
     for (int i = tid; i < A.n_cells; i += 256) L.mask[i] = A.fb_mask[i];
   __syncthreads();
-  const int lane = tid & 63, half = lane >> 5, col = lane & 31;
   const int64_t wave = (int64_t)blockIdx.x * 4 + (tid >> 6);
   const int64_t nwave = (int64_t)gridDim.x * 4;
-  const int64_t stride = nwave * 32;
-  // the field of the lane's point in the wave's next tile, read one
-  // iteration ahead so that its latency overlaps the current tile's work
-  // (an index clamped into the array, so that the load needs no branch)
-  float en_next = A.EN[min(wave * 32 + col, A.n - 1)];
-  for (int64_t p0 = wave * 32; p0 < A.n; p0 += stride) {
-    const int64_t p = p0 + col;
-    const bool valid = p < A.n;
-    const float EN = valid ? en_next : 1.0f;
-    en_next = A.EN[min(p + stride, A.n - 1)];
-    const float lnEN = logf(EN);
-    const float xs = (lnEN - A.mu_x) * A.inv_sd_x;
-    const int cell = A.n_cells > 0 ? min(max((int)floorf((lnEN - A.cell_lo) * A.inv_cell_w), 0), A.n_cells - 1) : 0;
-    // bit o set: output o of this cell takes the table
-    const unsigned fbm =
-        A.n_cells > 0 ? (unsigned)(mask_lds ? L.mask[cell] : A.fb_mask[cell]) & kAllOut : 0u;
-    floatx16 c3;
-    for (int r = 0; r < 16; ++r) c3[r] = 0.0f;
-    // The perceptron runs unless every output of every point of the wave
-    // falls back to the table (the condition is wave-uniform, as the matrix
-    // instructions need).
-    if (__ballot(valid && fbm != kAllOut) != 0) {
-      // layer 2: C2[m] = W2[32m.., :] s1 over 4 k-steps of 16
-      floatx16 c2[2];
-      for (int m = 0; m < 2; ++m)
-        for (int r = 0; r < 16; ++r) c2[m][r] = 0.0f;
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        bf16x8 b;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const int k = 16 * s + 8 * half + q;
-          b[q] = (__bf16)logistic_l2(fmaf(L.a1[k], xs, L.c1[k]));
-        }
-        c2[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(L.A2[0][s][lane], b, c2[0], 0, 0, 0);
-        c2[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(L.A2[1][s][lane], b, c2[1], 0, 0, 0);
-      }
-      // activation of layer 2 (z = 2 C2 + b2 - row sum); rows of C2 held by
-      // this lane: 8 i + 4 half + j (i = reg / 4, j = reg % 4)
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int m = s >> 1;
-        bf16x8 b;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const int i = 2 * (s & 1) + (q >> 2), j = q & 3;
-          const int row = 8 * i + 4 * half + j;
-          b[q] = (__bf16)logistic_l2(fmaf(c2[m][4 * i + j], 2.0f * kM2L2E, L.c2[32 * m + row]));
-        }
-        c3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(L.A3[s][lane], b, c3, 0, 0, 0);
-      }
-    }
-    if (!valid) continue;
-    // outputs: rows 4 half + j (j < 4) of C3 are outputs 0..3 (half 0) and 4..7 (half 1)
-    float tf = 0.0f;
-    int ti = 0;
-    if (fbm) {
-      const float u = fminf(fmaxf((lnEN - A.tab_lo) * A.inv_tab_w, 0.0f), (float)(A.n_nodes - 1));
-      const float fl = fminf(floorf(u), (float)(A.n_nodes - 2));
-      ti = (int)fl;
-      tf = u - fl;
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int o = 4 * half + j;
-      if (o >= kOut) break;
-      float y = fmaf(c3[j], L.y_scale[o], L.y_off[o]);
-      if ((fbm >> o) & 1u) {
-        const float a = A.table[ti * kOut + o], bb = A.table[(ti + 1) * kOut + o];
-        y = fmaf(tf, bb - a, a);
-      }
-      A.out[(size_t)o * A.n + p] = y;
-    }
-  }
+  if (mask_lds)
+    infer_tiles<true>(A, L, tid & 63, wave, nwave);
+  else
+    infer_tiles<false>(A, L, tid & 63, wave, nwave);
 }
 
 // ---------------------------------------------------------------------------
