@@ -34,7 +34,15 @@ struct SwarmField {
   const float* a_abs;  // LDS [S]: |az| in single precision
   Key base;
   using Where = int;
-  __device__ __forceinline__ Key key(uint32_t s) const { return swarm_key(base, (int)s); }
+  // The run's key passes through an empty asm statement at every use, so that
+  // the Philox round keys of its uniform word are derived there with scalar
+  // adds instead of being hoisted out of the mover loop (where they spill into
+  // vector lanes and come back one v_readlane each).
+  __device__ __forceinline__ Key key(uint32_t s) const {
+    uint32_t k0 = base.k0, k1 = base.k1;
+    asm volatile("" : "+s"(k0), "+s"(k1));
+    return swarm_key(Key{k0, k1}, (int)s);
+  }
   __device__ __forceinline__ double3 accel(double, double, double, uint32_t s, Where&) const {
     return make_double3(0.0, 0.0, az[s]);
   }
