@@ -354,6 +354,9 @@ __device__ __forceinline__ void infer_tiles(const InferArgs& A, const InferLds& 
   }
 }
 
+// Five waves per SIMD (92 registers, no spills): left to itself the compiler
+// gives the table rows held across the network registers of their own (103)
+// and the kernel would drop to four.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_mlp_infer(InferArgs A) {
   __shared__ InferLds L;
   const int tid = threadIdx.x;
