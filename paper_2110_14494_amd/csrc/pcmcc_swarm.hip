@@ -196,9 +196,9 @@ __device__ __forceinline__ void add128(unsigned long long& lo, long long& hi, lo
 
 // Fixed-point exponents of the moments (value * 2^e, |value * 2^e| < 2^54 so
 // that a 256-particle block sum fits in 64 bits).
-__constant__ int kMomExp[kNMom] = {0, 53, 53, 53, 53, 53, 25, 25, 25, 24, 24, 36, 0, 0};
-__constant__ double kMomLim[kNMom] = {2.0, 1.0, 1.0, 1.0, 1.0, 1.0, 0x1p29, 0x1p29, 0x1p29, 0x1p30, 0x1p30,
-                                      0x1p18, 0x1p53, 0x1p53};
+constexpr int kMomExp[kNMom] = {0, 53, 53, 53, 53, 53, 25, 25, 25, 24, 24, 36, 0, 0};
+constexpr double kMomLim[kNMom] = {2.0, 1.0, 1.0, 1.0, 1.0, 1.0, 0x1p29, 0x1p29, 0x1p29, 0x1p30, 0x1p30,
+                                    0x1p18, 0x1p53, 0x1p53};
 
 // Block-level exclusive scan of per-swarm tile counts into LDS prefix[0..S].
 __device__ void tile_prefix(const unsigned long long* n, int S, int tile, uint32_t* prefix, uint32_t* tmp) {
