@@ -532,15 +532,24 @@ __global__ __launch_bounds__(kFbThreads) void k_field_bounds(const float4* __res
 // Corner-packed field (layout in pcmcc_device.hpp): one thread per record,
 // the record of lower centre index (i, j, k) in [-1, n]^3 holding the fields
 // of the 8 centres around it (indices clamped to the grid) and the bound of
-// the cell clamp(i, j, k).
-// One block row of records per (j, k) in [-1, n]^2 (blockIdx.y, blockIdx.z).
-__global__ __launch_bounds__(128) void k_pack_field(const float4* __restrict__ E, const float2* __restrict__ bound,
-                                                    int nx, int ny, int nz, float4* __restrict__ P) {
-  const uint64_t px = (uint64_t)nx + 2, py = (uint64_t)ny + 2;
-  const int ri = blockIdx.x * blockDim.x + threadIdx.x;
-  if (ri < nx + 2) {
-    const uint64_t r = ((uint64_t)blockIdx.z * py + blockIdx.y) * px + (uint64_t)ri;
-    const int i = ri - 1, j = (int)blockIdx.y - 1, k = (int)blockIdx.z - 1;
+// the cell clamp(i, j, k).  A block takes 128 consecutive records of the flat
+// record order, forms them in registers, stages them in LDS and writes them
+// out as consecutive float4s: each store instruction then covers 1 KiB of
+// consecutive records instead of one 16-byte piece of 64 different records.
+constexpr int kPackThreads = 128;
+constexpr int kPackStride = kRecFloats / 4 + 1;  // float4 per record in LDS (one of padding spreads the banks)
+__global__ __launch_bounds__(kPackThreads) void k_pack_field(const float4* __restrict__ E,
+                                                             const float2* __restrict__ bound, int nx, int ny,
+                                                             int nz, float4* __restrict__ P) {
+  __shared__ float4 st[kPackThreads * kPackStride];
+  const uint32_t px = (uint32_t)nx + 2, py = (uint32_t)ny + 2;
+  const uint32_t nrec = px * py * ((uint32_t)nz + 2);  // below 2^31 (checked by the caller)
+  const uint32_t r0 = blockIdx.x * kPackThreads;
+  const uint32_t r = r0 + threadIdx.x;
+  if (r < nrec) {
+    const uint32_t row = r / px, ri = r - row * px;
+    const uint32_t rk = row / py, rj = row - rk * py;
+    const int i = (int)ri - 1, j = (int)rj - 1, k = (int)rk - 1;
     const int ci[2] = {min(max(i, 0), nx - 1), min(max(i + 1, 0), nx - 1)};
     const int cj[2] = {min(max(j, 0), ny - 1), min(max(j + 1, 0), ny - 1)};
     const int ck[2] = {min(max(k, 0), nz - 1), min(max(k + 1, 0), nz - 1)};
@@ -563,10 +572,15 @@ __global__ __launch_bounds__(128) void k_pack_field(const float4* __restrict__ E
     v[25] = b.y;
 #pragma unroll
     for (int q = 26; q < kRecFloats; ++q) v[q] = 0.0f;
-    float4* out = P + r * (kRecFloats / 4);
 #pragma unroll
-    for (int q = 0; q < kRecFloats / 4; ++q) out[q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+    for (int q = 0; q < kRecFloats / 4; ++q)
+      st[threadIdx.x * kPackStride + q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
   }
+  __syncthreads();
+  const uint32_t nb = min((uint32_t)kPackThreads, nrec - r0);  // records of this block
+  float4* out = P + (size_t)r0 * (kRecFloats / 4);
+  for (uint32_t f = threadIdx.x; f < nb * (kRecFloats / 4); f += kPackThreads)
+    out[f] = st[(f / (kRecFloats / 4)) * kPackStride + f % (kRecFloats / 4)];
 }
 
 // ---------------------------------------------------------------------------
@@ -697,8 +711,10 @@ hipError_t launch_field_bounds(const float4* E, int nx, int ny, int nz, float2* 
 
 hipError_t launch_pack_field(const float4* E, const float2* bound, int nx, int ny, int nz, float4* P,
                              hipStream_t stream) {
-  hipLaunchKernelGGL(k_pack_field, dim3((unsigned)((nx + 2 + 127) / 128), (unsigned)(ny + 2), (unsigned)(nz + 2)),
-                     dim3(128), 0, stream, E, bound, nx, ny, nz, P);
+  const uint64_t nrec = ((uint64_t)nx + 2) * ((uint64_t)ny + 2) * ((uint64_t)nz + 2);
+  if (nrec >= ((uint64_t)1 << 31)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_pack_field, dim3((unsigned)((nrec + kPackThreads - 1) / kPackThreads)), dim3(kPackThreads), 0,
+                     stream, E, bound, nx, ny, nz, P);
   return hipGetLastError();
 }
 
